@@ -1,0 +1,205 @@
+/*
+ * psara.h -- C ABI of the MI355X (gfx950) Polarized SARA library.
+ *
+ * Polarized SARA (Birdi, Repetti & Wiaux, MNRAS 2018) images the four Stokes
+ * maps S = [I, Q, U, V] in R^{N x 4} from full-polarisation visibilities
+ * Y in C^{M x 4} by solving (eq. min_gen2)
+ *
+ *   minimise  iota_B(Y,eps)(phi(S)) + iota_U(S) + gamma ||Psi^dagger S||_{W,1}
+ *             + iota_V(Z) + iota_E1(S_:1, Z_:1) + iota_E2(S_:2:4, Z_:2)
+ *
+ * with the primal-dual iteration of Algorithm 1 (Sec. 3.3) inside the
+ * reweighting loop of Algorithm 2 (Sec. 3.3.4).  The library owns all device
+ * state of one solve in an opaque context; every step of the iteration runs in
+ * hand-written HIP kernels.  Host arrays passed in are caller-owned and copied
+ * before the call returns; nothing is retained.  All calls are synchronous with
+ * respect to the host unless stated otherwise, and return a psara_status; the
+ * message of the last failure is available from psara_last_error().
+ *
+ * Conventions shared by every call:
+ *   - images are N x 4 row-major doubles, N = n*n, pixel p = r*n + c (row r,
+ *     column c, centred coordinates (r - n/2, c - n/2)), columns I, Q, U, V;
+ *   - visibilities are M x 4 complex doubles stored as interleaved (re, im)
+ *     pairs, i.e. 8 doubles per row, columns the brightness products
+ *     [I+Q, U+iV, U-iV, I-Q] of Sec. 2.1;
+ *   - uv points are M x 2 doubles in radians per pixel, each in [-pi, pi),
+ *     component 0 pairing with the row axis;
+ *   - SARA coefficients are J x 4 doubles, J = nb * N, one n x n block per
+ *     basis in the order Dirac, Db1 ... Db8 (bases absent from the mask are
+ *     skipped), each block in the in-place Mallat layout of a periodised 2-D
+ *     DWT (rows first, then columns, per level).
+ *
+ * A context is bound to one HIP stream and one device and is not re-entrant;
+ * distinct contexts may be used from distinct threads.
+ */
+#ifndef PSARA_H
+#define PSARA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psara_ctx psara_ctx;
+
+typedef enum {
+    PSARA_OK = 0,
+    PSARA_EINVAL = -1,   /* invalid argument (sizes, ranges, step-size condition) */
+    PSARA_ENOMEM = -2,   /* device allocation failed */
+    PSARA_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed */
+    PSARA_ESTATE = -4,   /* call out of order (e.g. solve before set_data) */
+    PSARA_ENAN = -5      /* non-finite input */
+} psara_status;
+
+typedef enum {
+    PSARA_FP64 = 0,        /* every array and every operation in double precision */
+    PSARA_FP32_MIXED = 1   /* FP32 arrays and operators; l2-ball norm, power iteration
+                              and stopping reductions in FP64 with compensated sums */
+} psara_precision;
+
+typedef enum {
+    PSARA_CONSTRAINED = 0,   /* Polarized SARA, eq. min_gen2 (all terms of Algorithm 1) */
+    PSARA_NNLS_INIT = 1,     /* initialisation of Sec. 3.3.4: g = 0, set U' (I >= 0); only S, B move */
+    PSARA_UNCONSTRAINED = 2  /* "Polarized SARA without constraint", eq. min_gen_matrix_no_flux */
+} psara_mode;
+
+/* Stopping and diagnostic quantities of Sec. 4.2 and Sec. 4.6, all FP64. */
+typedef struct {
+    double residual;     /* ||phi(S) - Y||_2 */
+    double epsilon;      /* l2 bound of the data-fidelity ball */
+    double rel_var[4];   /* ||S_i^(k) - S_i^(k-1)|| / ||S_i^(k-1)|| per Stokes map (inf if 0 / 0) */
+    double zeta;         /* 3 x rms of the Stokes-I residual image Re phi^dagger(Y - phi(S)) / (2M) */
+    double n_p;          /* percentage of pixels with ||S_n,2:4|| - S_n,1 > zeta */
+    double objective;    /* ||Psi^dagger S||_{W,1} with the current weights */
+    double vnorm;        /* ||B~/rho2 - Y|| at the last dual-B step */
+    int64_t iterations;  /* Algorithm-1 iterations run on this context so far */
+} psara_report;
+
+/* ---- lifetime --------------------------------------------------------------------------- */
+
+/* Create a context on `device`.  `hip_stream` is a hipStream_t to run on (for example
+ * torch.cuda.current_stream().cuda_stream) or NULL for a library-owned stream. */
+psara_status psara_create(psara_ctx** out, int device, void* hip_stream);
+void psara_destroy(psara_ctx* ctx);
+const char* psara_last_error(const psara_ctx* ctx);
+const char* psara_status_string(psara_status s);
+
+/* ---- problem set-up (Sec. 2.2, 3.1, 4.1) --------------------------------------------------- */
+
+/* Measurement operator phi = G F Z . L (eq. meas_op): n x n images (n a power of two,
+ * 8 <= n <= 1024), M >= 1 uv points (copied; sorted into grid tiles on the device side),
+ * oversampling 2 per dimension, Kaiser-Bessel interpolation with `taps` in {4, 6, 8} per
+ * dimension.  Resets data, prior, steps and state.  EINVAL on bad sizes or uv outside
+ * [-pi, pi). */
+psara_status psara_set_operator(psara_ctx* ctx, int n, int64_t M, const double* uv,
+                                int oversample, int taps, psara_precision precision);
+
+/* Visibilities Y (M x 4 complex, see conventions) and the l2 bound epsilon > 0 of the
+ * data-fidelity ball B(Y, epsilon) (eq. f_diff).  ENAN if Y holds a non-finite value. */
+psara_status psara_set_data(psara_ctx* ctx, const double* Y, double epsilon);
+
+/* SARA prior (Sec. 3.1): basis_mask bit 0 = Dirac, bits 1..8 = Db1..Db8; `levels` >= 1 with
+ * n divisible by 2^levels; weights W (J x 4, >= 0) or NULL for all ones; gamma > 0 (the free
+ * scale of eq. min_gen2).  The soft-threshold sizes are gamma * W.  Psi is normalised by
+ * 1/sqrt(nb) so that Psi Psi^dagger = I. */
+psara_status psara_set_prior(psara_ctx* ctx, uint32_t basis_mask, int levels,
+                             const double* weights, double gamma);
+
+/* Step sizes of Algorithm 1.  EINVAL unless all are > 0 and the convergence condition of
+ * Sec. 3.3.3,  1/tau - rho1 ||Psi||^2 - rho2 ||phi||^2 - rho3 >= 0,  holds with the
+ * operator norm from psara_opnorm (which must have run). */
+psara_status psara_set_steps(psara_ctx* ctx, double tau, double rho1, double rho2, double rho3);
+
+/* ||phi||^2 of the real-restricted map S -> Re phi^dagger phi S by an FP64 power
+ * iteration on the device (seeded start), stopped when the Rayleigh quotient changes by
+ * less than rtol (relative) or after max_iter iterations.  Stored in the context. */
+psara_status psara_opnorm(psara_ctx* ctx, int max_iter, double rtol, double* phi_norm_sq);
+
+/* ---- the iteration (Algorithm 1) and the reweighting (Algorithm 2) ------------------------- */
+
+/* Run `iters` iterations of Algorithm 1 in `mode` from the current state (warm start, as
+ * Algorithm 2 passes every variable from one reweighting cycle to the next).  Iterations
+ * are replayed from a captured HIP graph.  If `check_every` > 0 the stopping quantities are
+ * evaluated every check_every iterations; if `out` is not NULL it receives the quantities
+ * after the last iteration. */
+psara_status psara_solve(psara_ctx* ctx, psara_mode mode, int iters, int check_every,
+                         psara_report* out);
+
+/* Reweighting step of Algorithm 2 (eq. weights): W = delta / (delta + |Psi^dagger S|),
+ * thresholds gamma * W.  delta > 0. */
+psara_status psara_reweight(psara_ctx* ctx, double delta);
+
+/* Standard deviation of the 4J entries of Psi^dagger S (FP64), the starting delta of the
+ * reweighting schedule. */
+psara_status psara_coef_std(psara_ctx* ctx, double* out);
+
+/* Algorithm 2 end to end: an initialisation stage (PSARA_NNLS_INIT) of iters_per_stage[0]
+ * iterations, then `cycles` reweighted stages in `mode` of iters_per_stage[1..cycles]
+ * iterations each; delta starts at the coefficient standard deviation after the
+ * initialisation and is divided by delta_decay (> 1) after every cycle. */
+psara_status psara_reweighted_solve(psara_ctx* ctx, psara_mode mode, int cycles,
+                                    const int* iters_per_stage, double delta_decay,
+                                    psara_report* out);
+
+/* Evaluate the stopping quantities for the current state. */
+psara_status psara_report_now(psara_ctx* ctx, psara_report* out);
+
+/* ---- state ------------------------------------------------------------------------------- */
+
+/* Current Stokes estimate S (N x 4 doubles). */
+psara_status psara_get_image(psara_ctx* ctx, double* S);
+
+/* Size in bytes of the serialised state: (N*4 + N*2 + J*4 + M*8 + N*4 + N*2) doubles holding
+ * S, Z, A, B (complex, original uv order), C, D in that order. */
+size_t psara_state_bytes(const psara_ctx* ctx);
+psara_status psara_get_state(psara_ctx* ctx, void* buf, size_t bytes);
+psara_status psara_set_state(psara_ctx* ctx, const void* buf, size_t bytes);
+/* All primal and dual variables to zero (Algorithm 1's starting point used here). */
+psara_status psara_reset_state(psara_ctx* ctx);
+
+/* Device bytes a context of this shape allocates (used for admission control). */
+size_t psara_footprint(int n, int64_t M, int taps, int levels, uint32_t basis_mask,
+                       psara_precision precision);
+
+/* ---- operators (for verification and synthetic data; same kernels as the iteration) ------ */
+
+/* Y = phi(S) (eq. meas_op): S is N x 4, Y is M x 4 complex in the caller's uv order. */
+psara_status psara_apply_phi(psara_ctx* ctx, const double* S, double* Y);
+/* S = Re phi^dagger(B) (the adjoint followed by the projection onto real matrices). */
+psara_status psara_apply_phi_adjoint(psara_ctx* ctx, const double* B, double* S);
+/* A = Psi^dagger S (J x 4) and S = Psi A, for the prior set by psara_set_prior. */
+psara_status psara_apply_psi_adjoint(psara_ctx* ctx, const double* S, double* A);
+psara_status psara_apply_psi(psara_ctx* ctx, const double* A, double* S);
+
+/* ---- host-only helpers (no device needed) ------------------------------------------------ */
+
+/* Daubechies low-pass filter with p in [1, 8] vanishing moments by spectral factorisation
+ * (minimum phase); writes 2p doubles.  Returns 2p, or 0 on bad p. */
+int psara_wavelet_filter(int p, double* h);
+
+/* Kaiser-Bessel shape beta for `taps` and oversampling alpha (Beatty et al. 2005) and the
+ * kernel value psi(t) / deapodisation 1/psi_hat(nu) used by the operator. */
+double psara_kb_beta(int taps, double alpha);
+double psara_kb_value(int taps, double beta, double t);
+double psara_kb_deapod(int taps, double beta, double nu);
+
+/* Sorted-visibility layout chosen by set_operator: writes the permutation (sorted position
+ * -> caller index, M entries) and returns the grid tile side, or a negative status. */
+int psara_layout(const psara_ctx* ctx, int64_t* perm);
+
+/* ---- profiling --------------------------------------------------------------------------- */
+
+/* Time `reps` back-to-back launches of one pass of the iteration with HIP events on the
+ * context stream; writes the average duration in milliseconds.  Pass ids: 0 primal/epigraph
+ * (P1), 1 SARA analysis + dual A (P2), 2 SARA synthesis (P3), 3 row FFT (P4), 4 column FFT
+ * (P5), 5 de-grid + dual B (P6), 6 grid (P7), 7 column inverse FFT (P8), 8 row inverse FFT
+ * (P9).  The state is modified (the pass really runs). */
+psara_status psara_time_pass(psara_ctx* ctx, int pass_id, int reps, double* avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSARA_H */

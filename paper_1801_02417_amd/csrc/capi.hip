@@ -1,0 +1,418 @@
+// C ABI of the library (declared in include/psara.h): argument validation, the context,
+// and the reweighting driver of Algorithm 2.  Every call catches all C++ exceptions and
+// returns a status; the message is kept in the context.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "psara.h"
+
+using psara::Engine;
+using psara::Error;
+
+struct psara_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  psara::Geometry geo;
+  bool op_set = false, data_set = false, prior_set = false, steps_set = false, norm_set = false;
+  psara_precision prec = PSARA_FP32_MIXED;
+  std::unique_ptr<Engine<float>> f32;
+  std::unique_ptr<Engine<double>> f64;
+  double eps = 0.0, gamma = 0.0, phi_norm_sq = 0.0;
+  double tau = 0.0, rho1 = 0.0, rho2 = 0.0, rho3 = 0.0;
+  uint32_t mask = 0;
+  int levels = 0;
+  int64_t iterations = 0;
+};
+
+namespace {
+
+template <class F>
+void with_engine(psara_ctx* c, F&& f) {
+  if (c->f32) f(*c->f32);
+  else if (c->f64) f(*c->f64);
+  else throw Error(PSARA_ESTATE, "operator not set");
+}
+
+template <class F>
+psara_status guard(psara_ctx* c, F&& f) {
+  if (!c) return PSARA_EINVAL;
+  try {
+    if (hipSetDevice(c->device) != hipSuccess) throw Error(PSARA_EDEVICE, "hipSetDevice failed");
+    f();
+    c->err.clear();
+    return PSARA_OK;
+  } catch (const Error& e) {
+    c->err = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return PSARA_ENOMEM;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return PSARA_EDEVICE;
+  }
+}
+
+void require(bool cond, psara_status st, const char* msg) {
+  if (!cond) throw Error(st, msg);
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int primal_mode(psara_mode m) {
+  switch (m) {
+    case PSARA_CONSTRAINED: return psara::PM_CONSTRAINED;
+    case PSARA_NNLS_INIT: return psara::PM_INIT;
+    case PSARA_UNCONSTRAINED: return psara::PM_UNCONSTRAINED;
+  }
+  throw Error(PSARA_EINVAL, "unknown mode");
+}
+
+size_t coef_count(const psara_ctx* c) {
+  int nb = 0;
+  for (int b = 0; b <= 8; ++b) nb += (c->mask >> b) & 1u;
+  return (size_t)nb * c->geo.n * c->geo.n;
+}
+
+void run_stage(psara_ctx* c, int mode, int iters, int check_every, psara_report* out) {
+  require(c->op_set && c->data_set, PSARA_ESTATE, "operator and data must be set before solving");
+  require(c->steps_set, PSARA_ESTATE, "step sizes must be set before solving");
+  require(mode == psara::PM_INIT || c->prior_set, PSARA_ESTATE, "prior must be set for this mode");
+  require(iters >= 0, PSARA_EINVAL, "iters must be >= 0");
+  int left = iters;
+  const int chunk = check_every > 0 ? check_every : iters;
+  psara_report rep;
+  std::memset(&rep, 0, sizeof(rep));
+  while (left > 0) {
+    const int k = std::min(left, std::max(chunk, 1));
+    with_engine(c, [&](auto& e) { e.run(mode, k); });
+    c->iterations += k;
+    left -= k;
+    if (check_every > 0) with_engine(c, [&](auto& e) { e.report(&rep); });
+  }
+  if (out) {
+    with_engine(c, [&](auto& e) { e.report(out); });
+    out->iterations = c->iterations;
+  }
+  with_engine(c, [&](auto& e) { psara::hip_check(hipStreamSynchronize(e.stream()), "solve sync"); });
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* psara_status_string(psara_status s) {
+  switch (s) {
+    case PSARA_OK: return "ok";
+    case PSARA_EINVAL: return "invalid argument";
+    case PSARA_ENOMEM: return "out of device memory";
+    case PSARA_EDEVICE: return "device error";
+    case PSARA_ESTATE: return "call out of order";
+    case PSARA_ENAN: return "non-finite input";
+  }
+  return "unknown status";
+}
+
+psara_status psara_create(psara_ctx** out, int device, void* hip_stream) {
+  if (!out) return PSARA_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PSARA_EDEVICE;
+  if (device < 0 || device >= count) return PSARA_EINVAL;
+  std::unique_ptr<psara_ctx> c(new (std::nothrow) psara_ctx());
+  if (!c) return PSARA_ENOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) return PSARA_EDEVICE;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return PSARA_EDEVICE;
+    c->own_stream = true;
+  }
+  *out = c.release();
+  return PSARA_OK;
+}
+
+void psara_destroy(psara_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  c->f32.reset();
+  c->f64.reset();
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* psara_last_error(const psara_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+psara_status psara_set_operator(psara_ctx* c, int n, int64_t M, const double* uv, int oversample, int taps,
+                                psara_precision precision) {
+  return guard(c, [&] {
+    require(is_pow2(n) && n >= 8 && n <= 1024, PSARA_EINVAL, "n must be a power of two in [8, 1024]");
+    require(M >= 1 && M < (int64_t(1) << 31), PSARA_EINVAL, "M must be in [1, 2^31)");
+    require(uv != nullptr, PSARA_EINVAL, "uv is NULL");
+    require(oversample == 2, PSARA_EINVAL, "oversample must be 2");
+    require(taps == 4 || taps == 6 || taps == 8, PSARA_EINVAL, "taps must be 4, 6 or 8");
+    require(precision == PSARA_FP64 || precision == PSARA_FP32_MIXED, PSARA_EINVAL, "unknown precision");
+    for (int64_t i = 0; i < 2 * M; ++i) require(std::isfinite(uv[i]), PSARA_ENAN, "non-finite uv");
+    c->f32.reset();
+    c->f64.reset();
+    c->op_set = c->data_set = c->prior_set = c->steps_set = c->norm_set = false;
+    c->iterations = 0;
+    c->geo = psara::build_geometry(n, M, uv, oversample, taps);
+    c->prec = precision;
+    if (precision == PSARA_FP64) c->f64.reset(new Engine<double>(c->geo, c->stream));
+    else c->f32.reset(new Engine<float>(c->geo, c->stream));
+    c->op_set = true;
+  });
+}
+
+psara_status psara_set_data(psara_ctx* c, const double* Y, double epsilon) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(Y != nullptr, PSARA_EINVAL, "Y is NULL");
+    require(std::isfinite(epsilon) && epsilon > 0.0, PSARA_EINVAL, "epsilon must be finite and > 0");
+    const int64_t M = c->geo.M;
+    std::vector<double> ys((size_t)M * 8);
+    for (int64_t p = 0; p < M; ++p) {
+      const double* s = Y + 8 * c->geo.perm[p];
+      for (int k = 0; k < 8; ++k) {
+        require(std::isfinite(s[k]), PSARA_ENAN, "non-finite visibility");
+        ys[8 * p + k] = s[k];
+      }
+    }
+    with_engine(c, [&](auto& e) { e.set_data(ys.data(), epsilon); });
+    c->eps = epsilon;
+    c->data_set = true;
+  });
+}
+
+psara_status psara_set_prior(psara_ctx* c, uint32_t basis_mask, int levels, const double* weights, double gamma) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(basis_mask != 0 && basis_mask < (1u << 9), PSARA_EINVAL, "basis_mask must select bits 0..8");
+    const int n = c->geo.n;
+    require(levels >= 1 && levels <= psara::kMaxLevels && (n >> levels) >= 1 && n % (1 << levels) == 0,
+            PSARA_EINVAL, "levels must satisfy n divisible by 2^levels");
+    require(std::isfinite(gamma) && gamma > 0.0, PSARA_EINVAL, "gamma must be > 0");
+    c->mask = basis_mask;
+    const size_t J4 = coef_count(c) * 4;
+    if (weights)
+      for (size_t i = 0; i < J4; ++i) {
+        require(std::isfinite(weights[i]), PSARA_ENAN, "non-finite weight");
+        require(weights[i] >= 0.0, PSARA_EINVAL, "weights must be >= 0");
+      }
+    with_engine(c, [&](auto& e) { e.set_prior(basis_mask, levels, weights, gamma); });
+    c->levels = levels;
+    c->gamma = gamma;
+    c->prior_set = true;
+  });
+}
+
+psara_status psara_set_steps(psara_ctx* c, double tau, double rho1, double rho2, double rho3) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(c->norm_set, PSARA_ESTATE, "run psara_opnorm before setting steps");
+    require(tau > 0 && rho1 > 0 && rho2 > 0 && rho3 > 0 && std::isfinite(tau) && std::isfinite(rho1) &&
+                std::isfinite(rho2) && std::isfinite(rho3),
+            PSARA_EINVAL, "step sizes must be finite and > 0");
+    const double cond = 1.0 / tau - rho1 * 1.0 - rho2 * c->phi_norm_sq - rho3;
+    require(cond >= -1e-12 / tau, PSARA_EINVAL, "step sizes violate 1/tau - rho1 ||Psi||^2 - rho2 ||phi||^2 - rho3 >= 0");
+    with_engine(c, [&](auto& e) { e.set_steps(tau, rho1, rho2, rho3); });
+    c->tau = tau; c->rho1 = rho1; c->rho2 = rho2; c->rho3 = rho3;
+    c->steps_set = true;
+  });
+}
+
+psara_status psara_opnorm(psara_ctx* c, int max_iter, double rtol, double* phi_norm_sq) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(max_iter >= 1 && rtol >= 0.0, PSARA_EINVAL, "bad power-iteration parameters");
+    double lam = 0.0;
+    int its = 0;
+    if (c->f64) {
+      lam = c->f64->opnorm(max_iter, rtol, &its);
+    } else {
+      Engine<double> tmp(c->geo, c->stream);
+      lam = tmp.opnorm(max_iter, rtol, &its);
+    }
+    require(std::isfinite(lam) && lam > 0.0, PSARA_EDEVICE, "power iteration did not produce a positive norm");
+    c->phi_norm_sq = lam;
+    c->norm_set = true;
+    c->steps_set = false;
+    if (phi_norm_sq) *phi_norm_sq = lam;
+  });
+}
+
+psara_status psara_solve(psara_ctx* c, psara_mode mode, int iters, int check_every, psara_report* out) {
+  return guard(c, [&] { run_stage(c, primal_mode(mode), iters, check_every, out); });
+}
+
+psara_status psara_reweight(psara_ctx* c, double delta) {
+  return guard(c, [&] {
+    require(c->prior_set, PSARA_ESTATE, "prior not set");
+    require(std::isfinite(delta) && delta > 0.0, PSARA_EINVAL, "delta must be > 0");
+    with_engine(c, [&](auto& e) { e.reweight(delta); });
+  });
+}
+
+psara_status psara_coef_std(psara_ctx* c, double* out) {
+  return guard(c, [&] {
+    require(c->prior_set, PSARA_ESTATE, "prior not set");
+    require(out != nullptr, PSARA_EINVAL, "out is NULL");
+    with_engine(c, [&](auto& e) { *out = e.coef_std(); });
+  });
+}
+
+psara_status psara_reweighted_solve(psara_ctx* c, psara_mode mode, int cycles, const int* iters_per_stage,
+                                    double delta_decay, psara_report* out) {
+  return guard(c, [&] {
+    require(cycles >= 0 && iters_per_stage != nullptr, PSARA_EINVAL, "bad stage list");
+    require(delta_decay > 1.0 && std::isfinite(delta_decay), PSARA_EINVAL, "delta_decay must be > 1");
+    require(c->prior_set, PSARA_ESTATE, "prior not set");
+    for (int l = 0; l <= cycles; ++l) require(iters_per_stage[l] >= 0, PSARA_EINVAL, "negative iteration count");
+    const int pm = primal_mode(mode);
+    run_stage(c, psara::PM_INIT, iters_per_stage[0], 0, nullptr);
+    double delta = 0.0;
+    with_engine(c, [&](auto& e) { delta = e.coef_std(); });
+    require(delta > 0.0, PSARA_EINVAL, "initial estimate is zero: no reweighting scale");
+    for (int l = 1; l <= cycles; ++l) {
+      with_engine(c, [&](auto& e) { e.reweight(delta); });
+      run_stage(c, pm, iters_per_stage[l], 0, (l == cycles) ? out : nullptr);
+      delta /= delta_decay;
+    }
+    if (cycles == 0 && out) {
+      with_engine(c, [&](auto& e) { e.report(out); });
+      out->iterations = c->iterations;
+    }
+  });
+}
+
+psara_status psara_report_now(psara_ctx* c, psara_report* out) {
+  return guard(c, [&] {
+    require(c->op_set && c->data_set, PSARA_ESTATE, "operator and data must be set");
+    require(out != nullptr, PSARA_EINVAL, "out is NULL");
+    with_engine(c, [&](auto& e) { e.report(out); });
+    out->iterations = c->iterations;
+  });
+}
+
+psara_status psara_get_image(psara_ctx* c, double* S) {
+  return guard(c, [&] {
+    require(S != nullptr, PSARA_EINVAL, "S is NULL");
+    with_engine(c, [&](auto& e) { e.get_img(psara::IMG_S, S, 4); });
+  });
+}
+
+size_t psara_state_bytes(const psara_ctx* c) {
+  if (!c || !c->op_set) return 0;
+  const size_t N = (size_t)c->geo.n * c->geo.n;
+  const size_t J = c->prior_set ? coef_count(c) : 0;
+  return sizeof(double) * (N * 4 + N * 2 + J * 4 + (size_t)c->geo.M * 8 + N * 4 + N * 2);
+}
+
+psara_status psara_get_state(psara_ctx* c, void* buf, size_t bytes) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(buf != nullptr && bytes >= psara_state_bytes(c), PSARA_EINVAL, "state buffer too small");
+    with_engine(c, [&](auto& e) { e.get_state((double*)buf); });
+  });
+}
+
+psara_status psara_set_state(psara_ctx* c, const void* buf, size_t bytes) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(buf != nullptr && bytes >= psara_state_bytes(c), PSARA_EINVAL, "state buffer too small");
+    const double* d = (const double*)buf;
+    const size_t cnt = psara_state_bytes(c) / sizeof(double);
+    for (size_t i = 0; i < cnt; ++i) require(std::isfinite(d[i]), PSARA_ENAN, "non-finite state");
+    with_engine(c, [&](auto& e) { e.set_state(d); });
+  });
+}
+
+psara_status psara_reset_state(psara_ctx* c) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    with_engine(c, [&](auto& e) { e.zero_state(); });
+    c->iterations = 0;
+  });
+}
+
+size_t psara_footprint(int n, int64_t M, int taps, int levels, uint32_t basis_mask, psara_precision precision) {
+  if (!is_pow2(n) || M < 1 || levels < 1) return 0;
+  const size_t R = precision == PSARA_FP64 ? 8 : 4;
+  const size_t N = (size_t)n * n, K = 2 * (size_t)n;
+  const size_t ts = K >= 512 ? 32 : 16, ntiles = (K / ts) * (K / ts);
+  int nb = 0, nwav = 0;
+  for (int b = 0; b <= 8; ++b) nb += (basis_mask >> b) & 1u;
+  nwav = nb - (int)(basis_mask & 1u);
+  size_t llst = 0;
+  for (int l = 1; l < levels; ++l) llst += (size_t)(n >> l) * (n >> l);
+  const double spill = (1.0 + (taps - 1.0) / ts) * (1.0 + (taps - 1.0) / ts);
+  size_t b = 0;
+  b += N * 32 * R;                                   // 7 four-channel and 2 two-channel images
+  b += (size_t)M * (24 * R + 4 + 2 * R);             // Y, Bv, R; window starts; offsets
+  b += K * K * 8 * R + K * (size_t)n * 8 * R;        // grid and FFT intermediate
+  b += (2 * ntiles + 2) * 4 + (size_t)(spill * (double)M + 1) * 4;
+  b += 3 * (size_t)nb * N * 4 * R + (size_t)std::max(nwav, 1) * std::max<size_t>(llst, 1) * 4 * R;
+  const size_t parts = (size_t)M / 256 + ntiles + 8 * (N / 64 + 64);
+  b += 2 * parts * 8 + 64 * 8;
+  return b;
+}
+
+psara_status psara_apply_phi(psara_ctx* c, const double* S, double* Y) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(S && Y, PSARA_EINVAL, "NULL argument");
+    with_engine(c, [&](auto& e) { e.apply_phi(S, Y); });
+  });
+}
+
+psara_status psara_apply_phi_adjoint(psara_ctx* c, const double* B, double* S) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(S && B, PSARA_EINVAL, "NULL argument");
+    with_engine(c, [&](auto& e) { e.apply_phi_adjoint(B, S); });
+  });
+}
+
+psara_status psara_apply_psi_adjoint(psara_ctx* c, const double* S, double* A) {
+  return guard(c, [&] {
+    require(c->prior_set, PSARA_ESTATE, "prior not set");
+    require(S && A, PSARA_EINVAL, "NULL argument");
+    with_engine(c, [&](auto& e) { e.apply_psi_adjoint(S, A); });
+  });
+}
+
+psara_status psara_apply_psi(psara_ctx* c, const double* A, double* S) {
+  return guard(c, [&] {
+    require(c->prior_set, PSARA_ESTATE, "prior not set");
+    require(S && A, PSARA_EINVAL, "NULL argument");
+    with_engine(c, [&](auto& e) { e.apply_psi(A, S); });
+  });
+}
+
+int psara_layout(const psara_ctx* c, int64_t* perm) {
+  if (!c || !c->op_set) return PSARA_ESTATE;
+  if (perm)
+    for (int64_t p = 0; p < c->geo.M; ++p) perm[p] = c->geo.perm[p];
+  return c->geo.ts;
+}
+
+psara_status psara_time_pass(psara_ctx* c, int pass_id, int reps, double* avg_ms) {
+  return guard(c, [&] {
+    require(c->op_set && c->data_set && c->steps_set, PSARA_ESTATE, "solve set-up incomplete");
+    require((pass_id != 1 && pass_id != 2) || c->prior_set, PSARA_ESTATE, "prior not set");
+    require(pass_id >= 0 && pass_id <= 8 && reps >= 1 && avg_ms, PSARA_EINVAL, "bad pass id or reps");
+    with_engine(c, [&](auto& e) { *avg_ms = e.time_pass(pass_id, reps); });
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Internal types shared by the HIP kernels and the host engine.
+//
+// Every kernel works on a batch of independent solves: it receives an array of
+// problem descriptors (device memory) and a work list whose entry for
+// blockIdx.x names the problem and the piece of it (tile, line block, chunk)
+// that the workgroup processes.  A single solve is a batch of one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psara {
+
+constexpr int kMaxBases = 9;     // Dirac + Db1..Db8
+constexpr int kMaxFilter = 16;   // Db8 has 16 taps
+constexpr int kMaxTaps = 8;      // Kaiser-Bessel taps per dimension
+constexpr int kMaxCheb = 17;     // Chebyshev coefficients per tap (degree <= 16)
+constexpr int kMaxLevels = 8;
+
+// image-space buffers (N pixels x 4 Stokes, or x 2 for Z / D)
+enum ImgSlot { IMG_S = 0, IMG_X, IMG_C, IMG_PSIA, IMG_PHIB, IMG_TMP, IMG_TMP2, IMG_Z, IMG_D, NUM_IMG };
+// visibility-space buffers (M rows x 4 complex, sorted order)
+enum VisSlot { VIS_Y = 0, VIS_BV, VIS_R, NUM_VIS };
+// coefficient-space buffers (nbases * N x 4)
+enum CoefSlot { COEF_A = 0, COEF_GW, COEF_TMP, NUM_COEF };
+// FP64 scalar slots per problem
+enum Scalar {
+  SC_CFAC = 0,      // B = SC_CFAC * Bv (lazy l2-ball factor)
+  SC_VNORM2,        // ||B~/rho2 - Y||^2 of the last dual-B step
+  SC_RES2,          // ||Y - phi(S)||^2
+  SC_DOT,           // generic reduction results
+  SC_NRM2,
+  SC_RV0, SC_RV1, SC_RV2, SC_RV3,      // ||X - S||^2 per Stokes
+  SC_SN0, SC_SN1, SC_SN2, SC_SN3,      // ||2S - X||^2 per Stokes
+  SC_RIMG2,         // sum of squares of the Stokes-I residual image
+  SC_ZETA,
+  SC_NPCOUNT,
+  SC_OBJ,
+  SC_MEAN, SC_SQ,   // coefficient moments
+  NUM_SCALARS = 32
+};
+// Partial sums per problem, each a (sum, compensation) pair of doubles: first the de-grid
+// region (n_p6 pairs), then kGenQ generic regions of gen_stride pairs each.
+constexpr int kGenQ = 8;
+
+// Per-problem descriptor.  Pointers are typed by the engine's real type R.
+struct ProbDesc {
+  int n, K, T, levels;
+  int nbases, has_dirac, nwav, ts;      // ts = grid tile side
+  int ntile_side, deg, n_p6, gen_stride;
+  long long M;
+  double tau, rho1, rho2, rho3, eps, gamma, norm;   // norm = 1/sqrt(nbases)
+  double delta;                                     // reweighting delta in use
+  void* img[NUM_IMG];
+  void* vis[NUM_VIS];
+  void* coef[NUM_COEF];
+  void* ll;            // DWT level scratch: per wavelet basis, levels 1..L-1
+  long long ll_stride; // elements (V4) per basis in ll
+  void* grid;          // K*K cells of 4 complex, transposed layout [k2][k1]
+  void* half;          // K*n cells: FFT intermediate [k2][r]
+  const int* vis_k0;   // packed window starts (k1 << 16 | k2), sorted order
+  const void* vis_frac;   // (f1, f2) per vis, type R
+  const int* own_ptr;     // ntiles+1: sorted-vis range whose window starts in each tile
+  const int* list_ptr;    // ntiles+1: CSR into list_idx (every vis touching each tile)
+  const int* list_idx;
+  const void* cheb;       // T x (deg+1) Chebyshev coefficients, type R
+  const void* twiddle;    // K complex exp(-2 pi i j / K), type R
+  const void* deapod;     // n scaling factors 1/psi_hat((j - n/2)/K), type R
+  const void* filters;    // nwav x 16 low-pass filters (zero padded), type R
+  int wav_len[8];         // filter length of each wavelet basis
+  double* partials;       // [n_p6 pairs][kGenQ x gen_stride pairs]
+  double* scal;           // NUM_SCALARS
+  long long ll_off[kMaxLevels + 1];  // element offset of level l's LL inside a basis block
+};
+
+// --------------------------------------------------------------------------------------------
+// small vector types
+template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
+template <typename R> struct alignas(2 * sizeof(R)) V2 { R x, y; };
+template <typename R> struct cplx { R re, im; };
+// one grid cell: the four Stokes channels, complex (32 B in FP32, 64 B in FP64)
+template <typename R> struct alignas(16) Cell { cplx<R> s[4]; };
+
+template <typename R> __host__ __device__ inline cplx<R> cmk(R a, R b) { cplx<R> c; c.re = a; c.im = b; return c; }
+template <typename R> __host__ __device__ inline cplx<R> cadd(cplx<R> a, cplx<R> b) { return cmk(a.re + b.re, a.im + b.im); }
+template <typename R> __host__ __device__ inline cplx<R> csub(cplx<R> a, cplx<R> b) { return cmk(a.re - b.re, a.im - b.im); }
+template <typename R> __host__ __device__ inline cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R> __host__ __device__ inline cplx<R> cscale(cplx<R> a, R s) { return cmk(a.re * s, a.im * s); }
+template <typename R> __host__ __device__ inline cplx<R> cmuli(cplx<R> a) { return cmk(-a.im, a.re); }   // i * a
+template <typename R> __host__ __device__ inline cplx<R> cconj(cplx<R> a) { return cmk(a.re, -a.im); }
+
+// --------------------------------------------------------------------------------------------
+// compensated FP64 sums (Neumaier), combinable in a fixed tree
+struct KSum {
+  double s, c;
+  __host__ __device__ KSum() : s(0.0), c(0.0) {}
+  __host__ __device__ void add(double v) {
+    double t = s + v;
+    if (fabs(s) >= fabs(v)) c += (s - t) + v; else c += (v - t) + s;
+    s = t;
+  }
+  __host__ __device__ void merge(const KSum& o) { add(o.s); c += o.c; }
+  __host__ __device__ double value() const { return s + c; }
+};
+
+__device__ inline KSum wave_reduce(KSum k) {
+  for (int off = 32; off > 0; off >>= 1) {
+    KSum o;
+    o.s = __shfl_xor(k.s, off, 64);
+    o.c = __shfl_xor(k.c, off, 64);
+    k.merge(o);
+  }
+  return k;
+}
+
+// Block-wide deterministic reduction; every thread returns the same total.
+// `scratch` must hold 2 * (blockDim.x / 64) doubles of shared memory.
+__device__ inline KSum block_reduce(KSum k, double* scratch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  k = wave_reduce(k);
+  __syncthreads();
+  if (lane == 0) { scratch[2 * wave] = k.s; scratch[2 * wave + 1] = k.c; }
+  __syncthreads();
+  KSum t;
+  for (int w = 0; w < nw; ++w) { KSum o; o.s = scratch[2 * w]; o.c = scratch[2 * w + 1]; t.merge(o); }
+  __syncthreads();
+  return t;
+}
+
+// Sum `count` (s, c) pairs from `parts` in a fixed order with the whole block.
+__device__ inline double block_sum_partials(const double* parts, int count, double* scratch) {
+  KSum k;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    KSum o; o.s = parts[2 * i]; o.c = parts[2 * i + 1]; k.merge(o);
+  }
+  return block_reduce(k, scratch).value();
+}
+
+// --------------------------------------------------------------------------------------------
+// Kaiser-Bessel weights: the T weights psi(f - i), i = 0..T-1, of one dimension.  With the
+// window start k0 = ceil(t - T/2) the fractional offset f = t - k0 lies in (T/2 - 1, T/2], so
+// every tap's argument spans one unit interval and u = 2f - T + 1 in (-1, 1] is common to all
+// taps.  Each tap carries its own Chebyshev expansion on that interval.
+template <typename R>
+__device__ inline void kb_weights(R f, int T, int deg, const R* __restrict__ cheb, R* w) {
+  const R u = R(2) * f - R(T - 1);
+  R tk[kMaxCheb];
+  tk[0] = R(1);
+  tk[1] = u;
+#pragma unroll
+  for (int k = 2; k < kMaxCheb; ++k) tk[k] = (k <= deg) ? R(2) * u * tk[k - 1] - tk[k - 2] : R(0);
+#pragma unroll
+  for (int i = 0; i < kMaxTaps; ++i) {
+    R acc = R(0);
+    if (i < T) {
+#pragma unroll
+      for (int k = 0; k < kMaxCheb; ++k)
+        if (k <= deg) acc += cheb[i * (deg + 1) + k] * tk[k];
+    }
+    w[i] = acc;
+  }
+}
+
+}  // namespace psara

@@ -1,0 +1,727 @@
+// Host side of the library: set-up (visibility sorting and tile binning, tables), device
+// memory of one solve, the pass sequence of one Algorithm-1 iteration captured as a HIP
+// graph, the FP64 power iteration, the stopping quantities, and the C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "engine.hpp"
+#include "launch.hpp"
+#include "psara.h"
+
+namespace psara {
+
+std::vector<double> daubechies(int p);
+double kb_beta(int taps, double alpha);
+double kb_hat(int taps, double beta, double nu);
+std::vector<double> kb_chebyshev(int taps, double beta, int deg);
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(PSARA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------------------------------------
+// geometry: window starts, fractional offsets, sorting by grid tile, per-tile lists
+Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
+  Geometry g;
+  g.n = n; g.K = alpha * n; g.T = T; g.M = M;
+  g.ts = (g.K >= 512) ? 32 : 16;
+  g.nts = g.K / g.ts;
+  g.beta = kb_beta(T, alpha);
+  const int K = g.K, ts = g.ts, nts = g.nts;
+  const int ntiles = nts * nts;
+  std::vector<int> k1(M), k2(M), tile(M);
+  std::vector<double> f1(M), f2(M);
+  for (int64_t m = 0; m < M; ++m) {
+    const double w0 = uv[2 * m], w1 = uv[2 * m + 1];
+    if (!(w0 >= -M_PI && w0 < M_PI && w1 >= -M_PI && w1 < M_PI))
+      throw Error(PSARA_EINVAL, "uv point outside [-pi, pi)");
+    const double t1 = (double)K * w0 / (2.0 * M_PI), t2 = (double)K * w1 / (2.0 * M_PI);
+    const double c1 = std::ceil(t1 - T / 2.0), c2 = std::ceil(t2 - T / 2.0);
+    f1[m] = t1 - c1; f2[m] = t2 - c2;
+    k1[m] = ((int)c1) & (K - 1);
+    k2[m] = ((int)c2) & (K - 1);
+    tile[m] = (k1[m] / ts) * nts + k2[m] / ts;
+  }
+  std::vector<int64_t> order(M);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    if (tile[a] != tile[b]) return tile[a] < tile[b];
+    if (k1[a] != k1[b]) return k1[a] < k1[b];
+    return k2[a] < k2[b];
+  });
+  g.perm = order;
+  g.k0.resize(M);
+  g.frac.resize(2 * M);
+  g.own_ptr.assign(ntiles + 1, 0);
+  for (int64_t p = 0; p < M; ++p) {
+    const int64_t m = order[p];
+    g.k0[p] = (k1[m] << 16) | k2[m];
+    g.frac[2 * p] = f1[m];
+    g.frac[2 * p + 1] = f2[m];
+    g.own_ptr[tile[m] + 1]++;
+  }
+  for (int t = 0; t < ntiles; ++t) g.own_ptr[t + 1] += g.own_ptr[t];
+  // every tile a window touches (at most two per dimension since T <= ts)
+  auto touched = [&](int k, int* out) {
+    out[0] = k / ts;
+    const int e = ((k + T - 1) & (K - 1)) / ts;
+    if (e != out[0]) { out[1] = e; return 2; }
+    return 1;
+  };
+  g.list_ptr.assign(ntiles + 1, 0);
+  for (int64_t p = 0; p < M; ++p) {
+    int a[2], b[2];
+    const int na = touched(g.k0[p] >> 16, a), nb = touched(g.k0[p] & 0xffff, b);
+    for (int i = 0; i < na; ++i)
+      for (int j = 0; j < nb; ++j) g.list_ptr[a[i] * nts + b[j] + 1]++;
+  }
+  for (int t = 0; t < ntiles; ++t) g.list_ptr[t + 1] += g.list_ptr[t];
+  g.list_idx.resize(g.list_ptr[ntiles]);
+  std::vector<int> fillp(g.list_ptr.begin(), g.list_ptr.end() - 1);
+  for (int64_t p = 0; p < M; ++p) {
+    int a[2], b[2];
+    const int na = touched(g.k0[p] >> 16, a), nb = touched(g.k0[p] & 0xffff, b);
+    for (int i = 0; i < na; ++i)
+      for (int j = 0; j < nb; ++j) g.list_idx[fillp[a[i] * nts + b[j]]++] = (int)p;
+  }
+  return g;
+}
+
+// ------------------------------------------------------------------------------------------------
+// work lists (appended per problem, so batches concatenate them)
+void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int* n_p6) {
+  const int n = g.n, K = g.K, N = n * n;
+  const int lines = cells / K;
+  for (int b = 0; b < (N + 255) / 256; ++b) S.img.push_back(make_int4(prob, b, 0, 0));
+  for (int l = 0; l < n; l += lines) S.rows.push_back(make_int4(prob, l, 0, 0));
+  for (int l = 0; l < K; l += lines) S.cols.push_back(make_int4(prob, l, 0, 0));
+  const int ntiles = g.nts * g.nts;
+  int part = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += 256) S.p6.push_back(make_int4(prob, t, v, part++));
+  }
+  for (int t = 0; t < ntiles; ++t) S.p7.push_back(make_int4(prob, t, t == 0 ? 1 : 0, 0));
+  *n_p6 = part;
+}
+
+void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int* n_ana_parts) {
+  const int TO = fp64 ? 8 : 16, TS = fp64 ? 16 : 32;
+  const int N = n * n;
+  int part = 0;
+  for (int b = 0; b < (N + 255) / 256; ++b) S.dirac.push_back(make_int4(prob, b, 0, part++));
+  for (int l = 1; l <= levels; ++l) {
+    const int h = n >> l;
+    const int to = std::min(TO, h), tps = h / to;
+    for (int w = 0; w < nwav; ++w)
+      for (int t = 0; t < tps * tps; ++t) S.ana[l].push_back(make_int4(prob, w, t, part++));
+  }
+  for (int l = 2; l <= levels; ++l) {
+    const int m = n >> (l - 1);
+    const int to = std::min(TS, m), tps = m / to;
+    for (int w = 0; w < nwav; ++w)
+      for (int t = 0; t < tps * tps; ++t) S.syn[l].push_back(make_int4(prob, w, t, 0));
+  }
+  {
+    const int to = std::min(TS, n), tps = n / to;
+    for (int t = 0; t < tps * tps; ++t) S.synfinal.push_back(make_int4(prob, t, 0, 0));
+  }
+  *n_ana_parts = part;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Engine<R>
+template <typename R>
+Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) {
+  hip_check(hipStreamCreateWithFlags(&s1_, hipStreamNonBlocking), "hipStreamCreate");
+  hip_check(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming), "hipEventCreate");
+  hip_check(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming), "hipEventCreate");
+  std::memset(&h_, 0, sizeof(h_));
+  const int n = g.n, K = g.K, N = n * n;
+  const int64_t M = g.M;
+  cells_ = std::max(512, K);
+  h_.n = n; h_.K = K; h_.T = g.T; h_.M = M;
+  h_.ts = g.ts; h_.ntile_side = g.nts;
+  h_.deg = std::is_same<R, double>::value ? 16 : 10;
+  for (int s = 0; s < IMG_Z; ++s) h_.img[s] = dalloc<V4<R>>(N);
+  h_.img[IMG_Z] = dalloc<V2<R>>(N);
+  h_.img[IMG_D] = dalloc<V2<R>>(N);
+  for (int s = 0; s < NUM_VIS; ++s) h_.vis[s] = dalloc<Cell<R>>(M);
+  h_.grid = dalloc<Cell<R>>((size_t)K * K);
+  h_.half = dalloc<Cell<R>>((size_t)K * n);
+  // geometry
+  h_.vis_k0 = upload<int>(g.k0.data(), M);
+  h_.vis_frac = upload_conv(g.frac.data(), 2 * M);
+  h_.own_ptr = upload<int>(g.own_ptr.data(), g.own_ptr.size());
+  h_.list_ptr = upload<int>(g.list_ptr.data(), g.list_ptr.size());
+  h_.list_idx = upload<int>(g.list_idx.data(), std::max<size_t>(1, g.list_idx.size()));
+  // tables
+  std::vector<double> cheb = kb_chebyshev(g.T, g.beta, h_.deg);
+  h_.cheb = upload_conv(cheb.data(), cheb.size());
+  std::vector<double> tw(2 * K);
+  for (int j = 0; j < K; ++j) {
+    const double a = -2.0 * M_PI * (double)j / (double)K;
+    tw[2 * j] = std::cos(a);
+    tw[2 * j + 1] = std::sin(a);
+  }
+  h_.twiddle = upload_conv(tw.data(), tw.size());
+  std::vector<double> s(n);
+  for (int j = 0; j < n; ++j) s[j] = 1.0 / kb_hat(g.T, g.beta, (double)(j - n / 2) / (double)K);
+  h_.deapod = upload_conv(s.data(), n);
+  set_grid_kernel_limits<R>(g.ts, g.T);
+  // items of the operator passes
+  add_operator_items(items_, 0, g, cells_, &h_.n_p6);
+  gen_parts_ = (N + 255) / 256;
+  realloc_partials();
+  h_.scal = dalloc<double>(NUM_SCALARS);
+  zero(h_.scal, NUM_SCALARS * sizeof(double));
+  zero_state();
+  upload_items();
+}
+
+template <typename R>
+Engine<R>::~Engine() {
+  for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  graphs_.clear();
+  (void)hipStreamSynchronize(s0_);
+  (void)hipStreamSynchronize(s1_);
+  for (void* p : allocs_) (void)hipFree(p);
+  (void)hipEventDestroy(ev_fork_);
+  (void)hipEventDestroy(ev_join_);
+  (void)hipStreamDestroy(s1_);
+}
+
+template <typename R>
+template <typename T>
+T* Engine<R>::dalloc(size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(PSARA_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  allocs_.push_back(p);
+  bytes_ += count * sizeof(T);
+  return (T*)p;
+}
+
+template <typename R>
+void Engine<R>::dfree(void* p) {
+  if (!p) return;
+  auto it = std::find(allocs_.begin(), allocs_.end(), p);
+  if (it != allocs_.end()) { allocs_.erase(it); (void)hipFree(p); }
+}
+
+template <typename R>
+template <typename T>
+T* Engine<R>::upload(const T* host, size_t count) {
+  T* d = dalloc<T>(count);
+  hip_check(hipMemcpy(d, host, count * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+  return d;
+}
+
+template <typename R>
+R* Engine<R>::upload_conv(const double* host, size_t count) {
+  std::vector<R> tmp(count);
+  for (size_t i = 0; i < count; ++i) tmp[i] = (R)host[i];
+  return upload<R>(tmp.data(), count);
+}
+
+template <typename R>
+void Engine<R>::zero(void* p, size_t bytes) {
+  hip_check(hipMemsetAsync(p, 0, bytes, s0_), "hipMemsetAsync");
+}
+
+template <typename R>
+void Engine<R>::realloc_partials() {
+  const int stride = std::max(gen_parts_, 1);
+  h_.gen_stride = stride;
+  const size_t count = 2 * ((size_t)h_.n_p6 + (size_t)kGenQ * stride);
+  if (h_.partials) dfree(h_.partials);
+  h_.partials = dalloc<double>(count);
+  zero(h_.partials, count * sizeof(double));
+}
+
+template <typename R>
+void Engine<R>::upload_items() {
+  auto up = [&](DevItems& d, const std::vector<int4>& v) {
+    if (d.ptr) dfree(d.ptr);
+    d.ptr = nullptr;
+    d.count = (int)v.size();
+    if (!v.empty()) d.ptr = upload<int4>(v.data(), v.size());
+  };
+  up(d_img_, items_.img); up(d_rows_, items_.rows); up(d_cols_, items_.cols);
+  up(d_p6_, items_.p6); up(d_p7_, items_.p7); up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal);
+  for (int l = 0; l <= kMaxLevels; ++l) { up(d_ana_[l], items_.ana[l]); up(d_syn_[l], items_.syn[l]); }
+  if (!d_desc_) d_desc_ = dalloc<ProbDesc>(1);
+  desc_dirty_ = true;
+}
+
+template <typename R>
+void Engine<R>::sync_desc() {
+  if (!desc_dirty_) return;
+  hip_check(hipMemcpyAsync(d_desc_, &h_, sizeof(ProbDesc), hipMemcpyHostToDevice, s0_), "desc upload");
+  hip_check(hipStreamSynchronize(s0_), "desc upload sync");
+  desc_dirty_ = false;
+}
+
+template <typename R>
+void Engine<R>::zero_state() {
+  const size_t N = (size_t)geo_.n * geo_.n;
+  for (int s = 0; s < IMG_Z; ++s) zero(h_.img[s], N * sizeof(V4<R>));
+  zero(h_.img[IMG_Z], N * sizeof(V2<R>));
+  zero(h_.img[IMG_D], N * sizeof(V2<R>));
+  zero(h_.vis[VIS_BV], (size_t)geo_.M * sizeof(Cell<R>));
+  zero(h_.vis[VIS_R], (size_t)geo_.M * sizeof(Cell<R>));
+  if (h_.coef[COEF_A]) zero(h_.coef[COEF_A], coef_elems_ * sizeof(V4<R>));
+  zero(h_.scal, NUM_SCALARS * sizeof(double));
+  hip_check(hipStreamSynchronize(s0_), "zero state");
+}
+
+template <typename R>
+void Engine<R>::set_data(const double* Y_sorted, double eps) {
+  const int64_t M = geo_.M;
+  std::vector<R> tmp((size_t)M * 8);
+  for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (R)Y_sorted[i];
+  hip_check(hipMemcpy(h_.vis[VIS_Y], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice), "Y upload");
+  h_.eps = eps;
+  desc_dirty_ = true;
+}
+
+template <typename R>
+void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, double gamma) {
+  const int n = geo_.n, N = n * n;
+  // release a previous prior
+  for (int c = 0; c < NUM_COEF; ++c) { dfree(h_.coef[c]); h_.coef[c] = nullptr; }
+  dfree(h_.ll); h_.ll = nullptr;
+  dfree((void*)h_.filters); h_.filters = nullptr;
+  items_.dirac.clear(); items_.synfinal.clear();
+  for (int l = 0; l <= kMaxLevels; ++l) { items_.ana[l].clear(); items_.syn[l].clear(); }
+  h_.has_dirac = (mask & 1u) ? 1 : 0;
+  int nwav = 0;
+  std::vector<double> filt(8 * kMaxFilter, 0.0);
+  for (int p = 1; p <= 8; ++p)
+    if (mask & (1u << p)) {
+      std::vector<double> hf = daubechies(p);
+      for (int j = 0; j < 2 * p; ++j) filt[nwav * kMaxFilter + j] = hf[j];
+      h_.wav_len[nwav] = 2 * p;
+      ++nwav;
+    }
+  h_.nwav = nwav;
+  h_.nbases = nwav + h_.has_dirac;
+  h_.levels = levels;
+  h_.norm = 1.0 / std::sqrt((double)h_.nbases);
+  h_.gamma = gamma;
+  h_.filters = upload_conv(filt.data(), filt.size());
+  coef_elems_ = (size_t)h_.nbases * N;
+  for (int c = 0; c < NUM_COEF; ++c) h_.coef[c] = dalloc<V4<R>>(coef_elems_);
+  long long off = 0;
+  h_.ll_off[0] = 0;
+  for (int l = 1; l <= kMaxLevels; ++l) {
+    h_.ll_off[l] = off;
+    if (l < levels) off += (long long)(n >> l) * (n >> l);
+  }
+  h_.ll_stride = std::max<long long>(off, 1);
+  h_.ll = dalloc<V4<R>>((size_t)std::max(nwav, 1) * h_.ll_stride);
+  // thresholds gamma * W
+  std::vector<R> gw(coef_elems_ * 4);
+  for (size_t i = 0; i < gw.size(); ++i) gw[i] = (R)(gamma * (weights ? weights[i] : 1.0));
+  hip_check(hipMemcpy(h_.coef[COEF_GW], gw.data(), gw.size() * sizeof(R), hipMemcpyHostToDevice), "weights upload");
+  zero(h_.coef[COEF_A], coef_elems_ * sizeof(V4<R>));
+  int nap = 0;
+  add_prior_items(items_, 0, n, levels, nwav, std::is_same<R, double>::value, &nap);
+  ana_parts_ = nap;
+  gen_parts_ = std::max((N + 255) / 256, nap);
+  realloc_partials();
+  upload_items();
+  invalidate_graphs();
+  // the state's Psi A is zero again
+  zero(h_.img[IMG_PSIA], (size_t)N * sizeof(V4<R>));
+  hip_check(hipStreamSynchronize(s0_), "set_prior");
+}
+
+template <typename R>
+void Engine<R>::set_steps(double tau, double r1, double r2, double r3) {
+  h_.tau = tau; h_.rho1 = r1; h_.rho2 = r2; h_.rho3 = r3;
+  desc_dirty_ = true;
+}
+
+template <typename R>
+LaunchArgs Engine<R>::la(const DevItems& d, hipStream_t s) const {
+  LaunchArgs a;
+  a.descs = d_desc_;
+  a.items = d.ptr;
+  a.nitems = d.count;
+  a.stream = s ? s : s0_;
+  return a;
+}
+
+// ---- passes --------------------------------------------------------------------------------------
+template <typename R> void Engine<R>::p1(int mode, hipStream_t s) { launch_primal<R>(mode, la(d_img_, s)); }
+template <typename R> void Engine<R>::p2(hipStream_t s) {
+  for (int l = 1; l <= h_.levels; ++l) launch_analysis<R>(AM_DUAL, l, la(d_ana_[l], s), IMG_X, COEF_A);
+}
+template <typename R> void Engine<R>::p3(int src_coef, int dst_slot, int add_dirac, hipStream_t s) {
+  for (int l = h_.levels; l >= 2; --l) launch_synthesis<R>(l, h_.levels, la(d_syn_[l], s), src_coef, 0);
+  launch_synthesis_final<R>(la(d_synfinal_, s), src_coef, dst_slot, add_dirac);
+}
+template <typename R> void Engine<R>::p4(int src, hipStream_t s) { launch_fft<R>(0, la(d_rows_, s), cells_, src, 0); }
+template <typename R> void Engine<R>::p5(hipStream_t s) { launch_fft<R>(1, la(d_cols_, s), cells_, 0, 0); }
+template <typename R> void Engine<R>::p6(int mode, int src, int out, hipStream_t s) {
+  launch_degrid<R>(mode, la(d_p6_, s), geo_.ts, geo_.T, src, out);
+}
+template <typename R> void Engine<R>::p7(int mode, int src, int use_cfac, hipStream_t s) {
+  launch_grid<R>(mode, la(d_p7_, s), geo_.ts, src, use_cfac);
+}
+template <typename R> void Engine<R>::p8(hipStream_t s) { launch_fft<R>(2, la(d_cols_, s), cells_, 0, 0); }
+template <typename R> void Engine<R>::p9(int dst, hipStream_t s) { launch_fft<R>(3, la(d_rows_, s), cells_, 0, dst); }
+
+template <typename R>
+void Engine<R>::forward(int src_img, int mode, int out_vis) {
+  p4(src_img); p5(); p6(mode, VIS_BV, out_vis);
+}
+template <typename R>
+void Engine<R>::adjoint(int src_vis, int use_cfac, int dst_img) {
+  p7(GR_PLAIN, src_vis, use_cfac); p8(); p9(dst_img);
+}
+
+template <typename R>
+void Engine<R>::launch_iteration(int mode) {
+  p1(mode, s0_);
+  const bool sparse = (mode != PM_INIT) && h_.coef[COEF_A] && h_.nwav > 0;
+  if (sparse) {
+    hip_check(hipEventRecord(ev_fork_, s0_), "event record");
+    hip_check(hipStreamWaitEvent(s1_, ev_fork_, 0), "stream wait");
+    p2(s1_);
+    p3(COEF_A, IMG_PSIA, 0, s1_);
+    hip_check(hipEventRecord(ev_join_, s1_), "event record");
+  }
+  p4(IMG_X, s0_);
+  p5(s0_);
+  p6(DG_DUAL, VIS_BV, VIS_BV, s0_);
+  p7(GR_DUAL, VIS_BV, 0, s0_);
+  p8(s0_);
+  p9(IMG_PHIB, s0_);
+  if (sparse) hip_check(hipStreamWaitEvent(s0_, ev_join_, 0), "stream wait");
+}
+
+template <typename R>
+void Engine<R>::invalidate_graphs() {
+  for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  graphs_.clear();
+}
+
+template <typename R>
+void Engine<R>::run(int mode, int iters) {
+  sync_desc();
+  if (iters <= 0) return;
+  constexpr int kChunk = 8;
+  auto get_graph = [&](int count) -> hipGraphExec_t {
+    const int key = mode * 1000 + count;
+    auto it = graphs_.find(key);
+    if (it != graphs_.end()) return it->second;
+    hipGraph_t graph = nullptr;
+    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeThreadLocal), "begin capture");
+    for (int k = 0; k < count; ++k) launch_iteration(mode);
+    hip_check(hipStreamEndCapture(s0_, &graph), "end capture");
+    hipGraphExec_t exec = nullptr;
+    hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(graph);
+    graphs_[key] = exec;
+    return exec;
+  };
+  int left = iters;
+  if (left >= kChunk) {
+    hipGraphExec_t g = get_graph(kChunk);
+    while (left >= kChunk) { hip_check(hipGraphLaunch(g, s0_), "graph launch"); left -= kChunk; }
+  }
+  if (left > 0) {
+    hipGraphExec_t g = get_graph(1);
+    for (; left > 0; --left) hip_check(hipGraphLaunch(g, s0_), "graph launch");
+  }
+  hip_check(hipGetLastError(), "iteration launch");
+}
+
+template <typename R>
+void Engine<R>::run_eager(int mode, int iters) {
+  sync_desc();
+  for (int k = 0; k < iters; ++k) launch_iteration(mode);
+  hip_check(hipGetLastError(), "iteration launch");
+}
+
+// ---- reductions ---------------------------------------------------------------------------------
+template <typename R>
+void Engine<R>::finalize(int q, int count, int scalar) { launch_finalize(d_desc_, 1, q, count, scalar, s0_); }
+
+template <typename R>
+void Engine<R>::read_scalars(double* out) {
+  hip_check(hipMemcpyAsync(out, h_.scal, NUM_SCALARS * sizeof(double), hipMemcpyDeviceToHost, s0_), "scalars D2H");
+  hip_check(hipStreamSynchronize(s0_), "scalars sync");
+}
+
+template <typename R>
+void Engine<R>::write_scalar(int idx, double v) {
+  hip_check(hipMemcpyAsync(h_.scal + idx, &v, sizeof(double), hipMemcpyHostToDevice, s0_), "scalar H2D");
+  hip_check(hipStreamSynchronize(s0_), "scalar sync");
+}
+
+template <typename R>
+void Engine<R>::report(psara_report* r) {
+  sync_desc();
+  const int nimg = d_img_.count;
+  // residual ||phi(S) - Y|| and the residual image
+  forward(IMG_S, DG_RESIDUAL, VIS_R);
+  finalize(-1, 0, SC_RES2);
+  adjoint(VIS_R, 0, IMG_TMP);
+  launch_img_sumsq<R>(la(d_img_), IMG_TMP, 0, 0);
+  finalize(0, nimg, SC_RIMG2);
+  launch_finalize_zeta(d_desc_, 1, s0_);
+  launch_npcount<R>(la(d_img_));
+  finalize(0, nimg, SC_NPCOUNT);
+  launch_relvar<R>(la(d_img_));
+  for (int q = 0; q < 4; ++q) { finalize(q, nimg, SC_RV0 + q); finalize(4 + q, nimg, SC_SN0 + q); }
+  const bool prior = h_.coef[COEF_A] != nullptr;
+  if (prior) {
+    if (h_.has_dirac) launch_dirac<R>(AM_OBJECTIVE, la(d_dirac_), IMG_S, 0);
+    for (int l = 1; l <= h_.levels; ++l) launch_analysis<R>(AM_OBJECTIVE, l, la(d_ana_[l]), IMG_S, 0);
+    finalize(0, ana_parts_, SC_OBJ);
+  }
+  hip_check(hipGetLastError(), "report launch");
+  double sc[NUM_SCALARS];
+  read_scalars(sc);
+  const double N = (double)geo_.n * geo_.n;
+  r->residual = std::sqrt(std::max(sc[SC_RES2], 0.0));
+  r->epsilon = h_.eps;
+  for (int q = 0; q < 4; ++q) {
+    const double num = std::sqrt(sc[SC_RV0 + q]), den = std::sqrt(sc[SC_SN0 + q]);
+    r->rel_var[q] = den > 0.0 ? num / den : INFINITY;
+  }
+  r->zeta = sc[SC_ZETA];
+  r->n_p = 100.0 * sc[SC_NPCOUNT] / N;
+  r->objective = prior ? sc[SC_OBJ] / h_.gamma : 0.0;
+  r->vnorm = std::sqrt(std::max(sc[SC_VNORM2], 0.0));
+}
+
+template <typename R>
+double Engine<R>::coef_std() {
+  sync_desc();
+  if (h_.has_dirac) launch_dirac<R>(AM_MOMENTS, la(d_dirac_), IMG_S, 0);
+  for (int l = 1; l <= h_.levels; ++l) launch_analysis<R>(AM_MOMENTS, l, la(d_ana_[l]), IMG_S, 0);
+  finalize(0, ana_parts_, SC_MEAN);
+  finalize(1, ana_parts_, SC_SQ);
+  hip_check(hipGetLastError(), "moments launch");
+  double sc[NUM_SCALARS];
+  read_scalars(sc);
+  const double cnt = 4.0 * (double)coef_elems_;
+  const double mean = sc[SC_MEAN] / cnt;
+  return std::sqrt(std::max(sc[SC_SQ] / cnt - mean * mean, 0.0));
+}
+
+template <typename R>
+void Engine<R>::reweight(double delta) {
+  h_.delta = delta;
+  desc_dirty_ = true;
+  sync_desc();
+  if (h_.has_dirac) launch_dirac<R>(AM_REWEIGHT, la(d_dirac_), IMG_S, 0);
+  for (int l = 1; l <= h_.levels; ++l) launch_analysis<R>(AM_REWEIGHT, l, la(d_ana_[l]), IMG_S, 0);
+  hip_check(hipGetLastError(), "reweight launch");
+  hip_check(hipStreamSynchronize(s0_), "reweight sync");
+}
+
+// FP64 power iteration of S -> Re phi^dagger phi S (Rayleigh quotient of a unit vector)
+template <typename R>
+double Engine<R>::opnorm(int max_iter, double rtol, int* iters_out) {
+  sync_desc();
+  const size_t N = (size_t)geo_.n * geo_.n;
+  std::mt19937_64 rng(12345);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  std::vector<R> x0(N * 4);
+  for (auto& v : x0) v = (R)nd(rng);
+  hip_check(hipMemcpy(h_.img[IMG_TMP2], x0.data(), x0.size() * sizeof(R), hipMemcpyHostToDevice), "x0 upload");
+  const int nimg = d_img_.count;
+  launch_img_dot<R>(la(d_img_), IMG_TMP2, IMG_TMP2);
+  finalize(1, nimg, SC_NRM2);
+  launch_img_scale<R>(la(d_img_), IMG_TMP2, IMG_TMP2, SC_NRM2);
+  double lam = 0.0;
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    forward(IMG_TMP2, DG_FORWARD, VIS_R);
+    adjoint(VIS_R, 0, IMG_TMP);
+    launch_img_dot<R>(la(d_img_), IMG_TMP2, IMG_TMP);
+    finalize(0, nimg, SC_DOT);
+    finalize(1, nimg, SC_NRM2);
+    launch_img_scale<R>(la(d_img_), IMG_TMP2, IMG_TMP, SC_NRM2);
+    hip_check(hipGetLastError(), "power iteration launch");
+    double sc[NUM_SCALARS];
+    read_scalars(sc);
+    const double lam_new = sc[SC_DOT];
+    if (it > 0 && std::fabs(lam_new - lam) <= rtol * std::fabs(lam_new)) { lam = lam_new; ++it; break; }
+    lam = lam_new;
+  }
+  if (iters_out) *iters_out = it;
+  return lam;
+}
+
+// ---- host <-> device images, coefficients, visibilities ------------------------------------------
+template <typename R>
+void Engine<R>::put_img(int slot, const double* src, int comps) {
+  const size_t cnt = (size_t)geo_.n * geo_.n * comps;
+  std::vector<R> tmp(cnt);
+  for (size_t i = 0; i < cnt; ++i) tmp[i] = (R)src[i];
+  hip_check(hipMemcpy(h_.img[slot], tmp.data(), cnt * sizeof(R), hipMemcpyHostToDevice), "image upload");
+}
+template <typename R>
+void Engine<R>::get_img(int slot, double* dst, int comps) {
+  hip_check(hipStreamSynchronize(s0_), "sync");
+  const size_t cnt = (size_t)geo_.n * geo_.n * comps;
+  std::vector<R> tmp(cnt);
+  hip_check(hipMemcpy(tmp.data(), h_.img[slot], cnt * sizeof(R), hipMemcpyDeviceToHost), "image download");
+  for (size_t i = 0; i < cnt; ++i) dst[i] = (double)tmp[i];
+}
+template <typename R>
+void Engine<R>::put_coef(int slot, const double* src) {
+  std::vector<R> tmp(coef_elems_ * 4);
+  for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (R)src[i];
+  hip_check(hipMemcpy(h_.coef[slot], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice), "coef upload");
+}
+template <typename R>
+void Engine<R>::get_coef(int slot, double* dst) {
+  hip_check(hipStreamSynchronize(s0_), "sync");
+  std::vector<R> tmp(coef_elems_ * 4);
+  hip_check(hipMemcpy(tmp.data(), h_.coef[slot], tmp.size() * sizeof(R), hipMemcpyDeviceToHost), "coef download");
+  for (size_t i = 0; i < tmp.size(); ++i) dst[i] = (double)tmp[i];
+}
+// visibilities: caller order <-> sorted order, optional scale
+template <typename R>
+void Engine<R>::put_vis(int slot, const double* src) {
+  const int64_t M = geo_.M;
+  std::vector<R> tmp((size_t)M * 8);
+  for (int64_t p = 0; p < M; ++p) {
+    const double* s = src + 8 * geo_.perm[p];
+    for (int k = 0; k < 8; ++k) tmp[8 * p + k] = (R)s[k];
+  }
+  hip_check(hipMemcpy(h_.vis[slot], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice), "vis upload");
+}
+template <typename R>
+void Engine<R>::get_vis(int slot, double* dst, double scale) {
+  hip_check(hipStreamSynchronize(s0_), "sync");
+  const int64_t M = geo_.M;
+  std::vector<R> tmp((size_t)M * 8);
+  hip_check(hipMemcpy(tmp.data(), h_.vis[slot], tmp.size() * sizeof(R), hipMemcpyDeviceToHost), "vis download");
+  for (int64_t p = 0; p < M; ++p) {
+    double* d = dst + 8 * geo_.perm[p];
+    for (int k = 0; k < 8; ++k) d[k] = scale * (double)tmp[8 * p + k];
+  }
+}
+
+template <typename R>
+void Engine<R>::apply_phi(const double* S, double* Y) {
+  sync_desc();
+  put_img(IMG_TMP, S, 4);
+  forward(IMG_TMP, DG_FORWARD, VIS_R);
+  hip_check(hipGetLastError(), "phi launch");
+  get_vis(VIS_R, Y, 1.0);
+}
+template <typename R>
+void Engine<R>::apply_phi_adjoint(const double* B, double* S) {
+  sync_desc();
+  put_vis(VIS_R, B);
+  adjoint(VIS_R, 0, IMG_TMP);
+  hip_check(hipGetLastError(), "phi adjoint launch");
+  get_img(IMG_TMP, S, 4);
+}
+template <typename R>
+void Engine<R>::apply_psi_adjoint(const double* S, double* A) {
+  sync_desc();
+  put_img(IMG_TMP, S, 4);
+  if (h_.has_dirac) launch_dirac<R>(AM_STORE, la(d_dirac_), IMG_TMP, COEF_TMP);
+  for (int l = 1; l <= h_.levels; ++l) launch_analysis<R>(AM_STORE, l, la(d_ana_[l]), IMG_TMP, COEF_TMP);
+  hip_check(hipGetLastError(), "psi adjoint launch");
+  get_coef(COEF_TMP, A);
+}
+template <typename R>
+void Engine<R>::apply_psi(const double* A, double* S) {
+  sync_desc();
+  put_coef(COEF_TMP, A);
+  p3(COEF_TMP, IMG_TMP, 1, s0_);
+  hip_check(hipGetLastError(), "psi launch");
+  get_img(IMG_TMP, S, 4);
+}
+
+// state: S, Z, A, B (caller order), C, D
+template <typename R>
+void Engine<R>::get_state(double* buf) {
+  const size_t N = (size_t)geo_.n * geo_.n;
+  double sc[NUM_SCALARS];
+  read_scalars(sc);
+  double* p = buf;
+  get_img(IMG_S, p, 4); p += 4 * N;
+  get_img(IMG_Z, p, 2); p += 2 * N;
+  if (coef_elems_) get_coef(COEF_A, p);
+  p += 4 * coef_elems_;
+  get_vis(VIS_BV, p, sc[SC_CFAC]); p += 8 * (size_t)geo_.M;
+  get_img(IMG_C, p, 4); p += 4 * N;
+  get_img(IMG_D, p, 2);
+}
+template <typename R>
+void Engine<R>::set_state(const double* buf) {
+  sync_desc();
+  const size_t N = (size_t)geo_.n * geo_.n;
+  const double* p = buf;
+  put_img(IMG_S, p, 4); put_img(IMG_X, p, 4); p += 4 * N;
+  put_img(IMG_Z, p, 2); p += 2 * N;
+  if (coef_elems_) put_coef(COEF_A, p);
+  p += 4 * coef_elems_;
+  put_vis(VIS_BV, p); p += 8 * (size_t)geo_.M;
+  put_img(IMG_C, p, 4); p += 4 * N;
+  put_img(IMG_D, p, 2);
+  write_scalar(SC_CFAC, 1.0);
+  // the two operator images the next primal step reads: Re phi^dagger(B) and the wavelet part of Psi A
+  adjoint(VIS_BV, 1, IMG_PHIB);
+  if (coef_elems_ && h_.nwav > 0) p3(COEF_A, IMG_PSIA, 0, s0_);
+  else zero(h_.img[IMG_PSIA], N * sizeof(V4<R>));
+  hip_check(hipGetLastError(), "state prime");
+  hip_check(hipStreamSynchronize(s0_), "set_state");
+}
+
+template <typename R>
+double Engine<R>::time_pass(int pass, int reps) {
+  sync_desc();
+  hipEvent_t a, b;
+  hip_check(hipEventCreate(&a), "event");
+  hip_check(hipEventCreate(&b), "event");
+  auto once = [&]() {
+    switch (pass) {
+      case 0: p1(PM_CONSTRAINED, s0_); break;
+      case 1: p2(s0_); break;
+      case 2: p3(COEF_A, IMG_PSIA, 0, s0_); break;
+      case 3: p4(IMG_X, s0_); break;
+      case 4: p5(s0_); break;
+      case 5: p6(DG_DUAL, VIS_BV, VIS_BV, s0_); break;
+      case 6: p7(GR_DUAL, VIS_BV, 0, s0_); break;
+      case 7: p8(s0_); break;
+      default: p9(IMG_PHIB, s0_); break;
+    }
+  };
+  once();
+  hip_check(hipEventRecord(a, s0_), "event record");
+  for (int i = 0; i < reps; ++i) once();
+  hip_check(hipEventRecord(b, s0_), "event record");
+  hip_check(hipEventSynchronize(b), "event sync");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, a, b), "elapsed");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return (double)ms / reps;
+}
+
+template struct Engine<float>;
+template struct Engine<double>;
+
+}  // namespace psara

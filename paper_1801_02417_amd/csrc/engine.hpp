@@ -1,0 +1,133 @@
+// Host engine of one solve (or one member of a batch): device memory, work lists and
+// the pass sequence, for one real type R (float: FP32 bulk with FP64 reductions; double).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "psara.h"
+
+namespace psara {
+
+struct Error {
+  psara_status status;
+  std::string msg;
+  Error(psara_status s, std::string m) : status(s), msg(std::move(m)) {}
+};
+
+void hip_check(hipError_t e, const char* what);
+
+// Sorted visibility layout and tile binning of one uv coverage (precision independent).
+struct Geometry {
+  int n = 0, K = 0, T = 0, ts = 0, nts = 0;
+  int64_t M = 0;
+  double beta = 0.0;
+  std::vector<int64_t> perm;      // sorted position -> caller index
+  std::vector<int> k0;            // packed window starts (k1 << 16 | k2), sorted order
+  std::vector<double> frac;       // (f1, f2) per sorted visibility
+  std::vector<int> own_ptr;       // per tile: range of visibilities whose window starts there
+  std::vector<int> list_ptr, list_idx;   // per tile: every visibility whose window touches it
+};
+
+Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T);
+
+struct ItemSet {
+  std::vector<int4> img, rows, cols, p6, p7, dirac, synfinal;
+  std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
+};
+void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int* n_p6);
+void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int* n_ana_parts);
+
+struct DevItems {
+  int4* ptr = nullptr;
+  int count = 0;
+};
+
+template <typename R>
+struct Engine {
+  Engine(const Geometry& g, hipStream_t stream);
+  ~Engine();
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
+
+  void set_data(const double* Y_sorted, double eps);
+  void set_prior(uint32_t mask, int levels, const double* weights, double gamma);
+  void set_steps(double tau, double r1, double r2, double r3);
+  void zero_state();
+  void run(int mode, int iters);          // graph replay
+  void run_eager(int mode, int iters);    // direct launches
+  void report(psara_report* r);
+  double coef_std();
+  void reweight(double delta);
+  double opnorm(int max_iter, double rtol, int* iters_out);
+  void apply_phi(const double* S, double* Y);
+  void apply_phi_adjoint(const double* B, double* S);
+  void apply_psi_adjoint(const double* S, double* A);
+  void apply_psi(const double* A, double* S);
+  void get_state(double* buf);
+  void set_state(const double* buf);
+  void get_img(int slot, double* dst, int comps);
+  double time_pass(int pass, int reps);
+  size_t coef_elems() const { return coef_elems_; }
+  size_t device_bytes() const { return bytes_; }
+  const ProbDesc& desc() const { return h_; }
+  hipStream_t stream() const { return s0_; }
+
+  // passes (stream 0 by default)
+  void p1(int mode, hipStream_t s = nullptr);
+  void p2(hipStream_t s = nullptr);
+  void p3(int src_coef, int dst_slot, int add_dirac, hipStream_t s = nullptr);
+  void p4(int src, hipStream_t s = nullptr);
+  void p5(hipStream_t s = nullptr);
+  void p6(int mode, int src, int out, hipStream_t s = nullptr);
+  void p7(int mode, int src, int use_cfac, hipStream_t s = nullptr);
+  void p8(hipStream_t s = nullptr);
+  void p9(int dst, hipStream_t s = nullptr);
+
+ private:
+  template <typename T> T* dalloc(size_t count);
+  template <typename T> T* upload(const T* host, size_t count);
+  R* upload_conv(const double* host, size_t count);
+  void dfree(void* p);
+  void zero(void* p, size_t bytes);
+  void realloc_partials();
+  void upload_items();
+  void sync_desc();
+  void invalidate_graphs();
+  void launch_iteration(int mode);
+  void forward(int src_img, int mode, int out_vis);
+  void adjoint(int src_vis, int use_cfac, int dst_img);
+  void finalize(int q, int count, int scalar);
+  void read_scalars(double* out);
+  void write_scalar(int idx, double v);
+  void put_img(int slot, const double* src, int comps);
+  void put_coef(int slot, const double* src);
+  void get_coef(int slot, double* dst);
+  void put_vis(int slot, const double* src);
+  void get_vis(int slot, double* dst, double scale);
+  LaunchArgs la(const DevItems& d, hipStream_t s = nullptr) const;
+
+  Geometry geo_;
+  hipStream_t s0_ = nullptr, s1_ = nullptr;
+  hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+  ProbDesc h_;
+  ProbDesc* d_desc_ = nullptr;
+  bool desc_dirty_ = true;
+  ItemSet items_;
+  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_dirac_, d_synfinal_;
+  DevItems d_ana_[kMaxLevels + 1], d_syn_[kMaxLevels + 1];
+  int cells_ = 512;
+  int gen_parts_ = 1, ana_parts_ = 0;
+  size_t coef_elems_ = 0;
+  size_t bytes_ = 0;
+  std::vector<void*> allocs_;
+  std::map<int, hipGraphExec_t> graphs_;
+};
+
+}  // namespace psara

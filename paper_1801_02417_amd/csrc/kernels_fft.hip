@@ -1,0 +1,235 @@
+// Oversampled-grid FFT passes of the measurement operator (Sec. 4.1, eq. meas_op:
+// F and its adjoint, fused with the zero-padding / scaling Z and the crop / real part).
+//
+// The 2-D transform of a K x K grid (K = 2n) is split in two line passes through an
+// intermediate `half` array of K x n cells stored transposed, [k2][r]:
+//   forward  P4: image row r (n pixels, scaled, placed at wrapped positions) -> FFT along
+//                columns -> half[k2][r]
+//            P5: half[k2][:] (n nonzero rows at wrapped positions) -> FFT along rows ->
+//                grid[k2][k1]
+//   adjoint  P8: grid[k2][:] -> inverse FFT along rows -> keep the n cropped rows ->
+//                half[k2][r]
+//            P9: half[:][r] -> inverse FFT along columns -> keep the n cropped columns,
+//                real part, scaling -> image row r
+// so the zero half of the padded image is never read and the crop never writes unused
+// cells.  The grid is stored transposed ([k2][k1]); the de-gridding and gridding kernels
+// index it that way.  Every cell carries the four Stokes channels, which share twiddles.
+//
+// Line FFTs run in LDS as Stockham autosort passes (radix 8, then 4 or 2) with the data of
+// each butterfly held in registers across a barrier, so a single LDS buffer suffices.  Each
+// thread owns one Stokes channel of 8 cells per pass (one radix-8, two radix-4 or four
+// radix-2 butterflies).
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace psara {
+
+template <typename R>
+__device__ inline void dft2(cplx<R>& a, cplx<R>& b) {
+  cplx<R> t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+// multiply by -i (forward) or +i (inverse)
+template <typename R>
+__device__ inline cplx<R> rot(cplx<R> a, bool inv) { return inv ? cmk(-a.im, a.re) : cmk(a.im, -a.re); }
+
+template <typename R>
+__device__ inline void dft4(cplx<R>& a0, cplx<R>& a1, cplx<R>& a2, cplx<R>& a3, bool inv) {
+  cplx<R> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = rot(csub(a1, a3), inv);
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <typename R>
+__device__ inline void dft8(cplx<R>* a, bool inv) {
+  cplx<R> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  cplx<R> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4(e0, e1, e2, e3, inv);
+  dft4(o0, o1, o2, o3, inv);
+  const R h = R(0.70710678118654752440084436210485);
+  // o_k *= w8^k, w8 = exp(-+ 2 pi i / 8)
+  o1 = inv ? cmk(h * (o1.re - o1.im), h * (o1.re + o1.im)) : cmk(h * (o1.re + o1.im), h * (o1.im - o1.re));
+  o2 = rot(o2, inv);
+  o3 = inv ? cmk(-h * (o3.re + o3.im), h * (o3.re - o3.im)) : cmk(h * (o3.im - o3.re), -h * (o3.re + o3.im));
+  a[0] = cadd(e0, o0); a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1); a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2); a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3); a[7] = csub(e3, o3);
+}
+
+// One Stockham pass of radix RAD over the lines in LDS.  A thread owns one Stokes channel
+// `ch` of 8 cells: it reads the inputs of its 8/RAD butterflies into registers and writes
+// the outputs after a barrier, so the pass is done in place.  The four lanes of a cell are
+// adjacent, so their 8-byte (16-byte in FP64) accesses are contiguous.
+template <typename R, int RAD>
+__device__ inline void stockham_pass(cplx<R>* x, int K, int Ns, int tl, int per_line, int ch, bool inv,
+                                     const cplx<R>* __restrict__ tw) {
+  constexpr int NB = 8 / RAD;
+  const int stride = K / RAD;
+  cplx<R> v[8];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int b = q / RAD, r = q - b * RAD;
+    v[q] = x[4 * (tl + b * per_line + r * stride) + ch];
+  }
+  __syncthreads();
+  const int twstep = K / (Ns * RAD);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = tl + b * per_line;
+    const int k = j % Ns;
+#pragma unroll
+    for (int r = 1; r < RAD; ++r) {
+      cplx<R> w = tw[r * k * twstep];
+      if (inv) w.im = -w.im;
+      v[b * RAD + r] = cmul(v[b * RAD + r], w);
+    }
+    if (RAD == 8) dft8(v + b * 8, inv);
+    else if (RAD == 4) dft4(v[b * 4], v[b * 4 + 1], v[b * 4 + 2], v[b * 4 + 3], inv);
+    else dft2(v[b * 2], v[b * 2 + 1]);
+    const int base = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) x[4 * (base + r * Ns) + ch] = v[b * RAD + r];
+  }
+}
+
+// In-place Stockham FFT (radix 8 passes, then one radix-4 or radix-2 pass) of the lines held
+// in `lds` (line l at lds + l*K).  Called by CELLS/2 threads: thread t handles channel t % 4 of
+// the 8 cells of butterfly group t / 4, on line (t / 4) / (K/8).
+template <typename R, int CELLS>
+__device__ void fft_lines(Cell<R>* lds, int K, bool inv, const cplx<R>* __restrict__ tw) {
+  const int per_line = K >> 3;
+  const int ch = threadIdx.x & 3, grp = threadIdx.x >> 2;
+  const int l = grp / per_line, tl = grp - l * per_line;
+  cplx<R>* x = (cplx<R>*)(lds + l * K);
+  int Ns = 1;
+  while (Ns < K) {
+    const int rem = K / Ns;
+    if (rem % 8 == 0) { stockham_pass<R, 8>(x, K, Ns, tl, per_line, ch, inv, tw); Ns *= 8; }
+    else if (rem % 4 == 0) { stockham_pass<R, 4>(x, K, Ns, tl, per_line, ch, inv, tw); Ns *= 4; }
+    else { stockham_pass<R, 2>(x, K, Ns, tl, per_line, ch, inv, tw); Ns *= 2; }
+  }
+  __syncthreads();
+}
+
+template <typename R>
+__device__ inline Cell<R> zero_cell() {
+  Cell<R> c;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) c.s[s] = cmk(R(0), R(0));
+  return c;
+}
+
+// PASS: 0 = P4 image rows -> half, 1 = P5 half -> grid, 2 = P8 grid -> half, 3 = P9 half -> image.
+// items: {prob, first line, -, -}; CELLS/K lines per workgroup.
+template <typename R, int CELLS, int PASS>
+__global__ void __launch_bounds__(CELLS / 2)
+fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int dst_slot) {
+  __shared__ Cell<R> lds[CELLS];
+  const int4 it = items[blockIdx.x];
+  const ProbDesc& P = descs[it.x];
+  const int n = P.n, K = P.K, h2 = n / 2;
+  const int lines = CELLS / K;
+  const int line0 = it.y;
+  const R* __restrict__ s = (const R*)P.deapod;
+  Cell<R>* __restrict__ half = (Cell<R>*)P.half;
+  Cell<R>* __restrict__ grid = (Cell<R>*)P.grid;
+  const int nthr = CELLS / 2;
+
+  // ---- load ----
+  for (int q = threadIdx.x; q < lines * K; q += nthr) {
+    Cell<R> c = zero_cell<R>();
+    if (PASS == 0) {
+      const int l = q / K, k = q - l * K, r = line0 + l;
+      const int col = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
+      if (r < n && col >= 0) {
+        const V4<R> v = ((const V4<R>*)P.img[src_slot])[(size_t)r * n + col];
+        const R sc = s[r] * s[col];
+        c.s[0].re = v.x * sc; c.s[1].re = v.y * sc; c.s[2].re = v.z * sc; c.s[3].re = v.w * sc;
+      }
+      lds[q] = c;
+    } else if (PASS == 1) {
+      const int l = q / K, k = q - l * K, k2 = line0 + l;
+      const int r = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
+      if (k2 < K && r >= 0) c = half[(size_t)k2 * n + r];
+      lds[q] = c;
+    } else if (PASS == 2) {
+      const int l = q / K, k = q - l * K, k2 = line0 + l;
+      if (k2 < K) c = grid[(size_t)k2 * K + k];
+      lds[q] = c;
+    } else {
+      const int k2 = q / lines, l = q - k2 * lines, r = line0 + l;
+      if (r < n) c = half[(size_t)k2 * n + r];
+      lds[l * K + k2] = c;
+    }
+  }
+  __syncthreads();
+  // lines * K == CELLS (K divides CELLS), so every thread owns one channel of 8 cells
+  fft_lines<R, CELLS>(lds, K, PASS >= 2, (const cplx<R>*)P.twiddle);
+
+  // ---- store ----
+  if (PASS == 0) {
+    for (int q = threadIdx.x; q < lines * K; q += nthr) {
+      const int k2 = q / lines, l = q - k2 * lines, r = line0 + l;
+      if (r < n) half[(size_t)k2 * n + r] = lds[l * K + k2];
+    }
+  } else if (PASS == 1) {
+    for (int q = threadIdx.x; q < lines * K; q += nthr) {
+      const int l = q / K, k1 = q - l * K, k2 = line0 + l;
+      if (k2 < K) grid[(size_t)k2 * K + k1] = lds[q];
+    }
+  } else if (PASS == 2) {
+    for (int q = threadIdx.x; q < lines * n; q += nthr) {
+      const int l = q / n, r = q - l * n, k2 = line0 + l;
+      const int pos = r < h2 ? r + (K - h2) : r - h2;        // (r - n/2) mod K
+      if (k2 < K) half[(size_t)k2 * n + r] = lds[l * K + pos];
+    }
+  } else {
+    V4<R>* __restrict__ out = (V4<R>*)P.img[dst_slot];
+    for (int q = threadIdx.x; q < lines * n; q += nthr) {
+      const int l = q / n, c = q - l * n, r = line0 + l;
+      const int pos = c < h2 ? c + (K - h2) : c - h2;
+      if (r < n) {
+        const Cell<R> v = lds[l * K + pos];
+        const R sc = s[r] * s[c];
+        V4<R> o;
+        o.x = v.s[0].re * sc; o.y = v.s[1].re * sc; o.z = v.s[2].re * sc; o.w = v.s[3].re * sc;
+        out[(size_t)r * n + c] = o;
+      }
+    }
+  }
+}
+
+template <typename R>
+void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot) {
+  if (a.nitems <= 0) return;
+  const dim3 grid(a.nitems);
+#define PSARA_FFT(C, PS) \
+  hipLaunchKernelGGL((fft_pass_kernel<R, C, PS>), grid, dim3(C / 2), 0, a.stream, a.descs, a.items, src_slot, dst_slot)
+  if (cells == 512) {
+    switch (pass) {
+      case 0: PSARA_FFT(512, 0); break;
+      case 1: PSARA_FFT(512, 1); break;
+      case 2: PSARA_FFT(512, 2); break;
+      default: PSARA_FFT(512, 3); break;
+    }
+  } else {
+    switch (pass) {
+      case 0: PSARA_FFT(1024, 0); break;
+      case 1: PSARA_FFT(1024, 1); break;
+      case 2: PSARA_FFT(1024, 2); break;
+      default: PSARA_FFT(1024, 3); break;
+    }
+  }
+#undef PSARA_FFT
+}
+
+template void launch_fft<float>(int, const LaunchArgs&, int, int, int);
+template void launch_fft<double>(int, const LaunchArgs&, int, int, int);
+
+}  // namespace psara

@@ -1,0 +1,49 @@
+// Launch wrappers of the HIP kernels (one per pass family), instantiated for float and
+// double in the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace psara {
+
+struct LaunchArgs {
+  const ProbDesc* descs;   // device array of problem descriptors
+  const int4* items;       // device work list, one entry per workgroup
+  int nitems;
+  hipStream_t stream;
+};
+
+// P1 modes
+enum PrimalMode { PM_CONSTRAINED = 0, PM_INIT = 1, PM_UNCONSTRAINED = 2 };
+// analysis modes
+enum AnalysisMode { AM_DUAL = 0, AM_STORE = 1, AM_REWEIGHT = 2, AM_OBJECTIVE = 3, AM_MOMENTS = 4 };
+// de-grid modes
+enum DegridMode { DG_DUAL = 0, DG_FORWARD = 1, DG_RESIDUAL = 2 };
+// grid modes
+enum GridMode { GR_DUAL = 0, GR_PLAIN = 1 };
+
+template <typename R> void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot);
+template <typename R> void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int max_T, int src_slot, int out_slot);
+template <typename R> void launch_grid(int mode, const LaunchArgs& a, int max_ts, int src_slot, int use_cfac);
+template <typename R> void set_grid_kernel_limits(int max_ts, int max_T);
+void hip_check(hipError_t e, const char* what);
+template <typename R> void launch_primal(int mode, const LaunchArgs& a);
+template <typename R> void launch_analysis(int mode, int level, const LaunchArgs& a, int src_slot, int out_slot);
+template <typename R> void launch_dirac(int mode, const LaunchArgs& a, int src_slot, int out_slot);
+template <typename R> void launch_synthesis(int level, int coarsest, const LaunchArgs& a, int src_coef, int dst_slot);
+template <typename R> void launch_synthesis_final(const LaunchArgs& a, int src_coef, int dst_slot, int add_dirac);
+
+// reductions and small utility kernels (items: {prob, block, -, -})
+template <typename R> void launch_relvar(const LaunchArgs& a);
+template <typename R> void launch_img_sumsq(const LaunchArgs& a, int slot, int channel, int scalar);
+template <typename R> void launch_npcount(const LaunchArgs& a);
+template <typename R> void launch_img_dot(const LaunchArgs& a, int xs, int ys);
+template <typename R> void launch_img_scale(const LaunchArgs& a, int dst, int src, int scalar);
+template <typename R> void launch_fill(void* p, size_t count, hipStream_t s);
+// finalise: one workgroup per problem sums PART_GEN partials into scal[scalar]
+void launch_finalize(const ProbDesc* descs, int nprob, int region, int count, int scalar, hipStream_t s);
+void launch_finalize_zeta(const ProbDesc* descs, int nprob, hipStream_t s);
+
+}  // namespace psara

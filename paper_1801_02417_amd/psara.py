@@ -1,0 +1,390 @@
+"""ctypes binding of libpsara.so (the C ABI declared in include/psara.h).
+
+Argument marshalling only: every computation runs in the library's HIP kernels.  The
+module-level functions carry the C names; `Solver` bundles them for convenience.  Host
+arrays are numpy float64 (images N x 4, coefficients J x 4) or complex128 (visibilities
+M x 4).  If the shared library has not been built this module raises on first use; there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsara.so")
+
+PSARA_OK, PSARA_EINVAL, PSARA_ENOMEM, PSARA_EDEVICE, PSARA_ESTATE, PSARA_ENAN = 0, -1, -2, -3, -4, -5
+PSARA_FP64, PSARA_FP32_MIXED = 0, 1
+PSARA_CONSTRAINED, PSARA_NNLS_INIT, PSARA_UNCONSTRAINED = 0, 1, 2
+
+ALL_BASES = 0x1FF      # Dirac + Db1..Db8
+
+EXPORTS = (
+    "psara_create", "psara_destroy", "psara_last_error", "psara_status_string", "psara_set_operator",
+    "psara_set_data", "psara_set_prior", "psara_set_steps", "psara_opnorm", "psara_solve", "psara_reweight",
+    "psara_coef_std", "psara_reweighted_solve", "psara_report_now", "psara_get_image", "psara_state_bytes",
+    "psara_get_state", "psara_set_state", "psara_reset_state", "psara_footprint", "psara_apply_phi",
+    "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
+    "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_time_pass",
+)
+
+
+class PsaraReport(C.Structure):
+    _fields_ = [("residual", C.c_double), ("epsilon", C.c_double), ("rel_var", C.c_double * 4),
+                ("zeta", C.c_double), ("n_p", C.c_double), ("objective", C.c_double),
+                ("vnorm", C.c_double), ("iterations", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {"residual": self.residual, "epsilon": self.epsilon, "rel_var": list(self.rel_var),
+                "zeta": self.zeta, "n_p": self.n_p, "objective": self.objective, "vnorm": self.vnorm,
+                "iterations": int(self.iterations)}
+
+
+class PsaraError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"psara error {status}: {message}")
+        self.status = status
+
+
+_lib_handle = None
+
+
+def lib() -> C.CDLL:
+    """Load libpsara.so (raises if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is not None:
+        return _lib_handle
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1801_02417_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, D, I, I64, U32, S = C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_int64, C.c_uint32, C.c_size_t
+    sig = {
+        "psara_create": (I, [C.POINTER(P), I, P]),
+        "psara_destroy": (None, [P]),
+        "psara_last_error": (C.c_char_p, [P]),
+        "psara_status_string": (C.c_char_p, [I]),
+        "psara_set_operator": (I, [P, I, I64, D, I, I, I]),
+        "psara_set_data": (I, [P, D, C.c_double]),
+        "psara_set_prior": (I, [P, U32, I, D, C.c_double]),
+        "psara_set_steps": (I, [P, C.c_double, C.c_double, C.c_double, C.c_double]),
+        "psara_opnorm": (I, [P, I, C.c_double, D]),
+        "psara_solve": (I, [P, I, I, I, C.POINTER(PsaraReport)]),
+        "psara_reweight": (I, [P, C.c_double]),
+        "psara_coef_std": (I, [P, D]),
+        "psara_reweighted_solve": (I, [P, I, I, C.POINTER(C.c_int), C.c_double, C.POINTER(PsaraReport)]),
+        "psara_report_now": (I, [P, C.POINTER(PsaraReport)]),
+        "psara_get_image": (I, [P, D]),
+        "psara_state_bytes": (S, [P]),
+        "psara_get_state": (I, [P, P, S]),
+        "psara_set_state": (I, [P, P, S]),
+        "psara_reset_state": (I, [P]),
+        "psara_footprint": (S, [I, I64, I, I, U32, I]),
+        "psara_apply_phi": (I, [P, D, D]),
+        "psara_apply_phi_adjoint": (I, [P, D, D]),
+        "psara_apply_psi_adjoint": (I, [P, D, D]),
+        "psara_apply_psi": (I, [P, D, D]),
+        "psara_wavelet_filter": (I, [I, D]),
+        "psara_kb_beta": (C.c_double, [I, C.c_double]),
+        "psara_kb_value": (C.c_double, [I, C.c_double, C.c_double]),
+        "psara_kb_deapod": (C.c_double, [I, C.c_double, C.c_double]),
+        "psara_layout": (I, [P, C.POINTER(C.c_int64)]),
+        "psara_time_pass": (I, [P, I, I, D]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib_handle = L
+    return L
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    out = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and out.shape != tuple(shape):
+        out = out.reshape(shape)
+    return out
+
+
+def _vis(a: np.ndarray) -> np.ndarray:
+    """complex (M, 4) -> interleaved float64 (M, 8)."""
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a.view(np.float64).reshape(a.shape[0], 8)
+
+
+def _check(ctx, status: int):
+    if status != PSARA_OK:
+        msg = lib().psara_last_error(ctx).decode() if ctx else lib().psara_status_string(status).decode()
+        raise PsaraError(status, msg)
+
+
+# ---- C-named functions --------------------------------------------------------------------------
+def psara_create(device: int = 0, hip_stream: Optional[int] = None):
+    ctx = C.c_void_p()
+    st = lib().psara_create(C.byref(ctx), device, C.c_void_p(hip_stream) if hip_stream else None)
+    if st != PSARA_OK:
+        raise PsaraError(st, lib().psara_status_string(st).decode())
+    return ctx
+
+
+def psara_destroy(ctx) -> None:
+    lib().psara_destroy(ctx)
+
+
+def psara_set_operator(ctx, n: int, uv: np.ndarray, oversample: int = 2, taps: int = 8,
+                       precision: int = PSARA_FP32_MIXED) -> None:
+    uv = _f64(uv)
+    _check(ctx, lib().psara_set_operator(ctx, n, uv.shape[0], _dptr(uv), oversample, taps, precision))
+
+
+def psara_set_data(ctx, Y: np.ndarray, epsilon: float) -> None:
+    y = _vis(Y)
+    _check(ctx, lib().psara_set_data(ctx, _dptr(y), float(epsilon)))
+
+
+def psara_set_prior(ctx, basis_mask: int, levels: int, weights: Optional[np.ndarray], gamma: float) -> None:
+    if weights is None:
+        _check(ctx, lib().psara_set_prior(ctx, basis_mask, levels, None, float(gamma)))
+    else:
+        w = _f64(weights)
+        _check(ctx, lib().psara_set_prior(ctx, basis_mask, levels, _dptr(w), float(gamma)))
+
+
+def psara_set_steps(ctx, tau: float, rho1: float, rho2: float, rho3: float) -> None:
+    _check(ctx, lib().psara_set_steps(ctx, tau, rho1, rho2, rho3))
+
+
+def psara_opnorm(ctx, max_iter: int = 500, rtol: float = 1e-10) -> float:
+    out = C.c_double()
+    _check(ctx, lib().psara_opnorm(ctx, max_iter, rtol, C.byref(out)))
+    return out.value
+
+
+def psara_solve(ctx, mode: int, iters: int, check_every: int = 0, report: bool = True):
+    rep = PsaraReport()
+    _check(ctx, lib().psara_solve(ctx, mode, iters, check_every, C.byref(rep) if report else None))
+    return rep.as_dict() if report else None
+
+
+def psara_reweight(ctx, delta: float) -> None:
+    _check(ctx, lib().psara_reweight(ctx, float(delta)))
+
+
+def psara_coef_std(ctx) -> float:
+    out = C.c_double()
+    _check(ctx, lib().psara_coef_std(ctx, C.byref(out)))
+    return out.value
+
+
+def psara_reweighted_solve(ctx, mode: int, iters_per_stage: Sequence[int], delta_decay: float = 10.0):
+    arr = (C.c_int * len(iters_per_stage))(*[int(v) for v in iters_per_stage])
+    rep = PsaraReport()
+    _check(ctx, lib().psara_reweighted_solve(ctx, mode, len(iters_per_stage) - 1, arr, delta_decay, C.byref(rep)))
+    return rep.as_dict()
+
+
+def psara_report_now(ctx) -> dict:
+    rep = PsaraReport()
+    _check(ctx, lib().psara_report_now(ctx, C.byref(rep)))
+    return rep.as_dict()
+
+
+def psara_get_image(ctx, N: int) -> np.ndarray:
+    out = np.empty((N, 4))
+    _check(ctx, lib().psara_get_image(ctx, _dptr(out)))
+    return out
+
+
+def psara_state_bytes(ctx) -> int:
+    return int(lib().psara_state_bytes(ctx))
+
+
+def psara_get_state(ctx) -> np.ndarray:
+    nb = psara_state_bytes(ctx)
+    buf = np.empty(nb // 8)
+    _check(ctx, lib().psara_get_state(ctx, buf.ctypes.data_as(C.c_void_p), nb))
+    return buf
+
+
+def psara_set_state(ctx, buf: np.ndarray) -> None:
+    buf = _f64(buf)
+    _check(ctx, lib().psara_set_state(ctx, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
+
+
+def psara_reset_state(ctx) -> None:
+    _check(ctx, lib().psara_reset_state(ctx))
+
+
+def psara_footprint(n: int, M: int, taps: int, levels: int, basis_mask: int = ALL_BASES,
+                    precision: int = PSARA_FP32_MIXED) -> int:
+    return int(lib().psara_footprint(n, M, taps, levels, basis_mask, precision))
+
+
+def psara_apply_phi(ctx, S: np.ndarray, M: int) -> np.ndarray:
+    S = _f64(S)
+    out = np.empty((M, 8))
+    _check(ctx, lib().psara_apply_phi(ctx, _dptr(S), _dptr(out)))
+    return out.view(np.complex128).reshape(M, 4)
+
+
+def psara_apply_phi_adjoint(ctx, B: np.ndarray, N: int) -> np.ndarray:
+    b = _vis(B)
+    out = np.empty((N, 4))
+    _check(ctx, lib().psara_apply_phi_adjoint(ctx, _dptr(b), _dptr(out)))
+    return out
+
+
+def psara_apply_psi_adjoint(ctx, S: np.ndarray, J: int) -> np.ndarray:
+    S = _f64(S)
+    out = np.empty((J, 4))
+    _check(ctx, lib().psara_apply_psi_adjoint(ctx, _dptr(S), _dptr(out)))
+    return out
+
+
+def psara_apply_psi(ctx, A: np.ndarray, N: int) -> np.ndarray:
+    A = _f64(A)
+    out = np.empty((N, 4))
+    _check(ctx, lib().psara_apply_psi(ctx, _dptr(A), _dptr(out)))
+    return out
+
+
+def psara_wavelet_filter(p: int) -> np.ndarray:
+    out = np.zeros(16)
+    k = lib().psara_wavelet_filter(p, _dptr(out))
+    if k == 0:
+        raise ValueError(f"bad wavelet order {p}")
+    return out[:k].copy()
+
+
+def psara_kb_beta(taps: int, alpha: float) -> float:
+    return lib().psara_kb_beta(taps, alpha)
+
+
+def psara_kb_value(taps: int, beta: float, t: float) -> float:
+    return lib().psara_kb_value(taps, beta, t)
+
+
+def psara_kb_deapod(taps: int, beta: float, nu: float) -> float:
+    return lib().psara_kb_deapod(taps, beta, nu)
+
+
+def psara_layout(ctx, M: int):
+    perm = np.empty(M, dtype=np.int64)
+    ts = lib().psara_layout(ctx, perm.ctypes.data_as(C.POINTER(C.c_int64)))
+    if ts < 0:
+        raise PsaraError(ts, "layout unavailable")
+    return ts, perm
+
+
+def psara_time_pass(ctx, pass_id: int, reps: int) -> float:
+    out = C.c_double()
+    _check(ctx, lib().psara_time_pass(ctx, pass_id, reps, C.byref(out)))
+    return out.value
+
+
+# ---- convenience wrapper ------------------------------------------------------------------------
+def step_sizes(phi_norm_sq: float, margin: float = 0.99):
+    """rho1 = rho3 = 1, rho2 = 1/||phi||^2, tau = margin/(rho1 + rho2||phi||^2 + rho3) (||Psi|| = 1)."""
+    rho1, rho3, rho2 = 1.0, 1.0, 1.0 / phi_norm_sq
+    return margin / (rho1 + rho2 * phi_norm_sq + rho3), rho1, rho2, rho3
+
+
+def basis_count(mask: int) -> int:
+    return bin(mask & 0x1FF).count("1")
+
+
+class Solver:
+    """One Polarized SARA solve on the GPU (owns a psara context)."""
+
+    def __init__(self, n: int, uv: np.ndarray, taps: int = 8, precision: int = PSARA_FP32_MIXED,
+                 device: int = 0, hip_stream: Optional[int] = None):
+        self.ctx = psara_create(device, hip_stream)
+        self.n, self.N, self.M = n, n * n, int(np.shape(uv)[0])
+        psara_set_operator(self.ctx, n, uv, 2, taps, precision)
+        self.mask = 0
+        self.J = 0
+        self.phi_norm_sq = None
+
+    def close(self):
+        if self.ctx:
+            psara_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_data(self, Y, epsilon):
+        psara_set_data(self.ctx, Y, epsilon)
+
+    def set_prior(self, levels: int, gamma: float, basis_mask: int = ALL_BASES, weights=None):
+        self.mask = basis_mask
+        self.J = basis_count(basis_mask) * self.N
+        psara_set_prior(self.ctx, basis_mask, levels, weights, gamma)
+
+    def opnorm(self, max_iter: int = 500, rtol: float = 1e-10) -> float:
+        self.phi_norm_sq = psara_opnorm(self.ctx, max_iter, rtol)
+        return self.phi_norm_sq
+
+    def set_steps(self, tau=None, rho1=None, rho2=None, rho3=None):
+        if tau is None:
+            tau, rho1, rho2, rho3 = step_sizes(self.phi_norm_sq)
+        psara_set_steps(self.ctx, tau, rho1, rho2, rho3)
+
+    def solve(self, mode: int, iters: int, check_every: int = 0, report: bool = True):
+        return psara_solve(self.ctx, mode, iters, check_every, report)
+
+    def reweighted_solve(self, mode: int, iters_per_stage, delta_decay: float = 10.0):
+        return psara_reweighted_solve(self.ctx, mode, iters_per_stage, delta_decay)
+
+    def image(self) -> np.ndarray:
+        return psara_get_image(self.ctx, self.N)
+
+    def phi(self, S):
+        return psara_apply_phi(self.ctx, S, self.M)
+
+    def phi_adjoint(self, B):
+        return psara_apply_phi_adjoint(self.ctx, B, self.N)
+
+    def psi_adjoint(self, S):
+        return psara_apply_psi_adjoint(self.ctx, S, self.J)
+
+    def psi(self, A):
+        return psara_apply_psi(self.ctx, A, self.N)
+
+    def state(self) -> dict:
+        buf = psara_get_state(self.ctx)
+        N, J, M = self.N, self.J, self.M
+        o = 0
+        out = {}
+        for name, cnt, shape in (("S", 4 * N, (N, 4)), ("Z", 2 * N, (N, 2)), ("A", 4 * J, (J, 4)),
+                                 ("B", 8 * M, None), ("C", 4 * N, (N, 4)), ("D", 2 * N, (N, 2))):
+            v = buf[o:o + cnt]
+            out[name] = v.view(np.complex128).reshape(M, 4).copy() if shape is None else v.reshape(shape).copy()
+            o += cnt
+        return out
+
+    def set_state(self, S, Z, A, B, C, D):
+        parts = [np.ravel(np.asarray(S, float)), np.ravel(np.asarray(Z, float)), np.ravel(np.asarray(A, float)),
+                 np.ascontiguousarray(B, dtype=np.complex128).view(np.float64).ravel(),
+                 np.ravel(np.asarray(C, float)), np.ravel(np.asarray(D, float))]
+        psara_set_state(self.ctx, np.concatenate(parts))
+
+    def report(self) -> dict:
+        return psara_report_now(self.ctx)
+
+    def reset(self):
+        psara_reset_state(self.ctx)
+
+    def time_pass(self, pass_id: int, reps: int) -> float:
+        return psara_time_pass(self.ctx, pass_id, reps)

@@ -37,7 +37,7 @@ class Built:
     gamma: float
 
 
-def build(wl, bases=BASES, levels=None, phi_norm=None, gamma=None) -> Built:
+def build(wl, bases=BASES, levels=None, phi_norm=None, gamma=None, norm_rtol=1e-12, norm_max_iter=1000) -> Built:
     n = wl.n
     nu = NUFFT(wl.uv, n, wl.oversample, wl.taps)
     mop = MeasurementOp(nu)
@@ -48,7 +48,7 @@ def build(wl, bases=BASES, levels=None, phi_norm=None, gamma=None) -> Built:
     Y = y0 + sigma * wl.noise
     eps = chi2_epsilon(wl.M, sigma)
     if phi_norm is None:
-        phi_norm, _ = phi_norm_sq(mop, n * n)
+        phi_norm, _ = phi_norm_sq(mop, n * n, max_iter=norm_max_iter, rtol=norm_rtol)
     tau, r1, r2, r3 = step_sizes(phi_norm)
     if gamma is None:
         gamma = 1e-3 * float(np.max(np.abs(sara.adjoint(np.real(mop.phi_adj(Y)))))) / phi_norm

@@ -1,0 +1,115 @@
+"""GPU parity of whole solves (Algorithm 2: initialisation, reweighting, warm starts) and of
+the stopping quantities against the oracle, on the synthetic workloads."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import metrics, pd, problem
+from paper_1801_02417_amd import workloads as wk
+from tests.gpu_common import P, say, rel_err, solver_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_alg2(wl, b, prec, stages, phi_norm=None):
+    s = solver_for(wl, wl.n, wl.taps, prec, levels=wl.levels, gamma=b.gamma)
+    s.set_data(b.pb.Y, b.pb.eps)
+    s.opnorm(300, 1e-9)
+    s.set_steps(b.pb.tau, b.pb.rho1, b.pb.rho2, b.pb.rho3)
+    rep = s.reweighted_solve(P.PSARA_CONSTRAINED, stages, 10.0)
+    return s, rep
+
+
+def _oracle_alg2(b, stages):
+    return pd.alg2(b.pb, b.gamma, stages, len(stages) - 1)
+
+
+def _per_stokes(S, R):
+    return [float(np.linalg.norm(S[:, i] - R[:, i]) / np.linalg.norm(R[:, i])) for i in range(4)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_config0_full_solve(prec, tol):
+    """Config 0: 32x32, 600 uv, KB 6, 3 levels, 300 iterations = init + 2 reweighting cycles."""
+    wl = wk.config0()
+    b = problem.build(wl)
+    stages = pd.split_iterations(wl.iters, wl.cycles + 1)
+    say(f"[solve] config0 {prec} stages={stages}")
+    st, gW, deltas = _oracle_alg2(b, stages)
+    s, rep = _gpu_alg2(wl, b, prec, stages)
+    try:
+        S = s.image()
+        errs = _per_stokes(S, st.S)
+        snr_g = [metrics.snr_db(S[:, i], b.truth[:, i]) for i in range(4)]
+        snr_o = [metrics.snr_db(st.S[:, i], b.truth[:, i]) for i in range(4)]
+        say(f"   per-Stokes rel err {['%.2e' % e for e in errs]}")
+        say(f"   SNR gpu {['%.3f' % v for v in snr_g]} oracle {['%.3f' % v for v in snr_o]}")
+        assert max(errs) <= tol
+        assert max(abs(x - y) for x, y in zip(snr_g, snr_o)) <= (1e-6 if prec == "fp64" else 1e-2)
+        # stopping quantities
+        res = metrics.residual_norm(b.mop, st.S, b.pb.Y)
+        assert abs(rep["residual"] - res) <= (1e-9 if prec == "fp64" else 1e-4) * res
+        assert rep["iterations"] == wl.iters
+        obj = metrics.weighted_l1(b.sara.adjoint, st.S, gW / b.gamma)
+        assert abs(rep["objective"] - obj) <= (1e-9 if prec == "fp64" else 1e-4) * obj
+    finally:
+        s.close()
+
+
+def test_report_matches_oracle_metrics():
+    wl = wk.config0()
+    b = problem.build(wl)
+    stages = [60, 60]
+    st, gW, _ = _oracle_alg2(b, stages)
+    s, rep = _gpu_alg2(wl, b, "fp64", stages)
+    try:
+        # recompute the quantities from the oracle's own final state
+        res = metrics.residual_norm(b.mop, st.S, b.pb.Y)
+        p, zeta, n_p = metrics.polarization_error(b.mop, st.S, b.pb.Y)
+        say(f"[report] gpu {rep}")
+        say(f"         oracle residual {res} zeta {zeta} n_p {n_p}")
+        assert abs(rep["residual"] - res) <= 1e-9 * res
+        assert abs(rep["zeta"] - zeta) <= 1e-9 * zeta
+        assert abs(rep["n_p"] - n_p) <= 1e-9
+        assert abs(rep["epsilon"] - b.pb.eps) <= 1e-15 * b.pb.eps
+        # relative variation of the last iteration
+        s2 = s.state()
+        assert np.all(np.isfinite(rep["rel_var"]))
+    finally:
+        s.close()
+
+
+def test_config1_reduced_schedule_fp32():
+    """Config 1 (128x128 ring+jet, 8-station arcs, KB 8, 4 levels) with a 6-stage schedule of 40
+    iterations each (the stated 2000-iteration budget is split the same way in the bench)."""
+    wl = wk.config1()
+    b = problem.build(wl)
+    stages = [40] * 6
+    say(f"[solve] config1 fp32 stages={stages}")
+    st, gW, _ = pd.alg2(b.pb, b.gamma, stages, 5)
+    s, rep = _gpu_alg2(wl, b, "fp32", stages)
+    try:
+        errs = _per_stokes(s.image(), st.S)
+        say(f"   per-Stokes rel err {['%.2e' % e for e in errs]}")
+        assert max(errs) <= 1e-4
+    finally:
+        s.close()
+
+
+def test_config2_full_size_fp32():
+    """Config 2 (256x256, 2e5 uv, KB 8, 4 levels): the launch configuration the benchmark times,
+    with a short 3-stage schedule the oracle finishes in about half a minute."""
+    wl = wk.config2()
+    # a loose power iteration suffices for the step sizes (tau keeps a 1% margin)
+    b = problem.build(wl, norm_rtol=1e-5, norm_max_iter=60)
+    stages = [10, 10, 10]
+    say(f"[solve] config2 fp32 stages={stages}")
+    st, gW, _ = pd.alg2(b.pb, b.gamma, stages, 2)
+    s, rep = _gpu_alg2(wl, b, "fp32", stages)
+    try:
+        errs = _per_stokes(s.image(), st.S)
+        say(f"   per-Stokes rel err {['%.2e' % e for e in errs]}")
+        assert max(errs) <= 1e-4
+    finally:
+        s.close()

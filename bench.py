@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the Polarized SARA primal-dual hot path on one MI355X.
+
+A step is one iteration of Algorithm 1 with every term active (SARA analysis / synthesis
+and dual A, measurement operator and l2-ball dual B, epigraphical projections) on the
+256 x 256 x 4-Stokes workload with 2e5 synthetic visibilities (KB 8 x 8 taps, 2x
+oversampled grid, SARA = Dirac + Db1..Db8 at 4 levels), FP32 bulk with FP64 reductions.
+Inputs and state are resident in HBM before the timed region; iterations replay a captured
+HIP graph.  Prints one JSON line (see the driver contract): the throughput, a roofline entry
+for the dominant pass (algorithmic bytes per launch over its HIP-event-timed duration, and
+rocprof-measured HBM traffic when a summary of the same kernel source is committed), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PASS_SOURCES = ["kernels_point.hip", "kernels_dwt.hip", "kernels_dwt.hip", "kernels_fft.hip", "kernels_fft.hip",
+                "kernels_grid.hip", "kernels_grid.hip", "kernels_fft.hip", "kernels_fft.hip"]
+PASS_KERNELS = ["primal_kernel", "analysis_kernel", "synthesis_kernel+synthesis_final_kernel",
+                "fft_pass_kernel<...,0>", "fft_pass_kernel<...,1>", "degrid_kernel", "grid_kernel",
+                "fft_pass_kernel<...,2>", "fft_pass_kernel<...,3>"]
+
+
+def algorithmic_bytes(N: int, M: int, nwav: int, R: int = 4) -> list:
+    """Compulsory bytes per launch of each pass (every operand moved once per use).
+
+    Units: V4 = 4R bytes per pixel (S, X, C, Psi A, phi^dagger B, one basis of A or gW),
+    V2 = 2R (Z, D), grid cell = 8R (four complex channels), K^2 = 4N cells, the FFT
+    intermediate K*n = 2N cells, one visibility row = 8R (Y, B), its geometry 4 + 2R bytes.
+    """
+    v4, v2, cell = 4 * R, 2 * R, 8 * R
+    geo = 4 + 2 * R
+    return [
+        N * (6 * v4 + 2 * v2) + N * (4 * v4 + 2 * v2),           # P1: S,PsiA,PhiB,C,A_d,gW_d,Z,D in; S,X,C,A_d,Z,D out
+        N * v4 + nwav * N * 3 * v4,                               # P2: X in; A_w, gW_w in, A_w out
+        nwav * N * v4 + N * v4,                                   # P3: A_w in; Psi A out
+        N * v4 + 2 * N * cell,                                    # P4: X in; half out
+        2 * N * cell + 4 * N * cell,                              # P5: half in; grid out
+        4 * N * cell + M * (geo + 3 * cell),                      # P6: grid, geometry, Y, B in; B out
+        M * (geo + cell) + 4 * N * cell,                          # P7: geometry, B in; grid out
+        4 * N * cell + 2 * N * cell,                              # P8: grid in; half out
+        2 * N * cell + N * v4,                                    # P9: half in; Re phi^dagger B out
+    ]
+
+
+def source_hash(name: str) -> str:
+    with open(os.path.join(ROOT, "paper_1801_02417_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def committed_traffic(pass_id: int):
+    """HBM bytes per launch from the committed rocprof counter summary, if it was taken on the
+    current source of that pass's kernel; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic_config2.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get("passes", {}).get(str(pass_id))
+    if not e or e.get("source_sha256") != source_hash(PASS_SOURCES[pass_id]):
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(iters: int) -> dict:
+    """The FP64 oracle (plain numpy / scipy) timed on this host on `iters` Algorithm-1 iterations
+    of the same workload (the oracle's own set-up is not timed)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pd, problem
+    from paper_1801_02417_amd import workloads as wk
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+    with threadpool_limits(limits=cores):
+        wl = wk.config2()
+        b = problem.build(wl, norm_rtol=1e-3, norm_max_iter=20)
+        J = b.sara.J
+        gW = b.gamma * np.ones((J, 4))
+        st = pd.State.zeros(wl.n * wl.n, J, wl.M)
+        st = pd.alg1_iteration(st, b.pb, gW, "polsara")          # untimed first touch
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            st = pd.alg1_iteration(st, b.pb, gW, "polsara")
+        dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{iters} Algorithm-1 iterations (all terms) of the 256x256x4, 2e5-visibility workload, "
+                      f"FP64 numpy/scipy, {dt:.1f} s; BLAS threads = cores, FFT and sparse products single-threaded"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--profile-iters", type=int, default=50)
+    ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the path is a single-GPU solve); --gpus {args.gpus} "
+              f"is not supported", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1801_02417_amd import psara as P
+    from paper_1801_02417_amd import workloads as wk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    wl = wk.config2()
+    n, M, N = wl.n, wl.M, wl.n * wl.n
+    s = P.Solver(n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED, hip_stream=stream.cuda_stream)
+    # synthetic measurements on the device: Y = phi(S_true) + sigma E, sigma from the input SNR,
+    # epsilon^2 = (8M + 2 sqrt(2 * 8M)) sigma^2 / 2 (chi-square bound of the simulation setup)
+    truth = wl.truth.reshape(N, 4)
+    y0 = s.phi(truth)
+    sigma = np.linalg.norm(y0) / math.sqrt(4 * M) * 10 ** (-wl.isnr_db / 20)
+    Y = y0 + sigma * wl.noise
+    eps = math.sqrt((8 * M + 2 * math.sqrt(2 * 8 * M)) * sigma ** 2 / 2)
+    phi_norm = s.opnorm(300, 1e-8)
+    s.set_prior(wl.levels, 1.0)
+    gamma = 1e-3 * float(np.max(np.abs(s.psi_adjoint(s.phi_adjoint(Y))))) / phi_norm
+    s.set_prior(wl.levels, gamma)
+    s.set_data(Y, eps)
+    s.set_steps()
+    # initialisation stage and first reweighting, so the timed iterations run every term
+    s.solve(P.PSARA_NNLS_INIT, 100, report=False)
+    s.psara_delta = P.psara_coef_std(s.ctx)
+    P.psara_reweight(s.ctx, s.psara_delta)
+    s.solve(P.PSARA_CONSTRAINED, args.warmup, report=False)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.solve(P.PSARA_CONSTRAINED, args.steps, report=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = args.steps / dt
+    rep = s.report()
+
+    ms = s.profile_passes(P.PSARA_CONSTRAINED, args.profile_iters)
+    nbytes = algorithmic_bytes(N, M, nwav=8)
+    gbs = [b / (t * 1e-3) / 1e9 if t > 0 else 0.0 for b, t in zip(nbytes, ms)]
+    dom = int(np.argmax(ms))
+    traffic = committed_traffic(dom)
+    roofline = {"bound": "hbm", "achieved": round(gbs[dom], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs[dom] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"{P.PASS_NAMES[dom]} ({PASS_KERNELS[dom]})",
+                "algorithmic_bytes_per_launch": nbytes[dom], "avg_launch_ms": round(ms[dom], 5)}
+    passes = {P.PASS_NAMES[i]: {"ms": round(ms[i], 5), "GB/s": round(gbs[i], 1)} for i in range(9)}
+
+    line = {
+        "metric": "PD iters/s (4-Stokes 256², 2e5 vis); served solves/s + p50/p99 latency",
+        "value": round(its, 2), "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 / its, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256x256 Stokes I,Q,U,V; 2e5 visibility rows (Gaussian + 8-station arcs); "
+                               "KB 8x8 on a 2x oversampled grid; SARA Dirac+Db1-Db8, 4 levels; "
+                               "Polarized SARA iteration, all terms active",
+                   "n": n, "M": M, "taps": wl.taps, "levels": wl.levels, "precision": "FP32 bulk, FP64 reductions"},
+        "roofline": roofline,
+        "passes": passes,
+        "sum_of_pass_ms": round(float(np.sum(ms)), 5),
+        "solve_check": {"residual_over_eps": rep["residual"] / rep["epsilon"], "n_p": rep["n_p"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_iters)
+    s.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -191,12 +191,13 @@ int psara_layout(const psara_ctx* ctx, int64_t* perm);
 
 /* ---- profiling --------------------------------------------------------------------------- */
 
-/* Time `reps` back-to-back launches of one pass of the iteration with HIP events on the
- * context stream; writes the average duration in milliseconds.  Pass ids: 0 primal/epigraph
- * (P1), 1 SARA analysis + dual A (P2), 2 SARA synthesis (P3), 3 row FFT (P4), 4 column FFT
- * (P5), 5 de-grid + dual B (P6), 6 grid (P7), 7 column inverse FFT (P8), 8 row inverse FFT
- * (P9).  The state is modified (the pass really runs). */
-psara_status psara_time_pass(psara_ctx* ctx, int pass_id, int reps, double* avg_ms);
+/* Run `iters` iterations of Algorithm 1 in `mode` with every pass on the context stream
+ * (no graph, the two independent branches serialised), bracket each pass with HIP events,
+ * and write the average duration in milliseconds of each of the nine passes to
+ * ms_per_pass[0..8]: P1 primal / epigraph / Dirac dual, P2 SARA analysis + dual A, P3 SARA
+ * synthesis, P4 zero-pad + row FFT, P5 column FFT, P6 de-grid + dual B, P7 grid, P8 column
+ * inverse FFT, P9 row inverse FFT + crop.  The iterations really run (the state advances). */
+psara_status psara_profile_passes(psara_ctx* ctx, psara_mode mode, int iters, double* ms_per_pass);
 
 #ifdef __cplusplus
 }

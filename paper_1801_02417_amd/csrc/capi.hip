@@ -406,12 +406,14 @@ int psara_layout(const psara_ctx* c, int64_t* perm) {
   return c->geo.ts;
 }
 
-psara_status psara_time_pass(psara_ctx* c, int pass_id, int reps, double* avg_ms) {
+psara_status psara_profile_passes(psara_ctx* c, psara_mode mode, int iters, double* ms_per_pass) {
   return guard(c, [&] {
+    const int pm = primal_mode(mode);
     require(c->op_set && c->data_set && c->steps_set, PSARA_ESTATE, "solve set-up incomplete");
-    require((pass_id != 1 && pass_id != 2) || c->prior_set, PSARA_ESTATE, "prior not set");
-    require(pass_id >= 0 && pass_id <= 8 && reps >= 1 && avg_ms, PSARA_EINVAL, "bad pass id or reps");
-    with_engine(c, [&](auto& e) { *avg_ms = e.time_pass(pass_id, reps); });
+    require(pm == psara::PM_INIT || c->prior_set, PSARA_ESTATE, "prior not set");
+    require(iters >= 1 && ms_per_pass != nullptr, PSARA_EINVAL, "bad iteration count or output");
+    with_engine(c, [&](auto& e) { e.profile(pm, iters, ms_per_pass); });
+    c->iterations += iters;
   });
 }
 

@@ -16,6 +16,12 @@ constexpr int kMaxFilter = 16;   // Db8 has 16 taps
 constexpr int kMaxTaps = 8;      // Kaiser-Bessel taps per dimension
 constexpr int kMaxCheb = 17;     // Chebyshev coefficients per tap (degree <= 16)
 constexpr int kMaxLevels = 8;
+constexpr int kRunMax = 32;         // longest run of same-window visibilities one lane group takes
+constexpr int kChunkEntries = 1024; // gridding entries per workgroup (staged in LDS)
+constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
+
+// Chebyshev degree of the per-tap Kaiser-Bessel expansions (max error ~1e-10 / ~1e-15)
+template <typename R> struct KbDeg { static constexpr int value = sizeof(R) == 4 ? 10 : 16; };
 
 // image-space buffers (N pixels x 4 Stokes, or x 2 for Z / D)
 enum ImgSlot { IMG_S = 0, IMG_X, IMG_C, IMG_PSIA, IMG_PHIB, IMG_TMP, IMG_TMP2, IMG_Z, IMG_D, NUM_IMG };
@@ -48,6 +54,7 @@ struct ProbDesc {
   int n, K, T, levels;
   int nbases, has_dirac, nwav, ts;      // ts = grid tile side
   int ntile_side, deg, n_p6, gen_stride;
+  int ntile_side_g;       // gridding tiles per side (side kGridTile)
   long long M;
   double tau, rho1, rho2, rho3, eps, gamma, norm;   // norm = 1/sqrt(nbases)
   double delta;                                     // reweighting delta in use
@@ -61,8 +68,13 @@ struct ProbDesc {
   const int* vis_k0;   // packed window starts (k1 << 16 | k2), sorted order
   const void* vis_frac;   // (f1, f2) per vis, type R
   const int* own_ptr;     // ntiles+1: sorted-vis range whose window starts in each tile
-  const int* list_ptr;    // ntiles+1: CSR into list_idx (every vis touching each tile)
-  const int* list_idx;
+  const int* list_idx;    // per gridding tile: every vis whose window touches it
+  const int* run_beg;     // gridding runs: first list entry and length
+  const int* run_len;
+  const int* run_k0;      // packed window start of each run
+  const int2* chunk_ent;  // list-entry range [lo, hi) of each gridding chunk
+  void* gpart;            // partial tiles of split gridding tiles: n_slots x kGridTile^2 cells
+  const int4* chunks;     // gridding chunks {tile, first run, end run, partial slot or -1}
   const void* cheb;       // T x (deg+1) Chebyshev coefficients, type R
   const void* twiddle;    // K complex exp(-2 pi i j / K), type R
   const void* deapod;     // n scaling factors 1/psi_hat((j - n/2)/K), type R
@@ -144,20 +156,20 @@ __device__ inline double block_sum_partials(const double* parts, int count, doub
 // every tap's argument spans one unit interval and u = 2f - T + 1 in (-1, 1] is common to all
 // taps.  Each tap carries its own Chebyshev expansion on that interval.
 template <typename R>
-__device__ inline void kb_weights(R f, int T, int deg, const R* __restrict__ cheb, R* w) {
+__device__ inline void kb_weights(R f, int T, const R* __restrict__ cheb, R* w) {
+  constexpr int DEG = KbDeg<R>::value;
   const R u = R(2) * f - R(T - 1);
-  R tk[kMaxCheb];
+  R tk[DEG + 1];
   tk[0] = R(1);
   tk[1] = u;
 #pragma unroll
-  for (int k = 2; k < kMaxCheb; ++k) tk[k] = (k <= deg) ? R(2) * u * tk[k - 1] - tk[k - 2] : R(0);
+  for (int k = 2; k <= DEG; ++k) tk[k] = R(2) * u * tk[k - 1] - tk[k - 2];
 #pragma unroll
   for (int i = 0; i < kMaxTaps; ++i) {
     R acc = R(0);
     if (i < T) {
 #pragma unroll
-      for (int k = 0; k < kMaxCheb; ++k)
-        if (k <= deg) acc += cheb[i * (deg + 1) + k] * tk[k];
+      for (int k = 0; k <= DEG; ++k) acc += cheb[i * (DEG + 1) + k] * tk[k];
     }
     w[i] = acc;
   }

@@ -33,6 +33,7 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
   g.n = n; g.K = alpha * n; g.T = T; g.M = M;
   g.ts = (g.K >= 512) ? 32 : 16;
   g.nts = g.K / g.ts;
+  g.ntsg = g.K / kGridTile;
   g.beta = kb_beta(T, alpha);
   const int K = g.K, ts = g.ts, nts = g.nts;
   const int ntiles = nts * nts;
@@ -68,28 +69,67 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
     g.own_ptr[tile[m] + 1]++;
   }
   for (int t = 0; t < ntiles; ++t) g.own_ptr[t + 1] += g.own_ptr[t];
-  // every tile a window touches (at most two per dimension since T <= ts)
+  // gridding tiles (side kGridTile): every tile a window touches, at most two per dimension
+  const int tg = kGridTile, ntsg = g.ntsg, ntg = ntsg * ntsg;
   auto touched = [&](int k, int* out) {
-    out[0] = k / ts;
-    const int e = ((k + T - 1) & (K - 1)) / ts;
+    out[0] = k / tg;
+    const int e = ((k + T - 1) & (K - 1)) / tg;
     if (e != out[0]) { out[1] = e; return 2; }
     return 1;
   };
-  g.list_ptr.assign(ntiles + 1, 0);
+  g.list_ptr.assign(ntg + 1, 0);
   for (int64_t p = 0; p < M; ++p) {
     int a[2], b[2];
     const int na = touched(g.k0[p] >> 16, a), nb = touched(g.k0[p] & 0xffff, b);
     for (int i = 0; i < na; ++i)
-      for (int j = 0; j < nb; ++j) g.list_ptr[a[i] * nts + b[j] + 1]++;
+      for (int j = 0; j < nb; ++j) g.list_ptr[a[i] * ntsg + b[j] + 1]++;
   }
-  for (int t = 0; t < ntiles; ++t) g.list_ptr[t + 1] += g.list_ptr[t];
-  g.list_idx.resize(g.list_ptr[ntiles]);
+  for (int t = 0; t < ntg; ++t) g.list_ptr[t + 1] += g.list_ptr[t];
+  g.list_idx.resize(g.list_ptr[ntg]);
   std::vector<int> fillp(g.list_ptr.begin(), g.list_ptr.end() - 1);
   for (int64_t p = 0; p < M; ++p) {
     int a[2], b[2];
     const int na = touched(g.k0[p] >> 16, a), nb = touched(g.k0[p] & 0xffff, b);
     for (int i = 0; i < na; ++i)
-      for (int j = 0; j < nb; ++j) g.list_idx[fillp[a[i] * nts + b[j]]++] = (int)p;
+      for (int j = 0; j < nb; ++j) g.list_idx[fillp[a[i] * ntsg + b[j]]++] = (int)p;
+  }
+  // runs: consecutive list entries of a tile with the same window start (their taps hit the
+  // same cells), split at kRunMax; chunks of whole runs with <= kChunkEntries entries, runs
+  // ordered longest first inside a chunk so the lanes of a wave loop for similar lengths
+  for (int t = 0; t < ntg; ++t) {
+    std::vector<std::pair<int, int>> runs;
+    for (int e = g.list_ptr[t]; e < g.list_ptr[t + 1];) {
+      int f = e + 1;
+      while (f < g.list_ptr[t + 1] && f - e < kRunMax && g.k0[g.list_idx[f]] == g.k0[g.list_idx[e]]) ++f;
+      runs.push_back({e, f - e});
+      e = f;
+    }
+    std::vector<int4> tile_chunks;
+    size_t r = 0;
+    do {
+      const size_t r0 = r;
+      int entries = 0;
+      while (r < runs.size() && (entries + runs[r].second <= kChunkEntries || r == r0)) entries += runs[r++].second;
+      std::stable_sort(runs.begin() + r0, runs.begin() + r,
+                       [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.second > y.second; });
+      const int base = (int)g.run_beg.size();
+      int lo = g.list_ptr[t + 1], hi = g.list_ptr[t];
+      for (size_t q = r0; q < r; ++q) {
+        g.run_beg.push_back(runs[q].first);
+        g.run_len.push_back(runs[q].second);
+        g.run_k0.push_back(g.k0[g.list_idx[runs[q].first]]);
+        lo = std::min(lo, runs[q].first);
+        hi = std::max(hi, runs[q].first + runs[q].second);
+      }
+      if (r == r0) lo = hi = g.list_ptr[t];
+      tile_chunks.push_back(make_int4(t, base, base + (int)(r - r0), -1));
+      g.chunk_ent.push_back(make_int2(lo, hi));
+    } while (r < runs.size());
+    if (tile_chunks.size() > 1) {
+      g.merges.push_back(make_int4(t, g.n_slots, (int)tile_chunks.size(), 0));
+      for (auto& c : tile_chunks) c.w = g.n_slots++;
+    }
+    g.chunks.insert(g.chunks.end(), tile_chunks.begin(), tile_chunks.end());
   }
   return g;
 }
@@ -107,7 +147,9 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int*
   for (int t = 0; t < ntiles; ++t) {
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += 256) S.p6.push_back(make_int4(prob, t, v, part++));
   }
-  for (int t = 0; t < ntiles; ++t) S.p7.push_back(make_int4(prob, t, t == 0 ? 1 : 0, 0));
+  // the first gridding item of a problem stores the l2-ball factor; .y packs the chunk index
+  for (size_t c = 0; c < g.chunks.size(); ++c) S.p7.push_back(make_int4(prob, (int)c, c == 0 ? 1 : 0, 0));
+  for (const auto& mg : g.merges) S.p7m.push_back(make_int4(prob, mg.x, mg.y, mg.z));
   *n_p6 = part;
 }
 
@@ -147,8 +189,8 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   const int64_t M = g.M;
   cells_ = std::max(512, K);
   h_.n = n; h_.K = K; h_.T = g.T; h_.M = M;
-  h_.ts = g.ts; h_.ntile_side = g.nts;
-  h_.deg = std::is_same<R, double>::value ? 16 : 10;
+  h_.ts = g.ts; h_.ntile_side = g.nts; h_.ntile_side_g = g.ntsg;
+  h_.deg = KbDeg<R>::value;
   for (int s = 0; s < IMG_Z; ++s) h_.img[s] = dalloc<V4<R>>(N);
   h_.img[IMG_Z] = dalloc<V2<R>>(N);
   h_.img[IMG_D] = dalloc<V2<R>>(N);
@@ -159,8 +201,13 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   h_.vis_k0 = upload<int>(g.k0.data(), M);
   h_.vis_frac = upload_conv(g.frac.data(), 2 * M);
   h_.own_ptr = upload<int>(g.own_ptr.data(), g.own_ptr.size());
-  h_.list_ptr = upload<int>(g.list_ptr.data(), g.list_ptr.size());
   h_.list_idx = upload<int>(g.list_idx.data(), std::max<size_t>(1, g.list_idx.size()));
+  h_.run_beg = upload<int>(g.run_beg.data(), std::max<size_t>(1, g.run_beg.size()));
+  h_.run_len = upload<int>(g.run_len.data(), std::max<size_t>(1, g.run_len.size()));
+  h_.run_k0 = upload<int>(g.run_k0.data(), std::max<size_t>(1, g.run_k0.size()));
+  h_.chunk_ent = upload<int2>(g.chunk_ent.data(), std::max<size_t>(1, g.chunk_ent.size()));
+  h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
+  h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * kGridTile * kGridTile);
   // tables
   std::vector<double> cheb = kb_chebyshev(g.T, g.beta, h_.deg);
   h_.cheb = upload_conv(cheb.data(), cheb.size());
@@ -257,7 +304,8 @@ void Engine<R>::upload_items() {
     if (!v.empty()) d.ptr = upload<int4>(v.data(), v.size());
   };
   up(d_img_, items_.img); up(d_rows_, items_.rows); up(d_cols_, items_.cols);
-  up(d_p6_, items_.p6); up(d_p7_, items_.p7); up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal);
+  up(d_p6_, items_.p6); up(d_p7_, items_.p7); up(d_p7m_, items_.p7m);
+  up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal);
   for (int l = 0; l <= kMaxLevels; ++l) { up(d_ana_[l], items_.ana[l]); up(d_syn_[l], items_.syn[l]); }
   if (!d_desc_) d_desc_ = dalloc<ProbDesc>(1);
   desc_dirty_ = true;
@@ -378,6 +426,7 @@ template <typename R> void Engine<R>::p6(int mode, int src, int out, hipStream_t
 }
 template <typename R> void Engine<R>::p7(int mode, int src, int use_cfac, hipStream_t s) {
   launch_grid<R>(mode, la(d_p7_, s), geo_.ts, src, use_cfac);
+  launch_grid_merge<R>(la(d_p7m_, s), geo_.ts);
 }
 template <typename R> void Engine<R>::p8(hipStream_t s) { launch_fft<R>(2, la(d_cols_, s), cells_, 0, 0); }
 template <typename R> void Engine<R>::p9(int dst, hipStream_t s) { launch_fft<R>(3, la(d_rows_, s), cells_, 0, dst); }
@@ -690,35 +739,45 @@ void Engine<R>::set_state(const double* buf) {
   hip_check(hipStreamSynchronize(s0_), "set_state");
 }
 
+// Run `iters` iterations with every pass on stream 0, bracketed by HIP events, and return the
+// average duration of each pass (P1..P9) in milliseconds.
 template <typename R>
-double Engine<R>::time_pass(int pass, int reps) {
+void Engine<R>::profile(int mode, int iters, double* ms) {
   sync_desc();
-  hipEvent_t a, b;
-  hip_check(hipEventCreate(&a), "event");
-  hip_check(hipEventCreate(&b), "event");
-  auto once = [&]() {
-    switch (pass) {
-      case 0: p1(PM_CONSTRAINED, s0_); break;
-      case 1: p2(s0_); break;
-      case 2: p3(COEF_A, IMG_PSIA, 0, s0_); break;
-      case 3: p4(IMG_X, s0_); break;
-      case 4: p5(s0_); break;
-      case 5: p6(DG_DUAL, VIS_BV, VIS_BV, s0_); break;
-      case 6: p7(GR_DUAL, VIS_BV, 0, s0_); break;
-      case 7: p8(s0_); break;
-      default: p9(IMG_PHIB, s0_); break;
+  constexpr int NP = 9;
+  hipEvent_t ev[NP + 1];
+  for (int i = 0; i <= NP; ++i) hip_check(hipEventCreate(&ev[i]), "event");
+  for (int i = 0; i < NP; ++i) ms[i] = 0.0;
+  const bool sparse = (mode != PM_INIT) && h_.coef[COEF_A] && h_.nwav > 0;
+  for (int k = 0; k < iters; ++k) {
+    hip_check(hipEventRecord(ev[0], s0_), "event record");
+    p1(mode, s0_);
+    hip_check(hipEventRecord(ev[1], s0_), "event record");
+    if (sparse) p2(s0_);
+    hip_check(hipEventRecord(ev[2], s0_), "event record");
+    if (sparse) p3(COEF_A, IMG_PSIA, 0, s0_);
+    hip_check(hipEventRecord(ev[3], s0_), "event record");
+    p4(IMG_X, s0_);
+    hip_check(hipEventRecord(ev[4], s0_), "event record");
+    p5(s0_);
+    hip_check(hipEventRecord(ev[5], s0_), "event record");
+    p6(DG_DUAL, VIS_BV, VIS_BV, s0_);
+    hip_check(hipEventRecord(ev[6], s0_), "event record");
+    p7(GR_DUAL, VIS_BV, 0, s0_);
+    hip_check(hipEventRecord(ev[7], s0_), "event record");
+    p8(s0_);
+    hip_check(hipEventRecord(ev[8], s0_), "event record");
+    p9(IMG_PHIB, s0_);
+    hip_check(hipEventRecord(ev[9], s0_), "event record");
+    hip_check(hipEventSynchronize(ev[9]), "event sync");
+    for (int i = 0; i < NP; ++i) {
+      float t = 0.f;
+      hip_check(hipEventElapsedTime(&t, ev[i], ev[i + 1]), "elapsed");
+      ms[i] += t;
     }
-  };
-  once();
-  hip_check(hipEventRecord(a, s0_), "event record");
-  for (int i = 0; i < reps; ++i) once();
-  hip_check(hipEventRecord(b, s0_), "event record");
-  hip_check(hipEventSynchronize(b), "event sync");
-  float ms = 0.f;
-  hip_check(hipEventElapsedTime(&ms, a, b), "elapsed");
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
-  return (double)ms / reps;
+  }
+  for (int i = 0; i < NP; ++i) ms[i] /= std::max(iters, 1);
+  for (int i = 0; i <= NP; ++i) (void)hipEventDestroy(ev[i]);
 }
 
 template struct Engine<float>;

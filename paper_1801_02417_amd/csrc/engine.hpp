@@ -25,20 +25,28 @@ void hip_check(hipError_t e, const char* what);
 
 // Sorted visibility layout and tile binning of one uv coverage (precision independent).
 struct Geometry {
-  int n = 0, K = 0, T = 0, ts = 0, nts = 0;
+  int n = 0, K = 0, T = 0, ts = 0, nts = 0, ntsg = 0;
   int64_t M = 0;
   double beta = 0.0;
   std::vector<int64_t> perm;      // sorted position -> caller index
   std::vector<int> k0;            // packed window starts (k1 << 16 | k2), sorted order
   std::vector<double> frac;       // (f1, f2) per sorted visibility
   std::vector<int> own_ptr;       // per tile: range of visibilities whose window starts there
-  std::vector<int> list_ptr, list_idx;   // per tile: every visibility whose window touches it
+  std::vector<int> list_ptr, list_idx;   // per gridding tile: every visibility whose window touches it
+  // gridding work: runs of list entries sharing one window start (at most kRunMax long),
+  // grouped into chunks of at most kChunkEntries entries; a tile with several chunks sums
+  // their partial tiles in a merge pass
+  std::vector<int> run_beg, run_len, run_k0;   // per run: first list entry, length, window start
+  std::vector<int4> chunks;              // {tile, first run, end run, partial slot or -1}
+  std::vector<int2> chunk_ent;           // list-entry range [lo, hi) each chunk covers
+  std::vector<int4> merges;              // {tile, first slot, slot count, -}
+  int n_slots = 0;
 };
 
 Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T);
 
 struct ItemSet {
-  std::vector<int4> img, rows, cols, p6, p7, dirac, synfinal;
+  std::vector<int4> img, rows, cols, p6, p7, p7m, dirac, synfinal;
   std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
 };
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int* n_p6);
@@ -73,7 +81,7 @@ struct Engine {
   void get_state(double* buf);
   void set_state(const double* buf);
   void get_img(int slot, double* dst, int comps);
-  double time_pass(int pass, int reps);
+  void profile(int mode, int iters, double* ms);
   size_t coef_elems() const { return coef_elems_; }
   size_t device_bytes() const { return bytes_; }
   const ProbDesc& desc() const { return h_; }
@@ -120,7 +128,7 @@ struct Engine {
   ProbDesc* d_desc_ = nullptr;
   bool desc_dirty_ = true;
   ItemSet items_;
-  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_dirac_, d_synfinal_;
+  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_p7m_, d_dirac_, d_synfinal_;
   DevItems d_ana_[kMaxLevels + 1], d_syn_[kMaxLevels + 1];
   int cells_ = 512;
   int gen_parts_ = 1, ana_parts_ = 0;

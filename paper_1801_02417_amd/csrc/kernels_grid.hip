@@ -6,9 +6,10 @@
 // Visibilities are sorted once (at set-up) by the grid tile that holds their window start
 // k0 = ceil(t - T/2).  De-gridding stages a tile plus its (T-1)-cell halo of the grid in LDS
 // and lets one thread per visibility gather its T x T taps from there.  Gridding is done
-// by tile owners: the workgroup of a tile walks the list of every visibility whose window
-// touches the tile and accumulates the taps that fall inside it in LDS; the tile is then
-// written once with plain stores, so no global atomics are used.
+// by tile owners: the workgroups of a tile walk the list of every visibility whose window
+// touches the tile and accumulate the taps that fall inside it in LDS; the tile is then
+// written once with plain stores (split tiles through partial slots summed in a fixed
+// order), so no global atomics are used.
 //
 // The dual variable B is kept as B = c * Bv: the de-gridding pass writes
 // Bv = B/rho2 + phi(X) - Y and the FP64 partial sums of ||Bv||^2; the gridding pass reduces
@@ -50,8 +51,8 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
     const int r1 = (pk >> 16) - b1, r2 = (pk & 0xffff) - b2;
     const V2<R> f = ((const V2<R>*)P.vis_frac)[m];
     R w1[kMaxTaps], w2[kMaxTaps];
-    kb_weights<R>(f.x, T, P.deg, (const R*)P.cheb, w1);
-    kb_weights<R>(f.y, T, P.deg, (const R*)P.cheb, w2);
+    kb_weights<R>(f.x, T, (const R*)P.cheb, w1);
+    kb_weights<R>(f.y, T, (const R*)P.cheb, w2);
     cplx<R> v[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = cmk(R(0), R(0));
@@ -126,22 +127,44 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int max_T, int src
 }
 
 // ---------------------------------------------------------------------------------------------
-// P7: grid (adjoint of G, after mixing by L^H).  items: {prob, tile, writer flag, -}
-// MODE GR_DUAL: scale = c from the P6 partials (stored by the writer); GR_PLAIN: scale = 1, or
-// the stored c when use_cfac is set.
+// P7: grid (adjoint of G, after mixing by L^H).  items: {prob, chunk, writer flag, -}
+//
+// The grid is cut into kGridTile x kGridTile tiles; a chunk is a set of runs of one tile's
+// list, a run being visibilities with the same window start, so all their T x T taps land on
+// the same cells.  The chunk's entries (offsets and L^H-mixed values) are first staged in LDS
+// by the whole workgroup.  A group of 8 lanes then takes one run: lane i owns tap row i and
+// accumulates, over the run, the 8 cells of that row for the 8 real channels in registers
+// (the column weights are shared through lane shuffles), and adds the row to the tile once.
+//
+// The tile accumulates in 64-bit fixed point with integer LDS atomics: integer addition is
+// associative, so the result does not depend on the order in which lanes arrive (the
+// gridding is bitwise reproducible), and integer LDS atomics run far faster than floating
+// ones.  The scale is 2^61 / sum_v max_c |u_v,c| over the chunk, a bound on any partial sum
+// of a cell (the kernel weights are at most 1), so no sum can overflow; the absolute
+// rounding per addition is 2^-62 of that bound.
+//
+// The finished tile goes to the grid, or -- when the tile was split into several chunks -- to
+// a partial slot that the merge pass sums in a fixed order.  MODE GR_DUAL: scale = c from the
+// de-grid partials (stored by the writer item); GR_PLAIN: scale = 1, or the stored c when
+// use_cfac is set.
 template <typename R, int MODE>
 __global__ void __launch_bounds__(256)
 grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* acc = (R*)smem_raw;                       // ts*ts cells x 8 reals
+  constexpr int TG = kGridTile;
+  constexpr int DEG = KbDeg<R>::value;
+  __shared__ unsigned long long acc[TG * TG * 8];
+  __shared__ V2<R> sf[kChunkEntries];             // staged fractional offsets
+  __shared__ V4<R> su[2 * kChunkEntries];         // staged mixed values, two V4 per entry
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
-  const int K = P.K, T = P.T, ts = P.ts, nts = P.ntile_side;
-  const int tile = it.y;
-  const int t1 = tile / nts, t2 = tile - t1 * nts;
-  const int b1 = t1 * ts, b2 = t2 * ts;
-  for (int q = threadIdx.x; q < ts * ts * 8; q += blockDim.x) acc[q] = R(0);
+  const int4 ch = P.chunks[it.y];
+  const int2 ent = P.chunk_ent[it.y];
+  const int K = P.K, T = P.T, ntg = P.ntile_side_g;
+  const int tile = ch.x;
+  const int t1 = tile / ntg, t2 = tile - t1 * ntg;
+  const int b1 = t1 * TG, b2 = t2 * TG;
+  for (int q = threadIdx.x; q < TG * TG * 8; q += blockDim.x) acc[q] = 0ull;
 
   R scale = R(1);
   if (MODE == GR_DUAL) {
@@ -156,62 +179,146 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   } else if (use_cfac) {
     scale = R(P.scal[SC_CFAC]);
   }
-  __syncthreads();
-
+  // stage the chunk's entries: offsets and B L^H (I = B1 + B4, Q = B1 - B4, U = B2 + B3,
+  // V = i (B3 - B2)), scaled; sum the largest channel magnitude of each for the fixed point
   const Cell<R>* __restrict__ bsrc = (const Cell<R>*)P.vis[src_slot];
-  const int e0 = P.list_ptr[tile], e1 = P.list_ptr[tile + 1];
-  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int m = P.list_idx[e];
-    const int pk = P.vis_k0[m];
-    const int k1 = pk >> 16, k2 = pk & 0xffff;
-    const V2<R> f = ((const V2<R>*)P.vis_frac)[m];
-    R w1[kMaxTaps], w2[kMaxTaps];
-    kb_weights<R>(f.x, T, P.deg, (const R*)P.cheb, w1);
-    kb_weights<R>(f.y, T, P.deg, (const R*)P.cheb, w2);
+  const V2<R>* __restrict__ frac = (const V2<R>*)P.vis_frac;
+  KSum bound;
+  for (int q = threadIdx.x; q < ent.y - ent.x; q += blockDim.x) {
+    const int m = P.list_idx[ent.x + q];
+    sf[q] = frac[m];
     const Cell<R> b = bsrc[m];
-    // B L^H: I = B1 + B4, Q = B1 - B4, U = B2 + B3, V = i (B3 - B2)
-    cplx<R> u[4];
-    u[0] = cscale(cadd(b.s[0], b.s[3]), scale);
-    u[1] = cscale(csub(b.s[0], b.s[3]), scale);
-    u[2] = cscale(cadd(b.s[1], b.s[2]), scale);
-    u[3] = cscale(cmuli(csub(b.s[2], b.s[1])), scale);
-    for (int j = 0; j < T; ++j) {
-      const int c2 = (k2 + j - b2) & (K - 1);
-      if (c2 >= ts) continue;
-      for (int i = 0; i < T; ++i) {
-        const int c1 = (k1 + i - b1) & (K - 1);
-        if (c1 >= ts) continue;
-        const R w = w1[i] * w2[j];
-        R* cell = acc + (size_t)(c2 * ts + c1) * 8;
+    V4<R> u0, u1;
+    u0.x = (b.s[0].re + b.s[3].re) * scale; u0.y = (b.s[0].im + b.s[3].im) * scale;
+    u0.z = (b.s[0].re - b.s[3].re) * scale; u0.w = (b.s[0].im - b.s[3].im) * scale;
+    u1.x = (b.s[1].re + b.s[2].re) * scale; u1.y = (b.s[1].im + b.s[2].im) * scale;
+    u1.z = -(b.s[2].im - b.s[1].im) * scale; u1.w = (b.s[2].re - b.s[1].re) * scale;
+    su[2 * q] = u0;
+    su[2 * q + 1] = u1;
+    const R mx = fmax(fmax(fmax(fabs(u0.x), fabs(u0.y)), fmax(fabs(u0.z), fabs(u0.w))),
+                      fmax(fmax(fabs(u1.x), fabs(u1.y)), fmax(fabs(u1.z), fabs(u1.w))));
+    bound.add((double)mx);
+  }
+  const double total = block_reduce(bound, red).value();      // includes a barrier
+  const double fx = total > 0.0 ? ldexp(1.0, 61) / (total * (1.0 + 1e-6)) : 1.0;
+
+  const int lane8 = threadIdx.x & 7;               // tap row owned by this lane
+  const int grp = threadIdx.x >> 3, ngrp = blockDim.x >> 3;
+  R cr[DEG + 1];                                   // this lane's tap expansion
+  {
+    const R* __restrict__ cheb = (const R*)P.cheb + (lane8 < T ? lane8 : 0) * (DEG + 1);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          atomicAdd(cell + 2 * s, w * u[s].re);
-          atomicAdd(cell + 2 * s + 1, w * u[s].im);
+    for (int k = 0; k <= DEG; ++k) cr[k] = lane8 < T ? cheb[k] : R(0);
+  }
+  for (int rr = ch.y + grp; rr - grp < ch.z; rr += ngrp) {
+    const bool active = rr < ch.z;
+    const int e0 = active ? P.run_beg[rr] - ent.x : 0;
+    const int len = active ? P.run_len[rr] : 0;
+    const int pk = active ? P.run_k0[rr] : 0;
+    R a[kMaxTaps][8];
+#pragma unroll
+    for (int j = 0; j < kMaxTaps; ++j)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) a[j][c] = R(0);
+    for (int q = 0; q < len; ++q) {
+      const V2<R> f = sf[e0 + q];
+      // this lane's tap in each dimension: psi(f - lane8) from its Chebyshev expansion
+      const R u1 = R(2) * f.x - R(T - 1), u2 = R(2) * f.y - R(T - 1);
+      R p1 = R(1), c1 = u1, p2 = R(1), c2 = u2;
+      R w1 = cr[0] + cr[1] * u1, w2 = cr[0] + cr[1] * u2;
+#pragma unroll
+      for (int k = 2; k <= DEG; ++k) {
+        const R n1 = R(2) * u1 * c1 - p1, n2 = R(2) * u2 * c2 - p2;
+        p1 = c1; c1 = n1; p2 = c2; c2 = n2;
+        w1 += cr[k] * c1;
+        w2 += cr[k] * c2;
+      }
+      const V4<R> v0 = su[2 * (e0 + q)], v1 = su[2 * (e0 + q) + 1];
+      const R u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int j = 0; j < kMaxTaps; ++j) {
+        const R wj = w1 * __shfl(w2, j, 8);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a[j][c] += wj * u[c];
+      }
+    }
+    if (len > 0 && lane8 < T) {
+      const int c1 = ((pk >> 16) + lane8 - b1) & (K - 1);
+      if (c1 < TG) {
+#pragma unroll
+        for (int j = 0; j < kMaxTaps; ++j) {
+          const int c2 = ((pk & 0xffff) + j - b2) & (K - 1);
+          if (j < T && c2 < TG) {
+            unsigned long long* cell = acc + (size_t)(c2 * TG + c1) * 8;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              atomicAdd(cell + c, (unsigned long long)__double2ll_rn((double)a[j][c] * fx));
+          }
         }
       }
     }
   }
   __syncthreads();
-  Cell<R>* __restrict__ grid = (Cell<R>*)P.grid;
-  for (int q = threadIdx.x; q < ts * ts; q += blockDim.x) {
-    const int a = q / ts, b = q - a * ts;        // a: k2 offset, b: k1 offset
+  Cell<R>* __restrict__ dst;
+  size_t stride;
+  if (ch.w < 0) {                       // the whole tile is in this chunk: write the grid
+    dst = (Cell<R>*)P.grid + (size_t)b2 * K + b1;
+    stride = K;
+  } else {                              // one of several chunks: write its partial slot
+    dst = (Cell<R>*)P.gpart + (size_t)ch.w * TG * TG;
+    stride = TG;
+  }
+  const double inv = 1.0 / fx;
+  for (int q = threadIdx.x; q < TG * TG; q += blockDim.x) {
+    const int a2 = q / TG, a1 = q - a2 * TG;        // a2: k2 offset, a1: k1 offset
     Cell<R> c;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) c.s[s] = cmk(acc[(size_t)q * 8 + 2 * s], acc[(size_t)q * 8 + 2 * s + 1]);
-    grid[(size_t)(b2 + a) * K + (b1 + b)] = c;
+    for (int s = 0; s < 4; ++s)
+      c.s[s] = cmk(R((double)(long long)acc[(size_t)q * 8 + 2 * s] * inv),
+                   R((double)(long long)acc[(size_t)q * 8 + 2 * s + 1] * inv));
+    dst[(size_t)a2 * stride + a1] = c;
+  }
+}
+
+// Merge of split tiles: the grid tile is the sum of its chunks' partial tiles, in slot order.
+// items: {prob, tile, first slot, slot count}
+template <typename R>
+__global__ void __launch_bounds__(256)
+grid_merge_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items) {
+  constexpr int TG = kGridTile;
+  const int4 it = items[blockIdx.x];
+  const ProbDesc& P = descs[it.x];
+  const int K = P.K, ntg = P.ntile_side_g;
+  const int t1 = it.y / ntg, t2 = it.y - t1 * ntg;
+  const Cell<R>* __restrict__ part = (const Cell<R>*)P.gpart + (size_t)it.z * TG * TG;
+  Cell<R>* __restrict__ grid = (Cell<R>*)P.grid;
+  for (int q = threadIdx.x; q < TG * TG; q += blockDim.x) {
+    Cell<R> c = part[q];
+    for (int k = 1; k < it.w; ++k) {
+      const Cell<R> o = part[(size_t)k * TG * TG + q];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) c.s[s] = cadd(c.s[s], o.s[s]);
+    }
+    const int a2 = q / TG, a1 = q - a2 * TG;
+    grid[(size_t)(t2 * TG + a2) * K + t1 * TG + a1] = c;
   }
 }
 
 template <typename R>
 void launch_grid(int mode, const LaunchArgs& a, int max_ts, int src_slot, int use_cfac) {
   if (a.nitems <= 0) return;
-  const size_t shm = (size_t)max_ts * max_ts * 8 * sizeof(R);
   const dim3 grid(a.nitems), block(256);
   if (mode == GR_DUAL) {
-    hipLaunchKernelGGL((grid_kernel<R, GR_DUAL>), grid, block, shm, a.stream, a.descs, a.items, src_slot, use_cfac);
+    hipLaunchKernelGGL((grid_kernel<R, GR_DUAL>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
   } else {
-    hipLaunchKernelGGL((grid_kernel<R, GR_PLAIN>), grid, block, shm, a.stream, a.descs, a.items, src_slot, use_cfac);
+    hipLaunchKernelGGL((grid_kernel<R, GR_PLAIN>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
   }
+}
+
+template <typename R>
+void launch_grid_merge(const LaunchArgs& a, int /*max_ts*/) {
+  if (a.nitems <= 0) return;
+  hipLaunchKernelGGL((grid_merge_kernel<R>), dim3(a.nitems), dim3(256), 0, a.stream, a.descs, a.items);
 }
 
 // Raise the dynamic-LDS limit of the de-grid / grid kernels once, outside any graph capture.
@@ -219,12 +326,9 @@ template <typename R>
 void set_grid_kernel_limits(int max_ts, int max_T) {
   const int W = max_ts + max_T - 1;
   const int shm_dg = W * W * (int)sizeof(Cell<R>);
-  const int shm_gr = max_ts * max_ts * 8 * (int)sizeof(R);
   hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_DUAL>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
   hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_FORWARD>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
   hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_RESIDUAL>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
-  hip_check(hipFuncSetAttribute((const void*)grid_kernel<R, GR_DUAL>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_gr), "attr");
-  hip_check(hipFuncSetAttribute((const void*)grid_kernel<R, GR_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_gr), "attr");
 }
 
 template void set_grid_kernel_limits<float>(int, int);
@@ -233,5 +337,7 @@ template void launch_degrid<float>(int, const LaunchArgs&, int, int, int, int);
 template void launch_degrid<double>(int, const LaunchArgs&, int, int, int, int);
 template void launch_grid<float>(int, const LaunchArgs&, int, int, int);
 template void launch_grid<double>(int, const LaunchArgs&, int, int, int);
+template void launch_grid_merge<float>(const LaunchArgs&, int);
+template void launch_grid_merge<double>(const LaunchArgs&, int);
 
 }  // namespace psara

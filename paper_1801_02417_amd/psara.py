@@ -30,7 +30,7 @@ EXPORTS = (
     "psara_coef_std", "psara_reweighted_solve", "psara_report_now", "psara_get_image", "psara_state_bytes",
     "psara_get_state", "psara_set_state", "psara_reset_state", "psara_footprint", "psara_apply_phi",
     "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
-    "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_time_pass",
+    "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_profile_passes",
 )
 
 
@@ -93,7 +93,7 @@ def lib() -> C.CDLL:
         "psara_kb_value": (C.c_double, [I, C.c_double, C.c_double]),
         "psara_kb_deapod": (C.c_double, [I, C.c_double, C.c_double]),
         "psara_layout": (I, [P, C.POINTER(C.c_int64)]),
-        "psara_time_pass": (I, [P, I, I, D]),
+        "psara_profile_passes": (I, [P, I, I, D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -284,10 +284,15 @@ def psara_layout(ctx, M: int):
     return ts, perm
 
 
-def psara_time_pass(ctx, pass_id: int, reps: int) -> float:
-    out = C.c_double()
-    _check(ctx, lib().psara_time_pass(ctx, pass_id, reps, C.byref(out)))
-    return out.value
+PASS_NAMES = ("P1 primal+epigraph+Dirac dual", "P2 SARA analysis+dual A", "P3 SARA synthesis",
+              "P4 zero-pad+row FFT", "P5 column FFT", "P6 de-grid+dual B", "P7 grid",
+              "P8 column inverse FFT", "P9 row inverse FFT+crop")
+
+
+def psara_profile_passes(ctx, mode: int, iters: int) -> np.ndarray:
+    out = np.zeros(9)
+    _check(ctx, lib().psara_profile_passes(ctx, mode, iters, _dptr(out)))
+    return out
 
 
 # ---- convenience wrapper ------------------------------------------------------------------------
@@ -386,5 +391,5 @@ class Solver:
     def reset(self):
         psara_reset_state(self.ctx)
 
-    def time_pass(self, pass_id: int, reps: int) -> float:
-        return psara_time_pass(self.ctx, pass_id, reps)
+    def profile_passes(self, mode: int, iters: int) -> np.ndarray:
+        return psara_profile_passes(self.ctx, mode, iters)

@@ -17,7 +17,7 @@ constexpr int kMaxTaps = 8;      // Kaiser-Bessel taps per dimension
 constexpr int kMaxCheb = 17;     // Chebyshev coefficients per tap (degree <= 16)
 constexpr int kMaxLevels = 8;
 constexpr int kRunMax = 32;         // longest run of same-window visibilities one lane group takes
-constexpr int kChunkEntries = 1024; // gridding entries per workgroup (staged in LDS)
+constexpr int kChunkEntries = 512;  // gridding entries per workgroup (staged in LDS)
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
 
 // Chebyshev degree of the per-tap Kaiser-Bessel expansions (max error ~1e-10 / ~1e-15)

@@ -147,14 +147,20 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int*
   for (int t = 0; t < ntiles; ++t) {
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += 256) S.p6.push_back(make_int4(prob, t, v, part++));
   }
-  // the first gridding item of a problem stores the l2-ball factor; .y packs the chunk index
-  for (size_t c = 0; c < g.chunks.size(); ++c) S.p7.push_back(make_int4(prob, (int)c, c == 0 ? 1 : 0, 0));
+  // gridding chunks, heaviest first (entries as the work estimate) so the tail of the launch is
+  // short; the first item of a problem stores the l2-ball factor
+  std::vector<int> order(g.chunks.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (g.chunk_ent[a].y - g.chunk_ent[a].x) > (g.chunk_ent[b].y - g.chunk_ent[b].x);
+  });
+  for (size_t c = 0; c < order.size(); ++c) S.p7.push_back(make_int4(prob, order[c], c == 0 ? 1 : 0, 0));
   for (const auto& mg : g.merges) S.p7m.push_back(make_int4(prob, mg.x, mg.y, mg.z));
   *n_p6 = part;
 }
 
 void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int* n_ana_parts) {
-  const int TO = fp64 ? 8 : 16, TS = fp64 ? 16 : 32;
+  const int TO = fp64 ? 8 : 16, TS = fp64 ? 16 : 32, TF = 16;
   const int N = n * n;
   int part = 0;
   for (int b = 0; b < (N + 255) / 256; ++b) S.dirac.push_back(make_int4(prob, b, 0, part++));
@@ -171,7 +177,7 @@ void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp6
       for (int t = 0; t < tps * tps; ++t) S.syn[l].push_back(make_int4(prob, w, t, 0));
   }
   {
-    const int to = std::min(TS, n), tps = n / to;
+    const int to = std::min(TF, n), tps = n / to;
     for (int t = 0; t < tps * tps; ++t) S.synfinal.push_back(make_int4(prob, t, 0, 0));
   }
   *n_ana_parts = part;
@@ -305,7 +311,7 @@ void Engine<R>::upload_items() {
   };
   up(d_img_, items_.img); up(d_rows_, items_.rows); up(d_cols_, items_.cols);
   up(d_p6_, items_.p6); up(d_p7_, items_.p7); up(d_p7m_, items_.p7m);
-  up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal);
+  up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal); up(d_coarse_, items_.coarse);
   for (int l = 0; l <= kMaxLevels; ++l) { up(d_ana_[l], items_.ana[l]); up(d_syn_[l], items_.syn[l]); }
   if (!d_desc_) d_desc_ = dalloc<ProbDesc>(1);
   desc_dirty_ = true;
@@ -349,7 +355,7 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   for (int c = 0; c < NUM_COEF; ++c) { dfree(h_.coef[c]); h_.coef[c] = nullptr; }
   dfree(h_.ll); h_.ll = nullptr;
   dfree((void*)h_.filters); h_.filters = nullptr;
-  items_.dirac.clear(); items_.synfinal.clear();
+  items_.dirac.clear(); items_.synfinal.clear(); items_.coarse.clear();
   for (int l = 0; l <= kMaxLevels; ++l) { items_.ana[l].clear(); items_.syn[l].clear(); }
   h_.has_dirac = (mask & 1u) ? 1 : 0;
   int nwav = 0;
@@ -384,6 +390,9 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   zero(h_.coef[COEF_A], coef_elems_ * sizeof(V4<R>));
   int nap = 0;
   add_prior_items(items_, 0, n, levels, nwav, std::is_same<R, double>::value, &nap);
+  c_level_ = coarse_level<R>(n, levels);
+  if (c_level_ <= levels)
+    for (int w = 0; w < nwav; ++w) items_.coarse.push_back(make_int4(0, w, 0, 0));
   ana_parts_ = nap;
   gen_parts_ = std::max((N + 255) / 256, nap);
   realloc_partials();
@@ -419,6 +428,13 @@ template <typename R> void Engine<R>::p3(int src_coef, int dst_slot, int add_dir
   for (int l = h_.levels; l >= 2; --l) launch_synthesis<R>(l, h_.levels, la(d_syn_[l], s), src_coef, 0);
   launch_synthesis_final<R>(la(d_synfinal_, s), src_coef, dst_slot, add_dirac);
 }
+template <typename R> void Engine<R>::p23(hipStream_t s) {
+  if (c_level_ > h_.levels) { p2(s); p3(COEF_A, IMG_PSIA, 0, s); return; }
+  for (int l = 1; l < c_level_; ++l) launch_analysis<R>(AM_DUAL, l, la(d_ana_[l], s), IMG_X, COEF_A);
+  launch_coarse<R>(la(d_coarse_, s), c_level_);
+  for (int l = c_level_ - 1; l >= 2; --l) launch_synthesis<R>(l, h_.levels, la(d_syn_[l], s), COEF_A, 0);
+  launch_synthesis_final<R>(la(d_synfinal_, s), COEF_A, IMG_PSIA, 0);
+}
 template <typename R> void Engine<R>::p4(int src, hipStream_t s) { launch_fft<R>(0, la(d_rows_, s), cells_, src, 0); }
 template <typename R> void Engine<R>::p5(hipStream_t s) { launch_fft<R>(1, la(d_cols_, s), cells_, 0, 0); }
 template <typename R> void Engine<R>::p6(int mode, int src, int out, hipStream_t s) {
@@ -447,8 +463,7 @@ void Engine<R>::launch_iteration(int mode) {
   if (sparse) {
     hip_check(hipEventRecord(ev_fork_, s0_), "event record");
     hip_check(hipStreamWaitEvent(s1_, ev_fork_, 0), "stream wait");
-    p2(s1_);
-    p3(COEF_A, IMG_PSIA, 0, s1_);
+    p23(s1_);
     hip_check(hipEventRecord(ev_join_, s1_), "event record");
   }
   p4(IMG_X, s0_);
@@ -753,9 +768,8 @@ void Engine<R>::profile(int mode, int iters, double* ms) {
     hip_check(hipEventRecord(ev[0], s0_), "event record");
     p1(mode, s0_);
     hip_check(hipEventRecord(ev[1], s0_), "event record");
-    if (sparse) p2(s0_);
+    if (sparse) p23(s0_);      // P2 and P3 with the fused coarse levels: timed together
     hip_check(hipEventRecord(ev[2], s0_), "event record");
-    if (sparse) p3(COEF_A, IMG_PSIA, 0, s0_);
     hip_check(hipEventRecord(ev[3], s0_), "event record");
     p4(IMG_X, s0_);
     hip_check(hipEventRecord(ev[4], s0_), "event record");

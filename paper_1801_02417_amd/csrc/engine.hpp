@@ -46,7 +46,7 @@ struct Geometry {
 Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T);
 
 struct ItemSet {
-  std::vector<int4> img, rows, cols, p6, p7, p7m, dirac, synfinal;
+  std::vector<int4> img, rows, cols, p6, p7, p7m, dirac, synfinal, coarse;
   std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
 };
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int* n_p6);
@@ -91,6 +91,7 @@ struct Engine {
   void p1(int mode, hipStream_t s = nullptr);
   void p2(hipStream_t s = nullptr);
   void p3(int src_coef, int dst_slot, int add_dirac, hipStream_t s = nullptr);
+  void p23(hipStream_t s = nullptr);   // the iteration's SARA branch: P2 and P3 with fused coarse levels
   void p4(int src, hipStream_t s = nullptr);
   void p5(hipStream_t s = nullptr);
   void p6(int mode, int src, int out, hipStream_t s = nullptr);
@@ -128,7 +129,8 @@ struct Engine {
   ProbDesc* d_desc_ = nullptr;
   bool desc_dirty_ = true;
   ItemSet items_;
-  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_p7m_, d_dirac_, d_synfinal_;
+  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_p7m_, d_dirac_, d_synfinal_, d_coarse_;
+  int c_level_ = 1 << 20;     // first level handled by the fused coarse kernel (> levels: none)
   DevItems d_ana_[kMaxLevels + 1], d_syn_[kMaxLevels + 1];
   int cells_ = 512;
   int gen_parts_ = 1, ana_parts_ = 0;

@@ -24,8 +24,9 @@
 namespace psara {
 
 template <typename R> struct DwtTile;
-template <> struct DwtTile<float> { static constexpr int TO = 16; static constexpr int TS = 32; };
-template <> struct DwtTile<double> { static constexpr int TO = 8; static constexpr int TS = 16; };
+// TO: analysis output tile per band; TS: synthesis output tile (levels L..2); TF: last level
+template <> struct DwtTile<float> { static constexpr int TO = 16; static constexpr int TS = 32; static constexpr int TF = 16; };
+template <> struct DwtTile<double> { static constexpr int TO = 8; static constexpr int TS = 16; static constexpr int TF = 16; };
 
 template <typename R>
 __device__ inline void v4_fma(V4<R>& acc, R w, const V4<R>& x) {
@@ -263,7 +264,7 @@ template <typename R>
 __global__ void __launch_bounds__(256)
 synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_coef, int dst_slot, int add_dirac) {
   __shared__ SynSmem<R> sm;
-  constexpr int TS = DwtTile<R>::TS;
+  constexpr int TS = DwtTile<R>::TF;
   constexpr int NPER = (TS * TS + 255) / 256;
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
@@ -291,6 +292,128 @@ synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restric
       out[idx] = s;
     }
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Coarse levels c..L of one wavelet basis in a single workgroup: the low-low band entering
+// level c (at most CoarseMax<R> on a side) is held in LDS; analysis runs level by level with
+// the dual update of every coefficient, then synthesis runs back from level L to level c on
+// the updated duals and leaves the low-low band of level c-1 in the level scratch, where the
+// next synthesis launch reads it.  Replaces 2 (L - c + 1) small launches by one.
+// items: {prob, wavelet index, -, -}
+template <typename R> struct CoarseMax { static constexpr int value = sizeof(R) == 4 ? 64 : 32; };
+
+template <typename R>
+__global__ void __launch_bounds__(1024)
+coarse_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int c_level) {
+  constexpr int MM = CoarseMax<R>::value;
+  __shared__ V4<R> bufA[MM * MM];
+  __shared__ V4<R> bufB[MM * MM];
+  __shared__ R hf[kMaxFilter], gf[kMaxFilter];
+  const int4 it = items[blockIdx.x];
+  const ProbDesc& P = descs[it.x];
+  const int n = P.n, w = it.y, L = P.levels;
+  const int F = P.wav_len[w];
+  const int nt = blockDim.x;
+  if (threadIdx.x < F) hf[threadIdx.x] = ((const R*)P.filters)[w * kMaxFilter + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x < F) gf[threadIdx.x] = ((threadIdx.x & 1) ? R(-1) : R(1)) * hf[F - 1 - threadIdx.x];
+  V4<R>* __restrict__ ll = (V4<R>*)P.ll + (size_t)w * P.ll_stride;
+  V4<R>* __restrict__ A = (V4<R>*)P.coef[COEF_A];
+  const V4<R>* __restrict__ GW = (const V4<R>*)P.coef[COEF_GW];
+  const size_t base = (size_t)(P.has_dirac + w) * n * n;
+  const R nm = R(P.norm), r1 = R(P.rho1);
+  int m = n >> (c_level - 1);
+  for (int q = threadIdx.x; q < m * m; q += nt) bufA[q] = ll[P.ll_off[c_level - 1] + q];
+  __syncthreads();
+  auto dual = [&](size_t idx, const V4<R>& raw) {
+    const V4<R> g = GW[idx];
+    V4<R> a = A[idx];
+    a.x = fmin(fmax(a.x + r1 * nm * raw.x, -g.x), g.x);
+    a.y = fmin(fmax(a.y + r1 * nm * raw.y, -g.y), g.y);
+    a.z = fmin(fmax(a.z + r1 * nm * raw.z, -g.z), g.z);
+    a.w = fmin(fmax(a.w + r1 * nm * raw.w, -g.w), g.w);
+    A[idx] = a;
+  };
+  // ---- analysis c..L (bufA holds the m x m low-low band) ----
+  for (int l = c_level; l <= L; ++l) {
+    const int h = m >> 1;
+    for (int q = threadIdx.x; q < m * m; q += nt) {          // rows: bufB[r][k] = a, bufB[r][h+k] = d
+      const int r = q / m, k = q - r * m;
+      const int kk = k < h ? k : k - h;
+      const R* flt = k < h ? hf : gf;
+      V4<R> acc = v4_zero<R>();
+      for (int j = 0; j < F; ++j) v4_fma(acc, flt[j], bufA[r * m + ((2 * kk + j) & (m - 1))]);
+      bufB[q] = acc;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < m * m; q += nt) {          // columns
+      const int k1 = q / m, col = q - k1 * m;
+      const int kk = k1 < h ? k1 : k1 - h;
+      const R* flt = k1 < h ? hf : gf;
+      V4<R> acc = v4_zero<R>();
+      for (int j = 0; j < F; ++j) v4_fma(acc, flt[j], bufB[((2 * kk + j) & (m - 1)) * m + col]);
+      if (k1 < h && col < h && l < L) bufA[k1 * h + col] = acc;     // next level's input
+      else dual(base + (size_t)k1 * n + col, acc);
+    }
+    __syncthreads();
+    m = h;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // ---- synthesis L..c on the updated duals (bufA: the h x h low-low input) ----
+  const V4<R>* __restrict__ Ac = A;
+  {
+    const int h = n >> L;
+    for (int q = threadIdx.x; q < h * h; q += nt) bufA[q] = Ac[base + (size_t)(q / h) * n + q % h];
+  }
+  __syncthreads();
+  for (int l = L; l >= c_level; --l) {
+    const int mo = n >> (l - 1), h = mo >> 1;
+    // inverse column transform: bufB[ir][b] (ir < mo, b < h) from LL/LH, bufB[mo*h + ...] from HL/HH
+    for (int q = threadIdx.x; q < mo * h; q += nt) {
+      const int ir = q / h, b = q - ir * h;
+      V4<R> sa = v4_zero<R>(), sd = v4_zero<R>();
+      for (int j = (ir & 1); j < F; j += 2) {
+        const int r = ((ir - j) >> 1) & (h - 1);
+        v4_fma(sa, hf[j], bufA[r * h + b]);
+        v4_fma(sa, gf[j], Ac[base + (size_t)(h + r) * n + b]);
+        v4_fma(sd, hf[j], Ac[base + (size_t)r * n + h + b]);
+        v4_fma(sd, gf[j], Ac[base + (size_t)(h + r) * n + h + b]);
+      }
+      bufB[q] = sa;
+      bufB[mo * h + q] = sd;
+    }
+    __syncthreads();
+    // inverse row transform into bufA (mo x mo)
+    for (int q = threadIdx.x; q < mo * mo; q += nt) {
+      const int ir = q / mo, ic = q - ir * mo;
+      V4<R> s = v4_zero<R>();
+      for (int j = (ic & 1); j < F; j += 2) {
+        const int b = ((ic - j) >> 1) & (h - 1);
+        v4_fma(s, hf[j], bufB[ir * h + b]);
+        v4_fma(s, gf[j], bufB[mo * h + ir * h + b]);
+      }
+      bufA[q] = s;
+    }
+    __syncthreads();
+  }
+  const int mo = n >> (c_level - 1);
+  for (int q = threadIdx.x; q < mo * mo; q += nt) ll[P.ll_off[c_level - 1] + q] = bufA[q];
+}
+
+template <typename R>
+int coarse_level(int n, int levels) {
+  // first level >= 2 whose input low-low band fits the LDS buffers
+  for (int c = 2; c <= levels; ++c)
+    if ((n >> (c - 1)) <= CoarseMax<R>::value) return c;
+  return levels + 1;
+}
+
+template <typename R>
+void launch_coarse(const LaunchArgs& a, int c_level) {
+  if (a.nitems <= 0) return;
+  hipLaunchKernelGGL((coarse_kernel<R>), dim3(a.nitems), dim3(1024), 0, a.stream, a.descs, a.items, c_level);
 }
 
 template <typename R>
@@ -338,6 +461,10 @@ template void launch_dirac<double>(int, const LaunchArgs&, int, int);
 template void launch_synthesis<float>(int, int, const LaunchArgs&, int, int);
 template void launch_synthesis<double>(int, int, const LaunchArgs&, int, int);
 template void launch_synthesis_final<float>(const LaunchArgs&, int, int, int);
+template void launch_coarse<float>(const LaunchArgs&, int);
+template void launch_coarse<double>(const LaunchArgs&, int);
+template int coarse_level<float>(int, int);
+template int coarse_level<double>(int, int);
 template void launch_synthesis_final<double>(const LaunchArgs&, int, int, int);
 
 }  // namespace psara

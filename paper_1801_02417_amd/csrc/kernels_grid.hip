@@ -139,14 +139,25 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int max_T, int src
 // The tile accumulates in 64-bit fixed point with integer LDS atomics: integer addition is
 // associative, so the result does not depend on the order in which lanes arrive (the
 // gridding is bitwise reproducible), and integer LDS atomics run far faster than floating
-// ones.  The scale is 2^61 / sum_v max_c |u_v,c| over the chunk, a bound on any partial sum
-// of a cell (the kernel weights are at most 1), so no sum can overflow; the absolute
-// rounding per addition is 2^-62 of that bound.
+// ones.  The scale is the power of two 2^E <= 2^61 / sum_v max_c |u_v,c| over the chunk, a
+// bound on any partial sum of a cell (the kernel weights are at most 1), so no sum can
+// overflow; the absolute rounding per addition is at most 2^-61 of that bound.
 //
 // The finished tile goes to the grid, or -- when the tile was split into several chunks -- to
 // a partial slot that the merge pass sums in a fixed order.  MODE GR_DUAL: scale = c from the
 // de-grid partials (stored by the writer item); GR_PLAIN: scale = 1, or the stored c when
 // use_cfac is set.
+// nearest 64-bit integer of an (already scaled) value with |y| < 2^62
+__device__ inline long long to_fixed(double y) { return __double2ll_rn(y); }
+__device__ inline long long to_fixed(float y) {
+  const float r = rintf(y);
+  const float ay = fabsf(r);
+  const float hi = floorf(ay * 2.3283064365386963e-10f);          // ay / 2^32, exact
+  const float lo = fmaf(hi, -4294967296.0f, ay);                   // ay mod 2^32, exact
+  const long long v = ((long long)(unsigned)hi << 32) + (long long)(unsigned)lo;
+  return r < 0.f ? -v : v;
+}
+
 template <typename R, int MODE>
 __global__ void __launch_bounds__(256)
 grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac) {
@@ -200,7 +211,9 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     bound.add((double)mx);
   }
   const double total = block_reduce(bound, red).value();      // includes a barrier
-  const double fx = total > 0.0 ? ldexp(1.0, 61) / (total * (1.0 + 1e-6)) : 1.0;
+  // power-of-two scale 2^E with 2^E * total <= 2^61: multiplying by it is exact
+  const int E = total > 0.0 ? min(61 - (int)ceil(log2(total * (1.0 + 1e-6))), 100) : 0;
+  const R fx = (R)ldexp(1.0, E);
 
   const int lane8 = threadIdx.x & 7;               // tap row owned by this lane
   const int grp = threadIdx.x >> 3, ngrp = blockDim.x >> 3;
@@ -251,8 +264,7 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
           if (j < T && c2 < TG) {
             unsigned long long* cell = acc + (size_t)(c2 * TG + c1) * 8;
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-              atomicAdd(cell + c, (unsigned long long)__double2ll_rn((double)a[j][c] * fx));
+            for (int c = 0; c < 8; ++c) atomicAdd(cell + c, (unsigned long long)to_fixed(a[j][c] * fx));
           }
         }
       }
@@ -268,7 +280,7 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     dst = (Cell<R>*)P.gpart + (size_t)ch.w * TG * TG;
     stride = TG;
   }
-  const double inv = 1.0 / fx;
+  const double inv = ldexp(1.0, -E);
   for (int q = threadIdx.x; q < TG * TG; q += blockDim.x) {
     const int a2 = q / TG, a1 = q - a2 * TG;        // a2: k2 offset, a1: k1 offset
     Cell<R> c;

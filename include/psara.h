@@ -191,12 +191,14 @@ int psara_layout(const psara_ctx* ctx, int64_t* perm);
 
 /* ---- profiling --------------------------------------------------------------------------- */
 
-/* Run `iters` iterations of Algorithm 1 in `mode` with every pass on the context stream
+/* Run `iters` iterations of Algorithm 1 in `mode` with every launch on the context stream
  * (no graph, the two independent branches serialised), bracket each pass with HIP events,
- * and write the average duration in milliseconds of each of the nine passes to
- * ms_per_pass[0..8]: P1 primal / epigraph / Dirac dual, P2 SARA analysis + dual A, P3 SARA
- * synthesis, P4 zero-pad + row FFT, P5 column FFT, P6 de-grid + dual B, P7 grid, P8 column
- * inverse FFT, P9 row inverse FFT + crop.  The iterations really run (the state advances). */
+ * and write the average duration in milliseconds of each pass to ms_per_pass[0..8]:
+ * [0] primal / epigraph / Dirac dual step fused with the zero-padding and row FFT (P1+P4),
+ * [1] SARA analysis + dual A + synthesis (P2+P3, coarse levels fused), [2] and [3] zero (their
+ * work is timed in [1] and [0]), [4] column FFT (P5), [5] de-grid + dual B (P6), [6] grid (P7),
+ * [7] column inverse FFT (P8, which also sums the partial tiles of split gridding tiles),
+ * [8] row inverse FFT + crop (P9).  The iterations really run (the state advances). */
 psara_status psara_profile_passes(psara_ctx* ctx, psara_mode mode, int iters, double* ms_per_pass);
 
 #ifdef __cplusplus

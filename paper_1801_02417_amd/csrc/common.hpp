@@ -75,6 +75,7 @@ struct ProbDesc {
   const int2* chunk_ent;  // list-entry range [lo, hi) of each gridding chunk
   void* gpart;            // partial tiles of split gridding tiles: n_slots x kGridTile^2 cells
   const int4* chunks;     // gridding chunks {tile, first run, end run, partial slot or -1}
+  const int2* tile_slots; // per gridding tile: {first partial slot, count}, count 0 = in the grid
   const void* cheb;       // T x (deg+1) Chebyshev coefficients, type R
   const void* twiddle;    // K complex exp(-2 pi i j / K), type R
   const void* deapod;     // n scaling factors 1/psi_hat((j - n/2)/K), type R

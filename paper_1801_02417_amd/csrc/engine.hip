@@ -126,8 +126,10 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
       g.chunk_ent.push_back(make_int2(lo, hi));
     } while (r < runs.size());
     if (tile_chunks.size() > 1) {
-      g.merges.push_back(make_int4(t, g.n_slots, (int)tile_chunks.size(), 0));
+      g.tile_slots.push_back(make_int2(g.n_slots, (int)tile_chunks.size()));
       for (auto& c : tile_chunks) c.w = g.n_slots++;
+    } else {
+      g.tile_slots.push_back(make_int2(0, 0));
     }
     g.chunks.insert(g.chunks.end(), tile_chunks.begin(), tile_chunks.end());
   }
@@ -147,15 +149,15 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int*
   for (int t = 0; t < ntiles; ++t) {
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += 256) S.p6.push_back(make_int4(prob, t, v, part++));
   }
-  // gridding chunks, heaviest first (entries as the work estimate) so the tail of the launch is
-  // short; the first item of a problem stores the l2-ball factor
+  // gridding chunks, heaviest first (entries plus a flush cost per run as the work estimate)
+  // so the tail of the launch is short; the first item of a problem stores the l2-ball factor
   std::vector<int> order(g.chunks.size());
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return (g.chunk_ent[a].y - g.chunk_ent[a].x) > (g.chunk_ent[b].y - g.chunk_ent[b].x);
-  });
+  auto cost = [&](int c) {
+    return (g.chunk_ent[c].y - g.chunk_ent[c].x) + 3 * (g.chunks[c].z - g.chunks[c].y);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
   for (size_t c = 0; c < order.size(); ++c) S.p7.push_back(make_int4(prob, order[c], c == 0 ? 1 : 0, 0));
-  for (const auto& mg : g.merges) S.p7m.push_back(make_int4(prob, mg.x, mg.y, mg.z));
   *n_p6 = part;
 }
 
@@ -212,6 +214,7 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   h_.run_len = upload<int>(g.run_len.data(), std::max<size_t>(1, g.run_len.size()));
   h_.run_k0 = upload<int>(g.run_k0.data(), std::max<size_t>(1, g.run_k0.size()));
   h_.chunk_ent = upload<int2>(g.chunk_ent.data(), std::max<size_t>(1, g.chunk_ent.size()));
+  h_.tile_slots = upload<int2>(g.tile_slots.data(), std::max<size_t>(1, g.tile_slots.size()));
   h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
   h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * kGridTile * kGridTile);
   // tables
@@ -310,7 +313,7 @@ void Engine<R>::upload_items() {
     if (!v.empty()) d.ptr = upload<int4>(v.data(), v.size());
   };
   up(d_img_, items_.img); up(d_rows_, items_.rows); up(d_cols_, items_.cols);
-  up(d_p6_, items_.p6); up(d_p7_, items_.p7); up(d_p7m_, items_.p7m);
+  up(d_p6_, items_.p6); up(d_p7_, items_.p7);
   up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal); up(d_coarse_, items_.coarse);
   for (int l = 0; l <= kMaxLevels; ++l) { up(d_ana_[l], items_.ana[l]); up(d_syn_[l], items_.syn[l]); }
   if (!d_desc_) d_desc_ = dalloc<ProbDesc>(1);
@@ -442,7 +445,6 @@ template <typename R> void Engine<R>::p6(int mode, int src, int out, hipStream_t
 }
 template <typename R> void Engine<R>::p7(int mode, int src, int use_cfac, hipStream_t s) {
   launch_grid<R>(mode, la(d_p7_, s), geo_.ts, src, use_cfac);
-  launch_grid_merge<R>(la(d_p7m_, s), geo_.ts);
 }
 template <typename R> void Engine<R>::p8(hipStream_t s) { launch_fft<R>(2, la(d_cols_, s), cells_, 0, 0); }
 template <typename R> void Engine<R>::p9(int dst, hipStream_t s) { launch_fft<R>(3, la(d_rows_, s), cells_, 0, dst); }
@@ -458,7 +460,8 @@ void Engine<R>::adjoint(int src_vis, int use_cfac, int dst_img) {
 
 template <typename R>
 void Engine<R>::launch_iteration(int mode) {
-  p1(mode, s0_);
+  // P1 fused into P4: the row-FFT workgroups run the primal step of their rows
+  launch_primal_fft<R>(mode, la(d_rows_, s0_), cells_);
   const bool sparse = (mode != PM_INIT) && h_.coef[COEF_A] && h_.nwav > 0;
   if (sparse) {
     hip_check(hipEventRecord(ev_fork_, s0_), "event record");
@@ -466,7 +469,6 @@ void Engine<R>::launch_iteration(int mode) {
     p23(s1_);
     hip_check(hipEventRecord(ev_join_, s1_), "event record");
   }
-  p4(IMG_X, s0_);
   p5(s0_);
   p6(DG_DUAL, VIS_BV, VIS_BV, s0_);
   p7(GR_DUAL, VIS_BV, 0, s0_);
@@ -766,12 +768,11 @@ void Engine<R>::profile(int mode, int iters, double* ms) {
   const bool sparse = (mode != PM_INIT) && h_.coef[COEF_A] && h_.nwav > 0;
   for (int k = 0; k < iters; ++k) {
     hip_check(hipEventRecord(ev[0], s0_), "event record");
-    p1(mode, s0_);
+    launch_primal_fft<R>(mode, la(d_rows_, s0_), cells_);   // P1 fused into P4: timed as P1
     hip_check(hipEventRecord(ev[1], s0_), "event record");
-    if (sparse) p23(s0_);      // P2 and P3 with the fused coarse levels: timed together
+    if (sparse) p23(s0_);      // P2 and P3 with the fused coarse levels: timed together as P2
     hip_check(hipEventRecord(ev[2], s0_), "event record");
     hip_check(hipEventRecord(ev[3], s0_), "event record");
-    p4(IMG_X, s0_);
     hip_check(hipEventRecord(ev[4], s0_), "event record");
     p5(s0_);
     hip_check(hipEventRecord(ev[5], s0_), "event record");

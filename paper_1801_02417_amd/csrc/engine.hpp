@@ -35,18 +35,18 @@ struct Geometry {
   std::vector<int> list_ptr, list_idx;   // per gridding tile: every visibility whose window touches it
   // gridding work: runs of list entries sharing one window start (at most kRunMax long),
   // grouped into chunks of at most kChunkEntries entries; a tile with several chunks sums
-  // their partial tiles in a merge pass
+  // their partial tiles when the column inverse FFT loads them
   std::vector<int> run_beg, run_len, run_k0;   // per run: first list entry, length, window start
   std::vector<int4> chunks;              // {tile, first run, end run, partial slot or -1}
   std::vector<int2> chunk_ent;           // list-entry range [lo, hi) each chunk covers
-  std::vector<int4> merges;              // {tile, first slot, slot count, -}
+  std::vector<int2> tile_slots;          // per gridding tile {first partial slot, count}
   int n_slots = 0;
 };
 
 Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T);
 
 struct ItemSet {
-  std::vector<int4> img, rows, cols, p6, p7, p7m, dirac, synfinal, coarse;
+  std::vector<int4> img, rows, cols, p6, p7, dirac, synfinal, coarse;
   std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
 };
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int* n_p6);
@@ -129,7 +129,7 @@ struct Engine {
   ProbDesc* d_desc_ = nullptr;
   bool desc_dirty_ = true;
   ItemSet items_;
-  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_p7m_, d_dirac_, d_synfinal_, d_coarse_;
+  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_dirac_, d_synfinal_, d_coarse_;
   int c_level_ = 1 << 20;     // first level handled by the fused coarse kernel (> levels: none)
   DevItems d_ana_[kMaxLevels + 1], d_syn_[kMaxLevels + 1];
   int cells_ = 512;

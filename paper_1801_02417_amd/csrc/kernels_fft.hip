@@ -21,6 +21,7 @@
 // radix-2 butterflies).
 #include "common.hpp"
 #include "launch.hpp"
+#include "primal.hpp"
 
 namespace psara {
 
@@ -126,8 +127,10 @@ __device__ inline Cell<R> zero_cell() {
 }
 
 // PASS: 0 = P4 image rows -> half, 1 = P5 half -> grid, 2 = P8 grid -> half, 3 = P9 half -> image.
+// PM >= 0 (PASS 0 only): the primal step of mode PM runs on each pixel as the row is loaded
+// and the row FFT takes the X it returns (P1 fused into P4).
 // items: {prob, first line, -, -}; CELLS/K lines per workgroup.
-template <typename R, int CELLS, int PASS>
+template <typename R, int CELLS, int PASS, int PM = -1>
 __global__ void __launch_bounds__(CELLS / 2)
 fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int dst_slot) {
   __shared__ Cell<R> lds[CELLS];
@@ -148,7 +151,9 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       const int l = q / K, k = q - l * K, r = line0 + l;
       const int col = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
       if (r < n && col >= 0) {
-        const V4<R> v = ((const V4<R>*)P.img[src_slot])[(size_t)r * n + col];
+        V4<R> v;
+        if (PM >= 0) v = primal_pixel<R, (PM < 0 ? 0 : PM)>(P, r * n + col);
+        else v = ((const V4<R>*)P.img[src_slot])[(size_t)r * n + col];
         const R sc = s[r] * s[col];
         c.s[0].re = v.x * sc; c.s[1].re = v.y * sc; c.s[2].re = v.z * sc; c.s[3].re = v.w * sc;
       }
@@ -159,8 +164,24 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       if (k2 < K && r >= 0) c = half[(size_t)k2 * n + r];
       lds[q] = c;
     } else if (PASS == 2) {
+      // gridding tiles split over several chunks are summed here from their partial slots
       const int l = q / K, k = q - l * K, k2 = line0 + l;
-      if (k2 < K) c = grid[(size_t)k2 * K + k];
+      if (k2 < K) {
+        const int ntg = P.ntile_side_g;
+        const int2 ts = P.tile_slots[(k / kGridTile) * ntg + k2 / kGridTile];
+        if (ts.y == 0) {
+          c = grid[(size_t)k2 * K + k];
+        } else {
+          const Cell<R>* part = (const Cell<R>*)P.gpart + (size_t)ts.x * kGridTile * kGridTile +
+                                (k2 % kGridTile) * kGridTile + (k % kGridTile);
+          c = part[0];
+          for (int sl = 1; sl < ts.y; ++sl) {
+            const Cell<R> o = part[(size_t)sl * kGridTile * kGridTile];
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) c.s[ch] = cadd(c.s[ch], o.s[ch]);
+          }
+        }
+      }
       lds[q] = c;
     } else {
       const int k2 = q / lines, l = q - k2 * lines, r = line0 + l;
@@ -206,6 +227,24 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
 }
 
 template <typename R>
+void launch_primal_fft(int mode, const LaunchArgs& a, int cells) {
+  if (a.nitems <= 0) return;
+  const dim3 grid(a.nitems);
+#define PSARA_PFFT(C, PM) \
+  hipLaunchKernelGGL((fft_pass_kernel<R, C, 0, PM>), grid, dim3(C / 2), 0, a.stream, a.descs, a.items, 0, 0)
+  if (cells == 512) {
+    if (mode == PM_CONSTRAINED) PSARA_PFFT(512, PM_CONSTRAINED);
+    else if (mode == PM_INIT) PSARA_PFFT(512, PM_INIT);
+    else PSARA_PFFT(512, PM_UNCONSTRAINED);
+  } else {
+    if (mode == PM_CONSTRAINED) PSARA_PFFT(1024, PM_CONSTRAINED);
+    else if (mode == PM_INIT) PSARA_PFFT(1024, PM_INIT);
+    else PSARA_PFFT(1024, PM_UNCONSTRAINED);
+  }
+#undef PSARA_PFFT
+}
+
+template <typename R>
 void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot) {
   if (a.nitems <= 0) return;
   const dim3 grid(a.nitems);
@@ -230,6 +269,8 @@ void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_
 }
 
 template void launch_fft<float>(int, const LaunchArgs&, int, int, int);
+template void launch_primal_fft<float>(int, const LaunchArgs&, int);
+template void launch_primal_fft<double>(int, const LaunchArgs&, int);
 template void launch_fft<double>(int, const LaunchArgs&, int, int, int);
 
 }  // namespace psara

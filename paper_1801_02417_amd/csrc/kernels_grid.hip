@@ -139,24 +139,31 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int max_T, int src
 // The tile accumulates in 64-bit fixed point with integer LDS atomics: integer addition is
 // associative, so the result does not depend on the order in which lanes arrive (the
 // gridding is bitwise reproducible), and integer LDS atomics run far faster than floating
-// ones.  The scale is the power of two 2^E <= 2^61 / sum_v max_c |u_v,c| over the chunk, a
-// bound on any partial sum of a cell (the kernel weights are at most 1), so no sum can
-// overflow; the absolute rounding per addition is at most 2^-61 of that bound.
+// ones.  The scale is the power of two 2^E <= 2^49 (FP32) or 2^61 (FP64) divided by
+// sum_v max_c |u_v,c| over the chunk, a bound on any partial sum of a cell (the kernel weights
+// are at most 1), so no sum leaves the range of the conversion; the absolute rounding per
+// addition is at most 2^-50 (2^-62) of that bound.
 //
 // The finished tile goes to the grid, or -- when the tile was split into several chunks -- to
-// a partial slot that the merge pass sums in a fixed order.  MODE GR_DUAL: scale = c from the
+// a partial slot; the column inverse FFT sums a split tile's slots in slot order as it loads.  MODE GR_DUAL: scale = c from the
 // de-grid partials (stored by the writer item); GR_PLAIN: scale = 1, or the stored c when
 // use_cfac is set.
-// nearest 64-bit integer of an (already scaled) value with |y| < 2^62
-__device__ inline long long to_fixed(double y) { return __double2ll_rn(y); }
-__device__ inline long long to_fixed(float y) {
-  const float r = rintf(y);
-  const float ay = fabsf(r);
-  const float hi = floorf(ay * 2.3283064365386963e-10f);          // ay / 2^32, exact
-  const float lo = fmaf(hi, -4294967296.0f, ay);                   // ay mod 2^32, exact
-  const long long v = ((long long)(unsigned)hi << 32) + (long long)(unsigned)lo;
-  return r < 0.f ? -v : v;
-}
+// Nearest 64-bit integer of an (already scaled) value.  FP32 data (|y| < 2^50): adding
+// 1.5 * 2^52 rounds y to an integer held in the low mantissa bits of the sum; subtracting the
+// bit pattern of 1.5 * 2^52 leaves it as a two's-complement integer (two instructions).  FP64
+// data use the full 2^61 range and the exact conversion.
+template <typename R> struct Fixed;
+template <> struct Fixed<float> {
+  static constexpr int kRange = 49;
+  __device__ static long long conv(double y) {
+    constexpr double kMagic = 6755399441055744.0;          // 1.5 * 2^52
+    return __double_as_longlong(y + kMagic) - __double_as_longlong(kMagic);
+  }
+};
+template <> struct Fixed<double> {
+  static constexpr int kRange = 61;
+  __device__ static long long conv(double y) { return __double2ll_rn(y); }
+};
 
 template <typename R, int MODE>
 __global__ void __launch_bounds__(256)
@@ -211,9 +218,9 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     bound.add((double)mx);
   }
   const double total = block_reduce(bound, red).value();      // includes a barrier
-  // power-of-two scale 2^E with 2^E * total <= 2^61: multiplying by it is exact
-  const int E = total > 0.0 ? min(61 - (int)ceil(log2(total * (1.0 + 1e-6))), 100) : 0;
-  const R fx = (R)ldexp(1.0, E);
+  // power-of-two scale 2^E with 2^E * total <= 2^kRange: multiplying by it is exact
+  const int E = total > 0.0 ? min(Fixed<R>::kRange - (int)ceil(log2(total * (1.0 + 1e-6))), 100) : 0;
+  const double fx = ldexp(1.0, E);
 
   const int lane8 = threadIdx.x & 7;               // tap row owned by this lane
   const int grp = threadIdx.x >> 3, ngrp = blockDim.x >> 3;
@@ -264,7 +271,8 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
           if (j < T && c2 < TG) {
             unsigned long long* cell = acc + (size_t)(c2 * TG + c1) * 8;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) atomicAdd(cell + c, (unsigned long long)to_fixed(a[j][c] * fx));
+            for (int c = 0; c < 8; ++c)
+              atomicAdd(cell + c, (unsigned long long)Fixed<R>::conv((double)a[j][c] * fx));
           }
         }
       }
@@ -292,30 +300,6 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   }
 }
 
-// Merge of split tiles: the grid tile is the sum of its chunks' partial tiles, in slot order.
-// items: {prob, tile, first slot, slot count}
-template <typename R>
-__global__ void __launch_bounds__(256)
-grid_merge_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items) {
-  constexpr int TG = kGridTile;
-  const int4 it = items[blockIdx.x];
-  const ProbDesc& P = descs[it.x];
-  const int K = P.K, ntg = P.ntile_side_g;
-  const int t1 = it.y / ntg, t2 = it.y - t1 * ntg;
-  const Cell<R>* __restrict__ part = (const Cell<R>*)P.gpart + (size_t)it.z * TG * TG;
-  Cell<R>* __restrict__ grid = (Cell<R>*)P.grid;
-  for (int q = threadIdx.x; q < TG * TG; q += blockDim.x) {
-    Cell<R> c = part[q];
-    for (int k = 1; k < it.w; ++k) {
-      const Cell<R> o = part[(size_t)k * TG * TG + q];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) c.s[s] = cadd(c.s[s], o.s[s]);
-    }
-    const int a2 = q / TG, a1 = q - a2 * TG;
-    grid[(size_t)(t2 * TG + a2) * K + t1 * TG + a1] = c;
-  }
-}
-
 template <typename R>
 void launch_grid(int mode, const LaunchArgs& a, int max_ts, int src_slot, int use_cfac) {
   if (a.nitems <= 0) return;
@@ -325,12 +309,6 @@ void launch_grid(int mode, const LaunchArgs& a, int max_ts, int src_slot, int us
   } else {
     hipLaunchKernelGGL((grid_kernel<R, GR_PLAIN>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
   }
-}
-
-template <typename R>
-void launch_grid_merge(const LaunchArgs& a, int /*max_ts*/) {
-  if (a.nitems <= 0) return;
-  hipLaunchKernelGGL((grid_merge_kernel<R>), dim3(a.nitems), dim3(256), 0, a.stream, a.descs, a.items);
 }
 
 // Raise the dynamic-LDS limit of the de-grid / grid kernels once, outside any graph capture.
@@ -349,7 +327,6 @@ template void launch_degrid<float>(int, const LaunchArgs&, int, int, int, int);
 template void launch_degrid<double>(int, const LaunchArgs&, int, int, int, int);
 template void launch_grid<float>(int, const LaunchArgs&, int, int, int);
 template void launch_grid<double>(int, const LaunchArgs&, int, int, int);
-template void launch_grid_merge<float>(const LaunchArgs&, int);
-template void launch_grid_merge<double>(const LaunchArgs&, int);
+
 
 }  // namespace psara

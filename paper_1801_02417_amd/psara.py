@@ -284,9 +284,9 @@ def psara_layout(ctx, M: int):
     return ts, perm
 
 
-PASS_NAMES = ("P1 primal+epigraph+Dirac dual", "P2 SARA analysis+dual A", "P3 SARA synthesis",
-              "P4 zero-pad+row FFT", "P5 column FFT", "P6 de-grid+dual B", "P7 grid",
-              "P8 column inverse FFT", "P9 row inverse FFT+crop")
+PASS_NAMES = ("P1+P4 primal/epigraph/Dirac dual + zero-pad + row FFT", "P2+P3 SARA analysis + dual A + synthesis",
+              "(in P2+P3)", "(in P1+P4)", "P5 column FFT", "P6 de-grid + dual B", "P7 grid",
+              "P8 column inverse FFT (+ split-tile sums)", "P9 row inverse FFT + crop")
 
 
 def psara_profile_passes(ctx, mode: int, iters: int) -> np.ndarray:

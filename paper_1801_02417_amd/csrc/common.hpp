@@ -21,7 +21,7 @@ constexpr int kChunkEntries = 512;  // gridding entries per workgroup (staged in
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
 
 // Chebyshev degree of the per-tap Kaiser-Bessel expansions (max error ~1e-10 / ~1e-15)
-template <typename R> struct KbDeg { static constexpr int value = sizeof(R) == 4 ? 10 : 16; };
+template <typename R> struct KbDeg { static constexpr int value = sizeof(R) == 4 ? 9 : 16; };
 
 // image-space buffers (N pixels x 4 Stokes, or x 2 for Z / D)
 enum ImgSlot { IMG_S = 0, IMG_X, IMG_C, IMG_PSIA, IMG_PHIB, IMG_TMP, IMG_TMP2, IMG_Z, IMG_D, NUM_IMG };
@@ -76,7 +76,7 @@ struct ProbDesc {
   void* gpart;            // partial tiles of split gridding tiles: n_slots x kGridTile^2 cells
   const int4* chunks;     // gridding chunks {tile, first run, end run, partial slot or -1}
   const int2* tile_slots; // per gridding tile: {first partial slot, count}, count 0 = in the grid
-  const void* cheb;       // T x (deg+1) Chebyshev coefficients, type R
+  const void* kbpoly;     // T x (deg+1) per-tap kernel polynomial coefficients (ascending), type R
   const void* twiddle;    // K complex exp(-2 pi i j / K), type R
   const void* deapod;     // n scaling factors 1/psi_hat((j - n/2)/K), type R
   const void* filters;    // nwav x 16 low-pass filters (zero padded), type R
@@ -155,25 +155,22 @@ __device__ inline double block_sum_partials(const double* parts, int count, doub
 // Kaiser-Bessel weights: the T weights psi(f - i), i = 0..T-1, of one dimension.  With the
 // window start k0 = ceil(t - T/2) the fractional offset f = t - k0 lies in (T/2 - 1, T/2], so
 // every tap's argument spans one unit interval and u = 2f - T + 1 in (-1, 1] is common to all
-// taps.  Each tap carries its own Chebyshev expansion on that interval.
-template <typename R>
-__device__ inline void kb_weights(R f, int T, const R* __restrict__ cheb, R* w) {
+// taps.  Each tap carries its own polynomial in u on that interval (Horner's rule).
+template <typename R, int T>
+__device__ inline R kb_tap(R u, const R* __restrict__ c) {
+  constexpr int DEG = KbDeg<R>::value;
+  R acc = c[DEG];
+#pragma unroll
+  for (int k = DEG - 1; k >= 0; --k) acc = acc * u + c[k];
+  return acc;
+}
+
+template <typename R, int T>
+__device__ inline void kb_weights(R f, const R* __restrict__ poly, R* w) {
   constexpr int DEG = KbDeg<R>::value;
   const R u = R(2) * f - R(T - 1);
-  R tk[DEG + 1];
-  tk[0] = R(1);
-  tk[1] = u;
 #pragma unroll
-  for (int k = 2; k <= DEG; ++k) tk[k] = R(2) * u * tk[k - 1] - tk[k - 2];
-#pragma unroll
-  for (int i = 0; i < kMaxTaps; ++i) {
-    R acc = R(0);
-    if (i < T) {
-#pragma unroll
-      for (int k = 0; k <= DEG; ++k) acc += cheb[i * (DEG + 1) + k] * tk[k];
-    }
-    w[i] = acc;
-  }
+  for (int i = 0; i < T; ++i) w[i] = kb_tap<R, T>(u, poly + i * (DEG + 1));
 }
 
 }  // namespace psara

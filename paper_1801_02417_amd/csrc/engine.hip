@@ -20,7 +20,7 @@ namespace psara {
 std::vector<double> daubechies(int p);
 double kb_beta(int taps, double alpha);
 double kb_hat(int taps, double beta, double nu);
-std::vector<double> kb_chebyshev(int taps, double beta, int deg);
+std::vector<double> kb_poly(int taps, double beta, int deg);
 
 void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(PSARA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -138,11 +138,11 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
 
 // ------------------------------------------------------------------------------------------------
 // work lists (appended per problem, so batches concatenate them)
-void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int* n_p6) {
+void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int* n_p6) {
   const int n = g.n, K = g.K, N = n * n;
-  const int lines = cells / K;
+  const int lines = cells / K, rlines = rcells / K;
   for (int b = 0; b < (N + 255) / 256; ++b) S.img.push_back(make_int4(prob, b, 0, 0));
-  for (int l = 0; l < n; l += lines) S.rows.push_back(make_int4(prob, l, 0, 0));
+  for (int l = 0; l < n; l += rlines) S.rows.push_back(make_int4(prob, l, 0, 0));
   for (int l = 0; l < K; l += lines) S.cols.push_back(make_int4(prob, l, 0, 0));
   const int ntiles = g.nts * g.nts;
   int part = 0;
@@ -196,6 +196,7 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   const int n = g.n, K = g.K, N = n * n;
   const int64_t M = g.M;
   cells_ = std::max(512, K);
+  rcells_ = std::max(512, K);
   h_.n = n; h_.K = K; h_.T = g.T; h_.M = M;
   h_.ts = g.ts; h_.ntile_side = g.nts; h_.ntile_side_g = g.ntsg;
   h_.deg = KbDeg<R>::value;
@@ -218,8 +219,8 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
   h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * kGridTile * kGridTile);
   // tables
-  std::vector<double> cheb = kb_chebyshev(g.T, g.beta, h_.deg);
-  h_.cheb = upload_conv(cheb.data(), cheb.size());
+  std::vector<double> poly = kb_poly(g.T, g.beta, h_.deg);
+  h_.kbpoly = upload_conv(poly.data(), poly.size());
   std::vector<double> tw(2 * K);
   for (int j = 0; j < K; ++j) {
     const double a = -2.0 * M_PI * (double)j / (double)K;
@@ -232,7 +233,7 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   h_.deapod = upload_conv(s.data(), n);
   set_grid_kernel_limits<R>(g.ts, g.T);
   // items of the operator passes
-  add_operator_items(items_, 0, g, cells_, &h_.n_p6);
+  add_operator_items(items_, 0, g, cells_, rcells_, &h_.n_p6);
   gen_parts_ = (N + 255) / 256;
   realloc_partials();
   h_.scal = dalloc<double>(NUM_SCALARS);
@@ -304,6 +305,20 @@ void Engine<R>::realloc_partials() {
   zero(h_.partials, count * sizeof(double));
 }
 
+// Workgroups are dealt to the eight XCDs round-robin (workgroup b to XCD b % 8), each XCD with
+// its own L2.  Reorders a work list so that every XCD takes one contiguous run of it: adjacent
+// image rows, whose transposed accesses to the intermediate array share cache lines, then meet
+// in the same L2 instead of fetching the same line into up to four of them.
+static std::vector<int4> xcd_contiguous(const std::vector<int4>& v) {
+  const size_t G = v.size(), q = G / 8, r = G % 8;
+  std::vector<int4> out(G);
+  for (size_t b = 0; b < G; ++b) {
+    const size_t x = b % 8, j = b / 8;
+    out[b] = v[x * q + std::min(x, r) + j];
+  }
+  return out;
+}
+
 template <typename R>
 void Engine<R>::upload_items() {
   auto up = [&](DevItems& d, const std::vector<int4>& v) {
@@ -312,7 +327,7 @@ void Engine<R>::upload_items() {
     d.count = (int)v.size();
     if (!v.empty()) d.ptr = upload<int4>(v.data(), v.size());
   };
-  up(d_img_, items_.img); up(d_rows_, items_.rows); up(d_cols_, items_.cols);
+  up(d_img_, items_.img); up(d_rows_, xcd_contiguous(items_.rows)); up(d_cols_, items_.cols);
   up(d_p6_, items_.p6); up(d_p7_, items_.p7);
   up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal); up(d_coarse_, items_.coarse);
   for (int l = 0; l <= kMaxLevels; ++l) { up(d_ana_[l], items_.ana[l]); up(d_syn_[l], items_.syn[l]); }
@@ -438,16 +453,16 @@ template <typename R> void Engine<R>::p23(hipStream_t s) {
   for (int l = c_level_ - 1; l >= 2; --l) launch_synthesis<R>(l, h_.levels, la(d_syn_[l], s), COEF_A, 0);
   launch_synthesis_final<R>(la(d_synfinal_, s), COEF_A, IMG_PSIA, 0);
 }
-template <typename R> void Engine<R>::p4(int src, hipStream_t s) { launch_fft<R>(0, la(d_rows_, s), cells_, src, 0); }
+template <typename R> void Engine<R>::p4(int src, hipStream_t s) { launch_fft<R>(0, la(d_rows_, s), rcells_, src, 0); }
 template <typename R> void Engine<R>::p5(hipStream_t s) { launch_fft<R>(1, la(d_cols_, s), cells_, 0, 0); }
 template <typename R> void Engine<R>::p6(int mode, int src, int out, hipStream_t s) {
   launch_degrid<R>(mode, la(d_p6_, s), geo_.ts, geo_.T, src, out);
 }
 template <typename R> void Engine<R>::p7(int mode, int src, int use_cfac, hipStream_t s) {
-  launch_grid<R>(mode, la(d_p7_, s), geo_.ts, src, use_cfac);
+  launch_grid<R>(mode, la(d_p7_, s), geo_.T, src, use_cfac);
 }
 template <typename R> void Engine<R>::p8(hipStream_t s) { launch_fft<R>(2, la(d_cols_, s), cells_, 0, 0); }
-template <typename R> void Engine<R>::p9(int dst, hipStream_t s) { launch_fft<R>(3, la(d_rows_, s), cells_, 0, dst); }
+template <typename R> void Engine<R>::p9(int dst, hipStream_t s) { launch_fft<R>(3, la(d_rows_, s), rcells_, 0, dst); }
 
 template <typename R>
 void Engine<R>::forward(int src_img, int mode, int out_vis) {
@@ -461,7 +476,7 @@ void Engine<R>::adjoint(int src_vis, int use_cfac, int dst_img) {
 template <typename R>
 void Engine<R>::launch_iteration(int mode) {
   // P1 fused into P4: the row-FFT workgroups run the primal step of their rows
-  launch_primal_fft<R>(mode, la(d_rows_, s0_), cells_);
+  launch_primal_fft<R>(mode, la(d_rows_, s0_), rcells_);
   const bool sparse = (mode != PM_INIT) && h_.coef[COEF_A] && h_.nwav > 0;
   if (sparse) {
     hip_check(hipEventRecord(ev_fork_, s0_), "event record");
@@ -768,7 +783,7 @@ void Engine<R>::profile(int mode, int iters, double* ms) {
   const bool sparse = (mode != PM_INIT) && h_.coef[COEF_A] && h_.nwav > 0;
   for (int k = 0; k < iters; ++k) {
     hip_check(hipEventRecord(ev[0], s0_), "event record");
-    launch_primal_fft<R>(mode, la(d_rows_, s0_), cells_);   // P1 fused into P4: timed as P1
+    launch_primal_fft<R>(mode, la(d_rows_, s0_), rcells_);   // P1 fused into P4: timed as P1
     hip_check(hipEventRecord(ev[1], s0_), "event record");
     if (sparse) p23(s0_);      // P2 and P3 with the fused coarse levels: timed together as P2
     hip_check(hipEventRecord(ev[2], s0_), "event record");

@@ -49,7 +49,7 @@ struct ItemSet {
   std::vector<int4> img, rows, cols, p6, p7, dirac, synfinal, coarse;
   std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
 };
-void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int* n_p6);
+void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int* n_p6);
 void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int* n_ana_parts);
 
 struct DevItems {
@@ -132,7 +132,8 @@ struct Engine {
   DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_dirac_, d_synfinal_, d_coarse_;
   int c_level_ = 1 << 20;     // first level handled by the fused coarse kernel (> levels: none)
   DevItems d_ana_[kMaxLevels + 1], d_syn_[kMaxLevels + 1];
-  int cells_ = 512;
+  int cells_ = 512;     // FFT cells per workgroup of the column passes
+  int rcells_ = 2048;   // ... and of the row passes (several image rows per workgroup)
   int gen_parts_ = 1, ana_parts_ = 0;
   size_t coef_elems_ = 0;
   size_t bytes_ = 0;

@@ -127,11 +127,23 @@ double kb_hat(int taps, double beta, double nu) {
   return taps / bessel_i0(beta) * r;
 }
 
-// Chebyshev coefficients c[i][k] (k = 0..deg) with psi(f - i) = sum_k c[i][k] T_k(2f - T + 1)
-// for f in (T/2 - 1, T/2], by interpolation at the deg+1 Chebyshev nodes.
-std::vector<double> kb_chebyshev(int taps, double beta, int deg) {
+// Per-tap polynomial of the Kaiser-Bessel kernel: c[i][k] (k = 0..deg, ascending powers) with
+// psi(f - i) ~= sum_k c[i][k] u^k, u = 2f - T + 1 in (-1, 1] for f in (T/2 - 1, T/2].  The
+// polynomial interpolates at the deg+1 Chebyshev nodes of [-1, 1] (near-minimax on a unit
+// interval of the smooth kernel) and is then rewritten in the monomial basis for Horner
+// evaluation; on a single unit interval the coefficients stay small, so Horner's rule loses
+// nothing measurable against the Chebyshev form (max error about one rounding of the
+// evaluation precision for degree 9 in FP32 and 16 in FP64).
+std::vector<double> kb_poly(int taps, double beta, int deg) {
   const int nn = deg + 1;
   std::vector<double> c(size_t(taps) * nn, 0.0);
+  // monomial coefficients of T_0 .. T_deg by T_{k+1} = 2u T_k - T_{k-1}
+  std::vector<std::vector<double>> tp(nn, std::vector<double>(nn, 0.0));
+  tp[0][0] = 1.0;
+  if (deg >= 1) tp[1][1] = 1.0;
+  for (int k = 1; k < deg; ++k)
+    for (int p = 0; p <= k + 1; ++p)
+      tp[k + 1][p] = (p > 0 ? 2.0 * tp[k][p - 1] : 0.0) - tp[k - 1][p];
   for (int i = 0; i < taps; ++i) {
     std::vector<double> fv(nn);
     for (int j = 0; j < nn; ++j) {
@@ -142,7 +154,8 @@ std::vector<double> kb_chebyshev(int taps, double beta, int deg) {
     for (int k = 0; k < nn; ++k) {
       double s = 0.0;
       for (int j = 0; j < nn; ++j) s += fv[j] * std::cos(M_PI * k * (j + 0.5) / nn);
-      c[size_t(i) * nn + k] = (k == 0 ? 1.0 : 2.0) * s / nn;
+      const double ck = (k == 0 ? 1.0 : 2.0) * s / nn;
+      for (int p = 0; p <= k; ++p) c[size_t(i) * nn + p] += ck * tp[k][p];
     }
   }
   return c;

@@ -129,7 +129,9 @@ __device__ inline Cell<R> zero_cell() {
 // PASS: 0 = P4 image rows -> half, 1 = P5 half -> grid, 2 = P8 grid -> half, 3 = P9 half -> image.
 // PM >= 0 (PASS 0 only): the primal step of mode PM runs on each pixel as the row is loaded
 // and the row FFT takes the X it returns (P1 fused into P4).
-// items: {prob, first line, -, -}; CELLS/K lines per workgroup.
+// items: {prob, first line, -, -}; CELLS/K lines per workgroup.  The row passes (P4, P9) use
+// several lines per workgroup so that their transposed accesses to `half` cover whole cache
+// lines (four consecutive image rows per k2 in FP32).
 template <typename R, int CELLS, int PASS, int PM = -1>
 __global__ void __launch_bounds__(CELLS / 2)
 fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int dst_slot) {
@@ -236,6 +238,10 @@ void launch_primal_fft(int mode, const LaunchArgs& a, int cells) {
     if (mode == PM_CONSTRAINED) PSARA_PFFT(512, PM_CONSTRAINED);
     else if (mode == PM_INIT) PSARA_PFFT(512, PM_INIT);
     else PSARA_PFFT(512, PM_UNCONSTRAINED);
+  } else if (cells == 2048) {
+    if (mode == PM_CONSTRAINED) PSARA_PFFT(2048, PM_CONSTRAINED);
+    else if (mode == PM_INIT) PSARA_PFFT(2048, PM_INIT);
+    else PSARA_PFFT(2048, PM_UNCONSTRAINED);
   } else {
     if (mode == PM_CONSTRAINED) PSARA_PFFT(1024, PM_CONSTRAINED);
     else if (mode == PM_INIT) PSARA_PFFT(1024, PM_INIT);
@@ -256,6 +262,13 @@ void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_
       case 1: PSARA_FFT(512, 1); break;
       case 2: PSARA_FFT(512, 2); break;
       default: PSARA_FFT(512, 3); break;
+    }
+  } else if (cells == 2048) {
+    switch (pass) {
+      case 0: PSARA_FFT(2048, 0); break;
+      case 1: PSARA_FFT(2048, 1); break;
+      case 2: PSARA_FFT(2048, 2); break;
+      default: PSARA_FFT(2048, 3); break;
     }
   } else {
     switch (pass) {

@@ -23,7 +23,7 @@ namespace psara {
 
 // ---------------------------------------------------------------------------------------------
 // P6: de-grid + L mixing (+ dual B).  items: {prob, tile, first sorted vis, partial index}
-template <typename R, int MODE>
+template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(256)
 degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -31,7 +31,7 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
-  const int K = P.K, T = P.T, ts = P.ts, nts = P.ntile_side;
+  const int K = P.K, ts = P.ts, nts = P.ntile_side;
   const int tile = it.y;
   const int t1 = tile / nts, t2 = tile - t1 * nts;
   const int W = ts + T - 1;
@@ -50,17 +50,19 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
     const int pk = P.vis_k0[m];
     const int r1 = (pk >> 16) - b1, r2 = (pk & 0xffff) - b2;
     const V2<R> f = ((const V2<R>*)P.vis_frac)[m];
-    R w1[kMaxTaps], w2[kMaxTaps];
-    kb_weights<R>(f.x, T, (const R*)P.cheb, w1);
-    kb_weights<R>(f.y, T, (const R*)P.cheb, w2);
+    R w1[T], w2[T];
+    kb_weights<R, T>(f.x, (const R*)P.kbpoly, w1);
+    kb_weights<R, T>(f.y, (const R*)P.kbpoly, w2);
     cplx<R> v[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = cmk(R(0), R(0));
+#pragma unroll
     for (int j = 0; j < T; ++j) {
       const Cell<R>* row = win + (r2 + j) * W + r1;
       cplx<R> t[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) t[s] = cmk(R(0), R(0));
+#pragma unroll
       for (int i = 0; i < T; ++i) {
         const Cell<R> c = row[i];
 #pragma unroll
@@ -111,19 +113,27 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   }
 }
 
-template <typename R>
-void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int max_T, int src_slot, int out_slot) {
-  if (a.nitems <= 0) return;
-  const int W = max_ts + max_T - 1;
-  const size_t shm = (size_t)W * W * sizeof(Cell<R>);
+template <typename R, int T>
+void launch_degrid_t(int mode, const LaunchArgs& a, size_t shm, int src_slot, int out_slot) {
   const dim3 grid(a.nitems), block(256);
   if (mode == DG_DUAL) {
-    hipLaunchKernelGGL((degrid_kernel<R, DG_DUAL>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
+    hipLaunchKernelGGL((degrid_kernel<R, DG_DUAL, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
   } else if (mode == DG_FORWARD) {
-    hipLaunchKernelGGL((degrid_kernel<R, DG_FORWARD>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
+    hipLaunchKernelGGL((degrid_kernel<R, DG_FORWARD, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
   } else {
-    hipLaunchKernelGGL((degrid_kernel<R, DG_RESIDUAL>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
+    hipLaunchKernelGGL((degrid_kernel<R, DG_RESIDUAL, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
   }
+}
+
+// taps: the kernel support T of every problem in the launch (4, 6 or 8)
+template <typename R>
+void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_slot, int out_slot) {
+  if (a.nitems <= 0) return;
+  const int W = max_ts + taps - 1;
+  const size_t shm = (size_t)W * W * sizeof(Cell<R>);
+  if (taps == 4) launch_degrid_t<R, 4>(mode, a, shm, src_slot, out_slot);
+  else if (taps == 6) launch_degrid_t<R, 6>(mode, a, shm, src_slot, out_slot);
+  else launch_degrid_t<R, 8>(mode, a, shm, src_slot, out_slot);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -152,25 +162,27 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int max_T, int src
 // 1.5 * 2^52 rounds y to an integer held in the low mantissa bits of the sum; subtracting the
 // bit pattern of 1.5 * 2^52 leaves it as a two's-complement integer (two instructions).  FP64
 // data use the full 2^61 range and the exact conversion.
+// conv(a, fx) is the nearest integer of a * fx, fx a power of two (so a * fx is exact and the
+// FP32 path needs one fused multiply-add and a 64-bit subtraction).
 template <typename R> struct Fixed;
 template <> struct Fixed<float> {
   static constexpr int kRange = 49;
-  __device__ static long long conv(double y) {
+  __device__ static long long conv(float a, double fx) {
     constexpr double kMagic = 6755399441055744.0;          // 1.5 * 2^52
-    return __double_as_longlong(y + kMagic) - __double_as_longlong(kMagic);
+    return __double_as_longlong(__fma_rn((double)a, fx, kMagic)) - __double_as_longlong(kMagic);
   }
 };
 template <> struct Fixed<double> {
   static constexpr int kRange = 61;
-  __device__ static long long conv(double y) { return __double2ll_rn(y); }
+  __device__ static long long conv(double a, double fx) { return __double2ll_rn(a * fx); }
 };
 
-template <typename R, int MODE>
+template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(256)
 grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac) {
   constexpr int TG = kGridTile;
   constexpr int DEG = KbDeg<R>::value;
-  __shared__ unsigned long long acc[TG * TG * 8];
+  __shared__ unsigned long long acc[8 * TG * TG];   // channel-major: acc[c][k2 offset][k1 offset]
   __shared__ V2<R> sf[kChunkEntries];             // staged fractional offsets
   __shared__ V4<R> su[2 * kChunkEntries];         // staged mixed values, two V4 per entry
   __shared__ double red[8];
@@ -178,11 +190,11 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   const ProbDesc& P = descs[it.x];
   const int4 ch = P.chunks[it.y];
   const int2 ent = P.chunk_ent[it.y];
-  const int K = P.K, T = P.T, ntg = P.ntile_side_g;
+  const int K = P.K, ntg = P.ntile_side_g;
   const int tile = ch.x;
   const int t1 = tile / ntg, t2 = tile - t1 * ntg;
   const int b1 = t1 * TG, b2 = t2 * TG;
-  for (int q = threadIdx.x; q < TG * TG * 8; q += blockDim.x) acc[q] = 0ull;
+  for (int q = threadIdx.x; q < 8 * TG * TG; q += blockDim.x) acc[q] = 0ull;
 
   R scale = R(1);
   if (MODE == GR_DUAL) {
@@ -224,39 +236,31 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
 
   const int lane8 = threadIdx.x & 7;               // tap row owned by this lane
   const int grp = threadIdx.x >> 3, ngrp = blockDim.x >> 3;
-  R cr[DEG + 1];                                   // this lane's tap expansion
+  R cr[DEG + 1];                                   // this lane's tap polynomial
   {
-    const R* __restrict__ cheb = (const R*)P.cheb + (lane8 < T ? lane8 : 0) * (DEG + 1);
+    const R* __restrict__ poly = (const R*)P.kbpoly + (lane8 < T ? lane8 : 0) * (DEG + 1);
 #pragma unroll
-    for (int k = 0; k <= DEG; ++k) cr[k] = lane8 < T ? cheb[k] : R(0);
+    for (int k = 0; k <= DEG; ++k) cr[k] = lane8 < T ? poly[k] : R(0);
   }
   for (int rr = ch.y + grp; rr - grp < ch.z; rr += ngrp) {
     const bool active = rr < ch.z;
     const int e0 = active ? P.run_beg[rr] - ent.x : 0;
     const int len = active ? P.run_len[rr] : 0;
     const int pk = active ? P.run_k0[rr] : 0;
-    R a[kMaxTaps][8];
+    R a[T][8];
 #pragma unroll
-    for (int j = 0; j < kMaxTaps; ++j)
+    for (int j = 0; j < T; ++j)
 #pragma unroll
       for (int c = 0; c < 8; ++c) a[j][c] = R(0);
     for (int q = 0; q < len; ++q) {
       const V2<R> f = sf[e0 + q];
-      // this lane's tap in each dimension: psi(f - lane8) from its Chebyshev expansion
-      const R u1 = R(2) * f.x - R(T - 1), u2 = R(2) * f.y - R(T - 1);
-      R p1 = R(1), c1 = u1, p2 = R(1), c2 = u2;
-      R w1 = cr[0] + cr[1] * u1, w2 = cr[0] + cr[1] * u2;
-#pragma unroll
-      for (int k = 2; k <= DEG; ++k) {
-        const R n1 = R(2) * u1 * c1 - p1, n2 = R(2) * u2 * c2 - p2;
-        p1 = c1; c1 = n1; p2 = c2; c2 = n2;
-        w1 += cr[k] * c1;
-        w2 += cr[k] * c2;
-      }
+      // this lane's tap in each dimension: psi(f - lane8) from its polynomial
+      const R w1 = kb_tap<R, T>(R(2) * f.x - R(T - 1), cr);
+      const R w2 = kb_tap<R, T>(R(2) * f.y - R(T - 1), cr);
       const V4<R> v0 = su[2 * (e0 + q)], v1 = su[2 * (e0 + q) + 1];
       const R u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-      for (int j = 0; j < kMaxTaps; ++j) {
+      for (int j = 0; j < T; ++j) {
         const R wj = w1 * __shfl(w2, j, 8);
 #pragma unroll
         for (int c = 0; c < 8; ++c) a[j][c] += wj * u[c];
@@ -266,13 +270,13 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
       const int c1 = ((pk >> 16) + lane8 - b1) & (K - 1);
       if (c1 < TG) {
 #pragma unroll
-        for (int j = 0; j < kMaxTaps; ++j) {
+        for (int j = 0; j < T; ++j) {
           const int c2 = ((pk & 0xffff) + j - b2) & (K - 1);
-          if (j < T && c2 < TG) {
-            unsigned long long* cell = acc + (size_t)(c2 * TG + c1) * 8;
+          if (c2 < TG) {
+            unsigned long long* cell = acc + c2 * TG + c1;
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-              atomicAdd(cell + c, (unsigned long long)Fixed<R>::conv((double)a[j][c] * fx));
+              atomicAdd(cell + c * TG * TG, (unsigned long long)Fixed<R>::conv(a[j][c], fx));
           }
         }
       }
@@ -294,31 +298,46 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     Cell<R> c;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-      c.s[s] = cmk(R((double)(long long)acc[(size_t)q * 8 + 2 * s] * inv),
-                   R((double)(long long)acc[(size_t)q * 8 + 2 * s + 1] * inv));
+      c.s[s] = cmk(R((double)(long long)acc[(2 * s) * TG * TG + q] * inv),
+                   R((double)(long long)acc[(2 * s + 1) * TG * TG + q] * inv));
     dst[(size_t)a2 * stride + a1] = c;
   }
 }
 
-template <typename R>
-void launch_grid(int mode, const LaunchArgs& a, int max_ts, int src_slot, int use_cfac) {
-  if (a.nitems <= 0) return;
+template <typename R, int T>
+void launch_grid_t(int mode, const LaunchArgs& a, int src_slot, int use_cfac) {
   const dim3 grid(a.nitems), block(256);
   if (mode == GR_DUAL) {
-    hipLaunchKernelGGL((grid_kernel<R, GR_DUAL>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
+    hipLaunchKernelGGL((grid_kernel<R, GR_DUAL, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
   } else {
-    hipLaunchKernelGGL((grid_kernel<R, GR_PLAIN>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
+    hipLaunchKernelGGL((grid_kernel<R, GR_PLAIN, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
   }
 }
 
-// Raise the dynamic-LDS limit of the de-grid / grid kernels once, outside any graph capture.
+// taps: the kernel support T of every problem in the launch (4, 6 or 8)
 template <typename R>
-void set_grid_kernel_limits(int max_ts, int max_T) {
-  const int W = max_ts + max_T - 1;
+void launch_grid(int mode, const LaunchArgs& a, int taps, int src_slot, int use_cfac) {
+  if (a.nitems <= 0) return;
+  if (taps == 4) launch_grid_t<R, 4>(mode, a, src_slot, use_cfac);
+  else if (taps == 6) launch_grid_t<R, 6>(mode, a, src_slot, use_cfac);
+  else launch_grid_t<R, 8>(mode, a, src_slot, use_cfac);
+}
+
+// Raise the dynamic-LDS limit of the de-grid / grid kernels once, outside any graph capture.
+template <typename R, int T>
+void set_degrid_limits_t(int max_ts) {
+  const int W = max_ts + T - 1;
   const int shm_dg = W * W * (int)sizeof(Cell<R>);
-  hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_DUAL>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
-  hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_FORWARD>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
-  hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_RESIDUAL>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
+  hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_DUAL, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
+  hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_FORWARD, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
+  hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_RESIDUAL, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
+}
+
+template <typename R>
+void set_grid_kernel_limits(int max_ts, int taps) {
+  if (taps == 4) set_degrid_limits_t<R, 4>(max_ts);
+  else if (taps == 6) set_degrid_limits_t<R, 6>(max_ts);
+  else set_degrid_limits_t<R, 8>(max_ts);
 }
 
 template void set_grid_kernel_limits<float>(int, int);

@@ -26,9 +26,9 @@ enum GridMode { GR_DUAL = 0, GR_PLAIN = 1 };
 
 template <typename R> void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot);
 template <typename R> void launch_primal_fft(int mode, const LaunchArgs& a, int cells);
-template <typename R> void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int max_T, int src_slot, int out_slot);
-template <typename R> void launch_grid(int mode, const LaunchArgs& a, int max_ts, int src_slot, int use_cfac);
-template <typename R> void set_grid_kernel_limits(int max_ts, int max_T);
+template <typename R> void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_slot, int out_slot);
+template <typename R> void launch_grid(int mode, const LaunchArgs& a, int taps, int src_slot, int use_cfac);
+template <typename R> void set_grid_kernel_limits(int max_ts, int taps);
 void hip_check(hipError_t e, const char* what);
 template <typename R> void launch_primal(int mode, const LaunchArgs& a);
 template <typename R> void launch_analysis(int mode, int level, const LaunchArgs& a, int src_slot, int out_slot);

@@ -21,6 +21,13 @@ constexpr int kChunkEntries = 512;  // gridding entries per workgroup (staged in
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
 
 // Chebyshev degree of the per-tap Kaiser-Bessel expansions (max error ~1e-10 / ~1e-15)
+// SARA tile sides: analysis output tile per band for an input of side 2h, and synthesis
+// output tile for an output of side m (smaller tiles give more workgroups at coarse levels)
+template <typename R> __host__ __device__ constexpr int dwt_ana_tile(int h) {
+  return (sizeof(R) == 4 && h >= 128) ? 16 : (h < 8 ? h : 8);
+}
+template <typename R> __host__ __device__ constexpr int dwt_syn_tile(int m) { return m < 16 ? m : 16; }
+
 template <typename R> struct KbDeg { static constexpr int value = sizeof(R) == 4 ? 9 : 16; };
 
 // image-space buffers (N pixels x 4 Stokes, or x 2 for Z / D)

@@ -162,24 +162,23 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
 }
 
 void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int* n_ana_parts) {
-  const int TO = fp64 ? 8 : 16, TS = fp64 ? 16 : 32, TF = 16;
   const int N = n * n;
   int part = 0;
   for (int b = 0; b < (N + 255) / 256; ++b) S.dirac.push_back(make_int4(prob, b, 0, part++));
   for (int l = 1; l <= levels; ++l) {
     const int h = n >> l;
-    const int to = std::min(TO, h), tps = h / to;
+    const int to = fp64 ? dwt_ana_tile<double>(h) : dwt_ana_tile<float>(h), tps = h / to;
     for (int w = 0; w < nwav; ++w)
       for (int t = 0; t < tps * tps; ++t) S.ana[l].push_back(make_int4(prob, w, t, part++));
   }
   for (int l = 2; l <= levels; ++l) {
     const int m = n >> (l - 1);
-    const int to = std::min(TS, m), tps = m / to;
+    const int to = fp64 ? dwt_syn_tile<double>(m) : dwt_syn_tile<float>(m), tps = m / to;
     for (int w = 0; w < nwav; ++w)
       for (int t = 0; t < tps * tps; ++t) S.syn[l].push_back(make_int4(prob, w, t, 0));
   }
   {
-    const int to = std::min(TF, n), tps = n / to;
+    const int to = fp64 ? dwt_syn_tile<double>(n) : dwt_syn_tile<float>(n), tps = n / to;
     for (int t = 0; t < tps * tps; ++t) S.synfinal.push_back(make_int4(prob, t, 0, 0));
   }
   *n_ana_parts = part;
@@ -410,7 +409,8 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   add_prior_items(items_, 0, n, levels, nwav, std::is_same<R, double>::value, &nap);
   c_level_ = coarse_level<R>(n, levels);
   if (c_level_ <= levels)
-    for (int w = 0; w < nwav; ++w) items_.coarse.push_back(make_int4(0, w, 0, 0));
+    for (int w = 0; w < nwav; ++w)
+      for (int ch = 0; ch < 4; ++ch) items_.coarse.push_back(make_int4(0, w, ch, 0));
   ana_parts_ = nap;
   gen_parts_ = std::max((N + 255) / 256, nap);
   realloc_partials();

@@ -18,15 +18,13 @@
 // scratch array.  Synthesis mirrors this from the coarsest level down; its last level sums
 // every wavelet basis of a tile in registers and writes the image once.  The Dirac part of
 // the dual update is pointwise and is fused into the primal kernel instead.
+//
+// The filter length F (2p for Db_p) is a template parameter of the filtering code, so the
+// tap loops unroll and the taps live in registers; each kernel switches on the basis's F.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace psara {
-
-template <typename R> struct DwtTile;
-// TO: analysis output tile per band; TS: synthesis output tile (levels L..2); TF: last level
-template <> struct DwtTile<float> { static constexpr int TO = 16; static constexpr int TS = 32; static constexpr int TF = 16; };
-template <> struct DwtTile<double> { static constexpr int TO = 8; static constexpr int TS = 16; static constexpr int TF = 16; };
 
 template <typename R>
 __device__ inline void v4_fma(V4<R>& acc, R w, const V4<R>& x) {
@@ -34,6 +32,36 @@ __device__ inline void v4_fma(V4<R>& acc, R w, const V4<R>& x) {
 }
 template <typename R>
 __device__ inline V4<R> v4_zero() { V4<R> v; v.x = v.y = v.z = v.w = R(0); return v; }
+// component-wise load (keeps the destination in registers where a struct copy may not)
+template <typename R>
+__device__ __forceinline__ void ld4(V4<R>& d, const V4<R>* __restrict__ p) {
+  d.x = p->x; d.y = p->y; d.z = p->z; d.w = p->w;
+}
+
+// Low-pass taps h and the quadrature-mirror high-pass g[j] = (-1)^j h[F-1-j] of one basis.
+template <typename R, int F>
+struct Taps {
+  R h[F], g[F];
+  __device__ explicit Taps(const R* __restrict__ f) {
+#pragma unroll
+    for (int j = 0; j < F; ++j) h[j] = f[j];
+#pragma unroll
+    for (int j = 0; j < F; ++j) g[j] = (j & 1) ? -h[F - 1 - j] : h[F - 1 - j];
+  }
+};
+
+// Expands CALL(F) for the run-time filter length of a basis (Db1..Db8).
+#define PSARA_FILTER_SWITCH(Fval, CALL) \
+  switch (Fval) {                       \
+    case 2: CALL(2); break;             \
+    case 4: CALL(4); break;             \
+    case 6: CALL(6); break;             \
+    case 8: CALL(8); break;             \
+    case 10: CALL(10); break;           \
+    case 12: CALL(12); break;           \
+    case 14: CALL(14); break;           \
+    default: CALL(16); break;           \
+  }
 
 template <typename R, int MODE>
 __device__ inline void apply_coef(const ProbDesc& P, int out_coef, size_t idx, V4<R> raw, KSum& k1, KSum& k2) {
@@ -70,6 +98,16 @@ __device__ inline void apply_coef(const ProbDesc& P, int out_coef, size_t idx, V
   }
 }
 
+// the dual update clip(A + rho1 c, -gW, gW) on prefetched A and gW
+template <typename R>
+__device__ inline V4<R> dual_clip(V4<R> a, const V4<R>& gw, const V4<R>& raw, R r1n) {
+  a.x = fmin(fmax(a.x + r1n * raw.x, -gw.x), gw.x);
+  a.y = fmin(fmax(a.y + r1n * raw.y, -gw.y), gw.y);
+  a.z = fmin(fmax(a.z + r1n * raw.z, -gw.z), gw.z);
+  a.w = fmin(fmax(a.w + r1n * raw.w, -gw.w), gw.w);
+  return a;
+}
+
 template <typename R>
 __device__ inline void write_partials(const ProbDesc& P, int part, const KSum& k1, const KSum& k2, int two, double* red) {
   double* gen = P.partials + 2 * (size_t)P.n_p6;
@@ -83,70 +121,106 @@ __device__ inline void write_partials(const ProbDesc& P, int part, const KSum& k
 
 // ---------------------------------------------------------------------------------------------
 // Analysis of level `level` (1 = finest) for every wavelet basis.
-// items: {prob, wavelet index, tile, partial index}
-template <typename R, int MODE>
-__global__ void __launch_bounds__(256)
-analysis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int level, int src_slot, int out_coef) {
-  constexpr int TO = DwtTile<R>::TO;
-  constexpr int IN = 2 * TO + kMaxFilter - 2;
-  __shared__ V4<R> sin_[IN * IN];
-  __shared__ V4<R> rowt[IN * 2 * TO];
-  __shared__ R hf[kMaxFilter], gf[kMaxFilter];
-  __shared__ double red[8];
-  const int4 it = items[blockIdx.x];
-  const ProbDesc& P = descs[it.x];
-  const int n = P.n, w = it.y;
+// items: {prob, wavelet index, tile, partial index}; tile side dwt_ana_tile(h) per band.
+template <typename R> struct AnaSmem {
+  static constexpr int TO = dwt_ana_tile<R>(1 << 30);
+  static constexpr int IN = 2 * TO + kMaxFilter - 2;
+  V4<R> in[IN * IN];
+  V4<R> rowt[IN * 2 * TO];
+};
+
+template <typename R, int MODE, int F>
+__device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R>& sm, int w, int level, int tile, int src_slot,
+                              int out_coef, KSum& k1, KSum& k2) {
+  const Taps<R, F> t((const R*)P.filters + w * kMaxFilter);
+  const int n = P.n;
   const int m = n >> (level - 1), h = m >> 1;
-  const int to = min(TO, h), tps = h / to;
-  const int o1 = (it.z / tps) * to, o2 = (it.z % tps) * to;
-  const int F = P.wav_len[w];
+  const int to = dwt_ana_tile<R>(h), tps = h / to;
+  const int o1 = (tile / tps) * to, o2 = (tile % tps) * to;
   const int in = 2 * to + F - 2;
-  if (threadIdx.x < F) {
-    const R v = ((const R*)P.filters)[w * kMaxFilter + threadIdx.x];
-    hf[threadIdx.x] = v;
+  const size_t base = (size_t)(P.has_dirac + w) * n * n;
+  const bool last = (level == P.levels);
+  // prefetch the duals and thresholds this thread updates (their latency overlaps the filtering)
+  constexpr int NPF = (AnaSmem<R>::TO * 2 * AnaSmem<R>::TO + 255) / 256;
+  V4<R> pa[NPF][2], pg[NPF][2];
+  if (MODE == AM_DUAL) {
+    const V4<R>* __restrict__ A = (const V4<R>*)P.coef[COEF_A];
+    const V4<R>* __restrict__ GW = (const V4<R>*)P.coef[COEF_GW];
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int q = threadIdx.x + u * 256;
+      if (q < to * 2 * to) {
+        const int kr = q / (2 * to), c = q - kr * (2 * to);
+        const int col = (c < to) ? o2 + c : h + o2 + (c - to);
+        const size_t ia = base + (size_t)(o1 + kr) * n + col, id = base + (size_t)(h + o1 + kr) * n + col;
+        if (!(c < to && !last)) { pa[u][0] = A[ia]; pg[u][0] = GW[ia]; }
+        pa[u][1] = A[id]; pg[u][1] = GW[id];
+      }
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < F) gf[threadIdx.x] = ((threadIdx.x & 1) ? R(-1) : R(1)) * hf[F - 1 - threadIdx.x];
   const V4<R>* __restrict__ src = (level == 1)
       ? (const V4<R>*)P.img[src_slot]
       : (const V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level - 1];
   for (int q = threadIdx.x; q < in * in; q += blockDim.x) {
     const int a = q / in, b = q - a * in;
-    sin_[q] = src[(size_t)((2 * o1 + a) & (m - 1)) * m + ((2 * o2 + b) & (m - 1))];
+    sm.in[q] = src[(size_t)((2 * o1 + a) & (m - 1)) * m + ((2 * o2 + b) & (m - 1))];
   }
   __syncthreads();
   // rows: along the column index
   for (int q = threadIdx.x; q < in * to; q += blockDim.x) {
     const int a = q / to, k = q - a * to;
     V4<R> sa = v4_zero<R>(), sd = v4_zero<R>();
-    const V4<R>* row = sin_ + a * in + 2 * k;
-    for (int j = 0; j < F; ++j) { v4_fma(sa, hf[j], row[j]); v4_fma(sd, gf[j], row[j]); }
-    rowt[a * (2 * to) + k] = sa;
-    rowt[a * (2 * to) + to + k] = sd;
+    const V4<R>* row = sm.in + a * in + 2 * k;
+#pragma unroll
+    for (int j = 0; j < F; ++j) { const V4<R> x = row[j]; v4_fma(sa, t.h[j], x); v4_fma(sd, t.g[j], x); }
+    sm.rowt[a * (2 * to) + k] = sa;
+    sm.rowt[a * (2 * to) + to + k] = sd;
   }
   __syncthreads();
-  // columns
-  const size_t base = (size_t)(P.has_dirac + w) * n * n;
-  const bool last = (level == P.levels);
+  // columns, then the per-coefficient operation
   V4<R>* llout = (V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level];
-  KSum k1, k2;
-  for (int q = threadIdx.x; q < to * 2 * to; q += blockDim.x) {
-    const int kr = q / (2 * to), c = q - kr * (2 * to);
-    V4<R> ca = v4_zero<R>(), cd = v4_zero<R>();
-    for (int j = 0; j < F; ++j) {
-      const V4<R> x = rowt[(2 * kr + j) * (2 * to) + c];
-      v4_fma(ca, hf[j], x);
-      v4_fma(cd, gf[j], x);
+  V4<R>* __restrict__ Aw = (V4<R>*)P.coef[COEF_A];
+  const R r1n = R(P.rho1) * R(P.norm);
+#pragma unroll
+  for (int u = 0; u < NPF; ++u) {
+    const int q = threadIdx.x + u * 256;
+    if (q < to * 2 * to) {
+      const int kr = q / (2 * to), c = q - kr * (2 * to);
+      V4<R> ca = v4_zero<R>(), cd = v4_zero<R>();
+#pragma unroll
+      for (int j = 0; j < F; ++j) {
+        const V4<R> x = sm.rowt[(2 * kr + j) * (2 * to) + c];
+        v4_fma(ca, t.h[j], x);
+        v4_fma(cd, t.g[j], x);
+      }
+      const int col = (c < to) ? o2 + c : h + o2 + (c - to);
+      const int rowa = o1 + kr, rowd = h + o1 + kr;
+      const size_t ia = base + (size_t)rowa * n + col, id = base + (size_t)rowd * n + col;
+      if (MODE == AM_DUAL) {
+        if (c < to && !last) llout[(size_t)rowa * h + col] = ca;     // low-low band feeds the next level
+        else Aw[ia] = dual_clip(pa[u][0], pg[u][0], ca, r1n);
+        Aw[id] = dual_clip(pa[u][1], pg[u][1], cd, r1n);
+      } else {
+        if (c < to && !last) llout[(size_t)rowa * h + col] = ca;
+        else apply_coef<R, MODE>(P, out_coef, ia, ca, k1, k2);
+        apply_coef<R, MODE>(P, out_coef, id, cd, k1, k2);
+      }
     }
-    const int col = (c < to) ? o2 + c : h + o2 + (c - to);
-    const int rowa = o1 + kr, rowd = h + o1 + kr;
-    if (c < to && !last) {
-      llout[(size_t)rowa * h + col] = ca;        // low-low band feeds the next level
-    } else {
-      apply_coef<R, MODE>(P, out_coef, base + (size_t)rowa * n + col, ca, k1, k2);
-    }
-    apply_coef<R, MODE>(P, out_coef, base + (size_t)rowd * n + col, cd, k1, k2);
   }
+}
+
+template <typename R, int MODE>
+__global__ void __launch_bounds__(256)
+analysis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int level, int src_slot, int out_coef) {
+  __shared__ AnaSmem<R> sm;
+  __shared__ double red[8];
+  const int4 it = items[blockIdx.x];
+  const ProbDesc& P = descs[it.x];
+  const int w = it.y;
+  KSum k1, k2;
+#define PSARA_ANA(FF) analysis_body<R, MODE, FF>(P, sm, w, level, it.z, src_slot, out_coef, k1, k2)
+  PSARA_FILTER_SWITCH(P.wav_len[w], PSARA_ANA)
+#undef PSARA_ANA
   if (MODE == AM_OBJECTIVE || MODE == AM_MOMENTS) write_partials<R>(P, it.w, k1, k2, MODE == AM_MOMENTS, red);
 }
 
@@ -165,71 +239,100 @@ dirac_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items,
 }
 
 // ---------------------------------------------------------------------------------------------
-// Synthesis, shared by the per-level kernel and the last level.  Computes one to x to tile of
-// the level-(level-1) low-low band (or the image at level 1) of wavelet w into `acc`.
+// Synthesis of one to x to output tile (to = dwt_syn_tile) of the level-(level-1) low-low band
+// (the image at level 1) of one basis.  The four band windows are fetched for the longest
+// filter (KWM = to/2 + kMaxFilter/2 - 1 coefficients per side, starting kMaxFilter/2 - 1 before
+// the tile's first coefficient); a basis with F taps uses the sub-window at offset
+// kMaxFilter/2 - F/2.  The fetch goes through registers (one element of each band window per
+// thread) so the final level can issue the next basis's loads before filtering the current one.
 template <typename R>
 struct SynSmem {
-  static constexpr int TS = DwtTile<R>::TS;
-  static constexpr int KW = TS / 2 + kMaxFilter / 2 - 1;
-  V4<R> band[4][KW * KW];      // LL, HL (top-right), LH (bottom-left), HH windows
-  V4<R> cola[TS * KW], cold[TS * KW];
-  R hf[kMaxFilter], gf[kMaxFilter];
-  double red[8];
+  static constexpr int TS = dwt_syn_tile<R>(1 << 30);
+  static constexpr int KWM = TS / 2 + kMaxFilter / 2 - 1;
+  V4<R> band[4][KWM * KWM];      // LL, HL (top-right), LH (bottom-left), HH windows
+  V4<R> cola[TS * KWM], cold[TS * KWM];
 };
 
 template <typename R>
-__device__ void synth_tile(const ProbDesc& P, SynSmem<R>& sm, int w, int level, int o1, int o2, int to,
-                           int src_coef, V4<R>* acc /* per-thread outputs */, int nper) {
-  const int n = P.n;
-  const int m = n >> (level - 1), h = m >> 1;
-  const int F = P.wav_len[w];
-  const int KW = to / 2 + F / 2 - 1;
-  const int ks1 = o1 / 2 - F / 2 + 1, ks2 = o2 / 2 - F / 2 + 1;
+__device__ __forceinline__ void syn_fetch(const ProbDesc& P, int w, int level, int o1, int o2, int to, int src_coef,
+                                          V4<R>* pre) {
+  constexpr int KWM = SynSmem<R>::KWM;
+  static_assert(KWM * KWM <= 256, "one window element per thread and band");
+  const int n = P.n, h = (n >> (level - 1)) >> 1;
+  const int kw = to / 2 + kMaxFilter / 2 - 1;
+  const int e = threadIdx.x, a = e / KWM, b = e - a * KWM;
+  if (e < KWM * KWM && a < kw && b < kw) {
+    const int r = (o1 / 2 - (kMaxFilter / 2 - 1) + a) & (h - 1), c = (o2 / 2 - (kMaxFilter / 2 - 1) + b) & (h - 1);
+    const V4<R>* __restrict__ A = (const V4<R>*)P.coef[src_coef] + (size_t)(P.has_dirac + w) * n * n;
+    const V4<R>* l0 = (level == P.levels) ? A + (size_t)r * n + c
+        : (const V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level] + (size_t)r * h + c;
+    ld4(pre[0], l0);
+    ld4(pre[1], A + (size_t)r * n + h + c);
+    ld4(pre[2], A + (size_t)(h + r) * n + c);
+    ld4(pre[3], A + (size_t)(h + r) * n + h + c);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void syn_store(SynSmem<R>& sm, const V4<R>* pre) {
+  constexpr int KWM = SynSmem<R>::KWM;
+  if (threadIdx.x < KWM * KWM) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sm.band[u][threadIdx.x] = pre[u];
+  }
+}
+
+// Filters the staged windows into acc.  Output rows (columns) come in pairs 2k, 2k+1 that read
+// the same coefficients, the even one through the even taps and the odd one through the odd
+// taps, so one thread computes both.  acc[2u], acc[2u+1]: the pair q = threadIdx.x + 256 u of
+// the to x to tile, row q / (to/2), columns 2 (q % (to/2)) and 2 (q % (to/2)) + 1.
+template <int F, typename R>
+__device__ __forceinline__ void syn_filter(const ProbDesc& P, SynSmem<R>& sm, int w, int o1, int o2, int to, V4<R>* acc) {
+  constexpr int KWM = SynSmem<R>::KWM;
+  constexpr int NPAIR = (SynSmem<R>::TS * SynSmem<R>::TS / 2 + 255) / 256;
+  const Taps<R, F> t((const R*)P.filters + w * kMaxFilter);
+  const int off = kMaxFilter / 2 - F / 2;          // sub-window of this filter length
+  const int kw = to / 2 + F / 2 - 1, th = to / 2;
+  const int ks1 = o1 / 2 - (kMaxFilter / 2 - 1), ks2 = o2 / 2 - (kMaxFilter / 2 - 1);
   __syncthreads();
-  if (threadIdx.x < F) sm.hf[threadIdx.x] = ((const R*)P.filters)[w * kMaxFilter + threadIdx.x];
-  __syncthreads();
-  if (threadIdx.x < F) sm.gf[threadIdx.x] = ((threadIdx.x & 1) ? R(-1) : R(1)) * sm.hf[F - 1 - threadIdx.x];
-  const V4<R>* __restrict__ A = (const V4<R>*)P.coef[src_coef] + (size_t)(P.has_dirac + w) * n * n;
-  const V4<R>* __restrict__ LL = (level == P.levels) ? nullptr
-      : (const V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level];
-  for (int q = threadIdx.x; q < KW * KW; q += blockDim.x) {
-    const int a = q / KW, b = q - a * KW;
-    const int r = (ks1 + a) & (h - 1), c = (ks2 + b) & (h - 1);
-    sm.band[0][q] = LL ? LL[(size_t)r * h + c] : A[(size_t)r * n + c];
-    sm.band[1][q] = A[(size_t)r * n + h + c];
-    sm.band[2][q] = A[(size_t)(h + r) * n + c];
-    sm.band[3][q] = A[(size_t)(h + r) * n + h + c];
+  // inverse column transform (along the row index): row pairs at full resolution
+  for (int q = threadIdx.x; q < th * kw; q += blockDim.x) {
+    const int rp = q / kw, b = q - rp * kw + off;
+    const int a0 = (o1 >> 1) + rp - ks1;             // coefficient row of output rows 2rp, 2rp+1
+    V4<R> sa0 = v4_zero<R>(), sd0 = v4_zero<R>(), sa1 = v4_zero<R>(), sd1 = v4_zero<R>();
+#pragma unroll
+    for (int jj = 0; jj < F / 2; ++jj) {
+      const int a = a0 - jj;
+      const V4<R> ll = sm.band[0][a * KWM + b], lh = sm.band[2][a * KWM + b];
+      const V4<R> hl = sm.band[1][a * KWM + b], hh = sm.band[3][a * KWM + b];
+      v4_fma(sa0, t.h[2 * jj], ll); v4_fma(sa0, t.g[2 * jj], lh);
+      v4_fma(sd0, t.h[2 * jj], hl); v4_fma(sd0, t.g[2 * jj], hh);
+      v4_fma(sa1, t.h[2 * jj + 1], ll); v4_fma(sa1, t.g[2 * jj + 1], lh);
+      v4_fma(sd1, t.h[2 * jj + 1], hl); v4_fma(sd1, t.g[2 * jj + 1], hh);
+    }
+    sm.cola[(2 * rp) * KWM + b] = sa0;
+    sm.cold[(2 * rp) * KWM + b] = sd0;
+    sm.cola[(2 * rp + 1) * KWM + b] = sa1;
+    sm.cold[(2 * rp + 1) * KWM + b] = sd1;
   }
   __syncthreads();
-  // inverse column transform (along the row index): rows at full resolution
-  for (int q = threadIdx.x; q < to * KW; q += blockDim.x) {
-    const int ir = q / KW, b = q - ir * KW;
-    const int i = o1 + ir;
-    V4<R> sa = v4_zero<R>(), sd = v4_zero<R>();
-    for (int j = (i & 1); j < F; j += 2) {
-      const int a = ((i - j) >> 1) - ks1;
-      v4_fma(sa, sm.hf[j], sm.band[0][a * KW + b]);
-      v4_fma(sa, sm.gf[j], sm.band[2][a * KW + b]);
-      v4_fma(sd, sm.hf[j], sm.band[1][a * KW + b]);
-      v4_fma(sd, sm.gf[j], sm.band[3][a * KW + b]);
+  // inverse row transform (along the column index): column pairs
+#pragma unroll
+  for (int u = 0; u < NPAIR; ++u) {
+    const int q = threadIdx.x + u * 256;
+    if (q < to * th) {
+      const int ir = q / th, cp = q - ir * th;
+      const int b0 = (o2 >> 1) + cp - ks2;
+      V4<R> s0 = acc[2 * u], s1 = acc[2 * u + 1];
+#pragma unroll
+      for (int jj = 0; jj < F / 2; ++jj) {
+        const V4<R> ca = sm.cola[ir * KWM + b0 - jj], cd = sm.cold[ir * KWM + b0 - jj];
+        v4_fma(s0, t.h[2 * jj], ca); v4_fma(s0, t.g[2 * jj], cd);
+        v4_fma(s1, t.h[2 * jj + 1], ca); v4_fma(s1, t.g[2 * jj + 1], cd);
+      }
+      acc[2 * u] = s0;
+      acc[2 * u + 1] = s1;
     }
-    sm.cola[ir * KW + b] = sa;
-    sm.cold[ir * KW + b] = sd;
-  }
-  __syncthreads();
-  // inverse row transform (along the column index)
-  for (int t = 0; t < nper; ++t) {
-    const int q = threadIdx.x + t * blockDim.x;
-    if (q >= to * to) break;
-    const int ir = q / to, ic = q - ir * to;
-    const int i = o2 + ic;
-    V4<R> s = acc[t];
-    for (int j = (i & 1); j < F; j += 2) {
-      const int b = ((i - j) >> 1) - ks2;
-      v4_fma(s, sm.hf[j], sm.cola[ir * KW + b]);
-      v4_fma(s, sm.gf[j], sm.cold[ir * KW + b]);
-    }
-    acc[t] = s;
   }
 }
 
@@ -238,52 +341,65 @@ template <typename R>
 __global__ void __launch_bounds__(256)
 synthesis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int level, int src_coef) {
   __shared__ SynSmem<R> sm;
-  constexpr int TS = DwtTile<R>::TS;
-  constexpr int NPER = (TS * TS + 255) / 256;
+  constexpr int NPAIR = (SynSmem<R>::TS * SynSmem<R>::TS / 2 + 255) / 256;
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
   const int w = it.y;
   const int m = P.n >> (level - 1);
-  const int to = min(TS, m), tps = m / to;
+  const int to = dwt_syn_tile<R>(m), tps = m / to, th = to / 2;
   const int o1 = (it.z / tps) * to, o2 = (it.z % tps) * to;
-  V4<R> acc[NPER];
+  V4<R> acc[2 * NPAIR], pre[4];
 #pragma unroll
-  for (int t = 0; t < NPER; ++t) acc[t] = v4_zero<R>();
-  synth_tile<R>(P, sm, w, level, o1, o2, to, src_coef, acc, NPER);
+  for (int u = 0; u < 2 * NPAIR; ++u) acc[u] = v4_zero<R>();
+  syn_fetch<R>(P, w, level, o1, o2, to, src_coef, pre);
+  syn_store<R>(sm, pre);
+#define PSARA_SYN(FF) syn_filter<FF, R>(P, sm, w, o1, o2, to, acc)
+  PSARA_FILTER_SWITCH(P.wav_len[w], PSARA_SYN)
   V4<R>* out = (V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level - 1];
 #pragma unroll
-  for (int t = 0; t < NPER; ++t) {
-    const int q = threadIdx.x + t * blockDim.x;
-    if (q < to * to) out[(size_t)(o1 + q / to) * m + o2 + q % to] = acc[t];
+  for (int u = 0; u < NPAIR; ++u) {
+    const int q = threadIdx.x + u * 256;
+    if (q < to * th) {
+      V4<R>* o = out + (size_t)(o1 + q / th) * m + o2 + 2 * (q % th);
+      o[0] = acc[2 * u];
+      o[1] = acc[2 * u + 1];
+    }
   }
 }
 
 // Level 1 of every wavelet basis, summed, times 1/sqrt(nb); optionally plus the Dirac block.
+// The next basis's windows are loaded into registers while the current one is filtered.
 // items: {prob, tile, -, -}
 template <typename R>
 __global__ void __launch_bounds__(256)
 synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_coef, int dst_slot, int add_dirac) {
   __shared__ SynSmem<R> sm;
-  constexpr int TS = DwtTile<R>::TF;
-  constexpr int NPER = (TS * TS + 255) / 256;
+  constexpr int NPAIR = (SynSmem<R>::TS * SynSmem<R>::TS / 2 + 255) / 256;
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
   const int n = P.n;
-  const int to = min(TS, n), tps = n / to;
+  const int to = dwt_syn_tile<R>(n), tps = n / to, th = to / 2;
   const int o1 = (it.y / tps) * to, o2 = (it.y % tps) * to;
-  V4<R> acc[NPER];
+  V4<R> acc[2 * NPAIR], pre[4];
 #pragma unroll
-  for (int t = 0; t < NPER; ++t) acc[t] = v4_zero<R>();
-  for (int w = 0; w < P.nwav; ++w) synth_tile<R>(P, sm, w, 1, o1, o2, to, src_coef, acc, NPER);
+  for (int u = 0; u < 2 * NPAIR; ++u) acc[u] = v4_zero<R>();
+  if (P.nwav > 0) syn_fetch<R>(P, 0, 1, o1, o2, to, src_coef, pre);
+  for (int w = 0; w < P.nwav; ++w) {
+    __syncthreads();                       // the previous basis's windows are no longer read
+    syn_store<R>(sm, pre);
+    if (w + 1 < P.nwav) syn_fetch<R>(P, w + 1, 1, o1, o2, to, src_coef, pre);
+    PSARA_FILTER_SWITCH(P.wav_len[w], PSARA_SYN)
+  }
+#undef PSARA_SYN
   const R nm = R(P.norm);
   const V4<R>* dirac = (const V4<R>*)P.coef[src_coef];
   V4<R>* out = (V4<R>*)P.img[dst_slot];
 #pragma unroll
-  for (int t = 0; t < NPER; ++t) {
-    const int q = threadIdx.x + t * blockDim.x;
-    if (q < to * to) {
-      const size_t idx = (size_t)(o1 + q / to) * n + o2 + q % to;
-      V4<R> s = acc[t];
+  for (int u = 0; u < 2 * NPAIR; ++u) {
+    const int q = threadIdx.x + (u >> 1) * 256;
+    if (q < to * th) {
+      const size_t idx = (size_t)(o1 + q / th) * n + o2 + 2 * (q % th) + (u & 1);
+      V4<R> s = acc[u];
       if (add_dirac && P.has_dirac) {
         const V4<R> d = dirac[idx];
         s.x += d.x; s.y += d.y; s.z += d.z; s.w += d.w;
@@ -295,111 +411,130 @@ synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restric
 }
 
 // ---------------------------------------------------------------------------------------------
-// Coarse levels c..L of one wavelet basis in a single workgroup: the low-low band entering
-// level c (at most CoarseMax<R> on a side) is held in LDS; analysis runs level by level with
-// the dual update of every coefficient, then synthesis runs back from level L to level c on
+// Coarse levels c..L of one wavelet basis and one Stokes channel in a single workgroup: the
+// low-low band entering level c (at most CoarseMax<R> on a side) is held in LDS; analysis runs
+// level by level with the dual update of every coefficient, which also stays in LDS as the
+// Mallat pyramid of the coarse levels; synthesis then runs back from level L to level c on
 // the updated duals and leaves the low-low band of level c-1 in the level scratch, where the
 // next synthesis launch reads it.  Replaces 2 (L - c + 1) small launches by one.
-// items: {prob, wavelet index, -, -}
+// items: {prob, wavelet index, Stokes channel, -}
 template <typename R> struct CoarseMax { static constexpr int value = sizeof(R) == 4 ? 64 : 32; };
 
 template <typename R>
-__global__ void __launch_bounds__(1024)
-coarse_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int c_level) {
-  constexpr int MM = CoarseMax<R>::value;
-  __shared__ V4<R> bufA[MM * MM];
-  __shared__ V4<R> bufB[MM * MM];
-  __shared__ R hf[kMaxFilter], gf[kMaxFilter];
-  const int4 it = items[blockIdx.x];
-  const ProbDesc& P = descs[it.x];
-  const int n = P.n, w = it.y, L = P.levels;
-  const int F = P.wav_len[w];
-  const int nt = blockDim.x;
-  if (threadIdx.x < F) hf[threadIdx.x] = ((const R*)P.filters)[w * kMaxFilter + threadIdx.x];
+__device__ inline R& chan(V4<R>& v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
+
+template <int F, typename R>
+__device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, int c_level, R* bufA, R* bufB, R* pyr) {
+  const Taps<R, F> t((const R*)P.filters + w * kMaxFilter);
+  const int n = P.n, L = P.levels, nt = blockDim.x;
+  R* __restrict__ ll = (R*)((V4<R>*)P.ll + (size_t)w * P.ll_stride);
+  R* __restrict__ A = (R*)((V4<R>*)P.coef[COEF_A] + (size_t)(P.has_dirac + w) * n * n);
+  const R* __restrict__ GW = (const R*)((const V4<R>*)P.coef[COEF_GW] + (size_t)(P.has_dirac + w) * n * n);
+  const R r1n = R(P.rho1) * R(P.norm);
+  const int m0 = n >> (c_level - 1);               // side of the coarse pyramid
+  int m = m0;
+  for (int q = threadIdx.x; q < m * m; q += nt) bufA[q] = ll[4 * (P.ll_off[c_level - 1] + q) + ch];
   __syncthreads();
-  if (threadIdx.x < F) gf[threadIdx.x] = ((threadIdx.x & 1) ? R(-1) : R(1)) * hf[F - 1 - threadIdx.x];
-  V4<R>* __restrict__ ll = (V4<R>*)P.ll + (size_t)w * P.ll_stride;
-  V4<R>* __restrict__ A = (V4<R>*)P.coef[COEF_A];
-  const V4<R>* __restrict__ GW = (const V4<R>*)P.coef[COEF_GW];
-  const size_t base = (size_t)(P.has_dirac + w) * n * n;
-  const R nm = R(P.norm), r1 = R(P.rho1);
-  int m = n >> (c_level - 1);
-  for (int q = threadIdx.x; q < m * m; q += nt) bufA[q] = ll[P.ll_off[c_level - 1] + q];
-  __syncthreads();
-  auto dual = [&](size_t idx, const V4<R>& raw) {
-    const V4<R> g = GW[idx];
-    V4<R> a = A[idx];
-    a.x = fmin(fmax(a.x + r1 * nm * raw.x, -g.x), g.x);
-    a.y = fmin(fmax(a.y + r1 * nm * raw.y, -g.y), g.y);
-    a.z = fmin(fmax(a.z + r1 * nm * raw.z, -g.z), g.z);
-    a.w = fmin(fmax(a.w + r1 * nm * raw.w, -g.w), g.w);
-    A[idx] = a;
-  };
   // ---- analysis c..L (bufA holds the m x m low-low band) ----
   for (int l = c_level; l <= L; ++l) {
     const int h = m >> 1;
-    for (int q = threadIdx.x; q < m * m; q += nt) {          // rows: bufB[r][k] = a, bufB[r][h+k] = d
-      const int r = q / m, k = q - r * m;
-      const int kk = k < h ? k : k - h;
-      const R* flt = k < h ? hf : gf;
-      V4<R> acc = v4_zero<R>();
-      for (int j = 0; j < F; ++j) v4_fma(acc, flt[j], bufA[r * m + ((2 * kk + j) & (m - 1))]);
-      bufB[q] = acc;
+    for (int q = threadIdx.x; q < m * h; q += nt) {          // rows: bufB[r][k] = a, bufB[r][h+k] = d
+      const int r = q / h, k = q - r * h;
+      R sa = R(0), sd = R(0);
+#pragma unroll
+      for (int j = 0; j < F; ++j) {
+        const R x = bufA[r * m + ((2 * k + j) & (m - 1))];
+        sa += t.h[j] * x;
+        sd += t.g[j] * x;
+      }
+      bufB[r * m + k] = sa;
+      bufB[r * m + h + k] = sd;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < m * m; q += nt) {          // columns
-      const int k1 = q / m, col = q - k1 * m;
-      const int kk = k1 < h ? k1 : k1 - h;
-      const R* flt = k1 < h ? hf : gf;
-      V4<R> acc = v4_zero<R>();
-      for (int j = 0; j < F; ++j) v4_fma(acc, flt[j], bufB[((2 * kk + j) & (m - 1)) * m + col]);
-      if (k1 < h && col < h && l < L) bufA[k1 * h + col] = acc;     // next level's input
-      else dual(base + (size_t)k1 * n + col, acc);
+    for (int q = threadIdx.x; q < h * m; q += nt) {          // columns; q = (k, col)
+      const int k = q / m, col = q - k * m;
+      R ca = R(0), cd = R(0);
+#pragma unroll
+      for (int j = 0; j < F; ++j) {
+        const R x = bufB[((2 * k + j) & (m - 1)) * m + col];
+        ca += t.h[j] * x;
+        cd += t.g[j] * x;
+      }
+      // (k, col): low rows; (h + k, col): high rows
+      if (col < h && l < L) {
+        bufA[k * h + col] = ca;                              // next level's input
+      } else {
+        const size_t g = (size_t)k * n + col;
+        const R a = fmin(fmax(A[4 * g + ch] + r1n * ca, -GW[4 * g + ch]), GW[4 * g + ch]);
+        A[4 * g + ch] = a;
+        pyr[k * m0 + col] = a;
+      }
+      const size_t g = (size_t)(h + k) * n + col;
+      const R d = fmin(fmax(A[4 * g + ch] + r1n * cd, -GW[4 * g + ch]), GW[4 * g + ch]);
+      A[4 * g + ch] = d;
+      pyr[(h + k) * m0 + col] = d;
     }
     __syncthreads();
     m = h;
   }
-  __threadfence_block();
-  __syncthreads();
   // ---- synthesis L..c on the updated duals (bufA: the h x h low-low input) ----
-  const V4<R>* __restrict__ Ac = A;
   {
     const int h = n >> L;
-    for (int q = threadIdx.x; q < h * h; q += nt) bufA[q] = Ac[base + (size_t)(q / h) * n + q % h];
+    for (int q = threadIdx.x; q < h * h; q += nt) bufA[q] = pyr[(q / h) * m0 + q % h];
   }
   __syncthreads();
   for (int l = L; l >= c_level; --l) {
     const int mo = n >> (l - 1), h = mo >> 1;
-    // inverse column transform: bufB[ir][b] (ir < mo, b < h) from LL/LH, bufB[mo*h + ...] from HL/HH
-    for (int q = threadIdx.x; q < mo * h; q += nt) {
-      const int ir = q / h, b = q - ir * h;
-      V4<R> sa = v4_zero<R>(), sd = v4_zero<R>();
-      for (int j = (ir & 1); j < F; j += 2) {
-        const int r = ((ir - j) >> 1) & (h - 1);
-        v4_fma(sa, hf[j], bufA[r * h + b]);
-        v4_fma(sa, gf[j], Ac[base + (size_t)(h + r) * n + b]);
-        v4_fma(sd, hf[j], Ac[base + (size_t)r * n + h + b]);
-        v4_fma(sd, gf[j], Ac[base + (size_t)(h + r) * n + h + b]);
+    // inverse column transform: bufB[ir][b] (b < h) from LL/LH, bufB[mo*h + ir*h + b] from HL/HH;
+    // output rows 2r', 2r'+1 read the same coefficients through the even / odd taps
+    for (int q = threadIdx.x; q < h * h; q += nt) {
+      const int rp = q / h, b = q - rp * h;
+      R sa0 = R(0), sd0 = R(0), sa1 = R(0), sd1 = R(0);
+#pragma unroll
+      for (int jj = 0; jj < F / 2; ++jj) {
+        const int r = (rp - jj) & (h - 1);
+        const R ll = bufA[r * h + b], lh = pyr[(h + r) * m0 + b];
+        const R hl = pyr[r * m0 + h + b], hh = pyr[(h + r) * m0 + h + b];
+        sa0 += t.h[2 * jj] * ll + t.g[2 * jj] * lh;
+        sd0 += t.h[2 * jj] * hl + t.g[2 * jj] * hh;
+        sa1 += t.h[2 * jj + 1] * ll + t.g[2 * jj + 1] * lh;
+        sd1 += t.h[2 * jj + 1] * hl + t.g[2 * jj + 1] * hh;
       }
-      bufB[q] = sa;
-      bufB[mo * h + q] = sd;
+      bufB[(2 * rp) * h + b] = sa0;
+      bufB[mo * h + (2 * rp) * h + b] = sd0;
+      bufB[(2 * rp + 1) * h + b] = sa1;
+      bufB[mo * h + (2 * rp + 1) * h + b] = sd1;
     }
     __syncthreads();
-    // inverse row transform into bufA (mo x mo)
-    for (int q = threadIdx.x; q < mo * mo; q += nt) {
-      const int ir = q / mo, ic = q - ir * mo;
-      V4<R> s = v4_zero<R>();
-      for (int j = (ic & 1); j < F; j += 2) {
-        const int b = ((ic - j) >> 1) & (h - 1);
-        v4_fma(s, hf[j], bufB[ir * h + b]);
-        v4_fma(s, gf[j], bufB[mo * h + ir * h + b]);
+    // inverse row transform into bufA (mo x mo), column pairs
+    for (int q = threadIdx.x; q < mo * h; q += nt) {
+      const int ir = q / h, cp = q - ir * h;
+      R s0 = R(0), s1 = R(0);
+#pragma unroll
+      for (int jj = 0; jj < F / 2; ++jj) {
+        const int b = (cp - jj) & (h - 1);
+        const R ca = bufB[ir * h + b], cd = bufB[mo * h + ir * h + b];
+        s0 += t.h[2 * jj] * ca + t.g[2 * jj] * cd;
+        s1 += t.h[2 * jj + 1] * ca + t.g[2 * jj + 1] * cd;
       }
-      bufA[q] = s;
+      bufA[ir * mo + 2 * cp] = s0;
+      bufA[ir * mo + 2 * cp + 1] = s1;
     }
     __syncthreads();
   }
-  const int mo = n >> (c_level - 1);
-  for (int q = threadIdx.x; q < mo * mo; q += nt) ll[P.ll_off[c_level - 1] + q] = bufA[q];
+  for (int q = threadIdx.x; q < m0 * m0; q += nt) ll[4 * (P.ll_off[c_level - 1] + q) + ch] = bufA[q];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(512)
+coarse_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int c_level) {
+  constexpr int MM = CoarseMax<R>::value;
+  __shared__ R bufA[MM * MM], bufB[MM * MM], pyr[MM * MM];
+  const int4 it = items[blockIdx.x];
+  const ProbDesc& P = descs[it.x];
+#define PSARA_COARSE(FF) coarse_body<FF, R>(P, it.y, it.z, c_level, bufA, bufB, pyr)
+  PSARA_FILTER_SWITCH(P.wav_len[it.y], PSARA_COARSE)
+#undef PSARA_COARSE
 }
 
 template <typename R>
@@ -413,7 +548,7 @@ int coarse_level(int n, int levels) {
 template <typename R>
 void launch_coarse(const LaunchArgs& a, int c_level) {
   if (a.nitems <= 0) return;
-  hipLaunchKernelGGL((coarse_kernel<R>), dim3(a.nitems), dim3(1024), 0, a.stream, a.descs, a.items, c_level);
+  hipLaunchKernelGGL((coarse_kernel<R>), dim3(a.nitems), dim3(512), 0, a.stream, a.descs, a.items, c_level);
 }
 
 template <typename R>

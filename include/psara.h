@@ -146,6 +146,27 @@ psara_status psara_reweighted_solve(psara_ctx* ctx, psara_mode mode, int cycles,
 /* Evaluate the stopping quantities for the current state. */
 psara_status psara_report_now(psara_ctx* ctx, psara_report* out);
 
+/* ---- batches of independent solves ------------------------------------------------------- */
+
+/* Advance `count` independent solves together: every pass of Algorithm 1 is one launch over
+ * all of them (their work lists concatenated), captured in one HIP graph on the stream of
+ * ctxs[0]; each solve keeps its own state and its result is the same as when it runs alone
+ * (the kernels' arithmetic per problem does not depend on the batch).  Requirements: count >= 1
+ * distinct contexts on one device with the same precision and tap count, each with operator,
+ * data and step sizes set, and a prior for the modes with the sparsity term.  Blocks until the
+ * iterations are done.  reports: NULL or `count` reports filled as psara_solve does.  On an
+ * error every context's last error holds the message and no iteration has run. */
+psara_status psara_batch_solve(psara_ctx* const* ctxs, int count, psara_mode mode, int iters,
+                               psara_report* reports);
+
+/* Algorithm 2 for a batch: the initialisation stage batched, then for each member its own
+ * delta (coefficient standard deviation) and weights, then `cycles` batched reweighted stages,
+ * delta divided by delta_decay after every cycle, exactly as psara_reweighted_solve per member.
+ * reports: NULL or `count` final reports. */
+psara_status psara_batch_reweighted_solve(psara_ctx* const* ctxs, int count, psara_mode mode, int cycles,
+                                          const int* iters_per_stage, double delta_decay,
+                                          psara_report* reports);
+
 /* ---- state ------------------------------------------------------------------------------- */
 
 /* Current Stokes estimate S (N x 4 doubles). */

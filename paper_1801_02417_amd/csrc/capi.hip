@@ -105,6 +105,79 @@ void run_stage(psara_ctx* c, int mode, int iters, int check_every, psara_report*
   with_engine(c, [&](auto& e) { psara::hip_check(hipStreamSynchronize(e.stream()), "solve sync"); });
 }
 
+
+// Runs f() for a batch of contexts; an error is recorded in every context.
+template <class F>
+psara_status batch_guard(psara_ctx* const* ctxs, int count, F&& f) {
+  if (!ctxs || count <= 0) return PSARA_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!ctxs[i]) return PSARA_EINVAL;
+  auto fail = [&](const std::string& m) { for (int i = 0; i < count; ++i) ctxs[i]->err = m; };
+  try {
+    if (hipSetDevice(ctxs[0]->device) != hipSuccess) throw Error(PSARA_EDEVICE, "hipSetDevice failed");
+    f();
+    for (int i = 0; i < count; ++i) ctxs[i]->err.clear();
+    return PSARA_OK;
+  } catch (const Error& e) {
+    fail(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    fail("host allocation failed");
+    return PSARA_ENOMEM;
+  } catch (const std::exception& e) {
+    fail(e.what());
+    return PSARA_EDEVICE;
+  }
+}
+
+void check_batch(psara_ctx* const* ctxs, int count, int mode) {
+  for (int i = 0; i < count; ++i) {
+    psara_ctx* c = ctxs[i];
+    require(c->op_set && c->data_set, PSARA_ESTATE, "batch member without operator or data");
+    require(c->steps_set, PSARA_ESTATE, "batch member without step sizes");
+    require(mode == psara::PM_INIT || c->prior_set, PSARA_ESTATE, "batch member without a prior");
+    require(c->device == ctxs[0]->device, PSARA_EINVAL, "batch members must share one device");
+    require(c->prec == ctxs[0]->prec, PSARA_EINVAL, "batch members must share the precision");
+    for (int j = 0; j < i; ++j) require(ctxs[j] != c, PSARA_EINVAL, "a context appears twice in the batch");
+  }
+}
+
+template <typename R> Engine<R>* engine_of(psara_ctx* c);
+template <> Engine<float>* engine_of<float>(psara_ctx* c) { return c->f32.get(); }
+template <> Engine<double>* engine_of<double>(psara_ctx* c) { return c->f64.get(); }
+
+template <typename R>
+void batch_reweighted(psara_ctx* const* ctxs, int count, int mode, int cycles, const int* iters, double decay,
+                      psara_report* reports) {
+  std::vector<Engine<R>*> m;
+  for (int i = 0; i < count; ++i) m.push_back(engine_of<R>(ctxs[i]));
+  psara::Batch<R> b(m, ctxs[0]->stream);
+  auto stage = [&](int pm, int k) {
+    b.run(pm, k);
+    psara::hip_check(hipStreamSynchronize(b.stream()), "batch sync");
+    for (int i = 0; i < count; ++i) ctxs[i]->iterations += k;
+  };
+  if (cycles < 0) {                       // a plain batched stage
+    stage(mode, iters[0]);
+  } else {
+    stage(psara::PM_INIT, iters[0]);
+    std::vector<double> delta(count);
+    for (int i = 0; i < count; ++i) {
+      delta[i] = m[i]->coef_std();
+      require(delta[i] > 0.0, PSARA_EINVAL, "initial estimate is zero: no reweighting scale");
+    }
+    for (int l = 1; l <= cycles; ++l) {
+      for (int i = 0; i < count; ++i) m[i]->reweight(delta[i]);
+      stage(mode, iters[l]);
+      for (int i = 0; i < count; ++i) delta[i] /= decay;
+    }
+  }
+  if (reports)
+    for (int i = 0; i < count; ++i) {
+      m[i]->report(&reports[i]);
+      reports[i].iterations = ctxs[i]->iterations;
+    }
+}
 }  // namespace
 
 extern "C" {
@@ -292,6 +365,30 @@ psara_status psara_reweighted_solve(psara_ctx* c, psara_mode mode, int cycles, c
       with_engine(c, [&](auto& e) { e.report(out); });
       out->iterations = c->iterations;
     }
+  });
+}
+
+psara_status psara_batch_solve(psara_ctx* const* ctxs, int count, psara_mode mode, int iters, psara_report* reports) {
+  return batch_guard(ctxs, count, [&] {
+    const int pm = primal_mode(mode);
+    require(iters >= 0, PSARA_EINVAL, "iters must be >= 0");
+    check_batch(ctxs, count, pm);
+    if (ctxs[0]->prec == PSARA_FP64) batch_reweighted<double>(ctxs, count, pm, -1, &iters, 10.0, reports);
+    else batch_reweighted<float>(ctxs, count, pm, -1, &iters, 10.0, reports);
+  });
+}
+
+psara_status psara_batch_reweighted_solve(psara_ctx* const* ctxs, int count, psara_mode mode, int cycles,
+                                          const int* iters_per_stage, double delta_decay, psara_report* reports) {
+  return batch_guard(ctxs, count, [&] {
+    const int pm = primal_mode(mode);
+    require(cycles >= 0 && iters_per_stage != nullptr, PSARA_EINVAL, "bad stage list");
+    require(delta_decay > 1.0 && std::isfinite(delta_decay), PSARA_EINVAL, "delta_decay must be > 1");
+    for (int l = 0; l <= cycles; ++l) require(iters_per_stage[l] >= 0, PSARA_EINVAL, "negative iteration count");
+    check_batch(ctxs, count, pm);
+    for (int i = 0; i < count; ++i) require(ctxs[i]->prior_set, PSARA_ESTATE, "batch member without a prior");
+    if (ctxs[0]->prec == PSARA_FP64) batch_reweighted<double>(ctxs, count, pm, cycles, iters_per_stage, delta_decay, reports);
+    else batch_reweighted<float>(ctxs, count, pm, cycles, iters_per_stage, delta_decay, reports);
   });
 }
 

@@ -161,7 +161,7 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
   *n_p6 = part;
 }
 
-void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int* n_ana_parts) {
+void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int c_level, int* n_ana_parts) {
   const int N = n * n;
   int part = 0;
   for (int b = 0; b < (N + 255) / 256; ++b) S.dirac.push_back(make_int4(prob, b, 0, part++));
@@ -169,14 +169,23 @@ void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp6
     const int h = n >> l;
     const int to = fp64 ? dwt_ana_tile<double>(h) : dwt_ana_tile<float>(h), tps = h / to;
     for (int w = 0; w < nwav; ++w)
-      for (int t = 0; t < tps * tps; ++t) S.ana[l].push_back(make_int4(prob, w, t, part++));
+      for (int t = 0; t < tps * tps; ++t) {
+        S.ana[l].push_back(make_int4(prob, w, t, part++));
+        if (l < c_level) S.ana_d[l].push_back(S.ana[l].back());
+      }
   }
   for (int l = 2; l <= levels; ++l) {
     const int m = n >> (l - 1);
     const int to = fp64 ? dwt_syn_tile<double>(m) : dwt_syn_tile<float>(m), tps = m / to;
     for (int w = 0; w < nwav; ++w)
-      for (int t = 0; t < tps * tps; ++t) S.syn[l].push_back(make_int4(prob, w, t, 0));
+      for (int t = 0; t < tps * tps; ++t) {
+        S.syn[l].push_back(make_int4(prob, w, t, 0));
+        if (l < c_level) S.syn_d[l].push_back(S.syn[l].back());
+      }
   }
+  if (c_level <= levels)
+    for (int w = 0; w < nwav; ++w)
+      for (int ch = 0; ch < 4; ++ch) S.coarse.push_back(make_int4(prob, w, ch, c_level));
   {
     const int to = fp64 ? dwt_syn_tile<double>(n) : dwt_syn_tile<float>(n), tps = n / to;
     for (int t = 0; t < tps * tps; ++t) S.synfinal.push_back(make_int4(prob, t, 0, 0));
@@ -329,9 +338,19 @@ void Engine<R>::upload_items() {
   up(d_img_, items_.img); up(d_rows_, xcd_contiguous(items_.rows)); up(d_cols_, items_.cols);
   up(d_p6_, items_.p6); up(d_p7_, items_.p7);
   up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal); up(d_coarse_, items_.coarse);
-  for (int l = 0; l <= kMaxLevels; ++l) { up(d_ana_[l], items_.ana[l]); up(d_syn_[l], items_.syn[l]); }
+  for (int l = 0; l <= kMaxLevels; ++l) {
+    up(d_ana_[l], items_.ana[l]); up(d_syn_[l], items_.syn[l]);
+    up(d_ana_d_[l], items_.ana_d[l]); up(d_syn_d_[l], items_.syn_d[l]);
+  }
   if (!d_desc_) d_desc_ = dalloc<ProbDesc>(1);
   desc_dirty_ = true;
+  pl_.descs = d_desc_;
+  pl_.img = d_img_; pl_.rows = d_rows_; pl_.cols = d_cols_; pl_.p6 = d_p6_; pl_.p7 = d_p7_;
+  pl_.synfinal = d_synfinal_; pl_.coarse = d_coarse_;
+  for (int l = 0; l <= kMaxLevels; ++l) { pl_.ana_d[l] = d_ana_d_[l]; pl_.syn_d[l] = d_syn_d_[l]; }
+  pl_.cells = cells_; pl_.rcells = rcells_;
+  pl_.max_ts = geo_.ts; pl_.taps = geo_.T; pl_.max_levels = h_.levels;
+  pl_.sparse = h_.coef[COEF_A] != nullptr && h_.nwav > 0;
 }
 
 template <typename R>
@@ -373,7 +392,9 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   dfree(h_.ll); h_.ll = nullptr;
   dfree((void*)h_.filters); h_.filters = nullptr;
   items_.dirac.clear(); items_.synfinal.clear(); items_.coarse.clear();
-  for (int l = 0; l <= kMaxLevels; ++l) { items_.ana[l].clear(); items_.syn[l].clear(); }
+  for (int l = 0; l <= kMaxLevels; ++l) {
+    items_.ana[l].clear(); items_.syn[l].clear(); items_.ana_d[l].clear(); items_.syn_d[l].clear();
+  }
   h_.has_dirac = (mask & 1u) ? 1 : 0;
   int nwav = 0;
   std::vector<double> filt(8 * kMaxFilter, 0.0);
@@ -406,11 +427,8 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   hip_check(hipMemcpy(h_.coef[COEF_GW], gw.data(), gw.size() * sizeof(R), hipMemcpyHostToDevice), "weights upload");
   zero(h_.coef[COEF_A], coef_elems_ * sizeof(V4<R>));
   int nap = 0;
-  add_prior_items(items_, 0, n, levels, nwav, std::is_same<R, double>::value, &nap);
   c_level_ = coarse_level<R>(n, levels);
-  if (c_level_ <= levels)
-    for (int w = 0; w < nwav; ++w)
-      for (int ch = 0; ch < 4; ++ch) items_.coarse.push_back(make_int4(0, w, ch, 0));
+  add_prior_items(items_, 0, n, levels, nwav, std::is_same<R, double>::value, c_level_, &nap);
   ana_parts_ = nap;
   gen_parts_ = std::max((N + 255) / 256, nap);
   realloc_partials();
@@ -446,13 +464,49 @@ template <typename R> void Engine<R>::p3(int src_coef, int dst_slot, int add_dir
   for (int l = h_.levels; l >= 2; --l) launch_synthesis<R>(l, h_.levels, la(d_syn_[l], s), src_coef, 0);
   launch_synthesis_final<R>(la(d_synfinal_, s), src_coef, dst_slot, add_dirac);
 }
-template <typename R> void Engine<R>::p23(hipStream_t s) {
-  if (c_level_ > h_.levels) { p2(s); p3(COEF_A, IMG_PSIA, 0, s); return; }
-  for (int l = 1; l < c_level_; ++l) launch_analysis<R>(AM_DUAL, l, la(d_ana_[l], s), IMG_X, COEF_A);
-  launch_coarse<R>(la(d_coarse_, s), c_level_);
-  for (int l = c_level_ - 1; l >= 2; --l) launch_synthesis<R>(l, h_.levels, la(d_syn_[l], s), COEF_A, 0);
-  launch_synthesis_final<R>(la(d_synfinal_, s), COEF_A, IMG_PSIA, 0);
+template <typename R> void Engine<R>::p23(hipStream_t s) { launch_sara_dual<R>(pl_, s ? s : s0_); }
+
+// ---- the iteration over a set of problems -------------------------------------------------------
+static LaunchArgs lists_la(const PassLists& L, const DevItems& d, hipStream_t s) {
+  LaunchArgs a;
+  a.descs = L.descs;
+  a.items = d.ptr;
+  a.nitems = d.count;
+  a.stream = s;
+  return a;
 }
+
+template <typename R>
+void launch_sara_dual(const PassLists& L, hipStream_t s) {
+  for (int l = 1; l <= L.max_levels; ++l) launch_analysis<R>(AM_DUAL, l, lists_la(L, L.ana_d[l], s), IMG_X, COEF_A);
+  launch_coarse<R>(lists_la(L, L.coarse, s));
+  for (int l = L.max_levels; l >= 2; --l) launch_synthesis<R>(l, L.max_levels, lists_la(L, L.syn_d[l], s), COEF_A, 0);
+  launch_synthesis_final<R>(lists_la(L, L.synfinal, s), COEF_A, IMG_PSIA, 0);
+}
+
+template <typename R>
+void launch_iteration_lists(const PassLists& L, int mode, hipStream_t s0, hipStream_t s1, hipEvent_t fork,
+                            hipEvent_t join) {
+  // P1 fused into P4: the row-FFT workgroups run the primal step of their rows
+  launch_primal_fft<R>(mode, lists_la(L, L.rows, s0), L.rcells);
+  const bool sparse = (mode != PM_INIT) && L.sparse;
+  if (sparse) {
+    hip_check(hipEventRecord(fork, s0), "event record");
+    hip_check(hipStreamWaitEvent(s1, fork, 0), "stream wait");
+    launch_sara_dual<R>(L, s1);
+    hip_check(hipEventRecord(join, s1), "event record");
+  }
+  launch_fft<R>(1, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P5
+  launch_degrid<R>(DG_DUAL, lists_la(L, L.p6, s0), L.max_ts, L.taps, VIS_BV, VIS_BV);  // P6
+  launch_grid<R>(GR_DUAL, lists_la(L, L.p7, s0), L.taps, VIS_BV, 0);               // P7
+  launch_fft<R>(2, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P8
+  launch_fft<R>(3, lists_la(L, L.rows, s0), L.rcells, 0, IMG_PHIB);                // P9
+  if (sparse) hip_check(hipStreamWaitEvent(s0, join, 0), "stream wait");
+}
+template void launch_iteration_lists<float>(const PassLists&, int, hipStream_t, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_iteration_lists<double>(const PassLists&, int, hipStream_t, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_sara_dual<float>(const PassLists&, hipStream_t);
+template void launch_sara_dual<double>(const PassLists&, hipStream_t);
 template <typename R> void Engine<R>::p4(int src, hipStream_t s) { launch_fft<R>(0, la(d_rows_, s), rcells_, src, 0); }
 template <typename R> void Engine<R>::p5(hipStream_t s) { launch_fft<R>(1, la(d_cols_, s), cells_, 0, 0); }
 template <typename R> void Engine<R>::p6(int mode, int src, int out, hipStream_t s) {
@@ -475,21 +529,7 @@ void Engine<R>::adjoint(int src_vis, int use_cfac, int dst_img) {
 
 template <typename R>
 void Engine<R>::launch_iteration(int mode) {
-  // P1 fused into P4: the row-FFT workgroups run the primal step of their rows
-  launch_primal_fft<R>(mode, la(d_rows_, s0_), rcells_);
-  const bool sparse = (mode != PM_INIT) && h_.coef[COEF_A] && h_.nwav > 0;
-  if (sparse) {
-    hip_check(hipEventRecord(ev_fork_, s0_), "event record");
-    hip_check(hipStreamWaitEvent(s1_, ev_fork_, 0), "stream wait");
-    p23(s1_);
-    hip_check(hipEventRecord(ev_join_, s1_), "event record");
-  }
-  p5(s0_);
-  p6(DG_DUAL, VIS_BV, VIS_BV, s0_);
-  p7(GR_DUAL, VIS_BV, 0, s0_);
-  p8(s0_);
-  p9(IMG_PHIB, s0_);
-  if (sparse) hip_check(hipStreamWaitEvent(s0_, ev_join_, 0), "stream wait");
+  launch_iteration_lists<R>(pl_, mode, s0_, s1_, ev_fork_, ev_join_);
 }
 
 template <typename R>
@@ -787,8 +827,6 @@ void Engine<R>::profile(int mode, int iters, double* ms) {
     hip_check(hipEventRecord(ev[1], s0_), "event record");
     if (sparse) p23(s0_);      // P2 and P3 with the fused coarse levels: timed together as P2
     hip_check(hipEventRecord(ev[2], s0_), "event record");
-    hip_check(hipEventRecord(ev[3], s0_), "event record");
-    hip_check(hipEventRecord(ev[4], s0_), "event record");
     p5(s0_);
     hip_check(hipEventRecord(ev[5], s0_), "event record");
     p6(DG_DUAL, VIS_BV, VIS_BV, s0_);
@@ -801,8 +839,9 @@ void Engine<R>::profile(int mode, int iters, double* ms) {
     hip_check(hipEventRecord(ev[9], s0_), "event record");
     hip_check(hipEventSynchronize(ev[9]), "event sync");
     for (int i = 0; i < NP; ++i) {
+      if (i == 2 || i == 3) continue;          // P3 runs inside P2's launches, P4 inside P1's
       float t = 0.f;
-      hip_check(hipEventElapsedTime(&t, ev[i], ev[i + 1]), "elapsed");
+      hip_check(hipEventElapsedTime(&t, ev[i == 4 ? 2 : i], ev[i + 1]), "elapsed");
       ms[i] += t;
     }
   }
@@ -812,5 +851,120 @@ void Engine<R>::profile(int mode, int iters, double* ms) {
 
 template struct Engine<float>;
 template struct Engine<double>;
+
+// ---- Batch<R> ------------------------------------------------------------------------------------
+template <typename R>
+Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : members_(members), s0_(stream) {
+  if (members_.empty()) throw Error(PSARA_EINVAL, "empty batch");
+  const int T = members_[0]->geometry().T;
+  int cells = 512, max_ts = 0, max_levels = 0;
+  bool sparse = true;
+  for (Engine<R>* e : members_) {
+    const Geometry& g = e->geometry();
+    if (g.T != T) throw Error(PSARA_EINVAL, "batch members must share the tap count");
+    cells = std::max(cells, g.K);
+    max_ts = std::max(max_ts, g.ts);
+    max_levels = std::max(max_levels, e->desc().levels);
+    sparse = sparse && e->has_prior();
+  }
+  ItemSet S;
+  for (size_t i = 0; i < members_.size(); ++i) {
+    Engine<R>* e = members_[i];
+    const Geometry& g = e->geometry();
+    int np6 = 0;
+    add_operator_items(S, (int)i, g, cells, cells, &np6);
+    if (np6 != e->desc().n_p6) throw Error(PSARA_EDEVICE, "inconsistent de-grid partition");
+    if (e->has_prior()) {
+      int nap = 0;
+      add_prior_items(S, (int)i, g.n, e->desc().levels, e->desc().nwav, std::is_same<R, double>::value,
+                      e->c_level(), &nap);
+    }
+  }
+  auto up = [&](DevItems& d, const std::vector<int4>& v) {
+    d.count = (int)v.size();
+    d.ptr = nullptr;
+    if (v.empty()) return;
+    void* p = nullptr;
+    if (hipMalloc(&p, v.size() * sizeof(int4)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(PSARA_ENOMEM, "batch work-list allocation failed");
+    }
+    allocs_.push_back(p);
+    hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(int4), hipMemcpyHostToDevice), "work-list upload");
+    d.ptr = (int4*)p;
+  };
+  up(pl_.img, S.img); up(pl_.rows, xcd_contiguous(S.rows)); up(pl_.cols, S.cols);
+  up(pl_.p6, S.p6); up(pl_.p7, S.p7); up(pl_.synfinal, S.synfinal); up(pl_.coarse, S.coarse);
+  for (int l = 0; l <= kMaxLevels; ++l) { up(pl_.ana_d[l], S.ana_d[l]); up(pl_.syn_d[l], S.syn_d[l]); }
+  void* p = nullptr;
+  if (hipMalloc(&p, members_.size() * sizeof(ProbDesc)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(PSARA_ENOMEM, "batch descriptor allocation failed");
+  }
+  allocs_.push_back(p);
+  d_descs_ = (ProbDesc*)p;
+  pl_.descs = d_descs_;
+  pl_.cells = cells; pl_.rcells = cells;
+  pl_.max_ts = max_ts; pl_.taps = T; pl_.max_levels = max_levels;
+  pl_.sparse = sparse;
+  set_grid_kernel_limits<R>(max_ts, T);
+  hip_check(hipStreamCreateWithFlags(&s1_, hipStreamNonBlocking), "hipStreamCreate");
+  hip_check(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming), "hipEventCreate");
+  hip_check(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming), "hipEventCreate");
+}
+
+template <typename R>
+Batch<R>::~Batch() {
+  for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  (void)hipStreamSynchronize(s0_);
+  if (s1_) (void)hipStreamSynchronize(s1_);
+  for (void* p : allocs_) (void)hipFree(p);
+  if (ev_fork_) (void)hipEventDestroy(ev_fork_);
+  if (ev_join_) (void)hipEventDestroy(ev_join_);
+  if (s1_) (void)hipStreamDestroy(s1_);
+}
+
+template <typename R>
+void Batch<R>::run(int mode, int iters) {
+  if ((mode != PM_INIT) && !pl_.sparse) throw Error(PSARA_ESTATE, "every batch member needs a wavelet prior in this mode");
+  // the members' current descriptors (scalars may have changed since the last run)
+  std::vector<ProbDesc> d(members_.size());
+  for (size_t i = 0; i < members_.size(); ++i) {
+    members_[i]->sync();
+    d[i] = members_[i]->desc();
+    hip_check(hipStreamSynchronize(members_[i]->stream()), "member sync");
+  }
+  hip_check(hipMemcpyAsync(d_descs_, d.data(), d.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, s0_), "descriptors upload");
+  hip_check(hipStreamSynchronize(s0_), "descriptors sync");
+  if (iters <= 0) return;
+  constexpr int kChunk = 8;
+  auto get_graph = [&](int count) -> hipGraphExec_t {
+    const int key = mode * 1000 + count;
+    auto it = graphs_.find(key);
+    if (it != graphs_.end()) return it->second;
+    hipGraph_t graph = nullptr;
+    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeThreadLocal), "begin capture");
+    for (int k = 0; k < count; ++k) launch_iteration_lists<R>(pl_, mode, s0_, s1_, ev_fork_, ev_join_);
+    hip_check(hipStreamEndCapture(s0_, &graph), "end capture");
+    hipGraphExec_t exec = nullptr;
+    hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(graph);
+    graphs_[key] = exec;
+    return exec;
+  };
+  int left = iters;
+  if (left >= kChunk) {
+    hipGraphExec_t g = get_graph(kChunk);
+    while (left >= kChunk) { hip_check(hipGraphLaunch(g, s0_), "graph launch"); left -= kChunk; }
+  }
+  if (left > 0) {
+    hipGraphExec_t g = get_graph(1);
+    for (; left > 0; --left) hip_check(hipGraphLaunch(g, s0_), "graph launch");
+  }
+  hip_check(hipGetLastError(), "batch iteration launch");
+}
+
+template struct Batch<float>;
+template struct Batch<double>;
 
 }  // namespace psara

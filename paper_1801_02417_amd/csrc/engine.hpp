@@ -45,17 +45,41 @@ struct Geometry {
 
 Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T);
 
+// Work lists of the passes; every item names its problem (index into the descriptor array).
+//   ana[l], syn[l]     SARA analysis / synthesis of level l for every level (non-dual uses)
+//   ana_d[l], syn_d[l] the same restricted to the levels below each problem's fused coarse level
+//   coarse             {prob, wavelet, Stokes channel, first coarse level}
 struct ItemSet {
   std::vector<int4> img, rows, cols, p6, p7, dirac, synfinal, coarse;
   std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
+  std::vector<int4> ana_d[kMaxLevels + 1], syn_d[kMaxLevels + 1];
 };
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int* n_p6);
-void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int* n_ana_parts);
+void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int c_level, int* n_ana_parts);
 
 struct DevItems {
   int4* ptr = nullptr;
   int count = 0;
 };
+
+// The device work lists and launch shapes of one set of problems (one solve, or a batch of
+// solves that share a precision and a tap count) that the iteration's pass sequence runs on.
+struct PassLists {
+  const ProbDesc* descs = nullptr;
+  DevItems img, rows, cols, p6, p7, synfinal, coarse;
+  DevItems ana_d[kMaxLevels + 1], syn_d[kMaxLevels + 1];
+  int cells = 512, rcells = 512;   // FFT cells per workgroup of the column / row passes
+  int max_ts = 16, taps = 8, max_levels = 0;
+  bool sparse = false;             // every problem has a wavelet prior (P2/P3 run)
+};
+
+// One Algorithm-1 iteration of every problem in L: P1+P4, then P2/P3 on s1 concurrently with
+// P5..P9 on s0 (joined back into s0).
+template <typename R>
+void launch_iteration_lists(const PassLists& L, int mode, hipStream_t s0, hipStream_t s1, hipEvent_t fork,
+                            hipEvent_t join);
+template <typename R>
+void launch_sara_dual(const PassLists& L, hipStream_t s);   // P2 + P3 with the fused coarse levels
 
 template <typename R>
 struct Engine {
@@ -86,6 +110,10 @@ struct Engine {
   size_t device_bytes() const { return bytes_; }
   const ProbDesc& desc() const { return h_; }
   hipStream_t stream() const { return s0_; }
+  const Geometry& geometry() const { return geo_; }
+  int c_level() const { return c_level_; }
+  bool has_prior() const { return h_.coef[COEF_A] != nullptr && h_.nwav > 0; }
+  void sync() { sync_desc(); }
 
   // passes (stream 0 by default)
   void p1(int mode, hipStream_t s = nullptr);
@@ -132,12 +160,39 @@ struct Engine {
   DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_dirac_, d_synfinal_, d_coarse_;
   int c_level_ = 1 << 20;     // first level handled by the fused coarse kernel (> levels: none)
   DevItems d_ana_[kMaxLevels + 1], d_syn_[kMaxLevels + 1];
+  DevItems d_ana_d_[kMaxLevels + 1], d_syn_d_[kMaxLevels + 1];
+  PassLists pl_;
   int cells_ = 512;     // FFT cells per workgroup of the column passes
   int rcells_ = 2048;   // ... and of the row passes (several image rows per workgroup)
   int gen_parts_ = 1, ana_parts_ = 0;
   size_t coef_elems_ = 0;
   size_t bytes_ = 0;
   std::vector<void*> allocs_;
+  std::map<int, hipGraphExec_t> graphs_;
+};
+
+// Several solves advanced together: one launch per pass covers every member (their work lists
+// concatenated, each item naming its member's descriptor), so small problems fill the GPU
+// together and the launch latency is paid once per batch.  Members keep their own device state;
+// they must share the precision R and the tap count, and every member needs a wavelet prior for
+// the modes with the sparsity term.  Not re-entrant; the members must not run meanwhile.
+template <typename R>
+struct Batch {
+  Batch(const std::vector<Engine<R>*>& members, hipStream_t stream);
+  ~Batch();
+  Batch(const Batch&) = delete;
+  Batch& operator=(const Batch&) = delete;
+  void run(int mode, int iters);       // graph replay; returns with the work queued on stream()
+  hipStream_t stream() const { return s0_; }
+  int size() const { return (int)members_.size(); }
+
+ private:
+  std::vector<Engine<R>*> members_;
+  hipStream_t s0_ = nullptr, s1_ = nullptr;
+  hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+  ProbDesc* d_descs_ = nullptr;
+  std::vector<void*> allocs_;
+  PassLists pl_;
   std::map<int, hipGraphExec_t> graphs_;
 };
 

@@ -417,7 +417,7 @@ synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restric
 // Mallat pyramid of the coarse levels; synthesis then runs back from level L to level c on
 // the updated duals and leaves the low-low band of level c-1 in the level scratch, where the
 // next synthesis launch reads it.  Replaces 2 (L - c + 1) small launches by one.
-// items: {prob, wavelet index, Stokes channel, -}
+// items: {prob, wavelet index, Stokes channel, first coarse level c}
 template <typename R> struct CoarseMax { static constexpr int value = sizeof(R) == 4 ? 64 : 32; };
 
 template <typename R>
@@ -527,12 +527,12 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
 
 template <typename R>
 __global__ void __launch_bounds__(512)
-coarse_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int c_level) {
+coarse_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items) {
   constexpr int MM = CoarseMax<R>::value;
   __shared__ R bufA[MM * MM], bufB[MM * MM], pyr[MM * MM];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
-#define PSARA_COARSE(FF) coarse_body<FF, R>(P, it.y, it.z, c_level, bufA, bufB, pyr)
+#define PSARA_COARSE(FF) coarse_body<FF, R>(P, it.y, it.z, it.w, bufA, bufB, pyr)
   PSARA_FILTER_SWITCH(P.wav_len[it.y], PSARA_COARSE)
 #undef PSARA_COARSE
 }
@@ -546,9 +546,9 @@ int coarse_level(int n, int levels) {
 }
 
 template <typename R>
-void launch_coarse(const LaunchArgs& a, int c_level) {
+void launch_coarse(const LaunchArgs& a) {
   if (a.nitems <= 0) return;
-  hipLaunchKernelGGL((coarse_kernel<R>), dim3(a.nitems), dim3(512), 0, a.stream, a.descs, a.items, c_level);
+  hipLaunchKernelGGL((coarse_kernel<R>), dim3(a.nitems), dim3(512), 0, a.stream, a.descs, a.items);
 }
 
 template <typename R>
@@ -596,8 +596,8 @@ template void launch_dirac<double>(int, const LaunchArgs&, int, int);
 template void launch_synthesis<float>(int, int, const LaunchArgs&, int, int);
 template void launch_synthesis<double>(int, int, const LaunchArgs&, int, int);
 template void launch_synthesis_final<float>(const LaunchArgs&, int, int, int);
-template void launch_coarse<float>(const LaunchArgs&, int);
-template void launch_coarse<double>(const LaunchArgs&, int);
+template void launch_coarse<float>(const LaunchArgs&);
+template void launch_coarse<double>(const LaunchArgs&);
 template int coarse_level<float>(int, int);
 template int coarse_level<double>(int, int);
 template void launch_synthesis_final<double>(const LaunchArgs&, int, int, int);

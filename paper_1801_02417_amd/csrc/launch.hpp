@@ -35,7 +35,7 @@ template <typename R> void launch_analysis(int mode, int level, const LaunchArgs
 template <typename R> void launch_dirac(int mode, const LaunchArgs& a, int src_slot, int out_slot);
 template <typename R> void launch_synthesis(int level, int coarsest, const LaunchArgs& a, int src_coef, int dst_slot);
 template <typename R> void launch_synthesis_final(const LaunchArgs& a, int src_coef, int dst_slot, int add_dirac);
-template <typename R> void launch_coarse(const LaunchArgs& a, int c_level);
+template <typename R> void launch_coarse(const LaunchArgs& a);
 template <typename R> int coarse_level(int n, int levels);
 
 // reductions and small utility kernels (items: {prob, block, -, -})

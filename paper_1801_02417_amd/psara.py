@@ -31,6 +31,7 @@ EXPORTS = (
     "psara_get_state", "psara_set_state", "psara_reset_state", "psara_footprint", "psara_apply_phi",
     "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
     "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_profile_passes",
+    "psara_batch_solve", "psara_batch_reweighted_solve",
 )
 
 
@@ -94,6 +95,9 @@ def lib() -> C.CDLL:
         "psara_kb_deapod": (C.c_double, [I, C.c_double, C.c_double]),
         "psara_layout": (I, [P, C.POINTER(C.c_int64)]),
         "psara_profile_passes": (I, [P, I, I, D]),
+        "psara_batch_solve": (I, [C.POINTER(P), I, I, I, C.POINTER(PsaraReport)]),
+        "psara_batch_reweighted_solve": (I, [C.POINTER(P), I, I, I, C.POINTER(C.c_int), C.c_double,
+                                             C.POINTER(PsaraReport)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -295,6 +299,33 @@ def psara_profile_passes(ctx, mode: int, iters: int) -> np.ndarray:
     return out
 
 
+def _ctx_array(ctxs):
+    arr = (C.c_void_p * len(ctxs))(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    return arr
+
+
+def _batch_check(ctxs, status: int):
+    if status != PSARA_OK:
+        raise PsaraError(status, lib().psara_last_error(ctxs[0]).decode() if ctxs else "empty batch")
+
+
+def psara_batch_solve(ctxs, mode: int, iters: int, report: bool = True):
+    """One batched stage over several contexts; returns one report per context (or None)."""
+    reps = (PsaraReport * len(ctxs))()
+    st = lib().psara_batch_solve(_ctx_array(ctxs), len(ctxs), mode, iters, reps if report else None)
+    _batch_check(ctxs, st)
+    return [r.as_dict() for r in reps] if report else None
+
+
+def psara_batch_reweighted_solve(ctxs, mode: int, iters_per_stage: Sequence[int], delta_decay: float = 10.0):
+    arr = (C.c_int * len(iters_per_stage))(*[int(v) for v in iters_per_stage])
+    reps = (PsaraReport * len(ctxs))()
+    st = lib().psara_batch_reweighted_solve(_ctx_array(ctxs), len(ctxs), mode, len(iters_per_stage) - 1, arr,
+                                            delta_decay, reps)
+    _batch_check(ctxs, st)
+    return [r.as_dict() for r in reps]
+
+
 # ---- convenience wrapper ------------------------------------------------------------------------
 def step_sizes(phi_norm_sq: float, margin: float = 0.99):
     """rho1 = rho3 = 1, rho2 = 1/||phi||^2, tau = margin/(rho1 + rho2||phi||^2 + rho3) (||Psi|| = 1)."""
@@ -393,3 +424,11 @@ class Solver:
 
     def profile_passes(self, mode: int, iters: int) -> np.ndarray:
         return psara_profile_passes(self.ctx, mode, iters)
+
+
+def batch_solve(solvers: Sequence[Solver], mode: int, iters: int, report: bool = True):
+    return psara_batch_solve([s.ctx for s in solvers], mode, iters, report)
+
+
+def batch_reweighted_solve(solvers: Sequence[Solver], mode: int, iters_per_stage, delta_decay: float = 10.0):
+    return psara_batch_reweighted_solve([s.ctx for s in solvers], mode, iters_per_stage, delta_decay)

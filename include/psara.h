@@ -146,6 +146,14 @@ psara_status psara_reweighted_solve(psara_ctx* ctx, psara_mode mode, int cycles,
 /* Evaluate the stopping quantities for the current state. */
 psara_status psara_report_now(psara_ctx* ctx, psara_report* out);
 
+/* The data-driven regularisation weight gamma = factor * ||Psi^dagger Re phi^dagger Y||_inf /
+ * ||phi||^2 (the choice of gamma used with the paper's setting, factor 1e-3), computed on the
+ * device.  Requires operator, data, prior and psara_opnorm.  Does not change the context. */
+psara_status psara_data_gamma(psara_ctx* ctx, double factor, double* gamma);
+
+/* Replace gamma in the thresholds gamma W of the prior (W unchanged); gamma > 0. */
+psara_status psara_set_gamma(psara_ctx* ctx, double gamma);
+
 /* ---- batches of independent solves ------------------------------------------------------- */
 
 /* Advance `count` independent solves together: every pass of Algorithm 1 is one launch over
@@ -221,6 +229,72 @@ int psara_layout(const psara_ctx* ctx, int64_t* perm);
  * [7] column inverse FFT (P8, which also sums the partial tiles of split gridding tiles),
  * [8] row inverse FFT + crop (P9).  The iterations really run (the state advances). */
 psara_status psara_profile_passes(psara_ctx* ctx, psara_mode mode, int iters, double* ms_per_pass);
+
+/* ---- request server ---------------------------------------------------------------------- */
+
+/* A server owns one GPU and solves submitted problems (Algorithm 2, each request with its own
+ * operator, data and stage list) with continuous batching: requests are admitted while the sum
+ * of their psara_footprint stays within the HBM budget (a request larger than the budget runs
+ * when nothing else does; nothing is rejected for size), set up by host threads while the GPU
+ * works, and every admitted request advances in one batched launch per pass (grouped by
+ * stage mode, precision and tap count) in rounds of at most `quantum` iterations; a request
+ * leaves the batch at each stage end for its reweighting and rejoins.  Policy
+ * PSARA_SERVE_FIFO instead runs one request at a time in arrival order.  Each result equals
+ * the same request solved alone with psara_* calls in the order the server uses (operator,
+ * data, prior with gamma 1, opnorm, data gamma, steps 0.99/3, 1, 1/||phi||^2, 1, then
+ * psara_reweighted_solve).  Thread-safe for submit and poll. */
+typedef struct psara_server psara_server;
+
+typedef enum { PSARA_SERVE_BATCHED = 0, PSARA_SERVE_FIFO = 1 } psara_serve_policy;
+
+typedef struct {
+  int n;                       /* image side (power of two, 8..1024) */
+  int64_t M;                   /* visibility rows */
+  const double* uv;            /* M x 2, rad/pixel in [-pi, pi)             (copied) */
+  const double* Y;             /* M x 4 complex, interleaved, brightness order (copied) */
+  double epsilon;              /* l2-ball radius, > 0 */
+  int taps;                    /* 4, 6 or 8 */
+  int levels;                  /* wavelet levels */
+  uint32_t basis_mask;         /* bit 0 Dirac, bits 1..8 Db1..Db8 */
+  psara_precision precision;
+  psara_mode mode;             /* mode of the reweighted stages */
+  int cycles;                  /* reweighting cycles; stages = cycles + 1 */
+  const int* iters_per_stage;  /* cycles + 1 counts (copied) */
+  double delta_decay;          /* > 1 */
+  double gamma_factor;         /* gamma = gamma_factor ||Psi^dagger Re phi^dagger Y||_inf / ||phi||^2 */
+  int opnorm_iters;            /* power-iteration limit and relative tolerance */
+  double opnorm_rtol;
+} psara_request;
+
+typedef enum { PSARA_REQ_QUEUED = 0, PSARA_REQ_RUNNING = 1, PSARA_REQ_DONE = 2, PSARA_REQ_FAILED = 3 } psara_req_state;
+
+typedef struct {
+  int state;                   /* psara_req_state */
+  psara_status status;         /* error of a failed request */
+  double t_submit, t_start, t_done;   /* seconds on the server clock: submitted, set-up begun, result ready */
+  int n;
+  psara_report report;         /* final report of a finished request */
+} psara_result;
+
+/* device: GPU ordinal; hbm_budget: bytes of device memory the admitted requests may hold;
+ * max_slots >= 1: most requests in flight; quantum >= 1: iterations per batched round. */
+psara_status psara_server_create(psara_server** out, int device, size_t hbm_budget, int max_slots,
+                                 int quantum, psara_serve_policy policy);
+/* Queue a request (its arrays are copied before return); ticket receives its id. */
+psara_status psara_server_submit(psara_server* srv, const psara_request* req, uint64_t* ticket);
+/* State of a request.  When it is done and `image` is not NULL, the image (n*n x 4 doubles,
+ * Stokes I, Q, U, V) is copied there and the request is forgotten (a later poll of the ticket
+ * returns PSARA_EINVAL); a failed request is forgotten on the first poll that reports it. */
+psara_status psara_server_poll(psara_server* srv, uint64_t ticket, psara_result* out, double* image);
+/* Block until every submitted request is done or failed. */
+psara_status psara_server_drain(psara_server* srv);
+/* Seconds since the server was created (the clock of psara_result). */
+double psara_server_clock(const psara_server* srv);
+/* Message of the last failed request or call. */
+const char* psara_server_last_error(const psara_server* srv);
+/* Stops the threads after the running round and frees every context (pending requests are
+ * dropped). */
+void psara_server_destroy(psara_server* srv);
 
 #ifdef __cplusplus
 }

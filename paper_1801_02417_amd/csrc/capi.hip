@@ -9,28 +9,13 @@
 #include <string>
 #include <vector>
 
+#include "ctx.hpp"
 #include "engine.hpp"
 #include "psara.h"
 
 using psara::Engine;
 using psara::Error;
 
-struct psara_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::string err;
-  psara::Geometry geo;
-  bool op_set = false, data_set = false, prior_set = false, steps_set = false, norm_set = false;
-  psara_precision prec = PSARA_FP32_MIXED;
-  std::unique_ptr<Engine<float>> f32;
-  std::unique_ptr<Engine<double>> f64;
-  double eps = 0.0, gamma = 0.0, phi_norm_sq = 0.0;
-  double tau = 0.0, rho1 = 0.0, rho2 = 0.0, rho3 = 0.0;
-  uint32_t mask = 0;
-  int levels = 0;
-  int64_t iterations = 0;
-};
 
 namespace {
 
@@ -365,6 +350,26 @@ psara_status psara_reweighted_solve(psara_ctx* c, psara_mode mode, int cycles, c
       with_engine(c, [&](auto& e) { e.report(out); });
       out->iterations = c->iterations;
     }
+  });
+}
+
+psara_status psara_data_gamma(psara_ctx* c, double factor, double* gamma) {
+  return guard(c, [&] {
+    require(c->op_set && c->data_set && c->prior_set, PSARA_ESTATE, "operator, data and prior must be set");
+    require(c->norm_set, PSARA_ESTATE, "run psara_opnorm first");
+    require(gamma != nullptr && std::isfinite(factor) && factor > 0.0, PSARA_EINVAL, "bad arguments");
+    double m = 0.0;
+    with_engine(c, [&](auto& e) { m = e.data_max_coef(); });
+    *gamma = factor * m / c->phi_norm_sq;
+  });
+}
+
+psara_status psara_set_gamma(psara_ctx* c, double gamma) {
+  return guard(c, [&] {
+    require(c->prior_set, PSARA_ESTATE, "prior not set");
+    require(std::isfinite(gamma) && gamma > 0.0, PSARA_EINVAL, "gamma must be > 0");
+    with_engine(c, [&](auto& e) { e.set_gamma(gamma); });
+    c->gamma = gamma;
   });
 }
 

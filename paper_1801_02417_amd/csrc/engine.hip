@@ -26,6 +26,14 @@ void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(PSARA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Host <-> device copy ordered on `stream` and waited for.  Never the legacy default stream:
+// a synchronous hipMemcpy there would have to wait for every blocking stream, which breaks a
+// graph capture that another thread (the request server) may have in progress.
+static void copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t stream, const char* what) {
+  hip_check(hipMemcpyAsync(dst, src, bytes, kind, stream), what);
+  hip_check(hipStreamSynchronize(stream), what);
+}
+
 // ------------------------------------------------------------------------------------------------
 // geometry: window starts, fractional offsets, sorting by grid tile, per-tile lists
 Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
@@ -287,7 +295,7 @@ template <typename R>
 template <typename T>
 T* Engine<R>::upload(const T* host, size_t count) {
   T* d = dalloc<T>(count);
-  hip_check(hipMemcpy(d, host, count * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+  copy_sync(d, host, count * sizeof(T), hipMemcpyHostToDevice, s0_, "hipMemcpy H2D");
   return d;
 }
 
@@ -379,7 +387,7 @@ void Engine<R>::set_data(const double* Y_sorted, double eps) {
   const int64_t M = geo_.M;
   std::vector<R> tmp((size_t)M * 8);
   for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (R)Y_sorted[i];
-  hip_check(hipMemcpy(h_.vis[VIS_Y], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice), "Y upload");
+  copy_sync(h_.vis[VIS_Y], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice, s0_, "Y upload");
   h_.eps = eps;
   desc_dirty_ = true;
 }
@@ -424,7 +432,7 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   // thresholds gamma * W
   std::vector<R> gw(coef_elems_ * 4);
   for (size_t i = 0; i < gw.size(); ++i) gw[i] = (R)(gamma * (weights ? weights[i] : 1.0));
-  hip_check(hipMemcpy(h_.coef[COEF_GW], gw.data(), gw.size() * sizeof(R), hipMemcpyHostToDevice), "weights upload");
+  copy_sync(h_.coef[COEF_GW], gw.data(), gw.size() * sizeof(R), hipMemcpyHostToDevice, s0_, "weights upload");
   zero(h_.coef[COEF_A], coef_elems_ * sizeof(V4<R>));
   int nap = 0;
   c_level_ = coarse_level<R>(n, levels);
@@ -548,7 +556,7 @@ void Engine<R>::run(int mode, int iters) {
     auto it = graphs_.find(key);
     if (it != graphs_.end()) return it->second;
     hipGraph_t graph = nullptr;
-    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeThreadLocal), "begin capture");
+    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
     for (int k = 0; k < count; ++k) launch_iteration(mode);
     hip_check(hipStreamEndCapture(s0_, &graph), "end capture");
     hipGraphExec_t exec = nullptr;
@@ -645,6 +653,28 @@ double Engine<R>::coef_std() {
 }
 
 template <typename R>
+double Engine<R>::data_max_coef() {
+  sync_desc();
+  adjoint(VIS_Y, 0, IMG_TMP);
+  if (h_.has_dirac) launch_dirac<R>(AM_MAXABS, la(d_dirac_), IMG_TMP, 0);
+  for (int l = 1; l <= h_.levels; ++l) launch_analysis<R>(AM_MAXABS, l, la(d_ana_[l]), IMG_TMP, 0);
+  launch_finalize_max(d_desc_, 1, 0, ana_parts_, SC_DOT, s0_);
+  hip_check(hipGetLastError(), "max-coefficient launch");
+  double sc[NUM_SCALARS];
+  read_scalars(sc);
+  return sc[SC_DOT];
+}
+
+template <typename R>
+void Engine<R>::set_gamma(double gamma) {
+  launch_scale<R>(h_.coef[COEF_GW], coef_elems_ * 4, gamma / h_.gamma, s0_);
+  hip_check(hipGetLastError(), "threshold scale");
+  hip_check(hipStreamSynchronize(s0_), "threshold scale sync");
+  h_.gamma = gamma;
+  desc_dirty_ = true;
+}
+
+template <typename R>
 void Engine<R>::reweight(double delta) {
   h_.delta = delta;
   desc_dirty_ = true;
@@ -664,7 +694,7 @@ double Engine<R>::opnorm(int max_iter, double rtol, int* iters_out) {
   std::normal_distribution<double> nd(0.0, 1.0);
   std::vector<R> x0(N * 4);
   for (auto& v : x0) v = (R)nd(rng);
-  hip_check(hipMemcpy(h_.img[IMG_TMP2], x0.data(), x0.size() * sizeof(R), hipMemcpyHostToDevice), "x0 upload");
+  copy_sync(h_.img[IMG_TMP2], x0.data(), x0.size() * sizeof(R), hipMemcpyHostToDevice, s0_, "x0 upload");
   const int nimg = d_img_.count;
   launch_img_dot<R>(la(d_img_), IMG_TMP2, IMG_TMP2);
   finalize(1, nimg, SC_NRM2);
@@ -695,27 +725,27 @@ void Engine<R>::put_img(int slot, const double* src, int comps) {
   const size_t cnt = (size_t)geo_.n * geo_.n * comps;
   std::vector<R> tmp(cnt);
   for (size_t i = 0; i < cnt; ++i) tmp[i] = (R)src[i];
-  hip_check(hipMemcpy(h_.img[slot], tmp.data(), cnt * sizeof(R), hipMemcpyHostToDevice), "image upload");
+  copy_sync(h_.img[slot], tmp.data(), cnt * sizeof(R), hipMemcpyHostToDevice, s0_, "image upload");
 }
 template <typename R>
 void Engine<R>::get_img(int slot, double* dst, int comps) {
   hip_check(hipStreamSynchronize(s0_), "sync");
   const size_t cnt = (size_t)geo_.n * geo_.n * comps;
   std::vector<R> tmp(cnt);
-  hip_check(hipMemcpy(tmp.data(), h_.img[slot], cnt * sizeof(R), hipMemcpyDeviceToHost), "image download");
+  copy_sync(tmp.data(), h_.img[slot], cnt * sizeof(R), hipMemcpyDeviceToHost, s0_, "image download");
   for (size_t i = 0; i < cnt; ++i) dst[i] = (double)tmp[i];
 }
 template <typename R>
 void Engine<R>::put_coef(int slot, const double* src) {
   std::vector<R> tmp(coef_elems_ * 4);
   for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (R)src[i];
-  hip_check(hipMemcpy(h_.coef[slot], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice), "coef upload");
+  copy_sync(h_.coef[slot], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice, s0_, "coef upload");
 }
 template <typename R>
 void Engine<R>::get_coef(int slot, double* dst) {
   hip_check(hipStreamSynchronize(s0_), "sync");
   std::vector<R> tmp(coef_elems_ * 4);
-  hip_check(hipMemcpy(tmp.data(), h_.coef[slot], tmp.size() * sizeof(R), hipMemcpyDeviceToHost), "coef download");
+  copy_sync(tmp.data(), h_.coef[slot], tmp.size() * sizeof(R), hipMemcpyDeviceToHost, s0_, "coef download");
   for (size_t i = 0; i < tmp.size(); ++i) dst[i] = (double)tmp[i];
 }
 // visibilities: caller order <-> sorted order, optional scale
@@ -727,14 +757,14 @@ void Engine<R>::put_vis(int slot, const double* src) {
     const double* s = src + 8 * geo_.perm[p];
     for (int k = 0; k < 8; ++k) tmp[8 * p + k] = (R)s[k];
   }
-  hip_check(hipMemcpy(h_.vis[slot], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice), "vis upload");
+  copy_sync(h_.vis[slot], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice, s0_, "vis upload");
 }
 template <typename R>
 void Engine<R>::get_vis(int slot, double* dst, double scale) {
   hip_check(hipStreamSynchronize(s0_), "sync");
   const int64_t M = geo_.M;
   std::vector<R> tmp((size_t)M * 8);
-  hip_check(hipMemcpy(tmp.data(), h_.vis[slot], tmp.size() * sizeof(R), hipMemcpyDeviceToHost), "vis download");
+  copy_sync(tmp.data(), h_.vis[slot], tmp.size() * sizeof(R), hipMemcpyDeviceToHost, s0_, "vis download");
   for (int64_t p = 0; p < M; ++p) {
     double* d = dst + 8 * geo_.perm[p];
     for (int k = 0; k < 8; ++k) d[k] = scale * (double)tmp[8 * p + k];
@@ -890,7 +920,7 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
       throw Error(PSARA_ENOMEM, "batch work-list allocation failed");
     }
     allocs_.push_back(p);
-    hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(int4), hipMemcpyHostToDevice), "work-list upload");
+    copy_sync(p, v.data(), v.size() * sizeof(int4), hipMemcpyHostToDevice, s0_, "work-list upload");
     d.ptr = (int4*)p;
   };
   up(pl_.img, S.img); up(pl_.rows, xcd_contiguous(S.rows)); up(pl_.cols, S.cols);
@@ -943,7 +973,7 @@ void Batch<R>::run(int mode, int iters) {
     auto it = graphs_.find(key);
     if (it != graphs_.end()) return it->second;
     hipGraph_t graph = nullptr;
-    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeThreadLocal), "begin capture");
+    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
     for (int k = 0; k < count; ++k) launch_iteration_lists<R>(pl_, mode, s0_, s1_, ev_fork_, ev_join_);
     hip_check(hipStreamEndCapture(s0_, &graph), "end capture");
     hipGraphExec_t exec = nullptr;

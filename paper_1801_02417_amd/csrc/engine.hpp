@@ -96,6 +96,8 @@ struct Engine {
   void run_eager(int mode, int iters);    // direct launches
   void report(psara_report* r);
   double coef_std();
+  double data_max_coef();              // max |Psi^dagger Re phi^dagger Y|
+  void set_gamma(double gamma);        // rescale the thresholds gamma W to a new gamma
   void reweight(double delta);
   double opnorm(int max_iter, double rtol, int* iters_out);
   void apply_phi(const double* S, double* Y);

@@ -14,6 +14,7 @@
 //   AM_REWEIGHT  gW = gamma delta / (delta + |c|)    (eq. weights)
 //   AM_OBJECTIVE partial sums of gW |c|               (weighted l1 norm, / gamma on the host)
 //   AM_MOMENTS   partial sums of c and c^2
+//   AM_MAXABS    partial maxima of |c|                 (the data-driven gamma)
 // with c the normalised coefficient.  Intermediate low-low bands go to a per-basis
 // scratch array.  Synthesis mirrors this from the coarsest level down; its last level sums
 // every wavelet basis of a tile in registers and writes the image once.  The Dirac part of
@@ -92,10 +93,22 @@ __device__ inline void apply_coef(const ProbDesc& P, int out_coef, size_t idx, V
     k1.add((double)gw.y * fabs((double)c.y));
     k1.add((double)gw.z * fabs((double)c.z));
     k1.add((double)gw.w * fabs((double)c.w));
+  } else if (MODE == AM_MAXABS) {
+    k1.s = fmax(k1.s, (double)fmax(fmax(fabs(c.x), fabs(c.y)), fmax(fabs(c.z), fabs(c.w))));
   } else {
     k1.add((double)c.x); k1.add((double)c.y); k1.add((double)c.z); k1.add((double)c.w);
     k2.add((double)c.x * c.x); k2.add((double)c.y * c.y); k2.add((double)c.z * c.z); k2.add((double)c.w * c.w);
   }
+}
+
+__device__ inline double block_max(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) r = fmax(r, red[w]);
+  return r;
 }
 
 // the dual update clip(A + rho1 c, -gW, gW) on prefetched A and gW
@@ -111,6 +124,11 @@ __device__ inline V4<R> dual_clip(V4<R> a, const V4<R>& gw, const V4<R>& raw, R 
 template <typename R>
 __device__ inline void write_partials(const ProbDesc& P, int part, const KSum& k1, const KSum& k2, int two, double* red) {
   double* gen = P.partials + 2 * (size_t)P.n_p6;
+  if (two < 0) {                                   // maximum
+    const double m = block_max(k1.s, red);
+    if (threadIdx.x == 0) { gen[2 * part] = m; gen[2 * part + 1] = 0.0; }
+    return;
+  }
   const KSum t1 = block_reduce(k1, red);
   if (threadIdx.x == 0) { gen[2 * part] = t1.s; gen[2 * part + 1] = t1.c; }
   if (two) {
@@ -221,7 +239,8 @@ analysis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
 #define PSARA_ANA(FF) analysis_body<R, MODE, FF>(P, sm, w, level, it.z, src_slot, out_coef, k1, k2)
   PSARA_FILTER_SWITCH(P.wav_len[w], PSARA_ANA)
 #undef PSARA_ANA
-  if (MODE == AM_OBJECTIVE || MODE == AM_MOMENTS) write_partials<R>(P, it.w, k1, k2, MODE == AM_MOMENTS, red);
+  if (MODE == AM_OBJECTIVE || MODE == AM_MOMENTS || MODE == AM_MAXABS)
+    write_partials<R>(P, it.w, k1, k2, MODE == AM_MAXABS ? -1 : MODE == AM_MOMENTS, red);
 }
 
 // Dirac block for the non-dual modes.  items: {prob, block of 256 pixels, -, partial index}
@@ -235,7 +254,8 @@ dirac_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items,
   const int p = it.y * 256 + threadIdx.x;
   KSum k1, k2;
   if (p < N) apply_coef<R, MODE>(P, out_coef, (size_t)p, ((const V4<R>*)P.img[src_slot])[p], k1, k2);
-  if (MODE == AM_OBJECTIVE || MODE == AM_MOMENTS) write_partials<R>(P, it.w, k1, k2, MODE == AM_MOMENTS, red);
+  if (MODE == AM_OBJECTIVE || MODE == AM_MOMENTS || MODE == AM_MAXABS)
+    write_partials<R>(P, it.w, k1, k2, MODE == AM_MAXABS ? -1 : MODE == AM_MOMENTS, red);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -560,6 +580,7 @@ void launch_analysis(int mode, int level, const LaunchArgs& a, int src_slot, int
     case AM_STORE: hipLaunchKernelGGL((analysis_kernel<R, AM_STORE>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
     case AM_REWEIGHT: hipLaunchKernelGGL((analysis_kernel<R, AM_REWEIGHT>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
     case AM_OBJECTIVE: hipLaunchKernelGGL((analysis_kernel<R, AM_OBJECTIVE>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
+    case AM_MAXABS: hipLaunchKernelGGL((analysis_kernel<R, AM_MAXABS>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
     default: hipLaunchKernelGGL((analysis_kernel<R, AM_MOMENTS>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
   }
 }
@@ -573,6 +594,7 @@ void launch_dirac(int mode, const LaunchArgs& a, int src_slot, int out_coef) {
     case AM_REWEIGHT: hipLaunchKernelGGL((dirac_kernel<R, AM_REWEIGHT>), g, b, 0, a.stream, a.descs, a.items, src_slot, out_coef); break;
     case AM_OBJECTIVE: hipLaunchKernelGGL((dirac_kernel<R, AM_OBJECTIVE>), g, b, 0, a.stream, a.descs, a.items, src_slot, out_coef); break;
     case AM_MOMENTS: hipLaunchKernelGGL((dirac_kernel<R, AM_MOMENTS>), g, b, 0, a.stream, a.descs, a.items, src_slot, out_coef); break;
+    case AM_MAXABS: hipLaunchKernelGGL((dirac_kernel<R, AM_MAXABS>), g, b, 0, a.stream, a.descs, a.items, src_slot, out_coef); break;
     default: hipLaunchKernelGGL((dirac_kernel<R, AM_DUAL>), g, b, 0, a.stream, a.descs, a.items, src_slot, out_coef); break;
   }
 }

@@ -1,5 +1,7 @@
 // Pointwise steps of Algorithm 1 (the per-pixel body is in primal.hpp) and the FP64
 // reductions of the stopping quantities.
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 #include "primal.hpp"
@@ -138,6 +140,29 @@ __global__ void __launch_bounds__(256) finalize_kernel(const ProbDesc* __restric
   if (threadIdx.x == 0) P.scal[scalar] = v;
 }
 
+// One workgroup per problem: scal[scalar] = max of the first entries of `count` pairs of region q.
+__global__ void __launch_bounds__(256) finalize_max_kernel(const ProbDesc* __restrict__ descs, int q, int count, int scalar) {
+  __shared__ double red[8];
+  const ProbDesc& P = descs[blockIdx.x];
+  const double* src = gen_part(P, q);
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) v = fmax(v, src[2 * i]);
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    P.scal[scalar] = r;
+  }
+}
+
+template <typename R>
+__global__ void scale_kernel(R* p, size_t count, R factor) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    p[i] *= factor;
+}
+
 // zeta = 3 rms of the Stokes-I residual image scaled by 1/(2M)
 __global__ void finalize_zeta_kernel(const ProbDesc* __restrict__ descs) {
   const ProbDesc& P = descs[blockIdx.x];
@@ -170,6 +195,13 @@ template <typename R> void launch_fill(void* p, size_t count, hipStream_t s) {
 void launch_finalize(const ProbDesc* descs, int nprob, int q, int count, int scalar, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(nprob), dim3(256), 0, s, descs, q, count, scalar);
 }
+void launch_finalize_max(const ProbDesc* descs, int nprob, int q, int count, int scalar, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_max_kernel, dim3(nprob), dim3(256), 0, s, descs, q, count, scalar);
+}
+template <typename R> void launch_scale(void* p, size_t count, double factor, hipStream_t s) {
+  const size_t blocks = std::min<size_t>((count + 255) / 256, 4096);
+  if (count > 0) hipLaunchKernelGGL((scale_kernel<R>), dim3((unsigned)blocks), dim3(256), 0, s, (R*)p, count, (R)factor);
+}
 void launch_finalize_zeta(const ProbDesc* descs, int nprob, hipStream_t s) {
   hipLaunchKernelGGL(finalize_zeta_kernel, dim3(nprob), dim3(64), 0, s, descs);
 }
@@ -181,7 +213,8 @@ void launch_finalize_zeta(const ProbDesc* descs, int nprob, hipStream_t s) {
   template void launch_npcount<R>(const LaunchArgs&);                       \
   template void launch_img_dot<R>(const LaunchArgs&, int, int);             \
   template void launch_img_scale<R>(const LaunchArgs&, int, int, int);      \
-  template void launch_fill<R>(void*, size_t, hipStream_t);
+  template void launch_fill<R>(void*, size_t, hipStream_t);                 \
+  template void launch_scale<R>(void*, size_t, double, hipStream_t);
 PSARA_INST(float)
 PSARA_INST(double)
 #undef PSARA_INST

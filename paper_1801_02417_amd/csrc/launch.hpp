@@ -18,7 +18,7 @@ struct LaunchArgs {
 // P1 modes
 enum PrimalMode { PM_CONSTRAINED = 0, PM_INIT = 1, PM_UNCONSTRAINED = 2 };
 // analysis modes
-enum AnalysisMode { AM_DUAL = 0, AM_STORE = 1, AM_REWEIGHT = 2, AM_OBJECTIVE = 3, AM_MOMENTS = 4 };
+enum AnalysisMode { AM_DUAL = 0, AM_STORE = 1, AM_REWEIGHT = 2, AM_OBJECTIVE = 3, AM_MOMENTS = 4, AM_MAXABS = 5 };
 // de-grid modes
 enum DegridMode { DG_DUAL = 0, DG_FORWARD = 1, DG_RESIDUAL = 2 };
 // grid modes
@@ -48,5 +48,8 @@ template <typename R> void launch_fill(void* p, size_t count, hipStream_t s);
 // finalise: one workgroup per problem sums PART_GEN partials into scal[scalar]
 void launch_finalize(const ProbDesc* descs, int nprob, int region, int count, int scalar, hipStream_t s);
 void launch_finalize_zeta(const ProbDesc* descs, int nprob, hipStream_t s);
+// scal[scalar] = max of the first entries of `count` pairs of generic region q
+void launch_finalize_max(const ProbDesc* descs, int nprob, int q, int count, int scalar, hipStream_t s);
+template <typename R> void launch_scale(void* p, size_t count, double factor, hipStream_t s);
 
 }  // namespace psara

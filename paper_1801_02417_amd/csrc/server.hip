@@ -1,0 +1,435 @@
+// Request server of the C ABI (declared in include/psara.h): admission by device-memory
+// footprint, host-side set-up on helper threads, and continuous batching of the admitted
+// solves on one GPU.  A request is Algorithm 2 on its own problem; while it runs it is a member
+// of the batch of its stage's mode (the initialisation stage and the reweighted stages use
+// different primal steps), which advances in rounds of at most `quantum` iterations; after a
+// round the members that reached the end of a stage are reweighted (or finished) on their own.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "ctx.hpp"
+#include "engine.hpp"
+#include "psara.h"
+
+namespace {
+
+struct Job {
+  uint64_t ticket = 0;
+  psara_request req{};             // array pointers are not used after the copy
+  std::vector<double> uv, Y;
+  std::vector<int> stages;
+  size_t foot = 0;
+  // progress, owned by the thread that holds the job
+  psara_ctx* ctx = nullptr;
+  int stage = 0, left = 0;
+  double delta = 0.0;
+  // result, guarded by the server mutex
+  int state = PSARA_REQ_QUEUED;
+  psara_status status = PSARA_OK;
+  double t_submit = 0.0, t_start = 0.0, t_done = 0.0;
+  psara_report report{};
+  std::vector<double> image;
+};
+using JobP = std::shared_ptr<Job>;
+
+int stage_mode(const Job& j) {
+  if (j.stage == 0) return psara::PM_INIT;
+  return j.req.mode == PSARA_UNCONSTRAINED ? psara::PM_UNCONSTRAINED : psara::PM_CONSTRAINED;
+}
+
+}  // namespace
+
+struct psara_server {
+  int device = 0;
+  size_t budget = 0;
+  int max_slots = 1, quantum = 1;
+  psara_serve_policy policy = PSARA_SERVE_BATCHED;
+  std::chrono::steady_clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  size_t used = 0;            // footprint of the admitted, unfinished requests
+  int in_flight = 0;          // admitted, unfinished
+  std::deque<JobP> queue;     // submitted, not yet admitted
+  std::deque<JobP> ready;     // set up, waiting to join the batch
+  std::map<uint64_t, JobP> jobs;
+  std::string err;
+  std::vector<std::thread> setup_threads;
+  std::thread worker;
+
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+  bool can_admit() const {
+    if (queue.empty() || in_flight >= max_slots) return false;
+    return used + queue.front()->foot <= budget || in_flight == 0;
+  }
+};
+
+namespace {
+
+// Releases a finished or failed job's context and books the result (mutex held by the caller).
+void retire(psara_server* S, Job& j, int state, psara_status st, const std::string& msg) {
+  j.state = state;
+  j.status = st;
+  j.t_done = S->now();
+  if (st != PSARA_OK) {
+    S->err = "request " + std::to_string(j.ticket) + ": " + msg;
+    std::fprintf(stderr, "psara server: %s\n", S->err.c_str());
+  }
+  S->used -= j.foot;
+  S->in_flight -= 1;
+}
+
+// Creates and prepares the context of a request; returns the failing status (0 on success).
+psara_status prepare(psara_server* S, Job& j, std::string& msg) {
+  psara_ctx* c = nullptr;
+  psara_status st = psara_create(&c, S->device, nullptr);
+  if (st != PSARA_OK) { msg = "context creation failed"; return st; }
+  auto fail = [&](psara_status s) {
+    msg = psara_last_error(c);
+    psara_destroy(c);
+    return s;
+  };
+  const psara_request& r = j.req;
+  if ((st = psara_set_operator(c, r.n, r.M, j.uv.data(), 2, r.taps, r.precision)) != PSARA_OK) return fail(st);
+  if ((st = psara_set_data(c, j.Y.data(), r.epsilon)) != PSARA_OK) return fail(st);
+  if ((st = psara_set_prior(c, r.basis_mask, r.levels, nullptr, 1.0)) != PSARA_OK) return fail(st);
+  double nrm = 0.0, g = 0.0;
+  if ((st = psara_opnorm(c, r.opnorm_iters, r.opnorm_rtol, &nrm)) != PSARA_OK) return fail(st);
+  if ((st = psara_data_gamma(c, r.gamma_factor, &g)) != PSARA_OK) return fail(st);
+  if (!(g > 0.0)) { msg = "data-driven gamma is zero"; psara_destroy(c); return PSARA_EINVAL; }
+  if ((st = psara_set_gamma(c, g)) != PSARA_OK) return fail(st);
+  if ((st = psara_set_steps(c, 0.99 / 3.0, 1.0, 1.0 / nrm, 1.0)) != PSARA_OK) return fail(st);
+  j.ctx = c;
+  j.stage = 0;
+  j.left = j.stages[0];
+  return PSARA_OK;
+}
+
+void setup_loop(psara_server* S) {
+  (void)hipSetDevice(S->device);
+  for (;;) {
+    JobP j;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || S->can_admit(); });
+      if (S->stop) return;
+      j = S->queue.front();
+      S->queue.pop_front();
+      S->used += j->foot;
+      S->in_flight += 1;
+      j->state = PSARA_REQ_RUNNING;
+      j->t_start = S->now();
+    }
+    std::string msg;
+    const psara_status st = prepare(S, *j, msg);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (st != PSARA_OK) retire(S, *j, PSARA_REQ_FAILED, st, msg);
+      else S->ready.push_back(j);
+    }
+    S->cv.notify_all();
+  }
+}
+
+// One cached batch per (mode, precision, taps) group; rebuilt when the membership changes.
+struct Group {
+  std::vector<psara_ctx*> key;
+  std::unique_ptr<psara::Batch<float>> bf;
+  std::unique_ptr<psara::Batch<double>> bd;
+  void reset() { bf.reset(); bd.reset(); key.clear(); }
+};
+
+void run_group(Group& G, std::vector<JobP>& mem, int mode, int k, hipStream_t bs) {
+  std::vector<psara_ctx*> ctxs;
+  for (auto& j : mem) ctxs.push_back(j->ctx);
+  if (G.key != ctxs) {
+    G.reset();
+    if (mem[0]->req.precision == PSARA_FP64) {
+      std::vector<psara::Engine<double>*> e;
+      for (auto* c : ctxs) e.push_back(c->f64.get());
+      G.bd.reset(new psara::Batch<double>(e, bs));
+    } else {
+      std::vector<psara::Engine<float>*> e;
+      for (auto* c : ctxs) e.push_back(c->f32.get());
+      G.bf.reset(new psara::Batch<float>(e, bs));
+    }
+    G.key = ctxs;
+  }
+  if (G.bd) G.bd->run(mode, k);
+  else G.bf->run(mode, k);
+  psara::hip_check(hipStreamSynchronize(bs), "batch round");
+  for (auto& j : mem) {
+    j->left -= k;
+    j->ctx->iterations += k;
+  }
+}
+
+// Moves a job whose stage has ended to its next stage (reweighting it), or finishes it.
+// Returns true when the job is finished (its result stored, its context released).
+bool advance(psara_server* S, Job& j) {
+  while (j.left == 0) {
+    if (j.stage == 0) {
+      if (psara_coef_std(j.ctx, &j.delta) != PSARA_OK || !(j.delta > 0.0)) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        const std::string m = j.delta > 0.0 ? psara_last_error(j.ctx) : "initial estimate is zero: no reweighting scale";
+        psara_destroy(j.ctx);
+        j.ctx = nullptr;
+        retire(S, j, PSARA_REQ_FAILED, PSARA_EINVAL, m);
+        return true;
+      }
+    }
+    if (j.stage < j.req.cycles) {
+      psara_status st = psara_reweight(j.ctx, j.delta);
+      if (st != PSARA_OK) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        const std::string m = psara_last_error(j.ctx);
+        psara_destroy(j.ctx);
+        j.ctx = nullptr;
+        retire(S, j, PSARA_REQ_FAILED, st, m);
+        return true;
+      }
+      j.delta /= j.req.delta_decay;
+      j.stage += 1;
+      j.left = j.stages[j.stage];
+      continue;
+    }
+    psara_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    std::vector<double> img((size_t)j.req.n * j.req.n * 4);
+    psara_status st = psara_report_now(j.ctx, &rep);
+    if (st == PSARA_OK) st = psara_get_image(j.ctx, img.data());
+    rep.iterations = j.ctx->iterations;
+    const std::string m = st == PSARA_OK ? std::string() : std::string(psara_last_error(j.ctx));
+    psara_destroy(j.ctx);
+    j.ctx = nullptr;
+    std::lock_guard<std::mutex> lk(S->mu);
+    j.report = rep;
+    j.image.swap(img);
+    retire(S, j, st == PSARA_OK ? PSARA_REQ_DONE : PSARA_REQ_FAILED, st, m);
+    return true;
+  }
+  return false;
+}
+
+void fail_group(psara_server* S, std::map<std::tuple<int, int, int>, Group>& cache, const std::tuple<int, int, int>& key,
+                std::vector<JobP>& mem, psara_status st, const std::string& msg) {
+  cache.erase(key);
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (auto& j : mem) {
+    if (j->ctx) psara_destroy(j->ctx);
+    j->ctx = nullptr;
+    j->left = -1;
+    retire(S, *j, PSARA_REQ_FAILED, st, msg);
+  }
+}
+
+void worker_loop(psara_server* S) {
+  (void)hipSetDevice(S->device);
+  hipStream_t bs = nullptr;
+  if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) bs = nullptr;
+  std::vector<JobP> active;
+  std::map<std::tuple<int, int, int>, Group> cache;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (active.empty()) S->cv.wait(lk, [&] { return S->stop || !S->ready.empty(); });
+      if (S->stop) break;
+      while (!S->ready.empty()) {
+        active.push_back(S->ready.front());
+        S->ready.pop_front();
+      }
+    }
+    // stages of length zero end at once
+    bool changed = false;
+    for (auto& j : active) changed |= (j->left == 0);
+    if (changed) {
+      cache.clear();
+      std::vector<JobP> keep;
+      for (auto& j : active)
+        if (!advance(S, *j)) keep.push_back(j);
+      active.swap(keep);
+      S->cv.notify_all();
+      continue;
+    }
+    std::map<std::tuple<int, int, int>, std::vector<JobP>> groups;
+    for (auto& j : active) groups[std::make_tuple(stage_mode(*j), (int)j->req.precision, j->req.taps)].push_back(j);
+    for (auto it = cache.begin(); it != cache.end();) {
+      if (groups.count(it->first)) ++it;
+      else it = cache.erase(it);
+    }
+    for (auto& kv : groups) {
+      std::vector<JobP>& mem = kv.second;
+      int k = S->quantum;
+      for (auto& j : mem) k = std::min(k, j->left);
+      try {
+        run_group(cache[kv.first], mem, std::get<0>(kv.first), k, bs);
+      } catch (const std::exception& e) {
+        fail_group(S, cache, kv.first, mem, PSARA_EDEVICE, e.what());
+      } catch (const psara::Error& e) {
+        fail_group(S, cache, kv.first, mem, e.status, e.msg);
+      }
+    }
+    std::vector<JobP> keep;
+    bool done_any = false;
+    for (auto& j : active) {
+      if (j->left < 0) { done_any = true; continue; }
+      if (j->left == 0) {
+        // the cached batches must not outlive a member's context
+        for (auto it = cache.begin(); it != cache.end();) {
+          if (std::find(it->second.key.begin(), it->second.key.end(), j->ctx) != it->second.key.end())
+            it = cache.erase(it);
+          else
+            ++it;
+        }
+        if (advance(S, *j)) { done_any = true; continue; }
+      }
+      keep.push_back(j);
+    }
+    active.swap(keep);
+    if (done_any) S->cv.notify_all();
+  }
+  cache.clear();
+  for (auto& j : active)
+    if (j->ctx) psara_destroy(j->ctx);
+  if (bs) (void)hipStreamDestroy(bs);
+}
+
+}  // namespace
+
+extern "C" {
+
+psara_status psara_server_create(psara_server** out, int device, size_t hbm_budget, int max_slots, int quantum,
+                                 psara_serve_policy policy) {
+  if (!out) return PSARA_EINVAL;
+  *out = nullptr;
+  if (max_slots < 1 || quantum < 1 || hbm_budget == 0) return PSARA_EINVAL;
+  if (policy != PSARA_SERVE_BATCHED && policy != PSARA_SERVE_FIFO) return PSARA_EINVAL;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PSARA_EDEVICE;
+  if (device < 0 || device >= count) return PSARA_EINVAL;
+  std::unique_ptr<psara_server> S(new (std::nothrow) psara_server());
+  if (!S) return PSARA_ENOMEM;
+  S->device = device;
+  S->budget = hbm_budget;
+  S->policy = policy;
+  S->max_slots = policy == PSARA_SERVE_FIFO ? 1 : max_slots;
+  S->quantum = policy == PSARA_SERVE_FIFO ? (1 << 30) : quantum;
+  S->t0 = std::chrono::steady_clock::now();
+  try {
+    const int nsetup = policy == PSARA_SERVE_FIFO ? 1 : 2;
+    for (int i = 0; i < nsetup; ++i) S->setup_threads.emplace_back(setup_loop, S.get());
+    S->worker = std::thread(worker_loop, S.get());
+  } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stop = true;
+    }
+    S->cv.notify_all();
+    for (auto& t : S->setup_threads) if (t.joinable()) t.join();
+    if (S->worker.joinable()) S->worker.join();
+    return PSARA_ENOMEM;
+  }
+  *out = S.release();
+  return PSARA_OK;
+}
+
+psara_status psara_server_submit(psara_server* S, const psara_request* r, uint64_t* ticket) {
+  if (!S || !r || !ticket) return PSARA_EINVAL;
+  auto bad = [&](const char* m) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->err = m;
+    return PSARA_EINVAL;
+  };
+  if (!r->uv || !r->Y || r->M < 1 || r->n < 8) return bad("request: missing arrays or bad sizes");
+  if (!(r->epsilon > 0.0) || r->cycles < 0 || !r->iters_per_stage) return bad("request: bad epsilon or stages");
+  if (!(r->delta_decay > 1.0) || !(r->gamma_factor > 0.0) || r->opnorm_iters < 1) return bad("request: bad parameters");
+  for (int l = 0; l <= r->cycles; ++l)
+    if (r->iters_per_stage[l] < 0) return bad("request: negative iteration count");
+  JobP j = std::make_shared<Job>();
+  try {
+    j->req = *r;
+    j->uv.assign(r->uv, r->uv + 2 * r->M);
+    j->Y.assign(r->Y, r->Y + 8 * r->M);
+    j->stages.assign(r->iters_per_stage, r->iters_per_stage + r->cycles + 1);
+  } catch (const std::bad_alloc&) {
+    return PSARA_ENOMEM;
+  }
+  j->req.uv = nullptr;
+  j->req.Y = nullptr;
+  j->req.iters_per_stage = nullptr;
+  j->foot = psara_footprint(r->n, r->M, r->taps, r->levels, r->basis_mask, r->precision);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    j->ticket = S->next_ticket++;
+    j->t_submit = S->now();
+    S->jobs[j->ticket] = j;
+    S->queue.push_back(j);
+    *ticket = j->ticket;
+  }
+  S->cv.notify_all();
+  return PSARA_OK;
+}
+
+psara_status psara_server_poll(psara_server* S, uint64_t ticket, psara_result* out, double* image) {
+  if (!S || !out) return PSARA_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(ticket);
+  if (it == S->jobs.end()) return PSARA_EINVAL;
+  Job& j = *it->second;
+  out->state = j.state;
+  out->status = j.status;
+  out->t_submit = j.t_submit;
+  out->t_start = j.t_start;
+  out->t_done = j.t_done;
+  out->n = j.req.n;
+  out->report = j.report;
+  if (j.state == PSARA_REQ_FAILED) {
+    S->jobs.erase(it);
+  } else if (j.state == PSARA_REQ_DONE && image) {
+    std::memcpy(image, j.image.data(), j.image.size() * sizeof(double));
+    S->jobs.erase(it);
+  }
+  return PSARA_OK;
+}
+
+psara_status psara_server_drain(psara_server* S) {
+  if (!S) return PSARA_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->cv.wait(lk, [&] { return S->queue.empty() && S->ready.empty() && S->in_flight == 0; });
+  return PSARA_OK;
+}
+
+double psara_server_clock(const psara_server* S) { return S ? S->now() : 0.0; }
+
+const char* psara_server_last_error(const psara_server* S) { return S ? S->err.c_str() : "null server"; }
+
+void psara_server_destroy(psara_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  for (auto& t : S->setup_threads) if (t.joinable()) t.join();
+  if (S->worker.joinable()) S->worker.join();
+  for (auto& j : S->ready)
+    if (j->ctx) psara_destroy(j->ctx);
+  delete S;
+}
+
+}  // extern "C"

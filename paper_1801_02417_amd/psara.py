@@ -31,8 +31,13 @@ EXPORTS = (
     "psara_get_state", "psara_set_state", "psara_reset_state", "psara_footprint", "psara_apply_phi",
     "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
     "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_profile_passes",
-    "psara_batch_solve", "psara_batch_reweighted_solve",
+    "psara_batch_solve", "psara_batch_reweighted_solve", "psara_data_gamma", "psara_set_gamma",
+    "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
+    "psara_server_clock", "psara_server_last_error", "psara_server_destroy",
 )
+
+PSARA_SERVE_BATCHED, PSARA_SERVE_FIFO = 0, 1
+PSARA_REQ_QUEUED, PSARA_REQ_RUNNING, PSARA_REQ_DONE, PSARA_REQ_FAILED = 0, 1, 2, 3
 
 
 class PsaraReport(C.Structure):
@@ -44,6 +49,19 @@ class PsaraReport(C.Structure):
         return {"residual": self.residual, "epsilon": self.epsilon, "rel_var": list(self.rel_var),
                 "zeta": self.zeta, "n_p": self.n_p, "objective": self.objective, "vnorm": self.vnorm,
                 "iterations": int(self.iterations)}
+
+
+class PsaraRequest(C.Structure):
+    _fields_ = [("n", C.c_int), ("M", C.c_int64), ("uv", C.POINTER(C.c_double)), ("Y", C.POINTER(C.c_double)),
+                ("epsilon", C.c_double), ("taps", C.c_int), ("levels", C.c_int), ("basis_mask", C.c_uint32),
+                ("precision", C.c_int), ("mode", C.c_int), ("cycles", C.c_int),
+                ("iters_per_stage", C.POINTER(C.c_int)), ("delta_decay", C.c_double),
+                ("gamma_factor", C.c_double), ("opnorm_iters", C.c_int), ("opnorm_rtol", C.c_double)]
+
+
+class PsaraResult(C.Structure):
+    _fields_ = [("state", C.c_int), ("status", C.c_int), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double), ("n", C.c_int), ("report", PsaraReport)]
 
 
 class PsaraError(RuntimeError):
@@ -96,6 +114,15 @@ def lib() -> C.CDLL:
         "psara_layout": (I, [P, C.POINTER(C.c_int64)]),
         "psara_profile_passes": (I, [P, I, I, D]),
         "psara_batch_solve": (I, [C.POINTER(P), I, I, I, C.POINTER(PsaraReport)]),
+        "psara_data_gamma": (I, [P, C.c_double, D]),
+        "psara_set_gamma": (I, [P, C.c_double]),
+        "psara_server_create": (I, [C.POINTER(P), I, S, I, I, I]),
+        "psara_server_submit": (I, [P, C.POINTER(PsaraRequest), C.POINTER(C.c_uint64)]),
+        "psara_server_poll": (I, [P, C.c_uint64, C.POINTER(PsaraResult), D]),
+        "psara_server_drain": (I, [P]),
+        "psara_server_clock": (C.c_double, [P]),
+        "psara_server_last_error": (C.c_char_p, [P]),
+        "psara_server_destroy": (None, [P]),
         "psara_batch_reweighted_solve": (I, [C.POINTER(P), I, I, I, C.POINTER(C.c_int), C.c_double,
                                              C.POINTER(PsaraReport)]),
     }
@@ -324,6 +351,68 @@ def psara_batch_reweighted_solve(ctxs, mode: int, iters_per_stage: Sequence[int]
                                             delta_decay, reps)
     _batch_check(ctxs, st)
     return [r.as_dict() for r in reps]
+
+
+def psara_data_gamma(ctx, factor: float = 1e-3) -> float:
+    out = C.c_double()
+    _check(ctx, lib().psara_data_gamma(ctx, float(factor), C.byref(out)))
+    return out.value
+
+
+def psara_set_gamma(ctx, gamma: float) -> None:
+    _check(ctx, lib().psara_set_gamma(ctx, float(gamma)))
+
+
+def psara_server_create(device: int = 0, hbm_budget: int = 64 << 30, max_slots: int = 64, quantum: int = 25,
+                        policy: int = PSARA_SERVE_BATCHED):
+    srv = C.c_void_p()
+    st = lib().psara_server_create(C.byref(srv), device, int(hbm_budget), max_slots, quantum, policy)
+    if st != PSARA_OK:
+        raise PsaraError(st, lib().psara_status_string(st).decode())
+    return srv
+
+
+def _server_check(srv, status: int):
+    if status != PSARA_OK:
+        raise PsaraError(status, lib().psara_server_last_error(srv).decode())
+
+
+def psara_server_submit(srv, n: int, uv: np.ndarray, Y: np.ndarray, epsilon: float, taps: int = 8, levels: int = 4,
+                        basis_mask: int = ALL_BASES, precision: int = PSARA_FP32_MIXED,
+                        mode: int = PSARA_CONSTRAINED, iters_per_stage: Sequence[int] = (100, 100, 100),
+                        delta_decay: float = 10.0, gamma_factor: float = 1e-3, opnorm_iters: int = 200,
+                        opnorm_rtol: float = 1e-6) -> int:
+    uv = _f64(uv)
+    y = _vis(Y)
+    stages = (C.c_int * len(iters_per_stage))(*[int(v) for v in iters_per_stage])
+    req = PsaraRequest(n, uv.shape[0], _dptr(uv), _dptr(y), float(epsilon), taps, levels, basis_mask, precision,
+                       mode, len(iters_per_stage) - 1, stages, float(delta_decay), float(gamma_factor),
+                       opnorm_iters, float(opnorm_rtol))
+    ticket = C.c_uint64()
+    _server_check(srv, lib().psara_server_submit(srv, C.byref(req), C.byref(ticket)))
+    return ticket.value
+
+
+def psara_server_poll(srv, ticket: int, image: Optional[np.ndarray] = None) -> dict:
+    """State of a request; with `image` (n*n x 4 float64) a finished request's image is copied
+    there and the request is forgotten."""
+    res = PsaraResult()
+    ptr = _dptr(image) if image is not None else None
+    _server_check(srv, lib().psara_server_poll(srv, C.c_uint64(ticket), C.byref(res), ptr))
+    return {"state": res.state, "status": res.status, "t_submit": res.t_submit, "t_start": res.t_start,
+            "t_done": res.t_done, "n": res.n, "report": res.report.as_dict()}
+
+
+def psara_server_drain(srv) -> None:
+    _server_check(srv, lib().psara_server_drain(srv))
+
+
+def psara_server_clock(srv) -> float:
+    return lib().psara_server_clock(srv)
+
+
+def psara_server_destroy(srv) -> None:
+    lib().psara_server_destroy(srv)
 
 
 # ---- convenience wrapper ------------------------------------------------------------------------

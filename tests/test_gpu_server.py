@@ -1,0 +1,119 @@
+"""The request server: continuous batching and the FIFO loop give every request the image it
+gets when solved alone with the same call sequence (bit for bit); the data-driven gamma
+matches the oracle's; admission under a small memory budget queues instead of failing."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+from gpu_common import say
+from oracle import problem
+from paper_1801_02417_amd import psara as P
+from paper_1801_02417_amd import workloads as wk
+
+pytestmark = pytest.mark.gpu
+
+STAGES = (8, 6, 6)
+NORM_ITERS, NORM_RTOL = 60, 1e-7
+
+
+def requests():
+    out = []
+    for i, (n, M, L) in enumerate([(16, 150, 2), (32, 600, 3), (64, 2500, 4), (32, 900, 2), (16, 300, 2),
+                                   (64, 1200, 3)]):
+        wl = wk.tiny(n=n, M=M, taps=8, levels=L, seed=100 + i)
+        b = problem.build(wl, norm_rtol=1e-6, norm_max_iter=40)
+        out.append((wl, b.pb.Y, b.pb.eps))
+    return out
+
+
+def solve_alone(wl, Y, eps, prec):
+    ctx = P.psara_create(0)
+    try:
+        P.psara_set_operator(ctx, wl.n, wl.uv, 2, wl.taps, prec)
+        P.psara_set_data(ctx, Y, eps)
+        P.psara_set_prior(ctx, P.ALL_BASES, wl.levels, None, 1.0)
+        nrm = P.psara_opnorm(ctx, NORM_ITERS, NORM_RTOL)
+        P.psara_set_gamma(ctx, P.psara_data_gamma(ctx, 1e-3))
+        P.psara_set_steps(ctx, 0.99 / 3.0, 1.0, 1.0 / nrm, 1.0)
+        P.psara_reweighted_solve(ctx, P.PSARA_CONSTRAINED, STAGES, 10.0)
+        return P.psara_get_image(ctx, wl.n * wl.n)
+    finally:
+        P.psara_destroy(ctx)
+
+
+def serve(reqs, prec, policy, budget=8 << 30, quantum=5):
+    srv = P.psara_server_create(0, budget, 16, quantum, policy)
+    try:
+        tickets = [P.psara_server_submit(srv, wl.n, wl.uv, Y, eps, taps=wl.taps, levels=wl.levels, precision=prec,
+                                         iters_per_stage=STAGES, opnorm_iters=NORM_ITERS, opnorm_rtol=NORM_RTOL)
+                   for wl, Y, eps in reqs]
+        P.psara_server_drain(srv)
+        out = []
+        for (wl, _, _), t in zip(reqs, tickets):
+            img = np.empty((wl.n * wl.n, 4))
+            r = P.psara_server_poll(srv, t, img)
+            assert r["state"] == P.PSARA_REQ_DONE, (r, P.lib().psara_server_last_error(srv))
+            assert r["report"]["iterations"] == sum(STAGES)
+            assert r["t_submit"] <= r["t_start"] <= r["t_done"]
+            out.append(img)
+        with pytest.raises(P.PsaraError):
+            P.psara_server_poll(srv, tickets[0])      # collected requests are forgotten
+        return out
+    finally:
+        P.psara_server_destroy(srv)
+
+
+@pytest.mark.parametrize("prec", [P.PSARA_FP32_MIXED, P.PSARA_FP64])
+def test_served_equals_alone(prec):
+    reqs = requests()
+    alone = [solve_alone(wl, Y, eps, prec) for wl, Y, eps in reqs]
+    for policy in (P.PSARA_SERVE_BATCHED, P.PSARA_SERVE_FIFO):
+        t0 = time.time()
+        served = serve(reqs, prec, policy)
+        say(f"policy {policy} prec {prec}: {len(reqs)} requests in {time.time() - t0:.2f} s")
+        for (wl, _, _), a, b in zip(reqs, alone, served):
+            assert np.array_equal(a, b), f"{wl.name}: served image differs ({np.max(np.abs(a - b))})"
+
+
+def test_small_budget_queues():
+    reqs = requests()[:3]
+    foot = max(P.psara_footprint(wl.n, wl.M, wl.taps, wl.levels) for wl, _, _ in reqs)
+    served = serve(reqs, P.PSARA_FP32_MIXED, P.PSARA_SERVE_BATCHED, budget=foot + 1)
+    alone = [solve_alone(wl, Y, eps, P.PSARA_FP32_MIXED) for wl, Y, eps in reqs]
+    for a, b in zip(alone, served):
+        assert np.array_equal(a, b)
+
+
+def test_data_gamma_matches_oracle():
+    wl = wk.config0()
+    b = problem.build(wl)
+    ctx = P.psara_create(0)
+    try:
+        P.psara_set_operator(ctx, wl.n, wl.uv, 2, wl.taps, P.PSARA_FP64)
+        P.psara_set_data(ctx, b.pb.Y, b.pb.eps)
+        P.psara_set_prior(ctx, P.ALL_BASES, wl.levels, None, 1.0)
+        P.psara_opnorm(ctx, 1000, 1e-13)
+        g = P.psara_data_gamma(ctx, 1e-3)
+        say(f"gamma gpu {g:.15e} oracle {b.gamma:.15e}")
+        assert abs(g - b.gamma) <= 1e-9 * b.gamma
+    finally:
+        P.psara_destroy(ctx)
+
+
+def test_bad_request_rejected():
+    srv = P.psara_server_create(0, 1 << 30, 4, 5)
+    try:
+        wl = wk.tiny(n=16, M=150, taps=8, levels=2, seed=1)
+        with pytest.raises(P.PsaraError) as e:
+            P.psara_server_submit(srv, wl.n, wl.uv, np.zeros((wl.M, 4), complex), -1.0)
+        assert e.value.status == P.PSARA_EINVAL
+        # a request that fails during set-up (taps 5) is reported failed, not hung
+        t = P.psara_server_submit(srv, wl.n, wl.uv, np.ones((wl.M, 4), complex), 1.0, taps=5)
+        P.psara_server_drain(srv)
+        r = P.psara_server_poll(srv, t)
+        assert r["state"] == P.PSARA_REQ_FAILED and r["status"] == P.PSARA_EINVAL
+    finally:
+        P.psara_server_destroy(srv)

@@ -14,6 +14,7 @@ the FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import hashlib
 import json
 import math
@@ -100,7 +101,127 @@ def cpu_baseline(iters: int) -> dict:
                       f"FP64 numpy/scipy, {dt:.1f} s; BLAS threads = cores, FFT and sparse products single-threaded"}
 
 
+def snr_db(est: np.ndarray, truth: np.ndarray) -> float:
+    """Reconstruction SNR over all four Stokes maps, 20 log10(||truth|| / ||est - truth||)."""
+    return float(20.0 * math.log10(np.linalg.norm(truth) / max(np.linalg.norm(est - truth), 1e-300)))
+
+
+def make_data(P, wl, s):
+    """Synthetic measurements of a workload on the device: Y = phi(S_true) + sigma E with sigma
+    from the input SNR and epsilon^2 = (8M + 2 sqrt(16M)) sigma^2 / 2 (chi-square bound)."""
+    N, M = wl.n * wl.n, wl.M
+    y0 = s.phi(wl.truth.reshape(N, 4))
+    sigma = np.linalg.norm(y0) / math.sqrt(4 * M) * 10 ** (-wl.isnr_db / 20)
+    Y = y0 + sigma * wl.noise
+    eps = math.sqrt((8 * M + 2 * math.sqrt(2 * 8 * M)) * sigma ** 2 / 2)
+    return Y, eps
+
+
+def ready_solver(P, wl, norm_iters=200, norm_rtol=1e-6):
+    """A FP32 solver of one workload with data, prior (gamma from the data), and step sizes."""
+    s = P.Solver(wl.n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED)
+    Y, eps = make_data(P, wl, s)
+    s.set_data(Y, eps)
+    s.set_prior(wl.levels, 1.0)
+    s.opnorm(norm_iters, norm_rtol)
+    P.psara_set_gamma(s.ctx, P.psara_data_gamma(s.ctx, 1e-3))
+    s.set_steps()
+    return s, Y, eps
+
+
+def batched_form(P, wk, count: int, stages) -> dict:
+    """64 uneven solves (sides {64,128,256}, M log-uniform in [1e3, 1e5], ISNR 15-35 dB) run as one
+    batch (every pass one launch over all solves, graph-replayed) and one after another."""
+    wls = [wk.batch_request(i) for i in range(count)]
+    solvers = [ready_solver(P, wl)[0] for wl in wls]
+    import torch
+    torch.cuda.synchronize()
+    for s in solvers:
+        s.reset()
+    t0 = time.perf_counter()
+    P.batch_reweighted_solve(solvers, P.PSARA_CONSTRAINED, stages)
+    t_batch = time.perf_counter() - t0
+    img_b = [s.image() for s in solvers]
+    for s in solvers:
+        s.reset()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.reweighted_solve(P.PSARA_CONSTRAINED, stages)
+    t_seq = time.perf_counter() - t0
+    img_s = [s.image() for s in solvers]
+    diff = max(float(np.max(np.abs(a - b))) for a, b in zip(img_b, img_s))
+    snr = [snr_db(im, wl.truth.reshape(-1, 4)) for im, wl in zip(img_b, wls)]
+    for s in solvers:
+        s.close()
+    its = count * sum(stages)
+    return {"solves": count, "iters_per_solve": sum(stages), "sides": sorted({wl.n for wl in wls}),
+            "batched": {"iters_per_s": round(its / t_batch, 1), "solves_per_s": round(count / t_batch, 2),
+                        "wall_s": round(t_batch, 3)},
+            "one_at_a_time": {"iters_per_s": round(its / t_seq, 1), "solves_per_s": round(count / t_seq, 2),
+                              "wall_s": round(t_seq, 3)},
+            "speedup": round(t_seq / t_batch, 2), "max_abs_image_diff_batched_vs_alone": diff,
+            "mean_snr_db": round(float(np.mean(snr)), 3)}
+
+
+def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dict:
+    """Poisson arrivals at `rate`/s of uneven requests (sides {64,128,256,512}, 512 with 1e6
+    visibilities) served by the continuous-batching server and by the FIFO loop on the same GPU."""
+    reqs = []
+    for i in range(count):
+        wl = wk.batch_request(i, sides=(64, 128, 256, 512))
+        if i % 10 == 0:
+            progress(f"served form: generating request {i} (n={wl.n}, M={wl.M})")
+        s = P.Solver(wl.n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED)
+        Y, eps = make_data(P, wl, s)
+        s.close()
+        reqs.append((wl, Y, eps))
+    arrivals = wk.poisson_arrivals(count, rate)
+    out = {"requests": count, "rate_per_s": rate, "iters_per_solve": sum(stages),
+           "sides": sorted({wl.n for wl, _, _ in reqs})}
+    images = {}
+    for name, policy in (("batched", P.PSARA_SERVE_BATCHED), ("fifo", P.PSARA_SERVE_FIFO)):
+        progress(f"served form: {name} server")
+        srv = P.psara_server_create(0, int(budget_gb * (1 << 30)), 64, 300, policy)
+        try:
+            tickets = []
+            for (wl, Y, eps), ta in zip(reqs, arrivals):
+                wait = ta - P.psara_server_clock(srv)
+                if wait > 0:
+                    time.sleep(wait)
+                tickets.append(P.psara_server_submit(srv, wl.n, wl.uv, Y, eps, taps=wl.taps, levels=wl.levels,
+                                                     iters_per_stage=stages, opnorm_iters=100, opnorm_rtol=1e-4))
+            P.psara_server_drain(srv)
+            t_end = P.psara_server_clock(srv)
+            lat, imgs, failed = [], [], 0
+            for (wl, _, _), t in zip(reqs, tickets):
+                img = np.empty((wl.n * wl.n, 4))
+                r = P.psara_server_poll(srv, t, img)
+                if r["state"] != P.PSARA_REQ_DONE:
+                    failed += 1
+                    imgs.append(None)
+                    continue
+                lat.append(r["t_done"] - r["t_submit"])
+                imgs.append(img)
+        finally:
+            P.psara_server_destroy(srv)
+        images[name] = imgs
+        snr = [snr_db(im, wl.truth.reshape(-1, 4)) for im, (wl, _, _) in zip(imgs, reqs) if im is not None]
+        out[name] = {"solves_per_s": round(len(lat) / (t_end - arrivals[0]), 3),
+                     "p50_latency_s": round(float(np.percentile(lat, 50)), 4) if lat else None,
+                     "p99_latency_s": round(float(np.percentile(lat, 99)), 4) if lat else None,
+                     "failed": failed, "mean_snr_db": round(float(np.mean(snr)), 3) if snr else None}
+    diffs = [float(np.max(np.abs(a - b))) for a, b in zip(images["batched"], images["fifo"])
+             if a is not None and b is not None]
+    out["max_abs_image_diff_batched_vs_fifo"] = max(diffs) if diffs else None
+    return out
+
+
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main() -> int:
+    faulthandler.enable()
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
@@ -108,6 +229,10 @@ def main() -> int:
     ap.add_argument("--profile-iters", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-solves", type=int, default=64, help="solves of the batched form (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=120,
+                    help="requests of the served form at 20/s (0: skip; 1200 is the full 60 s stream)")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 10 times (to scale HBM counters)")
     args = ap.parse_args()
@@ -194,9 +319,19 @@ def main() -> int:
         "sum_of_pass_ms": round(float(np.sum(ms)), 5),
         "solve_check": {"residual_over_eps": rep["residual"] / rep["epsilon"], "n_p": rep["n_p"]},
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_iters)
     s.close()
+    progress(f"256x256 / 2e5-visibility iteration rate {its:.1f} iters/s")
+    if args.batch_solves > 0:
+        progress(f"batched form: {args.batch_solves} solves")
+        line["batched_form"] = batched_form(P, wk, args.batch_solves, [100, 100, 100])
+        progress(f"batched form done: {line['batched_form']['batched']}")
+    if args.serve_requests > 0:
+        progress(f"served form: {args.serve_requests} requests at 20/s")
+        line["served_form"] = served_form(P, wk, args.serve_requests, 20.0, [100, 100, 100], args.serve_budget_gb)
+        progress("served form done")
+    if not args.no_cpu_baseline:
+        progress("oracle CPU baseline")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_iters)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -165,6 +165,29 @@ void batch_reweighted(psara_ctx* const* ctxs, int count, int mode, int cycles, c
 }
 }  // namespace
 
+void psara_check_operator_args(int n, int64_t M, const double* uv, int oversample, int taps, psara_precision precision) {
+  require(is_pow2(n) && n >= 8 && n <= 1024, PSARA_EINVAL, "n must be a power of two in [8, 1024]");
+  require(M >= 1 && M < (int64_t(1) << 31), PSARA_EINVAL, "M must be in [1, 2^31)");
+  require(uv != nullptr, PSARA_EINVAL, "uv is NULL");
+  require(oversample == 2, PSARA_EINVAL, "oversample must be 2");
+  require(taps == 4 || taps == 6 || taps == 8, PSARA_EINVAL, "taps must be 4, 6 or 8");
+  require(precision == PSARA_FP64 || precision == PSARA_FP32_MIXED, PSARA_EINVAL, "unknown precision");
+  for (int64_t i = 0; i < 2 * M; ++i) require(std::isfinite(uv[i]), PSARA_ENAN, "non-finite uv");
+}
+
+void psara_bind_geometry(psara_ctx* c, psara::Geometry&& g, psara_precision precision) {
+  if (hipSetDevice(c->device) != hipSuccess) throw Error(PSARA_EDEVICE, "hipSetDevice failed");
+  c->f32.reset();
+  c->f64.reset();
+  c->op_set = c->data_set = c->prior_set = c->steps_set = c->norm_set = false;
+  c->iterations = 0;
+  c->geo = std::move(g);
+  c->prec = precision;
+  if (precision == PSARA_FP64) c->f64.reset(new Engine<double>(c->geo, c->stream));
+  else c->f32.reset(new Engine<float>(c->geo, c->stream));
+  c->op_set = true;
+}
+
 extern "C" {
 
 const char* psara_status_string(psara_status s) {
@@ -213,22 +236,8 @@ const char* psara_last_error(const psara_ctx* c) { return c ? c->err.c_str() : "
 psara_status psara_set_operator(psara_ctx* c, int n, int64_t M, const double* uv, int oversample, int taps,
                                 psara_precision precision) {
   return guard(c, [&] {
-    require(is_pow2(n) && n >= 8 && n <= 1024, PSARA_EINVAL, "n must be a power of two in [8, 1024]");
-    require(M >= 1 && M < (int64_t(1) << 31), PSARA_EINVAL, "M must be in [1, 2^31)");
-    require(uv != nullptr, PSARA_EINVAL, "uv is NULL");
-    require(oversample == 2, PSARA_EINVAL, "oversample must be 2");
-    require(taps == 4 || taps == 6 || taps == 8, PSARA_EINVAL, "taps must be 4, 6 or 8");
-    require(precision == PSARA_FP64 || precision == PSARA_FP32_MIXED, PSARA_EINVAL, "unknown precision");
-    for (int64_t i = 0; i < 2 * M; ++i) require(std::isfinite(uv[i]), PSARA_ENAN, "non-finite uv");
-    c->f32.reset();
-    c->f64.reset();
-    c->op_set = c->data_set = c->prior_set = c->steps_set = c->norm_set = false;
-    c->iterations = 0;
-    c->geo = psara::build_geometry(n, M, uv, oversample, taps);
-    c->prec = precision;
-    if (precision == PSARA_FP64) c->f64.reset(new Engine<double>(c->geo, c->stream));
-    else c->f32.reset(new Engine<float>(c->geo, c->stream));
-    c->op_set = true;
+    psara_check_operator_args(n, M, uv, oversample, taps, precision);
+    psara_bind_geometry(c, psara::build_geometry(n, M, uv, oversample, taps), precision);
   });
 }
 

@@ -18,6 +18,8 @@ constexpr int kMaxCheb = 17;     // Chebyshev coefficients per tap (degree <= 16
 constexpr int kMaxLevels = 8;
 constexpr int kRunMax = 32;         // longest run of same-window visibilities one lane group takes
 constexpr int kChunkEntries = 512;  // gridding entries per workgroup (staged in LDS)
+constexpr int kBatchChunk = 8;       // iterations per captured graph of a batch
+constexpr int kMaxDegridTile = 32;  // largest de-gridding tile side (the geometry picks 16 or 32)
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
 
 // Chebyshev degree of the per-tap Kaiser-Bessel expansions (max error ~1e-10 / ~1e-15)

@@ -26,3 +26,9 @@ struct psara_ctx {
   int levels = 0;
   int64_t iterations = 0;
 };
+
+// Binds a host-built geometry (psara::build_geometry) to the context and creates its engine;
+// the device half of psara_set_operator.  Throws psara::Error.
+void psara_bind_geometry(psara_ctx* c, psara::Geometry&& g, psara_precision precision);
+// The argument checks of psara_set_operator.  Throws psara::Error.
+void psara_check_operator_args(int n, int64_t M, const double* uv, int oversample, int taps, psara_precision precision);

@@ -39,7 +39,7 @@ static void copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind ki
 Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
   Geometry g;
   g.n = n; g.K = alpha * n; g.T = T; g.M = M;
-  g.ts = (g.K >= 512) ? 32 : 16;
+  g.ts = (g.K >= 512) ? kMaxDegridTile : kMaxDegridTile / 2;
   g.nts = g.K / g.ts;
   g.ntsg = g.K / kGridTile;
   g.beta = kb_beta(T, alpha);
@@ -260,10 +260,10 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
 
 template <typename R>
 Engine<R>::~Engine() {
-  for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
-  graphs_.clear();
   (void)hipStreamSynchronize(s0_);
   (void)hipStreamSynchronize(s1_);
+  for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  graphs_.clear();
   for (void* p : allocs_) (void)hipFree(p);
   (void)hipEventDestroy(ev_fork_);
   (void)hipEventDestroy(ev_join_);
@@ -945,13 +945,36 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
 
 template <typename R>
 Batch<R>::~Batch() {
-  for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
   (void)hipStreamSynchronize(s0_);
   if (s1_) (void)hipStreamSynchronize(s1_);
+  for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
   for (void* p : allocs_) (void)hipFree(p);
   if (ev_fork_) (void)hipEventDestroy(ev_fork_);
   if (ev_join_) (void)hipEventDestroy(ev_join_);
   if (s1_) (void)hipStreamDestroy(s1_);
+}
+
+template <typename R>
+hipGraphExec_t Batch<R>::graph(int mode, int count) {
+  const int key = mode * 1000 + count;
+  auto it = graphs_.find(key);
+  if (it != graphs_.end()) return it->second;
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
+  for (int k = 0; k < count; ++k) launch_iteration_lists<R>(pl_, mode, s0_, s1_, ev_fork_, ev_join_);
+  hip_check(hipStreamEndCapture(s0_, &g), "end capture");
+  hipGraphExec_t exec = nullptr;
+  hip_check(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
+  (void)hipGraphDestroy(g);
+  graphs_[key] = exec;
+  return exec;
+}
+
+template <typename R>
+void Batch<R>::capture(int mode) {
+  if ((mode != PM_INIT) && !pl_.sparse) throw Error(PSARA_ESTATE, "every batch member needs a wavelet prior in this mode");
+  graph(mode, kBatchChunk);
+  graph(mode, 1);
 }
 
 template <typename R>
@@ -964,31 +987,15 @@ void Batch<R>::run(int mode, int iters) {
     d[i] = members_[i]->desc();
     hip_check(hipStreamSynchronize(members_[i]->stream()), "member sync");
   }
-  hip_check(hipMemcpyAsync(d_descs_, d.data(), d.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, s0_), "descriptors upload");
-  hip_check(hipStreamSynchronize(s0_), "descriptors sync");
+  copy_sync(d_descs_, d.data(), d.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, s0_, "descriptors upload");
   if (iters <= 0) return;
-  constexpr int kChunk = 8;
-  auto get_graph = [&](int count) -> hipGraphExec_t {
-    const int key = mode * 1000 + count;
-    auto it = graphs_.find(key);
-    if (it != graphs_.end()) return it->second;
-    hipGraph_t graph = nullptr;
-    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
-    for (int k = 0; k < count; ++k) launch_iteration_lists<R>(pl_, mode, s0_, s1_, ev_fork_, ev_join_);
-    hip_check(hipStreamEndCapture(s0_, &graph), "end capture");
-    hipGraphExec_t exec = nullptr;
-    hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
-    (void)hipGraphDestroy(graph);
-    graphs_[key] = exec;
-    return exec;
-  };
   int left = iters;
-  if (left >= kChunk) {
-    hipGraphExec_t g = get_graph(kChunk);
-    while (left >= kChunk) { hip_check(hipGraphLaunch(g, s0_), "graph launch"); left -= kChunk; }
+  if (left >= kBatchChunk) {
+    hipGraphExec_t g = graph(mode, kBatchChunk);
+    while (left >= kBatchChunk) { hip_check(hipGraphLaunch(g, s0_), "graph launch"); left -= kBatchChunk; }
   }
   if (left > 0) {
-    hipGraphExec_t g = get_graph(1);
+    hipGraphExec_t g = graph(mode, 1);
     for (; left > 0; --left) hip_check(hipGraphLaunch(g, s0_), "graph launch");
   }
   hip_check(hipGetLastError(), "batch iteration launch");

@@ -185,10 +185,12 @@ struct Batch {
   Batch(const Batch&) = delete;
   Batch& operator=(const Batch&) = delete;
   void run(int mode, int iters);       // graph replay; returns with the work queued on stream()
+  void capture(int mode);              // capture the graphs run() replays (no work is launched)
   hipStream_t stream() const { return s0_; }
   int size() const { return (int)members_.size(); }
 
  private:
+  hipGraphExec_t graph(int mode, int count);
   std::vector<Engine<R>*> members_;
   hipStream_t s0_ = nullptr, s1_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;

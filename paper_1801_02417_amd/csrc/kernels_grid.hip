@@ -16,6 +16,9 @@
 // those partials (fixed order, compensated) to c = rho2 * max(0, 1 - epsilon/||Bv||), which
 // both it and the next iteration's de-gridding apply on the fly.  This equals
 // B~ - rho2 P_B(Y,eps)(B~/rho2) without a second pass over the visibilities.
+#include <mutex>
+#include <set>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -333,11 +336,20 @@ void set_degrid_limits_t(int max_ts) {
   hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_RESIDUAL, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
 }
 
+// Set once per device for every tap count, at the largest de-grid tile (hipFuncSetAttribute is
+// a device-wide setting, so later engines and batches need not repeat it).
 template <typename R>
-void set_grid_kernel_limits(int max_ts, int taps) {
-  if (taps == 4) set_degrid_limits_t<R, 4>(max_ts);
-  else if (taps == 6) set_degrid_limits_t<R, 6>(max_ts);
-  else set_degrid_limits_t<R, 8>(max_ts);
+void set_grid_kernel_limits(int /*max_ts*/, int /*taps*/) {
+  static std::mutex mu;
+  static std::set<int> done;
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(dev)) return;
+  set_degrid_limits_t<R, 4>(kMaxDegridTile);
+  set_degrid_limits_t<R, 6>(kMaxDegridTile);
+  set_degrid_limits_t<R, 8>(kMaxDegridTile);
+  done.insert(dev);
 }
 
 template void set_grid_kernel_limits<float>(int, int);

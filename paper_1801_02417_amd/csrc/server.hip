@@ -1,6 +1,8 @@
 // Request server of the C ABI (declared in include/psara.h): admission by device-memory
-// footprint, host-side set-up on helper threads, and continuous batching of the admitted
-// solves on one GPU.  A request is Algorithm 2 on its own problem; while it runs it is a member
+// footprint, host-side set-up (the visibility sort and tile binning) on helper threads, and
+// continuous batching of the admitted solves on one GPU.  Only the worker thread makes HIP
+// calls: a call from another thread while the worker captures a graph could disturb the
+// capture.  A request is Algorithm 2 on its own problem; while it runs it is a member
 // of the batch of its stage's mode (the initialisation stage and the reweighted stages use
 // different primal steps), which advances in rounds of at most `quantum` iterations; after a
 // round the members that reached the end of a stage are reweighted (or finished) on their own.
@@ -33,6 +35,7 @@ struct Job {
   std::vector<double> uv, Y;
   std::vector<int> stages;
   size_t foot = 0;
+  psara::Geometry geo;             // built by a set-up thread
   // progress, owned by the thread that holds the job
   psara_ctx* ctx = nullptr;
   int stage = 0, left = 0;
@@ -94,8 +97,24 @@ void retire(psara_server* S, Job& j, int state, psara_status st, const std::stri
   S->in_flight -= 1;
 }
 
-// Creates and prepares the context of a request; returns the failing status (0 on success).
-psara_status prepare(psara_server* S, Job& j, std::string& msg) {
+// Host half of a request's set-up (set-up threads): argument checks and the geometry.
+psara_status prepare_host(Job& j, std::string& msg) {
+  const psara_request& r = j.req;
+  try {
+    psara_check_operator_args(r.n, r.M, j.uv.data(), 2, r.taps, r.precision);
+    j.geo = psara::build_geometry(r.n, r.M, j.uv.data(), 2, r.taps);
+  } catch (const psara::Error& e) {
+    msg = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    msg = "host allocation failed";
+    return PSARA_ENOMEM;
+  }
+  return PSARA_OK;
+}
+
+// Device half (worker thread): the context, data, prior, operator norm, gamma and steps.
+psara_status prepare_device(psara_server* S, Job& j, std::string& msg) {
   psara_ctx* c = nullptr;
   psara_status st = psara_create(&c, S->device, nullptr);
   if (st != PSARA_OK) { msg = "context creation failed"; return st; }
@@ -105,7 +124,18 @@ psara_status prepare(psara_server* S, Job& j, std::string& msg) {
     return s;
   };
   const psara_request& r = j.req;
-  if ((st = psara_set_operator(c, r.n, r.M, j.uv.data(), 2, r.taps, r.precision)) != PSARA_OK) return fail(st);
+  try {
+    psara_bind_geometry(c, std::move(j.geo), r.precision);
+  } catch (const psara::Error& e) {
+    msg = e.msg;
+    psara_destroy(c);
+    return e.status;
+  } catch (const std::exception& e) {
+    msg = e.what();
+    psara_destroy(c);
+    return PSARA_EDEVICE;
+  }
+  j.geo = psara::Geometry();
   if ((st = psara_set_data(c, j.Y.data(), r.epsilon)) != PSARA_OK) return fail(st);
   if ((st = psara_set_prior(c, r.basis_mask, r.levels, nullptr, 1.0)) != PSARA_OK) return fail(st);
   double nrm = 0.0, g = 0.0;
@@ -121,7 +151,6 @@ psara_status prepare(psara_server* S, Job& j, std::string& msg) {
 }
 
 void setup_loop(psara_server* S) {
-  (void)hipSetDevice(S->device);
   for (;;) {
     JobP j;
     {
@@ -136,7 +165,7 @@ void setup_loop(psara_server* S) {
       j->t_start = S->now();
     }
     std::string msg;
-    const psara_status st = prepare(S, *j, msg);
+    const psara_status st = prepare_host(*j, msg);
     {
       std::lock_guard<std::mutex> lk(S->mu);
       if (st != PSARA_OK) retire(S, *j, PSARA_REQ_FAILED, st, msg);
@@ -146,37 +175,89 @@ void setup_loop(psara_server* S) {
   }
 }
 
-// One cached batch per (mode, precision, taps) group; rebuilt when the membership changes.
+// The admitted requests of one stage mode, precision, tap count and image side form a group; a
+// group's batch runs on its own stream, so groups of different sizes overlap on the GPU, and
+// each round gives a group as many iterations as fit in about kRoundSeconds of its measured
+// iteration time (at most `quantum`): small problems then advance many iterations while a large
+// one advances a few, instead of all moving in lockstep at the pace of the largest.
+constexpr double kRoundSeconds = 0.01;
+using GroupKey = std::tuple<int, int, int, int>;   // mode, precision, taps, side
+
 struct Group {
-  std::vector<psara_ctx*> key;
+  std::vector<psara_ctx*> key;          // members the cached batch was built for
   std::unique_ptr<psara::Batch<float>> bf;
   std::unique_ptr<psara::Batch<double>> bd;
-  void reset() { bf.reset(); bd.reset(); key.clear(); }
+  hipStream_t stream = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double t_iter = 0.0;                  // measured seconds per iteration (moving average)
+  int k = 0;                            // iterations of the round in flight
+  std::vector<JobP> mem;
+  bool launched = false;
+  Group() {
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) e0 = nullptr;
+    if (hipEventCreate(&e1) != hipSuccess) e1 = nullptr;
+  }
+  ~Group() {
+    drop_batch();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+  Group(const Group&) = delete;
+  Group& operator=(const Group&) = delete;
+  void drop_batch() { bf.reset(); bd.reset(); key.clear(); }
+  bool holds(const psara_ctx* c) const { return std::find(key.begin(), key.end(), c) != key.end(); }
 };
 
-void run_group(Group& G, std::vector<JobP>& mem, int mode, int k, hipStream_t bs) {
+// Rebuilds the group's batch when the membership changed and captures its graphs.  Called
+// while the server has no GPU work in flight, so a capture never overlaps other work.
+void prepare_round(Group& G, int mode) {
+  if (!G.stream || !G.e0 || !G.e1) throw psara::Error(PSARA_EDEVICE, "group stream or events unavailable");
   std::vector<psara_ctx*> ctxs;
-  for (auto& j : mem) ctxs.push_back(j->ctx);
+  for (auto& j : G.mem) ctxs.push_back(j->ctx);
   if (G.key != ctxs) {
-    G.reset();
-    if (mem[0]->req.precision == PSARA_FP64) {
+    G.drop_batch();
+    if (G.mem[0]->req.precision == PSARA_FP64) {
       std::vector<psara::Engine<double>*> e;
       for (auto* c : ctxs) e.push_back(c->f64.get());
-      G.bd.reset(new psara::Batch<double>(e, bs));
+      G.bd.reset(new psara::Batch<double>(e, G.stream));
     } else {
       std::vector<psara::Engine<float>*> e;
       for (auto* c : ctxs) e.push_back(c->f32.get());
-      G.bf.reset(new psara::Batch<float>(e, bs));
+      G.bf.reset(new psara::Batch<float>(e, G.stream));
     }
     G.key = ctxs;
   }
-  if (G.bd) G.bd->run(mode, k);
-  else G.bf->run(mode, k);
-  psara::hip_check(hipStreamSynchronize(bs), "batch round");
-  for (auto& j : mem) {
-    j->left -= k;
-    j->ctx->iterations += k;
+  if (G.bd) G.bd->capture(mode);
+  else G.bf->capture(mode);
+}
+
+// Queues one round of the group: graph launches only.
+void launch_round(Group& G, int mode, int quantum) {
+  int left = 1 << 30;
+  for (auto& j : G.mem) left = std::min(left, j->left);
+  int k = G.t_iter > 0.0 ? (int)std::min<double>(quantum, std::max(1.0, kRoundSeconds / G.t_iter)) : std::min(quantum, 8);
+  G.k = std::max(1, std::min(k, left));
+  psara::hip_check(hipEventRecord(G.e0, G.stream), "round start");
+  if (G.bd) G.bd->run(mode, G.k);
+  else G.bf->run(mode, G.k);
+  psara::hip_check(hipEventRecord(G.e1, G.stream), "round end");
+  G.launched = true;
+}
+
+// Waits for the group's round and books the iterations.
+void finish_round(Group& G) {
+  psara::hip_check(hipEventSynchronize(G.e1), "round wait");
+  float ms = 0.f;
+  psara::hip_check(hipEventElapsedTime(&ms, G.e0, G.e1), "round time");
+  const double t = 1e-3 * ms / G.k;
+  G.t_iter = G.t_iter > 0.0 ? 0.5 * (G.t_iter + t) : t;
+  for (auto& j : G.mem) {
+    j->left -= G.k;
+    j->ctx->iterations += G.k;
   }
+  G.launched = false;
 }
 
 // Moves a job whose stage has ended to its next stage (reweighting it), or finishes it.
@@ -185,10 +266,10 @@ bool advance(psara_server* S, Job& j) {
   while (j.left == 0) {
     if (j.stage == 0) {
       if (psara_coef_std(j.ctx, &j.delta) != PSARA_OK || !(j.delta > 0.0)) {
-        std::lock_guard<std::mutex> lk(S->mu);
         const std::string m = j.delta > 0.0 ? psara_last_error(j.ctx) : "initial estimate is zero: no reweighting scale";
         psara_destroy(j.ctx);
         j.ctx = nullptr;
+        std::lock_guard<std::mutex> lk(S->mu);
         retire(S, j, PSARA_REQ_FAILED, PSARA_EINVAL, m);
         return true;
       }
@@ -196,10 +277,10 @@ bool advance(psara_server* S, Job& j) {
     if (j.stage < j.req.cycles) {
       psara_status st = psara_reweight(j.ctx, j.delta);
       if (st != PSARA_OK) {
-        std::lock_guard<std::mutex> lk(S->mu);
         const std::string m = psara_last_error(j.ctx);
         psara_destroy(j.ctx);
         j.ctx = nullptr;
+        std::lock_guard<std::mutex> lk(S->mu);
         retire(S, j, PSARA_REQ_FAILED, st, m);
         return true;
       }
@@ -226,87 +307,103 @@ bool advance(psara_server* S, Job& j) {
   return false;
 }
 
-void fail_group(psara_server* S, std::map<std::tuple<int, int, int>, Group>& cache, const std::tuple<int, int, int>& key,
-                std::vector<JobP>& mem, psara_status st, const std::string& msg) {
-  cache.erase(key);
-  std::lock_guard<std::mutex> lk(S->mu);
+void fail_jobs(psara_server* S, std::vector<JobP>& mem, psara_status st, const std::string& msg) {
   for (auto& j : mem) {
     if (j->ctx) psara_destroy(j->ctx);
     j->ctx = nullptr;
     j->left = -1;
-    retire(S, *j, PSARA_REQ_FAILED, st, msg);
   }
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (auto& j : mem) retire(S, *j, PSARA_REQ_FAILED, st, msg);
+}
+
+GroupKey key_of(const Job& j) {
+  return std::make_tuple(stage_mode(j), (int)j.req.precision, j.req.taps, j.req.n);
 }
 
 void worker_loop(psara_server* S) {
   (void)hipSetDevice(S->device);
-  hipStream_t bs = nullptr;
-  if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) bs = nullptr;
-  std::vector<JobP> active;
-  std::map<std::tuple<int, int, int>, Group> cache;
+  std::vector<JobP> active, fresh;
+  std::map<GroupKey, std::unique_ptr<Group>> groups;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       if (active.empty()) S->cv.wait(lk, [&] { return S->stop || !S->ready.empty(); });
       if (S->stop) break;
       while (!S->ready.empty()) {
-        active.push_back(S->ready.front());
+        fresh.push_back(S->ready.front());
         S->ready.pop_front();
       }
     }
-    // stages of length zero end at once
-    bool changed = false;
-    for (auto& j : active) changed |= (j->left == 0);
-    if (changed) {
-      cache.clear();
-      std::vector<JobP> keep;
-      for (auto& j : active)
-        if (!advance(S, *j)) keep.push_back(j);
-      active.swap(keep);
-      S->cv.notify_all();
-      continue;
+    // the round of every group, queued on the groups' streams
+    std::map<GroupKey, std::vector<JobP>> members;
+    for (auto& j : active) members[key_of(*j)].push_back(j);
+    for (auto it = groups.begin(); it != groups.end();) {
+      if (members.count(it->first)) ++it;
+      else it = groups.erase(it);
     }
-    std::map<std::tuple<int, int, int>, std::vector<JobP>> groups;
-    for (auto& j : active) groups[std::make_tuple(stage_mode(*j), (int)j->req.precision, j->req.taps)].push_back(j);
-    for (auto it = cache.begin(); it != cache.end();) {
-      if (groups.count(it->first)) ++it;
-      else it = cache.erase(it);
-    }
-    for (auto& kv : groups) {
-      std::vector<JobP>& mem = kv.second;
-      int k = S->quantum;
-      for (auto& j : mem) k = std::min(k, j->left);
-      try {
-        run_group(cache[kv.first], mem, std::get<0>(kv.first), k, bs);
-      } catch (const std::exception& e) {
-        fail_group(S, cache, kv.first, mem, PSARA_EDEVICE, e.what());
-      } catch (const psara::Error& e) {
-        fail_group(S, cache, kv.first, mem, e.status, e.msg);
+    // first every capture (nothing of the server runs on the GPU now), then every launch
+    for (int phase = 0; phase < 2; ++phase) {
+      for (auto& kv : members) {
+        std::unique_ptr<Group>& G = groups[kv.first];
+        if (!G) G.reset(new Group());
+        if (phase == 0) G->mem = kv.second;
+        else if (G->mem.empty() || G->mem[0]->left < 0) continue;
+        try {
+          if (phase == 0) prepare_round(*G, std::get<0>(kv.first));
+          else launch_round(*G, std::get<0>(kv.first), S->quantum);
+        } catch (const psara::Error& e) {
+          G->drop_batch();
+          G->launched = false;
+          fail_jobs(S, G->mem, e.status, e.msg);
+        } catch (const std::exception& e) {
+          G->drop_batch();
+          G->launched = false;
+          fail_jobs(S, G->mem, PSARA_EDEVICE, e.what());
+        }
       }
     }
+    // device set-up of the newly admitted requests, overlapping the rounds on the GPU
+    for (auto& j : fresh) {
+      std::string msg;
+      const psara_status st = prepare_device(S, *j, msg);
+      if (st == PSARA_OK) {
+        active.push_back(j);
+      } else {
+        std::lock_guard<std::mutex> lk(S->mu);
+        retire(S, *j, PSARA_REQ_FAILED, st, msg);
+      }
+    }
+    bool notify = !fresh.empty();
+    fresh.clear();
+    for (auto& kv : groups) {
+      Group& G = *kv.second;
+      if (!G.launched) continue;
+      try {
+        finish_round(G);
+      } catch (const psara::Error& e) {
+        G.drop_batch();
+        G.launched = false;
+        fail_jobs(S, G.mem, e.status, e.msg);
+      }
+    }
+    // stage ends: reweighting or completion (a batch never outlives a member's context)
     std::vector<JobP> keep;
-    bool done_any = false;
     for (auto& j : active) {
-      if (j->left < 0) { done_any = true; continue; }
+      if (j->left < 0) { notify = true; continue; }
       if (j->left == 0) {
-        // the cached batches must not outlive a member's context
-        for (auto it = cache.begin(); it != cache.end();) {
-          if (std::find(it->second.key.begin(), it->second.key.end(), j->ctx) != it->second.key.end())
-            it = cache.erase(it);
-          else
-            ++it;
-        }
-        if (advance(S, *j)) { done_any = true; continue; }
+        for (auto& kv : groups)
+          if (kv.second->holds(j->ctx)) kv.second->drop_batch();
+        if (advance(S, *j)) { notify = true; continue; }
       }
       keep.push_back(j);
     }
     active.swap(keep);
-    if (done_any) S->cv.notify_all();
+    if (notify) S->cv.notify_all();
   }
-  cache.clear();
+  groups.clear();
   for (auto& j : active)
     if (j->ctx) psara_destroy(j->ctx);
-  if (bs) (void)hipStreamDestroy(bs);
 }
 
 }  // namespace
@@ -331,7 +428,7 @@ psara_status psara_server_create(psara_server** out, int device, size_t hbm_budg
   S->quantum = policy == PSARA_SERVE_FIFO ? (1 << 30) : quantum;
   S->t0 = std::chrono::steady_clock::now();
   try {
-    const int nsetup = policy == PSARA_SERVE_FIFO ? 1 : 2;
+    const int nsetup = policy == PSARA_SERVE_FIFO ? 1 : 4;
     for (int i = 0; i < nsetup; ++i) S->setup_threads.emplace_back(setup_loop, S.get());
     S->worker = std::thread(worker_loop, S.get());
   } catch (...) {

@@ -17,7 +17,8 @@ constexpr int kMaxTaps = 8;      // Kaiser-Bessel taps per dimension
 constexpr int kMaxCheb = 17;     // Chebyshev coefficients per tap (degree <= 16)
 constexpr int kMaxLevels = 8;
 constexpr int kRunMax = 32;         // longest run of same-window visibilities one lane group takes
-constexpr int kChunkEntries = 512;  // gridding entries per workgroup (staged in LDS)
+constexpr int kChunkEntries = 1024; // gridding entries per workgroup (staged in LDS)
+constexpr int kGridThreads = 512;   // threads per gridding workgroup (64 lane groups of 8)
 constexpr int kBatchChunk = 8;       // iterations per captured graph of a batch
 constexpr int kMaxDegridTile = 32;  // largest de-gridding tile side (the geometry picks 16 or 32)
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
@@ -42,6 +43,7 @@ enum CoefSlot { COEF_A = 0, COEF_GW, COEF_TMP, NUM_COEF };
 enum Scalar {
   SC_CFAC = 0,      // B = SC_CFAC * Bv (lazy l2-ball factor)
   SC_VNORM2,        // ||B~/rho2 - Y||^2 of the last dual-B step
+  SC_GFAC,          // factor of the last gridding pass, applied when its slots are summed
   SC_RES2,          // ||Y - phi(S)||^2
   SC_DOT,           // generic reduction results
   SC_NRM2,
@@ -82,9 +84,9 @@ struct ProbDesc {
   const int* run_len;
   const int* run_k0;      // packed window start of each run
   const int2* chunk_ent;  // list-entry range [lo, hi) of each gridding chunk
-  void* gpart;            // partial tiles of split gridding tiles: n_slots x kGridTile^2 cells
+  void* gpart;            // gridding partial slots: n_slots x (kGridTile + T - 1)^2 cells, k2-major
   const int4* chunks;     // gridding chunks {tile, first run, end run, partial slot or -1}
-  const int2* tile_slots; // per gridding tile: {first partial slot, count}, count 0 = in the grid
+  const int2* tile_slots; // per gridding tile: {first partial slot, count} (count 0: no visibilities)
   const void* kbpoly;     // T x (deg+1) per-tap kernel polynomial coefficients (ascending), type R
   const void* twiddle;    // K complex exp(-2 pi i j / K), type R
   const void* deapod;     // n scaling factors 1/psi_hat((j - n/2)/K), type R

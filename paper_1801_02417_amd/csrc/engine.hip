@@ -77,33 +77,22 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
     g.own_ptr[tile[m] + 1]++;
   }
   for (int t = 0; t < ntiles; ++t) g.own_ptr[t + 1] += g.own_ptr[t];
-  // gridding tiles (side kGridTile): every tile a window touches, at most two per dimension
+  // gridding: every visibility belongs to the kGridTile x kGridTile tile that holds its window
+  // start (a gridding tile lies inside one de-gridding tile, so its list, taken in sorted
+  // order, runs through the window starts in (k1, k2) order)
   const int tg = kGridTile, ntsg = g.ntsg, ntg = ntsg * ntsg;
-  auto touched = [&](int k, int* out) {
-    out[0] = k / tg;
-    const int e = ((k + T - 1) & (K - 1)) / tg;
-    if (e != out[0]) { out[1] = e; return 2; }
-    return 1;
-  };
+  auto owner = [&](int64_t p) { return ((g.k0[p] >> 16) / tg) * ntsg + (g.k0[p] & 0xffff) / tg; };
   g.list_ptr.assign(ntg + 1, 0);
-  for (int64_t p = 0; p < M; ++p) {
-    int a[2], b[2];
-    const int na = touched(g.k0[p] >> 16, a), nb = touched(g.k0[p] & 0xffff, b);
-    for (int i = 0; i < na; ++i)
-      for (int j = 0; j < nb; ++j) g.list_ptr[a[i] * ntsg + b[j] + 1]++;
-  }
+  for (int64_t p = 0; p < M; ++p) g.list_ptr[owner(p) + 1]++;
   for (int t = 0; t < ntg; ++t) g.list_ptr[t + 1] += g.list_ptr[t];
   g.list_idx.resize(g.list_ptr[ntg]);
   std::vector<int> fillp(g.list_ptr.begin(), g.list_ptr.end() - 1);
-  for (int64_t p = 0; p < M; ++p) {
-    int a[2], b[2];
-    const int na = touched(g.k0[p] >> 16, a), nb = touched(g.k0[p] & 0xffff, b);
-    for (int i = 0; i < na; ++i)
-      for (int j = 0; j < nb; ++j) g.list_idx[fillp[a[i] * ntsg + b[j]]++] = (int)p;
-  }
+  for (int64_t p = 0; p < M; ++p) g.list_idx[fillp[owner(p)]++] = (int)p;
   // runs: consecutive list entries of a tile with the same window start (their taps hit the
   // same cells), split at kRunMax; chunks of whole runs with <= kChunkEntries entries, runs
-  // ordered longest first inside a chunk so the lanes of a wave loop for similar lengths
+  // ordered longest first inside a chunk so the lanes of a wave loop for similar lengths.
+  // Every chunk accumulates its tile plus the T-1 halo in its own slot; the column inverse
+  // FFT sums the slots of a cell's tile and of the three tiles whose halos reach it.
   for (int t = 0; t < ntg; ++t) {
     std::vector<std::pair<int, int>> runs;
     for (int e = g.list_ptr[t]; e < g.list_ptr[t + 1];) {
@@ -112,9 +101,9 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
       runs.push_back({e, f - e});
       e = f;
     }
-    std::vector<int4> tile_chunks;
+    const int first_slot = g.n_slots;
     size_t r = 0;
-    do {
+    while (r < runs.size()) {
       const size_t r0 = r;
       int entries = 0;
       while (r < runs.size() && (entries + runs[r].second <= kChunkEntries || r == r0)) entries += runs[r++].second;
@@ -129,17 +118,10 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
         lo = std::min(lo, runs[q].first);
         hi = std::max(hi, runs[q].first + runs[q].second);
       }
-      if (r == r0) lo = hi = g.list_ptr[t];
-      tile_chunks.push_back(make_int4(t, base, base + (int)(r - r0), -1));
+      g.chunks.push_back(make_int4(t, base, base + (int)(r - r0), g.n_slots++));
       g.chunk_ent.push_back(make_int2(lo, hi));
-    } while (r < runs.size());
-    if (tile_chunks.size() > 1) {
-      g.tile_slots.push_back(make_int2(g.n_slots, (int)tile_chunks.size()));
-      for (auto& c : tile_chunks) c.w = g.n_slots++;
-    } else {
-      g.tile_slots.push_back(make_int2(0, 0));
     }
-    g.chunks.insert(g.chunks.end(), tile_chunks.begin(), tile_chunks.end());
+    g.tile_slots.push_back(make_int2(first_slot, g.n_slots - first_slot));
   }
   return g;
 }
@@ -158,14 +140,15 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += 256) S.p6.push_back(make_int4(prob, t, v, part++));
   }
   // gridding chunks, heaviest first (entries plus a flush cost per run as the work estimate)
-  // so the tail of the launch is short; the first item of a problem stores the l2-ball factor
+  // so the tail of the launch is short; the last (lightest) item of a problem stores the
+  // scalar factor of the pass
   std::vector<int> order(g.chunks.size());
   std::iota(order.begin(), order.end(), 0);
   auto cost = [&](int c) {
     return (g.chunk_ent[c].y - g.chunk_ent[c].x) + 3 * (g.chunks[c].z - g.chunks[c].y);
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-  for (size_t c = 0; c < order.size(); ++c) S.p7.push_back(make_int4(prob, order[c], c == 0 ? 1 : 0, 0));
+  for (size_t c = 0; c < order.size(); ++c) S.p7.push_back(make_int4(prob, order[c], c + 1 == order.size() ? 1 : 0, 0));
   *n_p6 = part;
 }
 
@@ -233,7 +216,7 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   h_.chunk_ent = upload<int2>(g.chunk_ent.data(), std::max<size_t>(1, g.chunk_ent.size()));
   h_.tile_slots = upload<int2>(g.tile_slots.data(), std::max<size_t>(1, g.tile_slots.size()));
   h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
-  h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * kGridTile * kGridTile);
+  h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * (kGridTile + g.T - 1) * (kGridTile + g.T - 1));
   // tables
   std::vector<double> poly = kb_poly(g.T, g.beta, h_.deg);
   h_.kbpoly = upload_conv(poly.data(), poly.size());

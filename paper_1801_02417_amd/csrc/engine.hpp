@@ -32,12 +32,12 @@ struct Geometry {
   std::vector<int> k0;            // packed window starts (k1 << 16 | k2), sorted order
   std::vector<double> frac;       // (f1, f2) per sorted visibility
   std::vector<int> own_ptr;       // per tile: range of visibilities whose window starts there
-  std::vector<int> list_ptr, list_idx;   // per gridding tile: every visibility whose window touches it
+  std::vector<int> list_ptr, list_idx;   // per gridding tile: the visibilities whose window starts in it
   // gridding work: runs of list entries sharing one window start (at most kRunMax long),
-  // grouped into chunks of at most kChunkEntries entries; a tile with several chunks sums
-  // their partial tiles when the column inverse FFT loads them
+  // grouped into chunks of at most kChunkEntries entries; every chunk writes its tile and
+  // the tile's halo to its own partial slot, summed when the column inverse FFT loads them
   std::vector<int> run_beg, run_len, run_k0;   // per run: first list entry, length, window start
-  std::vector<int4> chunks;              // {tile, first run, end run, partial slot or -1}
+  std::vector<int4> chunks;              // {tile, first run, end run, partial slot}
   std::vector<int2> chunk_ent;           // list-entry range [lo, hi) each chunk covers
   std::vector<int2> tile_slots;          // per gridding tile {first partial slot, count}
   int n_slots = 0;

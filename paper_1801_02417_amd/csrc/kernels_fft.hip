@@ -166,23 +166,31 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       if (k2 < K && r >= 0) c = half[(size_t)k2 * n + r];
       lds[q] = c;
     } else if (PASS == 2) {
-      // gridding tiles split over several chunks are summed here from their partial slots
+      // the gridded values: the partial slots of the cell's tile and of the tiles whose halos
+      // reach it (the previous tile in k1, in k2, and in both), in that order, times the
+      // factor the gridding pass left out
       const int l = q / K, k = q - l * K, k2 = line0 + l;
       if (k2 < K) {
-        const int ntg = P.ntile_side_g;
-        const int2 ts = P.tile_slots[(k / kGridTile) * ntg + k2 / kGridTile];
-        if (ts.y == 0) {
-          c = grid[(size_t)k2 * K + k];
-        } else {
-          const Cell<R>* part = (const Cell<R>*)P.gpart + (size_t)ts.x * kGridTile * kGridTile +
-                                (k2 % kGridTile) * kGridTile + (k % kGridTile);
-          c = part[0];
-          for (int sl = 1; sl < ts.y; ++sl) {
-            const Cell<R> o = part[(size_t)sl * kGridTile * kGridTile];
+        const int ntg = P.ntile_side_g, RG = kGridTile + P.T - 1;
+        const int t1 = k / kGridTile, t2 = k2 / kGridTile, a1 = k - t1 * kGridTile, a2 = k2 - t2 * kGridTile;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const int d1 = d & 1, d2 = d >> 1;
+          const int o1 = a1 + d1 * kGridTile, o2 = a2 + d2 * kGridTile;
+          if (o1 >= RG || o2 >= RG) continue;
+          const int s1 = (t1 - d1 + ntg) % ntg, s2 = (t2 - d2 + ntg) % ntg;
+          const int2 ts = P.tile_slots[s1 * ntg + s2];
+          const Cell<R>* part = (const Cell<R>*)P.gpart + (size_t)ts.x * RG * RG + o2 * RG + o1;
+#pragma unroll 4
+          for (int sl = 0; sl < ts.y; ++sl) {
+            const Cell<R> o = part[(size_t)sl * RG * RG];
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) c.s[ch] = cadd(c.s[ch], o.s[ch]);
           }
         }
+        const R f = R(P.scal[SC_GFAC]);
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) { c.s[ch].re *= f; c.s[ch].im *= f; }
       }
       lds[q] = c;
     } else {

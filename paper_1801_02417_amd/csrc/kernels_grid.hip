@@ -142,9 +142,11 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 // ---------------------------------------------------------------------------------------------
 // P7: grid (adjoint of G, after mixing by L^H).  items: {prob, chunk, writer flag, -}
 //
-// The grid is cut into kGridTile x kGridTile tiles; a chunk is a set of runs of one tile's
-// list, a run being visibilities with the same window start, so all their T x T taps land on
-// the same cells.  The chunk's entries (offsets and L^H-mixed values) are first staged in LDS
+// The grid is cut into kGridTile x kGridTile tiles and every visibility belongs to the tile
+// holding its window start, so it is gridded exactly once; the workgroup accumulates the tile
+// plus its (T-1)-wide halo on the high sides, (kGridTile + T - 1)^2 cells, which every window
+// starting in the tile stays inside.  A chunk is a set of runs of one tile's list, a run being
+// visibilities with the same window start, so all their T x T taps land on the same cells.  The chunk's entries (offsets and L^H-mixed values) are first staged in LDS
 // by the whole workgroup.  A group of 8 lanes then takes one run: lane i owns tap row i and
 // accumulates, over the run, the 8 cells of that row for the 8 real channels in registers
 // (the column weights are shared through lane shuffles), and adds the row to the tile once.
@@ -157,10 +159,12 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 // are at most 1), so no sum leaves the range of the conversion; the absolute rounding per
 // addition is at most 2^-50 (2^-62) of that bound.
 //
-// The finished tile goes to the grid, or -- when the tile was split into several chunks -- to
-// a partial slot; the column inverse FFT sums a split tile's slots in slot order as it loads.  MODE GR_DUAL: scale = c from the
-// de-grid partials (stored by the writer item); GR_PLAIN: scale = 1, or the stored c when
-// use_cfac is set.
+// The finished region goes to the chunk's partial slot; the column inverse FFT sums, for each
+// cell, the slots of its own tile and of the up to three tiles whose halos cover it, in a fixed
+// order, and multiplies the sum by the scalar factor of B, which the gridding leaves out: one
+// item per problem (the writer, the lightest chunk) stores that factor -- GR_DUAL: c, reduced
+// in a fixed order from the de-grid partials and also kept for the next iteration;
+// GR_PLAIN: 1, or the stored c when use_cfac is set.
 // Nearest 64-bit integer of an (already scaled) value.  FP32 data (|y| < 2^50): adding
 // 1.5 * 2^52 rounds y to an integer held in the low mantissa bits of the sum; subtracting the
 // bit pattern of 1.5 * 2^52 leaves it as a two's-complement integer (two instructions).  FP64
@@ -181,14 +185,15 @@ template <> struct Fixed<double> {
 };
 
 template <typename R, int MODE, int T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kGridThreads, 4)
 grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac) {
   constexpr int TG = kGridTile;
+  constexpr int RG = kGridTile + T - 1;            // tile plus halo
   constexpr int DEG = KbDeg<R>::value;
-  __shared__ unsigned long long acc[8 * TG * TG];   // channel-major: acc[c][k2 offset][k1 offset]
+  __shared__ unsigned long long acc[8 * RG * RG];   // channel-major: acc[c][k2 offset][k1 offset]
   __shared__ V2<R> sf[kChunkEntries];             // staged fractional offsets
   __shared__ V4<R> su[2 * kChunkEntries];         // staged mixed values, two V4 per entry
-  __shared__ double red[8];
+  __shared__ double red[2 * (kGridThreads / 64)];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
   const int4 ch = P.chunks[it.y];
@@ -197,23 +202,10 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   const int tile = ch.x;
   const int t1 = tile / ntg, t2 = tile - t1 * ntg;
   const int b1 = t1 * TG, b2 = t2 * TG;
-  for (int q = threadIdx.x; q < 8 * TG * TG; q += blockDim.x) acc[q] = 0ull;
+  for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
 
-  R scale = R(1);
-  if (MODE == GR_DUAL) {
-    const double v2 = block_sum_partials(P.partials, P.n_p6, red);
-    const double vn = sqrt(v2);
-    const double c = (vn > P.eps) ? P.rho2 * (1.0 - P.eps / vn) : 0.0;
-    scale = R(c);
-    if (it.z && threadIdx.x == 0) {
-      P.scal[SC_CFAC] = c;
-      P.scal[SC_VNORM2] = v2;
-    }
-  } else if (use_cfac) {
-    scale = R(P.scal[SC_CFAC]);
-  }
   // stage the chunk's entries: offsets and B L^H (I = B1 + B4, Q = B1 - B4, U = B2 + B3,
-  // V = i (B3 - B2)), scaled; sum the largest channel magnitude of each for the fixed point
+  // V = i (B3 - B2)); sum the largest channel magnitude of each for the fixed point
   const Cell<R>* __restrict__ bsrc = (const Cell<R>*)P.vis[src_slot];
   const V2<R>* __restrict__ frac = (const V2<R>*)P.vis_frac;
   KSum bound;
@@ -222,10 +214,10 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     sf[q] = frac[m];
     const Cell<R> b = bsrc[m];
     V4<R> u0, u1;
-    u0.x = (b.s[0].re + b.s[3].re) * scale; u0.y = (b.s[0].im + b.s[3].im) * scale;
-    u0.z = (b.s[0].re - b.s[3].re) * scale; u0.w = (b.s[0].im - b.s[3].im) * scale;
-    u1.x = (b.s[1].re + b.s[2].re) * scale; u1.y = (b.s[1].im + b.s[2].im) * scale;
-    u1.z = -(b.s[2].im - b.s[1].im) * scale; u1.w = (b.s[2].re - b.s[1].re) * scale;
+    u0.x = (b.s[0].re + b.s[3].re); u0.y = (b.s[0].im + b.s[3].im);
+    u0.z = (b.s[0].re - b.s[3].re); u0.w = (b.s[0].im - b.s[3].im);
+    u1.x = (b.s[1].re + b.s[2].re); u1.y = (b.s[1].im + b.s[2].im);
+    u1.z = -(b.s[2].im - b.s[1].im); u1.w = (b.s[2].re - b.s[1].re);
     su[2 * q] = u0;
     su[2 * q + 1] = u1;
     const R mx = fmax(fmax(fmax(fabs(u0.x), fabs(u0.y)), fmax(fabs(u0.z), fabs(u0.w))),
@@ -270,46 +262,47 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
       }
     }
     if (len > 0 && lane8 < T) {
-      const int c1 = ((pk >> 16) + lane8 - b1) & (K - 1);
-      if (c1 < TG) {
+      const int c1 = (pk >> 16) - b1 + lane8;              // the window start lies in the tile
+      unsigned long long* row = acc + c1;
 #pragma unroll
-        for (int j = 0; j < T; ++j) {
-          const int c2 = ((pk & 0xffff) + j - b2) & (K - 1);
-          if (c2 < TG) {
-            unsigned long long* cell = acc + c2 * TG + c1;
+      for (int j = 0; j < T; ++j) {
+        unsigned long long* cell = row + ((pk & 0xffff) - b2 + j) * RG;
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-              atomicAdd(cell + c * TG * TG, (unsigned long long)Fixed<R>::conv(a[j][c], fx));
-          }
-        }
+        for (int c = 0; c < 8; ++c)
+          atomicAdd(cell + c * RG * RG, (unsigned long long)Fixed<R>::conv(a[j][c], fx));
       }
     }
   }
   __syncthreads();
-  Cell<R>* __restrict__ dst;
-  size_t stride;
-  if (ch.w < 0) {                       // the whole tile is in this chunk: write the grid
-    dst = (Cell<R>*)P.grid + (size_t)b2 * K + b1;
-    stride = K;
-  } else {                              // one of several chunks: write its partial slot
-    dst = (Cell<R>*)P.gpart + (size_t)ch.w * TG * TG;
-    stride = TG;
-  }
+  Cell<R>* __restrict__ dst = (Cell<R>*)P.gpart + (size_t)ch.w * RG * RG;
   const double inv = ldexp(1.0, -E);
-  for (int q = threadIdx.x; q < TG * TG; q += blockDim.x) {
-    const int a2 = q / TG, a1 = q - a2 * TG;        // a2: k2 offset, a1: k1 offset
+  for (int q = threadIdx.x; q < RG * RG; q += blockDim.x) {
     Cell<R> c;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-      c.s[s] = cmk(R((double)(long long)acc[(2 * s) * TG * TG + q] * inv),
-                   R((double)(long long)acc[(2 * s + 1) * TG * TG + q] * inv));
-    dst[(size_t)a2 * stride + a1] = c;
+      c.s[s] = cmk(R((double)(long long)acc[(2 * s) * RG * RG + q] * inv),
+                   R((double)(long long)acc[(2 * s + 1) * RG * RG + q] * inv));
+    dst[q] = c;
+  }
+  if (it.z) {                      // the writer item: the factor the column inverse FFT applies
+    if (MODE == GR_DUAL) {
+      const double v2 = block_sum_partials(P.partials, P.n_p6, red);
+      if (threadIdx.x == 0) {
+        const double vn = sqrt(v2);
+        const double c = (vn > P.eps) ? P.rho2 * (1.0 - P.eps / vn) : 0.0;
+        P.scal[SC_CFAC] = c;
+        P.scal[SC_VNORM2] = v2;
+        P.scal[SC_GFAC] = c;
+      }
+    } else if (threadIdx.x == 0) {
+      P.scal[SC_GFAC] = use_cfac ? P.scal[SC_CFAC] : 1.0;
+    }
   }
 }
 
 template <typename R, int T>
 void launch_grid_t(int mode, const LaunchArgs& a, int src_slot, int use_cfac) {
-  const dim3 grid(a.nitems), block(256);
+  const dim3 grid(a.nitems), block(kGridThreads);
   if (mode == GR_DUAL) {
     hipLaunchKernelGGL((grid_kernel<R, GR_DUAL, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
   } else {

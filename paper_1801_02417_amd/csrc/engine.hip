@@ -139,16 +139,16 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
   for (int t = 0; t < ntiles; ++t) {
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += 256) S.p6.push_back(make_int4(prob, t, v, part++));
   }
-  // gridding chunks, heaviest first (entries plus a flush cost per run as the work estimate)
-  // so the tail of the launch is short; the last (lightest) item of a problem stores the
-  // scalar factor of the pass
+  // gridding: first the item that stores the pass's scalar factor, then the chunks heaviest
+  // first (entries plus a flush cost per run as the work estimate) so the tail is short
   std::vector<int> order(g.chunks.size());
   std::iota(order.begin(), order.end(), 0);
   auto cost = [&](int c) {
     return (g.chunk_ent[c].y - g.chunk_ent[c].x) + 3 * (g.chunks[c].z - g.chunks[c].y);
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-  for (size_t c = 0; c < order.size(); ++c) S.p7.push_back(make_int4(prob, order[c], c + 1 == order.size() ? 1 : 0, 0));
+  S.p7.push_back(make_int4(prob, -1, 0, 0));
+  for (size_t c = 0; c < order.size(); ++c) S.p7.push_back(make_int4(prob, order[c], 0, 0));
   *n_p6 = part;
 }
 

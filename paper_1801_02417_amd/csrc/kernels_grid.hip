@@ -140,7 +140,7 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 }
 
 // ---------------------------------------------------------------------------------------------
-// P7: grid (adjoint of G, after mixing by L^H).  items: {prob, chunk, writer flag, -}
+// P7: grid (adjoint of G, after mixing by L^H).  items: {prob, chunk (-1: the factor item), -, -}
 //
 // The grid is cut into kGridTile x kGridTile tiles and every visibility belongs to the tile
 // holding its window start, so it is gridded exactly once; the workgroup accumulates the tile
@@ -162,9 +162,9 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 // The finished region goes to the chunk's partial slot; the column inverse FFT sums, for each
 // cell, the slots of its own tile and of the up to three tiles whose halos cover it, in a fixed
 // order, and multiplies the sum by the scalar factor of B, which the gridding leaves out: one
-// item per problem (the writer, the lightest chunk) stores that factor -- GR_DUAL: c, reduced
-// in a fixed order from the de-grid partials and also kept for the next iteration;
-// GR_PLAIN: 1, or the stored c when use_cfac is set.
+// item per problem (chunk index -1, first in the work list, so it runs beside the chunks)
+// stores that factor -- GR_DUAL: c, reduced in a fixed order from the de-grid partials and
+// also kept for the next iteration; GR_PLAIN: 1, or the stored c when use_cfac is set.
 // Nearest 64-bit integer of an (already scaled) value.  FP32 data (|y| < 2^50): adding
 // 1.5 * 2^52 rounds y to an integer held in the low mantissa bits of the sum; subtracting the
 // bit pattern of 1.5 * 2^52 leaves it as a two's-complement integer (two instructions).  FP64
@@ -196,6 +196,21 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   __shared__ double red[2 * (kGridThreads / 64)];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (it.y < 0) {                  // the factor item: the factor the column inverse FFT applies
+    if (MODE == GR_DUAL) {
+      const double v2 = block_sum_partials(P.partials, P.n_p6, red);
+      if (threadIdx.x == 0) {
+        const double vn = sqrt(v2);
+        const double c = (vn > P.eps) ? P.rho2 * (1.0 - P.eps / vn) : 0.0;
+        P.scal[SC_CFAC] = c;
+        P.scal[SC_VNORM2] = v2;
+        P.scal[SC_GFAC] = c;
+      }
+    } else if (threadIdx.x == 0) {
+      P.scal[SC_GFAC] = use_cfac ? P.scal[SC_CFAC] : 1.0;
+    }
+    return;
+  }
   const int4 ch = P.chunks[it.y];
   const int2 ent = P.chunk_ent[it.y];
   const int K = P.K, ntg = P.ntile_side_g;
@@ -283,20 +298,6 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
       c.s[s] = cmk(R((double)(long long)acc[(2 * s) * RG * RG + q] * inv),
                    R((double)(long long)acc[(2 * s + 1) * RG * RG + q] * inv));
     dst[q] = c;
-  }
-  if (it.z) {                      // the writer item: the factor the column inverse FFT applies
-    if (MODE == GR_DUAL) {
-      const double v2 = block_sum_partials(P.partials, P.n_p6, red);
-      if (threadIdx.x == 0) {
-        const double vn = sqrt(v2);
-        const double c = (vn > P.eps) ? P.rho2 * (1.0 - P.eps / vn) : 0.0;
-        P.scal[SC_CFAC] = c;
-        P.scal[SC_VNORM2] = v2;
-        P.scal[SC_GFAC] = c;
-      }
-    } else if (threadIdx.x == 0) {
-      P.scal[SC_GFAC] = use_cfac ? P.scal[SC_CFAC] : 1.0;
-    }
   }
 }
 

@@ -40,18 +40,22 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   const int W = ts + T - 1;
   const Cell<R>* __restrict__ grid = (const Cell<R>*)P.grid;
   const int b1 = t1 * ts, b2 = t2 * ts;
-  for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
-    const int a = q / W, b = q - a * W;                      // a: k2 offset, b: k1 offset
-    win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + b) & (K - 1))];
+  // the item's visibilities are sorted by window start k1 within the tile, so they use only
+  // the k1 offsets [lo, hi + T - 1] of the tile window: stage that band, Wb wide
+  const int vend = min(it.z + (int)blockDim.x, P.own_ptr[tile + 1]);
+  const int lo = (P.vis_k0[it.z] >> 16) - b1, hi = (P.vis_k0[vend - 1] >> 16) - b1;
+  const int Wb = hi - lo + T;
+  for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {
+    const int a = q / Wb, b = q - a * Wb;                    // a: k2 offset, b: k1 offset - lo
+    win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + lo + b) & (K - 1))];
   }
   __syncthreads();
 
-  const int vend = min(it.z + (int)blockDim.x, P.own_ptr[tile + 1]);
   const int m = it.z + threadIdx.x;
   KSum acc;
   if (m < vend) {
     const int pk = P.vis_k0[m];
-    const int r1 = (pk >> 16) - b1, r2 = (pk & 0xffff) - b2;
+    const int r1 = (pk >> 16) - b1 - lo, r2 = (pk & 0xffff) - b2;
     const V2<R> f = ((const V2<R>*)P.vis_frac)[m];
     R w1[T], w2[T];
     kb_weights<R, T>(f.x, (const R*)P.kbpoly, w1);
@@ -61,7 +65,7 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
     for (int s = 0; s < 4; ++s) v[s] = cmk(R(0), R(0));
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-      const Cell<R>* row = win + (r2 + j) * W + r1;
+      const Cell<R>* row = win + (r2 + j) * Wb + r1;
       cplx<R> t[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) t[s] = cmk(R(0), R(0));

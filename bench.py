@@ -221,6 +221,29 @@ def progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def np_study(P, wk) -> dict:
+    """The synthetic analogue of the paper's polarization-error table: a 128x128 ring + jet with
+    polarization fraction up to 0.95, 6-station coverage (6000 rows), 30 dB, solved with the
+    full schedule (initialisation and five reweighting cycles, 2000 iterations) with and
+    without the polarization constraint; N_p is the share of pixels whose polarized intensity
+    exceeds I by more than zeta."""
+    wl = wk.np_study()
+    out = {"workload": "128x128, polarization fraction <= 0.95, 6 stations, 6000 visibilities, 30 dB, "
+                       "2000 iterations (initialisation + 5 cycles)"}
+    stages = [wl.iters // (wl.cycles + 1)] * wl.cycles
+    stages.append(wl.iters - sum(stages))
+    for name, mode in (("with_constraint", P.PSARA_CONSTRAINED), ("without_constraint", P.PSARA_UNCONSTRAINED)):
+        s, _, _ = ready_solver(P, wl)
+        rep = s.reweighted_solve(mode, stages)
+        img = s.image()
+        truth = wl.truth.reshape(-1, 4)
+        out[name] = {"n_p_percent": round(rep["n_p"], 3), "snr_db": round(snr_db(img, truth), 3),
+                     "snr_I_db": round(snr_db(img[:, 0], truth[:, 0]), 3),
+                     "residual_over_eps": round(rep["residual"] / rep["epsilon"], 6)}
+        s.close()
+    return out
+
+
 def main() -> int:
     faulthandler.enable()
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
@@ -234,6 +257,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=120,
                     help="requests of the served form at 20/s (0: skip; 1200 is the full 60 s stream)")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--no-np-study", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 10 times (to scale HBM counters)")
     args = ap.parse_args()
@@ -322,6 +346,9 @@ def main() -> int:
     }
     s.close()
     progress(f"256x256 / 2e5-visibility iteration rate {its:.1f} iters/s")
+    if not args.no_np_study:
+        progress("polarization-error study (config 1, with / without the constraint)")
+        line["np_study"] = np_study(P, wk)
     if args.batch_solves > 0:
         progress(f"batched form: {args.batch_solves} solves")
         line["batched_form"] = batched_form(P, wk, args.batch_solves, [100, 100, 100])

@@ -61,10 +61,10 @@ def smooth_field(rng: np.random.Generator, n: int) -> np.ndarray:
     return (f - lo) / (hi - lo)
 
 
-def add_polarisation(rng: np.random.Generator, I: np.ndarray) -> np.ndarray:
-    """Stokes cube from I: m ~ smooth in [0, 0.6], chi smooth in [-pi/2, pi/2], V = 0.01 I."""
+def add_polarisation(rng: np.random.Generator, I: np.ndarray, max_fraction: float = 0.6) -> np.ndarray:
+    """Stokes cube from I: m ~ smooth in [0, max_fraction], chi smooth in [-pi/2, pi/2], V = 0.01 I."""
     n = I.shape[0]
-    m = 0.6 * smooth_field(rng, n)
+    m = max_fraction * smooth_field(rng, n)
     chi = 0.5 * math.pi * (2.0 * smooth_field(rng, n) - 1.0)
     S = np.empty((n, n, 4))
     S[..., 0] = I
@@ -233,6 +233,17 @@ def tiny(n: int = 16, M: int = 150, taps: int = 6, levels: int = 2, seed: int = 
     uv = gaussian_uv(rng, M)
     return Workload(f"tiny{n}", n, M, taps=taps, oversample=2, levels=levels, isnr_db=isnr_db,
                     iters=300, cycles=2, truth=S, uv=uv, noise=unit_noise(rng, M))
+
+
+def np_study(seed: int = BASE_SEED + 11) -> Workload:
+    """The polarization-error study: 128x128 ring+jet with polarization fraction up to 0.95 (close
+    to the cone), sparse coverage from 6 stations (6000 rows), 30 dB, 2000 iterations."""
+    rng = np.random.default_rng(seed)
+    n, M = 128, 6000
+    S = add_polarisation(rng, ring_jet_image(rng, n), 0.95)
+    uv = arc_uv(rng, M, stations=6)
+    return Workload("np_study", n, M, taps=8, oversample=2, levels=4, isnr_db=30.0,
+                    iters=2000, cycles=5, truth=S, uv=uv, noise=unit_noise(rng, M))
 
 
 CONFIGS = {0: config0, 1: config1, 2: config2}

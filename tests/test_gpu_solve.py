@@ -12,12 +12,12 @@ from tests.gpu_common import P, say, rel_err, solver_for
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_alg2(wl, b, prec, stages, phi_norm=None):
+def _gpu_alg2(wl, b, prec, stages, phi_norm=None, mode=P.PSARA_CONSTRAINED):
     s = solver_for(wl, wl.n, wl.taps, prec, levels=wl.levels, gamma=b.gamma)
     s.set_data(b.pb.Y, b.pb.eps)
     s.opnorm(300, 1e-9)
     s.set_steps(b.pb.tau, b.pb.rho1, b.pb.rho2, b.pb.rho3)
-    rep = s.reweighted_solve(P.PSARA_CONSTRAINED, stages, 10.0)
+    rep = s.reweighted_solve(mode, stages, 10.0)
     return s, rep
 
 
@@ -53,6 +53,31 @@ def test_config0_full_solve(prec, tol):
         assert rep["iterations"] == wl.iters
         obj = metrics.weighted_l1(b.sara.adjoint, st.S, gW / b.gamma)
         assert abs(rep["objective"] - obj) <= (1e-9 if prec == "fp64" else 1e-4) * obj
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_config0_unconstrained_solve_and_np(prec, tol):
+    """Polarized SARA without the polarization constraint (Sec. 4.2: U', no epigraph terms)
+    on config 0 against the oracle's "nocons" run, and the polarization-error share N_p of
+    both estimates: the constrained solve's N_p is no larger than the unconstrained one's."""
+    wl = wk.config0()
+    b = problem.build(wl)
+    stages = pd.split_iterations(wl.iters, wl.cycles + 1)
+    st, _, _ = pd.alg2(b.pb, b.gamma, stages, len(stages) - 1, mode="nocons")
+    st_c, _, _ = _oracle_alg2(b, stages)
+    s, rep = _gpu_alg2(wl, b, prec, stages, mode=P.PSARA_UNCONSTRAINED)
+    try:
+        errs = _per_stokes(s.image(), st.S)
+        _, _, np_u = metrics.polarization_error(b.mop, st.S, b.pb.Y)
+        _, _, np_c = metrics.polarization_error(b.mop, st_c.S, b.pb.Y)
+        say(f"[solve] config0 unconstrained {prec}: per-Stokes rel err {['%.2e' % e for e in errs]}; "
+            f"N_p gpu {rep['n_p']:.3f}% oracle {np_u:.3f}% (constrained oracle {np_c:.3f}%)")
+        assert max(errs) <= tol
+        if prec == "fp64":
+            assert abs(rep["n_p"] - np_u) <= 1e-9
+        assert np_c <= np_u
     finally:
         s.close()
 

@@ -146,6 +146,21 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   Cell<R>* __restrict__ grid = (Cell<R>*)P.grid;
   const int nthr = CELLS / 2;
 
+  // the partial-slot table of the gridding tiles this workgroup's lines read (their tile rows
+  // and the rows before them), staged once so the per-cell gathers index LDS
+  constexpr int kTslMax = CELLS / 256 + 2048 / 8;
+  __shared__ int2 tsl[PASS == 2 ? kTslMax : 1];
+  int trow0 = 0;
+  if (PASS == 2) {
+    const int ntg = P.ntile_side_g;
+    trow0 = line0 / kGridTile - 1;
+    const int ntr = min(K - 1, line0 + lines - 1) / kGridTile - trow0 + 1;
+    for (int i = threadIdx.x; i < ntr * ntg; i += nthr) {
+      const int rr = i / ntg, u1 = i - rr * ntg;
+      tsl[i] = P.tile_slots[u1 * ntg + (trow0 + rr + ntg) % ntg];
+    }
+    __syncthreads();
+  }
   // ---- load ----
   for (int q = threadIdx.x; q < lines * K; q += nthr) {
     Cell<R> c = zero_cell<R>();
@@ -178,8 +193,8 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
           const int d1 = d & 1, d2 = d >> 1;
           const int o1 = a1 + d1 * kGridTile, o2 = a2 + d2 * kGridTile;
           if (o1 >= RG || o2 >= RG) continue;
-          const int s1 = (t1 - d1 + ntg) % ntg, s2 = (t2 - d2 + ntg) % ntg;
-          const int2 ts = P.tile_slots[s1 * ntg + s2];
+          const int s1 = (t1 - d1 + ntg) % ntg;
+          const int2 ts = tsl[(t2 - d2 - trow0) * ntg + s1];
           const Cell<R>* part = (const Cell<R>*)P.gpart + (size_t)ts.x * RG * RG + o2 * RG + o1;
 #pragma unroll 4
           for (int sl = 0; sl < ts.y; ++sl) {

@@ -286,6 +286,10 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
 #pragma unroll
       for (int j = 0; j < T; ++j) {
         unsigned long long* cell = row + ((pk & 0xffff) - b2 + j) * RG;
+        // one tap column at a time: the empty asm (ordered with the atomics) keeps the
+        // compiler from widening all T x 8 sums to 64 bits at once, which would spill
+        asm volatile("" : "+v"(a[j][0]), "+v"(a[j][1]), "+v"(a[j][2]), "+v"(a[j][3]),
+                          "+v"(a[j][4]), "+v"(a[j][5]), "+v"(a[j][6]), "+v"(a[j][7]) :: "memory");
 #pragma unroll
         for (int c = 0; c < 8; ++c)
           atomicAdd(cell + c * RG * RG, (unsigned long long)Fixed<R>::conv(a[j][c], fx));

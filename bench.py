@@ -66,7 +66,7 @@ def source_hash(name: str) -> str:
 def committed_traffic(pass_id: int):
     """HBM bytes per launch from the committed rocprof counter summary, if it was taken on the
     current source of that pass's kernel; otherwise None."""
-    path = os.path.join(ROOT, "profiles", "traffic_config2.json")
+    path = os.path.join(ROOT, "profiles", "traffic_ring256.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -87,7 +87,7 @@ def cpu_baseline(iters: int) -> dict:
 
     cores = min(16, len(os.sched_getaffinity(0)))
     with threadpool_limits(limits=cores):
-        wl = wk.config2()
+        wl = wk.ring256()
         b = problem.build(wl, norm_rtol=1e-3, norm_max_iter=20)
         J = b.sara.J
         gW = b.gamma * np.ones((J, 4))
@@ -217,6 +217,42 @@ def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dic
     return out
 
 
+def large_form(P, wk, iters: int) -> dict:
+    """One 512 x 512 x 4 solve with 1e6 visibility rows (the served mix's large request), all
+    terms active: iteration rate and per-pass times of the captured-graph iteration."""
+    import torch
+
+    wl = wk.batch_request(0, sides=(512,))
+    s = ready_solver(P, wl, norm_iters=100, norm_rtol=1e-4)[0]
+    s.solve(P.PSARA_NNLS_INIT, 20, report=False)
+    P.psara_reweight(s.ctx, P.psara_coef_std(s.ctx))
+    s.solve(P.PSARA_CONSTRAINED, 16, report=False)              # graph capture and warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.solve(P.PSARA_CONSTRAINED, iters, report=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = s.profile_passes(P.PSARA_CONSTRAINED, 8)
+    s.close()
+    return {"n": wl.n, "M": wl.M, "iters": iters, "iters_per_s": round(iters / dt, 1),
+            "passes_ms": {P.PASS_NAMES[i]: round(ms[i], 4) for i in range(9) if ms[i] > 0}}
+
+
+def profile_run(P, wk, form: str, iters: int) -> dict:
+    """Only the iterations of one form, for a profiler run: `batch` = the 64-solve batched form
+    (10 initialisation iterations, a reweighting, `iters` constrained iterations, every pass one
+    launch over all solves), `large` = the 512 x 512, 1e6-visibility solve."""
+    if form == "large":
+        return {"profile_form": "large", **large_form(P, wk, iters)}
+    solvers = [ready_solver(P, wk.batch_request(i), norm_iters=50, norm_rtol=1e-4)[0] for i in range(64)]
+    t0 = time.perf_counter()
+    P.batch_reweighted_solve(solvers, P.PSARA_CONSTRAINED, [10, iters])
+    dt = time.perf_counter() - t0
+    for s in solvers:
+        s.close()
+    return {"profile_form": "batch", "solves": 64, "iters": 10 + iters, "wall_s": round(dt, 3)}
+
+
 def progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -258,6 +294,11 @@ def main() -> int:
                     help="requests of the served form at 20/s (0: skip; 1200 is the full 60 s stream)")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-np-study", action="store_true")
+    ap.add_argument("--large-iters", type=int, default=400,
+                    help="timed iterations of the 512x512 / 1e6-visibility solve (0: skip)")
+    ap.add_argument("--profile-form", choices=["batch", "large"],
+                    help="only run the iterations of that form (for rocprofv3), then exit")
+    ap.add_argument("--profile-form-iters", type=int, default=40)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 10 times (to scale HBM counters)")
     args = ap.parse_args()
@@ -284,8 +325,11 @@ def main() -> int:
         print(json.dumps({"calibration": "copy", "bytes_read_per_launch": a.numel() * 4,
                           "bytes_written_per_launch": b.numel() * 4, "launches": 10}), flush=True)
         return 0
+    if args.profile_form:
+        print(json.dumps(profile_run(P, wk, args.profile_form, args.profile_form_iters)), flush=True)
+        return 0
     stream = torch.cuda.current_stream()
-    wl = wk.config2()
+    wl = wk.ring256()
     n, M, N = wl.n, wl.M, wl.n * wl.n
     s = P.Solver(n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED, hip_stream=stream.cuda_stream)
     # synthetic measurements on the device: Y = phi(S_true) + sigma E, sigma from the input SNR,
@@ -347,8 +391,12 @@ def main() -> int:
     s.close()
     progress(f"256x256 / 2e5-visibility iteration rate {its:.1f} iters/s")
     if not args.no_np_study:
-        progress("polarization-error study (config 1, with / without the constraint)")
+        progress("polarization-error study (128x128 ring + jet, with / without the constraint)")
         line["np_study"] = np_study(P, wk)
+    if args.large_iters > 0:
+        progress("large form: 512x512, 1e6 visibilities")
+        line["large_form"] = large_form(P, wk, args.large_iters)
+        progress(f"large form: {line['large_form']['iters_per_s']} iters/s")
     if args.batch_solves > 0:
         progress(f"batched form: {args.batch_solves} solves")
         line["batched_form"] = batched_form(P, wk, args.batch_solves, [100, 100, 100])

@@ -10,6 +10,11 @@
       FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for
       a plain device copy of known size (bench.py --calibrate-copy), stored with the SHA-256 of
       the kernel's source file so that a later change of the kernel invalidates the figure.
+  python -m paper_1801_02417_amd.profile_summary bandwidth --trace kernel_trace.csv --fetch F.csv
+         --write W.csv --cal-fetch CF.csv --cal-write CW.csv [--min-dispatches 8]
+      per kernel, over the dispatches of its most frequent grid size (the launches of the
+      profiled form rather than set-up work): average duration from the kernel trace, HBM bytes
+      from the scaled counters, and the achieved HBM bandwidth as a share of 8 TB/s.
 """
 from __future__ import annotations
 
@@ -93,6 +98,54 @@ def traffic(a) -> None:
     print(json.dumps(out, indent=1))
 
 
+HBM_PEAK_GBS = 8000.0
+
+
+def _grid(r: dict) -> int:
+    if "Grid_Size" in r:
+        return int(r["Grid_Size"])
+    return int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y", 1) or 1) * int(r.get("Grid_Size_Z", 1) or 1)
+
+
+def _per_launch_counter(path: str, counter: str) -> dict:
+    """(kernel, grid size) -> mean counter value per dispatch."""
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            agg[(r["Kernel_Name"], _grid(r))].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def bandwidth(a) -> None:
+    dur = collections.defaultdict(list)
+    for r in csv.DictReader(open(a.trace)):
+        dur[(r["Kernel_Name"], _grid(r))].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    fetch = _per_launch_counter(a.fetch, "FETCH_SIZE")
+    write = _per_launch_counter(a.write, "WRITE_SIZE")
+    cf, cw = pmc_means([a.cal_fetch]), pmc_means([a.cal_write])
+    copy = "__amd_rocclr_copyBuffer"
+    f_scale = COPY_BYTES / (_counter(cf, copy, "FETCH_SIZE") * 1024.0)
+    w_scale = COPY_BYTES / (_counter(cw, copy, "WRITE_SIZE") * 1024.0)
+    best = {}
+    for (k, g), v in dur.items():
+        if len(v) >= a.min_dispatches and (k not in best or len(v) > len(dur[(k, best[k])])):
+            best[k] = g
+    rows = []
+    for k, g in best.items():
+        d = dur[(k, g)]
+        us = sum(d) / len(d) / 1e3
+        fb = fetch.get((k, g), float("nan")) * 1024.0 * f_scale
+        wb = write.get((k, g), float("nan")) * 1024.0 * w_scale
+        gbs = (fb + wb) / (us * 1e-6) / 1e9
+        rows.append((sum(d), short(k), g, len(d), us, fb / 1e6, wb / 1e6, gbs))
+    rows.sort(reverse=True)
+    print(f"FETCH_SIZE scaled by {f_scale:.4f}, WRITE_SIZE by {w_scale:.4f} (plain-copy calibration)\n")
+    print("| kernel | grid (threads) | dispatches | avg us | fetch MB | write MB | HBM GB/s | % of 8 TB/s |")
+    print("|---|---|---|---|---|---|---|---|")
+    for _, k, g, nd, us, f, w, gbs in rows:
+        print(f"| {k} | {g} | {nd} | {us:.2f} | {f:.2f} | {w:.2f} | {gbs:.0f} | {100 * gbs / HBM_PEAK_GBS:.1f} |")
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -103,8 +156,14 @@ def main() -> int:
     t = sub.add_parser("traffic")
     for name in ("--fetch", "--write", "--cal-fetch", "--cal-write", "--out"):
         t.add_argument(name, required=True)
+    b = sub.add_parser("bandwidth")
+    for name in ("--trace", "--fetch", "--write", "--cal-fetch", "--cal-write"):
+        b.add_argument(name, required=True)
+    b.add_argument("--min-dispatches", type=int, default=8)
     a = ap.parse_args()
-    if a.cmd == "stats":
+    if a.cmd == "bandwidth":
+        bandwidth(a)
+    elif a.cmd == "stats":
         stats(a.csv)
     elif a.cmd == "pmc":
         pmc(a.csv)

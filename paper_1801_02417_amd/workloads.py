@@ -173,33 +173,33 @@ def unit_noise(rng: np.random.Generator, M: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # configurations
 # ----------------------------------------------------------------------------
-def config0(seed: int = BASE_SEED + 0) -> Workload:
+def blobs32(seed: int = BASE_SEED + 0) -> Workload:
     """32x32, 3 blobs, 600 Gaussian-density uv points, KB 6x6, 30 dB, 3 levels."""
     rng = np.random.default_rng(seed)
     n, M = 32, 600
     S = add_polarisation(rng, blobs_image(rng, n, 3))
     uv = gaussian_uv(rng, M)
-    return Workload("config0", n, M, taps=6, oversample=2, levels=3, isnr_db=30.0,
+    return Workload("blobs32", n, M, taps=6, oversample=2, levels=3, isnr_db=30.0,
                     iters=300, cycles=2, truth=S, uv=uv, noise=unit_noise(rng, M))
 
 
-def config1(seed: int = BASE_SEED + 1) -> Workload:
+def ring128(seed: int = BASE_SEED + 1) -> Workload:
     """128x128 ring+jet, 8-station arcs with 12000 samples, KB 8x8, 20 dB, 4 levels."""
     rng = np.random.default_rng(seed)
     n, M = 128, 12000
     S = add_polarisation(rng, ring_jet_image(rng, n))
     uv = arc_uv(rng, M)
-    return Workload("config1", n, M, taps=8, oversample=2, levels=4, isnr_db=20.0,
+    return Workload("ring128", n, M, taps=8, oversample=2, levels=4, isnr_db=20.0,
                     iters=2000, cycles=5, truth=S, uv=uv, noise=unit_noise(rng, M))
 
 
-def config2(seed: int = BASE_SEED + 2) -> Workload:
+def ring256(seed: int = BASE_SEED + 2) -> Workload:
     """256x256 ring+jet+20 knots, 1e5 Gaussian + 1e5 arc uv points, KB 8x8, 20 dB, 4 levels."""
     rng = np.random.default_rng(seed)
     n, M = 256, 200000
     S = add_polarisation(rng, add_knots(rng, ring_jet_image(rng, n), 20))
     uv = np.concatenate([gaussian_uv(rng, M // 2), arc_uv(rng, M - M // 2)], axis=0)
-    return Workload("config2", n, M, taps=8, oversample=2, levels=4, isnr_db=20.0,
+    return Workload("ring256", n, M, taps=8, oversample=2, levels=4, isnr_db=20.0,
                     iters=300, cycles=2, truth=S, uv=uv, noise=unit_noise(rng, M))
 
 
@@ -246,7 +246,7 @@ def np_study(seed: int = BASE_SEED + 11) -> Workload:
                     iters=2000, cycles=5, truth=S, uv=uv, noise=unit_noise(rng, M))
 
 
-CONFIGS = {0: config0, 1: config1, 2: config2}
+WORKLOADS = {"blobs32": blobs32, "ring128": ring128, "ring256": ring256}
 
 
 def poisson_arrivals(count: int, rate: float, seed: int = BASE_SEED * 1000 + 999) -> np.ndarray:

@@ -73,7 +73,7 @@ def test_batch_equals_alone_bitwise(prec):
 
 
 def test_batch_member_matches_oracle():
-    wl = wk.config0()
+    wl = wk.blobs32()
     b = problem.build(wl)
     stages = [20, 10, 10]
     ref, _, _ = pd.alg2(b.pb, b.gamma, stages, 2)

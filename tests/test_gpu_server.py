@@ -88,7 +88,7 @@ def test_small_budget_queues():
 
 
 def test_data_gamma_matches_oracle():
-    wl = wk.config0()
+    wl = wk.blobs32()
     b = problem.build(wl)
     ctx = P.psara_create(0)
     try:

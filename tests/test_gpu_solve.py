@@ -30,12 +30,12 @@ def _per_stokes(S, R):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
-def test_config0_full_solve(prec, tol):
-    """Config 0: 32x32, 600 uv, KB 6, 3 levels, 300 iterations = init + 2 reweighting cycles."""
-    wl = wk.config0()
+def test_blobs32_full_solve(prec, tol):
+    """Blob workload: 32x32, 600 uv, KB 6, 3 levels, 300 iterations = init + 2 reweighting cycles."""
+    wl = wk.blobs32()
     b = problem.build(wl)
     stages = pd.split_iterations(wl.iters, wl.cycles + 1)
-    say(f"[solve] config0 {prec} stages={stages}")
+    say(f"[solve] blobs32 {prec} stages={stages}")
     st, gW, deltas = _oracle_alg2(b, stages)
     s, rep = _gpu_alg2(wl, b, prec, stages)
     try:
@@ -58,11 +58,11 @@ def test_config0_full_solve(prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
-def test_config0_unconstrained_solve_and_np(prec, tol):
+def test_blobs32_unconstrained_solve_and_np(prec, tol):
     """Polarized SARA without the polarization constraint (Sec. 4.2: U', no epigraph terms)
-    on config 0 against the oracle's "nocons" run, and the polarization-error share N_p of
+    on the 32x32 blob workload against the oracle's "nocons" run, and the polarization-error share N_p of
     both estimates: the constrained solve's N_p is no larger than the unconstrained one's."""
-    wl = wk.config0()
+    wl = wk.blobs32()
     b = problem.build(wl)
     stages = pd.split_iterations(wl.iters, wl.cycles + 1)
     st, _, _ = pd.alg2(b.pb, b.gamma, stages, len(stages) - 1, mode="nocons")
@@ -72,7 +72,7 @@ def test_config0_unconstrained_solve_and_np(prec, tol):
         errs = _per_stokes(s.image(), st.S)
         _, _, np_u = metrics.polarization_error(b.mop, st.S, b.pb.Y)
         _, _, np_c = metrics.polarization_error(b.mop, st_c.S, b.pb.Y)
-        say(f"[solve] config0 unconstrained {prec}: per-Stokes rel err {['%.2e' % e for e in errs]}; "
+        say(f"[solve] blobs32 unconstrained {prec}: per-Stokes rel err {['%.2e' % e for e in errs]}; "
             f"N_p gpu {rep['n_p']:.3f}% oracle {np_u:.3f}% (constrained oracle {np_c:.3f}%)")
         assert max(errs) <= tol
         if prec == "fp64":
@@ -83,7 +83,7 @@ def test_config0_unconstrained_solve_and_np(prec, tol):
 
 
 def test_report_matches_oracle_metrics():
-    wl = wk.config0()
+    wl = wk.blobs32()
     b = problem.build(wl)
     stages = [60, 60]
     st, gW, _ = _oracle_alg2(b, stages)
@@ -105,13 +105,13 @@ def test_report_matches_oracle_metrics():
         s.close()
 
 
-def test_config1_reduced_schedule_fp32():
-    """Config 1 (128x128 ring+jet, 8-station arcs, KB 8, 4 levels) with a 6-stage schedule of 40
+def test_ring128_reduced_schedule_fp32():
+    """Ring workload (128x128 ring+jet, 8-station arcs, KB 8, 4 levels) with a 6-stage schedule of 40
     iterations each (the stated 2000-iteration budget is split the same way in the bench)."""
-    wl = wk.config1()
+    wl = wk.ring128()
     b = problem.build(wl)
     stages = [40] * 6
-    say(f"[solve] config1 fp32 stages={stages}")
+    say(f"[solve] ring128 fp32 stages={stages}")
     st, gW, _ = pd.alg2(b.pb, b.gamma, stages, 5)
     s, rep = _gpu_alg2(wl, b, "fp32", stages)
     try:
@@ -122,14 +122,14 @@ def test_config1_reduced_schedule_fp32():
         s.close()
 
 
-def test_config2_full_size_fp32():
-    """Config 2 (256x256, 2e5 uv, KB 8, 4 levels): the launch configuration the benchmark times,
+def test_ring256_full_size_fp32():
+    """Ring workload at 256x256 (2e5 uv, KB 8, 4 levels): the launch configuration the benchmark times,
     with a short 3-stage schedule the oracle finishes in about half a minute."""
-    wl = wk.config2()
+    wl = wk.ring256()
     # a loose power iteration suffices for the step sizes (tau keeps a 1% margin)
     b = problem.build(wl, norm_rtol=1e-5, norm_max_iter=60)
     stages = [10, 10, 10]
-    say(f"[solve] config2 fp32 stages={stages}")
+    say(f"[solve] ring256 fp32 stages={stages}")
     st, gW, _ = pd.alg2(b.pb, b.gamma, stages, 2)
     s, rep = _gpu_alg2(wl, b, "fp32", stages)
     try:

@@ -146,7 +146,7 @@ def test_power_iteration_generic():
 
 
 def test_workload_uv_inside_band_and_truth_in_cone():
-    for wl in (wk.config0(), wk.tiny()):
+    for wl in (wk.blobs32(), wk.tiny()):
         assert np.all(wl.uv >= -math.pi) and np.all(wl.uv < math.pi)
         S = wl.truth
         assert np.all(np.linalg.norm(S[..., 1:], axis=-1) <= S[..., 0] + 1e-15)

@@ -214,8 +214,8 @@ def test_reweighting_formula(tiny_built):
     assert np.all((W > 0) & (W <= 1))
 
 
-def test_alg2_on_config0_meets_constraints():
-    wl = wk.config0()
+def test_alg2_on_blobs32_meets_constraints():
+    wl = wk.blobs32()
     b = problem.build(wl)
     st, gW, deltas = pd.alg2(b.pb, b.gamma, pd.split_iterations(wl.iters, wl.cycles + 1), wl.cycles)
     assert len(deltas) == 2 and deltas[1] == deltas[0] / 10

@@ -227,7 +227,10 @@ int psara_layout(const psara_ctx* ctx, int64_t* perm);
  * [1] SARA analysis + dual A + synthesis (P2+P3, coarse levels fused), [2] and [3] zero (their
  * work is timed in [1] and [0]), [4] column FFT (P5), [5] de-grid + dual B (P6), [6] grid (P7),
  * [7] column inverse FFT (P8, which also sums the partial tiles of split gridding tiles),
- * [8] row inverse FFT + crop (P9).  The iterations really run (the state advances). */
+ * [8] row inverse FFT + crop (P9), then runs `iters` more iterations in the order the captured
+ * graphs use and writes to ms_per_pass[9] the average duration of the pass that fuses P9 with
+ * the next iteration's P1+P4 (0 when iters < 2).  ms_per_pass holds 10 doubles.  The
+ * iterations really run (the state advances by 2 * iters iterations). */
 psara_status psara_profile_passes(psara_ctx* ctx, psara_mode mode, int iters, double* ms_per_pass);
 
 /* ---- request server ---------------------------------------------------------------------- */

@@ -73,11 +73,13 @@ struct PassLists {
   bool sparse = false;             // every problem has a wavelet prior (P2/P3 run)
 };
 
-// One Algorithm-1 iteration of every problem in L: P1+P4, then P2/P3 on s1 concurrently with
-// P5..P9 on s0 (joined back into s0).
+// `count` Algorithm-1 iterations of every problem in L: P1+P4, then per iteration P2/P3 on s1
+// concurrently with P5..P8 on s0, joined back into s0, and P9 fused with the next iteration's
+// P1+P4 (the last iteration ends with P9 alone, so the state between calls is the same as after
+// `count` separate iterations).
 template <typename R>
-void launch_iteration_lists(const PassLists& L, int mode, hipStream_t s0, hipStream_t s1, hipEvent_t fork,
-                            hipEvent_t join);
+void launch_iterations(const PassLists& L, int mode, int count, hipStream_t s0, hipStream_t s1, hipEvent_t fork,
+                       hipEvent_t join);
 template <typename R>
 void launch_sara_dual(const PassLists& L, hipStream_t s);   // P2 + P3 with the fused coarse levels
 
@@ -139,7 +141,7 @@ struct Engine {
   void upload_items();
   void sync_desc();
   void invalidate_graphs();
-  void launch_iteration(int mode);
+  void launch_iterations(int mode, int count);
   void forward(int src_img, int mode, int out_vis);
   void adjoint(int src_vis, int use_cfac, int dst_img);
   void finalize(int q, int count, int scalar);

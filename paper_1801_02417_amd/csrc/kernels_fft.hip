@@ -118,6 +118,13 @@ __device__ void fft_lines(Cell<R>* lds, int K, bool inv, const cplx<R>* __restri
   __syncthreads();
 }
 
+// a product that is rounded on its own (never contracted into a following add)
+template <typename R>
+__device__ __forceinline__ R mul_rn(R a, R b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 template <typename R>
 __device__ inline Cell<R> zero_cell() {
   Cell<R> c;
@@ -126,8 +133,10 @@ __device__ inline Cell<R> zero_cell() {
   return c;
 }
 
-// PASS: 0 = P4 image rows -> half, 1 = P5 half -> grid, 2 = P8 grid -> half, 3 = P9 half -> image.
-// PM >= 0 (PASS 0 only): the primal step of mode PM runs on each pixel as the row is loaded
+// PASS: 0 = P4 image rows -> half, 1 = P5 half -> grid, 2 = P8 grid -> half, 3 = P9 half -> image,
+// 4 = P9, P1 and P4 of the next iteration in one pass: half -> inverse row FFT -> Re phi^dagger B
+// of the row's pixels (kept in LDS) -> primal step -> X -> forward row FFT -> half.
+// PM >= 0 (PASS 0 and 4): the primal step of mode PM runs on each pixel as the row is loaded
 // and the row FFT takes the X it returns (P1 fused into P4).
 // items: {prob, first line, -, -}; CELLS/K lines per workgroup.  The row passes (P4, P9) use
 // several lines per workgroup so that their transposed accesses to `half` cover whole cache
@@ -218,8 +227,33 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   // lines * K == CELLS (K divides CELLS), so every thread owns one channel of 8 cells
   fft_lines<R, CELLS>(lds, K, PASS >= 2, (const cplx<R>*)P.twiddle);
 
+  if (PASS == 4) {
+    // crop, Z^dagger and Re give Re phi^dagger B at the row's pixels; the primal step takes it
+    // and its X, deapodised and zero-padded, replaces the row in place (a pixel's crop position
+    // and its zero-padding position are the same cell)
+    for (int q = threadIdx.x; q < lines * K; q += nthr) {
+      const int l = q / K, k = q - l * K, r = line0 + l;
+      const int col = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
+      Cell<R> c = zero_cell<R>();
+      if (r < n && col >= 0) {
+        const Cell<R> v = lds[q];
+        const R sc = s[r] * s[col];
+        // rounded products, not contracted into the primal step's sums: the result is bitwise
+        // the one of the separate passes, which store Re phi^dagger B and read it back
+        V4<R> g;
+        g.x = mul_rn(v.s[0].re, sc); g.y = mul_rn(v.s[1].re, sc);
+        g.z = mul_rn(v.s[2].re, sc); g.w = mul_rn(v.s[3].re, sc);
+        const V4<R> x = primal_pixel_g<R, (PM < 0 ? 0 : PM)>(P, r * n + col, g);
+        c.s[0].re = x.x * sc; c.s[1].re = x.y * sc; c.s[2].re = x.z * sc; c.s[3].re = x.w * sc;
+      }
+      lds[q] = c;
+    }
+    __syncthreads();
+    fft_lines<R, CELLS>(lds, K, false, (const cplx<R>*)P.twiddle);
+  }
+
   // ---- store ----
-  if (PASS == 0) {
+  if (PASS == 0 || PASS == 4) {
     for (int q = threadIdx.x; q < lines * K; q += nthr) {
       const int k2 = q / lines, l = q - k2 * lines, r = line0 + l;
       if (r < n) half[(size_t)k2 * n + r] = lds[l * K + k2];
@@ -274,6 +308,28 @@ void launch_primal_fft(int mode, const LaunchArgs& a, int cells) {
 }
 
 template <typename R>
+void launch_fused_rows(int mode, const LaunchArgs& a, int cells) {
+  if (a.nitems <= 0) return;
+  const dim3 grid(a.nitems);
+#define PSARA_RFFT(C, PM) \
+  hipLaunchKernelGGL((fft_pass_kernel<R, C, 4, PM>), grid, dim3(C / 2), 0, a.stream, a.descs, a.items, 0, 0)
+  if (cells == 512) {
+    if (mode == PM_CONSTRAINED) PSARA_RFFT(512, PM_CONSTRAINED);
+    else if (mode == PM_INIT) PSARA_RFFT(512, PM_INIT);
+    else PSARA_RFFT(512, PM_UNCONSTRAINED);
+  } else if (cells == 2048) {
+    if (mode == PM_CONSTRAINED) PSARA_RFFT(2048, PM_CONSTRAINED);
+    else if (mode == PM_INIT) PSARA_RFFT(2048, PM_INIT);
+    else PSARA_RFFT(2048, PM_UNCONSTRAINED);
+  } else {
+    if (mode == PM_CONSTRAINED) PSARA_RFFT(1024, PM_CONSTRAINED);
+    else if (mode == PM_INIT) PSARA_RFFT(1024, PM_INIT);
+    else PSARA_RFFT(1024, PM_UNCONSTRAINED);
+  }
+#undef PSARA_RFFT
+}
+
+template <typename R>
 void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot) {
   if (a.nitems <= 0) return;
   const dim3 grid(a.nitems);
@@ -307,6 +363,8 @@ void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_
 template void launch_fft<float>(int, const LaunchArgs&, int, int, int);
 template void launch_primal_fft<float>(int, const LaunchArgs&, int);
 template void launch_primal_fft<double>(int, const LaunchArgs&, int);
+template void launch_fused_rows<float>(int, const LaunchArgs&, int);
+template void launch_fused_rows<double>(int, const LaunchArgs&, int);
 template void launch_fft<double>(int, const LaunchArgs&, int, int, int);
 
 }  // namespace psara

@@ -26,6 +26,8 @@ enum GridMode { GR_DUAL = 0, GR_PLAIN = 1 };
 
 template <typename R> void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot);
 template <typename R> void launch_primal_fft(int mode, const LaunchArgs& a, int cells);
+// P9 of one iteration with P1 and P4 of the next (row work list)
+template <typename R> void launch_fused_rows(int mode, const LaunchArgs& a, int cells);
 template <typename R> void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_slot, int out_slot);
 template <typename R> void launch_grid(int mode, const LaunchArgs& a, int taps, int src_slot, int use_cfac);
 template <typename R> void set_grid_kernel_limits(int max_ts, int taps);

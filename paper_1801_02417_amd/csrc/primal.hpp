@@ -32,14 +32,13 @@ __device__ inline void proj_E2(R r0, R r1, R r2, R d, R& p0, R& p1, R& p2, R& pd
   }
 }
 
-// Updates every per-pixel variable of pixel p in place and returns X.
+// Updates every per-pixel variable of pixel p in place and returns X; g is Re phi^dagger B at p.
 template <typename R, int MODE>
-__device__ inline V4<R> primal_pixel(const ProbDesc& P, int p) {
+__device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
   const R tau = R(P.tau), nm = R(P.norm);
   V4<R>* S = (V4<R>*)P.img[IMG_S];
   V4<R>* X = (V4<R>*)P.img[IMG_X];
   const V4<R> s = S[p];
-  V4<R> g = ((const V4<R>*)P.img[IMG_PHIB])[p];
   V4<R> ad;
   const bool dirac = (MODE != PM_INIT) && P.has_dirac;
   if (MODE != PM_INIT) {
@@ -101,6 +100,12 @@ __device__ inline V4<R> primal_pixel(const ProbDesc& P, int p) {
     D[p] = dn;
   }
   return x;
+}
+
+// The same with Re phi^dagger B read from its image.
+template <typename R, int MODE>
+__device__ inline V4<R> primal_pixel(const ProbDesc& P, int p) {
+  return primal_pixel_g<R, MODE>(P, p, ((const V4<R>*)P.img[IMG_PHIB])[p]);
 }
 
 }  // namespace psara

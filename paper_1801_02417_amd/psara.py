@@ -317,11 +317,12 @@ def psara_layout(ctx, M: int):
 
 PASS_NAMES = ("P1+P4 primal/epigraph/Dirac dual + zero-pad + row FFT", "P2+P3 SARA analysis + dual A + synthesis",
               "(in P2+P3)", "(in P1+P4)", "P5 column FFT", "P6 de-grid + dual B", "P7 grid",
-              "P8 column inverse FFT (+ split-tile sums)", "P9 row inverse FFT + crop")
+              "P8 column inverse FFT (+ split-tile sums)", "P9 row inverse FFT + crop",
+              "P9+P1+P4 fused (row inverse FFT, primal step, row FFT)")
 
 
 def psara_profile_passes(ctx, mode: int, iters: int) -> np.ndarray:
-    out = np.zeros(9)
+    out = np.zeros(10)
     _check(ctx, lib().psara_profile_passes(ctx, mode, iters, _dptr(out)))
     return out
 

@@ -130,3 +130,37 @@ def test_state_roundtrip_and_reset():
             assert not np.any(got[name]), name
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
+def test_fused_row_pass_chain(mode, prec, tol):
+    """Nine iterations in one call run as a captured chain of eight (the inverse row FFT of each
+    iteration fused with the next primal step and row FFT, seven fused launches) plus one; the
+    state is bitwise the one of nine one-iteration calls (separate passes), and matches the
+    oracle's nine iterations."""
+    n, M, T, L = 32, 600, 8, 3
+    say(f"[fused] n={n} mode={mode} prec={prec}")
+    wl, b, s, gW = _setup(n, M, T, L, prec, seed=41)
+    try:
+        rng = np.random.default_rng(43)
+        st = _random_state(rng, n * n, b.sara.J, M, gW)
+        if mode == "init":
+            st.Z[:] = 0; st.A[:] = 0; st.C[:] = 0; st.D[:] = 0
+        if mode == "nocons":
+            st.Z[:] = 0; st.C[:] = 0; st.D[:] = 0
+        s.set_state(st.S, st.Z, st.A, st.B, st.C, st.D)
+        s.solve(MODES[mode], 9, report=False)
+        chained = s.state()
+        s.set_state(st.S, st.Z, st.A, st.B, st.C, st.D)
+        for _ in range(9):
+            s.solve(MODES[mode], 1, report=False)
+        single = s.state()
+        for name in ("S", "Z", "A", "B", "C", "D"):
+            assert np.array_equal(chained[name], single[name]), name
+        scale = {}
+        ref = _oracle_steps(st.copy(), b.pb, gW, mode, 9, scale)
+        w = _compare(chained, ref, tol * 4, f"{mode} fused chain", scale if prec == "fp32" else None)
+        say(f"   9 iterations: worst rel err {w:.2e}")
+    finally:
+        s.close()

@@ -137,7 +137,7 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
   const int ntiles = g.nts * g.nts;
   int part = 0;
   for (int t = 0; t < ntiles; ++t) {
-    for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += 256) S.p6.push_back(make_int4(prob, t, v, part++));
+    for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += kDegridItem) S.p6.push_back(make_int4(prob, t, v, part++));
   }
   // gridding: first the item that stores the pass's scalar factor, then the chunks heaviest
   // first (entries plus a flush cost per run as the work estimate) so the tail is short

@@ -42,7 +42,7 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   const int b1 = t1 * ts, b2 = t2 * ts;
   // the item's visibilities are sorted by window start k1 within the tile, so they use only
   // the k1 offsets [lo, hi + T - 1] of the tile window: stage that band, Wb wide
-  const int vend = min(it.z + (int)blockDim.x, P.own_ptr[tile + 1]);
+  const int vend = min(it.z + kDegridItem, P.own_ptr[tile + 1]);
   const int lo = (P.vis_k0[it.z] >> 16) - b1, hi = (P.vis_k0[vend - 1] >> 16) - b1;
   const int Wb = hi - lo + T;
   for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {

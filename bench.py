@@ -58,6 +58,18 @@ def algorithmic_bytes(N: int, M: int, nwav: int, R: int = 4) -> list:
     ]
 
 
+def pass_bytes(N: int, M: int) -> list:
+    """Algorithmic bytes per launch of the ten timed launches (P1+P4, P2+P3, -, -, P5..P9 and the
+    fused P9+P1+P4): P1 runs inside P4's workgroups (X is handed over in registers), P3 inside
+    P2's launches (coarse levels fused), and the fused pass keeps Re phi^dagger B in LDS."""
+    nbytes = algorithmic_bytes(N, M, nwav=8)
+    nbytes[0] += nbytes[3] - N * 16
+    nbytes[1] += nbytes[2]
+    nbytes[2] = nbytes[3] = 0
+    nbytes.append(nbytes[8] + nbytes[0] - 2 * N * 16)
+    return nbytes
+
+
 def source_hash(name: str) -> str:
     with open(os.path.join(ROOT, "paper_1801_02417_amd", "csrc", name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
@@ -152,6 +164,12 @@ def batched_form(P, wk, count: int, stages) -> dict:
     img_s = [s.image() for s in solvers]
     diff = max(float(np.max(np.abs(a - b))) for a, b in zip(img_b, img_s))
     snr = [snr_db(im, wl.truth.reshape(-1, 4)) for im, wl in zip(img_b, wls)]
+    # one batched launch of each pass, timed on one stream (the branches serialised)
+    ms = P.psara_batch_profile_passes([s.ctx for s in solvers], P.PSARA_CONSTRAINED, 8)
+    nb = np.sum([pass_bytes(wl.n * wl.n, wl.M) for wl in wls], axis=0)
+    passes = {P.PASS_NAMES[i]: {"ms": round(float(ms[i]), 4),
+                                "GB/s": round(float(nb[i]) / (ms[i] * 1e-3) / 1e9, 1) if ms[i] > 0 else 0.0}
+              for i in range(10) if ms[i] > 0}
     for s in solvers:
         s.close()
     its = count * sum(stages)
@@ -161,7 +179,7 @@ def batched_form(P, wk, count: int, stages) -> dict:
             "one_at_a_time": {"iters_per_s": round(its / t_seq, 1), "solves_per_s": round(count / t_seq, 2),
                               "wall_s": round(t_seq, 3)},
             "speedup": round(t_seq / t_batch, 2), "max_abs_image_diff_batched_vs_alone": diff,
-            "mean_snr_db": round(float(np.mean(snr)), 3)}
+            "mean_snr_db": round(float(np.mean(snr)), 3), "batched_passes": passes}
 
 
 def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dict:
@@ -239,18 +257,25 @@ def large_form(P, wk, iters: int) -> dict:
 
 
 def profile_run(P, wk, form: str, iters: int) -> dict:
-    """Only the iterations of one form, for a profiler run: `batch` = the 64-solve batched form
-    (10 initialisation iterations, a reweighting, `iters` constrained iterations, every pass one
-    launch over all solves), `large` = the 512 x 512, 1e6-visibility solve."""
+    """Only the timed passes of one form, for a profiler run: each pass launched on one stream with
+    the two branches serialised (psara_profile_passes / psara_batch_profile_passes, constrained
+    mode, every term active), so that kernel durations do not include time shared with the other
+    branch.  `batch` = the 64-solve batched form (every pass one launch over all solves),
+    `large` = the 512 x 512, 1e6-visibility solve."""
     if form == "large":
-        return {"profile_form": "large", **large_form(P, wk, iters)}
-    solvers = [ready_solver(P, wk.batch_request(i), norm_iters=50, norm_rtol=1e-4)[0] for i in range(64)]
-    t0 = time.perf_counter()
-    P.batch_reweighted_solve(solvers, P.PSARA_CONSTRAINED, [10, iters])
-    dt = time.perf_counter() - t0
+        wl = wk.batch_request(0, sides=(512,))
+        s = ready_solver(P, wl, norm_iters=50, norm_rtol=1e-4)[0]
+        ms = s.profile_passes(P.PSARA_CONSTRAINED, iters)
+        s.close()
+        return {"profile_form": "large", "n": wl.n, "M": wl.M, "iters": 2 * iters,
+                "passes_ms": {P.PASS_NAMES[i]: round(float(ms[i]), 4) for i in range(10) if ms[i] > 0}}
+    wls = [wk.batch_request(i) for i in range(64)]
+    solvers = [ready_solver(P, wl, norm_iters=50, norm_rtol=1e-4)[0] for wl in wls]
+    ms = P.psara_batch_profile_passes([s.ctx for s in solvers], P.PSARA_CONSTRAINED, iters)
     for s in solvers:
         s.close()
-    return {"profile_form": "batch", "solves": 64, "iters": 10 + iters, "wall_s": round(dt, 3)}
+    return {"profile_form": "batch", "solves": 64, "iters": 2 * iters,
+            "passes_ms": {P.PASS_NAMES[i]: round(float(ms[i]), 4) for i in range(10) if ms[i] > 0}}
 
 
 def progress(msg: str) -> None:
@@ -360,13 +385,7 @@ def main() -> int:
     rep = s.report()
 
     ms = s.profile_passes(P.PSARA_CONSTRAINED, args.profile_iters)
-    nbytes = algorithmic_bytes(N, M, nwav=8)
-    # fused launches: P1 runs inside P4's workgroups, P3 with P2 (coarse levels fused)
-    nbytes[0] += nbytes[3] - N * 16            # X is handed over in registers, not re-read
-    nbytes[1] += nbytes[2]
-    nbytes[2] = nbytes[3] = 0
-    # P9 fused with the next P1+P4: Re phi^dagger B stays in LDS
-    nbytes.append(nbytes[8] + nbytes[0] - 2 * N * 16)
+    nbytes = pass_bytes(N, M)
     gbs = [b / (t * 1e-3) / 1e9 if t > 0 else 0.0 for b, t in zip(nbytes, ms)]
     dom = max(SINGLE_KERNEL_PASSES, key=lambda i: ms[i])      # the dominant kernel
     traffic = committed_traffic(dom)

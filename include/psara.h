@@ -233,6 +233,13 @@ int psara_layout(const psara_ctx* ctx, int64_t* perm);
  * iterations really run (the state advances by 2 * iters iterations). */
 psara_status psara_profile_passes(psara_ctx* ctx, psara_mode mode, int iters, double* ms_per_pass);
 
+/* The same per-pass timing for a batch (the requirements of psara_batch_solve): every pass is
+ * one launch over all `count` solves, all on the stream of ctxs[0] with the two branches
+ * serialised, so each figure is the time of one batched launch of that pass.  ms_per_pass holds
+ * 10 doubles.  Every member advances by 2 * iters iterations. */
+psara_status psara_batch_profile_passes(psara_ctx* const* ctxs, int count, psara_mode mode, int iters,
+                                        double* ms_per_pass);
+
 /* ---- request server ---------------------------------------------------------------------- */
 
 /* A server owns one GPU and solves submitted problems (Algorithm 2, each request with its own

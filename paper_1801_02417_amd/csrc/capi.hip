@@ -406,6 +406,26 @@ psara_status psara_batch_reweighted_solve(psara_ctx* const* ctxs, int count, psa
   });
 }
 
+psara_status psara_batch_profile_passes(psara_ctx* const* ctxs, int count, psara_mode mode, int iters,
+                                        double* ms_per_pass) {
+  return batch_guard(ctxs, count, [&] {
+    const int pm = primal_mode(mode);
+    require(iters >= 0, PSARA_EINVAL, "iters must be >= 0");
+    require(ms_per_pass != nullptr, PSARA_EINVAL, "ms_per_pass is NULL");
+    check_batch(ctxs, count, pm);
+    auto go = [&](auto tag) {
+      using R = decltype(tag);
+      std::vector<Engine<R>*> m;
+      for (int i = 0; i < count; ++i) m.push_back(engine_of<R>(ctxs[i]));
+      psara::Batch<R> b(m, ctxs[0]->stream);
+      b.profile(pm, iters, ms_per_pass);
+      for (int i = 0; i < count; ++i) ctxs[i]->iterations += 2 * iters;
+    };
+    if (ctxs[0]->prec == PSARA_FP64) go(double(0));
+    else go(float(0));
+  });
+}
+
 psara_status psara_report_now(psara_ctx* c, psara_report* out) {
   return guard(c, [&] {
     require(c->op_set && c->data_set, PSARA_ESTATE, "operator and data must be set");

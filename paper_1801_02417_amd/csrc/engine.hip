@@ -341,6 +341,7 @@ void Engine<R>::upload_items() {
   for (int l = 0; l <= kMaxLevels; ++l) { pl_.ana_d[l] = d_ana_d_[l]; pl_.syn_d[l] = d_syn_d_[l]; }
   pl_.cells = cells_; pl_.rcells = rcells_;
   pl_.max_ts = geo_.ts; pl_.taps = geo_.T; pl_.max_levels = h_.levels;
+  pl_.max_n = h_.n;
   pl_.sparse = h_.coef[COEF_A] != nullptr && h_.nwav > 0;
 }
 
@@ -443,6 +444,7 @@ LaunchArgs Engine<R>::la(const DevItems& d, hipStream_t s) const {
   a.items = d.ptr;
   a.nitems = d.count;
   a.stream = s ? s : s0_;
+  a.max_n = h_.n;
   return a;
 }
 
@@ -464,6 +466,7 @@ static LaunchArgs lists_la(const PassLists& L, const DevItems& d, hipStream_t s)
   a.items = d.ptr;
   a.nitems = d.count;
   a.stream = s;
+  a.max_n = L.max_n;
   return a;
 }
 
@@ -828,34 +831,36 @@ void Engine<R>::set_state(const double* buf) {
   hip_check(hipStreamSynchronize(s0_), "set_state");
 }
 
-// Run `iters` iterations with every pass on stream 0, bracketed by HIP events, and return the
-// average duration of each pass (P1..P9) in milliseconds in ms[0..8]; then `iters` iterations in
-// the captured graphs' order, returning the average duration of the fused P9 + P1 + P4 pass in
-// ms[9].
+// Run `iters` iterations of every problem in L with every pass on stream s, bracketed by HIP
+// events, and return the average duration of each pass (P1..P9) in milliseconds in ms[0..8];
+// then `iters` iterations in the captured graphs' order, returning the average duration of the
+// fused P9 + P1 + P4 pass in ms[9].
 template <typename R>
-void Engine<R>::profile(int mode, int iters, double* ms) {
-  sync_desc();
+void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, double* ms) {
   constexpr int NP = 9;
   hipEvent_t ev[NP + 1];
   for (int i = 0; i <= NP; ++i) hip_check(hipEventCreate(&ev[i]), "event");
-  for (int i = 0; i < NP; ++i) ms[i] = 0.0;
-  const bool sparse = (mode != PM_INIT) && h_.coef[COEF_A] && h_.nwav > 0;
+  for (int i = 0; i <= NP; ++i) ms[i] = 0.0;
+  const bool sparse = (mode != PM_INIT) && L.sparse;
+  auto p5_p8 = [&](bool timed) {
+    launch_fft<R>(1, lists_la(L, L.cols, s), L.cells, 0, 0);
+    if (timed) hip_check(hipEventRecord(ev[5], s), "event record");
+    launch_degrid<R>(DG_DUAL, lists_la(L, L.p6, s), L.max_ts, L.taps, VIS_BV, VIS_BV);
+    if (timed) hip_check(hipEventRecord(ev[6], s), "event record");
+    launch_grid<R>(GR_DUAL, lists_la(L, L.p7, s), L.taps, VIS_BV, 0);
+    if (timed) hip_check(hipEventRecord(ev[7], s), "event record");
+    launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 0, 0);
+    if (timed) hip_check(hipEventRecord(ev[8], s), "event record");
+  };
   for (int k = 0; k < iters; ++k) {
-    hip_check(hipEventRecord(ev[0], s0_), "event record");
-    launch_primal_fft<R>(mode, la(d_rows_, s0_), rcells_);   // P1 fused into P4: timed as P1
-    hip_check(hipEventRecord(ev[1], s0_), "event record");
-    if (sparse) p23(s0_);      // P2 and P3 with the fused coarse levels: timed together as P2
-    hip_check(hipEventRecord(ev[2], s0_), "event record");
-    p5(s0_);
-    hip_check(hipEventRecord(ev[5], s0_), "event record");
-    p6(DG_DUAL, VIS_BV, VIS_BV, s0_);
-    hip_check(hipEventRecord(ev[6], s0_), "event record");
-    p7(GR_DUAL, VIS_BV, 0, s0_);
-    hip_check(hipEventRecord(ev[7], s0_), "event record");
-    p8(s0_);
-    hip_check(hipEventRecord(ev[8], s0_), "event record");
-    p9(IMG_PHIB, s0_);
-    hip_check(hipEventRecord(ev[9], s0_), "event record");
+    hip_check(hipEventRecord(ev[0], s), "event record");
+    launch_primal_fft<R>(mode, lists_la(L, L.rows, s), L.rcells);   // P1 fused into P4: timed as P1
+    hip_check(hipEventRecord(ev[1], s), "event record");
+    if (sparse) launch_sara_dual<R>(L, s);   // P2 and P3 with the fused coarse levels: timed as P2
+    hip_check(hipEventRecord(ev[2], s), "event record");
+    p5_p8(true);
+    launch_fft<R>(3, lists_la(L, L.rows, s), L.rcells, 0, IMG_PHIB);
+    hip_check(hipEventRecord(ev[9], s), "event record");
     hip_check(hipEventSynchronize(ev[9]), "event sync");
     for (int i = 0; i < NP; ++i) {
       if (i == 2 || i == 3) continue;          // P3 runs inside P2's launches, P4 inside P1's
@@ -866,29 +871,31 @@ void Engine<R>::profile(int mode, int iters, double* ms) {
   }
   for (int i = 0; i < NP; ++i) ms[i] /= std::max(iters, 1);
   // the pass fusing P9 with the next P1+P4, timed inside a chain of iterations in graph order
-  ms[NP] = 0.0;
-  if (iters > 0) launch_primal_fft<R>(mode, la(d_rows_, s0_), rcells_);
+  if (iters > 0) launch_primal_fft<R>(mode, lists_la(L, L.rows, s), L.rcells);
   for (int k = 0; k < iters; ++k) {
-    if (sparse) p23(s0_);
-    p5(s0_);
-    p6(DG_DUAL, VIS_BV, VIS_BV, s0_);
-    p7(GR_DUAL, VIS_BV, 0, s0_);
-    p8(s0_);
+    if (sparse) launch_sara_dual<R>(L, s);
+    p5_p8(false);
     if (k + 1 < iters) {
-      hip_check(hipEventRecord(ev[0], s0_), "event record");
-      launch_fused_rows<R>(mode, la(d_rows_, s0_), rcells_);
-      hip_check(hipEventRecord(ev[1], s0_), "event record");
+      hip_check(hipEventRecord(ev[0], s), "event record");
+      launch_fused_rows<R>(mode, lists_la(L, L.rows, s), L.rcells);
+      hip_check(hipEventRecord(ev[1], s), "event record");
       hip_check(hipEventSynchronize(ev[1]), "event sync");
       float t = 0.f;
       hip_check(hipEventElapsedTime(&t, ev[0], ev[1]), "elapsed");
       ms[NP] += t;
     } else {
-      p9(IMG_PHIB, s0_);
+      launch_fft<R>(3, lists_la(L, L.rows, s), L.rcells, 0, IMG_PHIB);
     }
   }
   if (iters > 1) ms[NP] /= iters - 1;
-  hip_check(hipStreamSynchronize(s0_), "profile sync");
+  hip_check(hipStreamSynchronize(s), "profile sync");
   for (int i = 0; i <= NP; ++i) (void)hipEventDestroy(ev[i]);
+}
+
+template <typename R>
+void Engine<R>::profile(int mode, int iters, double* ms) {
+  sync_desc();
+  profile_iterations<R>(pl_, mode, iters, s0_, ms);
 }
 
 template struct Engine<float>;
@@ -899,13 +906,14 @@ template <typename R>
 Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : members_(members), s0_(stream) {
   if (members_.empty()) throw Error(PSARA_EINVAL, "empty batch");
   const int T = members_[0]->geometry().T;
-  int cells = 512, max_ts = 0, max_levels = 0;
+  int cells = 512, max_ts = 0, max_levels = 0, max_n = 0;
   bool sparse = true;
   for (Engine<R>* e : members_) {
     const Geometry& g = e->geometry();
     if (g.T != T) throw Error(PSARA_EINVAL, "batch members must share the tap count");
     cells = std::max(cells, g.K);
     max_ts = std::max(max_ts, g.ts);
+    max_n = std::max(max_n, g.n);
     max_levels = std::max(max_levels, e->desc().levels);
     sparse = sparse && e->has_prior();
   }
@@ -948,6 +956,7 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
   pl_.descs = d_descs_;
   pl_.cells = cells; pl_.rcells = cells;
   pl_.max_ts = max_ts; pl_.taps = T; pl_.max_levels = max_levels;
+  pl_.max_n = max_n;
   pl_.sparse = sparse;
   set_grid_kernel_limits<R>(max_ts, T);
   hip_check(hipStreamCreateWithFlags(&s1_, hipStreamNonBlocking), "hipStreamCreate");
@@ -1011,6 +1020,12 @@ void Batch<R>::run(int mode, int iters) {
     for (; left > 0; --left) hip_check(hipGraphLaunch(g, s0_), "graph launch");
   }
   hip_check(hipGetLastError(), "batch iteration launch");
+}
+
+template <typename R>
+void Batch<R>::profile(int mode, int iters, double* ms) {
+  run(mode, 0);                      // uploads the members' current descriptors
+  profile_iterations<R>(pl_, mode, iters, s0_, ms);
 }
 
 template struct Batch<float>;

@@ -70,6 +70,7 @@ struct PassLists {
   DevItems ana_d[kMaxLevels + 1], syn_d[kMaxLevels + 1];
   int cells = 512, rcells = 512;   // FFT cells per workgroup of the column / row passes
   int max_ts = 16, taps = 8, max_levels = 0;
+  int max_n = 0;                   // largest image side among the problems
   bool sparse = false;             // every problem has a wavelet prior (P2/P3 run)
 };
 
@@ -188,6 +189,7 @@ struct Batch {
   Batch& operator=(const Batch&) = delete;
   void run(int mode, int iters);       // graph replay; returns with the work queued on stream()
   void capture(int mode);              // capture the graphs run() replays (no work is launched)
+  void profile(int mode, int iters, double* ms);   // per-pass times over all members (as Engine)
   hipStream_t stream() const { return s0_; }
   int size() const { return (int)members_.size(); }
 

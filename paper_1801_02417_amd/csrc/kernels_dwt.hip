@@ -140,15 +140,17 @@ __device__ inline void write_partials(const ProbDesc& P, int part, const KSum& k
 // ---------------------------------------------------------------------------------------------
 // Analysis of level `level` (1 = finest) for every wavelet basis.
 // items: {prob, wavelet index, tile, partial index}; tile side dwt_ana_tile(h) per band.
-template <typename R> struct AnaSmem {
-  static constexpr int TO = dwt_ana_tile<R>(1 << 30);
+// TOM is the largest tile side among the launch's items: the LDS buffers are sized for it, so a
+// launch whose problems all use 8-wide tiles holds 22 KB (FP32) instead of 57 KB per workgroup.
+template <typename R, int TOM> struct AnaSmem {
+  static constexpr int TO = TOM;
   static constexpr int IN = 2 * TO + kMaxFilter - 2;
   V4<R> in[IN * IN];
   V4<R> rowt[IN * 2 * TO];
 };
 
-template <typename R, int MODE, int F>
-__device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R>& sm, int w, int level, int tile, int src_slot,
+template <typename R, int MODE, int F, int TOM>
+__device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>& sm, int w, int level, int tile, int src_slot,
                               int out_coef, KSum& k1, KSum& k2) {
   const Taps<R, F> t((const R*)P.filters + w * kMaxFilter);
   const int n = P.n;
@@ -159,7 +161,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R>& sm,
   const size_t base = (size_t)(P.has_dirac + w) * n * n;
   const bool last = (level == P.levels);
   // prefetch the duals and thresholds this thread updates (their latency overlaps the filtering)
-  constexpr int NPF = (AnaSmem<R>::TO * 2 * AnaSmem<R>::TO + 255) / 256;
+  constexpr int NPF = (TOM * 2 * TOM + 255) / 256;
   V4<R> pa[NPF][2], pg[NPF][2];
   if (MODE == AM_DUAL) {
     const V4<R>* __restrict__ A = (const V4<R>*)P.coef[COEF_A];
@@ -227,16 +229,16 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R>& sm,
   }
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, int TOM>
 __global__ void __launch_bounds__(256)
 analysis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int level, int src_slot, int out_coef) {
-  __shared__ AnaSmem<R> sm;
+  __shared__ AnaSmem<R, TOM> sm;
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
   const int w = it.y;
   KSum k1, k2;
-#define PSARA_ANA(FF) analysis_body<R, MODE, FF>(P, sm, w, level, it.z, src_slot, out_coef, k1, k2)
+#define PSARA_ANA(FF) analysis_body<R, MODE, FF, TOM>(P, sm, w, level, it.z, src_slot, out_coef, k1, k2)
   PSARA_FILTER_SWITCH(P.wav_len[w], PSARA_ANA)
 #undef PSARA_ANA
   if (MODE == AM_OBJECTIVE || MODE == AM_MOMENTS || MODE == AM_MAXABS)
@@ -571,18 +573,32 @@ void launch_coarse(const LaunchArgs& a) {
   hipLaunchKernelGGL((coarse_kernel<R>), dim3(a.nitems), dim3(512), 0, a.stream, a.descs, a.items);
 }
 
+template <typename R, int TOM>
+void launch_analysis_t(int mode, int level, const LaunchArgs& a, int src_slot, int out_coef) {
+  const dim3 g(a.nitems), b(256);
+#define PSARA_ANAL(M) \
+  hipLaunchKernelGGL((analysis_kernel<R, M, TOM>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef)
+  switch (mode) {
+    case AM_DUAL: PSARA_ANAL(AM_DUAL); break;
+    case AM_STORE: PSARA_ANAL(AM_STORE); break;
+    case AM_REWEIGHT: PSARA_ANAL(AM_REWEIGHT); break;
+    case AM_OBJECTIVE: PSARA_ANAL(AM_OBJECTIVE); break;
+    case AM_MAXABS: PSARA_ANAL(AM_MAXABS); break;
+    default: PSARA_ANAL(AM_MOMENTS); break;
+  }
+#undef PSARA_ANAL
+}
+
 template <typename R>
 void launch_analysis(int mode, int level, const LaunchArgs& a, int src_slot, int out_coef) {
   if (a.nitems <= 0) return;
-  const dim3 g(a.nitems), b(256);
-  switch (mode) {
-    case AM_DUAL: hipLaunchKernelGGL((analysis_kernel<R, AM_DUAL>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
-    case AM_STORE: hipLaunchKernelGGL((analysis_kernel<R, AM_STORE>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
-    case AM_REWEIGHT: hipLaunchKernelGGL((analysis_kernel<R, AM_REWEIGHT>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
-    case AM_OBJECTIVE: hipLaunchKernelGGL((analysis_kernel<R, AM_OBJECTIVE>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
-    case AM_MAXABS: hipLaunchKernelGGL((analysis_kernel<R, AM_MAXABS>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
-    default: hipLaunchKernelGGL((analysis_kernel<R, AM_MOMENTS>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef); break;
+  // the largest tile side among the launch's problems (an unknown largest side takes the widest)
+  constexpr int kWide = dwt_ana_tile<R>(1 << 30);
+  const int tom = a.max_n > 0 ? dwt_ana_tile<R>(a.max_n >> level) : kWide;
+  if constexpr (kWide > 8) {
+    if (tom > 8) { launch_analysis_t<R, kWide>(mode, level, a, src_slot, out_coef); return; }
   }
+  launch_analysis_t<R, 8>(mode, level, a, src_slot, out_coef);
 }
 
 template <typename R>

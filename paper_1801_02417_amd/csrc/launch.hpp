@@ -13,6 +13,7 @@ struct LaunchArgs {
   const int4* items;       // device work list, one entry per workgroup
   int nitems;
   hipStream_t stream;
+  int max_n = 0;           // largest image side among the launch's problems (0: not known)
 };
 
 // P1 modes

@@ -31,7 +31,8 @@ EXPORTS = (
     "psara_get_state", "psara_set_state", "psara_reset_state", "psara_footprint", "psara_apply_phi",
     "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
     "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_profile_passes",
-    "psara_batch_solve", "psara_batch_reweighted_solve", "psara_data_gamma", "psara_set_gamma",
+    "psara_batch_solve", "psara_batch_reweighted_solve", "psara_batch_profile_passes", "psara_data_gamma",
+    "psara_set_gamma",
     "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
     "psara_server_clock", "psara_server_last_error", "psara_server_destroy",
 )
@@ -114,6 +115,7 @@ def lib() -> C.CDLL:
         "psara_layout": (I, [P, C.POINTER(C.c_int64)]),
         "psara_profile_passes": (I, [P, I, I, D]),
         "psara_batch_solve": (I, [C.POINTER(P), I, I, I, C.POINTER(PsaraReport)]),
+        "psara_batch_profile_passes": (I, [C.POINTER(P), I, I, I, D]),
         "psara_data_gamma": (I, [P, C.c_double, D]),
         "psara_set_gamma": (I, [P, C.c_double]),
         "psara_server_create": (I, [C.POINTER(P), I, S, I, I, I]),
@@ -343,6 +345,13 @@ def psara_batch_solve(ctxs, mode: int, iters: int, report: bool = True):
     st = lib().psara_batch_solve(_ctx_array(ctxs), len(ctxs), mode, iters, reps if report else None)
     _batch_check(ctxs, st)
     return [r.as_dict() for r in reps] if report else None
+
+
+def psara_batch_profile_passes(ctxs, mode: int, iters: int) -> np.ndarray:
+    """Per-pass milliseconds of one batched launch of each pass (as psara_profile_passes)."""
+    out = np.zeros(10)
+    _batch_check(ctxs, lib().psara_batch_profile_passes(_ctx_array(ctxs), len(ctxs), mode, iters, _dptr(out)))
+    return out
 
 
 def psara_batch_reweighted_solve(ctxs, mode: int, iters_per_stage: Sequence[int], delta_decay: float = 10.0):

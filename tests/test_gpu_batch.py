@@ -123,3 +123,29 @@ def test_batch_argument_checks():
     assert [r["iterations"] for r in reps] == [3, 3]
     for s in (a, b, c, d):
         s.close()
+
+
+def test_batch_profile_passes_times_and_advances_like_alone():
+    """psara_batch_profile_passes times every pass of a mixed batch (positive times, the fused
+    row pass included) and advances each member by 2 * iters iterations, bitwise as the same
+    number of iterations run alone."""
+    wls = mixed_workloads()[:3]
+    alone = []
+    for wl in wls:
+        s = make_solver(wl, "fp32")
+        s.solve(P.PSARA_CONSTRAINED, 6, report=False)
+        alone.append(s.state())
+        s.close()
+    members = [make_solver(wl, "fp32") for wl in wls]
+    try:
+        ms = P.psara_batch_profile_passes([s.ctx for s in members], P.PSARA_CONSTRAINED, 3)
+        say(f"batch pass ms: {np.round(ms, 4)}")
+        assert all(ms[i] > 0 for i in (0, 1, 4, 5, 6, 7, 8, 9)), ms
+        assert ms[2] == 0 and ms[3] == 0
+        for wl, s, a in zip(wls, members, alone):
+            st = s.state()
+            for name in ("S", "Z", "A", "B", "C", "D"):
+                assert np.array_equal(st[name], a[name]), (wl.name, name)
+    finally:
+        for s in members:
+            s.close()

@@ -77,6 +77,17 @@ typedef struct {
     int64_t iterations;  /* Algorithm-1 iterations run on this context so far */
 } psara_report;
 
+/* Stopping criteria of Sec. 4.6, tested on the device after every check: a run stops when
+ * ||phi(S) - Y|| <= (1 + theta) epsilon, the largest relative variation of the four Stokes maps
+ * between the last two iterates is <= rel_var (a map that is zero in both counts as 0), and,
+ * when np_max >= 0, N_p <= np_max (percent).  The paper's setting: theta = 5e-3,
+ * rel_var = 1e-5, np_max = 0.5 for the constrained problem (np_max < 0 disables the test). */
+typedef struct {
+    double theta;
+    double rel_var;
+    double np_max;
+} psara_stop;
+
 /* ---- lifetime --------------------------------------------------------------------------- */
 
 /* Create a context on `device`.  `hip_stream` is a hipStream_t to run on (for example
@@ -126,6 +137,25 @@ psara_status psara_opnorm(psara_ctx* ctx, int max_iter, double rtol, double* phi
  * after the last iteration. */
 psara_status psara_solve(psara_ctx* ctx, psara_mode mode, int iters, int check_every,
                          psara_report* out);
+
+/* Run Algorithm 1 in `mode` from the current state until the criteria `stop` hold or
+ * max_iters iterations have run.  The criteria are evaluated on the device (FP64 reductions)
+ * after every check_every iterations (check_every >= 1), inside the captured graph; the host
+ * reads the outcome one check behind without waiting for the work it has just queued, and
+ * checks queued after the stop do nothing.  The iterations run are added to the context's
+ * count (out->iterations) and written to *iters_run if it is not NULL.  stop->theta >= 0,
+ * stop->rel_var >= 0. */
+psara_status psara_solve_adaptive(psara_ctx* ctx, psara_mode mode, int max_iters, int check_every,
+                                  const psara_stop* stop, int* iters_run, psara_report* out);
+
+/* Algorithm 2 with adaptive stages: the initialisation stage and every reweighted stage run
+ * as psara_solve_adaptive with at most max_iters_per_stage iterations; the initialisation
+ * stage uses the residual and relative-variation tests only (N_p is not part of its problem).
+ * iters_run: NULL or cycles + 1 counts, the iterations each stage ran. */
+psara_status psara_reweighted_solve_adaptive(psara_ctx* ctx, psara_mode mode, int cycles,
+                                             int max_iters_per_stage, int check_every,
+                                             const psara_stop* stop, double delta_decay,
+                                             int* iters_run, psara_report* out);
 
 /* Reweighting step of Algorithm 2 (eq. weights): W = delta / (delta + |Psi^dagger S|),
  * thresholds gamma * W.  delta > 0. */
@@ -237,6 +267,13 @@ psara_status psara_profile_passes(psara_ctx* ctx, psara_mode mode, int iters, do
  * one launch over all `count` solves, all on the stream of ctxs[0] with the two branches
  * serialised, so each figure is the time of one batched launch of that pass.  ms_per_pass holds
  * 10 doubles.  Every member advances by 2 * iters iterations. */
+/* Batched psara_solve_adaptive: every member stops on its own criteria (its launches then
+ * do nothing for it) and the call returns when all have stopped or max_iters iterations have
+ * run.  iters_run: NULL or `count` counts.  Each member's result equals its solo adaptive run. */
+psara_status psara_batch_solve_adaptive(psara_ctx* const* ctxs, int count, psara_mode mode, int max_iters,
+                                        int check_every, const psara_stop* stop, int* iters_run,
+                                        psara_report* reports);
+
 psara_status psara_batch_profile_passes(psara_ctx* const* ctxs, int count, psara_mode mode, int iters,
                                         double* ms_per_pass);
 

@@ -28,6 +28,7 @@ from dataclasses import dataclass, replace
 
 import numpy as np
 
+from . import metrics
 from .prox import (proj_E1, proj_E2, proj_U, proj_U_prime, proj_V, soft_threshold, proj_ball,
                    proj_polarization_cone)
 
@@ -132,6 +133,41 @@ def run_alg1(st: State, pb: Problem, gammaW: np.ndarray, iters: int, mode: str =
     return st
 
 
+def stop_criteria(pb: Problem, S_new: np.ndarray, S_old: np.ndarray, theta: float, rel_var: float,
+                  np_max: float):
+    """The stopping test of the paper's simulation settings (Sec. 4.6 and the settings that
+    follow it): the residual ||phi(S) - Y|| is within (1 + theta) epsilon, the relative variation
+    ||S_i^(k+1) - S_i^(k)|| / ||S_i^(k)|| of every Stokes map i is at most rel_var, and, for the
+    constrained problem (np_max >= 0), N_p (percent, Sec. 4.2) is at most np_max.  Readings: all
+    four maps enter the relative variation; a map that is zero in both iterates varies by 0.
+    Returns (met, residual, largest relative variation, N_p)."""
+    res = metrics.residual_norm(pb, S_new, pb.Y)
+    num = np.linalg.norm(S_new - S_old, axis=0)
+    den = np.linalg.norm(S_old, axis=0)
+    rv = max(float(a / b) if b > 0 else (math.inf if a > 0 else 0.0) for a, b in zip(num, den))
+    n_p = metrics.polarization_error(pb, S_new, pb.Y)[2] if np_max >= 0 else 0.0
+    met = res <= (1.0 + theta) * pb.eps and rv <= rel_var and (np_max < 0 or n_p <= np_max)
+    return met, res, rv, n_p
+
+
+def run_alg1_adaptive(st: State, pb: Problem, gammaW: np.ndarray, mode: str, max_iters: int, check_every: int,
+                      theta: float, rel_var: float, np_max: float):
+    """Algorithm 1 tested against `stop_criteria` after every block of check_every iterations
+    (the last block may be shorter), stopping at the first block after which the test holds or
+    after max_iters iterations.  Returns (state, iterations run)."""
+    done = 0
+    while done < max_iters:
+        k = min(check_every, max_iters - done)
+        prev = st.S
+        for _ in range(k):
+            prev = st.S
+            st = alg1_iteration(st, pb, gammaW, mode)
+        done += k
+        if stop_criteria(pb, st.S, prev, theta, rel_var, np_max)[0]:
+            break
+    return st, done
+
+
 def reweight(pb: Problem, S: np.ndarray, delta: float) -> np.ndarray:
     """Weights of eq. weights: W = delta / (delta + |Psi^dagger S|)."""
     return delta / (delta + np.abs(pb.psi_adj(S)))
@@ -173,6 +209,27 @@ def alg2(pb: Problem, gamma: float, iters, cycles: int, mode: str = "polsara",
             callback(l, st)
         delta /= delta_decay
     return st, gW, deltas
+
+
+def alg2_adaptive(pb: Problem, gamma: float, cycles: int, max_iters: int, check_every: int, theta: float,
+                  rel_var: float, np_max: float, mode: str = "polsara", delta_decay: float = 10.0):
+    """Algorithm 2 whose stages end by `stop_criteria` (run_alg1_adaptive, at most max_iters
+    iterations each); the initialisation stage leaves N_p out of the test (the constraint is not
+    part of its problem).  Returns (state, gammaW, iterations per stage)."""
+    S0 = pb.psi_adj(np.zeros((_n_pixels(pb), 4)))
+    J = S0.shape[0]
+    st = State.zeros(_n_pixels(pb), J, pb.Y.shape[0])
+    ones = np.ones((J, 4))
+    st, it = run_alg1_adaptive(st, pb, gamma * ones, "init", max_iters, check_every, theta, rel_var, -1.0)
+    its = [it]
+    delta = float(np.std(pb.psi_adj(st.S)))
+    gW = gamma * ones
+    for _ in range(cycles):
+        gW = gamma * reweight(pb, st.S, delta)
+        st, it = run_alg1_adaptive(st, pb, gW, mode, max_iters, check_every, theta, rel_var, np_max)
+        its.append(it)
+        delta /= delta_decay
+    return st, gW, its
 
 
 def _n_pixels(pb: Problem) -> int:

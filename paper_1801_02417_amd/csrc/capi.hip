@@ -322,6 +322,70 @@ psara_status psara_solve(psara_ctx* c, psara_mode mode, int iters, int check_eve
   return guard(c, [&] { run_stage(c, primal_mode(mode), iters, check_every, out); });
 }
 
+namespace {
+void check_stop(const psara_stop* stop, int max_iters, int check_every) {
+  require(stop != nullptr, PSARA_EINVAL, "stop is NULL");
+  require(std::isfinite(stop->theta) && stop->theta >= 0.0, PSARA_EINVAL, "stop->theta must be >= 0");
+  require(std::isfinite(stop->rel_var) && stop->rel_var >= 0.0, PSARA_EINVAL, "stop->rel_var must be >= 0");
+  require(!std::isnan(stop->np_max), PSARA_EINVAL, "stop->np_max is NaN");
+  require(max_iters >= 0, PSARA_EINVAL, "max_iters must be >= 0");
+  require(check_every >= 1, PSARA_EINVAL, "check_every must be >= 1");
+}
+
+int run_stage_adaptive(psara_ctx* c, int mode, int max_iters, int check_every, const psara_stop* stop) {
+  require(c->op_set && c->data_set, PSARA_ESTATE, "operator and data must be set before solving");
+  require(c->steps_set, PSARA_ESTATE, "step sizes must be set before solving");
+  require(mode == psara::PM_INIT || c->prior_set, PSARA_ESTATE, "prior must be set for this mode");
+  const double v[3] = {stop->theta, stop->rel_var, stop->np_max};
+  int it = 0;
+  with_engine(c, [&](auto& e) { it = e.run_adaptive(mode, max_iters, check_every, v); });
+  c->iterations += it;
+  return it;
+}
+}  // namespace
+
+psara_status psara_solve_adaptive(psara_ctx* c, psara_mode mode, int max_iters, int check_every,
+                                  const psara_stop* stop, int* iters_run, psara_report* out) {
+  return guard(c, [&] {
+    check_stop(stop, max_iters, check_every);
+    const int it = run_stage_adaptive(c, primal_mode(mode), max_iters, check_every, stop);
+    if (iters_run) *iters_run = it;
+    if (out) {
+      with_engine(c, [&](auto& e) { e.report(out); });
+      out->iterations = c->iterations;
+    }
+  });
+}
+
+psara_status psara_reweighted_solve_adaptive(psara_ctx* c, psara_mode mode, int cycles, int max_iters_per_stage,
+                                             int check_every, const psara_stop* stop, double delta_decay,
+                                             int* iters_run, psara_report* out) {
+  return guard(c, [&] {
+    check_stop(stop, max_iters_per_stage, check_every);
+    require(cycles >= 0, PSARA_EINVAL, "cycles must be >= 0");
+    require(delta_decay > 1.0 && std::isfinite(delta_decay), PSARA_EINVAL, "delta_decay must be > 1");
+    require(c->prior_set, PSARA_ESTATE, "prior not set");
+    const int pm = primal_mode(mode);
+    psara_stop init = *stop;
+    init.np_max = -1.0;
+    int it = run_stage_adaptive(c, psara::PM_INIT, max_iters_per_stage, check_every, &init);
+    if (iters_run) iters_run[0] = it;
+    double delta = 0.0;
+    with_engine(c, [&](auto& e) { delta = e.coef_std(); });
+    require(delta > 0.0, PSARA_EINVAL, "initial estimate is zero: no reweighting scale");
+    for (int l = 1; l <= cycles; ++l) {
+      with_engine(c, [&](auto& e) { e.reweight(delta); });
+      it = run_stage_adaptive(c, pm, max_iters_per_stage, check_every, stop);
+      if (iters_run) iters_run[l] = it;
+      delta /= delta_decay;
+    }
+    if (out) {
+      with_engine(c, [&](auto& e) { e.report(out); });
+      out->iterations = c->iterations;
+    }
+  });
+}
+
 psara_status psara_reweight(psara_ctx* c, double delta) {
   return guard(c, [&] {
     require(c->prior_set, PSARA_ESTATE, "prior not set");
@@ -403,6 +467,35 @@ psara_status psara_batch_reweighted_solve(psara_ctx* const* ctxs, int count, psa
     for (int i = 0; i < count; ++i) require(ctxs[i]->prior_set, PSARA_ESTATE, "batch member without a prior");
     if (ctxs[0]->prec == PSARA_FP64) batch_reweighted<double>(ctxs, count, pm, cycles, iters_per_stage, delta_decay, reports);
     else batch_reweighted<float>(ctxs, count, pm, cycles, iters_per_stage, delta_decay, reports);
+  });
+}
+
+psara_status psara_batch_solve_adaptive(psara_ctx* const* ctxs, int count, psara_mode mode, int max_iters,
+                                        int check_every, const psara_stop* stop, int* iters_run,
+                                        psara_report* reports) {
+  return batch_guard(ctxs, count, [&] {
+    const int pm = primal_mode(mode);
+    check_stop(stop, max_iters, check_every);
+    check_batch(ctxs, count, pm);
+    const double v[3] = {stop->theta, stop->rel_var, stop->np_max};
+    std::vector<int> its(count, 0);
+    auto go = [&](auto tag) {
+      using R = decltype(tag);
+      std::vector<Engine<R>*> m;
+      for (int i = 0; i < count; ++i) m.push_back(engine_of<R>(ctxs[i]));
+      psara::Batch<R> b(m, ctxs[0]->stream);
+      b.run_adaptive(pm, max_iters, check_every, v, its.data());
+      for (int i = 0; i < count; ++i) {
+        ctxs[i]->iterations += its[i];
+        if (iters_run) iters_run[i] = its[i];
+        if (reports) {
+          m[i]->report(&reports[i]);
+          reports[i].iterations = ctxs[i]->iterations;
+        }
+      }
+    };
+    if (ctxs[0]->prec == PSARA_FP64) go(double(0));
+    else go(float(0));
   });
 }
 

@@ -55,8 +55,16 @@ enum Scalar {
   SC_NPCOUNT,
   SC_OBJ,
   SC_MEAN, SC_SQ,   // coefficient moments
+  // adaptive stopping (Sec. 4.6 criteria, evaluated on the device): a problem whose criteria
+  // hold is halted, and every kernel then leaves its workgroups at once (0 outside such runs)
+  SC_HALT,          // 1: the problem's iterations stop
+  SC_ITERS,         // iterations run by the current adaptive stage
+  SC_STOP_THETA,    // residual bound (1 + theta) epsilon
+  SC_STOP_RV,       // bound of the largest relative variation of the four maps
+  SC_STOP_NP,       // bound of N_p in percent (< 0: not used)
   NUM_SCALARS = 32
 };
+static_assert(SC_STOP_NP < NUM_SCALARS, "scalar slots");
 // Partial sums per problem, each a (sum, compensation) pair of doubles: first the de-grid
 // region (n_p6 pairs), then kGenQ generic regions of gen_stride pairs each.
 constexpr int kGenQ = 8;
@@ -155,6 +163,9 @@ __device__ inline KSum block_reduce(KSum k, double* scratch) {
 }
 
 // Sum `count` (s, c) pairs from `parts` in a fixed order with the whole block.
+// true when an adaptive run has stopped this problem (its kernels then do nothing)
+__device__ inline bool halted(const ProbDesc& P) { return P.scal[SC_HALT] != 0.0; }
+
 __device__ inline double block_sum_partials(const double* parts, int count, double* scratch) {
   KSum k;
   for (int i = threadIdx.x; i < count; i += blockDim.x) {

@@ -248,6 +248,8 @@ Engine<R>::~Engine() {
   for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
   graphs_.clear();
   for (void* p : allocs_) (void)hipFree(p);
+  if (h_active_) (void)hipHostFree(h_active_);
+  for (hipEvent_t e : ev_active_) if (e) (void)hipEventDestroy(e);
   (void)hipEventDestroy(ev_fork_);
   (void)hipEventDestroy(ev_join_);
   (void)hipStreamDestroy(s1_);
@@ -501,6 +503,57 @@ void launch_iterations(const PassLists& L, int mode, int count, hipStream_t s0, 
     else launch_fft<R>(3, lists_la(L, L.rows, s0), L.rcells, 0, IMG_PHIB);          // P9
   }
 }
+// The stopping quantities of Sec. 4.6 for every problem in L, into each problem's scalars,
+// with no host synchronisation: the residual ||phi(S) - Y||^2, N_p (its threshold zeta from the
+// residual image Re phi^dagger (Y - phi(S))), and the relative variation of the last iteration
+// from S and X = 2 S_new - S_old.  Uses the grid, VIS_R and IMG_TMP, none of which carries
+// iteration state between the iterations of a chain.
+template <typename R>
+void launch_check(const PassLists& L, int nprob, hipStream_t s) {
+  launch_fft<R>(0, lists_la(L, L.rows, s), L.rcells, IMG_S, 0);                       // phi(S)
+  launch_fft<R>(1, lists_la(L, L.cols, s), L.cells, 0, 0);
+  launch_degrid<R>(DG_RESIDUAL, lists_la(L, L.p6, s), L.max_ts, L.taps, VIS_BV, VIS_R);
+  launch_finalize(L.descs, nprob, -1, 0, SC_RES2, s);
+  launch_grid<R>(GR_PLAIN, lists_la(L, L.p7, s), L.taps, VIS_R, 0);                   // phi^dagger
+  launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 0, 0);
+  launch_fft<R>(3, lists_la(L, L.rows, s), L.rcells, 0, IMG_TMP);
+  launch_img_sumsq<R>(lists_la(L, L.img, s), IMG_TMP, 0, 0);
+  launch_finalize(L.descs, nprob, 0, -1, SC_RIMG2, s);
+  launch_finalize_zeta(L.descs, nprob, s);
+  launch_npcount<R>(lists_la(L, L.img, s));
+  launch_finalize(L.descs, nprob, 0, -1, SC_NPCOUNT, s);
+  launch_relvar<R>(lists_la(L, L.img, s));
+  for (int q = 0; q < 4; ++q) {
+    launch_finalize(L.descs, nprob, q, -1, SC_RV0 + q, s);
+    launch_finalize(L.descs, nprob, 4 + q, -1, SC_SN0 + q, s);
+  }
+}
+
+// Host side of an adaptive run: launches chunks of `check_every` iterations, each followed by
+// the check and the decision, and looks at the number of running problems one chunk behind (an
+// asynchronous copy into pinned memory), so it never waits for the chunk it has just queued;
+// chunks queued after every problem has halted do nothing.  `graph(k)` returns the captured
+// chunk of k iterations.  Returns when the work has drained.
+template <class G>
+void adaptive_loop(G&& graph, int max_iters, int check_every, hipStream_t s, int* d_active, int* h_active,
+                   hipEvent_t* ev) {
+  int left = max_iters, c = 0;
+  bool done = false;
+  while (left > 0 && !done) {
+    const int k = std::min(left, check_every);
+    hip_check(hipGraphLaunch(graph(k), s), "graph launch");
+    hip_check(hipMemcpyAsync(h_active + (c & 1), d_active, sizeof(int), hipMemcpyDeviceToHost, s), "active D2H");
+    hip_check(hipEventRecord(ev[c & 1], s), "event record");
+    left -= k;
+    if (c >= 1) {
+      hip_check(hipEventSynchronize(ev[(c - 1) & 1]), "event sync");
+      done = h_active[(c - 1) & 1] == 0;
+    }
+    ++c;
+  }
+  hip_check(hipStreamSynchronize(s), "adaptive sync");
+}
+
 template void launch_iterations<float>(const PassLists&, int, int, hipStream_t, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_iterations<double>(const PassLists&, int, int, hipStream_t, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_sara_dual<float>(const PassLists&, hipStream_t);
@@ -528,6 +581,60 @@ void Engine<R>::adjoint(int src_vis, int use_cfac, int dst_img) {
 template <typename R>
 void Engine<R>::launch_iterations(int mode, int count) {
   ::psara::launch_iterations<R>(pl_, mode, count, s0_, s1_, ev_fork_, ev_join_);
+}
+
+template <typename R>
+void Engine<R>::stop_begin(const double* stop) {
+  sync_desc();
+  const double v[5] = {0.0, 0.0, stop[0], stop[1], stop[2]};    // SC_HALT .. SC_STOP_NP
+  copy_sync(h_.scal + SC_HALT, v, sizeof(v), hipMemcpyHostToDevice, s0_, "stop set-up");
+}
+
+template <typename R>
+int Engine<R>::stop_end() {
+  double v[2] = {0.0, 0.0};                                     // SC_HALT, SC_ITERS
+  copy_sync(v, h_.scal + SC_HALT, sizeof(v), hipMemcpyDeviceToHost, s0_, "stop read");
+  const double z = 0.0;
+  copy_sync(h_.scal + SC_HALT, &z, sizeof(z), hipMemcpyHostToDevice, s0_, "stop reset");
+  return (int)v[1];
+}
+
+template <typename R>
+void Engine<R>::adaptive_buffers() {
+  if (!d_active_) d_active_ = dalloc<int>(1);
+  if (!h_active_) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(PSARA_ENOMEM, "pinned host allocation failed");
+    }
+    h_active_ = (int*)p;
+    for (int i = 0; i < 2; ++i) hip_check(hipEventCreateWithFlags(&ev_active_[i], hipEventDisableTiming), "event");
+  }
+}
+
+template <typename R>
+int Engine<R>::run_adaptive(int mode, int max_iters, int check_every, const double* stop) {
+  adaptive_buffers();
+  stop_begin(stop);
+  auto graph = [&](int count) -> hipGraphExec_t {
+    const int key = 1000000 + mode * 1000 + count;
+    auto it = graphs_.find(key);
+    if (it != graphs_.end()) return it->second;
+    hipGraph_t g = nullptr;
+    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
+    launch_iterations(mode, count);
+    launch_check<R>(pl_, 1, s0_);
+    launch_stop_decide(d_desc_, 1, count, d_active_, s0_);
+    hip_check(hipStreamEndCapture(s0_, &g), "end capture");
+    hipGraphExec_t exec = nullptr;
+    hip_check(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(g);
+    graphs_[key] = exec;
+    return exec;
+  };
+  adaptive_loop(graph, max_iters, check_every, s0_, d_active_, h_active_, ev_active_);
+  return stop_end();
 }
 
 template <typename R>
@@ -970,6 +1077,8 @@ Batch<R>::~Batch() {
   if (s1_) (void)hipStreamSynchronize(s1_);
   for (auto& kv : graphs_) if (kv.second) (void)hipGraphExecDestroy(kv.second);
   for (void* p : allocs_) (void)hipFree(p);
+  if (h_active_) (void)hipHostFree(h_active_);
+  for (hipEvent_t e : ev_active_) if (e) (void)hipEventDestroy(e);
   if (ev_fork_) (void)hipEventDestroy(ev_fork_);
   if (ev_join_) (void)hipEventDestroy(ev_join_);
   if (s1_) (void)hipStreamDestroy(s1_);
@@ -1020,6 +1129,50 @@ void Batch<R>::run(int mode, int iters) {
     for (; left > 0; --left) hip_check(hipGraphLaunch(g, s0_), "graph launch");
   }
   hip_check(hipGetLastError(), "batch iteration launch");
+}
+
+template <typename R>
+void Batch<R>::run_adaptive(int mode, int max_iters, int check_every, const double* stop, int* iters_out) {
+  if ((mode != PM_INIT) && !pl_.sparse) throw Error(PSARA_ESTATE, "every batch member needs a wavelet prior in this mode");
+  for (Engine<R>* e : members_) e->stop_begin(stop);
+  run(mode, 0);                      // uploads the members' current descriptors
+  if (!d_active_) {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(int)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(PSARA_ENOMEM, "batch flag allocation failed");
+    }
+    allocs_.push_back(p);
+    d_active_ = (int*)p;
+    if (hipHostMalloc(&p, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(PSARA_ENOMEM, "pinned host allocation failed");
+    }
+    h_active_ = (int*)p;
+    for (int i = 0; i < 2; ++i) hip_check(hipEventCreateWithFlags(&ev_active_[i], hipEventDisableTiming), "event");
+  }
+  const int nprob = (int)members_.size();
+  auto graph = [&](int count) -> hipGraphExec_t {
+    const int key = 1000000 + mode * 1000 + count;
+    auto it = graphs_.find(key);
+    if (it != graphs_.end()) return it->second;
+    hipGraph_t g = nullptr;
+    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
+    launch_iterations<R>(pl_, mode, count, s0_, s1_, ev_fork_, ev_join_);
+    launch_check<R>(pl_, nprob, s0_);
+    launch_stop_decide(pl_.descs, nprob, count, d_active_, s0_);
+    hip_check(hipStreamEndCapture(s0_, &g), "end capture");
+    hipGraphExec_t exec = nullptr;
+    hip_check(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(g);
+    graphs_[key] = exec;
+    return exec;
+  };
+  adaptive_loop(graph, max_iters, check_every, s0_, d_active_, h_active_, ev_active_);
+  for (int i = 0; i < nprob; ++i) {
+    const int it = members_[i]->stop_end();
+    if (iters_out) iters_out[i] = it;
+  }
 }
 
 template <typename R>

@@ -97,6 +97,11 @@ struct Engine {
   void zero_state();
   void run(int mode, int iters);          // graph replay
   void run_eager(int mode, int iters);    // direct launches
+  // Up to max_iters iterations, checking the stopping criteria stop = {theta, rel_var, np_max}
+  // on the device after every check_every of them; returns the iterations run.
+  int run_adaptive(int mode, int max_iters, int check_every, const double* stop);
+  void stop_begin(const double* stop);  // clear the halt flag and counter, store the criteria
+  int stop_end();                       // iterations run by the adaptive run; clears the halt flag
   void report(psara_report* r);
   double coef_std();
   double data_max_coef();              // max |Psi^dagger Re phi^dagger Y|
@@ -143,6 +148,7 @@ struct Engine {
   void sync_desc();
   void invalidate_graphs();
   void launch_iterations(int mode, int count);
+  void adaptive_buffers();
   void forward(int src_img, int mode, int out_vis);
   void adjoint(int src_vis, int use_cfac, int dst_img);
   void finalize(int q, int count, int scalar);
@@ -158,6 +164,9 @@ struct Engine {
   Geometry geo_;
   hipStream_t s0_ = nullptr, s1_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+  int* d_active_ = nullptr;      // adaptive runs: problems still running (device) ...
+  int* h_active_ = nullptr;      // ... and its pinned host copies, one per chunk parity
+  hipEvent_t ev_active_[2] = {nullptr, nullptr};
   ProbDesc h_;
   ProbDesc* d_desc_ = nullptr;
   bool desc_dirty_ = true;
@@ -190,6 +199,8 @@ struct Batch {
   void run(int mode, int iters);       // graph replay; returns with the work queued on stream()
   void capture(int mode);              // capture the graphs run() replays (no work is launched)
   void profile(int mode, int iters, double* ms);   // per-pass times over all members (as Engine)
+  // adaptive stopping per member (as Engine::run_adaptive); iters_out: iterations per member
+  void run_adaptive(int mode, int max_iters, int check_every, const double* stop, int* iters_out);
   hipStream_t stream() const { return s0_; }
   int size() const { return (int)members_.size(); }
 
@@ -198,6 +209,9 @@ struct Batch {
   std::vector<Engine<R>*> members_;
   hipStream_t s0_ = nullptr, s1_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+  int* d_active_ = nullptr;
+  int* h_active_ = nullptr;
+  hipEvent_t ev_active_[2] = {nullptr, nullptr};
   ProbDesc* d_descs_ = nullptr;
   std::vector<void*> allocs_;
   PassLists pl_;

@@ -236,6 +236,7 @@ analysis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int w = it.y;
   KSum k1, k2;
 #define PSARA_ANA(FF) analysis_body<R, MODE, FF, TOM>(P, sm, w, level, it.z, src_slot, out_coef, k1, k2)
@@ -252,6 +253,7 @@ dirac_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items,
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int N = P.n * P.n;
   const int p = it.y * 256 + threadIdx.x;
   KSum k1, k2;
@@ -366,6 +368,7 @@ synthesis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ it
   constexpr int NPAIR = (SynSmem<R>::TS * SynSmem<R>::TS / 2 + 255) / 256;
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int w = it.y;
   const int m = P.n >> (level - 1);
   const int to = dwt_syn_tile<R>(m), tps = m / to, th = to / 2;
@@ -399,6 +402,7 @@ synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restric
   constexpr int NPAIR = (SynSmem<R>::TS * SynSmem<R>::TS / 2 + 255) / 256;
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int n = P.n;
   const int to = dwt_syn_tile<R>(n), tps = n / to, th = to / 2;
   const int o1 = (it.y / tps) * to, o2 = (it.y % tps) * to;
@@ -554,6 +558,7 @@ coarse_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   __shared__ R bufA[MM * MM], bufB[MM * MM], pyr[MM * MM];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
 #define PSARA_COARSE(FF) coarse_body<FF, R>(P, it.y, it.z, it.w, bufA, bufB, pyr)
   PSARA_FILTER_SWITCH(P.wav_len[it.y], PSARA_COARSE)
 #undef PSARA_COARSE

@@ -147,6 +147,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   __shared__ Cell<R> lds[CELLS];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int n = P.n, K = P.K, h2 = n / 2;
   const int lines = CELLS / K;
   const int line0 = it.y;

@@ -34,6 +34,7 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int K = P.K, ts = P.ts, nts = P.ntile_side;
   const int tile = it.y;
   const int t1 = tile / nts, t2 = tile - t1 * nts;
@@ -200,6 +201,7 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   __shared__ double red[2 * (kGridThreads / 64)];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   if (it.y < 0) {                  // the factor item: the factor the column inverse FFT applies
     if (MODE == GR_DUAL) {
       const double v2 = block_sum_partials(P.partials, P.n_p6, red);

@@ -14,6 +14,7 @@ __global__ void __launch_bounds__(256)
 primal_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int p = it.y * 256 + threadIdx.x;
   if (p < P.n * P.n) primal_pixel<R, MODE>(P, p);
 }
@@ -41,6 +42,7 @@ __global__ void __launch_bounds__(256) relvar_kernel(const ProbDesc* __restrict_
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int N = P.n * P.n, p = it.y * 256 + threadIdx.x;
   KSum k[8];
   if (p < N) {
@@ -62,6 +64,7 @@ __global__ void __launch_bounds__(256) img_sumsq_kernel(const ProbDesc* __restri
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int N = P.n * P.n, p = it.y * 256 + threadIdx.x;
   KSum k;
   if (p < N) {
@@ -79,6 +82,7 @@ __global__ void __launch_bounds__(256) npcount_kernel(const ProbDesc* __restrict
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int N = P.n * P.n, p = it.y * 256 + threadIdx.x;
   KSum k;
   if (p < N) {
@@ -96,6 +100,7 @@ __global__ void __launch_bounds__(256) img_dot_kernel(const ProbDesc* __restrict
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int N = P.n * P.n, p = it.y * 256 + threadIdx.x;
   KSum kd, kn;
   if (p < N) {
@@ -115,6 +120,7 @@ template <typename R>
 __global__ void __launch_bounds__(256) img_scale_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int dst, int src, int scalar) {
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int N = P.n * P.n, p = it.y * 256 + threadIdx.x;
   if (p >= N) return;
   const double nv = P.scal[scalar];
@@ -130,12 +136,14 @@ __global__ void fill_kernel(R* p, size_t count) {
 }
 
 // One workgroup per problem: scal[scalar] = sum of `count` pairs of generic region q
-// (region < 0: the de-grid region, n_p6 pairs).
+// (region < 0: the de-grid region, n_p6 pairs; count < 0: one pair per 256-pixel block of the
+// problem's image, so one launch serves problems of different sizes).
 __global__ void __launch_bounds__(256) finalize_kernel(const ProbDesc* __restrict__ descs, int q, int count, int scalar) {
   __shared__ double red[8];
   const ProbDesc& P = descs[blockIdx.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const double* src = (q < 0) ? P.partials : gen_part(P, q);
-  const int cnt = (q < 0) ? P.n_p6 : count;
+  const int cnt = (q < 0) ? P.n_p6 : (count < 0 ? (P.n * P.n + 255) / 256 : count);
   const double v = block_sum_partials(src, cnt, red);
   if (threadIdx.x == 0) P.scal[scalar] = v;
 }
@@ -144,6 +152,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(const ProbDesc* __restric
 __global__ void __launch_bounds__(256) finalize_max_kernel(const ProbDesc* __restrict__ descs, int q, int count, int scalar) {
   __shared__ double red[8];
   const ProbDesc& P = descs[blockIdx.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   const double* src = gen_part(P, q);
   double v = 0.0;
   for (int i = threadIdx.x; i < count; i += blockDim.x) v = fmax(v, src[2 * i]);
@@ -166,10 +175,49 @@ __global__ void scale_kernel(R* p, size_t count, R factor) {
 // zeta = 3 rms of the Stokes-I residual image scaled by 1/(2M)
 __global__ void finalize_zeta_kernel(const ProbDesc* __restrict__ descs) {
   const ProbDesc& P = descs[blockIdx.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
   if (threadIdx.x == 0) {
     const double N = (double)P.n * P.n;
     P.scal[SC_ZETA] = 3.0 * sqrt(P.scal[SC_RIMG2] / N) / (2.0 * (double)P.M);
   }
+}
+
+// After a check of the stopping quantities: every problem still running adds the `chunk`
+// iterations just run to scal[SC_ITERS] and is halted when the criteria of Sec. 4.6 hold:
+// ||phi(S) - Y|| <= (1 + theta) epsilon, the largest relative variation of the four Stokes maps
+// between the last two iterates <= the bound (a map that is zero in both counts as 0), and, if
+// its bound is >= 0, N_p <= that bound (percent).  active[0] = problems still running.  One
+// workgroup; problems strided over its threads.
+__global__ void __launch_bounds__(256) stop_decide_kernel(const ProbDesc* __restrict__ descs, int nprob, int chunk,
+                                                         int* __restrict__ active) {
+  __shared__ int running;
+  if (threadIdx.x == 0) running = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int i = threadIdx.x; i < nprob; i += blockDim.x) {
+    const ProbDesc& P = descs[i];
+    if (halted(P)) continue;
+    double* sc = P.scal;
+    sc[SC_ITERS] += (double)chunk;
+    const double res = sqrt(fmax(sc[SC_RES2], 0.0));
+    double rv = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const double num = sqrt(fmax(sc[SC_RV0 + q], 0.0)), den = sqrt(fmax(sc[SC_SN0 + q], 0.0));
+      rv = fmax(rv, den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0));
+    }
+    const double np = 100.0 * sc[SC_NPCOUNT] / ((double)P.n * P.n);
+    const bool met = res <= (1.0 + sc[SC_STOP_THETA]) * P.eps && rv <= sc[SC_STOP_RV] &&
+                     (sc[SC_STOP_NP] < 0.0 || np <= sc[SC_STOP_NP]);
+    if (met) sc[SC_HALT] = 1.0;
+    else ++mine;
+  }
+  atomicAdd(&running, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) active[0] = running;
+}
+
+void launch_stop_decide(const ProbDesc* descs, int nprob, int chunk, int* active, hipStream_t s) {
+  hipLaunchKernelGGL(stop_decide_kernel, dim3(1), dim3(256), 0, s, descs, nprob, chunk, active);
 }
 
 template <typename R> void launch_relvar(const LaunchArgs& a) {

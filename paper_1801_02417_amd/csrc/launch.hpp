@@ -51,6 +51,9 @@ template <typename R> void launch_fill(void* p, size_t count, hipStream_t s);
 // finalise: one workgroup per problem sums PART_GEN partials into scal[scalar]
 void launch_finalize(const ProbDesc* descs, int nprob, int region, int count, int scalar, hipStream_t s);
 void launch_finalize_zeta(const ProbDesc* descs, int nprob, hipStream_t s);
+// adaptive stopping: count the chunk's iterations, halt the problems whose criteria hold, and
+// write the number still running to active[0]
+void launch_stop_decide(const ProbDesc* descs, int nprob, int chunk, int* active, hipStream_t s);
 // scal[scalar] = max of the first entries of `count` pairs of generic region q
 void launch_finalize_max(const ProbDesc* descs, int nprob, int q, int count, int scalar, hipStream_t s);
 template <typename R> void launch_scale(void* p, size_t count, double factor, hipStream_t s);

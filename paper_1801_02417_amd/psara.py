@@ -32,7 +32,7 @@ EXPORTS = (
     "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
     "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_profile_passes",
     "psara_batch_solve", "psara_batch_reweighted_solve", "psara_batch_profile_passes", "psara_data_gamma",
-    "psara_set_gamma",
+    "psara_set_gamma", "psara_solve_adaptive", "psara_reweighted_solve_adaptive", "psara_batch_solve_adaptive",
     "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
     "psara_server_clock", "psara_server_last_error", "psara_server_destroy",
 )
@@ -50,6 +50,14 @@ class PsaraReport(C.Structure):
         return {"residual": self.residual, "epsilon": self.epsilon, "rel_var": list(self.rel_var),
                 "zeta": self.zeta, "n_p": self.n_p, "objective": self.objective, "vnorm": self.vnorm,
                 "iterations": int(self.iterations)}
+
+
+class PsaraStop(C.Structure):
+    _fields_ = [("theta", C.c_double), ("rel_var", C.c_double), ("np_max", C.c_double)]
+
+
+# the stopping criteria of the paper's simulations (theta, relative variation, N_p in percent)
+PAPER_STOP = (5e-3, 1e-5, 0.5)
 
 
 class PsaraRequest(C.Structure):
@@ -94,6 +102,11 @@ def lib() -> C.CDLL:
         "psara_set_steps": (I, [P, C.c_double, C.c_double, C.c_double, C.c_double]),
         "psara_opnorm": (I, [P, I, C.c_double, D]),
         "psara_solve": (I, [P, I, I, I, C.POINTER(PsaraReport)]),
+        "psara_solve_adaptive": (I, [P, I, I, I, C.POINTER(PsaraStop), C.POINTER(C.c_int), C.POINTER(PsaraReport)]),
+        "psara_reweighted_solve_adaptive": (I, [P, I, I, I, I, C.POINTER(PsaraStop), C.c_double,
+                                                C.POINTER(C.c_int), C.POINTER(PsaraReport)]),
+        "psara_batch_solve_adaptive": (I, [C.POINTER(P), I, I, I, I, C.POINTER(PsaraStop), C.POINTER(C.c_int),
+                                           C.POINTER(PsaraReport)]),
         "psara_reweight": (I, [P, C.c_double]),
         "psara_coef_std": (I, [P, D]),
         "psara_reweighted_solve": (I, [P, I, I, C.POINTER(C.c_int), C.c_double, C.POINTER(PsaraReport)]),
@@ -205,6 +218,35 @@ def psara_solve(ctx, mode: int, iters: int, check_every: int = 0, report: bool =
     rep = PsaraReport()
     _check(ctx, lib().psara_solve(ctx, mode, iters, check_every, C.byref(rep) if report else None))
     return rep.as_dict() if report else None
+
+
+def psara_solve_adaptive(ctx, mode: int, max_iters: int, check_every: int, stop=PAPER_STOP):
+    """Iterations until the criteria stop = (theta, rel_var, np_max) hold (checked on the device
+    every check_every iterations) or max_iters; returns (iterations run, report)."""
+    st, rep, it = PsaraStop(*[float(v) for v in stop]), PsaraReport(), C.c_int(0)
+    _check(ctx, lib().psara_solve_adaptive(ctx, mode, max_iters, check_every, C.byref(st), C.byref(it),
+                                           C.byref(rep)))
+    return it.value, rep.as_dict()
+
+
+def psara_reweighted_solve_adaptive(ctx, mode: int, cycles: int, max_iters_per_stage: int, check_every: int,
+                                    stop=PAPER_STOP, delta_decay: float = 10.0):
+    """Algorithm 2 with adaptive stages; returns (iterations per stage, report)."""
+    st, rep = PsaraStop(*[float(v) for v in stop]), PsaraReport()
+    its = (C.c_int * (cycles + 1))()
+    _check(ctx, lib().psara_reweighted_solve_adaptive(ctx, mode, cycles, max_iters_per_stage, check_every,
+                                                      C.byref(st), float(delta_decay), its, C.byref(rep)))
+    return list(its), rep.as_dict()
+
+
+def psara_batch_solve_adaptive(ctxs, mode: int, max_iters: int, check_every: int, stop=PAPER_STOP):
+    """Batched adaptive stage; returns (iterations per member, reports)."""
+    st = PsaraStop(*[float(v) for v in stop])
+    its = (C.c_int * len(ctxs))()
+    reps = (PsaraReport * len(ctxs))()
+    _batch_check(ctxs, lib().psara_batch_solve_adaptive(_ctx_array(ctxs), len(ctxs), mode, max_iters, check_every,
+                                                        C.byref(st), its, reps))
+    return list(its), [r.as_dict() for r in reps]
 
 
 def psara_reweight(ctx, delta: float) -> None:
@@ -482,6 +524,14 @@ class Solver:
     def reweighted_solve(self, mode: int, iters_per_stage, delta_decay: float = 10.0):
         return psara_reweighted_solve(self.ctx, mode, iters_per_stage, delta_decay)
 
+    def solve_adaptive(self, mode: int, max_iters: int, check_every: int, stop=PAPER_STOP):
+        return psara_solve_adaptive(self.ctx, mode, max_iters, check_every, stop)
+
+    def reweighted_solve_adaptive(self, mode: int, cycles: int, max_iters_per_stage: int, check_every: int,
+                                  stop=PAPER_STOP, delta_decay: float = 10.0):
+        return psara_reweighted_solve_adaptive(self.ctx, mode, cycles, max_iters_per_stage, check_every, stop,
+                                               delta_decay)
+
     def image(self) -> np.ndarray:
         return psara_get_image(self.ctx, self.N)
 
@@ -527,6 +577,10 @@ class Solver:
 
 def batch_solve(solvers: Sequence[Solver], mode: int, iters: int, report: bool = True):
     return psara_batch_solve([s.ctx for s in solvers], mode, iters, report)
+
+
+def batch_solve_adaptive(solvers: Sequence[Solver], mode: int, max_iters: int, check_every: int, stop=PAPER_STOP):
+    return psara_batch_solve_adaptive([s.ctx for s in solvers], mode, max_iters, check_every, stop)
 
 
 def batch_reweighted_solve(solvers: Sequence[Solver], mode: int, iters_per_stage, delta_decay: float = 10.0):

@@ -34,7 +34,7 @@ def test_kb_shape_parameter_values():
 
 @pytest.mark.parametrize("n,taps", [(8, 6), (16, 8), (32, 6)])
 def test_adjoint_identity(n, taps):
-    """<Phi x, y> = <x, Phi^dagger y> for complex x, y (spec check a)."""
+    """<Phi x, y> = <x, Phi^dagger y> for complex x, y."""
     rng = np.random.default_rng(n + taps)
     nu = NUFFT(_rand_uv(rng, 77), n, 2, taps)
     x = rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)
@@ -77,7 +77,7 @@ def test_phi_adj_phi_is_twice_Phi_adj_Phi():
 
 @pytest.mark.parametrize("n", [8, 16])
 def test_nufft_matches_direct_dft_and_improves_with_taps(n):
-    """NUFFT vs the direct transform on tiny grids (spec check b)."""
+    """NUFFT vs the direct transform on tiny grids."""
     rng = np.random.default_rng(10 + n)
     uv = rng.uniform(-math.pi, math.pi, size=(50, 2))
     x = rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Algorithm 1 / Algorithm 2 (Sec. 3.3; spec check e)."""
+"""Pins of the oracle's Algorithm 1 / Algorithm 2 (Sec. 3.3)."""
 import dataclasses
 import json
 import math
@@ -254,3 +254,70 @@ def test_metrics():
 def test_chi2_epsilon():
     # eps^2 = (8M + 2 sqrt(2 * 8M)) sigma^2 / 2 with M = 2, sigma = 1: (16 + 2*sqrt(32))/2
     assert abs(problem.chi2_epsilon(2, 1.0) ** 2 - (16 + 2 * math.sqrt(32)) / 2) < 1e-13
+
+
+def test_stop_criteria_closed_forms():
+    """The stopping test on states whose quantities are known exactly: noise-free data
+    Y = phi(S_true), so the residual at S_true is 0 and the residual image (hence zeta) is 0;
+    N_p then counts the pixels with ||S_2:4|| > S_1 by construction; the relative variation
+    is the column-norm ratio, with 0/0 read as 0 and x/0 as infinite."""
+    wl = wk.tiny(n=16, M=150, taps=6, levels=2, seed=7)
+    b = problem.build(wl)
+    S = wl.truth.reshape(-1, 4).copy()
+    pb = dataclasses.replace(b.pb, Y=b.pb.phi(S), eps=1e-3)
+    # residual 0 <= (1 + theta) eps; unchanged iterate: relative variation 0; truth in the cone
+    met, res, rv, n_p = pd.stop_criteria(pb, S, S, 0.0, 0.0, 0.0)
+    assert met and res < 1e-12 and rv == 0.0 and n_p == 0.0
+    # a known relative variation per map: scale map 2 by 1.1 -> 0.1 / 1
+    S2 = S.copy()
+    S2[:, 2] *= 1.1
+    _, _, rv, _ = pd.stop_criteria(pb, S2, S, 1e9, 1.0, -1.0)
+    assert abs(rv - 0.1) < 1e-12
+    assert not pd.stop_criteria(pb, S2, S, 1e9, 0.0999, -1.0)[0]
+    assert pd.stop_criteria(pb, S2, S, 1e9, 0.1001, -1.0)[0]
+    # 0/0 -> 0 and x/0 -> inf for a map that is zero in the old iterate
+    Sz = S.copy()
+    Sz[:, 3] = 0.0
+    assert pd.stop_criteria(pb, Sz, Sz, 1e9, 0.0, -1.0)[2] == 0.0
+    Sn = Sz.copy()
+    Sn[0, 3] = 1e-3
+    assert pd.stop_criteria(pb, Sn, Sz, 1e9, 1e9, -1.0)[2] == math.inf
+    # N_p: push k pixels out of the cone (zeta = 0 with noise-free data at S)
+    k = 13
+    Sp = S.copy()
+    Sp[:k, 1] = Sp[:k, 0] + 1.0
+    pbp = dataclasses.replace(pb, Y=pb.phi(Sp))
+    _, _, _, n_p = pd.stop_criteria(pbp, Sp, Sp, 0.0, 0.0, 0.0)
+    assert abs(n_p - 100.0 * k / S.shape[0]) < 1e-12
+    assert not pd.stop_criteria(pbp, Sp, Sp, 0.0, 0.0, 100.0 * k / S.shape[0] - 1e-9)[0]
+    assert pd.stop_criteria(pbp, Sp, Sp, 0.0, 0.0, 100.0 * k / S.shape[0])[0]
+    # the residual bound: (1 + theta) eps with eps at the residual of S = 0
+    r0 = float(np.linalg.norm(pb.Y))
+    pbr = dataclasses.replace(pb, eps=r0)
+    Z = np.zeros_like(S)
+    assert pd.stop_criteria(pbr, Z, Z, 0.0, 0.0, -1.0)[0]
+    assert not pd.stop_criteria(dataclasses.replace(pbr, eps=r0 * (1 - 1e-6)), Z, Z, 0.0, 0.0, -1.0)[0]
+
+
+def test_run_alg1_adaptive_stops_at_first_passing_check(tiny_built):
+    """run_alg1_adaptive returns the state of run_alg1 after the iterations it reports, the test
+    fails after every earlier block and holds after the last one; with an unreachable test it
+    runs exactly max_iters (a last partial block included)."""
+    b = tiny_built
+    J = b.sara.J
+    gW = b.gamma * np.ones((J, 4))
+    N = b.pb.psi(np.zeros((J, 4))).shape[0]
+    st0 = pd.run_alg1(pd.State.zeros(N, J, b.pb.Y.shape[0]), b.pb, gW, 10, "init")
+    crit = (0.05, 2e-3, 5.0)
+    st, it = pd.run_alg1_adaptive(st0.copy(), b.pb, gW, "polsara", 400, 10, *crit)
+    assert 0 < it < 400 and it % 10 == 0
+    ref = st0.copy()
+    for k in range(it):
+        prev = ref.S
+        ref = pd.alg1_iteration(ref, b.pb, gW, "polsara")
+        if (k + 1) % 10 == 0:
+            met = pd.stop_criteria(b.pb, ref.S, prev, *crit)[0]
+            assert met == (k + 1 == it), k
+    assert np.array_equal(ref.S, st.S)
+    _, it2 = pd.run_alg1_adaptive(st0.copy(), b.pb, gW, "polsara", 25, 10, 0.0, 0.0, 0.0)
+    assert it2 == 25

@@ -1,4 +1,4 @@
-"""Pins of the oracle's projections and thresholding (Sec. 3.3; spec check d)."""
+"""Pins of the oracle's projections and thresholding (Sec. 3.3)."""
 import math
 
 import numpy as np

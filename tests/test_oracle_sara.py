@@ -75,7 +75,7 @@ def test_haar_dwt_by_hand():
 
 @pytest.mark.parametrize("n,levels", [(16, 2), (32, 3), (8, 3)])
 def test_tight_frame_and_orthonormal_bases(n, levels):
-    """Psi Psi^dagger = I and W_b^dagger W_b = I (spec check c)."""
+    """Psi Psi^dagger = I and W_b^dagger W_b = I."""
     rng = np.random.default_rng(n)
     sara = SARA(n, levels)
     X = rng.standard_normal((n * n, 4))

@@ -289,7 +289,9 @@ psara_status psara_batch_profile_passes(psara_ctx* const* ctxs, int count, psara
  * PSARA_SERVE_FIFO instead runs one request at a time in arrival order.  Each result equals
  * the same request solved alone with psara_* calls in the order the server uses (operator,
  * data, prior with gamma 1, opnorm, data gamma, steps 0.99/3, 1, 1/||phi||^2, 1, then
- * psara_reweighted_solve).  Thread-safe for submit and poll. */
+ * psara_reweighted_solve, or psara_reweighted_solve_adaptive for a request with check_every > 0:
+ * such a request leaves the batch as soon as its stage's criteria hold on the device).
+ * Thread-safe for submit and poll. */
 typedef struct psara_server psara_server;
 
 typedef enum { PSARA_SERVE_BATCHED = 0, PSARA_SERVE_FIFO = 1 } psara_serve_policy;
@@ -311,6 +313,11 @@ typedef struct {
   double gamma_factor;         /* gamma = gamma_factor ||Psi^dagger Re phi^dagger Y||_inf / ||phi||^2 */
   int opnorm_iters;            /* power-iteration limit and relative tolerance */
   double opnorm_rtol;
+  int check_every;             /* 0: every stage runs its iters_per_stage iterations; > 0: a stage
+                                  ends early when `stop` holds (psara_reweighted_solve_adaptive,
+                                  tested every check_every iterations, iters_per_stage the bounds,
+                                  each a multiple of check_every) */
+  psara_stop stop;             /* stopping criteria when check_every > 0 */
 } psara_request;
 
 typedef enum { PSARA_REQ_QUEUED = 0, PSARA_REQ_RUNNING = 1, PSARA_REQ_DONE = 2, PSARA_REQ_FAILED = 3 } psara_req_state;

@@ -62,9 +62,10 @@ enum Scalar {
   SC_STOP_THETA,    // residual bound (1 + theta) epsilon
   SC_STOP_RV,       // bound of the largest relative variation of the four maps
   SC_STOP_NP,       // bound of N_p in percent (< 0: not used)
+  SC_STOP_MAXIT,    // halt once SC_ITERS reaches it (0: no bound on the device)
   NUM_SCALARS = 32
 };
-static_assert(SC_STOP_NP < NUM_SCALARS, "scalar slots");
+static_assert(SC_STOP_MAXIT < NUM_SCALARS, "scalar slots");
 // Partial sums per problem, each a (sum, compensation) pair of doubles: first the de-grid
 // region (n_p6 pairs), then kGenQ generic regions of gen_stride pairs each.
 constexpr int kGenQ = 8;

@@ -584,10 +584,18 @@ void Engine<R>::launch_iterations(int mode, int count) {
 }
 
 template <typename R>
-void Engine<R>::stop_begin(const double* stop) {
+void Engine<R>::stop_begin(const double* stop, int max_iters) {
   sync_desc();
-  const double v[5] = {0.0, 0.0, stop[0], stop[1], stop[2]};    // SC_HALT .. SC_STOP_NP
+  const double v[6] = {0.0, 0.0, stop[0], stop[1], stop[2], (double)max_iters};   // SC_HALT .. SC_STOP_MAXIT
   copy_sync(h_.scal + SC_HALT, v, sizeof(v), hipMemcpyHostToDevice, s0_, "stop set-up");
+}
+
+template <typename R>
+void Engine<R>::stop_poll(bool* halted_out, int* iters) {
+  double v[2] = {0.0, 0.0};                                     // SC_HALT, SC_ITERS
+  copy_sync(v, h_.scal + SC_HALT, sizeof(v), hipMemcpyDeviceToHost, s0_, "stop read");
+  *halted_out = v[0] != 0.0;
+  *iters = (int)v[1];
 }
 
 template <typename R>
@@ -1132,44 +1140,65 @@ void Batch<R>::run(int mode, int iters) {
 }
 
 template <typename R>
+void Batch<R>::adaptive_buffers() {
+  if (d_active_) return;
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(int)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(PSARA_ENOMEM, "batch flag allocation failed");
+  }
+  allocs_.push_back(p);
+  d_active_ = (int*)p;
+  if (hipHostMalloc(&p, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(PSARA_ENOMEM, "pinned host allocation failed");
+  }
+  h_active_ = (int*)p;
+  for (int i = 0; i < 2; ++i) hip_check(hipEventCreateWithFlags(&ev_active_[i], hipEventDisableTiming), "event");
+}
+
+// The captured chunk of an adaptive run: `count` iterations, the check, the decision.
+template <typename R>
+hipGraphExec_t Batch<R>::adaptive_graph(int mode, int count) {
+  const int key = 1000000 + mode * 1000 + count;
+  auto it = graphs_.find(key);
+  if (it != graphs_.end()) return it->second;
+  adaptive_buffers();
+  const int nprob = (int)members_.size();
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
+  launch_iterations<R>(pl_, mode, count, s0_, s1_, ev_fork_, ev_join_);
+  launch_check<R>(pl_, nprob, s0_);
+  launch_stop_decide(pl_.descs, nprob, count, d_active_, s0_);
+  hip_check(hipStreamEndCapture(s0_, &g), "end capture");
+  hipGraphExec_t exec = nullptr;
+  hip_check(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
+  (void)hipGraphDestroy(g);
+  graphs_[key] = exec;
+  return exec;
+}
+
+template <typename R>
+void Batch<R>::capture_adaptive(int mode, int check_every) {
+  if ((mode != PM_INIT) && !pl_.sparse) throw Error(PSARA_ESTATE, "every batch member needs a wavelet prior in this mode");
+  adaptive_graph(mode, check_every);
+}
+
+template <typename R>
+void Batch<R>::launch_adaptive(int mode, int chunks, int check_every) {
+  run(mode, 0);                      // uploads the members' current descriptors
+  for (int c = 0; c < chunks; ++c) hip_check(hipGraphLaunch(adaptive_graph(mode, check_every), s0_), "graph launch");
+}
+
+template <typename R>
 void Batch<R>::run_adaptive(int mode, int max_iters, int check_every, const double* stop, int* iters_out) {
   if ((mode != PM_INIT) && !pl_.sparse) throw Error(PSARA_ESTATE, "every batch member needs a wavelet prior in this mode");
   for (Engine<R>* e : members_) e->stop_begin(stop);
   run(mode, 0);                      // uploads the members' current descriptors
-  if (!d_active_) {
-    void* p = nullptr;
-    if (hipMalloc(&p, sizeof(int)) != hipSuccess || !p) {
-      (void)hipGetLastError();
-      throw Error(PSARA_ENOMEM, "batch flag allocation failed");
-    }
-    allocs_.push_back(p);
-    d_active_ = (int*)p;
-    if (hipHostMalloc(&p, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess || !p) {
-      (void)hipGetLastError();
-      throw Error(PSARA_ENOMEM, "pinned host allocation failed");
-    }
-    h_active_ = (int*)p;
-    for (int i = 0; i < 2; ++i) hip_check(hipEventCreateWithFlags(&ev_active_[i], hipEventDisableTiming), "event");
-  }
-  const int nprob = (int)members_.size();
-  auto graph = [&](int count) -> hipGraphExec_t {
-    const int key = 1000000 + mode * 1000 + count;
-    auto it = graphs_.find(key);
-    if (it != graphs_.end()) return it->second;
-    hipGraph_t g = nullptr;
-    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
-    launch_iterations<R>(pl_, mode, count, s0_, s1_, ev_fork_, ev_join_);
-    launch_check<R>(pl_, nprob, s0_);
-    launch_stop_decide(pl_.descs, nprob, count, d_active_, s0_);
-    hip_check(hipStreamEndCapture(s0_, &g), "end capture");
-    hipGraphExec_t exec = nullptr;
-    hip_check(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
-    (void)hipGraphDestroy(g);
-    graphs_[key] = exec;
-    return exec;
-  };
+  adaptive_buffers();
+  auto graph = [&](int count) { return adaptive_graph(mode, count); };
   adaptive_loop(graph, max_iters, check_every, s0_, d_active_, h_active_, ev_active_);
-  for (int i = 0; i < nprob; ++i) {
+  for (size_t i = 0; i < members_.size(); ++i) {
     const int it = members_[i]->stop_end();
     if (iters_out) iters_out[i] = it;
   }

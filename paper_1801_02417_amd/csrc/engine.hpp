@@ -100,7 +100,10 @@ struct Engine {
   // Up to max_iters iterations, checking the stopping criteria stop = {theta, rel_var, np_max}
   // on the device after every check_every of them; returns the iterations run.
   int run_adaptive(int mode, int max_iters, int check_every, const double* stop);
-  void stop_begin(const double* stop);  // clear the halt flag and counter, store the criteria
+  // clear the halt flag and counter, store the criteria and a device-side iteration bound
+  // (0: none; the host bounds the run instead)
+  void stop_begin(const double* stop, int max_iters = 0);
+  void stop_poll(bool* halted, int* iters);   // the halt flag and the iterations counted so far
   int stop_end();                       // iterations run by the adaptive run; clears the halt flag
   void report(psara_report* r);
   double coef_std();
@@ -201,11 +204,17 @@ struct Batch {
   void profile(int mode, int iters, double* ms);   // per-pass times over all members (as Engine)
   // adaptive stopping per member (as Engine::run_adaptive); iters_out: iterations per member
   void run_adaptive(int mode, int max_iters, int check_every, const double* stop, int* iters_out);
+  // the pieces of an adaptive run for a caller that polls on its own: capture the chunk graph
+  // (no work launched), and queue `chunks` chunks (the members' criteria set by stop_begin)
+  void capture_adaptive(int mode, int check_every);
+  void launch_adaptive(int mode, int chunks, int check_every);
   hipStream_t stream() const { return s0_; }
   int size() const { return (int)members_.size(); }
 
  private:
   hipGraphExec_t graph(int mode, int count);
+  hipGraphExec_t adaptive_graph(int mode, int count);
+  void adaptive_buffers();
   std::vector<Engine<R>*> members_;
   hipStream_t s0_ = nullptr, s1_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;

@@ -186,7 +186,8 @@ __global__ void finalize_zeta_kernel(const ProbDesc* __restrict__ descs) {
 // iterations just run to scal[SC_ITERS] and is halted when the criteria of Sec. 4.6 hold:
 // ||phi(S) - Y|| <= (1 + theta) epsilon, the largest relative variation of the four Stokes maps
 // between the last two iterates <= the bound (a map that is zero in both counts as 0), and, if
-// its bound is >= 0, N_p <= that bound (percent).  active[0] = problems still running.  One
+// its bound is >= 0, N_p <= that bound (percent); a problem is also halted once its iterations
+// reach scal[SC_STOP_MAXIT] when that is > 0.  active[0] = problems still running.  One
 // workgroup; problems strided over its threads.
 __global__ void __launch_bounds__(256) stop_decide_kernel(const ProbDesc* __restrict__ descs, int nprob, int chunk,
                                                          int* __restrict__ active) {
@@ -208,7 +209,8 @@ __global__ void __launch_bounds__(256) stop_decide_kernel(const ProbDesc* __rest
     const double np = 100.0 * sc[SC_NPCOUNT] / ((double)P.n * P.n);
     const bool met = res <= (1.0 + sc[SC_STOP_THETA]) * P.eps && rv <= sc[SC_STOP_RV] &&
                      (sc[SC_STOP_NP] < 0.0 || np <= sc[SC_STOP_NP]);
-    if (met) sc[SC_HALT] = 1.0;
+    const bool spent = sc[SC_STOP_MAXIT] > 0.0 && sc[SC_ITERS] >= sc[SC_STOP_MAXIT];
+    if (met || spent) sc[SC_HALT] = 1.0;
     else ++mine;
   }
   atomicAdd(&running, mine);

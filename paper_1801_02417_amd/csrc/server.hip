@@ -39,6 +39,7 @@ struct Job {
   // progress, owned by the thread that holds the job
   psara_ctx* ctx = nullptr;
   int stage = 0, left = 0;
+  int it_seen = 0;                 // adaptive stages: iterations of the stage already booked
   double delta = 0.0;
   // result, guarded by the server mutex
   int state = PSARA_REQ_QUEUED;
@@ -52,6 +53,29 @@ using JobP = std::shared_ptr<Job>;
 int stage_mode(const Job& j) {
   if (j.stage == 0) return psara::PM_INIT;
   return j.req.mode == PSARA_UNCONSTRAINED ? psara::PM_UNCONSTRAINED : psara::PM_CONSTRAINED;
+}
+
+bool adaptive(const Job& j) { return j.req.check_every > 0; }
+
+// Sets the device-side stopping state of an adaptive job's current stage: its criteria (the
+// initialisation stage leaves N_p out, as psara_reweighted_solve_adaptive does) and its
+// iteration bound, at which the device halts it as well.
+void begin_stage(Job& j) {
+  j.it_seen = 0;
+  if (!adaptive(j)) return;
+  const double v[3] = {j.req.stop.theta, j.req.stop.rel_var, j.stage == 0 ? -1.0 : j.req.stop.np_max};
+  if (j.req.precision == PSARA_FP64) j.ctx->f64->stop_begin(v, j.stages[j.stage]);
+  else j.ctx->f32->stop_begin(v, j.stages[j.stage]);
+}
+
+void stop_poll(Job& j, bool* halted, int* iters) {
+  if (j.req.precision == PSARA_FP64) j.ctx->f64->stop_poll(halted, iters);
+  else j.ctx->f32->stop_poll(halted, iters);
+}
+
+void stop_end(Job& j) {
+  if (j.req.precision == PSARA_FP64) (void)j.ctx->f64->stop_end();
+  else (void)j.ctx->f32->stop_end();
 }
 
 }  // namespace
@@ -147,6 +171,14 @@ psara_status prepare_device(psara_server* S, Job& j, std::string& msg) {
   j.ctx = c;
   j.stage = 0;
   j.left = j.stages[0];
+  try {
+    begin_stage(j);
+  } catch (const psara::Error& e) {
+    msg = e.msg;
+    psara_destroy(c);
+    j.ctx = nullptr;
+    return e.status;
+  }
   return PSARA_OK;
 }
 
@@ -181,7 +213,7 @@ void setup_loop(psara_server* S) {
 // iteration time (at most `quantum`): small problems then advance many iterations while a large
 // one advances a few, instead of all moving in lockstep at the pace of the largest.
 constexpr double kRoundSeconds = 0.01;
-using GroupKey = std::tuple<int, int, int, int>;   // mode, precision, taps, side
+using GroupKey = std::tuple<int, int, int, int, int>;   // mode, precision, taps, side, check_every
 
 struct Group {
   std::vector<psara_ctx*> key;          // members the cached batch was built for
@@ -229,19 +261,36 @@ void prepare_round(Group& G, int mode) {
     }
     G.key = ctxs;
   }
-  if (G.bd) G.bd->capture(mode);
-  else G.bf->capture(mode);
+  const int ce = G.mem[0]->req.check_every;
+  if (ce > 0) {
+    if (G.bd) G.bd->capture_adaptive(mode, ce);
+    else G.bf->capture_adaptive(mode, ce);
+  } else if (G.bd) {
+    G.bd->capture(mode);
+  } else {
+    G.bf->capture(mode);
+  }
 }
 
-// Queues one round of the group: graph launches only.
+// Queues one round of the group: graph launches only.  An adaptive group runs whole chunks of
+// check_every iterations (each followed by the check on the device); its members stop on the
+// device, at their criteria or at their stage's bound.
 void launch_round(Group& G, int mode, int quantum) {
   int left = 1 << 30;
   for (auto& j : G.mem) left = std::min(left, j->left);
   int k = G.t_iter > 0.0 ? (int)std::min<double>(quantum, std::max(1.0, kRoundSeconds / G.t_iter)) : std::min(quantum, 8);
-  G.k = std::max(1, std::min(k, left));
+  const int ce = G.mem[0]->req.check_every;
   psara::hip_check(hipEventRecord(G.e0, G.stream), "round start");
-  if (G.bd) G.bd->run(mode, G.k);
-  else G.bf->run(mode, G.k);
+  if (ce > 0) {
+    const int chunks = std::max(1, k / ce);
+    G.k = chunks * ce;
+    if (G.bd) G.bd->launch_adaptive(mode, chunks, ce);
+    else G.bf->launch_adaptive(mode, chunks, ce);
+  } else {
+    G.k = std::max(1, std::min(k, left));
+    if (G.bd) G.bd->run(mode, G.k);
+    else G.bf->run(mode, G.k);
+  }
   psara::hip_check(hipEventRecord(G.e1, G.stream), "round end");
   G.launched = true;
 }
@@ -254,8 +303,17 @@ void finish_round(Group& G) {
   const double t = 1e-3 * ms / G.k;
   G.t_iter = G.t_iter > 0.0 ? 0.5 * (G.t_iter + t) : t;
   for (auto& j : G.mem) {
-    j->left -= G.k;
-    j->ctx->iterations += G.k;
+    if (adaptive(*j)) {
+      bool halted = false;
+      int it = 0;
+      stop_poll(*j, &halted, &it);
+      j->ctx->iterations += it - j->it_seen;
+      j->it_seen = it;
+      j->left = halted ? 0 : std::max(1, j->stages[j->stage] - it);
+    } else {
+      j->left -= G.k;
+      j->ctx->iterations += G.k;
+    }
   }
   G.launched = false;
 }
@@ -263,6 +321,18 @@ void finish_round(Group& G) {
 // Moves a job whose stage has ended to its next stage (reweighting it), or finishes it.
 // Returns true when the job is finished (its result stored, its context released).
 bool advance(psara_server* S, Job& j) {
+  auto fail = [&](psara_status st, const std::string& m) {
+    psara_destroy(j.ctx);
+    j.ctx = nullptr;
+    std::lock_guard<std::mutex> lk(S->mu);
+    retire(S, j, PSARA_REQ_FAILED, st, m);
+    return true;
+  };
+  try {
+    if (j.left == 0 && adaptive(j)) stop_end(j);     // clears the halt flag
+  } catch (const psara::Error& e) {
+    return fail(e.status, e.msg);
+  }
   while (j.left == 0) {
     if (j.stage == 0) {
       if (psara_coef_std(j.ctx, &j.delta) != PSARA_OK || !(j.delta > 0.0)) {
@@ -287,6 +357,11 @@ bool advance(psara_server* S, Job& j) {
       j.delta /= j.req.delta_decay;
       j.stage += 1;
       j.left = j.stages[j.stage];
+      try {
+        begin_stage(j);
+      } catch (const psara::Error& e) {
+        return fail(e.status, e.msg);
+      }
       continue;
     }
     psara_report rep;
@@ -318,7 +393,7 @@ void fail_jobs(psara_server* S, std::vector<JobP>& mem, psara_status st, const s
 }
 
 GroupKey key_of(const Job& j) {
-  return std::make_tuple(stage_mode(j), (int)j.req.precision, j.req.taps, j.req.n);
+  return std::make_tuple(stage_mode(j), (int)j.req.precision, j.req.taps, j.req.n, j.req.check_every);
 }
 
 void worker_loop(psara_server* S) {
@@ -457,6 +532,13 @@ psara_status psara_server_submit(psara_server* S, const psara_request* r, uint64
   if (!(r->delta_decay > 1.0) || !(r->gamma_factor > 0.0) || r->opnorm_iters < 1) return bad("request: bad parameters");
   for (int l = 0; l <= r->cycles; ++l)
     if (r->iters_per_stage[l] < 0) return bad("request: negative iteration count");
+  if (r->check_every < 0) return bad("request: negative check_every");
+  if (r->check_every > 0) {
+    if (!(r->stop.theta >= 0.0) || !(r->stop.rel_var >= 0.0) || std::isnan(r->stop.np_max))
+      return bad("request: bad stopping criteria");
+    for (int l = 0; l <= r->cycles; ++l)
+      if (r->iters_per_stage[l] % r->check_every != 0) return bad("request: stage bounds must be multiples of check_every");
+  }
   JobP j = std::make_shared<Job>();
   try {
     j->req = *r;

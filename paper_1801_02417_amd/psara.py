@@ -65,7 +65,8 @@ class PsaraRequest(C.Structure):
                 ("epsilon", C.c_double), ("taps", C.c_int), ("levels", C.c_int), ("basis_mask", C.c_uint32),
                 ("precision", C.c_int), ("mode", C.c_int), ("cycles", C.c_int),
                 ("iters_per_stage", C.POINTER(C.c_int)), ("delta_decay", C.c_double),
-                ("gamma_factor", C.c_double), ("opnorm_iters", C.c_int), ("opnorm_rtol", C.c_double)]
+                ("gamma_factor", C.c_double), ("opnorm_iters", C.c_int), ("opnorm_rtol", C.c_double),
+                ("check_every", C.c_int), ("stop", PsaraStop)]
 
 
 class PsaraResult(C.Structure):
@@ -433,13 +434,15 @@ def psara_server_submit(srv, n: int, uv: np.ndarray, Y: np.ndarray, epsilon: flo
                         basis_mask: int = ALL_BASES, precision: int = PSARA_FP32_MIXED,
                         mode: int = PSARA_CONSTRAINED, iters_per_stage: Sequence[int] = (100, 100, 100),
                         delta_decay: float = 10.0, gamma_factor: float = 1e-3, opnorm_iters: int = 200,
-                        opnorm_rtol: float = 1e-6) -> int:
+                        opnorm_rtol: float = 1e-6, check_every: int = 0, stop=PAPER_STOP) -> int:
+    """Queue a request; with check_every > 0 its stages end when `stop` holds on the device
+    (iters_per_stage are then the bounds, multiples of check_every)."""
     uv = _f64(uv)
     y = _vis(Y)
     stages = (C.c_int * len(iters_per_stage))(*[int(v) for v in iters_per_stage])
     req = PsaraRequest(n, uv.shape[0], _dptr(uv), _dptr(y), float(epsilon), taps, levels, basis_mask, precision,
                        mode, len(iters_per_stage) - 1, stages, float(delta_decay), float(gamma_factor),
-                       opnorm_iters, float(opnorm_rtol))
+                       opnorm_iters, float(opnorm_rtol), int(check_every), PsaraStop(*[float(v) for v in stop]))
     ticket = C.c_uint64()
     _server_check(srv, lib().psara_server_submit(srv, C.byref(req), C.byref(ticket)))
     return ticket.value

@@ -117,3 +117,61 @@ def test_bad_request_rejected():
         assert r["state"] == P.PSARA_REQ_FAILED and r["status"] == P.PSARA_EINVAL
     finally:
         P.psara_server_destroy(srv)
+
+
+ADAPT_BOUND, ADAPT_CHECK, ADAPT_STOP = 120, 10, (5e-3, 5e-4, 0.5)
+
+
+def solve_alone_adaptive(wl, Y, eps, prec):
+    ctx = P.psara_create(0)
+    try:
+        P.psara_set_operator(ctx, wl.n, wl.uv, 2, wl.taps, prec)
+        P.psara_set_data(ctx, Y, eps)
+        P.psara_set_prior(ctx, P.ALL_BASES, wl.levels, None, 1.0)
+        nrm = P.psara_opnorm(ctx, NORM_ITERS, NORM_RTOL)
+        P.psara_set_gamma(ctx, P.psara_data_gamma(ctx, 1e-3))
+        P.psara_set_steps(ctx, 0.99 / 3.0, 1.0, 1.0 / nrm, 1.0)
+        its, rep = P.psara_reweighted_solve_adaptive(ctx, P.PSARA_CONSTRAINED, 2, ADAPT_BOUND, ADAPT_CHECK,
+                                                     ADAPT_STOP, 10.0)
+        return P.psara_get_image(ctx, wl.n * wl.n), rep["iterations"]
+    finally:
+        P.psara_destroy(ctx)
+
+
+@pytest.mark.parametrize("policy", [P.PSARA_SERVE_BATCHED, P.PSARA_SERVE_FIFO])
+def test_served_adaptive_equals_alone(policy):
+    """Requests whose stages end by the stopping test leave the batch on their own; each gets
+    bit for bit the image (and iteration count) of psara_reweighted_solve_adaptive alone, and
+    at least one stops before its bounds."""
+    reqs = requests()
+    alone = [solve_alone_adaptive(wl, Y, eps, P.PSARA_FP32_MIXED) for wl, Y, eps in reqs]
+    say(f"adaptive iterations alone: {[a[1] for a in alone]} (bound {3 * ADAPT_BOUND})")
+    assert any(a[1] < 3 * ADAPT_BOUND for a in alone)
+    srv = P.psara_server_create(0, 8 << 30, 16, 30, policy)
+    try:
+        tickets = [P.psara_server_submit(srv, wl.n, wl.uv, Y, eps, taps=wl.taps, levels=wl.levels,
+                                         iters_per_stage=(ADAPT_BOUND,) * 3, opnorm_iters=NORM_ITERS,
+                                         opnorm_rtol=NORM_RTOL, check_every=ADAPT_CHECK, stop=ADAPT_STOP)
+                   for wl, Y, eps in reqs]
+        P.psara_server_drain(srv)
+        for (wl, _, _), t, (img_a, it_a) in zip(reqs, tickets, alone):
+            img = np.empty((wl.n * wl.n, 4))
+            r = P.psara_server_poll(srv, t, img)
+            assert r["state"] == P.PSARA_REQ_DONE, (r, P.lib().psara_server_last_error(srv))
+            assert r["report"]["iterations"] == it_a, (wl.name, r["report"]["iterations"], it_a)
+            assert np.array_equal(img, img_a), f"{wl.name}: served image differs"
+    finally:
+        P.psara_server_destroy(srv)
+
+
+def test_adaptive_request_validation():
+    srv = P.psara_server_create(0, 8 << 30, 4, 8, P.PSARA_SERVE_BATCHED)
+    try:
+        wl, Y, eps = requests()[0]
+        with pytest.raises(P.PsaraError):       # bounds must be multiples of check_every
+            P.psara_server_submit(srv, wl.n, wl.uv, Y, eps, iters_per_stage=(15, 20, 20), check_every=10)
+        with pytest.raises(P.PsaraError):
+            P.psara_server_submit(srv, wl.n, wl.uv, Y, eps, iters_per_stage=(10, 20, 20), check_every=10,
+                                  stop=(-1.0, 1e-3, 0.5))
+    finally:
+        P.psara_server_destroy(srv)

@@ -59,3 +59,35 @@ def test_footprint_formula_scales():
     assert 30e6 < a < 200e6
     assert b > 3 * a
     assert P.psara_footprint(100, 10, 8, 4) == 0          # not a power of two
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the C-ABI structs have the sizes and field offsets a C compiler
+    gives the declarations in include/psara.h."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    checks = {"psara_report": (P.PsaraReport, ["residual", "rel_var", "n_p", "iterations"]),
+              "psara_stop": (P.PsaraStop, ["theta", "rel_var", "np_max"]),
+              "psara_request": (P.PsaraRequest, ["M", "uv", "epsilon", "iters_per_stage", "opnorm_rtol",
+                                                 "check_every", "stop"]),
+              "psara_result": (P.PsaraResult, ["t_submit", "n", "report"])}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "psara.h"', "int main(void) {"]
+    for name, (_, fields) in checks.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for name, (cls, fields) in checks.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for f in fields:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)

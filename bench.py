@@ -28,6 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# served form with adaptive stages: the paper's residual tolerance and N_p bound, a relative
+# variation of 1e-3 (the paper's 1e-5 is not reached within the stage bounds used here), tested
+# on the device every 20 iterations, the fixed runs' stage lengths as bounds
+ADAPTIVE_STOP, ADAPTIVE_CHECK = (5e-3, 1e-3, 0.5), 20
 PASS_SOURCES = ["kernels_fft.hip", "kernels_dwt.hip", "kernels_dwt.hip", "kernels_fft.hip", "kernels_fft.hip",
                 "kernels_grid.hip", "kernels_grid.hip", "kernels_fft.hip", "kernels_fft.hip", "kernels_fft.hip"]
 PASS_KERNELS = ["fft_pass_kernel<float,512,0,0>", "analysis_kernel+coarse_kernel+synthesis_kernel+synthesis_final_kernel",
@@ -198,7 +202,9 @@ def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dic
     out = {"requests": count, "rate_per_s": rate, "iters_per_solve": sum(stages),
            "sides": sorted({wl.n for wl, _, _ in reqs})}
     images = {}
-    for name, policy in (("batched", P.PSARA_SERVE_BATCHED), ("fifo", P.PSARA_SERVE_FIFO)):
+    runs = (("batched", P.PSARA_SERVE_BATCHED, 0), ("fifo", P.PSARA_SERVE_FIFO, 0),
+            ("batched_adaptive", P.PSARA_SERVE_BATCHED, ADAPTIVE_CHECK))
+    for name, policy, check in runs:
         progress(f"served form: {name} server")
         srv = P.psara_server_create(0, int(budget_gb * (1 << 30)), 64, 300, policy)
         try:
@@ -208,10 +214,11 @@ def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dic
                 if wait > 0:
                     time.sleep(wait)
                 tickets.append(P.psara_server_submit(srv, wl.n, wl.uv, Y, eps, taps=wl.taps, levels=wl.levels,
-                                                     iters_per_stage=stages, opnorm_iters=100, opnorm_rtol=1e-4))
+                                                     iters_per_stage=stages, opnorm_iters=100, opnorm_rtol=1e-4,
+                                                     check_every=check, stop=ADAPTIVE_STOP))
             P.psara_server_drain(srv)
             t_end = P.psara_server_clock(srv)
-            lat, imgs, failed = [], [], 0
+            lat, imgs, failed, iters = [], [], 0, []
             for (wl, _, _), t in zip(reqs, tickets):
                 img = np.empty((wl.n * wl.n, 4))
                 r = P.psara_server_poll(srv, t, img)
@@ -220,6 +227,7 @@ def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dic
                     imgs.append(None)
                     continue
                 lat.append(r["t_done"] - r["t_submit"])
+                iters.append(r["report"]["iterations"])
                 imgs.append(img)
         finally:
             P.psara_server_destroy(srv)
@@ -228,7 +236,8 @@ def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dic
         out[name] = {"solves_per_s": round(len(lat) / (t_end - arrivals[0]), 3),
                      "p50_latency_s": round(float(np.percentile(lat, 50)), 4) if lat else None,
                      "p99_latency_s": round(float(np.percentile(lat, 99)), 4) if lat else None,
-                     "failed": failed, "mean_snr_db": round(float(np.mean(snr)), 3) if snr else None}
+                     "failed": failed, "mean_snr_db": round(float(np.mean(snr)), 3) if snr else None,
+                     "mean_iterations": round(float(np.mean(iters)), 1) if iters else None}
     diffs = [float(np.max(np.abs(a - b))) for a, b in zip(images["batched"], images["fifo"])
              if a is not None and b is not None]
     out["max_abs_image_diff_batched_vs_fifo"] = max(diffs) if diffs else None
@@ -312,7 +321,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--profile-iters", type=int, default=50)
-    ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-solves", type=int, default=64, help="solves of the batched form (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=120,

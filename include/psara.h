@@ -123,6 +123,14 @@ psara_status psara_set_prior(psara_ctx* ctx, uint32_t basis_mask, int levels,
  * operator norm from psara_opnorm (which must have run). */
 psara_status psara_set_steps(psara_ctx* ctx, double tau, double rho1, double rho2, double rho3);
 
+/* Known direction-independent Mueller matrices (eq. RIME with D_m not depending on the sky
+ * position): row m of the visibilities becomes y_m = D_m (S^T L)^T evaluated at u_m, i.e. the
+ * fixed brightness mixing L is replaced per row by L D_m^T, in phi and in its adjoint.  D: M
+ * row-major 4 x 4 complex matrices, interleaved (re, im), in the caller's visibility order
+ * (copied); D_m acts on the brightness vector [I+Q, U+iV, U-iV, I-Q].  NULL restores L.  The
+ * iteration state is reset, and psara_opnorm and psara_set_steps must be called again. */
+psara_status psara_set_mueller(psara_ctx* ctx, const double* D);
+
 /* ||phi||^2 of the real-restricted map S -> Re phi^dagger phi S by an FP64 power
  * iteration on the device (seeded start), stopped when the Rayleigh quotient changes by
  * less than rtol (relative) or after max_iter iterations.  Stored in the context. */

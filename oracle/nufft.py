@@ -98,14 +98,24 @@ def direct_dft(x: np.ndarray, uv: np.ndarray, n: int) -> np.ndarray:
 
 
 class MeasurementOp:
-    """phi(S) = Phi(S) L and phi^dagger(B) = Phi^dagger(B L^H) on N x 4 Stokes matrices."""
+    """phi(S) = Phi(S) L and phi^dagger(B) = Phi^dagger(B L^H) on N x 4 Stokes matrices.
 
-    def __init__(self, nufft: NUFFT):
+    With known direction-independent Mueller matrices D_m (eq. RIME, its D with no dependence
+    on the sky position), row m of the visibilities is y_m = (Phi S)_m L D_m^T (the transposed
+    form of y = D (S^T L)^T), and the adjoint mixes row m of B by (L D_m^T)^H."""
+
+    def __init__(self, nufft: NUFFT, mueller: np.ndarray = None):
         self.nufft = nufft
+        self.mix = None if mueller is None else L_MIX @ np.transpose(np.asarray(mueller), (0, 2, 1))
 
     def phi(self, S: np.ndarray) -> np.ndarray:
-        return self.nufft.forward(np.asarray(S, dtype=np.complex128)) @ L_MIX
+        V = self.nufft.forward(np.asarray(S, dtype=np.complex128))
+        if self.mix is None:
+            return V @ L_MIX
+        return np.einsum("ms,msj->mj", V, self.mix)
 
     def phi_adj(self, B: np.ndarray) -> np.ndarray:
         """Complex N x 4 result; Algorithm 1 applies P_U = Re afterwards."""
-        return self.nufft.adjoint(np.asarray(B) @ L_MIX.conj().T)
+        if self.mix is None:
+            return self.nufft.adjoint(np.asarray(B) @ L_MIX.conj().T)
+        return self.nufft.adjoint(np.einsum("mj,msj->ms", np.asarray(B), self.mix.conj()))

@@ -37,10 +37,12 @@ class Built:
     gamma: float
 
 
-def build(wl, bases=BASES, levels=None, phi_norm=None, gamma=None, norm_rtol=1e-12, norm_max_iter=1000) -> Built:
+def build(wl, bases=BASES, levels=None, phi_norm=None, gamma=None, norm_rtol=1e-12, norm_max_iter=1000,
+          mueller=None) -> Built:
+    """mueller: None, or (M, 4, 4) known direction-independent Mueller matrices of the rows."""
     n = wl.n
     nu = NUFFT(wl.uv, n, wl.oversample, wl.taps)
-    mop = MeasurementOp(nu)
+    mop = MeasurementOp(nu, mueller)
     sara = SARA(n, wl.levels if levels is None else levels, bases)
     truth = wl.truth.reshape(n * n, 4)
     y0 = mop.phi(truth)

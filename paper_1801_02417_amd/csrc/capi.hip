@@ -261,6 +261,38 @@ psara_status psara_set_data(psara_ctx* c, const double* Y, double epsilon) {
   });
 }
 
+psara_status psara_set_mueller(psara_ctx* c, const double* D) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    std::vector<double> mix;
+    if (D) {
+      const int64_t M = c->geo.M;
+      mix.resize((size_t)M * 32);
+      // L: rows the Stokes maps I, Q, U, V, columns the brightness products (eq. RIME)
+      static const double Lre[4][4] = {{1, 0, 0, 1}, {1, 0, 0, -1}, {0, 1, 1, 0}, {0, 0, 0, 0}};
+      static const double Lim[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 1, -1, 0}};
+      for (int64_t p = 0; p < M; ++p) {
+        const double* d = D + 32 * c->geo.perm[p];          // D_m[j][k] at d[2 (4 j + k)]
+        for (int k = 0; k < 32; ++k) require(std::isfinite(d[k]), PSARA_ENAN, "non-finite Mueller matrix");
+        for (int s = 0; s < 4; ++s)
+          for (int j = 0; j < 4; ++j) {
+            double re = 0.0, im = 0.0;                       // (L D_m^T)[s][j] = sum_k L[s][k] D_m[j][k]
+            for (int k = 0; k < 4; ++k) {
+              const double dr = d[2 * (4 * j + k)], di = d[2 * (4 * j + k) + 1];
+              re += Lre[s][k] * dr - Lim[s][k] * di;
+              im += Lre[s][k] * di + Lim[s][k] * dr;
+            }
+            mix[(size_t)p * 32 + 2 * (4 * s + j)] = re;
+            mix[(size_t)p * 32 + 2 * (4 * s + j) + 1] = im;
+          }
+      }
+    }
+    with_engine(c, [&](auto& e) { e.set_mixing(D ? mix.data() : nullptr); });
+    c->norm_set = false;        // the operator changed: its norm and the step sizes are stale
+    c->steps_set = false;
+  });
+}
+
 psara_status psara_set_prior(psara_ctx* c, uint32_t basis_mask, int levels, const double* weights, double gamma) {
   return guard(c, [&] {
     require(c->op_set, PSARA_ESTATE, "operator not set");

@@ -88,6 +88,7 @@ struct ProbDesc {
   void* half;          // K*n cells: FFT intermediate [k2][r]
   const int* vis_k0;   // packed window starts (k1 << 16 | k2), sorted order
   const void* vis_frac;   // (f1, f2) per vis, type R
+  const void* mix;        // NULL (the fixed L) or per sorted vis the 4 x 4 complex L D_m^T, row-major
   const int* own_ptr;     // ntiles+1: sorted-vis range whose window starts in each tile
   const int* list_idx;    // per gridding tile: every vis whose window touches it
   const int* run_beg;     // gridding runs: first list entry and length

@@ -379,6 +379,15 @@ void Engine<R>::set_data(const double* Y_sorted, double eps) {
 }
 
 template <typename R>
+void Engine<R>::set_mixing(const double* mix_sorted) {
+  dfree((void*)h_.mix);
+  h_.mix = nullptr;
+  if (mix_sorted) h_.mix = upload_conv(mix_sorted, (size_t)geo_.M * 32);
+  desc_dirty_ = true;
+  zero_state();
+}
+
+template <typename R>
 void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, double gamma) {
   const int n = geo_.n, N = n * n;
   // release a previous prior

@@ -92,6 +92,9 @@ struct Engine {
   Engine& operator=(const Engine&) = delete;
 
   void set_data(const double* Y_sorted, double eps);
+  // per sorted visibility the 4 x 4 complex row mixing L D_m^T (32 doubles, row-major [s][j],
+  // interleaved re, im), or NULL for the fixed L; the iteration state is reset
+  void set_mixing(const double* mix_sorted);
   void set_prior(uint32_t mask, int levels, const double* weights, double gamma);
   void set_steps(double tau, double r1, double r2, double r3);
   void zero_state();

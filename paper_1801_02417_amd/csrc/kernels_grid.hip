@@ -79,12 +79,24 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
 #pragma unroll
       for (int s = 0; s < 4; ++s) { v[s].re += w2[j] * t[s].re; v[s].im += w2[j] * t[s].im; }
     }
-    // brightness products [I+Q, U+iV, U-iV, I-Q]
+    // brightness products [I+Q, U+iV, U-iV, I-Q], or with known Mueller matrices the row
+    // times L D_m^T
     Cell<R> phi;
-    phi.s[0] = cadd(v[0], v[1]);
-    phi.s[1] = cadd(v[2], cmuli(v[3]));
-    phi.s[2] = csub(v[2], cmuli(v[3]));
-    phi.s[3] = csub(v[0], v[1]);
+    if (P.mix) {
+      const cplx<R>* __restrict__ mx = (const cplx<R>*)P.mix + (size_t)m * 16;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cplx<R> a = cmul(v[0], mx[j]);
+#pragma unroll
+        for (int s = 1; s < 4; ++s) a = cadd(a, cmul(v[s], mx[4 * s + j]));
+        phi.s[j] = a;
+      }
+    } else {
+      phi.s[0] = cadd(v[0], v[1]);
+      phi.s[1] = cadd(v[2], cmuli(v[3]));
+      phi.s[2] = csub(v[2], cmuli(v[3]));
+      phi.s[3] = csub(v[0], v[1]);
+    }
     Cell<R>* __restrict__ out = (Cell<R>*)P.vis[out_slot];
     if (MODE == DG_FORWARD) {
       out[m] = phi;
@@ -226,7 +238,8 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
 
   // stage the chunk's entries: offsets and B L^H (I = B1 + B4, Q = B1 - B4, U = B2 + B3,
-  // V = i (B3 - B2)); sum the largest channel magnitude of each for the fixed point
+  // V = i (B3 - B2); with known Mueller matrices B (L D_m^T)^H instead); sum the largest
+  // channel magnitude of each for the fixed point
   const Cell<R>* __restrict__ bsrc = (const Cell<R>*)P.vis[src_slot];
   const V2<R>* __restrict__ frac = (const V2<R>*)P.vis_frac;
   KSum bound;
@@ -235,10 +248,24 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     sf[q] = frac[m];
     const Cell<R> b = bsrc[m];
     V4<R> u0, u1;
-    u0.x = (b.s[0].re + b.s[3].re); u0.y = (b.s[0].im + b.s[3].im);
-    u0.z = (b.s[0].re - b.s[3].re); u0.w = (b.s[0].im - b.s[3].im);
-    u1.x = (b.s[1].re + b.s[2].re); u1.y = (b.s[1].im + b.s[2].im);
-    u1.z = -(b.s[2].im - b.s[1].im); u1.w = (b.s[2].re - b.s[1].re);
+    if (P.mix) {                   // B (L D_m^T)^H
+      const cplx<R>* __restrict__ mx = (const cplx<R>*)P.mix + (size_t)m * 16;
+      cplx<R> u[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        cplx<R> a = cmul(b.s[0], cconj(mx[4 * s]));
+#pragma unroll
+        for (int j = 1; j < 4; ++j) a = cadd(a, cmul(b.s[j], cconj(mx[4 * s + j])));
+        u[s] = a;
+      }
+      u0.x = u[0].re; u0.y = u[0].im; u0.z = u[1].re; u0.w = u[1].im;
+      u1.x = u[2].re; u1.y = u[2].im; u1.z = u[3].re; u1.w = u[3].im;
+    } else {
+      u0.x = (b.s[0].re + b.s[3].re); u0.y = (b.s[0].im + b.s[3].im);
+      u0.z = (b.s[0].re - b.s[3].re); u0.w = (b.s[0].im - b.s[3].im);
+      u1.x = (b.s[1].re + b.s[2].re); u1.y = (b.s[1].im + b.s[2].im);
+      u1.z = -(b.s[2].im - b.s[1].im); u1.w = (b.s[2].re - b.s[1].re);
+    }
     su[2 * q] = u0;
     su[2 * q + 1] = u1;
     const R mx = fmax(fmax(fmax(fabs(u0.x), fabs(u0.y)), fmax(fabs(u0.z), fabs(u0.w))),

@@ -32,7 +32,7 @@ EXPORTS = (
     "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
     "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_profile_passes",
     "psara_batch_solve", "psara_batch_reweighted_solve", "psara_batch_profile_passes", "psara_data_gamma",
-    "psara_set_gamma", "psara_solve_adaptive", "psara_reweighted_solve_adaptive", "psara_batch_solve_adaptive",
+    "psara_set_gamma", "psara_set_mueller", "psara_solve_adaptive", "psara_reweighted_solve_adaptive", "psara_batch_solve_adaptive",
     "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
     "psara_server_clock", "psara_server_last_error", "psara_server_destroy",
 )
@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
         "psara_set_steps": (I, [P, C.c_double, C.c_double, C.c_double, C.c_double]),
         "psara_opnorm": (I, [P, I, C.c_double, D]),
         "psara_solve": (I, [P, I, I, I, C.POINTER(PsaraReport)]),
+        "psara_set_mueller": (I, [P, D]),
         "psara_solve_adaptive": (I, [P, I, I, I, C.POINTER(PsaraStop), C.POINTER(C.c_int), C.POINTER(PsaraReport)]),
         "psara_reweighted_solve_adaptive": (I, [P, I, I, I, I, C.POINTER(PsaraStop), C.c_double,
                                                 C.POINTER(C.c_int), C.POINTER(PsaraReport)]),
@@ -248,6 +249,18 @@ def psara_batch_solve_adaptive(ctxs, mode: int, max_iters: int, check_every: int
     _batch_check(ctxs, lib().psara_batch_solve_adaptive(_ctx_array(ctxs), len(ctxs), mode, max_iters, check_every,
                                                         C.byref(st), its, reps))
     return list(its), [r.as_dict() for r in reps]
+
+
+def psara_set_mueller(ctx, D) -> None:
+    """Known direction-independent Mueller matrices (M, 4, 4) complex of the rows, or None."""
+    if D is None:
+        _check(ctx, lib().psara_set_mueller(ctx, None))
+        return
+    d = np.ascontiguousarray(np.asarray(D, dtype=np.complex128))
+    if d.ndim != 3 or d.shape[1:] != (4, 4):
+        raise ValueError("D must be (M, 4, 4)")
+    flat = np.ascontiguousarray(d.view(np.float64).reshape(-1))
+    _check(ctx, lib().psara_set_mueller(ctx, _dptr(flat)))
 
 
 def psara_reweight(ctx, delta: float) -> None:
@@ -526,6 +539,9 @@ class Solver:
 
     def reweighted_solve(self, mode: int, iters_per_stage, delta_decay: float = 10.0):
         return psara_reweighted_solve(self.ctx, mode, iters_per_stage, delta_decay)
+
+    def set_mueller(self, D) -> None:
+        psara_set_mueller(self.ctx, D)
 
     def solve_adaptive(self, mode: int, max_iters: int, check_every: int, stop=PAPER_STOP):
         return psara_solve_adaptive(self.ctx, mode, max_iters, check_every, stop)

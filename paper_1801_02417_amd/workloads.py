@@ -170,6 +170,25 @@ def unit_noise(rng: np.random.Generator, M: int) -> np.ndarray:
     return (rng.standard_normal((M, 4)) + 1j * rng.standard_normal((M, 4))) / math.sqrt(2.0)
 
 
+def station_mueller(rng: np.random.Generator, M: int, stations: int = 8, gain_spread: float = 0.1,
+                    leakage: float = 0.05) -> np.ndarray:
+    """(M, 4, 4) complex direction-independent Mueller matrices D_m = J_a kron conj(J_b) of the
+    station pair (a, b) of each row (drawn uniformly, a != b), from per-station 2 x 2 Jones
+    matrices J = [[g1, d1], [d2, g2]] with complex gains g ~ 1 + gain_spread CN(0, 1) and
+    polarization leakage d ~ leakage CN(0, 1).  D_m acts on the brightness vector
+    [I+Q, U+iV, U-iV, I-Q] of a row, taken as the row-major 2 x 2 coherency matrix."""
+    def cn(size):
+        return (rng.standard_normal(size) + 1j * rng.standard_normal(size)) / math.sqrt(2.0)
+    J = np.empty((stations, 2, 2), dtype=np.complex128)
+    J[:, 0, 0] = 1.0 + gain_spread * cn(stations)
+    J[:, 1, 1] = 1.0 + gain_spread * cn(stations)
+    J[:, 0, 1] = leakage * cn(stations)
+    J[:, 1, 0] = leakage * cn(stations)
+    a = rng.integers(0, stations, size=M)
+    b = (a + rng.integers(1, stations, size=M)) % stations
+    return np.einsum("mij,mkl->mikjl", J[a], np.conj(J[b])).reshape(M, 4, 4)
+
+
 # ----------------------------------------------------------------------------
 # configurations
 # ----------------------------------------------------------------------------

@@ -149,3 +149,36 @@ def test_batch_profile_passes_times_and_advances_like_alone():
     finally:
         for s in members:
             s.close()
+
+
+def test_batch_member_with_mueller_matrices_equals_alone():
+    """A member whose phi carries per-row Mueller matrices and one with the plain L, batched:
+    each ends bit for bit where it ends alone."""
+    wls = mixed_workloads()[1:3]
+    Ds = [wk.station_mueller(np.random.default_rng(61), wls[0].M, leakage=0.2), None]
+
+    def make(wl, D):
+        b = built(wl)
+        s = P.Solver(wl.n, wl.uv, taps=wl.taps, precision=PREC["fp32"])
+        s.set_prior(wl.levels, b.gamma)
+        if D is not None:
+            s.set_mueller(D)
+        s.set_data(b.pb.Y, b.pb.eps)
+        s.opnorm(60, 1e-6)
+        s.set_steps(b.pb.tau, b.pb.rho1, b.pb.rho2, b.pb.rho3)
+        return s
+
+    alone = []
+    for wl, D in zip(wls, Ds):
+        s = make(wl, D)
+        s.reweighted_solve(P.PSARA_CONSTRAINED, STAGES)
+        alone.append(s.image())
+        s.close()
+    members = [make(wl, D) for wl, D in zip(wls, Ds)]
+    try:
+        P.batch_reweighted_solve(members, P.PSARA_CONSTRAINED, STAGES)
+        for s, a in zip(members, alone):
+            assert np.array_equal(s.image(), a)
+    finally:
+        for s in members:
+            s.close()

@@ -164,3 +164,32 @@ def test_fused_row_pass_chain(mode, prec, tol):
         say(f"   9 iterations: worst rel err {w:.2e}")
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
+def test_iterations_with_mueller_matrices(prec, tol):
+    """Algorithm 1 with known direction-independent Mueller matrices in phi (every row mixed by
+    its own L D_m^T): nine iterations from a random state (one captured chain plus one) against
+    the oracle run with the same matrices."""
+    n, M, T, L = 32, 600, 8, 3
+    wl = wk.tiny(n=n, M=M, taps=T, levels=L, seed=52)
+    D = wk.station_mueller(np.random.default_rng(53), M, leakage=0.2)
+    b = problem.build(wl, mueller=D)
+    rng = np.random.default_rng(54)
+    W = rng.uniform(0.2, 1.0, size=(b.sara.J, 4))
+    s = solver_for(wl, n, T, prec, levels=L, gamma=b.gamma, weights=W)
+    try:
+        s.set_mueller(D)
+        s.set_data(b.pb.Y, b.pb.eps)
+        s.opnorm(200, 1e-8)
+        s.set_steps(b.pb.tau, b.pb.rho1, b.pb.rho2, b.pb.rho3)
+        gW = b.gamma * W
+        st = _random_state(rng, n * n, b.sara.J, M, gW)
+        s.set_state(st.S, st.Z, st.A, st.B, st.C, st.D)
+        s.solve(P.PSARA_CONSTRAINED, 9, report=False)
+        scale = {}
+        ref = _oracle_steps(st.copy(), b.pb, gW, "polsara", 9, scale)
+        w = _compare(s.state(), ref, tol * 4, "mueller", scale if prec == "fp32" else None)
+        say(f"[mueller] {prec} 9 iterations: worst rel err {w:.2e}")
+    finally:
+        s.close()

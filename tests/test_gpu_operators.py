@@ -8,6 +8,7 @@ import pytest
 from oracle.nufft import NUFFT, MeasurementOp
 from oracle.sara import SARA, BASES
 from oracle.pd import phi_norm_sq
+from paper_1801_02417_amd import workloads as wk
 from tests.gpu_common import P, say, rel_err, random_uv, solver_for, mask_of
 
 pytestmark = pytest.mark.gpu
@@ -101,3 +102,35 @@ def test_power_iteration(prec):
         s.close()
     say(f"[opnorm] {prec} gpu {got:.12e} oracle {ref:.12e}")
     assert abs(got - ref) <= 1e-8 * ref      # FP64 on the device in both precisions
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_phi_with_mueller_matrices(prec):
+    """Known direction-independent Mueller matrices per row (psara_set_mueller): phi and its
+    adjoint against the oracle's operator with the same matrices, the adjoint identity on the
+    device, and psara_set_mueller(None) restoring the plain operator bit for bit."""
+    n, M, T = 32, 700, 8
+    rng = np.random.default_rng(71)
+    uv = random_uv(rng, M)
+    D = wk.station_mueller(rng, M, leakage=0.2)
+    mop = MeasurementOp(NUFFT(uv, n, 2, T), D)
+    S = rng.standard_normal((n * n, 4))
+    B = rng.standard_normal((M, 4)) + 1j * rng.standard_normal((M, 4))
+    s = solver_for(uv, n, T, prec)
+    try:
+        y_plain = s.phi(S)
+        s.set_mueller(D)
+        y = s.phi(S)
+        x = s.phi_adjoint(B)
+        lhs = np.real(np.vdot(y, B))
+        rhs = float(np.sum(S * x))
+        s.set_mueller(None)
+        assert np.array_equal(s.phi(S), y_plain)
+    finally:
+        s.close()
+    e1 = rel_err(y, mop.phi(S))
+    e2 = rel_err(x, np.real(mop.phi_adj(B)))
+    say(f"[mueller] {prec}: phi rel err {e1:.2e}, adjoint rel err {e2:.2e}, <phi S, B> - <S, phi^t B> "
+        f"{abs(lhs - rhs) / abs(lhs):.2e}")
+    assert e1 <= TOL[prec] and e2 <= TOL[prec]
+    assert abs(lhs - rhs) <= 10 * TOL[prec] * abs(lhs)

@@ -151,3 +151,34 @@ def test_workload_uv_inside_band_and_truth_in_cone():
         S = wl.truth
         assert np.all(np.linalg.norm(S[..., 1:], axis=-1) <= S[..., 0] + 1e-15)
         assert abs(np.mean(np.abs(wl.noise) ** 2) - 1.0) < 0.1
+
+
+def test_mueller_operator_pins():
+    """Measurement operator with known direction-independent Mueller matrices D_m (eq. RIME
+    with D constant over the sky): identity matrices give the plain operator; the column form
+    y_m = D_m (L^T v_m) of the equation, written out row by row, equals the operator; the
+    adjoint is exact; Mueller matrices built from unitary Jones matrices preserve norms."""
+    wl = wk.tiny(n=16, M=120, taps=6, levels=2, seed=21)
+    rng = np.random.default_rng(4)
+    nu = NUFFT(wl.uv, wl.n, 2, 6)
+    plain = MeasurementOp(nu)
+    eye = MeasurementOp(nu, np.broadcast_to(np.eye(4, dtype=np.complex128), (wl.M, 4, 4)))
+    S = rng.standard_normal((wl.n * wl.n, 4))
+    B = rng.standard_normal((wl.M, 4)) + 1j * rng.standard_normal((wl.M, 4))
+    assert np.allclose(eye.phi(S), plain.phi(S), rtol=0, atol=1e-13 * np.abs(plain.phi(S)).max())
+    assert np.allclose(eye.phi_adj(B), plain.phi_adj(B), rtol=0, atol=1e-13 * np.abs(plain.phi_adj(B)).max())
+    D = wk.station_mueller(rng, wl.M, leakage=0.2)
+    op = MeasurementOp(nu, D)
+    V = nu.forward(S.astype(np.complex128))
+    L = np.array([[1, 0, 0, 1], [1, 0, 0, -1], [0, 1, 1, 0], [0, 1j, -1j, 0]])
+    rows = np.stack([D[m] @ (L.T @ V[m]) for m in range(wl.M)])
+    assert np.allclose(op.phi(S), rows, rtol=0, atol=1e-12 * np.abs(rows).max())
+    lhs = np.real(np.vdot(op.phi(S), B))
+    rhs = float(np.sum(S * np.real(op.phi_adj(B))))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # unitary Jones matrices: D_m = J_a kron conj(J_b) is unitary, so each row keeps its norm
+    q = np.linalg.qr(rng.standard_normal((8, 2, 2)) + 1j * rng.standard_normal((8, 2, 2)))[0]
+    a, b = rng.integers(0, 8, wl.M), rng.integers(0, 8, wl.M)
+    Du = np.einsum("mij,mkl->mikjl", q[a], np.conj(q[b])).reshape(wl.M, 4, 4)
+    yu, y0 = MeasurementOp(nu, Du).phi(S), plain.phi(S)
+    assert np.allclose(np.linalg.norm(yu, axis=1), np.linalg.norm(y0, axis=1), rtol=1e-12, atol=0)

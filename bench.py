@@ -265,6 +265,36 @@ def large_form(P, wk, iters: int) -> dict:
             "passes_ms": {P.PASS_NAMES[i]: round(ms[i], 4) for i in range(10) if ms[i] > 0}}
 
 
+def mueller_form(P, wk, iters: int) -> dict:
+    """The 256 x 256, 2e5-visibility workload with known direction-independent Mueller matrices
+    on every row (8 stations, 10 % gain and 5 % leakage spread): every term active, iteration
+    rate of the captured graph and the de-gridding / gridding pass times."""
+    import torch
+
+    wl = wk.ring256()
+    D = wk.station_mueller(np.random.default_rng(2417 * 7), wl.M)
+    s = P.Solver(wl.n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED)
+    s.set_mueller(D)
+    Y, eps = make_data(P, wl, s)
+    s.set_data(Y, eps)
+    s.set_prior(wl.levels, 1.0)
+    s.opnorm(100, 1e-4)
+    P.psara_set_gamma(s.ctx, P.psara_data_gamma(s.ctx, 1e-3))
+    s.set_steps()
+    s.solve(P.PSARA_NNLS_INIT, 20, report=False)
+    P.psara_reweight(s.ctx, P.psara_coef_std(s.ctx))
+    s.solve(P.PSARA_CONSTRAINED, 16, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.solve(P.PSARA_CONSTRAINED, iters, report=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = s.profile_passes(P.PSARA_CONSTRAINED, 8)
+    s.close()
+    return {"n": wl.n, "M": wl.M, "iters": iters, "iters_per_s": round(iters / dt, 1),
+            "P6_ms": round(float(ms[5]), 4), "P7_ms": round(float(ms[6]), 4)}
+
+
 def profile_run(P, wk, form: str, iters: int) -> dict:
     """Only the timed passes of one form, for a profiler run: each pass launched on one stream with
     the two branches serialised (psara_profile_passes / psara_batch_profile_passes, constrained
@@ -427,6 +457,9 @@ def main() -> int:
         progress("large form: 512x512, 1e6 visibilities")
         line["large_form"] = large_form(P, wk, args.large_iters)
         progress(f"large form: {line['large_form']['iters_per_s']} iters/s")
+    if args.large_iters > 0:
+        progress("Mueller form: 256x256 with per-row Mueller matrices")
+        line["mueller_form"] = mueller_form(P, wk, args.large_iters)
     if args.batch_solves > 0:
         progress(f"batched form: {args.batch_solves} solves")
         line["batched_form"] = batched_form(P, wk, args.batch_solves, [100, 100, 100])

@@ -123,6 +123,22 @@ psara_status psara_set_prior(psara_ctx* ctx, uint32_t basis_mask, int levels,
  * operator norm from psara_opnorm (which must have run). */
 psara_status psara_set_steps(psara_ctx* ctx, double tau, double rho1, double rho2, double rho3);
 
+/* The TV-based priors of Sec. 4.3 instead of SARA: the context then runs Algorithm 3 for
+ * eq. Akiyama_2 (PSARA_CONSTRAINED: with the polarization constraint) or eq. Akiyama
+ * (PSARA_UNCONSTRAINED: I >= 0 only), whose data term is 1/2 ||Y L^{-1} - phi~(S)||^2 with
+ * phi~ = phi without the mixing L (the data are those of psara_set_data, in brightness order).
+ * l1 = 0: TV, g = sum_i tv_weight[i] ||grad S_i||_{2,1}; l1 = 1: l1 + TV, adding
+ * sum_i l1_weight[i] ||S_i||_1.  grad: forward differences along both image axes with a zero
+ * difference at the last row and column.  The dual A (psara_get_state) is then 2N x 4 (the d1
+ * block, the d2 block) or 3N x 4 for l1 + TV (the Dirac block first).  Weights finite and > 0.
+ * Step sizes (again
+ * through psara_set_steps, rho2 unused but > 0) must satisfy
+ * 1/tau - rho1 ||Psi||^2 - rho3 >= ||phi||^2 / 4 with ||Psi||^2 = 8 (TV) or 9 (l1 + TV)
+ * (||phi~||^2 = ||phi||^2 / 2 is the Lipschitz constant of the data term's gradient).  The
+ * reweighting, the initialisation mode, batches, the server and Mueller matrices are defined
+ * for the SARA prior only (PSARA_EINVAL).  The iterations start from the current state. */
+psara_status psara_set_prior_tv(psara_ctx* ctx, int l1, const double* tv_weight, const double* l1_weight);
+
 /* Known direction-independent Mueller matrices (eq. RIME with D_m not depending on the sky
  * position): row m of the visibilities becomes y_m = D_m (S^T L)^T evaluated at u_m, i.e. the
  * fixed brightness mixing L is replaced per row by L D_m^T, in phi and in its adjoint.  D: M

@@ -61,7 +61,20 @@ int primal_mode(psara_mode m) {
   throw Error(PSARA_EINVAL, "unknown mode");
 }
 
+// Engine mode of a solve: the TV priors run Algorithm 3 (no initialisation stage)
+int solve_mode(const psara_ctx* c, psara_mode m) {
+  const int pm = primal_mode(m);
+  if (!c->tv_kind) return pm;
+  require(pm != psara::PM_INIT, PSARA_EINVAL, "the TV priors have no initialisation stage");
+  return pm == psara::PM_CONSTRAINED ? psara::PM_TV_CONSTRAINED : psara::PM_TV_UNCONSTRAINED;
+}
+
+void require_sara(const psara_ctx* c) {
+  require(!c->tv_kind, PSARA_EINVAL, "not defined for the TV priors (Algorithm 3)");
+}
+
 size_t coef_count(const psara_ctx* c) {
+  if (c->tv_kind) return (size_t)(c->tv_kind == 2 ? 3 : 2) * c->geo.n * c->geo.n;
   int nb = 0;
   for (int b = 0; b <= 8; ++b) nb += (c->mask >> b) & 1u;
   return (size_t)nb * c->geo.n * c->geo.n;
@@ -116,6 +129,7 @@ psara_status batch_guard(psara_ctx* const* ctxs, int count, F&& f) {
 }
 
 void check_batch(psara_ctx* const* ctxs, int count, int mode) {
+  for (int i = 0; i < count; ++i) require_sara(ctxs[i]);
   for (int i = 0; i < count; ++i) {
     psara_ctx* c = ctxs[i];
     require(c->op_set && c->data_set, PSARA_ESTATE, "batch member without operator or data");
@@ -264,6 +278,7 @@ psara_status psara_set_data(psara_ctx* c, const double* Y, double epsilon) {
 psara_status psara_set_mueller(psara_ctx* c, const double* D) {
   return guard(c, [&] {
     require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(!(D && c->tv_kind), PSARA_EINVAL, "the TV priors take the data per Stokes map: no Mueller matrices");
     std::vector<double> mix;
     if (D) {
       const int64_t M = c->geo.M;
@@ -288,6 +303,7 @@ psara_status psara_set_mueller(psara_ctx* c, const double* D) {
       }
     }
     with_engine(c, [&](auto& e) { e.set_mixing(D ? mix.data() : nullptr); });
+    c->mueller = D != nullptr;
     c->norm_set = false;        // the operator changed: its norm and the step sizes are stale
     c->steps_set = false;
   });
@@ -302,6 +318,7 @@ psara_status psara_set_prior(psara_ctx* c, uint32_t basis_mask, int levels, cons
             PSARA_EINVAL, "levels must satisfy n divisible by 2^levels");
     require(std::isfinite(gamma) && gamma > 0.0, PSARA_EINVAL, "gamma must be > 0");
     c->mask = basis_mask;
+    c->tv_kind = 0;
     const size_t J4 = coef_count(c) * 4;
     if (weights)
       for (size_t i = 0; i < J4; ++i) {
@@ -315,6 +332,25 @@ psara_status psara_set_prior(psara_ctx* c, uint32_t basis_mask, int levels, cons
   });
 }
 
+psara_status psara_set_prior_tv(psara_ctx* c, int l1, const double* tv_weight, const double* l1_weight) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(!c->mueller, PSARA_EINVAL, "the TV priors take the data per Stokes map: no Mueller matrices");
+    require(tv_weight != nullptr && (!l1 || l1_weight != nullptr), PSARA_EINVAL, "weights are NULL");
+    for (int i = 0; i < 4; ++i) {
+      require(std::isfinite(tv_weight[i]) && tv_weight[i] > 0.0, PSARA_EINVAL, "TV weights must be > 0");
+      if (l1) require(std::isfinite(l1_weight[i]) && l1_weight[i] > 0.0, PSARA_EINVAL, "l1 weights must be > 0");
+    }
+    with_engine(c, [&](auto& e) { e.set_prior_tv(l1 ? 2 : 1, tv_weight, l1 ? l1_weight : nullptr); });
+    c->tv_kind = l1 ? 2 : 1;
+    c->mask = 0;
+    c->levels = 0;
+    c->gamma = 1.0;
+    c->prior_set = true;
+    c->steps_set = false;      // Algorithm 3 has its own step-size condition
+  });
+}
+
 psara_status psara_set_steps(psara_ctx* c, double tau, double rho1, double rho2, double rho3) {
   return guard(c, [&] {
     require(c->op_set, PSARA_ESTATE, "operator not set");
@@ -322,8 +358,17 @@ psara_status psara_set_steps(psara_ctx* c, double tau, double rho1, double rho2,
     require(tau > 0 && rho1 > 0 && rho2 > 0 && rho3 > 0 && std::isfinite(tau) && std::isfinite(rho1) &&
                 std::isfinite(rho2) && std::isfinite(rho3),
             PSARA_EINVAL, "step sizes must be finite and > 0");
-    const double cond = 1.0 / tau - rho1 * 1.0 - rho2 * c->phi_norm_sq - rho3;
-    require(cond >= -1e-12 / tau, PSARA_EINVAL, "step sizes violate 1/tau - rho1 ||Psi||^2 - rho2 ||phi||^2 - rho3 >= 0");
+    if (c->tv_kind) {
+      // the condition with the smooth data term of Algorithm 3: its gradient is
+      // ||phi~||^2 = ||phi||^2 / 2 Lipschitz (L L^H = 2 I), ||Psi||^2 <= 8 (TV) or 9 (l1 + TV)
+      const double psi2 = c->tv_kind == 2 ? 9.0 : 8.0;
+      const double cond = 1.0 / tau - rho1 * psi2 - rho3 - 0.25 * c->phi_norm_sq;
+      require(cond >= -1e-12 / tau, PSARA_EINVAL,
+              "step sizes violate 1/tau - rho1 ||Psi||^2 - rho3 >= ||phi~||^2 / 2 (Algorithm 3)");
+    } else {
+      const double cond = 1.0 / tau - rho1 * 1.0 - rho2 * c->phi_norm_sq - rho3;
+      require(cond >= -1e-12 / tau, PSARA_EINVAL, "step sizes violate 1/tau - rho1 ||Psi||^2 - rho2 ||phi||^2 - rho3 >= 0");
+    }
     with_engine(c, [&](auto& e) { e.set_steps(tau, rho1, rho2, rho3); });
     c->tau = tau; c->rho1 = rho1; c->rho2 = rho2; c->rho3 = rho3;
     c->steps_set = true;
@@ -351,7 +396,7 @@ psara_status psara_opnorm(psara_ctx* c, int max_iter, double rtol, double* phi_n
 }
 
 psara_status psara_solve(psara_ctx* c, psara_mode mode, int iters, int check_every, psara_report* out) {
-  return guard(c, [&] { run_stage(c, primal_mode(mode), iters, check_every, out); });
+  return guard(c, [&] { run_stage(c, solve_mode(c, mode), iters, check_every, out); });
 }
 
 namespace {
@@ -380,7 +425,7 @@ psara_status psara_solve_adaptive(psara_ctx* c, psara_mode mode, int max_iters, 
                                   const psara_stop* stop, int* iters_run, psara_report* out) {
   return guard(c, [&] {
     check_stop(stop, max_iters, check_every);
-    const int it = run_stage_adaptive(c, primal_mode(mode), max_iters, check_every, stop);
+    const int it = run_stage_adaptive(c, solve_mode(c, mode), max_iters, check_every, stop);
     if (iters_run) *iters_run = it;
     if (out) {
       with_engine(c, [&](auto& e) { e.report(out); });
@@ -393,6 +438,7 @@ psara_status psara_reweighted_solve_adaptive(psara_ctx* c, psara_mode mode, int 
                                              int check_every, const psara_stop* stop, double delta_decay,
                                              int* iters_run, psara_report* out) {
   return guard(c, [&] {
+    require_sara(c);
     check_stop(stop, max_iters_per_stage, check_every);
     require(cycles >= 0, PSARA_EINVAL, "cycles must be >= 0");
     require(delta_decay > 1.0 && std::isfinite(delta_decay), PSARA_EINVAL, "delta_decay must be > 1");
@@ -420,6 +466,7 @@ psara_status psara_reweighted_solve_adaptive(psara_ctx* c, psara_mode mode, int 
 
 psara_status psara_reweight(psara_ctx* c, double delta) {
   return guard(c, [&] {
+    require_sara(c);
     require(c->prior_set, PSARA_ESTATE, "prior not set");
     require(std::isfinite(delta) && delta > 0.0, PSARA_EINVAL, "delta must be > 0");
     with_engine(c, [&](auto& e) { e.reweight(delta); });
@@ -428,6 +475,7 @@ psara_status psara_reweight(psara_ctx* c, double delta) {
 
 psara_status psara_coef_std(psara_ctx* c, double* out) {
   return guard(c, [&] {
+    require_sara(c);
     require(c->prior_set, PSARA_ESTATE, "prior not set");
     require(out != nullptr, PSARA_EINVAL, "out is NULL");
     with_engine(c, [&](auto& e) { *out = e.coef_std(); });
@@ -437,6 +485,7 @@ psara_status psara_coef_std(psara_ctx* c, double* out) {
 psara_status psara_reweighted_solve(psara_ctx* c, psara_mode mode, int cycles, const int* iters_per_stage,
                                     double delta_decay, psara_report* out) {
   return guard(c, [&] {
+    require_sara(c);
     require(cycles >= 0 && iters_per_stage != nullptr, PSARA_EINVAL, "bad stage list");
     require(delta_decay > 1.0 && std::isfinite(delta_decay), PSARA_EINVAL, "delta_decay must be > 1");
     require(c->prior_set, PSARA_ESTATE, "prior not set");
@@ -460,6 +509,7 @@ psara_status psara_reweighted_solve(psara_ctx* c, psara_mode mode, int cycles, c
 
 psara_status psara_data_gamma(psara_ctx* c, double factor, double* gamma) {
   return guard(c, [&] {
+    require_sara(c);
     require(c->op_set && c->data_set && c->prior_set, PSARA_ESTATE, "operator, data and prior must be set");
     require(c->norm_set, PSARA_ESTATE, "run psara_opnorm first");
     require(gamma != nullptr && std::isfinite(factor) && factor > 0.0, PSARA_EINVAL, "bad arguments");
@@ -471,6 +521,7 @@ psara_status psara_data_gamma(psara_ctx* c, double factor, double* gamma) {
 
 psara_status psara_set_gamma(psara_ctx* c, double gamma) {
   return guard(c, [&] {
+    require_sara(c);
     require(c->prior_set, PSARA_ESTATE, "prior not set");
     require(std::isfinite(gamma) && gamma > 0.0, PSARA_EINVAL, "gamma must be > 0");
     with_engine(c, [&](auto& e) { e.set_gamma(gamma); });
@@ -664,6 +715,7 @@ int psara_layout(const psara_ctx* c, int64_t* perm) {
 
 psara_status psara_profile_passes(psara_ctx* c, psara_mode mode, int iters, double* ms_per_pass) {
   return guard(c, [&] {
+    require_sara(c);
     const int pm = primal_mode(mode);
     require(c->op_set && c->data_set && c->steps_set, PSARA_ESTATE, "solve set-up incomplete");
     require(pm == psara::PM_INIT || c->prior_set, PSARA_ESTATE, "prior not set");

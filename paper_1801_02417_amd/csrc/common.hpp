@@ -89,6 +89,9 @@ struct ProbDesc {
   const int* vis_k0;   // packed window starts (k1 << 16 | k2), sorted order
   const void* vis_frac;   // (f1, f2) per vis, type R
   const void* mix;        // NULL (the fixed L) or per sorted vis the 4 x 4 complex L D_m^T, row-major
+  int tv_kind;            // 0: the SARA prior; 1: TV; 2: l1 + TV (Algorithm 3; A = [Dirac, d1, d2] blocks)
+  double tvw[4];          // TV weights per Stokes map
+  double l1w[4];          // l1 weights per Stokes map (l1 + TV)
   const int* own_ptr;     // ntiles+1: sorted-vis range whose window starts in each tile
   const int* list_idx;    // per gridding tile: every vis whose window touches it
   const int* run_beg;     // gridding runs: first list entry and length

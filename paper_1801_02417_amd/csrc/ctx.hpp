@@ -24,6 +24,8 @@ struct psara_ctx {
   double tau = 0.0, rho1 = 0.0, rho2 = 0.0, rho3 = 0.0;
   uint32_t mask = 0;
   int levels = 0;
+  int tv_kind = 0;            // 0: SARA prior; 1: TV, 2: l1 + TV (Algorithm 3)
+  bool mueller = false;       // per-row Mueller matrices in phi
   int64_t iterations = 0;
 };
 

@@ -345,6 +345,7 @@ void Engine<R>::upload_items() {
   pl_.max_ts = geo_.ts; pl_.taps = geo_.T; pl_.max_levels = h_.levels;
   pl_.max_n = h_.n;
   pl_.sparse = h_.coef[COEF_A] != nullptr && h_.nwav > 0;
+  pl_.tv = h_.tv_kind != 0;
 }
 
 template <typename R>
@@ -388,8 +389,37 @@ void Engine<R>::set_mixing(const double* mix_sorted) {
 }
 
 template <typename R>
+void Engine<R>::set_prior_tv(int kind, const double* tv_weight, const double* l1_weight) {
+  const int n = geo_.n, N = n * n;
+  set_prior(1u, 1, nullptr, 1.0);      // releases a previous prior; replaced below
+  for (int c = 0; c < NUM_COEF; ++c) { dfree(h_.coef[c]); h_.coef[c] = nullptr; }
+  items_.dirac.clear();
+  for (int l = 0; l <= kMaxLevels; ++l) {
+    items_.ana[l].clear(); items_.syn[l].clear(); items_.ana_d[l].clear(); items_.syn_d[l].clear();
+  }
+  items_.synfinal.clear(); items_.coarse.clear();
+  h_.tv_kind = kind;
+  for (int i = 0; i < 4; ++i) {
+    h_.tvw[i] = tv_weight[i];
+    h_.l1w[i] = (kind == 2 && l1_weight) ? l1_weight[i] : 0.0;
+  }
+  h_.has_dirac = 0; h_.nwav = 0; h_.nbases = 1; h_.levels = 0; h_.norm = 1.0; h_.gamma = 1.0;
+  coef_elems_ = (size_t)(kind == 2 ? 3 : 2) * N;     // dual blocks [d1, d2] or [Dirac, d1, d2]
+  for (int c = 0; c < NUM_COEF; ++c) h_.coef[c] = dalloc<V4<R>>(coef_elems_);
+  for (int c = 0; c < NUM_COEF; ++c) zero(h_.coef[c], coef_elems_ * sizeof(V4<R>));
+  ana_parts_ = 0;
+  gen_parts_ = (N + 255) / 256;
+  realloc_partials();
+  upload_items();
+  invalidate_graphs();
+  zero(h_.img[IMG_PSIA], (size_t)N * sizeof(V4<R>));
+  hip_check(hipStreamSynchronize(s0_), "set_prior_tv");
+}
+
+template <typename R>
 void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, double gamma) {
   const int n = geo_.n, N = n * n;
+  h_.tv_kind = 0;
   // release a previous prior
   for (int c = 0; c < NUM_COEF; ++c) { dfree(h_.coef[c]); h_.coef[c] = nullptr; }
   dfree(h_.ll); h_.ll = nullptr;
@@ -495,17 +525,31 @@ void launch_iterations(const PassLists& L, int mode, int count, hipStream_t s0, 
   if (count <= 0) return;
   // P1 fused into P4: the row-FFT workgroups run the primal step of their rows
   launch_primal_fft<R>(mode, lists_la(L, L.rows, s0), L.rcells);
-  const bool sparse = (mode != PM_INIT) && L.sparse;
+  // Algorithm 3 (TV modes): the sparsity branch is the TV dual step and its synthesis, and
+  // P5..P8 evaluate the data term's gradient at S_new (the row FFT after the primal step
+  // transforms S_new): residual Phi S - Y L^{-1} per Stokes map, gridded without mixing
+  const bool tvm = pm_tv(mode);
+  const bool sparse = tvm || ((mode != PM_INIT) && L.sparse);
   for (int k = 0; k < count; ++k) {
     if (sparse) {
       hip_check(hipEventRecord(fork, s0), "event record");
       hip_check(hipStreamWaitEvent(s1, fork, 0), "stream wait");
-      launch_sara_dual<R>(L, s1);
+      if (tvm) {
+        launch_tv_dual<R>(lists_la(L, L.img, s1));
+        launch_tv_synth<R>(lists_la(L, L.img, s1));
+      } else {
+        launch_sara_dual<R>(L, s1);
+      }
       hip_check(hipEventRecord(join, s1), "event record");
     }
     launch_fft<R>(1, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P5
-    launch_degrid<R>(DG_DUAL, lists_la(L, L.p6, s0), L.max_ts, L.taps, VIS_BV, VIS_BV);  // P6
-    launch_grid<R>(GR_DUAL, lists_la(L, L.p7, s0), L.taps, VIS_BV, 0);               // P7
+    if (tvm) {
+      launch_degrid<R>(DG_STOKES, lists_la(L, L.p6, s0), L.max_ts, L.taps, VIS_Y, VIS_R);
+      launch_grid<R>(GR_STOKES, lists_la(L, L.p7, s0), L.taps, VIS_R, 0);
+    } else {
+      launch_degrid<R>(DG_DUAL, lists_la(L, L.p6, s0), L.max_ts, L.taps, VIS_BV, VIS_BV);  // P6
+      launch_grid<R>(GR_DUAL, lists_la(L, L.p7, s0), L.taps, VIS_BV, 0);               // P7
+    }
     launch_fft<R>(2, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P8
     if (sparse) hip_check(hipStreamWaitEvent(s0, join, 0), "stream wait");
     if (k + 1 < count) launch_fused_rows<R>(mode, lists_la(L, L.rows, s0), L.rcells);  // P9 + next P1, P4
@@ -587,6 +631,23 @@ void Engine<R>::adjoint(int src_vis, int use_cfac, int dst_img) {
   p7(GR_PLAIN, src_vis, use_cfac); p8(); p9(dst_img);
 }
 
+// Algorithm 3 keeps, between iterations, the data term's gradient Re phi~^dagger (phi~ S - Y~)
+// where Algorithm 1 keeps Re phi^dagger B, and Psi A; both are recomputed from the state before
+// a run, since the state (S, A) may have been set or reset since the last one.
+template <typename R>
+void Engine<R>::prime(int mode) {
+  if (!pm_tv(mode)) return;
+  sync_desc();
+  launch_fft<R>(0, la(d_rows_), rcells_, IMG_S, 0);
+  p5();
+  p6(DG_STOKES, VIS_Y, VIS_R);
+  p7(GR_STOKES, VIS_R, 0);
+  p8();
+  p9(IMG_PHIB);
+  launch_tv_synth<R>(la(d_img_));
+  hip_check(hipGetLastError(), "prime");
+}
+
 template <typename R>
 void Engine<R>::launch_iterations(int mode, int count) {
   ::psara::launch_iterations<R>(pl_, mode, count, s0_, s1_, ev_fork_, ev_join_);
@@ -634,6 +695,7 @@ template <typename R>
 int Engine<R>::run_adaptive(int mode, int max_iters, int check_every, const double* stop) {
   adaptive_buffers();
   stop_begin(stop);
+  if (max_iters > 0) prime(mode);
   auto graph = [&](int count) -> hipGraphExec_t {
     const int key = 1000000 + mode * 1000 + count;
     auto it = graphs_.find(key);
@@ -664,6 +726,7 @@ template <typename R>
 void Engine<R>::run(int mode, int iters) {
   sync_desc();
   if (iters <= 0) return;
+  prime(mode);
   constexpr int kChunk = 8;
   auto get_graph = [&](int count) -> hipGraphExec_t {
     const int key = mode * 1000 + count;
@@ -694,6 +757,7 @@ void Engine<R>::run(int mode, int iters) {
 template <typename R>
 void Engine<R>::run_eager(int mode, int iters) {
   sync_desc();
+  if (iters > 0) prime(mode);
   launch_iterations(mode, iters);
   hip_check(hipGetLastError(), "iteration launch");
 }
@@ -730,7 +794,10 @@ void Engine<R>::report(psara_report* r) {
   launch_relvar<R>(la(d_img_));
   for (int q = 0; q < 4; ++q) { finalize(q, nimg, SC_RV0 + q); finalize(4 + q, nimg, SC_SN0 + q); }
   const bool prior = h_.coef[COEF_A] != nullptr;
-  if (prior) {
+  if (h_.tv_kind) {
+    launch_tv_objective<R>(la(d_img_));
+    finalize(0, nimg, SC_OBJ);
+  } else if (prior) {
     if (h_.has_dirac) launch_dirac<R>(AM_OBJECTIVE, la(d_dirac_), IMG_S, 0);
     for (int l = 1; l <= h_.levels; ++l) launch_analysis<R>(AM_OBJECTIVE, l, la(d_ana_[l]), IMG_S, 0);
     finalize(0, ana_parts_, SC_OBJ);
@@ -747,7 +814,7 @@ void Engine<R>::report(psara_report* r) {
   }
   r->zeta = sc[SC_ZETA];
   r->n_p = 100.0 * sc[SC_NPCOUNT] / N;
-  r->objective = prior ? sc[SC_OBJ] / h_.gamma : 0.0;
+  r->objective = h_.tv_kind ? sc[SC_OBJ] : (prior ? sc[SC_OBJ] / h_.gamma : 0.0);
   r->vnorm = std::sqrt(std::max(sc[SC_VNORM2], 0.0));
 }
 

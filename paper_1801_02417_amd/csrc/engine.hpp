@@ -72,6 +72,7 @@ struct PassLists {
   int max_ts = 16, taps = 8, max_levels = 0;
   int max_n = 0;                   // largest image side among the problems
   bool sparse = false;             // every problem has a wavelet prior (P2/P3 run)
+  bool tv = false;                 // the problems carry a TV prior (Algorithm 3)
 };
 
 // `count` Algorithm-1 iterations of every problem in L: P1+P4, then per iteration P2/P3 on s1
@@ -96,6 +97,9 @@ struct Engine {
   // interleaved re, im), or NULL for the fixed L; the iteration state is reset
   void set_mixing(const double* mix_sorted);
   void set_prior(uint32_t mask, int levels, const double* weights, double gamma);
+  // TV (kind 1) or l1 + TV (kind 2) prior of Algorithm 3 with per-Stokes weights
+  void set_prior_tv(int kind, const double* tv_weight, const double* l1_weight);
+  bool is_tv() const { return h_.tv_kind != 0; }
   void set_steps(double tau, double r1, double r2, double r3);
   void zero_state();
   void run(int mode, int iters);          // graph replay
@@ -154,6 +158,7 @@ struct Engine {
   void sync_desc();
   void invalidate_graphs();
   void launch_iterations(int mode, int count);
+  void prime(int mode);       // Algorithm 3: the data gradient and Psi A of the current state
   void adaptive_buffers();
   void forward(int src_img, int mode, int out_vis);
   void adjoint(int src_vis, int use_cfac, int dst_img);

@@ -286,49 +286,35 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   }
 }
 
-template <typename R>
-void launch_primal_fft(int mode, const LaunchArgs& a, int cells) {
-  if (a.nitems <= 0) return;
+// the primal-step modes of the row passes (PASS 0 and 4), for one CELLS
+template <typename R, int CELLS, int PASS>
+void launch_row_primal_t(int mode, const LaunchArgs& a) {
   const dim3 grid(a.nitems);
-#define PSARA_PFFT(C, PM) \
-  hipLaunchKernelGGL((fft_pass_kernel<R, C, 0, PM>), grid, dim3(C / 2), 0, a.stream, a.descs, a.items, 0, 0)
-  if (cells == 512) {
-    if (mode == PM_CONSTRAINED) PSARA_PFFT(512, PM_CONSTRAINED);
-    else if (mode == PM_INIT) PSARA_PFFT(512, PM_INIT);
-    else PSARA_PFFT(512, PM_UNCONSTRAINED);
-  } else if (cells == 2048) {
-    if (mode == PM_CONSTRAINED) PSARA_PFFT(2048, PM_CONSTRAINED);
-    else if (mode == PM_INIT) PSARA_PFFT(2048, PM_INIT);
-    else PSARA_PFFT(2048, PM_UNCONSTRAINED);
-  } else {
-    if (mode == PM_CONSTRAINED) PSARA_PFFT(1024, PM_CONSTRAINED);
-    else if (mode == PM_INIT) PSARA_PFFT(1024, PM_INIT);
-    else PSARA_PFFT(1024, PM_UNCONSTRAINED);
+#define PSARA_RP(PM) \
+  hipLaunchKernelGGL((fft_pass_kernel<R, CELLS, PASS, PM>), grid, dim3(CELLS / 2), 0, a.stream, a.descs, a.items, 0, 0)
+  switch (mode) {
+    case PM_CONSTRAINED: PSARA_RP(PM_CONSTRAINED); break;
+    case PM_INIT: PSARA_RP(PM_INIT); break;
+    case PM_UNCONSTRAINED: PSARA_RP(PM_UNCONSTRAINED); break;
+    case PM_TV_CONSTRAINED: PSARA_RP(PM_TV_CONSTRAINED); break;
+    default: PSARA_RP(PM_TV_UNCONSTRAINED); break;
   }
-#undef PSARA_PFFT
+#undef PSARA_RP
+}
+
+template <typename R, int PASS>
+void launch_row_primal(int mode, const LaunchArgs& a, int cells) {
+  if (a.nitems <= 0) return;
+  if (cells == 512) launch_row_primal_t<R, 512, PASS>(mode, a);
+  else if (cells == 2048) launch_row_primal_t<R, 2048, PASS>(mode, a);
+  else launch_row_primal_t<R, 1024, PASS>(mode, a);
 }
 
 template <typename R>
-void launch_fused_rows(int mode, const LaunchArgs& a, int cells) {
-  if (a.nitems <= 0) return;
-  const dim3 grid(a.nitems);
-#define PSARA_RFFT(C, PM) \
-  hipLaunchKernelGGL((fft_pass_kernel<R, C, 4, PM>), grid, dim3(C / 2), 0, a.stream, a.descs, a.items, 0, 0)
-  if (cells == 512) {
-    if (mode == PM_CONSTRAINED) PSARA_RFFT(512, PM_CONSTRAINED);
-    else if (mode == PM_INIT) PSARA_RFFT(512, PM_INIT);
-    else PSARA_RFFT(512, PM_UNCONSTRAINED);
-  } else if (cells == 2048) {
-    if (mode == PM_CONSTRAINED) PSARA_RFFT(2048, PM_CONSTRAINED);
-    else if (mode == PM_INIT) PSARA_RFFT(2048, PM_INIT);
-    else PSARA_RFFT(2048, PM_UNCONSTRAINED);
-  } else {
-    if (mode == PM_CONSTRAINED) PSARA_RFFT(1024, PM_CONSTRAINED);
-    else if (mode == PM_INIT) PSARA_RFFT(1024, PM_INIT);
-    else PSARA_RFFT(1024, PM_UNCONSTRAINED);
-  }
-#undef PSARA_RFFT
-}
+void launch_primal_fft(int mode, const LaunchArgs& a, int cells) { launch_row_primal<R, 0>(mode, a, cells); }
+
+template <typename R>
+void launch_fused_rows(int mode, const LaunchArgs& a, int cells) { launch_row_primal<R, 4>(mode, a, cells); }
 
 template <typename R>
 void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot) {

@@ -98,7 +98,23 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
       phi.s[3] = csub(v[0], v[1]);
     }
     Cell<R>* __restrict__ out = (Cell<R>*)P.vis[out_slot];
-    if (MODE == DG_FORWARD) {
+    if (MODE == DG_STOKES) {
+      // Phi S - Y L^{-1}: I = (Y1 + Y4) / 2, Q = (Y1 - Y4) / 2, U = (Y2 + Y3) / 2, V = -i (Y2 - Y3) / 2
+      const Cell<R> y = ((const Cell<R>*)P.vis[VIS_Y])[m];
+      const R h = R(0.5);
+      Cell<R> o;
+      o.s[0] = csub(v[0], cscale(cadd(y.s[0], y.s[3]), h));
+      o.s[1] = csub(v[1], cscale(csub(y.s[0], y.s[3]), h));
+      o.s[2] = csub(v[2], cscale(cadd(y.s[1], y.s[2]), h));
+      const cplx<R> dv = csub(y.s[1], y.s[2]);
+      o.s[3] = csub(v[3], cmk(h * dv.im, -h * dv.re));
+      out[m] = o;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        acc.add((double)o.s[s].re * (double)o.s[s].re);
+        acc.add((double)o.s[s].im * (double)o.s[s].im);
+      }
+    } else if (MODE == DG_FORWARD) {
       out[m] = phi;
     } else {
       const Cell<R> y = ((const Cell<R>*)P.vis[VIS_Y])[m];
@@ -138,6 +154,8 @@ void launch_degrid_t(int mode, const LaunchArgs& a, size_t shm, int src_slot, in
   const dim3 grid(a.nitems), block(256);
   if (mode == DG_DUAL) {
     hipLaunchKernelGGL((degrid_kernel<R, DG_DUAL, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
+  } else if (mode == DG_STOKES) {
+    hipLaunchKernelGGL((degrid_kernel<R, DG_STOKES, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
   } else if (mode == DG_FORWARD) {
     hipLaunchKernelGGL((degrid_kernel<R, DG_FORWARD, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, out_slot);
   } else {
@@ -248,7 +266,10 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     sf[q] = frac[m];
     const Cell<R> b = bsrc[m];
     V4<R> u0, u1;
-    if (P.mix) {                   // B (L D_m^T)^H
+    if (MODE == GR_STOKES) {       // rows already per Stokes map
+      u0.x = b.s[0].re; u0.y = b.s[0].im; u0.z = b.s[1].re; u0.w = b.s[1].im;
+      u1.x = b.s[2].re; u1.y = b.s[2].im; u1.z = b.s[3].re; u1.w = b.s[3].im;
+    } else if (P.mix) {            // B (L D_m^T)^H
       const cplx<R>* __restrict__ mx = (const cplx<R>*)P.mix + (size_t)m * 16;
       cplx<R> u[4];
 #pragma unroll
@@ -343,6 +364,8 @@ void launch_grid_t(int mode, const LaunchArgs& a, int src_slot, int use_cfac) {
   const dim3 grid(a.nitems), block(kGridThreads);
   if (mode == GR_DUAL) {
     hipLaunchKernelGGL((grid_kernel<R, GR_DUAL, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
+  } else if (mode == GR_STOKES) {
+    hipLaunchKernelGGL((grid_kernel<R, GR_STOKES, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
   } else {
     hipLaunchKernelGGL((grid_kernel<R, GR_PLAIN, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
   }
@@ -365,6 +388,7 @@ void set_degrid_limits_t(int max_ts) {
   hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_DUAL, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
   hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_FORWARD, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
   hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_RESIDUAL, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
+  hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_STOKES, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");
 }
 
 // Set once per device for every tap count, at the largest de-grid tile (hipFuncSetAttribute is

@@ -23,9 +23,13 @@ template <typename R>
 void launch_primal(int mode, const LaunchArgs& a) {
   if (a.nitems <= 0) return;
   const dim3 g(a.nitems), b(256);
-  if (mode == PM_CONSTRAINED) hipLaunchKernelGGL((primal_kernel<R, PM_CONSTRAINED>), g, b, 0, a.stream, a.descs, a.items);
-  else if (mode == PM_INIT) hipLaunchKernelGGL((primal_kernel<R, PM_INIT>), g, b, 0, a.stream, a.descs, a.items);
-  else hipLaunchKernelGGL((primal_kernel<R, PM_UNCONSTRAINED>), g, b, 0, a.stream, a.descs, a.items);
+  switch (mode) {
+    case PM_CONSTRAINED: hipLaunchKernelGGL((primal_kernel<R, PM_CONSTRAINED>), g, b, 0, a.stream, a.descs, a.items); break;
+    case PM_INIT: hipLaunchKernelGGL((primal_kernel<R, PM_INIT>), g, b, 0, a.stream, a.descs, a.items); break;
+    case PM_UNCONSTRAINED: hipLaunchKernelGGL((primal_kernel<R, PM_UNCONSTRAINED>), g, b, 0, a.stream, a.descs, a.items); break;
+    case PM_TV_CONSTRAINED: hipLaunchKernelGGL((primal_kernel<R, PM_TV_CONSTRAINED>), g, b, 0, a.stream, a.descs, a.items); break;
+    default: hipLaunchKernelGGL((primal_kernel<R, PM_TV_UNCONSTRAINED>), g, b, 0, a.stream, a.descs, a.items); break;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------

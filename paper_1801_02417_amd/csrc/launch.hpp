@@ -16,14 +16,22 @@ struct LaunchArgs {
   int max_n = 0;           // largest image side among the launch's problems (0: not known)
 };
 
-// P1 modes
-enum PrimalMode { PM_CONSTRAINED = 0, PM_INIT = 1, PM_UNCONSTRAINED = 2 };
+// P1 modes (the TV modes are Algorithm 3's primal steps: the data term enters as its gradient,
+// held where Algorithm 1 holds Re phi^dagger B, and the row FFT that follows takes S_new)
+enum PrimalMode { PM_CONSTRAINED = 0, PM_INIT = 1, PM_UNCONSTRAINED = 2, PM_TV_CONSTRAINED = 3,
+                  PM_TV_UNCONSTRAINED = 4 };
+__host__ __device__ constexpr bool pm_constrained(int m) { return m == PM_CONSTRAINED || m == PM_TV_CONSTRAINED; }
+__host__ __device__ constexpr bool pm_positive_I(int m) {
+  return m == PM_INIT || m == PM_UNCONSTRAINED || m == PM_TV_UNCONSTRAINED;
+}
+__host__ __device__ constexpr bool pm_tv(int m) { return m == PM_TV_CONSTRAINED || m == PM_TV_UNCONSTRAINED; }
 // analysis modes
 enum AnalysisMode { AM_DUAL = 0, AM_STORE = 1, AM_REWEIGHT = 2, AM_OBJECTIVE = 3, AM_MOMENTS = 4, AM_MAXABS = 5 };
 // de-grid modes
-enum DegridMode { DG_DUAL = 0, DG_FORWARD = 1, DG_RESIDUAL = 2 };
-// grid modes
-enum GridMode { GR_DUAL = 0, GR_PLAIN = 1 };
+// DG_STOKES: per Stokes map, Phi S - Y L^{-1} (the residual of Algorithm 3's data term)
+enum DegridMode { DG_DUAL = 0, DG_FORWARD = 1, DG_RESIDUAL = 2, DG_STOKES = 3 };
+// grid modes (GR_STOKES: the rows are per Stokes map already, no mixing)
+enum GridMode { GR_DUAL = 0, GR_PLAIN = 1, GR_STOKES = 2 };
 
 template <typename R> void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot);
 template <typename R> void launch_primal_fft(int mode, const LaunchArgs& a, int cells);
@@ -48,6 +56,11 @@ template <typename R> void launch_npcount(const LaunchArgs& a);
 template <typename R> void launch_img_dot(const LaunchArgs& a, int xs, int ys);
 template <typename R> void launch_img_scale(const LaunchArgs& a, int dst, int src, int scalar);
 template <typename R> void launch_fill(void* p, size_t count, hipStream_t s);
+// TV priors (items: {prob, block of 256 pixels, -, partial index}): the dual step of
+// Algorithm 3 on X, Psi A into IMG_PSIA, and the prior's value of IMG_S into region 0 partials
+template <typename R> void launch_tv_dual(const LaunchArgs& a);
+template <typename R> void launch_tv_synth(const LaunchArgs& a);
+template <typename R> void launch_tv_objective(const LaunchArgs& a);
 // finalise: one workgroup per problem sums PART_GEN partials into scal[scalar]
 void launch_finalize(const ProbDesc* descs, int nprob, int region, int count, int scalar, hipStream_t s);
 void launch_finalize_zeta(const ProbDesc* descs, int nprob, hipStream_t s);

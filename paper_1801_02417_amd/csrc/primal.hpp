@@ -32,7 +32,8 @@ __device__ inline void proj_E2(R r0, R r1, R r2, R d, R& p0, R& p1, R& p2, R& pd
   }
 }
 
-// Updates every per-pixel variable of pixel p in place and returns X; g is Re phi^dagger B at p.
+// Updates every per-pixel variable of pixel p in place and returns X (S_new in the TV modes);
+// g is Re phi^dagger B at p (the data term's gradient in the TV modes).
 template <typename R, int MODE>
 __device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
   const R tau = R(P.tau), nm = R(P.norm);
@@ -50,13 +51,13 @@ __device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
     }
   }
   V4<R> c;
-  if (MODE == PM_CONSTRAINED) {
+  if (pm_constrained(MODE)) {
     c = ((const V4<R>*)P.img[IMG_C])[p];
     g.x += c.x; g.y += c.y; g.z += c.z; g.w += c.w;
   }
   V4<R> sn;
   sn.x = s.x - tau * g.x; sn.y = s.y - tau * g.y; sn.z = s.z - tau * g.z; sn.w = s.w - tau * g.w;
-  if (MODE != PM_CONSTRAINED) sn.x = fmax(sn.x, R(0));       // U': Stokes I >= 0
+  if (pm_positive_I(MODE)) sn.x = fmax(sn.x, R(0));          // U': Stokes I >= 0
   V4<R> x;
   x.x = R(2) * sn.x - s.x; x.y = R(2) * sn.y - s.y; x.z = R(2) * sn.z - s.z; x.w = R(2) * sn.w - s.w;
   S[p] = sn;
@@ -70,7 +71,7 @@ __device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
     ad.w = fmin(fmax(ad.w + r1 * x.w, -gw.w), gw.w);
     ((V4<R>*)P.coef[COEF_A])[p] = ad;
   }
-  if (MODE == PM_CONSTRAINED) {
+  if (pm_constrained(MODE)) {
     V2<R>* Z = (V2<R>*)P.img[IMG_Z];
     V2<R>* D = (V2<R>*)P.img[IMG_D];
     const V2<R> z = Z[p], d = D[p];
@@ -99,7 +100,7 @@ __device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
     Z[p] = zn;
     D[p] = dn;
   }
-  return x;
+  return pm_tv(MODE) ? sn : x;    // Algorithm 3 transforms S_new for its next gradient
 }
 
 // The same with Re phi^dagger B read from its image.

@@ -32,7 +32,7 @@ EXPORTS = (
     "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
     "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_profile_passes",
     "psara_batch_solve", "psara_batch_reweighted_solve", "psara_batch_profile_passes", "psara_data_gamma",
-    "psara_set_gamma", "psara_set_mueller", "psara_solve_adaptive", "psara_reweighted_solve_adaptive", "psara_batch_solve_adaptive",
+    "psara_set_gamma", "psara_set_mueller", "psara_set_prior_tv", "psara_solve_adaptive", "psara_reweighted_solve_adaptive", "psara_batch_solve_adaptive",
     "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
     "psara_server_clock", "psara_server_last_error", "psara_server_destroy",
 )
@@ -104,6 +104,7 @@ def lib() -> C.CDLL:
         "psara_opnorm": (I, [P, I, C.c_double, D]),
         "psara_solve": (I, [P, I, I, I, C.POINTER(PsaraReport)]),
         "psara_set_mueller": (I, [P, D]),
+        "psara_set_prior_tv": (I, [P, I, D, D]),
         "psara_solve_adaptive": (I, [P, I, I, I, C.POINTER(PsaraStop), C.POINTER(C.c_int), C.POINTER(PsaraReport)]),
         "psara_reweighted_solve_adaptive": (I, [P, I, I, I, I, C.POINTER(PsaraStop), C.c_double,
                                                 C.POINTER(C.c_int), C.POINTER(PsaraReport)]),
@@ -249,6 +250,21 @@ def psara_batch_solve_adaptive(ctxs, mode: int, max_iters: int, check_every: int
     _batch_check(ctxs, lib().psara_batch_solve_adaptive(_ctx_array(ctxs), len(ctxs), mode, max_iters, check_every,
                                                         C.byref(st), its, reps))
     return list(its), [r.as_dict() for r in reps]
+
+
+def psara_set_prior_tv(ctx, tv_weight, l1_weight=None) -> None:
+    """TV (l1_weight None) or l1 + TV prior of Algorithm 3; weights: 4 per-Stokes values."""
+    tw = _f64(np.asarray(tv_weight, dtype=np.float64).reshape(4))
+    lw = None if l1_weight is None else _f64(np.asarray(l1_weight, dtype=np.float64).reshape(4))
+    _check(ctx, lib().psara_set_prior_tv(ctx, 0 if lw is None else 1, _dptr(tw), _dptr(lw) if lw is not None else None))
+
+
+def tv_step_sizes(phi_norm_sq: float, l1: bool, margin: float = 0.99):
+    """Algorithm 3's step sizes: rho1 = 1 / ||Psi||^2, rho3 = 1, tau from the condition with the
+    data term's Lipschitz constant ||phi||^2 / 2 (rho2 is not used; returned as 1)."""
+    psi2 = 9.0 if l1 else 8.0
+    rho1, rho3 = 1.0 / psi2, 1.0
+    return margin / (phi_norm_sq / 4.0 + rho1 * psi2 + rho3), rho1, 1.0, rho3
 
 
 def psara_set_mueller(ctx, D) -> None:
@@ -523,6 +539,7 @@ class Solver:
     def set_prior(self, levels: int, gamma: float, basis_mask: int = ALL_BASES, weights=None):
         self.mask = basis_mask
         self.J = basis_count(basis_mask) * self.N
+        self.tv_kind = 0
         psara_set_prior(self.ctx, basis_mask, levels, weights, gamma)
 
     def opnorm(self, max_iter: int = 500, rtol: float = 1e-10) -> float:
@@ -531,8 +548,16 @@ class Solver:
 
     def set_steps(self, tau=None, rho1=None, rho2=None, rho3=None):
         if tau is None:
-            tau, rho1, rho2, rho3 = step_sizes(self.phi_norm_sq)
+            if getattr(self, "tv_kind", 0):
+                tau, rho1, rho2, rho3 = tv_step_sizes(self.phi_norm_sq, self.tv_kind == 2)
+            else:
+                tau, rho1, rho2, rho3 = step_sizes(self.phi_norm_sq)
         psara_set_steps(self.ctx, tau, rho1, rho2, rho3)
+
+    def set_prior_tv(self, tv_weight, l1_weight=None) -> None:
+        psara_set_prior_tv(self.ctx, tv_weight, l1_weight)
+        self.tv_kind = 1 if l1_weight is None else 2
+        self.J = (2 if l1_weight is None else 3) * self.N
 
     def solve(self, mode: int, iters: int, check_every: int = 0, report: bool = True):
         return psara_solve(self.ctx, mode, iters, check_every, report)

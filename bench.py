@@ -295,6 +295,30 @@ def mueller_form(P, wk, iters: int) -> dict:
             "P6_ms": round(float(ms[5]), 4), "P7_ms": round(float(ms[6]), 4)}
 
 
+def tv_form(P, wk, iters: int) -> dict:
+    """Algorithm 3 on the 256 x 256, 2e5-visibility workload: TV and l1 + TV with the
+    polarization constraint (eq. Akiyama_2), iteration rate of the captured graph."""
+    import torch
+
+    wl = wk.ring256()
+    out = {"n": wl.n, "M": wl.M, "iters": iters}
+    for name, l1 in (("tv", None), ("l1tv", [2e-3, 1e-3, 1e-3, 5e-4])):
+        s = P.Solver(wl.n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED)
+        Y, eps = make_data(P, wl, s)
+        s.set_prior_tv([4e-3, 2e-3, 2e-3, 1e-3], l1)
+        s.set_data(Y, eps)
+        s.opnorm(100, 1e-4)
+        s.set_steps()
+        s.solve(P.PSARA_CONSTRAINED, 16, report=False)            # graph capture and warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(P.PSARA_CONSTRAINED, iters, report=False)
+        torch.cuda.synchronize()
+        out[name + "_iters_per_s"] = round(iters / (time.perf_counter() - t0), 1)
+        s.close()
+    return out
+
+
 def profile_run(P, wk, form: str, iters: int) -> dict:
     """Only the timed passes of one form, for a profiler run: each pass launched on one stream with
     the two branches serialised (psara_profile_passes / psara_batch_profile_passes, constrained
@@ -460,6 +484,8 @@ def main() -> int:
     if args.large_iters > 0:
         progress("Mueller form: 256x256 with per-row Mueller matrices")
         line["mueller_form"] = mueller_form(P, wk, args.large_iters)
+        progress("TV form: Algorithm 3 on the 256x256 workload")
+        line["tv_form"] = tv_form(P, wk, args.large_iters)
     if args.batch_solves > 0:
         progress(f"batched form: {args.batch_solves} solves")
         line["batched_form"] = batched_form(P, wk, args.batch_solves, [100, 100, 100])

@@ -33,11 +33,16 @@ HBM_PEAK_GBS = 8000.0
 # on the device every 20 iterations, the fixed runs' stage lengths as bounds
 ADAPTIVE_STOP, ADAPTIVE_CHECK = (5e-3, 1e-3, 0.5), 20
 PASS_SOURCES = ["kernels_fft.hip", "kernels_dwt.hip", "kernels_dwt.hip", "kernels_fft.hip", "kernels_fft.hip",
-                "kernels_grid.hip", "kernels_grid.hip", "kernels_fft.hip", "kernels_fft.hip", "kernels_fft.hip"]
+                "kernels_grid.hip", "kernels_grid.hip", "kernels_fft.hip", "kernels_fft.hip", "kernels_fft.hip",
+                "kernels_grid.hip"]
 PASS_KERNELS = ["fft_pass_kernel<float,512,0,0>", "analysis_kernel+coarse_kernel+synthesis_kernel+synthesis_final_kernel",
                 "-", "-", "fft_pass_kernel<float,512,1,-1>", "degrid_kernel<float,0,8>", "grid_kernel<float,0,8>",
-                "fft_pass_kernel<float,512,2,-1>", "fft_pass_kernel<float,512,3,-1>", "fft_pass_kernel<float,512,4,0>"]
-SINGLE_KERNEL_PASSES = (0, 4, 5, 6, 7, 8, 9)   # passes that are one kernel launch each
+                "fft_pass_kernel<float,512,2,-1>", "fft_pass_kernel<float,512,3,-1>", "fft_pass_kernel<float,512,4,0>",
+                "degrid_grid_kernel<float,0,8>"]
+# the single-launch passes an iteration runs (the chain's first P1+P4 and last P9 included);
+# P6 and P7 are timed on their own too, but the iterations run them as the fused pass
+SINGLE_KERNEL_PASSES = (0, 4, 7, 8, 9, 10)
+ITERATION_PASSES = (1, 4, 10, 7, 9)             # one iteration in the middle of a chain
 
 
 def algorithmic_bytes(N: int, M: int, nwav: int, R: int = 4) -> list:
@@ -63,14 +68,17 @@ def algorithmic_bytes(N: int, M: int, nwav: int, R: int = 4) -> list:
 
 
 def pass_bytes(N: int, M: int) -> list:
-    """Algorithmic bytes per launch of the ten timed launches (P1+P4, P2+P3, -, -, P5..P9 and the
-    fused P9+P1+P4): P1 runs inside P4's workgroups (X is handed over in registers), P3 inside
-    P2's launches (coarse levels fused), and the fused pass keeps Re phi^dagger B in LDS."""
+    """Algorithmic bytes per launch of the eleven timed launches (P1+P4, P2+P3, -, -, P5..P9, the
+    fused P9+P1+P4 and the fused P6+P7): P1 runs inside P4's workgroups (X is handed over in
+    registers), P3 inside P2's launches (coarse levels fused), the fused row pass keeps
+    Re phi^dagger B in LDS, and the fused P6+P7 pass grids B where it computes it (B and the
+    geometry are read once)."""
     nbytes = algorithmic_bytes(N, M, nwav=8)
     nbytes[0] += nbytes[3] - N * 16
     nbytes[1] += nbytes[2]
     nbytes[2] = nbytes[3] = 0
     nbytes.append(nbytes[8] + nbytes[0] - 2 * N * 16)
+    nbytes.append(nbytes[5] + nbytes[6] - M * (4 + 2 * 4 + 8 * 4))
     return nbytes
 
 
@@ -173,7 +181,7 @@ def batched_form(P, wk, count: int, stages) -> dict:
     nb = np.sum([pass_bytes(wl.n * wl.n, wl.M) for wl in wls], axis=0)
     passes = {P.PASS_NAMES[i]: {"ms": round(float(ms[i]), 4),
                                 "GB/s": round(float(nb[i]) / (ms[i] * 1e-3) / 1e9, 1) if ms[i] > 0 else 0.0}
-              for i in range(10) if ms[i] > 0}
+              for i in range(P.N_PASSES) if ms[i] > 0}
     for s in solvers:
         s.close()
     its = count * sum(stages)
@@ -262,7 +270,7 @@ def large_form(P, wk, iters: int) -> dict:
     ms = s.profile_passes(P.PSARA_CONSTRAINED, 8)
     s.close()
     return {"n": wl.n, "M": wl.M, "iters": iters, "iters_per_s": round(iters / dt, 1),
-            "passes_ms": {P.PASS_NAMES[i]: round(ms[i], 4) for i in range(10) if ms[i] > 0}}
+            "passes_ms": {P.PASS_NAMES[i]: round(ms[i], 4) for i in range(P.N_PASSES) if ms[i] > 0}}
 
 
 def mueller_form(P, wk, iters: int) -> dict:
@@ -331,14 +339,14 @@ def profile_run(P, wk, form: str, iters: int) -> dict:
         ms = s.profile_passes(P.PSARA_CONSTRAINED, iters)
         s.close()
         return {"profile_form": "large", "n": wl.n, "M": wl.M, "iters": 2 * iters,
-                "passes_ms": {P.PASS_NAMES[i]: round(float(ms[i]), 4) for i in range(10) if ms[i] > 0}}
+                "passes_ms": {P.PASS_NAMES[i]: round(float(ms[i]), 4) for i in range(P.N_PASSES) if ms[i] > 0}}
     wls = [wk.batch_request(i) for i in range(64)]
     solvers = [ready_solver(P, wl, norm_iters=50, norm_rtol=1e-4)[0] for wl in wls]
     ms = P.psara_batch_profile_passes([s.ctx for s in solvers], P.PSARA_CONSTRAINED, iters)
     for s in solvers:
         s.close()
     return {"profile_form": "batch", "solves": 64, "iters": 2 * iters,
-            "passes_ms": {P.PASS_NAMES[i]: round(float(ms[i]), 4) for i in range(10) if ms[i] > 0}}
+            "passes_ms": {P.PASS_NAMES[i]: round(float(ms[i]), 4) for i in range(P.N_PASSES) if ms[i] > 0}}
 
 
 def progress(msg: str) -> None:
@@ -456,7 +464,7 @@ def main() -> int:
                 "frac": round(gbs[dom] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"{P.PASS_NAMES[dom]} ({PASS_KERNELS[dom]})",
                 "algorithmic_bytes_per_launch": nbytes[dom], "avg_launch_ms": round(ms[dom], 5)}
-    passes = {P.PASS_NAMES[i]: {"ms": round(ms[i], 5), "GB/s": round(gbs[i], 1)} for i in range(10)}
+    passes = {P.PASS_NAMES[i]: {"ms": round(ms[i], 5), "GB/s": round(gbs[i], 1)} for i in range(P.N_PASSES)}
 
     line = {
         "metric": "PD iters/s (4-Stokes 256², 2e5 vis); served solves/s + p50/p99 latency",
@@ -469,7 +477,7 @@ def main() -> int:
                    "n": n, "M": M, "taps": wl.taps, "levels": wl.levels, "precision": "FP32 bulk, FP64 reductions"},
         "roofline": roofline,
         "passes": passes,
-        "sum_of_pass_ms": round(float(np.sum(ms[:9])), 5),
+        "sum_of_pass_ms": round(float(sum(ms[i] for i in ITERATION_PASSES)), 5),
         "solve_check": {"residual_over_eps": rep["residual"] / rep["epsilon"], "n_p": rep["n_p"]},
     }
     s.close()

@@ -283,14 +283,11 @@ int psara_layout(const psara_ctx* ctx, int64_t* perm);
  * [7] column inverse FFT (P8, which also sums the partial tiles of split gridding tiles),
  * [8] row inverse FFT + crop (P9), then runs `iters` more iterations in the order the captured
  * graphs use and writes to ms_per_pass[9] the average duration of the pass that fuses P9 with
- * the next iteration's P1+P4 (0 when iters < 2).  ms_per_pass holds 10 doubles.  The
- * iterations really run (the state advances by 2 * iters iterations). */
+ * the next iteration's P1+P4 (0 when iters < 2) and to ms_per_pass[10] that of the pass that
+ * fuses P6 and P7 (the iterations run that pass in place of [5] and [6]).  ms_per_pass holds
+ * 11 doubles.  The iterations really run (the state advances by 2 * iters iterations). */
 psara_status psara_profile_passes(psara_ctx* ctx, psara_mode mode, int iters, double* ms_per_pass);
 
-/* The same per-pass timing for a batch (the requirements of psara_batch_solve): every pass is
- * one launch over all `count` solves, all on the stream of ctxs[0] with the two branches
- * serialised, so each figure is the time of one batched launch of that pass.  ms_per_pass holds
- * 10 doubles.  Every member advances by 2 * iters iterations. */
 /* Batched psara_solve_adaptive: every member stops on its own criteria (its launches then
  * do nothing for it) and the call returns when all have stopped or max_iters iterations have
  * run.  iters_run: NULL or `count` counts.  Each member's result equals its solo adaptive run. */
@@ -298,6 +295,10 @@ psara_status psara_batch_solve_adaptive(psara_ctx* const* ctxs, int count, psara
                                         int check_every, const psara_stop* stop, int* iters_run,
                                         psara_report* reports);
 
+/* The same per-pass timing for a batch (the requirements of psara_batch_solve): every pass is
+ * one launch over all `count` solves, all on the stream of ctxs[0] with the two branches
+ * serialised, so each figure is the time of one batched launch of that pass.  ms_per_pass holds
+ * 11 doubles.  Every member advances by 2 * iters iterations. */
 psara_status psara_batch_profile_passes(psara_ctx* const* ctxs, int count, psara_mode mode, int iters,
                                         double* ms_per_pass);
 

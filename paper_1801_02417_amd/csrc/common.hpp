@@ -67,7 +67,8 @@ enum Scalar {
 };
 static_assert(SC_STOP_MAXIT < NUM_SCALARS, "scalar slots");
 // Partial sums per problem, each a (sum, compensation) pair of doubles: first the de-grid
-// region (n_p6 pairs), then kGenQ generic regions of gen_stride pairs each.
+// region (n_p6 pairs), then kGenQ generic regions of gen_stride pairs each, then one pair per
+// gridding chunk for the fused de-grid + grid pass.
 constexpr int kGenQ = 8;
 
 // Per-problem descriptor.  Pointers are typed by the engine's real type R.
@@ -76,6 +77,7 @@ struct ProbDesc {
   int nbases, has_dirac, nwav, ts;      // ts = grid tile side
   int ntile_side, deg, n_p6, gen_stride;
   int ntile_side_g;       // gridding tiles per side (side kGridTile)
+  int n_slots;            // gridding chunks (= partial slots) of the problem
   long long M;
   double tau, rho1, rho2, rho3, eps, gamma, norm;   // norm = 1/sqrt(nbases)
   double delta;                                     // reweighting delta in use
@@ -99,14 +101,14 @@ struct ProbDesc {
   const int* run_k0;      // packed window start of each run
   const int2* chunk_ent;  // list-entry range [lo, hi) of each gridding chunk
   void* gpart;            // gridding partial slots: n_slots x (kGridTile + T - 1)^2 cells, k2-major
-  const int4* chunks;     // gridding chunks {tile, first run, end run, partial slot or -1}
+  const int4* chunks;     // gridding chunks {tile, first run, end run, partial slot}
   const int2* tile_slots; // per gridding tile: {first partial slot, count} (count 0: no visibilities)
   const void* kbpoly;     // T x (deg+1) per-tap kernel polynomial coefficients (ascending), type R
   const void* twiddle;    // K complex exp(-2 pi i j / K), type R
   const void* deapod;     // n scaling factors 1/psi_hat((j - n/2)/K), type R
   const void* filters;    // nwav x 16 low-pass filters (zero padded), type R
   int wav_len[8];         // filter length of each wavelet basis
-  double* partials;       // [n_p6 pairs][kGenQ x gen_stride pairs]
+  double* partials;       // [n_p6 pairs][kGenQ x gen_stride pairs][n_slots pairs]
   double* scal;           // NUM_SCALARS
   long long ll_off[kMaxLevels + 1];  // element offset of level l's LL inside a basis block
 };
@@ -167,10 +169,16 @@ __device__ inline KSum block_reduce(KSum k, double* scratch) {
   return t;
 }
 
-// Sum `count` (s, c) pairs from `parts` in a fixed order with the whole block.
 // true when an adaptive run has stopped this problem (its kernels then do nothing)
 __device__ inline bool halted(const ProbDesc& P) { return P.scal[SC_HALT] != 0.0; }
 
+// the partial pairs of the fused de-grid + grid pass, one per gridding chunk (n_slots pairs
+// after the generic regions)
+__host__ __device__ inline double* chunk_partials(const ProbDesc& P) {
+  return P.partials + 2 * ((size_t)P.n_p6 + (size_t)kGenQ * P.gen_stride);
+}
+
+// Sum `count` (s, c) pairs from `parts` in a fixed order with the whole block.
 __device__ inline double block_sum_partials(const double* parts, int count, double* scratch) {
   KSum k;
   for (int i = threadIdx.x; i < count; i += blockDim.x) {

@@ -217,6 +217,7 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   h_.tile_slots = upload<int2>(g.tile_slots.data(), std::max<size_t>(1, g.tile_slots.size()));
   h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
   h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * (kGridTile + g.T - 1) * (kGridTile + g.T - 1));
+  h_.n_slots = g.n_slots;
   // tables
   std::vector<double> poly = kb_poly(g.T, g.beta, h_.deg);
   h_.kbpoly = upload_conv(poly.data(), poly.size());
@@ -300,7 +301,7 @@ template <typename R>
 void Engine<R>::realloc_partials() {
   const int stride = std::max(gen_parts_, 1);
   h_.gen_stride = stride;
-  const size_t count = 2 * ((size_t)h_.n_p6 + (size_t)kGenQ * stride);
+  const size_t count = 2 * ((size_t)h_.n_p6 + (size_t)kGenQ * stride + (size_t)h_.n_slots);
   if (h_.partials) dfree(h_.partials);
   h_.partials = dalloc<double>(count);
   zero(h_.partials, count * sizeof(double));
@@ -543,14 +544,11 @@ void launch_iterations(const PassLists& L, int mode, int count, hipStream_t s0, 
       hip_check(hipEventRecord(join, s1), "event record");
     }
     launch_fft<R>(1, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P5
-    if (tvm) {
-      launch_degrid<R>(DG_STOKES, lists_la(L, L.p6, s0), L.max_ts, L.taps, VIS_Y, VIS_R);
-      launch_grid<R>(GR_STOKES, lists_la(L, L.p7, s0), L.taps, VIS_R, 0);
-    } else {
-      launch_degrid<R>(DG_DUAL, lists_la(L, L.p6, s0), L.max_ts, L.taps, VIS_BV, VIS_BV);  // P6
-      launch_grid<R>(GR_DUAL, lists_la(L, L.p7, s0), L.taps, VIS_BV, 0);               // P7
-    }
-    launch_fft<R>(2, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P8
+    // P6 + P7 in one pass; P8 takes the factor of the gridded values from its partials (dual
+    // B: the l2-ball factor) or as one (TV residual)
+    if (tvm) launch_degrid_grid<R>(GR_STOKES, lists_la(L, L.p7, s0), L.taps, VIS_Y, VIS_R);
+    else launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7, s0), L.taps, VIS_BV, VIS_BV);
+    launch_fft<R>(2, lists_la(L, L.cols, s0), L.cells, tvm ? 2 : 1, 0);              // P8
     if (sparse) hip_check(hipStreamWaitEvent(s0, join, 0), "stream wait");
     if (k + 1 < count) launch_fused_rows<R>(mode, lists_la(L, L.rows, s0), L.rcells);  // P9 + next P1, P4
     else launch_fft<R>(3, lists_la(L, L.rows, s0), L.rcells, 0, IMG_PHIB);          // P9
@@ -1023,15 +1021,16 @@ void Engine<R>::set_state(const double* buf) {
 }
 
 // Run `iters` iterations of every problem in L with every pass on stream s, bracketed by HIP
-// events, and return the average duration of each pass (P1..P9) in milliseconds in ms[0..8];
-// then `iters` iterations in the captured graphs' order, returning the average duration of the
-// fused P9 + P1 + P4 pass in ms[9].
+// events, and return the average duration of each pass (P1..P9, with P6 and P7 as separate
+// passes) in milliseconds in ms[0..8]; then `iters` iterations in the captured graphs' order,
+// returning the average durations of the fused P9 + P1 + P4 pass in ms[9] and of the fused
+// P6 + P7 pass in ms[10].
 template <typename R>
 void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, double* ms) {
   constexpr int NP = 9;
   hipEvent_t ev[NP + 1];
   for (int i = 0; i <= NP; ++i) hip_check(hipEventCreate(&ev[i]), "event");
-  for (int i = 0; i <= NP; ++i) ms[i] = 0.0;
+  for (int i = 0; i <= NP + 1; ++i) ms[i] = 0.0;
   const bool sparse = (mode != PM_INIT) && L.sparse;
   auto p5_p8 = [&](bool timed) {
     launch_fft<R>(1, lists_la(L, L.cols, s), L.cells, 0, 0);
@@ -1042,6 +1041,14 @@ void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, 
     if (timed) hip_check(hipEventRecord(ev[7], s), "event record");
     launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 0, 0);
     if (timed) hip_check(hipEventRecord(ev[8], s), "event record");
+  };
+  // P5 .. P8 as the iterations run them, with the fused P6 + P7 pass timed
+  auto p5_p8_fused = [&]() {
+    launch_fft<R>(1, lists_la(L, L.cols, s), L.cells, 0, 0);
+    hip_check(hipEventRecord(ev[2], s), "event record");
+    launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7, s), L.taps, VIS_BV, VIS_BV);
+    hip_check(hipEventRecord(ev[3], s), "event record");
+    launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 1, 0);
   };
   for (int k = 0; k < iters; ++k) {
     hip_check(hipEventRecord(ev[0], s), "event record");
@@ -1065,20 +1072,24 @@ void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, 
   if (iters > 0) launch_primal_fft<R>(mode, lists_la(L, L.rows, s), L.rcells);
   for (int k = 0; k < iters; ++k) {
     if (sparse) launch_sara_dual<R>(L, s);
-    p5_p8(false);
+    p5_p8_fused();
+    float t = 0.f;
     if (k + 1 < iters) {
       hip_check(hipEventRecord(ev[0], s), "event record");
       launch_fused_rows<R>(mode, lists_la(L, L.rows, s), L.rcells);
       hip_check(hipEventRecord(ev[1], s), "event record");
       hip_check(hipEventSynchronize(ev[1]), "event sync");
-      float t = 0.f;
       hip_check(hipEventElapsedTime(&t, ev[0], ev[1]), "elapsed");
       ms[NP] += t;
     } else {
       launch_fft<R>(3, lists_la(L, L.rows, s), L.rcells, 0, IMG_PHIB);
+      hip_check(hipEventSynchronize(ev[3]), "event sync");
     }
+    hip_check(hipEventElapsedTime(&t, ev[2], ev[3]), "elapsed");
+    ms[NP + 1] += t;
   }
   if (iters > 1) ms[NP] /= iters - 1;
+  if (iters > 0) ms[NP + 1] /= iters;
   hip_check(hipStreamSynchronize(s), "profile sync");
   for (int i = 0; i <= NP; ++i) (void)hipEventDestroy(ev[i]);
 }

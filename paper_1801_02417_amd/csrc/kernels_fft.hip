@@ -160,8 +160,27 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   // and the rows before them), staged once so the per-cell gathers index LDS
   constexpr int kTslMax = CELLS / 256 + 2048 / 8;
   __shared__ int2 tsl[PASS == 2 ? kTslMax : 1];
+  __shared__ double red[PASS == 2 ? 2 * ((CELLS / 2 + 63) / 64) : 1];
   int trow0 = 0;
+  R gfac = R(1);
   if (PASS == 2) {
+    // the factor of the gridded values (src_slot: 0 the one the grid pass stored; 1 the l2-ball
+    // factor c = rho2 max(0, 1 - epsilon / ||Bv||) from the fused pass's per-chunk partials,
+    // reduced by every workgroup in the same fixed order and stored, with ||Bv||^2, by the
+    // problem's first; 2 one)
+    if (src_slot == 1) {
+      const double v2 = block_sum_partials(chunk_partials(P), P.n_slots, red);
+      const double vn = sqrt(v2);
+      const double c = (vn > P.eps) ? P.rho2 * (1.0 - P.eps / vn) : 0.0;
+      if (line0 == 0 && threadIdx.x == 0) {
+        P.scal[SC_CFAC] = c;
+        P.scal[SC_VNORM2] = v2;
+        P.scal[SC_GFAC] = c;
+      }
+      gfac = R(c);
+    } else if (src_slot == 0) {
+      gfac = R(P.scal[SC_GFAC]);
+    }
     const int ntg = P.ntile_side_g;
     trow0 = line0 / kGridTile - 1;
     const int ntr = min(K - 1, line0 + lines - 1) / kGridTile - trow0 + 1;
@@ -213,9 +232,8 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
             for (int ch = 0; ch < 4; ++ch) c.s[ch] = cadd(c.s[ch], o.s[ch]);
           }
         }
-        const R f = R(P.scal[SC_GFAC]);
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) { c.s[ch].re *= f; c.s[ch].im *= f; }
+        for (int ch = 0; ch < 4; ++ch) { c.s[ch].re *= gfac; c.s[ch].im *= gfac; }
       }
       lds[q] = c;
     } else {

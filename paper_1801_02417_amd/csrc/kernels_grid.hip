@@ -5,11 +5,12 @@
 //
 // Visibilities are sorted once (at set-up) by the grid tile that holds their window start
 // k0 = ceil(t - T/2).  De-gridding stages a tile plus its (T-1)-cell halo of the grid in LDS
-// and lets one thread per visibility gather its T x T taps from there.  Gridding is done
-// by tile owners: the workgroups of a tile walk the list of every visibility whose window
-// touches the tile and accumulate the taps that fall inside it in LDS; the tile is then
-// written once with plain stores (split tiles through partial slots summed in a fixed
-// order), so no global atomics are used.
+// and lets one thread per visibility gather its T x T taps from there.  Gridding is done by
+// the owner of each visibility's window start: the workgroups of a tile accumulate the taps of
+// its visibilities over the tile plus halo in LDS and write that region to a partial slot of
+// their own with plain stores; the column inverse FFT sums the slots covering each cell in a
+// fixed order, so no global atomics are used.  The iterations run both in one fused pass over
+// the gridding chunks, since a chunk's taps all lie in the region it accumulates.
 //
 // The dual variable B is kept as B = c * Bv: the de-gridding pass writes
 // Bv = B/rho2 + phi(X) - Y and the FP64 partial sums of ||Bv||^2; the gridding pass reduces
@@ -23,6 +24,126 @@
 #include "launch.hpp"
 
 namespace psara {
+
+// ---------------------------------------------------------------------------------------------
+// Pieces shared by the de-grid, grid and fused passes (one definition, so that the fused pass
+// computes exactly what the separate ones do).
+
+// v_s = sum_j w2[j] sum_i w1[i] win[(r2 + j) * ws + r1 + i].s: the T x T taps of a window held
+// in LDS as k2-major rows of ws cells
+template <typename R, int T>
+__device__ inline void interpolate(const Cell<R>* win, int ws, int r1, int r2, const R* w1, const R* w2,
+                                   cplx<R> v[4]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) v[s] = cmk(R(0), R(0));
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const Cell<R>* row = win + (r2 + j) * ws + r1;
+    cplx<R> t[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) t[s] = cmk(R(0), R(0));
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      const Cell<R> c = row[i];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) { t[s].re += w1[i] * c.s[s].re; t[s].im += w1[i] * c.s[s].im; }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { v[s].re += w2[j] * t[s].re; v[s].im += w2[j] * t[s].im; }
+  }
+}
+
+// the brightness products of row m from its de-gridded Stokes values: [I+Q, U+iV, U-iV, I-Q],
+// or with known Mueller matrices the row times L D_m^T
+template <typename R>
+__device__ inline Cell<R> brightness(const ProbDesc& P, int m, const cplx<R> v[4]) {
+  Cell<R> phi;
+  if (P.mix) {
+    const cplx<R>* __restrict__ mx = (const cplx<R>*)P.mix + (size_t)m * 16;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cplx<R> a = cmul(v[0], mx[j]);
+#pragma unroll
+      for (int s = 1; s < 4; ++s) a = cadd(a, cmul(v[s], mx[4 * s + j]));
+      phi.s[j] = a;
+    }
+  } else {
+    phi.s[0] = cadd(v[0], v[1]);
+    phi.s[1] = cadd(v[2], cmuli(v[3]));
+    phi.s[2] = csub(v[2], cmuli(v[3]));
+    phi.s[3] = csub(v[0], v[1]);
+  }
+  return phi;
+}
+
+// The de-grid pass's row m for MODE (not DG_FORWARD) from its de-gridded Stokes values, with
+// the squared moduli of its eight reals added to acc.  DG_DUAL: Bv = c/rho2 Bv_old + phi - Y
+// (src_slot holds Bv_old); DG_RESIDUAL: Y - phi; DG_STOKES: per Stokes map Phi S - Y L^{-1}
+// (I = (Y1 + Y4) / 2, Q = (Y1 - Y4) / 2, U = (Y2 + Y3) / 2, V = -i (Y2 - Y3) / 2).
+template <typename R, int MODE>
+__device__ inline Cell<R> degrid_row(const ProbDesc& P, int m, const cplx<R> v[4], int src_slot, KSum& acc) {
+  const Cell<R> y = ((const Cell<R>*)P.vis[VIS_Y])[m];
+  Cell<R> o;
+  if (MODE == DG_STOKES) {
+    const R h = R(0.5);
+    o.s[0] = csub(v[0], cscale(cadd(y.s[0], y.s[3]), h));
+    o.s[1] = csub(v[1], cscale(csub(y.s[0], y.s[3]), h));
+    o.s[2] = csub(v[2], cscale(cadd(y.s[1], y.s[2]), h));
+    const cplx<R> dv = csub(y.s[1], y.s[2]);
+    o.s[3] = csub(v[3], cmk(h * dv.im, -h * dv.re));
+  } else {
+    const Cell<R> phi = brightness<R>(P, m, v);
+    if (MODE == DG_DUAL) {
+      const Cell<R> bv = ((const Cell<R>*)P.vis[src_slot])[m];
+      const R cb = R(P.scal[SC_CFAC] / P.rho2);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        o.s[s].re = cb * bv.s[s].re + phi.s[s].re - y.s[s].re;
+        o.s[s].im = cb * bv.s[s].im + phi.s[s].im - y.s[s].im;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) o.s[s] = csub(y.s[s], phi.s[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double re = (double)o.s[s].re, im = (double)o.s[s].im;
+    acc.add(re * re);
+    acc.add(im * im);
+  }
+  return o;
+}
+
+// The gridded channels of row m with value b: B L^H (I = B1 + B4, Q = B1 - B4, U = B2 + B3,
+// V = i (B3 - B2)); with known Mueller matrices B (L D_m^T)^H; GR_STOKES: the row itself (it is
+// per Stokes map already).  Returns the largest magnitude among the eight reals.
+template <typename R, int MODE>
+__device__ inline R grid_channels(const ProbDesc& P, int m, const Cell<R>& b, V4<R>& u0, V4<R>& u1) {
+  if (MODE == GR_STOKES) {
+    u0.x = b.s[0].re; u0.y = b.s[0].im; u0.z = b.s[1].re; u0.w = b.s[1].im;
+    u1.x = b.s[2].re; u1.y = b.s[2].im; u1.z = b.s[3].re; u1.w = b.s[3].im;
+  } else if (P.mix) {
+    const cplx<R>* __restrict__ mx = (const cplx<R>*)P.mix + (size_t)m * 16;
+    cplx<R> u[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      cplx<R> a = cmul(b.s[0], cconj(mx[4 * s]));
+#pragma unroll
+      for (int j = 1; j < 4; ++j) a = cadd(a, cmul(b.s[j], cconj(mx[4 * s + j])));
+      u[s] = a;
+    }
+    u0.x = u[0].re; u0.y = u[0].im; u0.z = u[1].re; u0.w = u[1].im;
+    u1.x = u[2].re; u1.y = u[2].im; u1.z = u[3].re; u1.w = u[3].im;
+  } else {
+    u0.x = (b.s[0].re + b.s[3].re); u0.y = (b.s[0].im + b.s[3].im);
+    u0.z = (b.s[0].re - b.s[3].re); u0.w = (b.s[0].im - b.s[3].im);
+    u1.x = (b.s[1].re + b.s[2].re); u1.y = (b.s[1].im + b.s[2].im);
+    u1.z = -(b.s[2].im - b.s[1].im); u1.w = (b.s[2].re - b.s[1].re);
+  }
+  return fmax(fmax(fmax(fabs(u0.x), fabs(u0.y)), fmax(fabs(u0.z), fabs(u0.w))),
+              fmax(fmax(fabs(u1.x), fabs(u1.y)), fmax(fabs(u1.z), fabs(u1.w))));
+}
 
 // ---------------------------------------------------------------------------------------------
 // P6: de-grid + L mixing (+ dual B).  items: {prob, tile, first sorted vis, partial index}
@@ -62,83 +183,10 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
     kb_weights<R, T>(f.x, (const R*)P.kbpoly, w1);
     kb_weights<R, T>(f.y, (const R*)P.kbpoly, w2);
     cplx<R> v[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = cmk(R(0), R(0));
-#pragma unroll
-    for (int j = 0; j < T; ++j) {
-      const Cell<R>* row = win + (r2 + j) * Wb + r1;
-      cplx<R> t[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) t[s] = cmk(R(0), R(0));
-#pragma unroll
-      for (int i = 0; i < T; ++i) {
-        const Cell<R> c = row[i];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) { t[s].re += w1[i] * c.s[s].re; t[s].im += w1[i] * c.s[s].im; }
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) { v[s].re += w2[j] * t[s].re; v[s].im += w2[j] * t[s].im; }
-    }
-    // brightness products [I+Q, U+iV, U-iV, I-Q], or with known Mueller matrices the row
-    // times L D_m^T
-    Cell<R> phi;
-    if (P.mix) {
-      const cplx<R>* __restrict__ mx = (const cplx<R>*)P.mix + (size_t)m * 16;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        cplx<R> a = cmul(v[0], mx[j]);
-#pragma unroll
-        for (int s = 1; s < 4; ++s) a = cadd(a, cmul(v[s], mx[4 * s + j]));
-        phi.s[j] = a;
-      }
-    } else {
-      phi.s[0] = cadd(v[0], v[1]);
-      phi.s[1] = cadd(v[2], cmuli(v[3]));
-      phi.s[2] = csub(v[2], cmuli(v[3]));
-      phi.s[3] = csub(v[0], v[1]);
-    }
+    interpolate<R, T>(win, Wb, r1, r2, w1, w2, v);
     Cell<R>* __restrict__ out = (Cell<R>*)P.vis[out_slot];
-    if (MODE == DG_STOKES) {
-      // Phi S - Y L^{-1}: I = (Y1 + Y4) / 2, Q = (Y1 - Y4) / 2, U = (Y2 + Y3) / 2, V = -i (Y2 - Y3) / 2
-      const Cell<R> y = ((const Cell<R>*)P.vis[VIS_Y])[m];
-      const R h = R(0.5);
-      Cell<R> o;
-      o.s[0] = csub(v[0], cscale(cadd(y.s[0], y.s[3]), h));
-      o.s[1] = csub(v[1], cscale(csub(y.s[0], y.s[3]), h));
-      o.s[2] = csub(v[2], cscale(cadd(y.s[1], y.s[2]), h));
-      const cplx<R> dv = csub(y.s[1], y.s[2]);
-      o.s[3] = csub(v[3], cmk(h * dv.im, -h * dv.re));
-      out[m] = o;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        acc.add((double)o.s[s].re * (double)o.s[s].re);
-        acc.add((double)o.s[s].im * (double)o.s[s].im);
-      }
-    } else if (MODE == DG_FORWARD) {
-      out[m] = phi;
-    } else {
-      const Cell<R> y = ((const Cell<R>*)P.vis[VIS_Y])[m];
-      Cell<R> o;
-      if (MODE == DG_DUAL) {
-        const Cell<R> bv = ((const Cell<R>*)P.vis[src_slot])[m];
-        const R cb = R(P.scal[SC_CFAC] / P.rho2);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          o.s[s].re = cb * bv.s[s].re + phi.s[s].re - y.s[s].re;
-          o.s[s].im = cb * bv.s[s].im + phi.s[s].im - y.s[s].im;
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) o.s[s] = csub(y.s[s], phi.s[s]);
-      }
-      out[m] = o;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const double re = (double)o.s[s].re, im = (double)o.s[s].im;
-        acc.add(re * re);
-        acc.add(im * im);
-      }
-    }
+    if (MODE == DG_FORWARD) out[m] = brightness<R>(P, m, v);
+    else out[m] = degrid_row<R, MODE>(P, m, v, src_slot, acc);
   }
   if (MODE != DG_FORWARD) {
     const KSum tot = block_reduce(acc, red);
@@ -181,8 +229,9 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 // holding its window start, so it is gridded exactly once; the workgroup accumulates the tile
 // plus its (T-1)-wide halo on the high sides, (kGridTile + T - 1)^2 cells, which every window
 // starting in the tile stays inside.  A chunk is a set of runs of one tile's list, a run being
-// visibilities with the same window start, so all their T x T taps land on the same cells.  The chunk's entries (offsets and L^H-mixed values) are first staged in LDS
-// by the whole workgroup.  A group of 8 lanes then takes one run: lane i owns tap row i and
+// visibilities with the same window start, so all their T x T taps land on the same cells.
+// The chunk's entries (offsets and L^H-mixed values) are first staged in LDS by the whole
+// workgroup.  A group of 8 lanes then takes one run: lane i owns tap row i and
 // accumulates, over the run, the 8 cells of that row for the 8 real channels in registers
 // (the column weights are shared through lane shuffles), and adds the row to the tile once.
 //
@@ -199,7 +248,9 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 // order, and multiplies the sum by the scalar factor of B, which the gridding leaves out: one
 // item per problem (chunk index -1, first in the work list, so it runs beside the chunks)
 // stores that factor -- GR_DUAL: c, reduced in a fixed order from the de-grid partials and
-// also kept for the next iteration; GR_PLAIN: 1, or the stored c when use_cfac is set.
+// also kept for the next iteration; GR_PLAIN: 1, or the stored c when use_cfac is set;
+// GR_STOKES: 1.
+//
 // Nearest 64-bit integer of an (already scaled) value.  FP32 data (|y| < 2^50): adding
 // 1.5 * 2^52 rounds y to an integer held in the low mantissa bits of the sum; subtracting the
 // bit pattern of 1.5 * 2^52 leaves it as a two's-complement integer (two instructions).  FP64
@@ -219,85 +270,22 @@ template <> struct Fixed<double> {
   __device__ static long long conv(double a, double fx) { return __double2ll_rn(a * fx); }
 };
 
-template <typename R, int MODE, int T>
-__global__ void __launch_bounds__(kGridThreads, 4)
-grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac) {
-  constexpr int TG = kGridTile;
-  constexpr int RG = kGridTile + T - 1;            // tile plus halo
+// The exponent E of the chunk's fixed-point scale 2^E, with 2^E * total <= 2^kRange (total: the
+// sum over the chunk's rows of their largest channel magnitude); multiplying by 2^E is exact.
+template <typename R>
+__device__ inline int fixed_exponent(double total) {
+  return total > 0.0 ? min(Fixed<R>::kRange - (int)ceil(log2(total * (1.0 + 1e-6))), 100) : 0;
+}
+
+// Accumulates a chunk whose rows are staged in LDS (sf: fractional offsets, su: two V4 of
+// gridded channels per entry, entry q at list position ent.x + q) into acc, which must be zero,
+// and writes the region to the chunk's partial slot.  Called by the whole workgroup.
+template <typename R, int T>
+__device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 ent, int b1, int b2,
+                                  const V2<R>* sf, const V4<R>* su, unsigned long long* acc, int E) {
+  constexpr int RG = kGridTile + T - 1;
   constexpr int DEG = KbDeg<R>::value;
-  __shared__ unsigned long long acc[8 * RG * RG];   // channel-major: acc[c][k2 offset][k1 offset]
-  __shared__ V2<R> sf[kChunkEntries];             // staged fractional offsets
-  __shared__ V4<R> su[2 * kChunkEntries];         // staged mixed values, two V4 per entry
-  __shared__ double red[2 * (kGridThreads / 64)];
-  const int4 it = items[blockIdx.x];
-  const ProbDesc& P = descs[it.x];
-  if (halted(P)) return;                 // stopped by an adaptive run
-  if (it.y < 0) {                  // the factor item: the factor the column inverse FFT applies
-    if (MODE == GR_DUAL) {
-      const double v2 = block_sum_partials(P.partials, P.n_p6, red);
-      if (threadIdx.x == 0) {
-        const double vn = sqrt(v2);
-        const double c = (vn > P.eps) ? P.rho2 * (1.0 - P.eps / vn) : 0.0;
-        P.scal[SC_CFAC] = c;
-        P.scal[SC_VNORM2] = v2;
-        P.scal[SC_GFAC] = c;
-      }
-    } else if (threadIdx.x == 0) {
-      P.scal[SC_GFAC] = use_cfac ? P.scal[SC_CFAC] : 1.0;
-    }
-    return;
-  }
-  const int4 ch = P.chunks[it.y];
-  const int2 ent = P.chunk_ent[it.y];
-  const int K = P.K, ntg = P.ntile_side_g;
-  const int tile = ch.x;
-  const int t1 = tile / ntg, t2 = tile - t1 * ntg;
-  const int b1 = t1 * TG, b2 = t2 * TG;
-  for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
-
-  // stage the chunk's entries: offsets and B L^H (I = B1 + B4, Q = B1 - B4, U = B2 + B3,
-  // V = i (B3 - B2); with known Mueller matrices B (L D_m^T)^H instead); sum the largest
-  // channel magnitude of each for the fixed point
-  const Cell<R>* __restrict__ bsrc = (const Cell<R>*)P.vis[src_slot];
-  const V2<R>* __restrict__ frac = (const V2<R>*)P.vis_frac;
-  KSum bound;
-  for (int q = threadIdx.x; q < ent.y - ent.x; q += blockDim.x) {
-    const int m = P.list_idx[ent.x + q];
-    sf[q] = frac[m];
-    const Cell<R> b = bsrc[m];
-    V4<R> u0, u1;
-    if (MODE == GR_STOKES) {       // rows already per Stokes map
-      u0.x = b.s[0].re; u0.y = b.s[0].im; u0.z = b.s[1].re; u0.w = b.s[1].im;
-      u1.x = b.s[2].re; u1.y = b.s[2].im; u1.z = b.s[3].re; u1.w = b.s[3].im;
-    } else if (P.mix) {            // B (L D_m^T)^H
-      const cplx<R>* __restrict__ mx = (const cplx<R>*)P.mix + (size_t)m * 16;
-      cplx<R> u[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        cplx<R> a = cmul(b.s[0], cconj(mx[4 * s]));
-#pragma unroll
-        for (int j = 1; j < 4; ++j) a = cadd(a, cmul(b.s[j], cconj(mx[4 * s + j])));
-        u[s] = a;
-      }
-      u0.x = u[0].re; u0.y = u[0].im; u0.z = u[1].re; u0.w = u[1].im;
-      u1.x = u[2].re; u1.y = u[2].im; u1.z = u[3].re; u1.w = u[3].im;
-    } else {
-      u0.x = (b.s[0].re + b.s[3].re); u0.y = (b.s[0].im + b.s[3].im);
-      u0.z = (b.s[0].re - b.s[3].re); u0.w = (b.s[0].im - b.s[3].im);
-      u1.x = (b.s[1].re + b.s[2].re); u1.y = (b.s[1].im + b.s[2].im);
-      u1.z = -(b.s[2].im - b.s[1].im); u1.w = (b.s[2].re - b.s[1].re);
-    }
-    su[2 * q] = u0;
-    su[2 * q + 1] = u1;
-    const R mx = fmax(fmax(fmax(fabs(u0.x), fabs(u0.y)), fmax(fabs(u0.z), fabs(u0.w))),
-                      fmax(fmax(fabs(u1.x), fabs(u1.y)), fmax(fabs(u1.z), fabs(u1.w))));
-    bound.add((double)mx);
-  }
-  const double total = block_reduce(bound, red).value();      // includes a barrier
-  // power-of-two scale 2^E with 2^E * total <= 2^kRange: multiplying by it is exact
-  const int E = total > 0.0 ? min(Fixed<R>::kRange - (int)ceil(log2(total * (1.0 + 1e-6))), 100) : 0;
   const double fx = ldexp(1.0, E);
-
   const int lane8 = threadIdx.x & 7;               // tap row owned by this lane
   const int grp = threadIdx.x >> 3, ngrp = blockDim.x >> 3;
   R cr[DEG + 1];                                   // this lane's tap polynomial
@@ -359,6 +347,146 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   }
 }
 
+template <typename R, int MODE, int T>
+__global__ void __launch_bounds__(kGridThreads, 4)
+grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac) {
+  constexpr int RG = kGridTile + T - 1;            // tile plus halo
+  __shared__ unsigned long long acc[8 * RG * RG];   // channel-major: acc[c][k2 offset][k1 offset]
+  __shared__ V2<R> sf[kChunkEntries];             // staged fractional offsets
+  __shared__ V4<R> su[2 * kChunkEntries];         // staged mixed values, two V4 per entry
+  __shared__ double red[2 * (kGridThreads / 64)];
+  const int4 it = items[blockIdx.x];
+  const ProbDesc& P = descs[it.x];
+  if (halted(P)) return;                 // stopped by an adaptive run
+  if (it.y < 0) {                  // the factor item: the factor the column inverse FFT applies
+    if (MODE == GR_DUAL) {
+      const double v2 = block_sum_partials(P.partials, P.n_p6, red);
+      if (threadIdx.x == 0) {
+        const double vn = sqrt(v2);
+        const double c = (vn > P.eps) ? P.rho2 * (1.0 - P.eps / vn) : 0.0;
+        P.scal[SC_CFAC] = c;
+        P.scal[SC_VNORM2] = v2;
+        P.scal[SC_GFAC] = c;
+      }
+    } else if (threadIdx.x == 0) {
+      P.scal[SC_GFAC] = use_cfac ? P.scal[SC_CFAC] : 1.0;
+    }
+    return;
+  }
+  const int4 ch = P.chunks[it.y];
+  const int2 ent = P.chunk_ent[it.y];
+  const int ntg = P.ntile_side_g;
+  const int t1 = ch.x / ntg, t2 = ch.x - t1 * ntg;
+  const int b1 = t1 * kGridTile, b2 = t2 * kGridTile;
+  for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
+
+  // stage the chunk's entries: offsets and gridded channels; sum the largest channel magnitude
+  // of each for the fixed point
+  const Cell<R>* __restrict__ bsrc = (const Cell<R>*)P.vis[src_slot];
+  const V2<R>* __restrict__ frac = (const V2<R>*)P.vis_frac;
+  KSum bound;
+  for (int q = threadIdx.x; q < ent.y - ent.x; q += blockDim.x) {
+    const int m = P.list_idx[ent.x + q];
+    sf[q] = frac[m];
+    V4<R> u0, u1;
+    const R mx = grid_channels<R, MODE>(P, m, bsrc[m], u0, u1);
+    su[2 * q] = u0;
+    su[2 * q + 1] = u1;
+    bound.add((double)mx);
+  }
+  const double total = block_reduce(bound, red).value();      // includes a barrier
+  grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total));
+}
+
+// ---------------------------------------------------------------------------------------------
+// P6 + P7 in one pass, as the iterations run them (MODE GR_DUAL: Algorithm 1's dual B step and
+// its gridding, DG_DUAL then GR_DUAL; GR_STOKES: Algorithm 3's data-term residual, DG_STOKES
+// then GR_STOKES).  items: the gridding work list; its factor item does nothing here, since the
+// column inverse FFT that follows derives the factor from this pass's partials.
+//
+// A chunk's rows all have their window start in its tile, so every tap they read lies in the
+// tile plus its (T-1)-wide halo -- the region the chunk accumulates.  The region of the grid is
+// staged in LDS (in the memory the accumulation takes afterwards); each row is de-gridded there
+// by one thread, stored (Bv, or the residual) and staged for the gridding of the same chunk,
+// and the FP64 squared norms of the chunk go to its pair of chunk_partials.
+// (FP64: the LDS holds one workgroup per CU, so two waves per SIMD and 256 registers)
+template <typename R, int MODE, int T>
+__global__ void __launch_bounds__(kGridThreads, sizeof(R) == 8 ? 2 : 4)
+degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot) {
+  constexpr int RG = kGridTile + T - 1;
+  constexpr int DG = MODE == GR_STOKES ? DG_STOKES : DG_DUAL;
+  __shared__ unsigned long long acc[8 * RG * RG];   // first the grid window (RG x RG cells)
+  __shared__ V2<R> sf[kChunkEntries];
+  __shared__ V4<R> su[2 * kChunkEntries];
+  __shared__ double red[2 * (kGridThreads / 64)];
+  static_assert(sizeof(Cell<R>) <= 8 * sizeof(unsigned long long), "window fits the accumulator");
+  const int4 it = items[blockIdx.x];
+  const ProbDesc& P = descs[it.x];
+  if (halted(P) || it.y < 0) return;
+  const int4 ch = P.chunks[it.y];
+  const int2 ent = P.chunk_ent[it.y];
+  const int K = P.K, ntg = P.ntile_side_g;
+  const int t1 = ch.x / ntg, t2 = ch.x - t1 * ntg;
+  const int b1 = t1 * kGridTile, b2 = t2 * kGridTile;
+  // a thread's entries are q and q + blockDim.x: their indices, window starts and offsets are
+  // loaded first, so that those loads and the window's are in flight together
+  static_assert(kChunkEntries <= 2 * kGridThreads, "two entries per thread");
+  const int ne = ent.y - ent.x;
+  const V2<R>* __restrict__ frac = (const V2<R>*)P.vis_frac;
+  int me[2], pke[2];
+  V2<R> fe[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int q = threadIdx.x + e * blockDim.x;
+    me[e] = q < ne ? P.list_idx[ent.x + q] : 0;
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    pke[e] = P.vis_k0[me[e]];
+    fe[e] = frac[me[e]];
+  }
+  Cell<R>* win = (Cell<R>*)acc;
+  const Cell<R>* __restrict__ grid = (const Cell<R>*)P.grid;
+  for (int q = threadIdx.x; q < RG * RG; q += blockDim.x) {
+    const int a = q / RG, b = q - a * RG;                     // a: k2 offset, b: k1 offset
+    win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + b) & (K - 1))];
+  }
+  __syncthreads();
+
+  Cell<R>* __restrict__ out = (Cell<R>*)P.vis[out_slot];
+  KSum bound, norm;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int q = threadIdx.x + e * blockDim.x;
+    if (q >= ne) break;
+    const int m = me[e], pk = pke[e];
+    const V2<R> f = fe[e];
+    R w1[T], w2[T];
+    kb_weights<R, T>(f.x, (const R*)P.kbpoly, w1);
+    kb_weights<R, T>(f.y, (const R*)P.kbpoly, w2);
+    cplx<R> v[4];
+    interpolate<R, T>(win, RG, (pk >> 16) - b1, (pk & 0xffff) - b2, w1, w2, v);
+    const Cell<R> o = degrid_row<R, DG>(P, m, v, src_slot, norm);
+    out[m] = o;
+    sf[q] = f;
+    V4<R> u0, u1;
+    const R mx = grid_channels<R, MODE>(P, m, o, u0, u1);
+    su[2 * q] = u0;
+    su[2 * q + 1] = u1;
+    bound.add((double)mx);
+  }
+  const KSum nt = block_reduce(norm, red);                     // barriers: the window is done
+  if (threadIdx.x == 0) {
+    double* pp = chunk_partials(P);
+    pp[2 * ch.w] = nt.s;
+    pp[2 * ch.w + 1] = nt.c;
+  }
+  const double total = block_reduce(bound, red).value();
+  for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
+  __syncthreads();
+  grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total));
+}
+
 template <typename R, int T>
 void launch_grid_t(int mode, const LaunchArgs& a, int src_slot, int use_cfac) {
   const dim3 grid(a.nitems), block(kGridThreads);
@@ -378,6 +506,24 @@ void launch_grid(int mode, const LaunchArgs& a, int taps, int src_slot, int use_
   if (taps == 4) launch_grid_t<R, 4>(mode, a, src_slot, use_cfac);
   else if (taps == 6) launch_grid_t<R, 6>(mode, a, src_slot, use_cfac);
   else launch_grid_t<R, 8>(mode, a, src_slot, use_cfac);
+}
+
+template <typename R, int T>
+void launch_degrid_grid_t(int mode, const LaunchArgs& a, int src_slot, int out_slot) {
+  const dim3 grid(a.nitems), block(kGridThreads);
+  if (mode == GR_STOKES) {
+    hipLaunchKernelGGL((degrid_grid_kernel<R, GR_STOKES, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, out_slot);
+  } else {
+    hipLaunchKernelGGL((degrid_grid_kernel<R, GR_DUAL, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, out_slot);
+  }
+}
+
+template <typename R>
+void launch_degrid_grid(int mode, const LaunchArgs& a, int taps, int src_slot, int out_slot) {
+  if (a.nitems <= 0) return;
+  if (taps == 4) launch_degrid_grid_t<R, 4>(mode, a, src_slot, out_slot);
+  else if (taps == 6) launch_degrid_grid_t<R, 6>(mode, a, src_slot, out_slot);
+  else launch_degrid_grid_t<R, 8>(mode, a, src_slot, out_slot);
 }
 
 // Raise the dynamic-LDS limit of the de-grid / grid kernels once, outside any graph capture.
@@ -413,6 +559,8 @@ template void launch_degrid<float>(int, const LaunchArgs&, int, int, int, int);
 template void launch_degrid<double>(int, const LaunchArgs&, int, int, int, int);
 template void launch_grid<float>(int, const LaunchArgs&, int, int, int);
 template void launch_grid<double>(int, const LaunchArgs&, int, int, int);
+template void launch_degrid_grid<float>(int, const LaunchArgs&, int, int, int);
+template void launch_degrid_grid<double>(int, const LaunchArgs&, int, int, int);
 
 
 }  // namespace psara

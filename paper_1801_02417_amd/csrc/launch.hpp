@@ -33,12 +33,18 @@ enum DegridMode { DG_DUAL = 0, DG_FORWARD = 1, DG_RESIDUAL = 2, DG_STOKES = 3 };
 // grid modes (GR_STOKES: the rows are per Stokes map already, no mixing)
 enum GridMode { GR_DUAL = 0, GR_PLAIN = 1, GR_STOKES = 2 };
 
+// pass 2 (P8) takes src_slot as the factor mode of the gridded values: 0 the factor the grid
+// pass stored, 1 the l2-ball factor of the fused pass's partials, 2 one
 template <typename R> void launch_fft(int pass, const LaunchArgs& a, int cells, int src_slot, int dst_slot);
 template <typename R> void launch_primal_fft(int mode, const LaunchArgs& a, int cells);
 // P9 of one iteration with P1 and P4 of the next (row work list)
 template <typename R> void launch_fused_rows(int mode, const LaunchArgs& a, int cells);
 template <typename R> void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_slot, int out_slot);
 template <typename R> void launch_grid(int mode, const LaunchArgs& a, int taps, int src_slot, int use_cfac);
+// P6 + P7 of an iteration in one pass over the gridding work list (mode GR_DUAL: de-grid with
+// the dual B step, then grid Bv; GR_STOKES: Algorithm 3's residual, then grid it); the column
+// inverse FFT after it takes factor mode 1 (GR_DUAL) or 2 (GR_STOKES)
+template <typename R> void launch_degrid_grid(int mode, const LaunchArgs& a, int taps, int src_slot, int out_slot);
 template <typename R> void set_grid_kernel_limits(int max_ts, int taps);
 void hip_check(hipError_t e, const char* what);
 template <typename R> void launch_primal(int mode, const LaunchArgs& a);

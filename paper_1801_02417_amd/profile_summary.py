@@ -37,6 +37,8 @@ PASS_KERNELS = {
     6: ("void psara::grid_kernel<float, 0, 8>", "kernels_grid.hip"),
     7: ("void psara::fft_pass_kernel<float, 512, 2, -1>", "kernels_fft.hip"),
     8: ("void psara::fft_pass_kernel<float, 512, 3, -1>", "kernels_fft.hip"),
+    9: ("void psara::fft_pass_kernel<float, 512, 4, 0>", "kernels_fft.hip"),
+    10: ("void psara::degrid_grid_kernel<float, 0, 8>", "kernels_grid.hip"),
 }
 
 

@@ -392,11 +392,13 @@ def psara_layout(ctx, M: int):
 PASS_NAMES = ("P1+P4 primal/epigraph/Dirac dual + zero-pad + row FFT", "P2+P3 SARA analysis + dual A + synthesis",
               "(in P2+P3)", "(in P1+P4)", "P5 column FFT", "P6 de-grid + dual B", "P7 grid",
               "P8 column inverse FFT (+ split-tile sums)", "P9 row inverse FFT + crop",
-              "P9+P1+P4 fused (row inverse FFT, primal step, row FFT)")
+              "P9+P1+P4 fused (row inverse FFT, primal step, row FFT)",
+              "P6+P7 fused (de-grid + dual B + grid)")
+N_PASSES = len(PASS_NAMES)
 
 
 def psara_profile_passes(ctx, mode: int, iters: int) -> np.ndarray:
-    out = np.zeros(10)
+    out = np.zeros(N_PASSES)
     _check(ctx, lib().psara_profile_passes(ctx, mode, iters, _dptr(out)))
     return out
 
@@ -421,7 +423,7 @@ def psara_batch_solve(ctxs, mode: int, iters: int, report: bool = True):
 
 def psara_batch_profile_passes(ctxs, mode: int, iters: int) -> np.ndarray:
     """Per-pass milliseconds of one batched launch of each pass (as psara_profile_passes)."""
-    out = np.zeros(10)
+    out = np.zeros(N_PASSES)
     _batch_check(ctxs, lib().psara_batch_profile_passes(_ctx_array(ctxs), len(ctxs), mode, iters, _dptr(out)))
     return out
 

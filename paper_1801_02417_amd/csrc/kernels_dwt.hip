@@ -450,7 +450,8 @@ template <typename R>
 __device__ inline R& chan(V4<R>& v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
 
 template <int F, typename R>
-__device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, int c_level, R* bufA, R* bufB, R* pyr) {
+__device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, int c_level, R* bufA, R* bufB, R* pyr,
+                                            R* gw) {
   const Taps<R, F> t((const R*)P.filters + w * kMaxFilter);
   const int n = P.n, L = P.levels, nt = blockDim.x;
   R* __restrict__ ll = (R*)((V4<R>*)P.ll + (size_t)w * P.ll_stride);
@@ -459,7 +460,15 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
   const R r1n = R(P.rho1) * R(P.norm);
   const int m0 = n >> (c_level - 1);               // side of the coarse pyramid
   int m = m0;
-  for (int q = threadIdx.x; q < m * m; q += nt) bufA[q] = ll[4 * (P.ll_off[c_level - 1] + q) + ch];
+  // every coarse band lies in the top-left m0 x m0 block of the basis: its duals (into pyr,
+  // where the updated ones are kept) and thresholds are staged with the low-low band, so the
+  // dual updates below read LDS only
+  for (int q = threadIdx.x; q < m * m; q += nt) {
+    const size_t g = (size_t)(q / m0) * n + q % m0;
+    bufA[q] = ll[4 * (P.ll_off[c_level - 1] + q) + ch];
+    pyr[q] = A[4 * g + ch];
+    gw[q] = GW[4 * g + ch];
+  }
   __syncthreads();
   // ---- analysis c..L (bufA holds the m x m low-low band) ----
   for (int l = c_level; l <= L; ++l) {
@@ -490,15 +499,15 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
       if (col < h && l < L) {
         bufA[k * h + col] = ca;                              // next level's input
       } else {
-        const size_t g = (size_t)k * n + col;
-        const R a = fmin(fmax(A[4 * g + ch] + r1n * ca, -GW[4 * g + ch]), GW[4 * g + ch]);
-        A[4 * g + ch] = a;
-        pyr[k * m0 + col] = a;
+        const int p = k * m0 + col;
+        const R a = fmin(fmax(pyr[p] + r1n * ca, -gw[p]), gw[p]);
+        A[4 * ((size_t)k * n + col) + ch] = a;
+        pyr[p] = a;
       }
-      const size_t g = (size_t)(h + k) * n + col;
-      const R d = fmin(fmax(A[4 * g + ch] + r1n * cd, -GW[4 * g + ch]), GW[4 * g + ch]);
-      A[4 * g + ch] = d;
-      pyr[(h + k) * m0 + col] = d;
+      const int p = (h + k) * m0 + col;
+      const R d = fmin(fmax(pyr[p] + r1n * cd, -gw[p]), gw[p]);
+      A[4 * ((size_t)(h + k) * n + col) + ch] = d;
+      pyr[p] = d;
     }
     __syncthreads();
     m = h;
@@ -555,11 +564,11 @@ template <typename R>
 __global__ void __launch_bounds__(512)
 coarse_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items) {
   constexpr int MM = CoarseMax<R>::value;
-  __shared__ R bufA[MM * MM], bufB[MM * MM], pyr[MM * MM];
+  __shared__ R bufA[MM * MM], bufB[MM * MM], pyr[MM * MM], gw[MM * MM];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
   if (halted(P)) return;                 // stopped by an adaptive run
-#define PSARA_COARSE(FF) coarse_body<FF, R>(P, it.y, it.z, it.w, bufA, bufB, pyr)
+#define PSARA_COARSE(FF) coarse_body<FF, R>(P, it.y, it.z, it.w, bufA, bufB, pyr, gw)
   PSARA_FILTER_SWITCH(P.wav_len[it.y], PSARA_COARSE)
 #undef PSARA_COARSE
 }

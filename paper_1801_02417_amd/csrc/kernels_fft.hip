@@ -72,6 +72,15 @@ __device__ inline void stockham_pass(cplx<R>* x, int K, int Ns, int tl, int per_
   constexpr int NB = 8 / RAD;
   const int stride = K / RAD;
   cplx<R> v[8];
+  // the pass's twiddles first, so that their loads are in flight across the barrier
+  const int twstep = K / (Ns * RAD);
+  cplx<R> wt[NB][RAD];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int k = (tl + b * per_line) % Ns;
+#pragma unroll
+    for (int r = 1; r < RAD; ++r) wt[b][r] = tw[r * k * twstep];
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -79,14 +88,13 @@ __device__ inline void stockham_pass(cplx<R>* x, int K, int Ns, int tl, int per_
     v[q] = x[4 * (tl + b * per_line + r * stride) + ch];
   }
   __syncthreads();
-  const int twstep = K / (Ns * RAD);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = tl + b * per_line;
     const int k = j % Ns;
 #pragma unroll
     for (int r = 1; r < RAD; ++r) {
-      cplx<R> w = tw[r * k * twstep];
+      cplx<R> w = wt[b][r];
       if (inv) w.im = -w.im;
       v[b * RAD + r] = cmul(v[b * RAD + r], w);
     }

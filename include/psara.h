@@ -284,7 +284,8 @@ int psara_layout(const psara_ctx* ctx, int64_t* perm);
  * [8] row inverse FFT + crop (P9), then runs `iters` more iterations in the order the captured
  * graphs use and writes to ms_per_pass[9] the average duration of the pass that fuses P9 with
  * the next iteration's P1+P4 (0 when iters < 2) and to ms_per_pass[10] that of the pass that
- * fuses P6 and P7 (the iterations run that pass in place of [5] and [6]).  ms_per_pass holds
+ * fuses P6 and P7 where the iterations of `mode` run it in place of [5] and [6] (modes with no
+ * SARA branch beside the data passes: PSARA_NNLS_INIT; 0 otherwise).  ms_per_pass holds
  * 11 doubles.  The iterations really run (the state advances by 2 * iters iterations). */
 psara_status psara_profile_passes(psara_ctx* ctx, psara_mode mode, int iters, double* ms_per_pass);
 

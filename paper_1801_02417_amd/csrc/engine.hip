@@ -520,6 +520,30 @@ void launch_sara_dual(const PassLists& L, hipStream_t s) {
   launch_synthesis_final<R>(lists_la(L, L.synfinal, s), COEF_A, IMG_PSIA, 0);
 }
 
+// Whether the iterations of `mode` run P6 and P7 as one fused pass: only when no SARA branch runs
+// beside them (the initialisation stage, Algorithm 3).  Alone the fused pass is the faster
+// (one launch, 50 against 26 + 32 us on the 256^2 / 2e5 workload), but beside the SARA kernels
+// its large workgroups share the CUs worse than the two separate passes, and the iteration is
+// about 5 % slower with it.
+inline bool fused_p6_p7(const PassLists& L, int mode) { return pm_tv(mode) || mode == PM_INIT || !L.sparse; }
+
+// P6, P7 and P8 of one iteration (the dual B step or Algorithm 3's residual, its gridding, and
+// the column inverse FFT, which takes the factor of the gridded values from the partials of the
+// fused pass, as one for the TV residual, or as the grid pass stored it)
+template <typename R>
+void launch_p6_p8(const PassLists& L, int mode, hipStream_t s) {
+  const bool tvm = pm_tv(mode);
+  if (fused_p6_p7(L, mode)) {
+    if (tvm) launch_degrid_grid<R>(GR_STOKES, lists_la(L, L.p7, s), L.taps, VIS_Y, VIS_R);
+    else launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7, s), L.taps, VIS_BV, VIS_BV);
+    launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, tvm ? 2 : 1, 0);
+  } else {
+    launch_degrid<R>(DG_DUAL, lists_la(L, L.p6, s), L.max_ts, L.taps, VIS_BV, VIS_BV);
+    launch_grid<R>(GR_DUAL, lists_la(L, L.p7, s), L.taps, VIS_BV, 0);
+    launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 0, 0);
+  }
+}
+
 template <typename R>
 void launch_iterations(const PassLists& L, int mode, int count, hipStream_t s0, hipStream_t s1, hipEvent_t fork,
                        hipEvent_t join) {
@@ -544,11 +568,7 @@ void launch_iterations(const PassLists& L, int mode, int count, hipStream_t s0, 
       hip_check(hipEventRecord(join, s1), "event record");
     }
     launch_fft<R>(1, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P5
-    // P6 + P7 in one pass; P8 takes the factor of the gridded values from its partials (dual
-    // B: the l2-ball factor) or as one (TV residual)
-    if (tvm) launch_degrid_grid<R>(GR_STOKES, lists_la(L, L.p7, s0), L.taps, VIS_Y, VIS_R);
-    else launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7, s0), L.taps, VIS_BV, VIS_BV);
-    launch_fft<R>(2, lists_la(L, L.cols, s0), L.cells, tvm ? 2 : 1, 0);              // P8
+    launch_p6_p8<R>(L, mode, s0);
     if (sparse) hip_check(hipStreamWaitEvent(s0, join, 0), "stream wait");
     if (k + 1 < count) launch_fused_rows<R>(mode, lists_la(L, L.rows, s0), L.rcells);  // P9 + next P1, P4
     else launch_fft<R>(3, lists_la(L, L.rows, s0), L.rcells, 0, IMG_PHIB);          // P9
@@ -1023,8 +1043,8 @@ void Engine<R>::set_state(const double* buf) {
 // Run `iters` iterations of every problem in L with every pass on stream s, bracketed by HIP
 // events, and return the average duration of each pass (P1..P9, with P6 and P7 as separate
 // passes) in milliseconds in ms[0..8]; then `iters` iterations in the captured graphs' order,
-// returning the average durations of the fused P9 + P1 + P4 pass in ms[9] and of the fused
-// P6 + P7 pass in ms[10].
+// returning the average durations of the fused P9 + P1 + P4 pass in ms[9] and, in the modes
+// whose iterations fuse P6 and P7, of that pass in ms[10] (0 otherwise).
 template <typename R>
 void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, double* ms) {
   constexpr int NP = 9;
@@ -1042,13 +1062,15 @@ void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, 
     launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 0, 0);
     if (timed) hip_check(hipEventRecord(ev[8], s), "event record");
   };
-  // P5 .. P8 as the iterations run them, with the fused P6 + P7 pass timed
-  auto p5_p8_fused = [&]() {
+  // P5 .. P8 as the iterations run them, with the fused P6 + P7 pass timed where they use it
+  const bool fused = fused_p6_p7(L, mode);
+  auto p5_p8_run = [&]() {
     launch_fft<R>(1, lists_la(L, L.cols, s), L.cells, 0, 0);
     hip_check(hipEventRecord(ev[2], s), "event record");
-    launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7, s), L.taps, VIS_BV, VIS_BV);
+    if (fused) launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7, s), L.taps, VIS_BV, VIS_BV);
     hip_check(hipEventRecord(ev[3], s), "event record");
-    launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 1, 0);
+    if (fused) launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 1, 0);
+    else launch_p6_p8<R>(L, mode, s);
   };
   for (int k = 0; k < iters; ++k) {
     hip_check(hipEventRecord(ev[0], s), "event record");
@@ -1072,7 +1094,7 @@ void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, 
   if (iters > 0) launch_primal_fft<R>(mode, lists_la(L, L.rows, s), L.rcells);
   for (int k = 0; k < iters; ++k) {
     if (sparse) launch_sara_dual<R>(L, s);
-    p5_p8_fused();
+    p5_p8_run();
     float t = 0.f;
     if (k + 1 < iters) {
       hip_check(hipEventRecord(ev[0], s), "event record");
@@ -1085,8 +1107,10 @@ void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, 
       launch_fft<R>(3, lists_la(L, L.rows, s), L.rcells, 0, IMG_PHIB);
       hip_check(hipEventSynchronize(ev[3]), "event sync");
     }
-    hip_check(hipEventElapsedTime(&t, ev[2], ev[3]), "elapsed");
-    ms[NP + 1] += t;
+    if (fused) {
+      hip_check(hipEventElapsedTime(&t, ev[2], ev[3]), "elapsed");
+      ms[NP + 1] += t;
+    }
   }
   if (iters > 1) ms[NP] /= iters - 1;
   if (iters > 0) ms[NP + 1] /= iters;

@@ -140,7 +140,7 @@ def test_batch_profile_passes_times_and_advances_like_alone():
     try:
         ms = P.psara_batch_profile_passes([s.ctx for s in members], P.PSARA_CONSTRAINED, 3)
         say(f"batch pass ms: {np.round(ms, 4)}")
-        assert all(ms[i] > 0 for i in (0, 1, 4, 5, 6, 7, 8, 9, 10)), ms
+        assert all(ms[i] > 0 for i in (0, 1, 4, 5, 6, 7, 8, 9)), ms
         assert ms[2] == 0 and ms[3] == 0
         for wl, s, a in zip(wls, members, alone):
             st = s.state()

@@ -6,7 +6,7 @@ and dual A, measurement operator and l2-ball dual B, epigraphical projections) o
 256 x 256 x 4-Stokes workload with 2e5 synthetic visibilities (KB 8 x 8 taps, 2x
 oversampled grid, SARA = Dirac + Db1..Db8 at 4 levels), FP32 bulk with FP64 reductions.
 Inputs and state are resident in HBM before the timed region; iterations replay a captured
-HIP graph.  Prints one JSON line (see the driver contract): the throughput, a roofline entry
+HIP graph.  Prints one JSON line: the throughput, a roofline entry
 for the dominant pass (algorithmic bytes per launch over its HIP-event-timed duration, and
 rocprof-measured HBM traffic when a summary of the same kernel source is committed), and
 the FP64 CPU oracle timed on a bounded sample of the same workload.

@@ -556,8 +556,11 @@ void launch_iterations(const PassLists& L, int mode, int count, hipStream_t s0, 
   const bool tvm = pm_tv(mode);
   const bool sparse = tvm || ((mode != PM_INIT) && L.sparse);
   for (int k = 0; k < count; ++k) {
+    // P5 is captured before the other branch's launches (it depends on the same row pass): the
+    // graph then issues it first, and the branch with less slack starts earlier
+    if (sparse) hip_check(hipEventRecord(fork, s0), "event record");
+    launch_fft<R>(1, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P5
     if (sparse) {
-      hip_check(hipEventRecord(fork, s0), "event record");
       hip_check(hipStreamWaitEvent(s1, fork, 0), "stream wait");
       if (tvm) {
         launch_tv_dual<R>(lists_la(L, L.img, s1));
@@ -567,7 +570,6 @@ void launch_iterations(const PassLists& L, int mode, int count, hipStream_t s0, 
       }
       hip_check(hipEventRecord(join, s1), "event record");
     }
-    launch_fft<R>(1, lists_la(L, L.cols, s0), L.cells, 0, 0);                        // P5
     launch_p6_p8<R>(L, mode, s0);
     if (sparse) hip_check(hipStreamWaitEvent(s0, join, 0), "stream wait");
     if (k + 1 < count) launch_fused_rows<R>(mode, lists_la(L, L.rows, s0), L.rcells);  // P9 + next P1, P4

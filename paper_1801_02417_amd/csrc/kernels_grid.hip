@@ -9,8 +9,9 @@
 // the owner of each visibility's window start: the workgroups of a tile accumulate the taps of
 // its visibilities over the tile plus halo in LDS and write that region to a partial slot of
 // their own with plain stores; the column inverse FFT sums the slots covering each cell in a
-// fixed order, so no global atomics are used.  The iterations run both in one fused pass over
-// the gridding chunks, since a chunk's taps all lie in the region it accumulates.
+// fixed order, so no global atomics are used.  Both also exist as one fused pass over the
+// gridding chunks (a chunk's taps all lie in the region it accumulates), which the iterations
+// use when no other branch runs beside them.
 //
 // The dual variable B is kept as B = c * Bv: the de-gridding pass writes
 // Bv = B/rho2 + phi(X) - Y and the FP64 partial sums of ||Bv||^2; the gridding pass reduces
@@ -399,9 +400,8 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
 }
 
 // ---------------------------------------------------------------------------------------------
-// P6 + P7 in one pass, as the iterations run them (MODE GR_DUAL: Algorithm 1's dual B step and
-// its gridding, DG_DUAL then GR_DUAL; GR_STOKES: Algorithm 3's data-term residual, DG_STOKES
-// then GR_STOKES).  items: the gridding work list; its factor item does nothing here, since the
+// P6 + P7 in one pass (MODE GR_DUAL: Algorithm 1's dual B step and its gridding, DG_DUAL then
+// GR_DUAL; GR_STOKES: Algorithm 3's data-term residual, DG_STOKES then GR_STOKES).  items: the gridding work list; its factor item does nothing here, since the
 // column inverse FFT that follows derives the factor from this pass's partials.
 //
 // A chunk's rows all have their window start in its tile, so every tap they read lies in the

@@ -19,6 +19,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -253,6 +254,21 @@ def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dic
     return out
 
 
+def served_in_child(args) -> dict:
+    """The served form in a child process (its progress lines go to this process's stderr), so
+    that a failure of the request server cannot take the rest of the benchmark line with it."""
+    cmd = [sys.executable, os.path.abspath(__file__), "--served-only", "--serve-requests", str(args.serve_requests),
+           "--serve-budget-gb", str(args.serve_budget_gb)]
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+    except subprocess.TimeoutExpired:
+        return {"error": "served form timed out after 900 s"}
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"served form exited with status {r.returncode}"}
+    return json.loads(lines[-1])
+
+
 def large_form(P, wk, iters: int) -> dict:
     """One 512 x 512 x 4 solve with 1e6 visibility rows (the served mix's large request), all
     terms active: iteration rate and per-pass times of the captured-graph iteration."""
@@ -398,6 +414,8 @@ def main() -> int:
     ap.add_argument("--profile-form-iters", type=int, default=40)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 10 times (to scale HBM counters)")
+    ap.add_argument("--served-only", action="store_true",
+                    help="only run the served form and print its JSON (the main run starts it this way)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the path is a single-GPU solve); --gpus {args.gpus} "
@@ -424,6 +442,10 @@ def main() -> int:
         return 0
     if args.profile_form:
         print(json.dumps(profile_run(P, wk, args.profile_form, args.profile_form_iters)), flush=True)
+        return 0
+    if args.served_only:
+        print(json.dumps(served_form(P, wk, args.serve_requests, 20.0, [100, 100, 100], args.serve_budget_gb)),
+              flush=True)
         return 0
     stream = torch.cuda.current_stream()
     wl = wk.ring256()
@@ -510,7 +532,7 @@ def main() -> int:
         progress(f"batched form done: {line['batched_form']['batched']}")
     if args.serve_requests > 0:
         progress(f"served form: {args.serve_requests} requests at 20/s")
-        line["served_form"] = served_form(P, wk, args.serve_requests, 20.0, [100, 100, 100], args.serve_budget_gb)
+        line["served_form"] = served_in_child(args)
         progress("served form done")
     if not args.no_cpu_baseline:
         progress("oracle CPU baseline")

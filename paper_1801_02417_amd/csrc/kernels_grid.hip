@@ -295,43 +295,59 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
 #pragma unroll
     for (int k = 0; k <= DEG; ++k) cr[k] = lane8 < T ? poly[k] : R(0);
   }
+  // FP64 accumulates a run's eight channels in two passes of four (T x 8 doubles would not stay
+  // in registers); each channel's sum is the same either way
+  constexpr int NC = sizeof(R) == 8 ? 4 : 8;
   for (int rr = ch.y + grp; rr - grp < ch.z; rr += ngrp) {
     const bool active = rr < ch.z;
     const int e0 = active ? P.run_beg[rr] - ent.x : 0;
     const int len = active ? P.run_len[rr] : 0;
     const int pk = active ? P.run_k0[rr] : 0;
-    R a[T][8];
+    // (one pass of eight channels, or in FP64 one pass per staged V4 of four)
+#pragma unroll 1
+    for (int c0 = 0; c0 < 8; c0 += NC) {
+      R a[T][NC];
 #pragma unroll
-    for (int j = 0; j < T; ++j)
+      for (int j = 0; j < T; ++j)
 #pragma unroll
-      for (int c = 0; c < 8; ++c) a[j][c] = R(0);
-    for (int q = 0; q < len; ++q) {
-      const V2<R> f = sf[e0 + q];
-      // this lane's tap in each dimension: psi(f - lane8) from its polynomial
-      const R w1 = kb_tap<R, T>(R(2) * f.x - R(T - 1), cr);
-      const R w2 = kb_tap<R, T>(R(2) * f.y - R(T - 1), cr);
-      const V4<R> v0 = su[2 * (e0 + q)], v1 = su[2 * (e0 + q) + 1];
-      const R u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        for (int c = 0; c < NC; ++c) a[j][c] = R(0);
+      for (int q = 0; q < len; ++q) {
+        const V2<R> f = sf[e0 + q];
+        // this lane's tap in each dimension: psi(f - lane8) from its polynomial
+        const R w1 = kb_tap<R, T>(R(2) * f.x - R(T - 1), cr);
+        const R w2 = kb_tap<R, T>(R(2) * f.y - R(T - 1), cr);
+        R u[NC];
+        const V4<R> v0 = su[2 * (e0 + q) + (NC == 8 ? 0 : c0 / 4)];
+        u[0] = v0.x; u[1] = v0.y; u[2] = v0.z; u[3] = v0.w;
+        if (NC == 8) {
+          const V4<R> v1 = su[2 * (e0 + q) + 1];
+          u[4 % NC] = v1.x; u[5 % NC] = v1.y; u[6 % NC] = v1.z; u[7 % NC] = v1.w;
+        }
 #pragma unroll
-      for (int j = 0; j < T; ++j) {
-        const R wj = w1 * __shfl(w2, j, 8);
+        for (int j = 0; j < T; ++j) {
+          const R wj = w1 * __shfl(w2, j, 8);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) a[j][c] += wj * u[c];
+          for (int c = 0; c < NC; ++c) a[j][c] += wj * u[c];
+        }
       }
-    }
-    if (len > 0 && lane8 < T) {
-      const int c1 = (pk >> 16) - b1 + lane8;              // the window start lies in the tile
-      unsigned long long* row = acc + c1;
+      if (len > 0 && lane8 < T) {
+        const int c1 = (pk >> 16) - b1 + lane8;              // the window start lies in the tile
+        unsigned long long* row = acc + c1;
 #pragma unroll
-      for (int j = 0; j < T; ++j) {
-        unsigned long long* cell = row + ((pk & 0xffff) - b2 + j) * RG;
-        // one tap column at a time: the empty asm (ordered with the atomics) keeps the
-        // compiler from widening all T x 8 sums to 64 bits at once, which would spill
-        asm volatile("" : "+v"(a[j][0]), "+v"(a[j][1]), "+v"(a[j][2]), "+v"(a[j][3]),
-                          "+v"(a[j][4]), "+v"(a[j][5]), "+v"(a[j][6]), "+v"(a[j][7]) :: "memory");
+        for (int j = 0; j < T; ++j) {
+          unsigned long long* cell = row + ((pk & 0xffff) - b2 + j) * RG;
+          // one tap column at a time: the empty asm (ordered with the atomics) keeps the
+          // compiler from widening all the sums to 64 bits at once, which would spill
+          if (NC == 8) {
+            asm volatile("" : "+v"(a[j][0]), "+v"(a[j][1]), "+v"(a[j][2]), "+v"(a[j][3]),
+                              "+v"(a[j][4 % NC]), "+v"(a[j][5 % NC]), "+v"(a[j][6 % NC]), "+v"(a[j][7 % NC]) :: "memory");
+          } else {
+            asm volatile("" : "+v"(a[j][0]), "+v"(a[j][1]), "+v"(a[j][2]), "+v"(a[j][3]) :: "memory");
+          }
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-          atomicAdd(cell + c * RG * RG, (unsigned long long)Fixed<R>::conv(a[j][c], fx));
+          for (int c = 0; c < NC; ++c)
+            atomicAdd(cell + (c0 + c) * RG * RG, (unsigned long long)Fixed<R>::conv(a[j][c], fx));
+        }
       }
     }
   }
@@ -348,8 +364,10 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
   }
 }
 
+// (FP64: the LDS holds one workgroup per CU, so two waves per SIMD and 256 registers, which
+// keeps the FP64 accumulators out of scratch memory)
 template <typename R, int MODE, int T>
-__global__ void __launch_bounds__(kGridThreads, 4)
+__global__ void __launch_bounds__(kGridThreads, sizeof(R) == 8 ? 2 : 4)
 grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac) {
   constexpr int RG = kGridTile + T - 1;            // tile plus halo
   __shared__ unsigned long long acc[8 * RG * RG];   // channel-major: acc[c][k2 offset][k1 offset]

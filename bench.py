@@ -403,8 +403,11 @@ def main() -> int:
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-solves", type=int, default=64, help="solves of the batched form (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=120,
-                    help="requests of the served form at 20/s (0: skip; 1200 is the full 60 s stream)")
+    # the served form is off by default: two of its runs ended with a host crash in a server
+    # thread whose cause is not known yet (see the design notes); 120 is the stream measured
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests of the served form at 20/s (0: skip, the default; 120 is the stream measured, "
+                         "1200 the full 60 s stream)")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-np-study", action="store_true")
     ap.add_argument("--large-iters", type=int, default=400,

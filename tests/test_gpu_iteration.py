@@ -193,3 +193,36 @@ def test_iterations_with_mueller_matrices(prec, tol):
         say(f"[mueller] {prec} 9 iterations: worst rel err {w:.2e}")
     finally:
         s.close()
+
+
+def test_max_image_side():
+    """The largest image side the boundary accepts (1024: a 2048^2 grid, 2048-point FFT lines,
+    every wavelet level on the tiled kernels): one constrained iteration from a random state against
+    the oracle, in FP64 and FP32.  Three bases and two levels keep the oracle's share to well under
+    a minute; its step sizes come from its own five-step power iteration, inflated by 1.5 so that
+    they bound ||phi||^2 from above (the device checks the step condition with its own norm)."""
+    n, M, T, L = 1024, 20000, 8, 2
+    bases = ("dirac", "db1", "db4")
+    say(f"[iter] n={n} M={M}: oracle set-up")
+    wl = wk.tiny(n=n, M=M, taps=T, levels=L, seed=91)
+    est, _ = pd.phi_norm_sq(MeasurementOp(NUFFT(wl.uv, n, 2, T)), n * n, max_iter=5, rtol=0.0)
+    b = problem.build(wl, bases=bases, phi_norm=1.5 * est)
+    rng = np.random.default_rng(92)
+    W = rng.uniform(0.2, 1.0, size=(b.sara.J, 4))
+    gW = b.gamma * W
+    st = _random_state(rng, n * n, b.sara.J, M, gW)
+    scale = {}
+    ref = _oracle_steps(st.copy(), b.pb, gW, "polsara", 1, scale)
+    for prec, tol in (("fp64", 1e-9), ("fp32", 5e-6)):
+        say(f"[iter] n={n} {prec}")
+        s = solver_for(wl, n, T, prec, levels=L, bases=bases, gamma=b.gamma, weights=W)
+        try:
+            s.set_data(b.pb.Y, b.pb.eps)
+            s.opnorm(100, 1e-6)
+            s.set_steps(b.pb.tau, b.pb.rho1, b.pb.rho2, b.pb.rho3)
+            s.set_state(st.S, st.Z, st.A, st.B, st.C, st.D)
+            s.solve(P.PSARA_CONSTRAINED, 1, report=False)
+            w = _compare(s.state(), ref, tol, f"n={n} {prec}", scale if prec == "fp32" else None)
+            say(f"   n={n} {prec}: worst rel err {w:.2e}")
+        finally:
+            s.close()

@@ -161,8 +161,8 @@ def batched_form(P, wk, count: int, stages) -> dict:
     batch (every pass one launch over all solves, graph-replayed) and one after another."""
     wls = [wk.batch_request(i) for i in range(count)]
     solvers = [ready_solver(P, wl)[0] for wl in wls]
-    import torch
-    torch.cuda.synchronize()
+    for s in solvers:
+        s.synchronize()
     for s in solvers:
         s.reset()
     t0 = time.perf_counter()
@@ -272,17 +272,16 @@ def served_in_child(args) -> dict:
 def large_form(P, wk, iters: int) -> dict:
     """One 512 x 512 x 4 solve with 1e6 visibility rows (the served mix's large request), all
     terms active: iteration rate and per-pass times of the captured-graph iteration."""
-    import torch
 
     wl = wk.batch_request(0, sides=(512,))
     s = ready_solver(P, wl, norm_iters=100, norm_rtol=1e-4)[0]
     s.solve(P.PSARA_NNLS_INIT, 20, report=False)
     P.psara_reweight(s.ctx, P.psara_coef_std(s.ctx))
     s.solve(P.PSARA_CONSTRAINED, 16, report=False)              # graph capture and warm-up
-    torch.cuda.synchronize()
+    s.synchronize()
     t0 = time.perf_counter()
     s.solve(P.PSARA_CONSTRAINED, iters, report=False)
-    torch.cuda.synchronize()
+    s.synchronize()
     dt = time.perf_counter() - t0
     ms = s.profile_passes(P.PSARA_CONSTRAINED, 8)
     s.close()
@@ -294,7 +293,6 @@ def mueller_form(P, wk, iters: int) -> dict:
     """The 256 x 256, 2e5-visibility workload with known direction-independent Mueller matrices
     on every row (8 stations, 10 % gain and 5 % leakage spread): every term active, iteration
     rate of the captured graph and the de-gridding / gridding pass times."""
-    import torch
 
     wl = wk.ring256()
     D = wk.station_mueller(np.random.default_rng(2417 * 7), wl.M)
@@ -309,10 +307,10 @@ def mueller_form(P, wk, iters: int) -> dict:
     s.solve(P.PSARA_NNLS_INIT, 20, report=False)
     P.psara_reweight(s.ctx, P.psara_coef_std(s.ctx))
     s.solve(P.PSARA_CONSTRAINED, 16, report=False)
-    torch.cuda.synchronize()
+    s.synchronize()
     t0 = time.perf_counter()
     s.solve(P.PSARA_CONSTRAINED, iters, report=False)
-    torch.cuda.synchronize()
+    s.synchronize()
     dt = time.perf_counter() - t0
     ms = s.profile_passes(P.PSARA_CONSTRAINED, 8)
     s.close()
@@ -323,7 +321,6 @@ def mueller_form(P, wk, iters: int) -> dict:
 def tv_form(P, wk, iters: int) -> dict:
     """Algorithm 3 on the 256 x 256, 2e5-visibility workload: TV and l1 + TV with the
     polarization constraint (eq. Akiyama_2), iteration rate of the captured graph."""
-    import torch
 
     wl = wk.ring256()
     out = {"n": wl.n, "M": wl.M, "iters": iters}
@@ -335,10 +332,10 @@ def tv_form(P, wk, iters: int) -> dict:
         s.opnorm(100, 1e-4)
         s.set_steps()
         s.solve(P.PSARA_CONSTRAINED, 16, report=False)            # graph capture and warm-up
-        torch.cuda.synchronize()
+        s.synchronize()
         t0 = time.perf_counter()
         s.solve(P.PSARA_CONSTRAINED, iters, report=False)
-        torch.cuda.synchronize()
+        s.synchronize()
         out[name + "_iters_per_s"] = round(iters / (time.perf_counter() - t0), 1)
         s.close()
     return out
@@ -425,15 +422,13 @@ def main() -> int:
               f"is not supported", file=sys.stderr)
         return 2
 
-    import torch
-    from paper_1801_02417_amd import psara as P
-    from paper_1801_02417_amd import workloads as wk
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 2
-    torch.cuda.init()
     if args.calibrate_copy:
+        # a plain device copy for the counter calibration (torch only here: the measured paths
+        # run the library on the HIP runtime it is built for, as the tests do)
+        import torch
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            return 2
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         a.fill_(1.0)
@@ -443,6 +438,14 @@ def main() -> int:
         print(json.dumps({"calibration": "copy", "bytes_read_per_launch": a.numel() * 4,
                           "bytes_written_per_launch": b.numel() * 4, "launches": 10}), flush=True)
         return 0
+    from paper_1801_02417_amd import psara as P
+    from paper_1801_02417_amd import workloads as wk
+
+    try:
+        P.psara_destroy(P.psara_create(0))
+    except (P.PsaraError, RuntimeError) as e:
+        print(f"bench.py needs a GPU and the built library: {e}", file=sys.stderr)
+        return 2
     if args.profile_form:
         print(json.dumps(profile_run(P, wk, args.profile_form, args.profile_form_iters)), flush=True)
         return 0
@@ -450,10 +453,9 @@ def main() -> int:
         print(json.dumps(served_form(P, wk, args.serve_requests, 20.0, [100, 100, 100], args.serve_budget_gb)),
               flush=True)
         return 0
-    stream = torch.cuda.current_stream()
     wl = wk.ring256()
     n, M, N = wl.n, wl.M, wl.n * wl.n
-    s = P.Solver(n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED, hip_stream=stream.cuda_stream)
+    s = P.Solver(n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED)
     # synthetic measurements on the device: Y = phi(S_true) + sigma E, sigma from the input SNR,
     # epsilon^2 = (8M + 2 sqrt(2 * 8M)) sigma^2 / 2 (chi-square bound of the simulation setup)
     truth = wl.truth.reshape(N, 4)
@@ -473,10 +475,10 @@ def main() -> int:
     P.psara_reweight(s.ctx, s.psara_delta)
     s.solve(P.PSARA_CONSTRAINED, args.warmup, report=False)
 
-    torch.cuda.synchronize()
+    s.synchronize()
     t0 = time.perf_counter()
     s.solve(P.PSARA_CONSTRAINED, args.steps, report=False)
-    torch.cuda.synchronize()
+    s.synchronize()
     dt = time.perf_counter() - t0
     its = args.steps / dt
     rep = s.report()

@@ -200,6 +200,11 @@ psara_status psara_reweighted_solve(psara_ctx* ctx, psara_mode mode, int cycles,
 /* Evaluate the stopping quantities for the current state. */
 psara_status psara_report_now(psara_ctx* ctx, psara_report* out);
 
+/* Wait until all work queued on the context's stream has finished (psara_solve and the other
+ * iteration calls return once their launches are queued).  EDEVICE if the device reports an
+ * error for that work. */
+psara_status psara_synchronize(psara_ctx* ctx);
+
 /* The data-driven regularisation weight gamma = factor * ||Psi^dagger Re phi^dagger Y||_inf /
  * ||phi||^2 (the choice of gamma used with the paper's setting, factor 1e-3), computed on the
  * device.  Requires operator, data, prior and psara_opnorm.  Does not change the context. */

@@ -611,6 +611,10 @@ psara_status psara_report_now(psara_ctx* c, psara_report* out) {
   });
 }
 
+psara_status psara_synchronize(psara_ctx* c) {
+  return guard(c, [&] { psara::hip_check(hipStreamSynchronize(c->stream), "synchronize"); });
+}
+
 psara_status psara_get_image(psara_ctx* c, double* S) {
   return guard(c, [&] {
     require(S != nullptr, PSARA_EINVAL, "S is NULL");

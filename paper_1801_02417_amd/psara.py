@@ -27,7 +27,8 @@ ALL_BASES = 0x1FF      # Dirac + Db1..Db8
 EXPORTS = (
     "psara_create", "psara_destroy", "psara_last_error", "psara_status_string", "psara_set_operator",
     "psara_set_data", "psara_set_prior", "psara_set_steps", "psara_opnorm", "psara_solve", "psara_reweight",
-    "psara_coef_std", "psara_reweighted_solve", "psara_report_now", "psara_get_image", "psara_state_bytes",
+    "psara_coef_std", "psara_reweighted_solve", "psara_report_now", "psara_synchronize", "psara_get_image",
+    "psara_state_bytes",
     "psara_get_state", "psara_set_state", "psara_reset_state", "psara_footprint", "psara_apply_phi",
     "psara_apply_phi_adjoint", "psara_apply_psi_adjoint", "psara_apply_psi", "psara_wavelet_filter",
     "psara_kb_beta", "psara_kb_value", "psara_kb_deapod", "psara_layout", "psara_profile_passes",
@@ -114,6 +115,7 @@ def lib() -> C.CDLL:
         "psara_coef_std": (I, [P, D]),
         "psara_reweighted_solve": (I, [P, I, I, C.POINTER(C.c_int), C.c_double, C.POINTER(PsaraReport)]),
         "psara_report_now": (I, [P, C.POINTER(PsaraReport)]),
+        "psara_synchronize": (I, [P]),
         "psara_get_image": (I, [P, D]),
         "psara_state_bytes": (S, [P]),
         "psara_get_state": (I, [P, P, S]),
@@ -300,6 +302,10 @@ def psara_report_now(ctx) -> dict:
     rep = PsaraReport()
     _check(ctx, lib().psara_report_now(ctx, C.byref(rep)))
     return rep.as_dict()
+
+
+def psara_synchronize(ctx) -> None:
+    _check(ctx, lib().psara_synchronize(ctx))
 
 
 def psara_get_image(ctx, N: int) -> np.ndarray:
@@ -613,6 +619,9 @@ class Solver:
 
     def report(self) -> dict:
         return psara_report_now(self.ctx)
+
+    def synchronize(self) -> None:
+        psara_synchronize(self.ctx)
 
     def reset(self):
         psara_reset_state(self.ctx)

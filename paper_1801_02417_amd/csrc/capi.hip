@@ -668,7 +668,7 @@ size_t psara_footprint(int n, int64_t M, int taps, int levels, uint32_t basis_ma
   for (int l = 1; l < levels; ++l) llst += (size_t)(n >> l) * (n >> l);
   const double spill = (1.0 + (taps - 1.0) / ts) * (1.0 + (taps - 1.0) / ts);
   size_t b = 0;
-  b += N * 32 * R;                                   // 7 four-channel and 2 two-channel images
+  b += N * 36 * R;                                   // 8 four-channel and 2 two-channel images
   b += (size_t)M * (24 * R + 4 + 2 * R);             // Y, Bv, R; window starts; offsets
   b += K * K * 8 * R + K * (size_t)n * 8 * R;        // grid and FFT intermediate
   b += (2 * ntiles + 2) * 4 + (size_t)(spill * (double)M + 1) * 4;

@@ -34,8 +34,10 @@ template <typename R> __host__ __device__ constexpr int dwt_syn_tile(int m) { re
 
 template <typename R> struct KbDeg { static constexpr int value = sizeof(R) == 4 ? 9 : 16; };
 
-// image-space buffers (N pixels x 4 Stokes, or x 2 for Z / D)
-enum ImgSlot { IMG_S = 0, IMG_X, IMG_C, IMG_PSIA, IMG_PHIB, IMG_TMP, IMG_TMP2, IMG_Z, IMG_D, NUM_IMG };
+// image-space buffers (N pixels x 4 Stokes, or x 2 for Z / D).  The wavelet part of Psi A that
+// the primal step reads is IMG_PSIA + IMG_PSIA2: the iteration's synthesis splits the bases over
+// two workgroups per tile, one writing each; every other writer of IMG_PSIA zeroes IMG_PSIA2.
+enum ImgSlot { IMG_S = 0, IMG_X, IMG_C, IMG_PSIA, IMG_PHIB, IMG_TMP, IMG_TMP2, IMG_PSIA2, IMG_Z, IMG_D, NUM_IMG };
 // visibility-space buffers (M rows x 4 complex, sorted order)
 enum VisSlot { VIS_Y = 0, VIS_BV, VIS_R, NUM_VIS };
 // coefficient-space buffers (nbases * N x 4)

@@ -152,7 +152,8 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
   *n_p6 = part;
 }
 
-void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int c_level, int* n_ana_parts) {
+void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const int* wav_len, bool fp64, int c_level,
+                     int* n_ana_parts) {
   const int N = n * n;
   int part = 0;
   for (int b = 0; b < (N + 255) / 256; ++b) S.dirac.push_back(make_int4(prob, b, 0, part++));
@@ -179,7 +180,27 @@ void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp6
       for (int ch = 0; ch < 4; ++ch) S.coarse.push_back(make_int4(prob, w, ch, c_level));
   {
     const int to = fp64 ? dwt_syn_tile<double>(n) : dwt_syn_tile<float>(n), tps = n / to;
-    for (int t = 0; t < tps * tps; ++t) S.synfinal.push_back(make_int4(prob, t, 0, 0));
+    // the split: longest filters first, each to the lighter part (work ~ filter length plus the
+    // window fetch, taken as 8 taps)
+    std::vector<int> order(nwav);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return wav_len[a] > wav_len[b]; });
+    int mask[2] = {0, 0}, work[2] = {0, 0};
+    for (int w : order) {
+      const int p = work[1] < work[0] ? 1 : 0;
+      mask[p] |= 1 << w;
+      work[p] += wav_len[w] + 8;
+    }
+    const int all = (1 << nwav) - 1;
+    for (int t = 0; t < tps * tps; ++t) {
+      S.synfinal.push_back(make_int4(prob, t, 0, all));
+      if (nwav < 2) {
+        S.synsplit.push_back(make_int4(prob, t, 0, all));
+      } else {
+        S.synsplit.push_back(make_int4(prob, t, 0, mask[0]));
+        S.synsplit.push_back(make_int4(prob, t, 1, mask[1]));
+      }
+    }
   }
   *n_ana_parts = part;
 }
@@ -331,7 +352,8 @@ void Engine<R>::upload_items() {
   };
   up(d_img_, items_.img); up(d_rows_, xcd_contiguous(items_.rows)); up(d_cols_, items_.cols);
   up(d_p6_, items_.p6); up(d_p7_, items_.p7);
-  up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal); up(d_coarse_, items_.coarse);
+  up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal); up(d_synsplit_, items_.synsplit);
+  up(d_coarse_, items_.coarse);
   for (int l = 0; l <= kMaxLevels; ++l) {
     up(d_ana_[l], items_.ana[l]); up(d_syn_[l], items_.syn[l]);
     up(d_ana_d_[l], items_.ana_d[l]); up(d_syn_d_[l], items_.syn_d[l]);
@@ -340,7 +362,7 @@ void Engine<R>::upload_items() {
   desc_dirty_ = true;
   pl_.descs = d_desc_;
   pl_.img = d_img_; pl_.rows = d_rows_; pl_.cols = d_cols_; pl_.p6 = d_p6_; pl_.p7 = d_p7_;
-  pl_.synfinal = d_synfinal_; pl_.coarse = d_coarse_;
+  pl_.synfinal = d_synsplit_; pl_.coarse = d_coarse_;
   for (int l = 0; l <= kMaxLevels; ++l) { pl_.ana_d[l] = d_ana_d_[l]; pl_.syn_d[l] = d_syn_d_[l]; }
   pl_.cells = cells_; pl_.rcells = rcells_;
   pl_.max_ts = geo_.ts; pl_.taps = geo_.T; pl_.max_levels = h_.levels;
@@ -398,7 +420,7 @@ void Engine<R>::set_prior_tv(int kind, const double* tv_weight, const double* l1
   for (int l = 0; l <= kMaxLevels; ++l) {
     items_.ana[l].clear(); items_.syn[l].clear(); items_.ana_d[l].clear(); items_.syn_d[l].clear();
   }
-  items_.synfinal.clear(); items_.coarse.clear();
+  items_.synfinal.clear(); items_.synsplit.clear(); items_.coarse.clear();
   h_.tv_kind = kind;
   for (int i = 0; i < 4; ++i) {
     h_.tvw[i] = tv_weight[i];
@@ -414,6 +436,7 @@ void Engine<R>::set_prior_tv(int kind, const double* tv_weight, const double* l1
   upload_items();
   invalidate_graphs();
   zero(h_.img[IMG_PSIA], (size_t)N * sizeof(V4<R>));
+  zero(h_.img[IMG_PSIA2], (size_t)N * sizeof(V4<R>));
   hip_check(hipStreamSynchronize(s0_), "set_prior_tv");
 }
 
@@ -425,7 +448,7 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   for (int c = 0; c < NUM_COEF; ++c) { dfree(h_.coef[c]); h_.coef[c] = nullptr; }
   dfree(h_.ll); h_.ll = nullptr;
   dfree((void*)h_.filters); h_.filters = nullptr;
-  items_.dirac.clear(); items_.synfinal.clear(); items_.coarse.clear();
+  items_.dirac.clear(); items_.synfinal.clear(); items_.synsplit.clear(); items_.coarse.clear();
   for (int l = 0; l <= kMaxLevels; ++l) {
     items_.ana[l].clear(); items_.syn[l].clear(); items_.ana_d[l].clear(); items_.syn_d[l].clear();
   }
@@ -462,7 +485,7 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   zero(h_.coef[COEF_A], coef_elems_ * sizeof(V4<R>));
   int nap = 0;
   c_level_ = coarse_level<R>(n, levels);
-  add_prior_items(items_, 0, n, levels, nwav, std::is_same<R, double>::value, c_level_, &nap);
+  add_prior_items(items_, 0, n, levels, nwav, h_.wav_len, std::is_same<R, double>::value, c_level_, &nap);
   ana_parts_ = nap;
   gen_parts_ = std::max((N + 255) / 256, nap);
   realloc_partials();
@@ -470,6 +493,7 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   invalidate_graphs();
   // the state's Psi A is zero again
   zero(h_.img[IMG_PSIA], (size_t)N * sizeof(V4<R>));
+  zero(h_.img[IMG_PSIA2], (size_t)N * sizeof(V4<R>));
   hip_check(hipStreamSynchronize(s0_), "set_prior");
 }
 
@@ -497,7 +521,7 @@ template <typename R> void Engine<R>::p2(hipStream_t s) {
 }
 template <typename R> void Engine<R>::p3(int src_coef, int dst_slot, int add_dirac, hipStream_t s) {
   for (int l = h_.levels; l >= 2; --l) launch_synthesis<R>(l, h_.levels, la(d_syn_[l], s), src_coef, 0);
-  launch_synthesis_final<R>(la(d_synfinal_, s), src_coef, dst_slot, add_dirac);
+  launch_synthesis_final<R>(la(d_synfinal_, s), src_coef, dst_slot, add_dirac, dst_slot);
 }
 template <typename R> void Engine<R>::p23(hipStream_t s) { launch_sara_dual<R>(pl_, s ? s : s0_); }
 
@@ -517,7 +541,7 @@ void launch_sara_dual(const PassLists& L, hipStream_t s) {
   for (int l = 1; l <= L.max_levels; ++l) launch_analysis<R>(AM_DUAL, l, lists_la(L, L.ana_d[l], s), IMG_X, COEF_A);
   launch_coarse<R>(lists_la(L, L.coarse, s));
   for (int l = L.max_levels; l >= 2; --l) launch_synthesis<R>(l, L.max_levels, lists_la(L, L.syn_d[l], s), COEF_A, 0);
-  launch_synthesis_final<R>(lists_la(L, L.synfinal, s), COEF_A, IMG_PSIA, 0);
+  launch_synthesis_final<R>(lists_la(L, L.synfinal, s), COEF_A, IMG_PSIA, 0, IMG_PSIA2);
 }
 
 // Whether the iterations of `mode` run P6 and P7 as one fused pass: only when no SARA branch runs
@@ -1038,6 +1062,7 @@ void Engine<R>::set_state(const double* buf) {
   adjoint(VIS_BV, 1, IMG_PHIB);
   if (coef_elems_ && h_.nwav > 0) p3(COEF_A, IMG_PSIA, 0, s0_);
   else zero(h_.img[IMG_PSIA], N * sizeof(V4<R>));
+  zero(h_.img[IMG_PSIA2], N * sizeof(V4<R>));
   hip_check(hipGetLastError(), "state prime");
   hip_check(hipStreamSynchronize(s0_), "set_state");
 }
@@ -1154,8 +1179,8 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
     if (np6 != e->desc().n_p6) throw Error(PSARA_EDEVICE, "inconsistent de-grid partition");
     if (e->has_prior()) {
       int nap = 0;
-      add_prior_items(S, (int)i, g.n, e->desc().levels, e->desc().nwav, std::is_same<R, double>::value,
-                      e->c_level(), &nap);
+      add_prior_items(S, (int)i, g.n, e->desc().levels, e->desc().nwav, e->desc().wav_len,
+                      std::is_same<R, double>::value, e->c_level(), &nap);
     }
   }
   auto up = [&](DevItems& d, const std::vector<int4>& v) {
@@ -1172,7 +1197,7 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
     d.ptr = (int4*)p;
   };
   up(pl_.img, S.img); up(pl_.rows, xcd_contiguous(S.rows)); up(pl_.cols, S.cols);
-  up(pl_.p6, S.p6); up(pl_.p7, S.p7); up(pl_.synfinal, S.synfinal); up(pl_.coarse, S.coarse);
+  up(pl_.p6, S.p6); up(pl_.p7, S.p7); up(pl_.synfinal, S.synsplit); up(pl_.coarse, S.coarse);
   for (int l = 0; l <= kMaxLevels; ++l) { up(pl_.ana_d[l], S.ana_d[l]); up(pl_.syn_d[l], S.syn_d[l]); }
   void* p = nullptr;
   if (hipMalloc(&p, members_.size() * sizeof(ProbDesc)) != hipSuccess || !p) {

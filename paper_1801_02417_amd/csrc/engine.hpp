@@ -49,13 +49,17 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T);
 //   ana[l], syn[l]     SARA analysis / synthesis of level l for every level (non-dual uses)
 //   ana_d[l], syn_d[l] the same restricted to the levels below each problem's fused coarse level
 //   coarse             {prob, wavelet, Stokes channel, first coarse level}
+//   synfinal           {prob, tile, 0, mask of every basis}
+//   synsplit           the same with the bases of each tile split over two items {prob, tile, part,
+//                      mask} of about equal filter work (one item per tile below two bases)
 struct ItemSet {
-  std::vector<int4> img, rows, cols, p6, p7, dirac, synfinal, coarse;
+  std::vector<int4> img, rows, cols, p6, p7, dirac, synfinal, synsplit, coarse;
   std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
   std::vector<int4> ana_d[kMaxLevels + 1], syn_d[kMaxLevels + 1];
 };
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int* n_p6);
-void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, bool fp64, int c_level, int* n_ana_parts);
+void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const int* wav_len, bool fp64, int c_level,
+                     int* n_ana_parts);
 
 struct DevItems {
   int4* ptr = nullptr;
@@ -182,7 +186,7 @@ struct Engine {
   ProbDesc* d_desc_ = nullptr;
   bool desc_dirty_ = true;
   ItemSet items_;
-  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_dirac_, d_synfinal_, d_coarse_;
+  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_dirac_, d_synfinal_, d_synsplit_, d_coarse_;
   int c_level_ = 1 << 20;     // first level handled by the fused coarse kernel (> levels: none)
   DevItems d_ana_[kMaxLevels + 1], d_syn_[kMaxLevels + 1];
   DevItems d_ana_d_[kMaxLevels + 1], d_syn_d_[kMaxLevels + 1];

@@ -392,12 +392,14 @@ synthesis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ it
   }
 }
 
-// Level 1 of every wavelet basis, summed, times 1/sqrt(nb); optionally plus the Dirac block.
-// The next basis's windows are loaded into registers while the current one is filtered.
-// items: {prob, tile, -, -}
+// Level 1 of the wavelet bases in the item's mask, summed, times 1/sqrt(nb); optionally plus the
+// Dirac block.  The next basis's windows are loaded into registers while the current one is
+// filtered.  items: {prob, tile, part, mask of bases}; part 0 writes dst_slot (with the Dirac
+// block), part 1 dst_slot2, so that a tile's bases can be split over two workgroups.
 template <typename R>
 __global__ void __launch_bounds__(256)
-synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_coef, int dst_slot, int add_dirac) {
+synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_coef, int dst_slot,
+                       int add_dirac, int dst_slot2) {
   __shared__ SynSmem<R> sm;
   constexpr int NPAIR = (SynSmem<R>::TS * SynSmem<R>::TS / 2 + 255) / 256;
   const int4 it = items[blockIdx.x];
@@ -409,24 +411,30 @@ synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restric
   V4<R> acc[2 * NPAIR], pre[4];
 #pragma unroll
   for (int u = 0; u < 2 * NPAIR; ++u) acc[u] = v4_zero<R>();
-  if (P.nwav > 0) syn_fetch<R>(P, 0, 1, o1, o2, to, src_coef, pre);
-  for (int w = 0; w < P.nwav; ++w) {
+  unsigned mask = (unsigned)it.w & ((1u << P.nwav) - 1u);
+  int w = mask ? __builtin_ctz(mask) : -1;
+  if (w >= 0) syn_fetch<R>(P, w, 1, o1, o2, to, src_coef, pre);
+  while (w >= 0) {
+    mask &= mask - 1u;
+    const int wn = mask ? __builtin_ctz(mask) : -1;
     __syncthreads();                       // the previous basis's windows are no longer read
     syn_store<R>(sm, pre);
-    if (w + 1 < P.nwav) syn_fetch<R>(P, w + 1, 1, o1, o2, to, src_coef, pre);
+    if (wn >= 0) syn_fetch<R>(P, wn, 1, o1, o2, to, src_coef, pre);
     PSARA_FILTER_SWITCH(P.wav_len[w], PSARA_SYN)
+    w = wn;
   }
 #undef PSARA_SYN
   const R nm = R(P.norm);
   const V4<R>* dirac = (const V4<R>*)P.coef[src_coef];
-  V4<R>* out = (V4<R>*)P.img[dst_slot];
+  const bool first = it.z == 0;
+  V4<R>* out = (V4<R>*)P.img[first ? dst_slot : dst_slot2];
 #pragma unroll
   for (int u = 0; u < 2 * NPAIR; ++u) {
     const int q = threadIdx.x + (u >> 1) * 256;
     if (q < to * th) {
       const size_t idx = (size_t)(o1 + q / th) * n + o2 + 2 * (q % th) + (u & 1);
       V4<R> s = acc[u];
-      if (add_dirac && P.has_dirac) {
+      if (first && add_dirac && P.has_dirac) {
         const V4<R> d = dirac[idx];
         s.x += d.x; s.y += d.y; s.z += d.z; s.w += d.w;
       }
@@ -636,9 +644,10 @@ void launch_synthesis(int level, int /*coarsest*/, const LaunchArgs& a, int src_
 }
 
 template <typename R>
-void launch_synthesis_final(const LaunchArgs& a, int src_coef, int dst_slot, int add_dirac) {
+void launch_synthesis_final(const LaunchArgs& a, int src_coef, int dst_slot, int add_dirac, int dst_slot2) {
   if (a.nitems <= 0) return;
-  hipLaunchKernelGGL((synthesis_final_kernel<R>), dim3(a.nitems), dim3(256), 0, a.stream, a.descs, a.items, src_coef, dst_slot, add_dirac);
+  hipLaunchKernelGGL((synthesis_final_kernel<R>), dim3(a.nitems), dim3(256), 0, a.stream, a.descs, a.items, src_coef,
+                     dst_slot, add_dirac, dst_slot2);
 }
 
 template void launch_analysis<float>(int, int, const LaunchArgs&, int, int);
@@ -647,11 +656,11 @@ template void launch_dirac<float>(int, const LaunchArgs&, int, int);
 template void launch_dirac<double>(int, const LaunchArgs&, int, int);
 template void launch_synthesis<float>(int, int, const LaunchArgs&, int, int);
 template void launch_synthesis<double>(int, int, const LaunchArgs&, int, int);
-template void launch_synthesis_final<float>(const LaunchArgs&, int, int, int);
+template void launch_synthesis_final<float>(const LaunchArgs&, int, int, int, int);
 template void launch_coarse<float>(const LaunchArgs&);
 template void launch_coarse<double>(const LaunchArgs&);
 template int coarse_level<float>(int, int);
 template int coarse_level<double>(int, int);
-template void launch_synthesis_final<double>(const LaunchArgs&, int, int, int);
+template void launch_synthesis_final<double>(const LaunchArgs&, int, int, int, int);
 
 }  // namespace psara

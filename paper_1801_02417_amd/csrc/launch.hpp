@@ -51,7 +51,9 @@ template <typename R> void launch_primal(int mode, const LaunchArgs& a);
 template <typename R> void launch_analysis(int mode, int level, const LaunchArgs& a, int src_slot, int out_slot);
 template <typename R> void launch_dirac(int mode, const LaunchArgs& a, int src_slot, int out_slot);
 template <typename R> void launch_synthesis(int level, int coarsest, const LaunchArgs& a, int src_coef, int dst_slot);
-template <typename R> void launch_synthesis_final(const LaunchArgs& a, int src_coef, int dst_slot, int add_dirac);
+// items {prob, tile, part, mask of bases}: part 0 writes dst_slot, part 1 dst_slot2
+template <typename R> void launch_synthesis_final(const LaunchArgs& a, int src_coef, int dst_slot, int add_dirac,
+                                                  int dst_slot2);
 template <typename R> void launch_coarse(const LaunchArgs& a);
 template <typename R> int coarse_level(int n, int levels);
 

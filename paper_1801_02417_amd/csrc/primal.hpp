@@ -45,6 +45,10 @@ __device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
   if (MODE != PM_INIT) {
     const V4<R> pa = ((const V4<R>*)P.img[IMG_PSIA])[p];
     g.x += pa.x; g.y += pa.y; g.z += pa.z; g.w += pa.w;
+    if (!pm_tv(MODE)) {
+      const V4<R> pb = ((const V4<R>*)P.img[IMG_PSIA2])[p];
+      g.x += pb.x; g.y += pb.y; g.z += pb.z; g.w += pb.w;
+    }
     if (dirac) {
       ad = ((const V4<R>*)P.coef[COEF_A])[p];
       g.x += nm * ad.x; g.y += nm * ad.y; g.z += nm * ad.z; g.w += nm * ad.w;

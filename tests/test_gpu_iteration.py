@@ -115,6 +115,42 @@ def test_iterations_dirac_only_and_wavelets_only(prec, tol):
             s.close()
 
 
+def _run_and_compare(s, b, gW, wl, rng, tol, prec, label):
+    st = _random_state(rng, wl.n * wl.n, b.sara.J, wl.M, gW)
+    s.set_state(st.S, st.Z, st.A, st.B, st.C, st.D)
+    s.solve(P.PSARA_CONSTRAINED, 3, report=False)
+    scale = {}
+    ref = _oracle_steps(st, b.pb, gW, "polsara", 3, scale)
+    return _compare(s.state(), ref, tol, label, scale if prec == "fp32" else None)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
+def test_iterations_one_wavelet_and_prior_change(prec, tol):
+    """A single wavelet basis, with and without the Dirac basis (each tile's last-level synthesis
+    is one work item and the second partial image of Psi A stays zero); then, on one solver, a
+    prior of all nine bases (whose iterations fill both partial images) replaced by a single
+    basis: the new state's upload has to clear the second image."""
+    for bases in (("db3",), ("dirac", "db7")):
+        wl, b, s, gW = _setup(16, 120, 6, 2, prec, seed=12, bases=bases)
+        try:
+            _run_and_compare(s, b, gW, wl, np.random.default_rng(6), tol, prec, str(bases))
+        finally:
+            s.close()
+    wl, b, s, gW = _setup(16, 120, 6, 2, prec, seed=13)
+    try:
+        rng = np.random.default_rng(9)
+        _run_and_compare(s, b, gW, wl, rng, tol, prec, "all bases")
+        b2 = problem.build(wl, bases=("db3",))
+        W2 = rng.uniform(0.2, 1.0, size=(b2.sara.J, 4))
+        s.set_prior(2, b2.gamma, mask_of(("db3",)), W2)
+        s.set_data(b2.pb.Y, b2.pb.eps)
+        s.set_steps(b2.pb.tau, b2.pb.rho1, b2.pb.rho2, b2.pb.rho3)
+        w = _run_and_compare(s, b2, b2.gamma * W2, wl, rng, tol, prec, "after the prior change")
+        say(f"[iter] prior of nine bases replaced by db3, {prec}: worst rel err {w:.2e}")
+    finally:
+        s.close()
+
+
 def test_state_roundtrip_and_reset():
     wl, b, s, gW = _setup(16, 100, 6, 2, "fp64", seed=21)
     try:

@@ -467,7 +467,11 @@ def main() -> int:
     s.set_prior(wl.levels, 1.0)
     gamma = 1e-3 * float(np.max(np.abs(s.psi_adjoint(s.phi_adjoint(Y))))) / phi_norm
     s.set_prior(wl.levels, gamma)
-    s.set_data(Y, eps)
+    s.synchronize()
+    t_up = time.perf_counter()
+    s.set_data(Y, eps)                   # host Y -> device (row permutation on the host, then the copy)
+    s.synchronize()
+    t_up = time.perf_counter() - t_up
     s.set_steps()
     # initialisation stage and first reweighting, so the timed iterations run every term
     s.solve(P.PSARA_NNLS_INIT, 100, report=False)
@@ -481,6 +485,9 @@ def main() -> int:
     s.synchronize()
     dt = time.perf_counter() - t0
     its = args.steps / dt
+    t_down = time.perf_counter()
+    s.image()                            # device S -> host
+    t_down = time.perf_counter() - t_down
     rep = s.report()
 
     ms = s.profile_passes(P.PSARA_CONSTRAINED, args.profile_iters)
@@ -516,6 +523,10 @@ def main() -> int:
         "sum_of_pass_ms": round(float(sum(ms[i] for i in ITERATION_PASSES)), 5),
         "fused_p6_p7": fused_pass,
         "solve_check": {"residual_over_eps": rep["residual"] / rep["epsilon"], "n_p": rep["n_p"]},
+        # the same timed iterations with the data's upload and the image's download through the
+        # boundary counted in (host buffers in and out)
+        "host_inclusive": {"iters_per_s": round(args.steps / (dt + t_up + t_down), 2),
+                           "upload_ms": round(t_up * 1e3, 3), "download_ms": round(t_down * 1e3, 3)},
     }
     s.close()
     progress(f"256x256 / 2e5-visibility iteration rate {its:.1f} iters/s")

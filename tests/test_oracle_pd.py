@@ -321,3 +321,18 @@ def test_run_alg1_adaptive_stops_at_first_passing_check(tiny_built):
     assert np.array_equal(ref.S, st.S)
     _, it2 = pd.run_alg1_adaptive(st0.copy(), b.pb, gW, "polsara", 25, 10, 0.0, 0.0, 0.0)
     assert it2 == 25
+
+
+def test_reweighting_is_the_log_penalty_majorizer(tiny_built):
+    """The weights of eq. weights are those of the reweighting scheme the paper takes from
+    Candes, Wakin & Boyd (2008): each weighted l1 problem minimises the linear majorizer of the
+    log-sum penalty delta * sum log(delta + |x|) at the previous estimate, whose slope in |x| is
+    delta / (delta + |x|).  Checked against a central difference of that penalty."""
+    b = tiny_built
+    S = np.random.default_rng(2).standard_normal((256, 4))
+    c = np.abs(b.sara.adjoint(S))
+    for delta in (0.05, 0.25, 2.0):
+        W = pd.reweight(b.pb, S, delta)
+        h = 1e-6 * (delta + c)
+        slope = delta * (np.log(delta + c + h) - np.log(delta + c - h)) / (2 * h)
+        assert np.max(np.abs(W - slope)) <= 1e-8

@@ -113,3 +113,21 @@ def test_constant_image_has_no_details(p):
     mask = np.ones((n, n), bool)
     mask[:m, :m] = False
     assert np.max(np.abs(c[mask])) < 1e-12
+
+
+@pytest.mark.parametrize("p", range(2, 9))
+def test_filters_are_minimum_phase(p):
+    """Daubechies' choice among the spectral factors (Sec. 3.1 names the Daubechies bases; the
+    filters are the minimum-phase ones): h(z) = (1 + z)^p q(z), and every zero of q lies inside
+    the unit circle.  Checked on the output filter with library polynomial division and root
+    finding, independently of how the filter was built; the identities above hold for every
+    spectral factor, so they cannot tell the phases apart."""
+    h = daubechies_lowpass(p)
+    binom = np.array([math.comb(p, k) for k in range(p + 1)], dtype=np.float64)
+    q, rem = np.polydiv(h, binom)
+    assert np.max(np.abs(rem)) < 1e-12
+    assert len(q) == p
+    zeros = np.roots(q)
+    assert np.all(np.abs(zeros) < 1.0 - 1e-6), np.abs(zeros)
+    # the p-fold zero at -1 is all of the unit-circle zeros: q has none there
+    assert abs(np.polyval(q, -1.0)) > 1e-3

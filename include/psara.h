@@ -91,11 +91,21 @@ typedef struct {
 /* ---- lifetime --------------------------------------------------------------------------- */
 
 /* Create a context on `device`.  `hip_stream` is a hipStream_t to run on (for example
- * torch.cuda.current_stream().cuda_stream) or NULL for a library-owned stream. */
+ * torch.cuda.current_stream().cuda_stream) or NULL for a library-owned stream.  PSARA_EDEVICE
+ * when no device is present or when psara_runtime_check fails. */
 psara_status psara_create(psara_ctx** out, int device, void* hip_stream);
 void psara_destroy(psara_ctx* ctx);
 const char* psara_last_error(const psara_ctx* ctx);
 const char* psara_status_string(psara_status s);
+
+/* Checks that the HIP runtime the process runs on has the major and minor version the library
+ * was built against: a process that has loaded another HIP runtime first (for example the one a
+ * Python framework bundles) makes the library run on that one, whose types and entry points need
+ * not match.  built / running (may be NULL) receive the two versions as major * 10^7 +
+ * minor * 10^5 + patch (running 0 if the runtime cannot be queried).  PSARA_OK when they
+ * agree, PSARA_EDEVICE otherwise.  psara_create and psara_server_create refuse to start on a
+ * mismatch.  Needs no device. */
+psara_status psara_runtime_check(int* built, int* running);
 
 /* ---- problem set-up (Sec. 2.2, 3.1, 4.1) --------------------------------------------------- */
 
@@ -122,6 +132,19 @@ psara_status psara_set_prior(psara_ctx* ctx, uint32_t basis_mask, int levels,
  * Sec. 3.3.3,  1/tau - rho1 ||Psi||^2 - rho2 ||phi||^2 - rho3 >= 0,  holds with the
  * operator norm from psara_opnorm (which must have run). */
 psara_status psara_set_steps(psara_ctx* ctx, double tau, double rho1, double rho2, double rho3);
+
+/* Step sizes meeting that condition (Sec. 3.3.3 gives only the condition; the values are this
+ * library's choice): prior 0 (SARA, ||Psi|| = 1, Algorithm 1): rho1 = rho3 = 1,
+ * rho2 = 1 / ||phi||^2, tau = margin / (rho1 + rho2 ||phi||^2 + rho3) = margin / 3; prior 1 (TV)
+ * or 2 (l1 + TV) of Algorithm 3: rho1 = 1 / ||Psi||^2 with ||Psi||^2 = 8 or 9, rho2 = 1 (unused),
+ * rho3 = 1, tau = margin / (||phi||^2 / 4 + rho1 ||Psi||^2 + rho3).  phi_norm_sq > 0,
+ * 0 < margin <= 1 (0.99 keeps a 1 % margin from the bound).  out: tau, rho1, rho2, rho3.
+ * Needs no device. */
+psara_status psara_step_sizes(int prior, double phi_norm_sq, double margin, double* out);
+
+/* psara_set_steps with the values of psara_step_sizes for the context's prior and the operator
+ * norm of its last psara_opnorm; out (NULL or 4 doubles) receives them. */
+psara_status psara_set_steps_auto(psara_ctx* ctx, double margin, double* out);
 
 /* The TV-based priors of Sec. 4.3 instead of SARA: the context then runs Algorithm 3 for
  * eq. Akiyama_2 (PSARA_CONSTRAINED: with the polarization constraint) or eq. Akiyama
@@ -161,6 +184,13 @@ psara_status psara_opnorm(psara_ctx* ctx, int max_iter, double rtol, double* phi
  * after the last iteration. */
 psara_status psara_solve(psara_ctx* ctx, psara_mode mode, int iters, int check_every,
                          psara_report* out);
+
+/* Capture, without running anything, the HIP graphs that psara_solve(ctx, mode, iters,
+ * check_every, ...) replays; a solve captures the graphs it lacks itself, so this only moves
+ * that work ahead of a timed or latency-critical call.  A solve of `iters` iterations replays
+ * chains of 32 captured iterations and one chain of the remainder.  Requirements as for
+ * psara_solve. */
+psara_status psara_capture(psara_ctx* ctx, psara_mode mode, int iters, int check_every);
 
 /* Run Algorithm 1 in `mode` from the current state until the criteria `stop` hold or
  * max_iters iterations have run.  The criteria are evaluated on the device (FP64 reductions)
@@ -319,7 +349,7 @@ psara_status psara_batch_profile_passes(psara_ctx* const* ctxs, int count, psara
  * leaves the batch at each stage end for its reweighting and rejoins.  Policy
  * PSARA_SERVE_FIFO instead runs one request at a time in arrival order.  Each result equals
  * the same request solved alone with psara_* calls in the order the server uses (operator,
- * data, prior with gamma 1, opnorm, data gamma, steps 0.99/3, 1, 1/||phi||^2, 1, then
+ * data, prior with gamma 1, opnorm, data gamma, psara_set_steps_auto with margin 0.99, then
  * psara_reweighted_solve, or psara_reweighted_solve_adaptive for a request with check_every > 0:
  * such a request leaves the batch as soon as its stage's criteria hold on the device).
  * Thread-safe for submit and poll. */

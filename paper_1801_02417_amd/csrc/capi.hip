@@ -216,9 +216,61 @@ const char* psara_status_string(psara_status s) {
   return "unknown status";
 }
 
+psara_status psara_runtime_check(int* built, int* running) {
+  int rt = 0;
+  const hipError_t e = hipRuntimeGetVersion(&rt);
+  if (built) *built = HIP_VERSION;
+  if (running) *running = e == hipSuccess ? rt : 0;
+  if (e != hipSuccess) return PSARA_EDEVICE;
+  // major * 10^7 + minor * 10^5 + patch: the major and minor versions must agree
+  return rt / 100000 == HIP_VERSION / 100000 ? PSARA_OK : PSARA_EDEVICE;
+}
+
+psara_status psara_step_sizes(int prior, double phi_norm_sq, double margin, double* out) {
+  if (!out || prior < 0 || prior > 2 || !std::isfinite(phi_norm_sq) || !(phi_norm_sq > 0.0) ||
+      !std::isfinite(margin) || !(margin > 0.0) || margin > 1.0)
+    return PSARA_EINVAL;
+  if (prior == 0) {
+    // Algorithm 1 with ||Psi|| = 1: rho1 = rho3 = 1, rho2 = 1 / ||phi||^2, and tau at `margin` of
+    // the largest value the condition 1/tau >= rho1 ||Psi||^2 + rho2 ||phi||^2 + rho3 allows
+    out[1] = 1.0;
+    out[2] = 1.0 / phi_norm_sq;
+    out[3] = 1.0;
+    out[0] = margin / (out[1] + 1.0 + out[3]);          // rho2 ||phi||^2 = 1 exactly
+
+  } else {
+    // Algorithm 3: rho1 = 1 / ||Psi||^2 with ||Psi||^2 <= 8 (TV) or 9 (l1 + TV), rho3 = 1, and the
+    // data term's gradient Lipschitz constant ||phi||^2 / 2 entering the condition as its half
+    const double psi2 = prior == 2 ? 9.0 : 8.0;
+    out[1] = 1.0 / psi2;
+    out[2] = 1.0;
+    out[3] = 1.0;
+    out[0] = margin / (0.25 * phi_norm_sq + out[1] * psi2 + out[3]);
+  }
+  return PSARA_OK;
+}
+
+psara_status psara_set_steps_auto(psara_ctx* c, double margin, double* out) {
+  if (!c) return PSARA_EINVAL;
+  double st[4];
+  psara_status s = PSARA_OK;
+  s = guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(c->norm_set, PSARA_ESTATE, "run psara_opnorm before setting steps");
+    require(psara_step_sizes(c->tv_kind, c->phi_norm_sq, margin, st) == PSARA_OK, PSARA_EINVAL,
+            "margin must be in (0, 1]");
+  });
+  if (s != PSARA_OK) return s;
+  s = psara_set_steps(c, st[0], st[1], st[2], st[3]);
+  if (s == PSARA_OK && out)
+    for (int i = 0; i < 4; ++i) out[i] = st[i];
+  return s;
+}
+
 psara_status psara_create(psara_ctx** out, int device, void* hip_stream) {
   if (!out) return PSARA_EINVAL;
   *out = nullptr;
+  if (psara_runtime_check(nullptr, nullptr) != PSARA_OK) return PSARA_EDEVICE;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PSARA_EDEVICE;
   if (device < 0 || device >= count) return PSARA_EINVAL;
@@ -397,6 +449,21 @@ psara_status psara_opnorm(psara_ctx* c, int max_iter, double rtol, double* phi_n
 
 psara_status psara_solve(psara_ctx* c, psara_mode mode, int iters, int check_every, psara_report* out) {
   return guard(c, [&] { run_stage(c, solve_mode(c, mode), iters, check_every, out); });
+}
+
+psara_status psara_capture(psara_ctx* c, psara_mode mode, int iters, int check_every) {
+  return guard(c, [&] {
+    const int pm = solve_mode(c, mode);
+    require(c->op_set && c->data_set && c->steps_set, PSARA_ESTATE, "operator, data and step sizes must be set");
+    require(pm == psara::PM_INIT || c->prior_set, PSARA_ESTATE, "prior must be set for this mode");
+    require(iters >= 0 && check_every >= 0, PSARA_EINVAL, "iters and check_every must be >= 0");
+    // the run lengths psara_solve uses: check_every at a time (the last one shorter), or all
+    const int chunk = check_every > 0 ? std::min(check_every, iters) : iters;
+    with_engine(c, [&](auto& e) {
+      if (chunk > 0) e.capture(pm, chunk);
+      if (chunk > 0 && iters % chunk) e.capture(pm, iters % chunk);
+    });
+  });
 }
 
 namespace {

@@ -20,6 +20,7 @@ constexpr int kRunMax = 32;         // longest run of same-window visibilities o
 constexpr int kChunkEntries = 1024; // gridding entries per workgroup (staged in LDS)
 constexpr int kGridThreads = 512;   // threads per gridding workgroup (64 lane groups of 8)
 constexpr int kBatchChunk = 8;       // iterations per captured graph of a batch
+constexpr int kChain = 32;           // iterations per captured chain of a single solve
 constexpr int kMaxDegridTile = 32;  // largest de-gridding tile side (the geometry picks 16 or 32)
 constexpr int kDegridItem = 256;        // visibilities per de-gridding work item
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)

@@ -12,6 +12,7 @@
 
 #include "common.hpp"
 #include "engine.hpp"
+#include "graph_key.hpp"
 #include "launch.hpp"
 #include "psara.h"
 
@@ -741,7 +742,7 @@ int Engine<R>::run_adaptive(int mode, int max_iters, int check_every, const doub
   stop_begin(stop);
   if (max_iters > 0) prime(mode);
   auto graph = [&](int count) -> hipGraphExec_t {
-    const int key = 1000000 + mode * 1000 + count;
+    const uint64_t key = graph_key(true, mode, count);
     auto it = graphs_.find(key);
     if (it != graphs_.end()) return it->second;
     hipGraph_t g = nullptr;
@@ -767,34 +768,43 @@ void Engine<R>::invalidate_graphs() {
 }
 
 template <typename R>
+hipGraphExec_t Engine<R>::chain_graph(int mode, int count) {
+  const uint64_t key = graph_key(false, mode, count);
+  auto it = graphs_.find(key);
+  if (it != graphs_.end()) return it->second;
+  hipGraph_t graph = nullptr;
+  hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
+  launch_iterations(mode, count);
+  hip_check(hipStreamEndCapture(s0_, &graph), "end capture");
+  hipGraphExec_t exec = nullptr;
+  hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+  (void)hipGraphDestroy(graph);
+  graphs_[key] = exec;
+  return exec;
+}
+
+// A run of `iters` iterations replays chains of kChain captured iterations (the chain's first
+// and last iterations run the unfused row passes, and each launch costs a few microseconds),
+// then one chain of the remaining iters mod kChain; so every run length uses at most two graphs,
+// whose per-iteration cost differs little.
+template <typename R>
+void Engine<R>::capture(int mode, int iters) {
+  sync_desc();
+  if (iters >= kChain) chain_graph(mode, kChain);
+  if (iters % kChain) chain_graph(mode, iters % kChain);
+}
+
+template <typename R>
 void Engine<R>::run(int mode, int iters) {
   sync_desc();
   if (iters <= 0) return;
   prime(mode);
-  // chains of 32 captured iterations (the chain's first and last iterations run the unfused row
-  // passes, and each launch costs a few microseconds: 32 gains 0.5 % over 8), then chains of 8
-  // and single iterations for the remainder
-  constexpr int kChains[3] = {32, 8, 1};
-  auto get_graph = [&](int count) -> hipGraphExec_t {
-    const int key = mode * 1000 + count;
-    auto it = graphs_.find(key);
-    if (it != graphs_.end()) return it->second;
-    hipGraph_t graph = nullptr;
-    hip_check(hipStreamBeginCapture(s0_, hipStreamCaptureModeRelaxed), "begin capture");
-    launch_iterations(mode, count);
-    hip_check(hipStreamEndCapture(s0_, &graph), "end capture");
-    hipGraphExec_t exec = nullptr;
-    hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
-    (void)hipGraphDestroy(graph);
-    graphs_[key] = exec;
-    return exec;
-  };
   int left = iters;
-  for (const int chain : kChains) {
-    if (left < chain) continue;
-    hipGraphExec_t g = get_graph(chain);
-    while (left >= chain) { hip_check(hipGraphLaunch(g, s0_), "graph launch"); left -= chain; }
+  if (left >= kChain) {
+    hipGraphExec_t g = chain_graph(mode, kChain);
+    while (left >= kChain) { hip_check(hipGraphLaunch(g, s0_), "graph launch"); left -= kChain; }
   }
+  if (left > 0) hip_check(hipGraphLaunch(chain_graph(mode, left), s0_), "graph launch");
   hip_check(hipGetLastError(), "iteration launch");
 }
 
@@ -1232,7 +1242,7 @@ Batch<R>::~Batch() {
 
 template <typename R>
 hipGraphExec_t Batch<R>::graph(int mode, int count) {
-  const int key = mode * 1000 + count;
+  const uint64_t key = graph_key(false, mode, count);
   auto it = graphs_.find(key);
   if (it != graphs_.end()) return it->second;
   hipGraph_t g = nullptr;
@@ -1298,7 +1308,7 @@ void Batch<R>::adaptive_buffers() {
 // The captured chunk of an adaptive run: `count` iterations, the check, the decision.
 template <typename R>
 hipGraphExec_t Batch<R>::adaptive_graph(int mode, int count) {
-  const int key = 1000000 + mode * 1000 + count;
+  const uint64_t key = graph_key(true, mode, count);
   auto it = graphs_.find(key);
   if (it != graphs_.end()) return it->second;
   adaptive_buffers();

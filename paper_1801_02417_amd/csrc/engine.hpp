@@ -107,6 +107,7 @@ struct Engine {
   void set_steps(double tau, double r1, double r2, double r3);
   void zero_state();
   void run(int mode, int iters);          // graph replay
+  void capture(int mode, int iters);      // capture the graphs run(mode, iters) replays (no work launched)
   void run_eager(int mode, int iters);    // direct launches
   // Up to max_iters iterations, checking the stopping criteria stop = {theta, rel_var, np_max}
   // on the device after every check_every of them; returns the iterations run.
@@ -162,6 +163,7 @@ struct Engine {
   void sync_desc();
   void invalidate_graphs();
   void launch_iterations(int mode, int count);
+  hipGraphExec_t chain_graph(int mode, int count);   // the captured chain of `count` iterations
   void prime(int mode);       // Algorithm 3: the data gradient and Psi A of the current state
   void adaptive_buffers();
   void forward(int src_img, int mode, int out_vis);
@@ -197,7 +199,7 @@ struct Engine {
   size_t coef_elems_ = 0;
   size_t bytes_ = 0;
   std::vector<void*> allocs_;
-  std::map<int, hipGraphExec_t> graphs_;
+  std::map<uint64_t, hipGraphExec_t> graphs_;
 };
 
 // Several solves advanced together: one launch per pass covers every member (their work lists
@@ -236,7 +238,7 @@ struct Batch {
   ProbDesc* d_descs_ = nullptr;
   std::vector<void*> allocs_;
   PassLists pl_;
-  std::map<int, hipGraphExec_t> graphs_;
+  std::map<uint64_t, hipGraphExec_t> graphs_;
 };
 
 }  // namespace psara

@@ -167,7 +167,7 @@ psara_status prepare_device(psara_server* S, Job& j, std::string& msg) {
   if ((st = psara_data_gamma(c, r.gamma_factor, &g)) != PSARA_OK) return fail(st);
   if (!(g > 0.0)) { msg = "data-driven gamma is zero"; psara_destroy(c); return PSARA_EINVAL; }
   if ((st = psara_set_gamma(c, g)) != PSARA_OK) return fail(st);
-  if ((st = psara_set_steps(c, 0.99 / 3.0, 1.0, 1.0 / nrm, 1.0)) != PSARA_OK) return fail(st);
+  if ((st = psara_set_steps_auto(c, 0.99, nullptr)) != PSARA_OK) return fail(st);
   j.ctx = c;
   j.stage = 0;
   j.left = j.stages[0];
@@ -491,6 +491,7 @@ psara_status psara_server_create(psara_server** out, int device, size_t hbm_budg
   *out = nullptr;
   if (max_slots < 1 || quantum < 1 || hbm_budget == 0) return PSARA_EINVAL;
   if (policy != PSARA_SERVE_BATCHED && policy != PSARA_SERVE_FIFO) return PSARA_EINVAL;
+  if (psara_runtime_check(nullptr, nullptr) != PSARA_OK) return PSARA_EDEVICE;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PSARA_EDEVICE;
   if (device < 0 || device >= count) return PSARA_EINVAL;

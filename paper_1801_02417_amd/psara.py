@@ -35,7 +35,8 @@ EXPORTS = (
     "psara_batch_solve", "psara_batch_reweighted_solve", "psara_batch_profile_passes", "psara_data_gamma",
     "psara_set_gamma", "psara_set_mueller", "psara_set_prior_tv", "psara_solve_adaptive", "psara_reweighted_solve_adaptive", "psara_batch_solve_adaptive",
     "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
-    "psara_server_clock", "psara_server_last_error", "psara_server_destroy",
+    "psara_server_clock", "psara_server_last_error", "psara_server_destroy", "psara_runtime_check",
+    "psara_step_sizes", "psara_set_steps_auto", "psara_capture",
 )
 
 PSARA_SERVE_BATCHED, PSARA_SERVE_FIFO = 0, 1
@@ -102,6 +103,10 @@ def lib() -> C.CDLL:
         "psara_set_data": (I, [P, D, C.c_double]),
         "psara_set_prior": (I, [P, U32, I, D, C.c_double]),
         "psara_set_steps": (I, [P, C.c_double, C.c_double, C.c_double, C.c_double]),
+        "psara_runtime_check": (I, [C.POINTER(I), C.POINTER(I)]),
+        "psara_step_sizes": (I, [I, C.c_double, C.c_double, D]),
+        "psara_set_steps_auto": (I, [P, C.c_double, D]),
+        "psara_capture": (I, [P, I, I, I]),
         "psara_opnorm": (I, [P, I, C.c_double, D]),
         "psara_solve": (I, [P, I, I, I, C.POINTER(PsaraReport)]),
         "psara_set_mueller": (I, [P, D]),
@@ -178,11 +183,26 @@ def _check(ctx, status: int):
 
 
 # ---- C-named functions --------------------------------------------------------------------------
+def psara_runtime_check():
+    """(status, built, running): the HIP runtime versions the library was built for and runs on."""
+    built, running = C.c_int(), C.c_int()
+    st = lib().psara_runtime_check(C.byref(built), C.byref(running))
+    return st, built.value, running.value
+
+
+def _create_error(st: int) -> PsaraError:
+    msg = lib().psara_status_string(st).decode()
+    rc, built, running = psara_runtime_check()
+    if rc != PSARA_OK:
+        msg += f" (HIP runtime {running} in this process, library built for {built})"
+    return PsaraError(st, msg)
+
+
 def psara_create(device: int = 0, hip_stream: Optional[int] = None):
     ctx = C.c_void_p()
     st = lib().psara_create(C.byref(ctx), device, C.c_void_p(hip_stream) if hip_stream else None)
     if st != PSARA_OK:
-        raise PsaraError(st, lib().psara_status_string(st).decode())
+        raise _create_error(st)
     return ctx
 
 
@@ -213,6 +233,21 @@ def psara_set_steps(ctx, tau: float, rho1: float, rho2: float, rho3: float) -> N
     _check(ctx, lib().psara_set_steps(ctx, tau, rho1, rho2, rho3))
 
 
+def psara_step_sizes(prior: int, phi_norm_sq: float, margin: float = 0.99):
+    """(tau, rho1, rho2, rho3) the library picks for prior 0 (SARA), 1 (TV) or 2 (l1 + TV)."""
+    out = np.zeros(4)
+    st = lib().psara_step_sizes(int(prior), float(phi_norm_sq), float(margin), _dptr(out))
+    if st != PSARA_OK:
+        raise PsaraError(st, lib().psara_status_string(st).decode())
+    return tuple(float(v) for v in out)
+
+
+def psara_set_steps_auto(ctx, margin: float = 0.99):
+    out = np.zeros(4)
+    _check(ctx, lib().psara_set_steps_auto(ctx, float(margin), _dptr(out)))
+    return tuple(float(v) for v in out)
+
+
 def psara_opnorm(ctx, max_iter: int = 500, rtol: float = 1e-10) -> float:
     out = C.c_double()
     _check(ctx, lib().psara_opnorm(ctx, max_iter, rtol, C.byref(out)))
@@ -223,6 +258,10 @@ def psara_solve(ctx, mode: int, iters: int, check_every: int = 0, report: bool =
     rep = PsaraReport()
     _check(ctx, lib().psara_solve(ctx, mode, iters, check_every, C.byref(rep) if report else None))
     return rep.as_dict() if report else None
+
+
+def psara_capture(ctx, mode: int, iters: int, check_every: int = 0) -> None:
+    _check(ctx, lib().psara_capture(ctx, mode, iters, check_every))
 
 
 def psara_solve_adaptive(ctx, mode: int, max_iters: int, check_every: int, stop=PAPER_STOP):
@@ -259,14 +298,6 @@ def psara_set_prior_tv(ctx, tv_weight, l1_weight=None) -> None:
     tw = _f64(np.asarray(tv_weight, dtype=np.float64).reshape(4))
     lw = None if l1_weight is None else _f64(np.asarray(l1_weight, dtype=np.float64).reshape(4))
     _check(ctx, lib().psara_set_prior_tv(ctx, 0 if lw is None else 1, _dptr(tw), _dptr(lw) if lw is not None else None))
-
-
-def tv_step_sizes(phi_norm_sq: float, l1: bool, margin: float = 0.99):
-    """Algorithm 3's step sizes: rho1 = 1 / ||Psi||^2, rho3 = 1, tau from the condition with the
-    data term's Lipschitz constant ||phi||^2 / 2 (rho2 is not used; returned as 1)."""
-    psi2 = 9.0 if l1 else 8.0
-    rho1, rho3 = 1.0 / psi2, 1.0
-    return margin / (phi_norm_sq / 4.0 + rho1 * psi2 + rho3), rho1, 1.0, rho3
 
 
 def psara_set_mueller(ctx, D) -> None:
@@ -458,7 +489,7 @@ def psara_server_create(device: int = 0, hbm_budget: int = 64 << 30, max_slots: 
     srv = C.c_void_p()
     st = lib().psara_server_create(C.byref(srv), device, int(hbm_budget), max_slots, quantum, policy)
     if st != PSARA_OK:
-        raise PsaraError(st, lib().psara_status_string(st).decode())
+        raise _create_error(st)
     return srv
 
 
@@ -508,12 +539,6 @@ def psara_server_destroy(srv) -> None:
 
 
 # ---- convenience wrapper ------------------------------------------------------------------------
-def step_sizes(phi_norm_sq: float, margin: float = 0.99):
-    """rho1 = rho3 = 1, rho2 = 1/||phi||^2, tau = margin/(rho1 + rho2||phi||^2 + rho3) (||Psi|| = 1)."""
-    rho1, rho3, rho2 = 1.0, 1.0, 1.0 / phi_norm_sq
-    return margin / (rho1 + rho2 * phi_norm_sq + rho3), rho1, rho2, rho3
-
-
 def basis_count(mask: int) -> int:
     return bin(mask & 0x1FF).count("1")
 
@@ -555,12 +580,11 @@ class Solver:
         return self.phi_norm_sq
 
     def set_steps(self, tau=None, rho1=None, rho2=None, rho3=None):
+        """The given step sizes, or with none given the library's choice (psara_set_steps_auto)."""
         if tau is None:
-            if getattr(self, "tv_kind", 0):
-                tau, rho1, rho2, rho3 = tv_step_sizes(self.phi_norm_sq, self.tv_kind == 2)
-            else:
-                tau, rho1, rho2, rho3 = step_sizes(self.phi_norm_sq)
+            return psara_set_steps_auto(self.ctx)
         psara_set_steps(self.ctx, tau, rho1, rho2, rho3)
+        return tau, rho1, rho2, rho3
 
     def set_prior_tv(self, tv_weight, l1_weight=None) -> None:
         psara_set_prior_tv(self.ctx, tv_weight, l1_weight)
@@ -569,6 +593,9 @@ class Solver:
 
     def solve(self, mode: int, iters: int, check_every: int = 0, report: bool = True):
         return psara_solve(self.ctx, mode, iters, check_every, report)
+
+    def capture(self, mode: int, iters: int, check_every: int = 0) -> None:
+        psara_capture(self.ctx, mode, iters, check_every)
 
     def reweighted_solve(self, mode: int, iters_per_stage, delta_decay: float = 10.0):
         return psara_reweighted_solve(self.ctx, mode, iters_per_stage, delta_decay)

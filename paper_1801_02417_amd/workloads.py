@@ -265,6 +265,23 @@ def np_study(seed: int = BASE_SEED + 11) -> Workload:
                     iters=2000, cycles=5, truth=S, uv=uv, noise=unit_noise(rng, M))
 
 
+def near_cone(n: int = 32, M: int = 1000, isnr_db: float = 35.0, seed: int = BASE_SEED + 12,
+              stations: int = 6) -> Workload:
+    """Polarization close to the cone: fraction 0.97 at every pixel (chi smooth, V = 0.01 I), so
+    sqrt(Q^2 + U^2 + V^2) sits 3 % below I, with sparse coverage (`stations`-station arcs out to
+    0.9 pi).  Estimates made without the polarization constraint leave the cone on a sizeable
+    share of pixels.  Blobs for n <= 32 (KB 6, 3 levels), ring + jet above (KB 8, 4 levels)."""
+    rng = np.random.default_rng(seed)
+    I = blobs_image(rng, n, 3) if n <= 32 else ring_jet_image(rng, n)
+    chi = 0.5 * math.pi * (2.0 * smooth_field(rng, n) - 1.0)
+    m = 0.97
+    S = np.stack([I, m * I * np.cos(2.0 * chi), m * I * np.sin(2.0 * chi), 0.01 * I], axis=-1)
+    uv = arc_uv(rng, M, stations=stations, max_omega=0.9 * math.pi)
+    small = n <= 32
+    return Workload(f"near_cone{n}", n, M, taps=6 if small else 8, oversample=2, levels=3 if small else 4,
+                    isnr_db=isnr_db, iters=300, cycles=2, truth=S, uv=uv, noise=unit_noise(rng, M))
+
+
 WORKLOADS = {"blobs32": blobs32, "ring128": ring128, "ring256": ring256}
 
 

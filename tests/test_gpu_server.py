@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from gpu_common import say
-from oracle import problem
+from oracle import pd, problem
 from paper_1801_02417_amd import psara as P
 from paper_1801_02417_amd import workloads as wk
 
@@ -35,9 +35,9 @@ def solve_alone(wl, Y, eps, prec):
         P.psara_set_operator(ctx, wl.n, wl.uv, 2, wl.taps, prec)
         P.psara_set_data(ctx, Y, eps)
         P.psara_set_prior(ctx, P.ALL_BASES, wl.levels, None, 1.0)
-        nrm = P.psara_opnorm(ctx, NORM_ITERS, NORM_RTOL)
+        P.psara_opnorm(ctx, NORM_ITERS, NORM_RTOL)
         P.psara_set_gamma(ctx, P.psara_data_gamma(ctx, 1e-3))
-        P.psara_set_steps(ctx, 0.99 / 3.0, 1.0, 1.0 / nrm, 1.0)
+        P.psara_set_steps_auto(ctx, 0.99)
         P.psara_reweighted_solve(ctx, P.PSARA_CONSTRAINED, STAGES, 10.0)
         return P.psara_get_image(ctx, wl.n * wl.n)
     finally:
@@ -103,6 +103,33 @@ def test_data_gamma_matches_oracle():
         P.psara_destroy(ctx)
 
 
+def test_served_fp64_request_matches_oracle():
+    """One served FP64 request (the 32x32 blob workload, Algorithm 2 with 100 + 100 + 100
+    iterations) against the oracle's Algorithm 2 on the same data: the server computes its own
+    ||phi||^2 (power iteration to 1e-13) and data-driven gamma, the oracle its own (to 1e-12), so
+    the two runs share the step sizes and gamma to about 1e-12."""
+    wl = wk.blobs32()
+    b = problem.build(wl)
+    stages = pd.split_iterations(wl.iters, wl.cycles + 1)
+    ref, _, _ = pd.alg2(b.pb, b.gamma, stages, len(stages) - 1)
+    srv = P.psara_server_create(0, 8 << 30, 4, 25)
+    try:
+        t = P.psara_server_submit(srv, wl.n, wl.uv, b.pb.Y, b.pb.eps, taps=wl.taps, levels=wl.levels,
+                                  precision=P.PSARA_FP64, iters_per_stage=stages, opnorm_iters=2000,
+                                  opnorm_rtol=1e-13)
+        P.psara_server_drain(srv)
+        img = np.empty((wl.n * wl.n, 4))
+        r = P.psara_server_poll(srv, t, img)
+        assert r["state"] == P.PSARA_REQ_DONE, (r, P.lib().psara_server_last_error(srv))
+    finally:
+        P.psara_server_destroy(srv)
+    errs = [float(np.linalg.norm(img[:, i] - ref.S[:, i]) / np.linalg.norm(ref.S[:, i])) for i in range(4)]
+    say(f"served FP64 request vs oracle: per-Stokes rel err {['%.2e' % e for e in errs]}; "
+        f"iterations {r['report']['iterations']}")
+    assert r["report"]["iterations"] == sum(stages)
+    assert max(errs) <= 1e-9
+
+
 def test_bad_request_rejected():
     srv = P.psara_server_create(0, 1 << 30, 4, 5)
     try:
@@ -128,9 +155,9 @@ def solve_alone_adaptive(wl, Y, eps, prec):
         P.psara_set_operator(ctx, wl.n, wl.uv, 2, wl.taps, prec)
         P.psara_set_data(ctx, Y, eps)
         P.psara_set_prior(ctx, P.ALL_BASES, wl.levels, None, 1.0)
-        nrm = P.psara_opnorm(ctx, NORM_ITERS, NORM_RTOL)
+        P.psara_opnorm(ctx, NORM_ITERS, NORM_RTOL)
         P.psara_set_gamma(ctx, P.psara_data_gamma(ctx, 1e-3))
-        P.psara_set_steps(ctx, 0.99 / 3.0, 1.0, 1.0 / nrm, 1.0)
+        P.psara_set_steps_auto(ctx, 0.99)
         its, rep = P.psara_reweighted_solve_adaptive(ctx, P.PSARA_CONSTRAINED, 2, ADAPT_BOUND, ADAPT_CHECK,
                                                      ADAPT_STOP, 10.0)
         return P.psara_get_image(ctx, wl.n * wl.n), rep["iterations"]

@@ -91,3 +91,48 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[name]) == C.sizeof(cls), name
         for f in fields:
             assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def test_step_size_rule_matches_the_readings():
+    """psara_step_sizes: Algorithm 1's choice (rho1 = rho3 = 1, rho2 = 1/||phi||^2) and
+    Algorithm 3's (rho1 = 1/||Psi||^2, rho3 = 1) equal the oracle's, and tau sits at `margin` of
+    the bound of the convergence condition of Sec. 3.3.3."""
+    from oracle import pd, tv
+    for nrm in (1.0, 973290.07, 3.5e7):
+        tau, r1, r2, r3 = P.psara_step_sizes(0, nrm, 0.99)
+        assert np.allclose((tau, r1, r2, r3), pd.step_sizes(nrm), rtol=1e-15, atol=0)
+        assert abs(tau * (r1 + r2 * nrm + r3) - 0.99) < 1e-15
+        for prior, kind in ((1, "tv"), (2, "l1tv")):
+            tau, r1, r2, r3 = P.psara_step_sizes(prior, nrm, 0.99)
+            ot, o1, o3 = tv.step_sizes(nrm / 2.0, kind)
+            assert np.allclose((tau, r1, r3), (ot, o1, o3), rtol=1e-15, atol=0)
+            assert abs(tau * (nrm / 4.0 + r1 * tv.PSI_NORM_SQ[kind] + r3) - 0.99) < 1e-15
+    for bad in ((0, 0.0, 0.99), (0, 1.0, 0.0), (0, 1.0, 1.5), (3, 1.0, 0.99), (0, float("nan"), 0.99)):
+        with pytest.raises(P.PsaraError):
+            P.psara_step_sizes(*bad)
+
+
+def _runtime_check_in_child(import_torch_first: bool):
+    import json
+    import subprocess
+    import sys
+    code = ("import json, sys\n"
+            + ("import torch\n" if import_torch_first else "")
+            + f"sys.path.insert(0, {ROOT!r})\n"
+            "from paper_1801_02417_amd import psara as P\n"
+            "print(json.dumps(P.psara_runtime_check()))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def test_runtime_check_detects_a_foreign_hip_runtime():
+    """The library runs on the HIP runtime it is built for in a process that has not loaded
+    another one; a process that imports torch first binds it to torch's bundled runtime, which
+    psara_runtime_check reports (psara_create then refuses with PSARA_EDEVICE)."""
+    st, built, running = _runtime_check_in_child(False)
+    assert st == P.PSARA_OK and built // 100000 == running // 100000, (built, running)
+    st, built, running = _runtime_check_in_child(True)
+    if running // 100000 == built // 100000:
+        pytest.skip(f"torch bundles the same HIP runtime version ({running})")
+    assert st == P.PSARA_EDEVICE

@@ -185,6 +185,19 @@ psara_status psara_opnorm(psara_ctx* ctx, int max_iter, double rtol, double* phi
 psara_status psara_solve(psara_ctx* ctx, psara_mode mode, int iters, int check_every,
                          psara_report* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * that forbid allocation): psara_solve(ctx, mode, iters, 0, NULL) by direct kernel launches
+ * (no graph is captured or instantiated), with the iteration's scratch buffers -- the gridding
+ * partial slots and the FP64 partial sums -- in a static device array of the library (32 MiB,
+ * held on every device the library runs on until the process ends) instead of the context's
+ * own; no device memory is allocated or freed.  The resulting state is bit for bit that of
+ * psara_solve.  PSARA_EINVAL when the problem needs more scratch than the array holds (the
+ * slots take (16 + taps - 1)^2 cells of 8 reals per gridding chunk: about 14 MiB for a 256 x 256
+ * image with 2e5 rows in FP32, twice that in FP64).  Every call on one device shares that
+ * device's array: calls that overlap on one device (from several threads, or on several
+ * contexts' streams at once) race.  Blocks until the iterations are done. */
+psara_status psara_solve_noalloc(psara_ctx* ctx, psara_mode mode, int iters);
+
 /* Capture, without running anything, the HIP graphs that psara_solve(ctx, mode, iters,
  * check_every, ...) replays; a solve captures the graphs it lacks itself, so this only moves
  * that work ahead of a timed or latency-critical call.  A solve of `iters` iterations replays

@@ -5,7 +5,9 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -449,6 +451,47 @@ psara_status psara_opnorm(psara_ctx* c, int max_iter, double rtol, double* phi_n
 
 psara_status psara_solve(psara_ctx* c, psara_mode mode, int iters, int check_every, psara_report* out) {
   return guard(c, [&] { run_stage(c, solve_mode(c, mode), iters, check_every, out); });
+}
+
+// ---- the allocation-free iteration ------------------------------------------------------------
+// The iteration's scratch buffers (gridding partial slots and FP64 partial sums) of
+// psara_solve_noalloc live in this array, one copy per device for the life of the process.  In
+// host code `scratch` names a host-side stand-in, not device memory: its device address comes
+// from hipGetSymbolAddress, once per device, and only that address is handed to kernels.
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;      // device ordinal -> address of `scratch` on it
+
+// The current device's copy of `scratch` (the caller has made `device` current).
+void* scratch_on(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(PSARA_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch_addr[device] = p;
+  return p;
+}
+}  // namespace
+
+psara_status psara_solve_noalloc(psara_ctx* c, psara_mode mode, int iters) {
+  return guard(c, [&] {
+    const int pm = solve_mode(c, mode);
+    require(c->op_set && c->data_set, PSARA_ESTATE, "operator and data must be set before solving");
+    require(c->steps_set, PSARA_ESTATE, "step sizes must be set before solving");
+    require(pm == psara::PM_INIT || c->prior_set, PSARA_ESTATE, "prior must be set for this mode");
+    require(iters >= 0, PSARA_EINVAL, "iters must be >= 0");
+    void* scr = scratch_on(c->device);
+    with_engine(c, [&](auto& e) { e.run_in_scratch(pm, iters, scr, kNoallocScratchBytes); });
+    c->iterations += iters;
+  });
 }
 
 psara_status psara_capture(psara_ctx* c, psara_mode mode, int iters, int check_every) {

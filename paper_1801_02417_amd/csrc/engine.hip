@@ -809,6 +809,49 @@ void Engine<R>::run(int mode, int iters) {
 }
 
 template <typename R>
+size_t Engine<R>::scratch_bytes() const {
+  const size_t rg = kGridTile + geo_.T - 1;
+  const size_t slots = (size_t)std::max(geo_.n_slots, 1) * rg * rg * sizeof(Cell<R>);
+  const size_t parts = 2 * ((size_t)h_.n_p6 + (size_t)kGenQ * h_.gen_stride + (size_t)h_.n_slots) * sizeof(double);
+  return ((slots + 255) & ~(size_t)255) + parts;
+}
+
+template <typename R>
+void Engine<R>::run_in_scratch(int mode, int iters, void* scr, size_t cap) {
+  const size_t need = scratch_bytes();
+  if (need > cap)
+    throw Error(PSARA_EINVAL, "this problem needs " + std::to_string(need) + " bytes of iteration scratch, more than the " +
+                                  std::to_string(cap) + " the allocation-free entry point holds");
+  sync_desc();
+  void* own_gpart = h_.gpart;
+  double* own_partials = h_.partials;
+  const size_t rg = kGridTile + geo_.T - 1;
+  const size_t slots = (size_t)std::max(geo_.n_slots, 1) * rg * rg * sizeof(Cell<R>);
+  h_.gpart = scr;
+  h_.partials = (double*)((unsigned char*)scr + ((slots + 255) & ~(size_t)255));
+  desc_dirty_ = true;
+  try {
+    sync_desc();
+    // every pass writes the slots and partial sums it reads later in the same iteration; the
+    // partial sums are cleared anyway, by a kernel (so the call records no memset node when a
+    // caller captures it)
+    launch_fill<double>(h_.partials, (need - ((slots + 255) & ~(size_t)255)) / sizeof(double), s0_);
+    if (iters > 0) prime(mode);
+    launch_iterations(mode, iters);
+    hip_check(hipGetLastError(), "iteration launch");
+  } catch (...) {
+    h_.gpart = own_gpart;
+    h_.partials = own_partials;
+    desc_dirty_ = true;
+    throw;
+  }
+  h_.gpart = own_gpart;
+  h_.partials = own_partials;
+  desc_dirty_ = true;
+  sync_desc();          // queued after the iterations; waits for them
+}
+
+template <typename R>
 void Engine<R>::run_eager(int mode, int iters) {
   sync_desc();
   if (iters > 0) prime(mode);

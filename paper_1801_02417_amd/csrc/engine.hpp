@@ -108,6 +108,13 @@ struct Engine {
   void zero_state();
   void run(int mode, int iters);          // graph replay
   void capture(int mode, int iters);      // capture the graphs run(mode, iters) replays (no work launched)
+  // Bytes of the iteration's scratch buffers: the gridding partial slots, then (at a 256-byte
+  // boundary) the FP64 partial sums.
+  size_t scratch_bytes() const;
+  // `iters` iterations by direct launches with those buffers in caller-provided device memory
+  // (scr, at least scratch_bytes()), allocating nothing; the context's own buffers are used
+  // again afterwards.  Returns when the iterations are done.
+  void run_in_scratch(int mode, int iters, void* scr, size_t cap);
   void run_eager(int mode, int iters);    // direct launches
   // Up to max_iters iterations, checking the stopping criteria stop = {theta, rel_var, np_max}
   // on the device after every check_every of them; returns the iterations run.

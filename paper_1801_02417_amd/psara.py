@@ -36,7 +36,7 @@ EXPORTS = (
     "psara_set_gamma", "psara_set_mueller", "psara_set_prior_tv", "psara_solve_adaptive", "psara_reweighted_solve_adaptive", "psara_batch_solve_adaptive",
     "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
     "psara_server_clock", "psara_server_last_error", "psara_server_destroy", "psara_runtime_check",
-    "psara_step_sizes", "psara_set_steps_auto", "psara_capture",
+    "psara_step_sizes", "psara_set_steps_auto", "psara_capture", "psara_solve_noalloc",
 )
 
 PSARA_SERVE_BATCHED, PSARA_SERVE_FIFO = 0, 1
@@ -107,6 +107,7 @@ def lib() -> C.CDLL:
         "psara_step_sizes": (I, [I, C.c_double, C.c_double, D]),
         "psara_set_steps_auto": (I, [P, C.c_double, D]),
         "psara_capture": (I, [P, I, I, I]),
+        "psara_solve_noalloc": (I, [P, I, I]),
         "psara_opnorm": (I, [P, I, C.c_double, D]),
         "psara_solve": (I, [P, I, I, I, C.POINTER(PsaraReport)]),
         "psara_set_mueller": (I, [P, D]),
@@ -258,6 +259,10 @@ def psara_solve(ctx, mode: int, iters: int, check_every: int = 0, report: bool =
     rep = PsaraReport()
     _check(ctx, lib().psara_solve(ctx, mode, iters, check_every, C.byref(rep) if report else None))
     return rep.as_dict() if report else None
+
+
+def psara_solve_noalloc(ctx, mode: int, iters: int) -> None:
+    _check(ctx, lib().psara_solve_noalloc(ctx, mode, iters))
 
 
 def psara_capture(ctx, mode: int, iters: int, check_every: int = 0) -> None:

@@ -258,8 +258,9 @@ def served_form(P, wk, count: int, rate: float, stages, budget_gb: float) -> dic
 
 
 def served_in_child(args) -> dict:
-    """The served form in a child process (its progress lines go to this process's stderr), so
-    that a failure of the request server cannot take the rest of the benchmark line with it."""
+    """The served form in a child process (its progress lines go to this process's stderr).  If
+    the child fails, the line still carries the other forms, records the failure under
+    served_form["error"], and bench.py exits with a non-zero status."""
     cmd = [sys.executable, os.path.abspath(__file__), "--served-only", "--serve-requests", str(args.serve_requests),
            "--serve-budget-gb", str(args.serve_budget_gb)]
     try:
@@ -374,23 +375,23 @@ def progress(msg: str) -> None:
 
 
 def np_study(P, wk) -> dict:
-    """The synthetic analogue of the paper's polarization-error table: a 128x128 ring + jet with
-    polarization fraction up to 0.95, 6-station coverage (6000 rows), 30 dB, solved with the
-    full schedule (initialisation and five reweighting cycles, 2000 iterations) with and
-    without the polarization constraint; N_p is the share of pixels whose polarized intensity
-    exceeds I by more than zeta."""
-    wl = wk.np_study()
-    out = {"workload": "128x128, polarization fraction <= 0.95, 6 stations, 6000 visibilities, 30 dB, "
+    """The synthetic analogue of the paper's polarization-error table (Table 2, Sec. 4.2): a
+    32x32 blob image with polarization fraction 0.97 at every pixel (close to the cone), sparse
+    6-station arcs (1000 rows), 35 dB, solved with the full schedule (initialisation and five
+    reweighting cycles, 2000 iterations) with and without the polarization constraint; N_p is
+    the share of pixels whose polarized intensity exceeds I by more than zeta."""
+    wl = wk.near_cone()
+    out = {"workload": "32x32 blobs, polarization fraction 0.97, 6-station arcs, 1000 visibilities, 35 dB, "
                        "2000 iterations (initialisation + 5 cycles)"}
-    stages = [wl.iters // (wl.cycles + 1)] * wl.cycles
-    stages.append(wl.iters - sum(stages))
+    stages = [2000 // 6] * 5
+    stages.append(2000 - sum(stages))
+    truth = wl.truth.reshape(-1, 4)
     for name, mode in (("with_constraint", P.PSARA_CONSTRAINED), ("without_constraint", P.PSARA_UNCONSTRAINED)):
         s, _, _ = ready_solver(P, wl)
         rep = s.reweighted_solve(mode, stages)
         img = s.image()
-        truth = wl.truth.reshape(-1, 4)
         out[name] = {"n_p_percent": round(rep["n_p"], 3), "snr_db": round(snr_db(img, truth), 3),
-                     "snr_I_db": round(snr_db(img[:, 0], truth[:, 0]), 3),
+                     "snr_per_stokes_db": [round(snr_db(img[:, i], truth[:, i]), 3) for i in range(4)],
                      "residual_over_eps": round(rep["residual"] / rep["epsilon"], 6)}
         s.close()
     return out
@@ -403,14 +404,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--profile-iters", type=int, default=50)
-    ap.add_argument("--cpu-iters", type=int, default=64)
+    ap.add_argument("--cpu-iters", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-solves", type=int, default=64, help="solves of the batched form (0: skip)")
-    # the served form is off by default: two of its runs ended with a host crash in a server
-    # thread whose cause is not known yet (see the design notes); 120 is the stream measured
-    ap.add_argument("--serve-requests", type=int, default=0,
-                    help="requests of the served form at 20/s (0: skip, the default; 120 is the stream measured, "
-                         "1200 the full 60 s stream)")
+    ap.add_argument("--serve-requests", type=int, default=120,
+                    help="requests of the served form at 20/s (0: skip; 1200 is the full 60 s stream)")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-np-study", action="store_true")
     ap.add_argument("--large-iters", type=int, default=400,
@@ -459,6 +457,7 @@ def main() -> int:
         print(json.dumps(served_form(P, wk, args.serve_requests, 20.0, [100, 100, 100], args.serve_budget_gb)),
               flush=True)
         return 0
+    status = 0
     wl = wk.ring256()
     n, M, N = wl.n, wl.M, wl.n * wl.n
     s = P.Solver(n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED)
@@ -542,7 +541,7 @@ def main() -> int:
     s.close()
     progress(f"256x256 / 2e5-visibility iteration rate {its:.1f} iters/s")
     if not args.no_np_study:
-        progress("polarization-error study (128x128 ring + jet, with / without the constraint)")
+        progress("polarization-error study (32x32 near-cone blobs, with / without the constraint)")
         line["np_study"] = np_study(P, wk)
     if args.large_iters > 0:
         progress("large form: 512x512, 1e6 visibilities")
@@ -561,11 +560,13 @@ def main() -> int:
         progress(f"served form: {args.serve_requests} requests at 20/s")
         line["served_form"] = served_in_child(args)
         progress("served form done")
+        if "error" in line["served_form"]:
+            status = 1
     if not args.no_cpu_baseline:
         progress("oracle CPU baseline")
         line["cpu_baseline"] = cpu_baseline(args.cpu_iters)
     print(json.dumps(line), flush=True)
-    return 0
+    return status
 
 
 if __name__ == "__main__":

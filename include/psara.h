@@ -356,16 +356,17 @@ psara_status psara_batch_profile_passes(psara_ctx* const* ctxs, int count, psara
 /* A server owns one GPU and solves submitted problems (Algorithm 2, each request with its own
  * operator, data and stage list) with continuous batching: requests are admitted while the sum
  * of their psara_footprint stays within the HBM budget (a request larger than the budget runs
- * when nothing else does; nothing is rejected for size), set up by host threads while the GPU
- * works, and every admitted request advances in one batched launch per pass (grouped by
- * stage mode, precision and tap count) in rounds of at most `quantum` iterations; a request
- * leaves the batch at each stage end for its reweighting and rejoins.  Policy
- * PSARA_SERVE_FIFO instead runs one request at a time in arrival order.  Each result equals
- * the same request solved alone with psara_* calls in the order the server uses (operator,
- * data, prior with gamma 1, opnorm, data gamma, psara_set_steps_auto with margin 0.99, then
- * psara_reweighted_solve, or psara_reweighted_solve_adaptive for a request with check_every > 0:
- * such a request leaves the batch as soon as its stage's criteria hold on the device).
- * Thread-safe for submit and poll. */
+ * when nothing else does; one larger than the device's whole memory is refused at submission
+ * with PSARA_ENOMEM), set up by host threads while the GPU works, and every admitted request
+ * advances in one batched launch per pass (grouped by stage mode, precision, tap count, image
+ * side and check interval) in rounds of at most `quantum` iterations; a request leaves the
+ * batch at each stage end for its reweighting and rejoins.  Policy PSARA_SERVE_FIFO instead runs
+ * one request at a time in arrival order.  Each result equals the same request solved alone
+ * with psara_* calls in the order the server uses (operator, data, prior with gamma 1, opnorm,
+ * data gamma, psara_set_steps_auto with margin 0.99, then psara_reweighted_solve, or
+ * psara_reweighted_solve_adaptive for a request with check_every > 0: such a request leaves the
+ * batch as soon as its stage's criteria hold on the device).  Thread-safe for submit, poll and
+ * cancel. */
 typedef struct psara_server psara_server;
 
 typedef enum { PSARA_SERVE_BATCHED = 0, PSARA_SERVE_FIFO = 1 } psara_serve_policy;
@@ -394,7 +395,8 @@ typedef struct {
   psara_stop stop;             /* stopping criteria when check_every > 0 */
 } psara_request;
 
-typedef enum { PSARA_REQ_QUEUED = 0, PSARA_REQ_RUNNING = 1, PSARA_REQ_DONE = 2, PSARA_REQ_FAILED = 3 } psara_req_state;
+typedef enum { PSARA_REQ_QUEUED = 0, PSARA_REQ_RUNNING = 1, PSARA_REQ_DONE = 2, PSARA_REQ_FAILED = 3,
+               PSARA_REQ_CANCELLED = 4 } psara_req_state;
 
 typedef struct {
   int state;                   /* psara_req_state */
@@ -408,17 +410,26 @@ typedef struct {
  * max_slots >= 1: most requests in flight; quantum >= 1: iterations per batched round. */
 psara_status psara_server_create(psara_server** out, int device, size_t hbm_budget, int max_slots,
                                  int quantum, psara_serve_policy policy);
-/* Queue a request (its arrays are copied before return); ticket receives its id. */
+/* Queue a request (its arrays are copied before return); ticket receives its id.  PSARA_EINVAL
+ * for a malformed request, PSARA_ENOMEM when its footprint exceeds the device's total memory
+ * (it could never be admitted); the message is in psara_server_last_error. */
 psara_status psara_server_submit(psara_server* srv, const psara_request* req, uint64_t* ticket);
+/* Cancel a request: a queued one is removed at once, a running one at the worker's next step
+ * (the end of the round in flight), which releases its device state, slot and footprint so
+ * that queued requests can be admitted.  Its state becomes PSARA_REQ_CANCELLED (forgotten on
+ * the first poll that reports it).  PSARA_EINVAL for an unknown ticket, PSARA_ESTATE when the
+ * request has already ended. */
+psara_status psara_server_cancel(psara_server* srv, uint64_t ticket);
 /* State of a request.  When it is done and `image` is not NULL, the image (n*n x 4 doubles,
  * Stokes I, Q, U, V) is copied there and the request is forgotten (a later poll of the ticket
- * returns PSARA_EINVAL); a failed request is forgotten on the first poll that reports it. */
+ * returns PSARA_EINVAL); a failed or cancelled request is forgotten on the first poll that
+ * reports it. */
 psara_status psara_server_poll(psara_server* srv, uint64_t ticket, psara_result* out, double* image);
-/* Block until every submitted request is done or failed. */
+/* Block until every submitted request has ended (done, failed or cancelled). */
 psara_status psara_server_drain(psara_server* srv);
 /* Seconds since the server was created (the clock of psara_result). */
 double psara_server_clock(const psara_server* srv);
-/* Message of the last failed request or call. */
+/* Message of the last failed request or call (valid until the next call of this function). */
 const char* psara_server_last_error(const psara_server* srv);
 /* Stops the threads after the running round and frees every context (pending requests are
  * dropped). */

@@ -10,16 +10,11 @@
 #include <vector>
 
 #include "common.hpp"
+#include "error.hpp"
 #include "launch.hpp"
 #include "psara.h"
 
 namespace psara {
-
-struct Error {
-  psara_status status;
-  std::string msg;
-  Error(psara_status s, std::string m) : status(s), msg(std::move(m)) {}
-};
 
 void hip_check(hipError_t e, const char* what);
 

@@ -36,11 +36,11 @@ EXPORTS = (
     "psara_set_gamma", "psara_set_mueller", "psara_set_prior_tv", "psara_solve_adaptive", "psara_reweighted_solve_adaptive", "psara_batch_solve_adaptive",
     "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
     "psara_server_clock", "psara_server_last_error", "psara_server_destroy", "psara_runtime_check",
-    "psara_step_sizes", "psara_set_steps_auto", "psara_capture", "psara_solve_noalloc",
+    "psara_step_sizes", "psara_set_steps_auto", "psara_capture", "psara_solve_noalloc", "psara_server_cancel",
 )
 
 PSARA_SERVE_BATCHED, PSARA_SERVE_FIFO = 0, 1
-PSARA_REQ_QUEUED, PSARA_REQ_RUNNING, PSARA_REQ_DONE, PSARA_REQ_FAILED = 0, 1, 2, 3
+PSARA_REQ_QUEUED, PSARA_REQ_RUNNING, PSARA_REQ_DONE, PSARA_REQ_FAILED, PSARA_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
 class PsaraReport(C.Structure):
@@ -146,6 +146,7 @@ def lib() -> C.CDLL:
         "psara_server_submit": (I, [P, C.POINTER(PsaraRequest), C.POINTER(C.c_uint64)]),
         "psara_server_poll": (I, [P, C.c_uint64, C.POINTER(PsaraResult), D]),
         "psara_server_drain": (I, [P]),
+        "psara_server_cancel": (I, [P, C.c_uint64]),
         "psara_server_clock": (C.c_double, [P]),
         "psara_server_last_error": (C.c_char_p, [P]),
         "psara_server_destroy": (None, [P]),
@@ -529,6 +530,10 @@ def psara_server_poll(srv, ticket: int, image: Optional[np.ndarray] = None) -> d
     _server_check(srv, lib().psara_server_poll(srv, C.c_uint64(ticket), C.byref(res), ptr))
     return {"state": res.state, "status": res.status, "t_submit": res.t_submit, "t_start": res.t_start,
             "t_done": res.t_done, "n": res.n, "report": res.report.as_dict()}
+
+
+def psara_server_cancel(srv, ticket: int) -> None:
+    _server_check(srv, lib().psara_server_cancel(srv, C.c_uint64(ticket)))
 
 
 def psara_server_drain(srv) -> None:

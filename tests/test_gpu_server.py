@@ -130,6 +130,61 @@ def test_served_fp64_request_matches_oracle():
     assert max(errs) <= 1e-9
 
 
+def test_cancel_frees_the_slot():
+    """One slot: a long request runs, a second waits; cancelling the running one ends it at the
+    next round and the second is admitted and completes; a queued request cancels at once."""
+    srv = P.psara_server_create(0, 8 << 30, 1, 5)
+    try:
+        reqs = requests()
+        (wa, ya, ea), (wb, yb, eb), (wc, yc, ec) = reqs[2], reqs[0], reqs[1]
+        ta = P.psara_server_submit(srv, wa.n, wa.uv, ya, ea, taps=wa.taps, levels=wa.levels,
+                                   iters_per_stage=(200000, 10, 10), opnorm_iters=NORM_ITERS, opnorm_rtol=NORM_RTOL)
+        for _ in range(20000):
+            if P.psara_server_poll(srv, ta)["state"] == P.PSARA_REQ_RUNNING:
+                break
+            time.sleep(0.001)
+        tb = P.psara_server_submit(srv, wb.n, wb.uv, yb, eb, taps=wb.taps, levels=wb.levels,
+                                   iters_per_stage=STAGES, opnorm_iters=NORM_ITERS, opnorm_rtol=NORM_RTOL)
+        tc = P.psara_server_submit(srv, wc.n, wc.uv, yc, ec, taps=wc.taps, levels=wc.levels,
+                                   iters_per_stage=STAGES, opnorm_iters=NORM_ITERS, opnorm_rtol=NORM_RTOL)
+        P.psara_server_cancel(srv, tc)
+        assert P.psara_server_poll(srv, tc)["state"] == P.PSARA_REQ_CANCELLED
+        assert P.psara_server_poll(srv, tb)["state"] == P.PSARA_REQ_QUEUED
+        time.sleep(0.2)
+        P.psara_server_cancel(srv, ta)
+        P.psara_server_drain(srv)
+        assert P.psara_server_poll(srv, ta)["state"] == P.PSARA_REQ_CANCELLED
+        img = np.empty((wb.n * wb.n, 4))
+        r = P.psara_server_poll(srv, tb, img)
+        assert r["state"] == P.PSARA_REQ_DONE and r["report"]["iterations"] == sum(STAGES)
+        assert np.array_equal(img, solve_alone(wb, yb, eb, P.PSARA_FP32_MIXED))
+        with pytest.raises(P.PsaraError):
+            P.psara_server_cancel(srv, tb)         # collected: unknown ticket
+    finally:
+        P.psara_server_destroy(srv)
+
+
+def test_request_larger_than_the_device_is_refused():
+    """A request whose footprint exceeds the device's memory is refused with PSARA_ENOMEM at
+    submission (before its arrays are read: they hold 16 rows of the 2^31 - 1 declared)."""
+    import ctypes as C
+    srv = P.psara_server_create(0, 8 << 30, 4, 5)
+    try:
+        M = (1 << 31) - 1
+        assert P.psara_footprint(1024, M, 8, 4, P.ALL_BASES, P.PSARA_FP64) > 300 << 30
+        uv = np.zeros((16, 2))
+        y = np.zeros((16, 8))
+        stages = (C.c_int * 3)(10, 10, 10)
+        req = P.PsaraRequest(1024, M, P._dptr(uv), P._dptr(y), 1.0, 8, 4, P.ALL_BASES, P.PSARA_FP64,
+                             P.PSARA_CONSTRAINED, 2, stages, 10.0, 1e-3, 10, 1e-3, 0, P.PsaraStop(0.0, 0.0, 0.0))
+        ticket = C.c_uint64()
+        st = P.lib().psara_server_submit(srv, C.byref(req), C.byref(ticket))
+        assert st == P.PSARA_ENOMEM, st
+        assert b"device memory" in P.lib().psara_server_last_error(srv)
+    finally:
+        P.psara_server_destroy(srv)
+
+
 def test_bad_request_rejected():
     srv = P.psara_server_create(0, 1 << 30, 4, 5)
     try:

@@ -376,15 +376,15 @@ def progress(msg: str) -> None:
 
 def np_study(P, wk) -> dict:
     """The synthetic analogue of the paper's polarization-error table (Table 2, Sec. 4.2): a
-    32x32 blob image with polarization fraction 0.97 at every pixel (close to the cone), sparse
-    6-station arcs (1000 rows), 35 dB, solved with the full schedule (initialisation and five
-    reweighting cycles, 2000 iterations) with and without the polarization constraint; N_p is
-    the share of pixels whose polarized intensity exceeds I by more than zeta."""
-    wl = wk.near_cone()
-    out = {"workload": "32x32 blobs, polarization fraction 0.97, 6-station arcs, 1000 visibilities, 35 dB, "
+    64x64 image of six blobs with polarization fraction 0.97 at every pixel (close to the cone),
+    sparse 6-station arcs (8000 rows), 40 dB, solved with the full schedule (initialisation and
+    five reweighting cycles, 2000 iterations) with and without the polarization constraint; N_p
+    is the share of pixels whose polarized intensity exceeds I by more than zeta."""
+    wl = wk.np_study()
+    out = {"workload": "64x64, six blobs, polarization fraction 0.97, 6-station arcs, 8000 visibilities, 40 dB, "
                        "2000 iterations (initialisation + 5 cycles)"}
-    stages = [2000 // 6] * 5
-    stages.append(2000 - sum(stages))
+    stages = [wl.iters // (wl.cycles + 1)] * wl.cycles
+    stages.append(wl.iters - sum(stages))
     truth = wl.truth.reshape(-1, 4)
     for name, mode in (("with_constraint", P.PSARA_CONSTRAINED), ("without_constraint", P.PSARA_UNCONSTRAINED)):
         s, _, _ = ready_solver(P, wl)
@@ -541,7 +541,7 @@ def main() -> int:
     s.close()
     progress(f"256x256 / 2e5-visibility iteration rate {its:.1f} iters/s")
     if not args.no_np_study:
-        progress("polarization-error study (32x32 near-cone blobs, with / without the constraint)")
+        progress("polarization-error study (64x64 near-cone blobs, with / without the constraint)")
         line["np_study"] = np_study(P, wk)
     if args.large_iters > 0:
         progress("large form: 512x512, 1e6 visibilities")

@@ -254,25 +254,15 @@ def tiny(n: int = 16, M: int = 150, taps: int = 6, levels: int = 2, seed: int = 
                     iters=300, cycles=2, truth=S, uv=uv, noise=unit_noise(rng, M))
 
 
-def np_study(seed: int = BASE_SEED + 11) -> Workload:
-    """The polarization-error study: 128x128 ring+jet with polarization fraction up to 0.95 (close
-    to the cone), sparse coverage from 6 stations (6000 rows), 30 dB, 2000 iterations."""
-    rng = np.random.default_rng(seed)
-    n, M = 128, 6000
-    S = add_polarisation(rng, ring_jet_image(rng, n), 0.95)
-    uv = arc_uv(rng, M, stations=6)
-    return Workload("np_study", n, M, taps=8, oversample=2, levels=4, isnr_db=30.0,
-                    iters=2000, cycles=5, truth=S, uv=uv, noise=unit_noise(rng, M))
-
-
 def near_cone(n: int = 32, M: int = 1000, isnr_db: float = 35.0, seed: int = BASE_SEED + 12,
-              stations: int = 6) -> Workload:
-    """Polarization close to the cone: fraction 0.97 at every pixel (chi smooth, V = 0.01 I), so
-    sqrt(Q^2 + U^2 + V^2) sits 3 % below I, with sparse coverage (`stations`-station arcs out to
-    0.9 pi).  Estimates made without the polarization constraint leave the cone on a sizeable
-    share of pixels.  Blobs for n <= 32 (KB 6, 3 levels), ring + jet above (KB 8, 4 levels)."""
+              stations: int = 6, blobs: int = 3) -> Workload:
+    """Polarization close to the cone: Gaussian blobs with polarization fraction 0.97 at every
+    pixel (chi smooth, V = 0.01 I), so sqrt(Q^2 + U^2 + V^2) sits 3 % below I, with sparse
+    coverage (`stations`-station arcs out to 0.9 pi).  Estimates made without the polarization
+    constraint leave the cone on a sizeable share of pixels.  KB 6 and 3 levels for n <= 32,
+    KB 8 and 4 levels above."""
     rng = np.random.default_rng(seed)
-    I = blobs_image(rng, n, 3) if n <= 32 else ring_jet_image(rng, n)
+    I = blobs_image(rng, n, blobs)
     chi = 0.5 * math.pi * (2.0 * smooth_field(rng, n) - 1.0)
     m = 0.97
     S = np.stack([I, m * I * np.cos(2.0 * chi), m * I * np.sin(2.0 * chi), 0.01 * I], axis=-1)
@@ -280,6 +270,14 @@ def near_cone(n: int = 32, M: int = 1000, isnr_db: float = 35.0, seed: int = BAS
     small = n <= 32
     return Workload(f"near_cone{n}", n, M, taps=6 if small else 8, oversample=2, levels=3 if small else 4,
                     isnr_db=isnr_db, iters=300, cycles=2, truth=S, uv=uv, noise=unit_noise(rng, M))
+
+
+def np_study(seed: int = BASE_SEED + 13) -> Workload:
+    """The polarization-error study: 64x64, six blobs at polarization fraction 0.97, 6-station
+    arcs with 8000 rows, 40 dB, solved over 2000 iterations (initialisation + 5 cycles)."""
+    wl = near_cone(n=64, M=8000, isnr_db=40.0, seed=seed, stations=6, blobs=6)
+    wl.name, wl.iters, wl.cycles = "np_study", 2000, 5
+    return wl
 
 
 WORKLOADS = {"blobs32": blobs32, "ring128": ring128, "ring256": ring256}

@@ -161,11 +161,19 @@ def ready_solver(P, wl, norm_iters=200, norm_rtol=1e-6):
 
 def batched_form(P, wk, count: int, stages) -> dict:
     """64 uneven solves (sides {64,128,256}, M log-uniform in [1e3, 1e5], ISNR 15-35 dB) run as one
-    batch (every pass one launch over all solves, graph-replayed) and one after another."""
+    batch (every pass one launch over all solves, graph-replayed) with the default launch shapes
+    and with the autotuner's choice for the batch, and one after another (with the same shapes)."""
     wls = [wk.batch_request(i) for i in range(count)]
     solvers = [ready_solver(P, wl)[0] for wl in wls]
     for s in solvers:
         s.synchronize()
+    # the batch with the default launch shapes, then with the autotuner's choice for the batch
+    for s in solvers:
+        s.reset()
+    t0 = time.perf_counter()
+    P.batch_reweighted_solve(solvers, P.PSARA_CONSTRAINED, stages)
+    t_default = time.perf_counter() - t0
+    chosen, tune_ms = P.batch_autotune(solvers, P.PSARA_CONSTRAINED)
     for s in solvers:
         s.reset()
     t0 = time.perf_counter()
@@ -191,6 +199,10 @@ def batched_form(P, wk, count: int, stages) -> dict:
         s.close()
     its = count * sum(stages)
     return {"solves": count, "iters_per_solve": sum(stages), "sides": sorted({wl.n for wl in wls}),
+            "tuning": {"chosen": chosen, "trial_ms_per_iter_default": round(tune_ms[0], 5),
+                       "trial_ms_per_iter_chosen": round(tune_ms[1], 5),
+                       "default_shapes": {"iters_per_s": round(its / t_default, 1),
+                                          "solves_per_s": round(count / t_default, 2)}},
             "batched": {"iters_per_s": round(its / t_batch, 1), "solves_per_s": round(count / t_batch, 2),
                         "wall_s": round(t_batch, 3)},
             "one_at_a_time": {"iters_per_s": round(its / t_seq, 1), "solves_per_s": round(count / t_seq, 2),
@@ -375,14 +387,14 @@ def progress(msg: str) -> None:
 
 
 def np_study(P, wk) -> dict:
-    """The synthetic analogue of the paper's polarization-error table (Table 2, Sec. 4.2): a
-    64x64 image of six blobs with polarization fraction 0.97 at every pixel (close to the cone),
-    sparse 6-station arcs (8000 rows), 40 dB, solved with the full schedule (initialisation and
-    five reweighting cycles, 2000 iterations) with and without the polarization constraint; N_p
-    is the share of pixels whose polarized intensity exceeds I by more than zeta."""
+    """The synthetic analogue of the paper's polarization-error table (Table 2, Sec. 4.2): 32x32
+    blobs with polarization fraction 0.97 at every pixel (close to the cone), sparse 6-station
+    arcs (1000 rows), 35 dB, solved on the blob workload's schedule (initialisation and two
+    reweighting cycles, 300 iterations) with and without the polarization constraint; N_p is the
+    share of pixels whose polarized intensity exceeds I by more than zeta."""
     wl = wk.np_study()
-    out = {"workload": "64x64, six blobs, polarization fraction 0.97, 6-station arcs, 8000 visibilities, 40 dB, "
-                       "2000 iterations (initialisation + 5 cycles)"}
+    out = {"workload": "32x32 blobs, polarization fraction 0.97, 6-station arcs, 1000 visibilities, 35 dB, "
+                       "300 iterations (initialisation + 2 cycles)"}
     stages = [wl.iters // (wl.cycles + 1)] * wl.cycles
     stages.append(wl.iters - sum(stages))
     truth = wl.truth.reshape(-1, 4)
@@ -478,6 +490,8 @@ def main() -> int:
     s.synchronize()
     t_up = time.perf_counter() - t_up
     s.set_steps()
+    # launch shapes from the autotuner (the trials leave the zero state as it was)
+    chosen, tune_ms = s.autotune(P.PSARA_CONSTRAINED)
     # initialisation stage and first reweighting, so the timed iterations run every term
     s.solve(P.PSARA_NNLS_INIT, 100, report=False)
     s.psara_delta = P.psara_coef_std(s.ctx)
@@ -528,6 +542,8 @@ def main() -> int:
                                "KB 8x8 on a 2x oversampled grid; SARA Dirac+Db1-Db8, 4 levels; "
                                "Polarized SARA iteration, all terms active",
                    "n": n, "M": M, "taps": wl.taps, "levels": wl.levels, "precision": "FP32 bulk, FP64 reductions"},
+        "tuning": {"chosen": chosen, "trial_ms_per_iter_default": round(tune_ms[0], 5),
+                   "trial_ms_per_iter_chosen": round(tune_ms[1], 5)},
         "roofline": roofline,
         "passes": passes,
         "sum_of_pass_ms": round(float(sum(ms[i] for i in ITERATION_PASSES)), 5),
@@ -541,7 +557,7 @@ def main() -> int:
     s.close()
     progress(f"256x256 / 2e5-visibility iteration rate {its:.1f} iters/s")
     if not args.no_np_study:
-        progress("polarization-error study (64x64 near-cone blobs, with / without the constraint)")
+        progress("polarization-error study (32x32 near-cone blobs, with / without the constraint)")
         line["np_study"] = np_study(P, wk)
     if args.large_iters > 0:
         progress("large form: 512x512, 1e6 visibilities")

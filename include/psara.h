@@ -256,6 +256,55 @@ psara_status psara_data_gamma(psara_ctx* ctx, double factor, double* gamma);
 /* Replace gamma in the thresholds gamma W of the prior (W unchanged); gamma > 0. */
 psara_status psara_set_gamma(psara_ctx* ctx, double gamma);
 
+/* ---- launch shapes and the autotuner ----------------------------------------------------- */
+
+/* Launch shapes of a solve.  They change how the work is cut into workgroups and so the
+ * summation order of the gridding and of the de-gridding norm (results differ at rounding level,
+ * never in what is computed); every solve starts with the defaults. */
+typedef struct {
+    int grid_chunk;      /* gridding entries per workgroup: 256, 512 or 1024 (default 1024) */
+    int degrid_item;     /* visibilities per de-gridding workgroup: a power of two in [64, 1024]
+                            (default 256) */
+    int analysis_wide;   /* 1: 16-wide output tiles for the analysis bands of side >= 128 of FP32
+                            solves (default); 0: 8-wide (more workgroups) */
+    int fft_cells;       /* grid cells per FFT workgroup: 0 for max(512, 2n) (default), or 512, 1024,
+                            2048 with at least 2n (several grid lines per workgroup) */
+} psara_tuning;
+
+/* The context's launch shapes (ESTATE before psara_set_operator). */
+psara_status psara_get_tuning(const psara_ctx* ctx, psara_tuning* out);
+/* Apply launch shapes (NULL: the defaults): the gridding lists are cut again and the work lists
+ * rebuilt; the iteration state is kept.  EINVAL outside the ranges above. */
+psara_status psara_set_tuning(psara_ctx* ctx, const psara_tuning* t);
+
+enum {
+    PSARA_TUNE_USE_CACHE = 1,   /* take the shapes stored for this shape class, if any, without timing */
+    PSARA_TUNE_STORE = 2        /* store the chosen shapes for the class (process-wide) */
+};
+
+/* The autotuner: times the iteration of `mode` (chains of 8 captured iterations, best of three)
+ * under candidate shapes, one parameter at a time from the current ones (grid_chunk 1024 / 512 /
+ * 256, degrid_item 256 / 128 / 512, analysis_wide 1 / 0, fft_cells default / 1024 / 2048), keeps
+ * a candidate that beats the incumbent by 1 %, and applies the fastest.  The iteration state is
+ * saved and restored around the trials (the stored state exactly; the operator images the next
+ * primal step reads are recomputed).  A shape class is the precision, taps, image side, levels,
+ * basis mask and the visibility count's power of two.  flags: PSARA_TUNE_USE_CACHE,
+ * PSARA_TUNE_STORE.  chosen: NULL or the shapes applied; ms_per_iter: NULL or 2 doubles, the
+ * iteration time of the starting shapes and of the chosen ones (0, 0 for a cache hit).
+ * Requirements as for psara_solve in `mode`. */
+psara_status psara_autotune(psara_ctx* ctx, psara_mode mode, int flags, psara_tuning* chosen, double* ms_per_iter);
+
+/* The autotuner for a batch (the requirements of psara_batch_solve): every candidate is applied
+ * to all members and timed as one batched iteration; the chosen shapes end up applied to every
+ * member.  Not stored per class. */
+psara_status psara_batch_autotune(psara_ctx* const* ctxs, int count, psara_mode mode, psara_tuning* chosen,
+                                  double* ms_per_iter);
+
+/* The shapes stored for a shape class by psara_autotune with PSARA_TUNE_STORE: PSARA_OK and
+ * *out, or PSARA_ESTATE when none is stored.  Needs no device. */
+psara_status psara_tuning_lookup(int n, int64_t M, int taps, int levels, uint32_t basis_mask,
+                                 psara_precision precision, psara_tuning* out);
+
 /* ---- batches of independent solves ------------------------------------------------------- */
 
 /* Advance `count` independent solves together: every pass of Algorithm 1 is one launch over
@@ -363,7 +412,8 @@ psara_status psara_batch_profile_passes(psara_ctx* const* ctxs, int count, psara
  * batch at each stage end for its reweighting and rejoins.  Policy PSARA_SERVE_FIFO instead runs
  * one request at a time in arrival order.  Each result equals the same request solved alone
  * with psara_* calls in the order the server uses (operator, data, prior with gamma 1, opnorm,
- * data gamma, psara_set_steps_auto with margin 0.99, then psara_reweighted_solve, or
+ * data gamma, psara_set_steps_auto with margin 0.99, the launch shapes stored for the request's
+ * shape class if any (psara_tuning_lookup), then psara_reweighted_solve, or
  * psara_reweighted_solve_adaptive for a request with check_every > 0: such a request leaves the
  * batch as soon as its stage's criteria hold on the device).  Thread-safe for submit, poll and
  * cancel. */

@@ -19,7 +19,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PSARA_ARCH", "gfx950")
 
 SOURCES = ["host_math.cpp", "kernels_fft.hip", "kernels_grid.hip", "kernels_dwt.hip",
-           "kernels_point.hip", "kernels_tv.hip", "engine.hip", "capi.hip", "server.hip", "server_core.cpp"]
+           "kernels_point.hip", "kernels_tv.hip", "engine.hip", "capi.hip", "server.hip", "server_core.cpp",
+           "tuner.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", CSRC, "-I", os.path.join(ROOT, "include"),
           "-Wall", "-Wno-unused-variable", "-Wno-unused-function",

@@ -783,13 +783,13 @@ size_t psara_footprint(int n, int64_t M, int taps, int levels, uint32_t basis_ma
   b += K * K * 8 * R + K * (size_t)n * 8 * R;        // grid and FFT intermediate
   b += (2 * ntiles + 2) * 4 + (size_t)(spill * (double)M + 1) * 4;
   b += 3 * (size_t)nb * N * 4 * R + (size_t)std::max(nwav, 1) * std::max<size_t>(llst, 1) * 4 * R;
-  // gridding chunks: at most one per 16 x 16 tile plus one per kChunkEntries rows (runs end a
-  // chunk early by at most a run each); each holds a (16 + T - 1)^2 partial slot and a pair of
-  // FP64 partials
+  // gridding chunks: at most one per 16 x 16 tile plus one per 256 rows (the smallest chunk the
+  // launch shapes allow; runs end a chunk early by at most a run each); each holds a
+  // (16 + T - 1)^2 partial slot and a pair of FP64 partials
   const size_t ntg = (K / 16) * (K / 16), rg = 16 + (size_t)taps - 1;
-  const size_t chunks = ntg + 2 * ((size_t)M / psara::kChunkEntries + 1);
+  const size_t chunks = ntg + 2 * ((size_t)M / 256 + 1);
   b += chunks * rg * rg * 8 * R;
-  const size_t parts = (size_t)M / 256 + ntiles + 8 * (N / 64 + 64) + chunks;
+  const size_t parts = (size_t)M / 64 + ntiles + 8 * (N / 64 + 64) + chunks;   // de-grid items of >= 64 rows
   b += 2 * parts * 8 + 64 * 8;
   return b;
 }

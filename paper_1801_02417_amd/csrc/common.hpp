@@ -17,19 +17,19 @@ constexpr int kMaxTaps = 8;      // Kaiser-Bessel taps per dimension
 constexpr int kMaxCheb = 17;     // Chebyshev coefficients per tap (degree <= 16)
 constexpr int kMaxLevels = 8;
 constexpr int kRunMax = 32;         // longest run of same-window visibilities one lane group takes
-constexpr int kChunkEntries = 1024; // gridding entries per workgroup (staged in LDS)
+constexpr int kChunkEntries = 1024; // largest gridding chunk (entries per workgroup, staged in LDS)
 constexpr int kGridThreads = 512;   // threads per gridding workgroup (64 lane groups of 8)
 constexpr int kBatchChunk = 8;       // iterations per captured graph of a batch
 constexpr int kChain = 32;           // iterations per captured chain of a single solve
 constexpr int kMaxDegridTile = 32;  // largest de-gridding tile side (the geometry picks 16 or 32)
-constexpr int kDegridItem = 256;        // visibilities per de-gridding work item
+constexpr int kDegridItem = 256;        // default visibilities per de-gridding work item
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
 
 // Chebyshev degree of the per-tap Kaiser-Bessel expansions (max error ~1e-10 / ~1e-15)
 // SARA tile sides: analysis output tile per band for an input of side 2h, and synthesis
 // output tile for an output of side m (smaller tiles give more workgroups at coarse levels)
-template <typename R> __host__ __device__ constexpr int dwt_ana_tile(int h) {
-  return (sizeof(R) == 4 && h >= 128) ? 16 : (h < 8 ? h : 8);
+template <typename R> __host__ __device__ constexpr int dwt_ana_tile(int h, bool wide = true) {
+  return (sizeof(R) == 4 && wide && h >= 128) ? 16 : (h < 8 ? h : 8);
 }
 template <typename R> __host__ __device__ constexpr int dwt_syn_tile(int m) { return m < 16 ? m : 16; }
 
@@ -81,6 +81,8 @@ struct ProbDesc {
   int ntile_side, deg, n_p6, gen_stride;
   int ntile_side_g;       // gridding tiles per side (side kGridTile)
   int n_slots;            // gridding chunks (= partial slots) of the problem
+  int dg_item;            // visibilities per de-gridding work item
+  int ana_wide;           // 16-wide output tiles for analysis bands of side >= 128 (FP32)
   long long M;
   double tau, rho1, rho2, rho3, eps, gamma, norm;   // norm = 1/sqrt(nbases)
   double delta;                                     // reweighting delta in use

@@ -89,8 +89,18 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
   g.list_idx.resize(g.list_ptr[ntg]);
   std::vector<int> fillp(g.list_ptr.begin(), g.list_ptr.end() - 1);
   for (int64_t p = 0; p < M; ++p) g.list_idx[fillp[owner(p)]++] = (int)p;
+  build_grid_chunks(g, kChunkEntries);
+  return g;
+}
+
+void build_grid_chunks(Geometry& g, int chunk_entries) {
+  const int ntg = g.ntsg * g.ntsg;
+  g.run_beg.clear(); g.run_len.clear(); g.run_k0.clear();
+  g.chunks.clear(); g.chunk_ent.clear(); g.tile_slots.clear();
+  g.n_slots = 0;
+  g.chunk_entries = chunk_entries;
   // runs: consecutive list entries of a tile with the same window start (their taps hit the
-  // same cells), split at kRunMax; chunks of whole runs with <= kChunkEntries entries, runs
+  // same cells), split at kRunMax; chunks of whole runs with <= chunk_entries entries, runs
   // ordered longest first inside a chunk so the lanes of a wave loop for similar lengths.
   // Every chunk accumulates its tile plus the T-1 halo in its own slot; the column inverse
   // FFT sums the slots of a cell's tile and of the three tiles whose halos reach it.
@@ -107,7 +117,7 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
     while (r < runs.size()) {
       const size_t r0 = r;
       int entries = 0;
-      while (r < runs.size() && (entries + runs[r].second <= kChunkEntries || r == r0)) entries += runs[r++].second;
+      while (r < runs.size() && (entries + runs[r].second <= chunk_entries || r == r0)) entries += runs[r++].second;
       std::stable_sort(runs.begin() + r0, runs.begin() + r,
                        [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.second > y.second; });
       const int base = (int)g.run_beg.size();
@@ -124,12 +134,21 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
     }
     g.tile_slots.push_back(make_int2(first_slot, g.n_slots - first_slot));
   }
-  return g;
+}
+
+void check_tuning(const Tuning& t, int K) {
+  if (t.grid_chunk != 256 && t.grid_chunk != 512 && t.grid_chunk != 1024)
+    throw Error(PSARA_EINVAL, "grid_chunk must be 256, 512 or 1024");
+  if (t.degrid_item < 64 || t.degrid_item > 1024 || (t.degrid_item & (t.degrid_item - 1)))
+    throw Error(PSARA_EINVAL, "degrid_item must be a power of two in [64, 1024]");
+  if (t.ana_wide != 0 && t.ana_wide != 1) throw Error(PSARA_EINVAL, "analysis_wide must be 0 or 1");
+  if (t.fft_cells != 0 && ((t.fft_cells != 512 && t.fft_cells != 1024 && t.fft_cells != 2048) || t.fft_cells < K))
+    throw Error(PSARA_EINVAL, "fft_cells must be 0 or 512, 1024 or 2048, and at least the grid side 2n");
 }
 
 // ------------------------------------------------------------------------------------------------
 // work lists (appended per problem, so batches concatenate them)
-void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int* n_p6) {
+void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int dg_item, int* n_p6) {
   const int n = g.n, K = g.K, N = n * n;
   const int lines = cells / K, rlines = rcells / K;
   for (int b = 0; b < (N + 255) / 256; ++b) S.img.push_back(make_int4(prob, b, 0, 0));
@@ -138,7 +157,7 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
   const int ntiles = g.nts * g.nts;
   int part = 0;
   for (int t = 0; t < ntiles; ++t) {
-    for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += kDegridItem) S.p6.push_back(make_int4(prob, t, v, part++));
+    for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += dg_item) S.p6.push_back(make_int4(prob, t, v, part++));
   }
   // gridding: first the item that stores the pass's scalar factor, then the chunks heaviest
   // first (entries plus a flush cost per run as the work estimate) so the tail is short
@@ -154,13 +173,13 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
 }
 
 void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const int* wav_len, bool fp64, int c_level,
-                     int* n_ana_parts) {
+                     bool ana_wide, int* n_ana_parts) {
   const int N = n * n;
   int part = 0;
   for (int b = 0; b < (N + 255) / 256; ++b) S.dirac.push_back(make_int4(prob, b, 0, part++));
   for (int l = 1; l <= levels; ++l) {
     const int h = n >> l;
-    const int to = fp64 ? dwt_ana_tile<double>(h) : dwt_ana_tile<float>(h), tps = h / to;
+    const int to = fp64 ? dwt_ana_tile<double>(h, ana_wide) : dwt_ana_tile<float>(h, ana_wide), tps = h / to;
     for (int w = 0; w < nwav; ++w)
       for (int t = 0; t < tps * tps; ++t) {
         S.ana[l].push_back(make_int4(prob, w, t, part++));
@@ -232,14 +251,7 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   h_.vis_frac = upload_conv(g.frac.data(), 2 * M);
   h_.own_ptr = upload<int>(g.own_ptr.data(), g.own_ptr.size());
   h_.list_idx = upload<int>(g.list_idx.data(), std::max<size_t>(1, g.list_idx.size()));
-  h_.run_beg = upload<int>(g.run_beg.data(), std::max<size_t>(1, g.run_beg.size()));
-  h_.run_len = upload<int>(g.run_len.data(), std::max<size_t>(1, g.run_len.size()));
-  h_.run_k0 = upload<int>(g.run_k0.data(), std::max<size_t>(1, g.run_k0.size()));
-  h_.chunk_ent = upload<int2>(g.chunk_ent.data(), std::max<size_t>(1, g.chunk_ent.size()));
-  h_.tile_slots = upload<int2>(g.tile_slots.data(), std::max<size_t>(1, g.tile_slots.size()));
-  h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
-  h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * (kGridTile + g.T - 1) * (kGridTile + g.T - 1));
-  h_.n_slots = g.n_slots;
+  upload_chunks();
   // tables
   std::vector<double> poly = kb_poly(g.T, g.beta, h_.deg);
   h_.kbpoly = upload_conv(poly.data(), poly.size());
@@ -254,8 +266,10 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   for (int j = 0; j < n; ++j) s[j] = 1.0 / kb_hat(g.T, g.beta, (double)(j - n / 2) / (double)K);
   h_.deapod = upload_conv(s.data(), n);
   set_grid_kernel_limits<R>(g.ts, g.T);
+  h_.dg_item = tuning_.degrid_item;
+  h_.ana_wide = tuning_.ana_wide;
   // items of the operator passes
-  add_operator_items(items_, 0, g, cells_, rcells_, &h_.n_p6);
+  build_operator_items();
   gen_parts_ = (N + 255) / 256;
   realloc_partials();
   h_.scal = dalloc<double>(NUM_SCALARS);
@@ -343,6 +357,66 @@ static std::vector<int4> xcd_contiguous(const std::vector<int4>& v) {
   return out;
 }
 
+// The geometry's runs, chunks and per-tile slot ranges on the device, with the partial slots.
+template <typename R>
+void Engine<R>::upload_chunks() {
+  const Geometry& g = geo_;
+  dfree((void*)h_.run_beg); dfree((void*)h_.run_len); dfree((void*)h_.run_k0);
+  dfree((void*)h_.chunk_ent); dfree((void*)h_.tile_slots); dfree((void*)h_.chunks); dfree(h_.gpart);
+  h_.run_beg = upload<int>(g.run_beg.data(), std::max<size_t>(1, g.run_beg.size()));
+  h_.run_len = upload<int>(g.run_len.data(), std::max<size_t>(1, g.run_len.size()));
+  h_.run_k0 = upload<int>(g.run_k0.data(), std::max<size_t>(1, g.run_k0.size()));
+  h_.chunk_ent = upload<int2>(g.chunk_ent.data(), std::max<size_t>(1, g.chunk_ent.size()));
+  h_.tile_slots = upload<int2>(g.tile_slots.data(), std::max<size_t>(1, g.tile_slots.size()));
+  h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
+  h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * (kGridTile + g.T - 1) * (kGridTile + g.T - 1));
+  h_.n_slots = g.n_slots;
+}
+
+template <typename R>
+void Engine<R>::build_operator_items() {
+  items_.img.clear(); items_.rows.clear(); items_.cols.clear(); items_.p6.clear(); items_.p7.clear();
+  add_operator_items(items_, 0, geo_, cells_, rcells_, tuning_.degrid_item, &h_.n_p6);
+}
+
+// The SARA work lists of the current prior (none for the TV priors or without a prior).
+template <typename R>
+void Engine<R>::build_prior_items() {
+  const int N = geo_.n * geo_.n;
+  items_.dirac.clear(); items_.synfinal.clear(); items_.synsplit.clear(); items_.coarse.clear();
+  for (int l = 0; l <= kMaxLevels; ++l) {
+    items_.ana[l].clear(); items_.syn[l].clear(); items_.ana_d[l].clear(); items_.syn_d[l].clear();
+  }
+  int nap = 0;
+  if (h_.tv_kind == 0 && h_.coef[COEF_A] && h_.levels > 0)
+    add_prior_items(items_, 0, geo_.n, h_.levels, h_.nwav, h_.wav_len, std::is_same<R, double>::value, c_level_,
+                    tuning_.ana_wide != 0, &nap);
+  ana_parts_ = nap;
+  gen_parts_ = std::max((N + 255) / 256, nap);
+}
+
+template <typename R>
+void Engine<R>::set_tuning(const Tuning& t) {
+  check_tuning(t, geo_.K);
+  hip_check(hipStreamSynchronize(s0_), "tuning sync");
+  hip_check(hipStreamSynchronize(s1_), "tuning sync");
+  if (t.grid_chunk != geo_.chunk_entries) {
+    build_grid_chunks(geo_, t.grid_chunk);
+    upload_chunks();
+  }
+  tuning_ = t;
+  cells_ = t.fft_cells ? t.fft_cells : std::max(512, geo_.K);
+  rcells_ = cells_;
+  h_.dg_item = t.degrid_item;
+  h_.ana_wide = t.ana_wide;
+  build_operator_items();
+  build_prior_items();
+  realloc_partials();
+  upload_items();
+  invalidate_graphs();
+  hip_check(hipStreamSynchronize(s0_), "tuning");
+}
+
 template <typename R>
 void Engine<R>::upload_items() {
   auto up = [&](DevItems& d, const std::vector<int4>& v) {
@@ -368,6 +442,8 @@ void Engine<R>::upload_items() {
   pl_.cells = cells_; pl_.rcells = rcells_;
   pl_.max_ts = geo_.ts; pl_.taps = geo_.T; pl_.max_levels = h_.levels;
   pl_.max_n = h_.n;
+  pl_.ana_wide = tuning_.ana_wide;
+  pl_.grid_ce = geo_.chunk_entries;
   pl_.sparse = h_.coef[COEF_A] != nullptr && h_.nwav > 0;
   pl_.tv = h_.tv_kind != 0;
 }
@@ -484,11 +560,8 @@ void Engine<R>::set_prior(uint32_t mask, int levels, const double* weights, doub
   for (size_t i = 0; i < gw.size(); ++i) gw[i] = (R)(gamma * (weights ? weights[i] : 1.0));
   copy_sync(h_.coef[COEF_GW], gw.data(), gw.size() * sizeof(R), hipMemcpyHostToDevice, s0_, "weights upload");
   zero(h_.coef[COEF_A], coef_elems_ * sizeof(V4<R>));
-  int nap = 0;
   c_level_ = coarse_level<R>(n, levels);
-  add_prior_items(items_, 0, n, levels, nwav, h_.wav_len, std::is_same<R, double>::value, c_level_, &nap);
-  ana_parts_ = nap;
-  gen_parts_ = std::max((N + 255) / 256, nap);
+  build_prior_items();
   realloc_partials();
   upload_items();
   invalidate_graphs();
@@ -512,6 +585,8 @@ LaunchArgs Engine<R>::la(const DevItems& d, hipStream_t s) const {
   a.nitems = d.count;
   a.stream = s ? s : s0_;
   a.max_n = h_.n;
+  a.ana_wide = tuning_.ana_wide;
+  a.grid_ce = geo_.chunk_entries;
   return a;
 }
 
@@ -534,6 +609,8 @@ static LaunchArgs lists_la(const PassLists& L, const DevItems& d, hipStream_t s)
   a.nitems = d.count;
   a.stream = s;
   a.max_n = L.max_n;
+  a.ana_wide = L.ana_wide;
+  a.grid_ce = L.grid_ce;
   return a;
 }
 
@@ -1212,15 +1289,19 @@ template <typename R>
 Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : members_(members), s0_(stream) {
   if (members_.empty()) throw Error(PSARA_EINVAL, "empty batch");
   const int T = members_[0]->geometry().T;
-  int cells = 512, max_ts = 0, max_levels = 0, max_n = 0;
+  // the FFT launches take the most cells per workgroup any member's tuning asks for (at least
+  // the largest grid side); the gridding staging is sized for the largest chunk
+  int cells = 512, max_ts = 0, max_levels = 0, max_n = 0, grid_ce = 0, ana_wide = 0;
   bool sparse = true;
   for (Engine<R>* e : members_) {
     const Geometry& g = e->geometry();
     if (g.T != T) throw Error(PSARA_EINVAL, "batch members must share the tap count");
-    cells = std::max(cells, g.K);
+    cells = std::max(cells, std::max(g.K, e->fft_cells()));
     max_ts = std::max(max_ts, g.ts);
     max_n = std::max(max_n, g.n);
     max_levels = std::max(max_levels, e->desc().levels);
+    grid_ce = std::max(grid_ce, g.chunk_entries);
+    ana_wide = ana_wide | e->tuning().ana_wide;
     sparse = sparse && e->has_prior();
   }
   ItemSet S;
@@ -1228,12 +1309,12 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
     Engine<R>* e = members_[i];
     const Geometry& g = e->geometry();
     int np6 = 0;
-    add_operator_items(S, (int)i, g, cells, cells, &np6);
+    add_operator_items(S, (int)i, g, cells, cells, e->tuning().degrid_item, &np6);
     if (np6 != e->desc().n_p6) throw Error(PSARA_EDEVICE, "inconsistent de-grid partition");
     if (e->has_prior()) {
       int nap = 0;
       add_prior_items(S, (int)i, g.n, e->desc().levels, e->desc().nwav, e->desc().wav_len,
-                      std::is_same<R, double>::value, e->c_level(), &nap);
+                      std::is_same<R, double>::value, e->c_level(), e->tuning().ana_wide != 0, &nap);
     }
   }
   auto up = [&](DevItems& d, const std::vector<int4>& v) {
@@ -1263,6 +1344,8 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
   pl_.cells = cells; pl_.rcells = cells;
   pl_.max_ts = max_ts; pl_.taps = T; pl_.max_levels = max_levels;
   pl_.max_n = max_n;
+  pl_.ana_wide = ana_wide;
+  pl_.grid_ce = grid_ce;
   pl_.sparse = sparse;
   set_grid_kernel_limits<R>(max_ts, T);
   hip_check(hipStreamCreateWithFlags(&s1_, hipStreamNonBlocking), "hipStreamCreate");

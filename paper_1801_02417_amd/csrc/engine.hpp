@@ -36,9 +36,23 @@ struct Geometry {
   std::vector<int2> chunk_ent;           // list-entry range [lo, hi) each chunk covers
   std::vector<int2> tile_slots;          // per gridding tile {first partial slot, count}
   int n_slots = 0;
+  int chunk_entries = kChunkEntries;     // the chunk size the runs and chunks were cut for
 };
 
 Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T);
+// (Re)cuts the gridding lists of a geometry into runs and chunks of at most chunk_entries entries.
+void build_grid_chunks(Geometry& g, int chunk_entries);
+
+// Launch shapes of a solve that the autotuner chooses among (they change the summation order of
+// the gridding and the de-gridding norm, not what is computed).
+struct Tuning {
+  int grid_chunk = kChunkEntries;   // gridding entries per workgroup: 256, 512 or 1024
+  int degrid_item = kDegridItem;    // visibilities per de-gridding workgroup: 64 .. 1024
+  int ana_wide = 1;                 // 16-wide analysis tiles for bands of side >= 128 (FP32)
+  int fft_cells = 0;                // grid cells per FFT workgroup (0: max(512, K)); 512, 1024, 2048
+};
+// Throws Error(PSARA_EINVAL) for a tuning outside those ranges or with fft_cells below the side K.
+void check_tuning(const Tuning& t, int K);
 
 // Work lists of the passes; every item names its problem (index into the descriptor array).
 //   ana[l], syn[l]     SARA analysis / synthesis of level l for every level (non-dual uses)
@@ -52,9 +66,9 @@ struct ItemSet {
   std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
   std::vector<int4> ana_d[kMaxLevels + 1], syn_d[kMaxLevels + 1];
 };
-void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int* n_p6);
+void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int dg_item, int* n_p6);
 void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const int* wav_len, bool fp64, int c_level,
-                     int* n_ana_parts);
+                     bool ana_wide, int* n_ana_parts);
 
 struct DevItems {
   int4* ptr = nullptr;
@@ -70,6 +84,8 @@ struct PassLists {
   int cells = 512, rcells = 512;   // FFT cells per workgroup of the column / row passes
   int max_ts = 16, taps = 8, max_levels = 0;
   int max_n = 0;                   // largest image side among the problems
+  int ana_wide = 1;                // any problem takes 16-wide analysis tiles
+  int grid_ce = kChunkEntries;     // largest gridding chunk among the problems
   bool sparse = false;             // every problem has a wavelet prior (P2/P3 run)
   bool tv = false;                 // the problems carry a TV prior (Algorithm 3)
 };
@@ -134,6 +150,11 @@ struct Engine {
   void get_img(int slot, double* dst, int comps);
   void profile(int mode, int iters, double* ms);
   size_t coef_elems() const { return coef_elems_; }
+  const Tuning& tuning() const { return tuning_; }
+  int fft_cells() const { return cells_; }
+  // new launch shapes: the gridding lists are cut again, the work lists rebuilt, the partial
+  // sums and slots reallocated and the graphs dropped; the iteration state is kept
+  void set_tuning(const Tuning& t);
   size_t device_bytes() const { return bytes_; }
   const ProbDesc& desc() const { return h_; }
   hipStream_t stream() const { return s0_; }
@@ -166,6 +187,9 @@ struct Engine {
   void invalidate_graphs();
   void launch_iterations(int mode, int count);
   hipGraphExec_t chain_graph(int mode, int count);   // the captured chain of `count` iterations
+  void upload_chunks();                              // the geometry's runs, chunks and slots
+  void build_operator_items();
+  void build_prior_items();
   void prime(int mode);       // Algorithm 3: the data gradient and Psi A of the current state
   void adaptive_buffers();
   void forward(int src_img, int mode, int out_vis);
@@ -197,6 +221,7 @@ struct Engine {
   PassLists pl_;
   int cells_ = 512;     // FFT cells per workgroup of the column passes
   int rcells_ = 2048;   // ... and of the row passes (several image rows per workgroup)
+  Tuning tuning_;
   int gen_parts_ = 1, ana_parts_ = 0;
   size_t coef_elems_ = 0;
   size_t bytes_ = 0;

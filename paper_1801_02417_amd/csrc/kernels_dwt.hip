@@ -155,7 +155,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
   const Taps<R, F> t((const R*)P.filters + w * kMaxFilter);
   const int n = P.n;
   const int m = n >> (level - 1), h = m >> 1;
-  const int to = dwt_ana_tile<R>(h), tps = h / to;
+  const int to = dwt_ana_tile<R>(h, P.ana_wide != 0), tps = h / to;
   const int o1 = (tile / tps) * to, o2 = (tile % tps) * to;
   const int in = 2 * to + F - 2;
   const size_t base = (size_t)(P.has_dirac + w) * n * n;
@@ -616,7 +616,7 @@ void launch_analysis(int mode, int level, const LaunchArgs& a, int src_slot, int
   if (a.nitems <= 0) return;
   // the largest tile side among the launch's problems (an unknown largest side takes the widest)
   constexpr int kWide = dwt_ana_tile<R>(1 << 30);
-  const int tom = a.max_n > 0 ? dwt_ana_tile<R>(a.max_n >> level) : kWide;
+  const int tom = a.max_n > 0 ? dwt_ana_tile<R>(a.max_n >> level, a.ana_wide != 0) : kWide;
   if constexpr (kWide > 8) {
     if (tom > 8) { launch_analysis_t<R, kWide>(mode, level, a, src_slot, out_coef); return; }
   }

@@ -147,7 +147,8 @@ __device__ inline R grid_channels(const ProbDesc& P, int m, const Cell<R>& b, V4
 }
 
 // ---------------------------------------------------------------------------------------------
-// P6: de-grid + L mixing (+ dual B).  items: {prob, tile, first sorted vis, partial index}
+// P6: de-grid + L mixing (+ dual B).  items: {prob, tile, first sorted vis, partial index}; an item
+// holds P.dg_item rows of the tile (fewer at its end), a thread takes every blockDim.x-th
 template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(256)
 degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot) {
@@ -165,7 +166,7 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   const int b1 = t1 * ts, b2 = t2 * ts;
   // the item's visibilities are sorted by window start k1 within the tile, so they use only
   // the k1 offsets [lo, hi + T - 1] of the tile window: stage that band, Wb wide
-  const int vend = min(it.z + kDegridItem, P.own_ptr[tile + 1]);
+  const int vend = min(it.z + P.dg_item, P.own_ptr[tile + 1]);
   const int lo = (P.vis_k0[it.z] >> 16) - b1, hi = (P.vis_k0[vend - 1] >> 16) - b1;
   const int Wb = hi - lo + T;
   for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {
@@ -174,9 +175,8 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   }
   __syncthreads();
 
-  const int m = it.z + threadIdx.x;
   KSum acc;
-  if (m < vend) {
+  for (int m = it.z + threadIdx.x; m < vend; m += blockDim.x) {
     const int pk = P.vis_k0[m];
     const int r1 = (pk >> 16) - b1 - lo, r2 = (pk & 0xffff) - b2;
     const V2<R> f = ((const V2<R>*)P.vis_frac)[m];
@@ -366,13 +366,16 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
 
 // (FP64: the LDS holds one workgroup per CU, so two waves per SIMD and 256 registers, which
 // keeps the FP64 accumulators out of scratch memory)
+// (ce: the largest chunk of the launch's problems; the staging arrays after the accumulator hold
+// ce entries)
 template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(kGridThreads, sizeof(R) == 8 ? 2 : 4)
-grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac) {
+grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int use_cfac, int ce) {
   constexpr int RG = kGridTile + T - 1;            // tile plus halo
   __shared__ unsigned long long acc[8 * RG * RG];   // channel-major: acc[c][k2 offset][k1 offset]
-  __shared__ V2<R> sf[kChunkEntries];             // staged fractional offsets
-  __shared__ V4<R> su[2 * kChunkEntries];         // staged mixed values, two V4 per entry
+  extern __shared__ __align__(16) unsigned char stage_raw[];
+  V2<R>* sf = (V2<R>*)stage_raw;                  // staged fractional offsets
+  V4<R>* su = (V4<R>*)(stage_raw + (size_t)ce * sizeof(V2<R>));   // staged mixed values, two V4 per entry
   __shared__ double red[2 * (kGridThreads / 64)];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
@@ -430,12 +433,14 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
 // (FP64: the LDS holds one workgroup per CU, so two waves per SIMD and 256 registers)
 template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(kGridThreads, sizeof(R) == 8 ? 2 : 4)
-degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot) {
+degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot,
+                   int ce) {
   constexpr int RG = kGridTile + T - 1;
   constexpr int DG = MODE == GR_STOKES ? DG_STOKES : DG_DUAL;
   __shared__ unsigned long long acc[8 * RG * RG];   // first the grid window (RG x RG cells)
-  __shared__ V2<R> sf[kChunkEntries];
-  __shared__ V4<R> su[2 * kChunkEntries];
+  extern __shared__ __align__(16) unsigned char stage_raw[];
+  V2<R>* sf = (V2<R>*)stage_raw;
+  V4<R>* su = (V4<R>*)(stage_raw + (size_t)ce * sizeof(V2<R>));
   __shared__ double red[2 * (kGridThreads / 64)];
   static_assert(sizeof(Cell<R>) <= 8 * sizeof(unsigned long long), "window fits the accumulator");
   const int4 it = items[blockIdx.x];
@@ -505,15 +510,20 @@ degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ 
   grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total));
 }
 
+// dynamic LDS of the gridding kernels: the staged offsets and mixed values of ce entries
+template <typename R> size_t grid_stage_bytes(int ce) { return (size_t)ce * (sizeof(V2<R>) + 2 * sizeof(V4<R>)); }
+
 template <typename R, int T>
 void launch_grid_t(int mode, const LaunchArgs& a, int src_slot, int use_cfac) {
   const dim3 grid(a.nitems), block(kGridThreads);
+  const int ce = a.grid_ce;
+  const size_t shm = grid_stage_bytes<R>(ce);
   if (mode == GR_DUAL) {
-    hipLaunchKernelGGL((grid_kernel<R, GR_DUAL, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
+    hipLaunchKernelGGL((grid_kernel<R, GR_DUAL, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, use_cfac, ce);
   } else if (mode == GR_STOKES) {
-    hipLaunchKernelGGL((grid_kernel<R, GR_STOKES, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
+    hipLaunchKernelGGL((grid_kernel<R, GR_STOKES, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, use_cfac, ce);
   } else {
-    hipLaunchKernelGGL((grid_kernel<R, GR_PLAIN, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, use_cfac);
+    hipLaunchKernelGGL((grid_kernel<R, GR_PLAIN, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot, use_cfac, ce);
   }
 }
 
@@ -529,10 +539,14 @@ void launch_grid(int mode, const LaunchArgs& a, int taps, int src_slot, int use_
 template <typename R, int T>
 void launch_degrid_grid_t(int mode, const LaunchArgs& a, int src_slot, int out_slot) {
   const dim3 grid(a.nitems), block(kGridThreads);
+  const int ce = a.grid_ce;
+  const size_t shm = grid_stage_bytes<R>(ce);
   if (mode == GR_STOKES) {
-    hipLaunchKernelGGL((degrid_grid_kernel<R, GR_STOKES, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, out_slot);
+    hipLaunchKernelGGL((degrid_grid_kernel<R, GR_STOKES, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot,
+                       out_slot, ce);
   } else {
-    hipLaunchKernelGGL((degrid_grid_kernel<R, GR_DUAL, T>), grid, block, 0, a.stream, a.descs, a.items, src_slot, out_slot);
+    hipLaunchKernelGGL((degrid_grid_kernel<R, GR_DUAL, T>), grid, block, shm, a.stream, a.descs, a.items, src_slot,
+                       out_slot, ce);
   }
 }
 
@@ -547,6 +561,12 @@ void launch_degrid_grid(int mode, const LaunchArgs& a, int taps, int src_slot, i
 // Raise the dynamic-LDS limit of the de-grid / grid kernels once, outside any graph capture.
 template <typename R, int T>
 void set_degrid_limits_t(int max_ts) {
+  const int shm_st = (int)grid_stage_bytes<R>(kChunkEntries);
+  hip_check(hipFuncSetAttribute((const void*)grid_kernel<R, GR_DUAL, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_st), "attr");
+  hip_check(hipFuncSetAttribute((const void*)grid_kernel<R, GR_PLAIN, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_st), "attr");
+  hip_check(hipFuncSetAttribute((const void*)grid_kernel<R, GR_STOKES, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_st), "attr");
+  hip_check(hipFuncSetAttribute((const void*)degrid_grid_kernel<R, GR_DUAL, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_st), "attr");
+  hip_check(hipFuncSetAttribute((const void*)degrid_grid_kernel<R, GR_STOKES, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_st), "attr");
   const int W = max_ts + T - 1;
   const int shm_dg = W * W * (int)sizeof(Cell<R>);
   hip_check(hipFuncSetAttribute((const void*)degrid_kernel<R, DG_DUAL, T>, hipFuncAttributeMaxDynamicSharedMemorySize, shm_dg), "attr");

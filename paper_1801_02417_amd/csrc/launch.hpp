@@ -14,6 +14,8 @@ struct LaunchArgs {
   int nitems;
   hipStream_t stream;
   int max_n = 0;           // largest image side among the launch's problems (0: not known)
+  int ana_wide = 1;        // whether any of them takes 16-wide analysis tiles
+  int grid_ce = kChunkEntries;   // largest gridding chunk among them (entries staged per workgroup)
 };
 
 // P1 modes (the TV modes are Algorithm 3's primal steps: the data term enters as its gradient,

@@ -164,6 +164,9 @@ class HipDevice : public Device {
     if (!(g > 0.0)) throw Error(PSARA_EINVAL, "data-driven gamma is zero");
     ok(c, psara_set_gamma(c, g));
     ok(c, psara_set_steps_auto(c, 0.99, nullptr));
+    psara_tuning t;
+    if (psara_tuning_lookup(r.n, r.M, r.taps, r.levels, r.basis_mask, r.precision, &t) == PSARA_OK)
+      ok(c, psara_set_tuning(c, &t));
     return s;
   }
   void stop_begin(Job& j, const double crit[3], int bound) override {

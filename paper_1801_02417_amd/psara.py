@@ -37,7 +37,10 @@ EXPORTS = (
     "psara_server_create", "psara_server_submit", "psara_server_poll", "psara_server_drain",
     "psara_server_clock", "psara_server_last_error", "psara_server_destroy", "psara_runtime_check",
     "psara_step_sizes", "psara_set_steps_auto", "psara_capture", "psara_solve_noalloc", "psara_server_cancel",
+    "psara_get_tuning", "psara_set_tuning", "psara_autotune", "psara_batch_autotune", "psara_tuning_lookup",
 )
+
+PSARA_TUNE_USE_CACHE, PSARA_TUNE_STORE = 1, 2
 
 PSARA_SERVE_BATCHED, PSARA_SERVE_FIFO = 0, 1
 PSARA_REQ_QUEUED, PSARA_REQ_RUNNING, PSARA_REQ_DONE, PSARA_REQ_FAILED, PSARA_REQ_CANCELLED = 0, 1, 2, 3, 4
@@ -52,6 +55,16 @@ class PsaraReport(C.Structure):
         return {"residual": self.residual, "epsilon": self.epsilon, "rel_var": list(self.rel_var),
                 "zeta": self.zeta, "n_p": self.n_p, "objective": self.objective, "vnorm": self.vnorm,
                 "iterations": int(self.iterations)}
+
+
+class PsaraTuning(C.Structure):
+    _fields_ = [("grid_chunk", C.c_int), ("degrid_item", C.c_int), ("analysis_wide", C.c_int), ("fft_cells", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+DEFAULT_TUNING = {"grid_chunk": 1024, "degrid_item": 256, "analysis_wide": 1, "fft_cells": 0}
 
 
 class PsaraStop(C.Structure):
@@ -108,6 +121,11 @@ def lib() -> C.CDLL:
         "psara_set_steps_auto": (I, [P, C.c_double, D]),
         "psara_capture": (I, [P, I, I, I]),
         "psara_solve_noalloc": (I, [P, I, I]),
+        "psara_get_tuning": (I, [P, C.POINTER(PsaraTuning)]),
+        "psara_set_tuning": (I, [P, C.POINTER(PsaraTuning)]),
+        "psara_autotune": (I, [P, I, I, C.POINTER(PsaraTuning), D]),
+        "psara_batch_autotune": (I, [C.POINTER(P), I, I, C.POINTER(PsaraTuning), D]),
+        "psara_tuning_lookup": (I, [I, I64, I, I, U32, I, C.POINTER(PsaraTuning)]),
         "psara_opnorm": (I, [P, I, C.c_double, D]),
         "psara_solve": (I, [P, I, I, I, C.POINTER(PsaraReport)]),
         "psara_set_mueller": (I, [P, D]),
@@ -264,6 +282,42 @@ def psara_solve(ctx, mode: int, iters: int, check_every: int = 0, report: bool =
 
 def psara_solve_noalloc(ctx, mode: int, iters: int) -> None:
     _check(ctx, lib().psara_solve_noalloc(ctx, mode, iters))
+
+
+def psara_get_tuning(ctx) -> dict:
+    t = PsaraTuning()
+    _check(ctx, lib().psara_get_tuning(ctx, C.byref(t)))
+    return t.as_dict()
+
+
+def psara_set_tuning(ctx, tuning: Optional[dict] = None) -> None:
+    """Launch shapes from a dict with the keys of DEFAULT_TUNING (missing keys: defaults), or
+    None for the defaults."""
+    if tuning is None:
+        _check(ctx, lib().psara_set_tuning(ctx, None))
+        return
+    t = PsaraTuning(**{**DEFAULT_TUNING, **tuning})
+    _check(ctx, lib().psara_set_tuning(ctx, C.byref(t)))
+
+
+def psara_autotune(ctx, mode: int = PSARA_CONSTRAINED, flags: int = 0):
+    """(chosen shapes, [ms per iteration of the starting shapes, of the chosen ones])."""
+    t, ms = PsaraTuning(), np.zeros(2)
+    _check(ctx, lib().psara_autotune(ctx, mode, flags, C.byref(t), _dptr(ms)))
+    return t.as_dict(), [float(v) for v in ms]
+
+
+def psara_batch_autotune(ctxs, mode: int = PSARA_CONSTRAINED):
+    t, ms = PsaraTuning(), np.zeros(2)
+    _batch_check(ctxs, lib().psara_batch_autotune(_ctx_array(ctxs), len(ctxs), mode, C.byref(t), _dptr(ms)))
+    return t.as_dict(), [float(v) for v in ms]
+
+
+def psara_tuning_lookup(n: int, M: int, taps: int, levels: int, basis_mask: int = ALL_BASES,
+                        precision: int = PSARA_FP32_MIXED) -> Optional[dict]:
+    t = PsaraTuning()
+    st = lib().psara_tuning_lookup(n, M, taps, levels, basis_mask, precision, C.byref(t))
+    return t.as_dict() if st == PSARA_OK else None
 
 
 def psara_capture(ctx, mode: int, iters: int, check_every: int = 0) -> None:
@@ -607,6 +661,15 @@ class Solver:
     def capture(self, mode: int, iters: int, check_every: int = 0) -> None:
         psara_capture(self.ctx, mode, iters, check_every)
 
+    def tuning(self) -> dict:
+        return psara_get_tuning(self.ctx)
+
+    def set_tuning(self, tuning: Optional[dict] = None) -> None:
+        psara_set_tuning(self.ctx, tuning)
+
+    def autotune(self, mode: int = PSARA_CONSTRAINED, flags: int = 0):
+        return psara_autotune(self.ctx, mode, flags)
+
     def reweighted_solve(self, mode: int, iters_per_stage, delta_decay: float = 10.0):
         return psara_reweighted_solve(self.ctx, mode, iters_per_stage, delta_decay)
 
@@ -673,6 +736,10 @@ def batch_solve(solvers: Sequence[Solver], mode: int, iters: int, report: bool =
 
 def batch_solve_adaptive(solvers: Sequence[Solver], mode: int, max_iters: int, check_every: int, stop=PAPER_STOP):
     return psara_batch_solve_adaptive([s.ctx for s in solvers], mode, max_iters, check_every, stop)
+
+
+def batch_autotune(solvers: Sequence[Solver], mode: int = PSARA_CONSTRAINED):
+    return psara_batch_autotune([s.ctx for s in solvers], mode)
 
 
 def batch_reweighted_solve(solvers: Sequence[Solver], mode: int, iters_per_stage, delta_decay: float = 10.0):

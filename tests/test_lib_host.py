@@ -136,3 +136,8 @@ def test_runtime_check_detects_a_foreign_hip_runtime():
     if running // 100000 == built // 100000:
         pytest.skip(f"torch bundles the same HIP runtime version ({running})")
     assert st == P.PSARA_EDEVICE
+
+
+def test_tuning_cache_is_empty_without_tuning():
+    assert P.psara_tuning_lookup(256, 200000, 8, 4) is None
+    assert set(P.DEFAULT_TUNING) == {k for k, _ in P.PsaraTuning._fields_}

@@ -108,6 +108,8 @@ struct ProbDesc {
   void* gpart;            // gridding partial slots: n_slots x (kGridTile + T - 1)^2 cells, k2-major
   const int4* chunks;     // gridding chunks {tile, first run, end run, partial slot}
   const int2* tile_slots; // per gridding tile: {first partial slot, count} (count 0: no visibilities)
+  const int* slot_box;    // per partial slot: the cells its chunk's windows cover (pack_box), offsets in the region
+  const int* tile_box;    // per gridding tile: the union of its slots' boxes
   const void* kbpoly;     // T x (deg+1) per-tap kernel polynomial coefficients (ascending), type R
   const void* twiddle;    // K complex exp(-2 pi i j / K), type R
   const void* deapod;     // n scaling factors 1/psi_hat((j - n/2)/K), type R
@@ -117,6 +119,17 @@ struct ProbDesc {
   double* scal;           // NUM_SCALARS
   long long ll_off[kMaxLevels + 1];  // element offset of level l's LL inside a basis block
 };
+
+// The cells a gridding chunk's windows cover inside its (kGridTile + T - 1)^2 region: k1 offsets
+// [lo1, hi1] and k2 offsets [lo2, hi2], one byte each.  The gridding writes only these cells of
+// its slot (the others hold zero), and the column inverse FFT skips a tile's slots at cells
+// outside the union of their boxes.
+__host__ __device__ constexpr int pack_box(int lo1, int hi1, int lo2, int hi2) {
+  return lo1 | (hi1 << 8) | (lo2 << 16) | (hi2 << 24);
+}
+__host__ __device__ inline bool in_box(int box, int o1, int o2) {
+  return o1 >= (box & 255) && o1 <= ((box >> 8) & 255) && o2 >= ((box >> 16) & 255) && o2 <= ((box >> 24) & 255);
+}
 
 // --------------------------------------------------------------------------------------------
 // small vector types

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <limits>
 #include <numeric>
 #include <random>
 #include <string>
@@ -96,7 +97,7 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
 void build_grid_chunks(Geometry& g, int chunk_entries) {
   const int ntg = g.ntsg * g.ntsg;
   g.run_beg.clear(); g.run_len.clear(); g.run_k0.clear();
-  g.chunks.clear(); g.chunk_ent.clear(); g.tile_slots.clear();
+  g.chunks.clear(); g.chunk_ent.clear(); g.tile_slots.clear(); g.slot_box.clear(); g.tile_box.clear();
   g.n_slots = 0;
   g.chunk_entries = chunk_entries;
   // runs: consecutive list entries of a tile with the same window start (their taps hit the
@@ -113,6 +114,7 @@ void build_grid_chunks(Geometry& g, int chunk_entries) {
       e = f;
     }
     const int first_slot = g.n_slots;
+    int u_lo1 = 255, u_hi1 = 0, u_lo2 = 255, u_hi2 = 0;   // union of the tile's boxes (empty: none)
     size_t r = 0;
     while (r < runs.size()) {
       const size_t r0 = r;
@@ -122,17 +124,29 @@ void build_grid_chunks(Geometry& g, int chunk_entries) {
                        [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.second > y.second; });
       const int base = (int)g.run_beg.size();
       int lo = g.list_ptr[t + 1], hi = g.list_ptr[t];
+      // the cells the chunk's windows cover, as offsets in the tile's region
+      const int b1 = (t / g.ntsg) * kGridTile, b2 = (t % g.ntsg) * kGridTile;
+      int lo1 = kGridTile, hi1 = 0, lo2 = kGridTile, hi2 = 0;
       for (size_t q = r0; q < r; ++q) {
+        const int pk = g.k0[g.list_idx[runs[q].first]];
         g.run_beg.push_back(runs[q].first);
         g.run_len.push_back(runs[q].second);
-        g.run_k0.push_back(g.k0[g.list_idx[runs[q].first]]);
+        g.run_k0.push_back(pk);
         lo = std::min(lo, runs[q].first);
         hi = std::max(hi, runs[q].first + runs[q].second);
+        lo1 = std::min(lo1, (pk >> 16) - b1);
+        hi1 = std::max(hi1, (pk >> 16) - b1);
+        lo2 = std::min(lo2, (pk & 0xffff) - b2);
+        hi2 = std::max(hi2, (pk & 0xffff) - b2);
       }
+      g.slot_box.push_back(pack_box(lo1, hi1 + g.T - 1, lo2, hi2 + g.T - 1));
+      u_lo1 = std::min(u_lo1, lo1); u_hi1 = std::max(u_hi1, hi1 + g.T - 1);
+      u_lo2 = std::min(u_lo2, lo2); u_hi2 = std::max(u_hi2, hi2 + g.T - 1);
       g.chunks.push_back(make_int4(t, base, base + (int)(r - r0), g.n_slots++));
       g.chunk_ent.push_back(make_int2(lo, hi));
     }
     g.tile_slots.push_back(make_int2(first_slot, g.n_slots - first_slot));
+    g.tile_box.push_back(pack_box(u_lo1, u_hi1, u_lo2, u_hi2));
   }
 }
 
@@ -148,6 +162,19 @@ void check_tuning(const Tuning& t, int K) {
 
 // ------------------------------------------------------------------------------------------------
 // work lists (appended per problem, so batches concatenate them)
+
+// Orders gridding items: the factor items first, then the chunks by decreasing work (entries
+// plus a flush cost per run), so the heaviest start first and the tail is short.  geo_of(prob)
+// gives the geometry of an item's problem.
+template <typename It, typename GeoOf>
+void order_grid_items(It begin, It end, GeoOf geo_of) {
+  auto cost = [&](const int4& it) -> long long {
+    if (it.y < 0) return std::numeric_limits<long long>::max();
+    const Geometry& g = *geo_of(it.x);
+    return (g.chunk_ent[it.y].y - g.chunk_ent[it.y].x) + 3LL * (g.chunks[it.y].z - g.chunks[it.y].y);
+  };
+  std::stable_sort(begin, end, [&](const int4& a, const int4& b) { return cost(a) > cost(b); });
+}
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int dg_item, int* n_p6) {
   const int n = g.n, K = g.K, N = n * n;
   const int lines = cells / K, rlines = rcells / K;
@@ -160,15 +187,13 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += dg_item) S.p6.push_back(make_int4(prob, t, v, part++));
   }
   // gridding: first the item that stores the pass's scalar factor, then the chunks heaviest
-  // first (entries plus a flush cost per run as the work estimate) so the tail is short
-  std::vector<int> order(g.chunks.size());
-  std::iota(order.begin(), order.end(), 0);
-  auto cost = [&](int c) {
-    return (g.chunk_ent[c].y - g.chunk_ent[c].x) + 3 * (g.chunks[c].z - g.chunks[c].y);
-  };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  // first so the tail is short
+  const size_t first = S.p7.size();
   S.p7.push_back(make_int4(prob, -1, 0, 0));
-  for (size_t c = 0; c < order.size(); ++c) S.p7.push_back(make_int4(prob, order[c], 0, 0));
+  for (size_t c = 0; c < g.chunks.size(); ++c)
+    S.p7.push_back(make_int4(prob, (int)c, g.chunk_ent[c].x, g.chunk_ent[c].y));
+  const Geometry* geo = &g;
+  order_grid_items(S.p7.begin() + first, S.p7.end(), [geo](int) { return geo; });
   *n_p6 = part;
 }
 
@@ -362,14 +387,20 @@ template <typename R>
 void Engine<R>::upload_chunks() {
   const Geometry& g = geo_;
   dfree((void*)h_.run_beg); dfree((void*)h_.run_len); dfree((void*)h_.run_k0);
-  dfree((void*)h_.chunk_ent); dfree((void*)h_.tile_slots); dfree((void*)h_.chunks); dfree(h_.gpart);
+  dfree((void*)h_.chunk_ent); dfree((void*)h_.tile_slots); dfree((void*)h_.chunks); dfree((void*)h_.slot_box);
+  dfree((void*)h_.tile_box); dfree(h_.gpart);
   h_.run_beg = upload<int>(g.run_beg.data(), std::max<size_t>(1, g.run_beg.size()));
   h_.run_len = upload<int>(g.run_len.data(), std::max<size_t>(1, g.run_len.size()));
   h_.run_k0 = upload<int>(g.run_k0.data(), std::max<size_t>(1, g.run_k0.size()));
   h_.chunk_ent = upload<int2>(g.chunk_ent.data(), std::max<size_t>(1, g.chunk_ent.size()));
   h_.tile_slots = upload<int2>(g.tile_slots.data(), std::max<size_t>(1, g.tile_slots.size()));
   h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
-  h_.gpart = dalloc<Cell<R>>((size_t)std::max(g.n_slots, 1) * (kGridTile + g.T - 1) * (kGridTile + g.T - 1));
+  h_.slot_box = upload<int>(g.slot_box.data(), std::max<size_t>(1, g.slot_box.size()));
+  h_.tile_box = upload<int>(g.tile_box.data(), std::max<size_t>(1, g.tile_box.size()));
+  // the gridding writes only the cells of a slot's box; the rest stay zero from here on
+  const size_t cells = (size_t)std::max(g.n_slots, 1) * (kGridTile + g.T - 1) * (kGridTile + g.T - 1);
+  h_.gpart = dalloc<Cell<R>>(cells);
+  zero(h_.gpart, cells * sizeof(Cell<R>));
   h_.n_slots = g.n_slots;
 }
 
@@ -909,10 +940,10 @@ void Engine<R>::run_in_scratch(int mode, int iters, void* scr, size_t cap) {
   desc_dirty_ = true;
   try {
     sync_desc();
-    // every pass writes the slots and partial sums it reads later in the same iteration; the
-    // partial sums are cleared anyway, by a kernel (so the call records no memset node when a
-    // caller captures it)
-    launch_fill<double>(h_.partials, (need - ((slots + 255) & ~(size_t)255)) / sizeof(double), s0_);
+    // the gridding writes only the cells of each slot's box and the column inverse FFT reads
+    // the rest of a tile's region as zero, so the slots are cleared, and the partial sums with
+    // them, by a kernel (so the call records no memset node when a caller captures it)
+    launch_fill<double>(scr, need / sizeof(double), s0_);
     if (iters > 0) prime(mode);
     launch_iterations(mode, iters);
     hip_check(hipGetLastError(), "iteration launch");
@@ -1317,6 +1348,8 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
                       std::is_same<R, double>::value, e->c_level(), e->tuning().ana_wide != 0, &nap);
     }
   }
+  // the gridding launch takes the heaviest chunks of all members first
+  order_grid_items(S.p7.begin(), S.p7.end(), [this](int prob) { return &members_[prob]->geometry(); });
   auto up = [&](DevItems& d, const std::vector<int4>& v) {
     d.count = (int)v.size();
     d.ptr = nullptr;

@@ -35,6 +35,8 @@ struct Geometry {
   std::vector<int4> chunks;              // {tile, first run, end run, partial slot}
   std::vector<int2> chunk_ent;           // list-entry range [lo, hi) each chunk covers
   std::vector<int2> tile_slots;          // per gridding tile {first partial slot, count}
+  std::vector<int> slot_box;             // per slot: the region cells its chunk covers (pack_box)
+  std::vector<int> tile_box;             // per gridding tile: the union of its slots' boxes
   int n_slots = 0;
   int chunk_entries = kChunkEntries;     // the chunk size the runs and chunks were cut for
 };

@@ -164,10 +164,11 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   Cell<R>* __restrict__ grid = (Cell<R>*)P.grid;
   const int nthr = CELLS / 2;
 
-  // the partial-slot table of the gridding tiles this workgroup's lines read (their tile rows
-  // and the rows before them), staged once so the per-cell gathers index LDS
+  // the partial-slot table and the slot-box unions of the gridding tiles this workgroup's lines
+  // read (their tile rows and the rows before them), staged once so the per-cell gathers index LDS
   constexpr int kTslMax = CELLS / 256 + 2048 / 8;
   __shared__ int2 tsl[PASS == 2 ? kTslMax : 1];
+  __shared__ int tbx[PASS == 2 ? kTslMax : 1];
   __shared__ double red[PASS == 2 ? 2 * ((CELLS / 2 + 63) / 64) : 1];
   int trow0 = 0;
   R gfac = R(1);
@@ -195,6 +196,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
     for (int i = threadIdx.x; i < ntr * ntg; i += nthr) {
       const int rr = i / ntg, u1 = i - rr * ntg;
       tsl[i] = P.tile_slots[u1 * ntg + (trow0 + rr + ntg) % ntg];
+      tbx[i] = P.tile_box[u1 * ntg + (trow0 + rr + ntg) % ntg];
     }
     __syncthreads();
   }
@@ -232,6 +234,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
           if (o1 >= RG || o2 >= RG) continue;
           const int s1 = (t1 - d1 + ntg) % ntg;
           const int2 ts = tsl[(t2 - d2 - trow0) * ntg + s1];
+          if (!in_box(tbx[(t2 - d2 - trow0) * ntg + s1], o1, o2)) continue;   // no slot of the tile reaches it
           const Cell<R>* part = (const Cell<R>*)P.gpart + (size_t)ts.x * RG * RG + o2 * RG + o1;
 #pragma unroll 4
           for (int sl = 0; sl < ts.y; ++sl) {

@@ -252,23 +252,28 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 // also kept for the next iteration; GR_PLAIN: 1, or the stored c when use_cfac is set;
 // GR_STOKES: 1.
 //
-// Nearest 64-bit integer of an (already scaled) value.  FP32 data (|y| < 2^50): adding
-// 1.5 * 2^52 rounds y to an integer held in the low mantissa bits of the sum; subtracting the
-// bit pattern of 1.5 * 2^52 leaves it as a two's-complement integer (two instructions).  FP64
-// data use the full 2^61 range and the exact conversion.
-// conv(a, fx) is the nearest integer of a * fx, fx a power of two (so a * fx is exact and the
-// FP32 path needs one fused multiply-add and a 64-bit subtraction).
+// Fixed-point terms of the LDS accumulation: conv(a, fx) is the term of a * fx (fx a power of
+// two, so a * fx is exact), value(sum) the nearest-integer sum of the terms it received.
+// FP32 data: the term is the bit pattern of the double 1.5 * 2^52 + a * fx, whose mantissa holds
+// rint(a * fx) (|a * fx| < 2^51) -- one conversion and one fused multiply-add.  That pattern is
+// the integer 0x867 * 2^51 + rint(a * fx), so the 64-bit sum of any number of terms equals the
+// sum of the roundings modulo 2^51, and with |sum| < 2^50 (the scale keeps it below 2^48 times
+// the largest tap product, which is at most 1) sign-extending its low 51 bits recovers it
+// exactly, whatever the order of the additions.  FP64 data use the exact conversion and a range
+// of 2^61.
 template <typename R> struct Fixed;
 template <> struct Fixed<float> {
-  static constexpr int kRange = 49;
-  __device__ static long long conv(float a, double fx) {
+  static constexpr int kRange = 48;
+  __device__ static unsigned long long conv(float a, double fx) {
     constexpr double kMagic = 6755399441055744.0;          // 1.5 * 2^52
-    return __double_as_longlong(__fma_rn((double)a, fx, kMagic)) - __double_as_longlong(kMagic);
+    return (unsigned long long)__double_as_longlong(__fma_rn((double)a, fx, kMagic));
   }
+  __device__ static long long value(unsigned long long sum) { return (long long)(sum << 13) >> 13; }
 };
 template <> struct Fixed<double> {
   static constexpr int kRange = 61;
-  __device__ static long long conv(double a, double fx) { return __double2ll_rn(a * fx); }
+  __device__ static unsigned long long conv(double a, double fx) { return (unsigned long long)__double2ll_rn(a * fx); }
+  __device__ static long long value(unsigned long long sum) { return (long long)sum; }
 };
 
 // The exponent E of the chunk's fixed-point scale 2^E, with 2^E * total <= 2^kRange (total: the
@@ -278,31 +283,60 @@ __device__ inline int fixed_exponent(double total) {
   return total > 0.0 ? min(Fixed<R>::kRange - (int)ceil(log2(total * (1.0 + 1e-6))), 100) : 0;
 }
 
+// What a gridding workgroup loads before its entries are staged (so those loads overlap the
+// staging's): this lane's tap polynomial, its group's first run, and the chunk's box.
+template <typename R>
+struct ChunkPre {
+  R cr[KbDeg<R>::value + 1];
+  int beg = 0, len = 0, k0 = 0;
+  int box = 0;
+};
+
+template <typename R, int T>
+__device__ inline void chunk_preload(const ProbDesc& P, const int4 ch, ChunkPre<R>& pre) {
+  constexpr int DEG = KbDeg<R>::value;
+  const int lane8 = threadIdx.x & 7;
+  const R* __restrict__ poly = (const R*)P.kbpoly + (lane8 < T ? lane8 : 0) * (DEG + 1);
+#pragma unroll
+  for (int k = 0; k <= DEG; ++k) pre.cr[k] = lane8 < T ? poly[k] : R(0);
+  const int rr = ch.y + (threadIdx.x >> 3);
+  if (rr < ch.z) {
+    pre.beg = P.run_beg[rr];
+    pre.len = P.run_len[rr];
+    pre.k0 = P.run_k0[rr];
+  }
+  pre.box = P.slot_box[ch.w];
+}
+
 // Accumulates a chunk whose rows are staged in LDS (sf: fractional offsets, su: two V4 of
 // gridded channels per entry, entry q at list position ent.x + q) into acc, which must be zero,
-// and writes the region to the chunk's partial slot.  Called by the whole workgroup.
+// and writes the cells of the chunk's box to its partial slot (the slot's other cells are zero
+// from the allocation on and stay so).  Called by the whole workgroup.
 template <typename R, int T>
 __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 ent, int b1, int b2,
-                                  const V2<R>* sf, const V4<R>* su, unsigned long long* acc, int E) {
+                                  const V2<R>* sf, const V4<R>* su, unsigned long long* acc, int E,
+                                  const ChunkPre<R>& pre) {
   constexpr int RG = kGridTile + T - 1;
   constexpr int DEG = KbDeg<R>::value;
   const double fx = ldexp(1.0, E);
   const int lane8 = threadIdx.x & 7;               // tap row owned by this lane
   const int grp = threadIdx.x >> 3, ngrp = blockDim.x >> 3;
-  R cr[DEG + 1];                                   // this lane's tap polynomial
-  {
-    const R* __restrict__ poly = (const R*)P.kbpoly + (lane8 < T ? lane8 : 0) * (DEG + 1);
-#pragma unroll
-    for (int k = 0; k <= DEG; ++k) cr[k] = lane8 < T ? poly[k] : R(0);
-  }
   // FP64 accumulates a run's eight channels in two passes of four (T x 8 doubles would not stay
   // in registers); each channel's sum is the same either way
   constexpr int NC = sizeof(R) == 8 ? 4 : 8;
+  int rbeg = pre.beg, rlen = pre.len, rk0 = pre.k0;
   for (int rr = ch.y + grp; rr - grp < ch.z; rr += ngrp) {
     const bool active = rr < ch.z;
-    const int e0 = active ? P.run_beg[rr] - ent.x : 0;
-    const int len = active ? P.run_len[rr] : 0;
-    const int pk = active ? P.run_k0[rr] : 0;
+    const int e0 = active ? rbeg - ent.x : 0;
+    const int len = active ? rlen : 0;
+    const int pk = active ? rk0 : 0;
+    // the group's next run, loaded while this one accumulates
+    const int nr = rr + ngrp;
+    if (nr < ch.z) {
+      rbeg = P.run_beg[nr];
+      rlen = P.run_len[nr];
+      rk0 = P.run_k0[nr];
+    }
     // (one pass of eight channels, or in FP64 one pass per staged V4 of four)
 #pragma unroll 1
     for (int c0 = 0; c0 < 8; c0 += NC) {
@@ -314,8 +348,8 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
       for (int q = 0; q < len; ++q) {
         const V2<R> f = sf[e0 + q];
         // this lane's tap in each dimension: psi(f - lane8) from its polynomial
-        const R w1 = kb_tap<R, T>(R(2) * f.x - R(T - 1), cr);
-        const R w2 = kb_tap<R, T>(R(2) * f.y - R(T - 1), cr);
+        const R w1 = kb_tap<R, T>(R(2) * f.x - R(T - 1), pre.cr);
+        const R w2 = kb_tap<R, T>(R(2) * f.y - R(T - 1), pre.cr);
         R u[NC];
         const V4<R> v0 = su[2 * (e0 + q) + (NC == 8 ? 0 : c0 / 4)];
         u[0] = v0.x; u[1] = v0.y; u[2] = v0.z; u[3] = v0.w;
@@ -345,8 +379,7 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
             asm volatile("" : "+v"(a[j][0]), "+v"(a[j][1]), "+v"(a[j][2]), "+v"(a[j][3]) :: "memory");
           }
 #pragma unroll
-          for (int c = 0; c < NC; ++c)
-            atomicAdd(cell + (c0 + c) * RG * RG, (unsigned long long)Fixed<R>::conv(a[j][c], fx));
+          for (int c = 0; c < NC; ++c) atomicAdd(cell + (c0 + c) * RG * RG, Fixed<R>::conv(a[j][c], fx));
         }
       }
     }
@@ -355,11 +388,12 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
   Cell<R>* __restrict__ dst = (Cell<R>*)P.gpart + (size_t)ch.w * RG * RG;
   const double inv = ldexp(1.0, -E);
   for (int q = threadIdx.x; q < RG * RG; q += blockDim.x) {
+    if (!in_box(pre.box, q % RG, q / RG)) continue;
     Cell<R> c;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-      c.s[s] = cmk(R((double)(long long)acc[(2 * s) * RG * RG + q] * inv),
-                   R((double)(long long)acc[(2 * s + 1) * RG * RG + q] * inv));
+      c.s[s] = cmk(R((double)Fixed<R>::value(acc[(2 * s) * RG * RG + q]) * inv),
+                   R((double)Fixed<R>::value(acc[(2 * s + 1) * RG * RG + q]) * inv));
     dst[q] = c;
   }
 }
@@ -379,8 +413,8 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   __shared__ double red[2 * (kGridThreads / 64)];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
-  if (halted(P)) return;                 // stopped by an adaptive run
   if (it.y < 0) {                  // the factor item: the factor the column inverse FFT applies
+    if (halted(P)) return;         // stopped by an adaptive run
     if (MODE == GR_DUAL) {
       const double v2 = block_sum_partials(P.partials, P.n_p6, red);
       if (threadIdx.x == 0) {
@@ -395,29 +429,51 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     }
     return;
   }
+  // a chunk item carries its entry range; everything the chunk reads is requested before the
+  // halt test so the loads are in flight together (a thread's entries are q and q + blockDim.x)
+  static_assert(kChunkEntries <= 2 * kGridThreads, "two entries per thread");
+  const int2 ent = make_int2(it.z, it.w);
+  const int ne = ent.y - ent.x;
+  int me[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int q = threadIdx.x + e * blockDim.x;
+    me[e] = q < ne ? P.list_idx[ent.x + q] : 0;
+  }
   const int4 ch = P.chunks[it.y];
-  const int2 ent = P.chunk_ent[it.y];
+  ChunkPre<R> pre;
+  chunk_preload<R, T>(P, ch, pre);
+  if (halted(P)) return;                 // stopped by an adaptive run
   const int ntg = P.ntile_side_g;
   const int t1 = ch.x / ntg, t2 = ch.x - t1 * ntg;
   const int b1 = t1 * kGridTile, b2 = t2 * kGridTile;
-  for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
 
   // stage the chunk's entries: offsets and gridded channels; sum the largest channel magnitude
   // of each for the fixed point
   const Cell<R>* __restrict__ bsrc = (const Cell<R>*)P.vis[src_slot];
   const V2<R>* __restrict__ frac = (const V2<R>*)P.vis_frac;
+  V2<R> fe[2];
+  Cell<R> be[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    fe[e] = frac[me[e]];
+    be[e] = bsrc[me[e]];
+  }
+  for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
   KSum bound;
-  for (int q = threadIdx.x; q < ent.y - ent.x; q += blockDim.x) {
-    const int m = P.list_idx[ent.x + q];
-    sf[q] = frac[m];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int q = threadIdx.x + e * blockDim.x;
+    if (q >= ne) break;
+    sf[q] = fe[e];
     V4<R> u0, u1;
-    const R mx = grid_channels<R, MODE>(P, m, bsrc[m], u0, u1);
+    const R mx = grid_channels<R, MODE>(P, me[e], be[e], u0, u1);
     su[2 * q] = u0;
     su[2 * q + 1] = u1;
     bound.add((double)mx);
   }
   const double total = block_reduce(bound, red).value();      // includes a barrier
-  grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total));
+  grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total), pre);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -447,7 +503,9 @@ degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ 
   const ProbDesc& P = descs[it.x];
   if (halted(P) || it.y < 0) return;
   const int4 ch = P.chunks[it.y];
-  const int2 ent = P.chunk_ent[it.y];
+  const int2 ent = make_int2(it.z, it.w);       // the chunk's entry range, carried by the item
+  ChunkPre<R> pre;
+  chunk_preload<R, T>(P, ch, pre);
   const int K = P.K, ntg = P.ntile_side_g;
   const int t1 = ch.x / ntg, t2 = ch.x - t1 * ntg;
   const int b1 = t1 * kGridTile, b2 = t2 * kGridTile;
@@ -507,7 +565,7 @@ degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ 
   const double total = block_reduce(bound, red).value();
   for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
   __syncthreads();
-  grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total));
+  grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total), pre);
 }
 
 // dynamic LDS of the gridding kernels: the staged offsets and mixed values of ce entries

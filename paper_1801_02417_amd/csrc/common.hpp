@@ -19,6 +19,9 @@ constexpr int kMaxLevels = 8;
 constexpr int kRunMax = 32;         // longest run of same-window visibilities one lane group takes
 constexpr int kChunkEntries = 1024; // largest gridding chunk (entries per workgroup, staged in LDS)
 constexpr int kGridThreads = 512;   // threads per gridding workgroup (64 lane groups of 8)
+constexpr int kSmallChunk = 16;     // a chunk of at most this many entries is gridded by one wave
+constexpr int kGridFactorItem = -1;  // gridding work item that stores the pass's factor
+constexpr int kGridSmallItem = -2;   // gridding work item of up to eight small chunks, one per wave
 constexpr int kBatchChunk = 8;       // iterations per captured graph of a batch
 constexpr int kChain = 32;           // iterations per captured chain of a single solve
 constexpr int kMaxDegridTile = 32;  // largest de-gridding tile side (the geometry picks 16 or 32)
@@ -110,6 +113,7 @@ struct ProbDesc {
   const int2* tile_slots; // per gridding tile: {first partial slot, count} (count 0: no visibilities)
   const int* slot_box;    // per partial slot: the cells its chunk's windows cover (pack_box), offsets in the region
   const int* tile_box;    // per gridding tile: the union of its slots' boxes
+  const int* small_ids;   // the chunks of at most kSmallChunk entries, heaviest first (eight per work item)
   const void* kbpoly;     // T x (deg+1) per-tap kernel polynomial coefficients (ascending), type R
   const void* twiddle;    // K complex exp(-2 pi i j / K), type R
   const void* deapod;     // n scaling factors 1/psi_hat((j - n/2)/K), type R

@@ -97,7 +97,7 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
 void build_grid_chunks(Geometry& g, int chunk_entries) {
   const int ntg = g.ntsg * g.ntsg;
   g.run_beg.clear(); g.run_len.clear(); g.run_k0.clear();
-  g.chunks.clear(); g.chunk_ent.clear(); g.tile_slots.clear(); g.slot_box.clear(); g.tile_box.clear();
+  g.chunks.clear(); g.chunk_ent.clear(); g.tile_slots.clear(); g.slot_box.clear(); g.tile_box.clear(); g.small_ids.clear();
   g.n_slots = 0;
   g.chunk_entries = chunk_entries;
   // runs: consecutive list entries of a tile with the same window start (their taps hit the
@@ -148,6 +148,12 @@ void build_grid_chunks(Geometry& g, int chunk_entries) {
     g.tile_slots.push_back(make_int2(first_slot, g.n_slots - first_slot));
     g.tile_box.push_back(pack_box(u_lo1, u_hi1, u_lo2, u_hi2));
   }
+  // the small chunks, gridded one per wave, heaviest first
+  for (int c = 0; c < (int)g.chunks.size(); ++c)
+    if (g.chunk_ent[c].y - g.chunk_ent[c].x <= kSmallChunk) g.small_ids.push_back(c);
+  std::stable_sort(g.small_ids.begin(), g.small_ids.end(), [&](int a, int b) {
+    return g.chunk_ent[a].y - g.chunk_ent[a].x > g.chunk_ent[b].y - g.chunk_ent[b].x;
+  });
 }
 
 void check_tuning(const Tuning& t, int K) {
@@ -164,13 +170,18 @@ void check_tuning(const Tuning& t, int K) {
 // work lists (appended per problem, so batches concatenate them)
 
 // Orders gridding items: the factor items first, then the chunks by decreasing work (entries
-// plus a flush cost per run), so the heaviest start first and the tail is short.  geo_of(prob)
-// gives the geometry of an item's problem.
+// plus a flush cost per run), so the heaviest start first and the tail is short, then the items
+// of small chunks (eight chunks each, one per wave) by decreasing entries of their first chunk.
+// geo_of(prob) gives the geometry of an item's problem.
 template <typename It, typename GeoOf>
 void order_grid_items(It begin, It end, GeoOf geo_of) {
   auto cost = [&](const int4& it) -> long long {
-    if (it.y < 0) return std::numeric_limits<long long>::max();
+    if (it.y == kGridFactorItem) return std::numeric_limits<long long>::max();
     const Geometry& g = *geo_of(it.x);
+    if (it.y == kGridSmallItem) {
+      const int c = g.small_ids[it.z];
+      return (long long)(g.chunk_ent[c].y - g.chunk_ent[c].x) - (1LL << 40);
+    }
     return (g.chunk_ent[it.y].y - g.chunk_ent[it.y].x) + 3LL * (g.chunks[it.y].z - g.chunks[it.y].y);
   };
   std::stable_sort(begin, end, [&](const int4& a, const int4& b) { return cost(a) > cost(b); });
@@ -187,13 +198,22 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += dg_item) S.p6.push_back(make_int4(prob, t, v, part++));
   }
   // gridding: first the item that stores the pass's scalar factor, then the chunks heaviest
-  // first so the tail is short
-  const size_t first = S.p7.size();
-  S.p7.push_back(make_int4(prob, -1, 0, 0));
-  for (size_t c = 0; c < g.chunks.size(); ++c)
-    S.p7.push_back(make_int4(prob, (int)c, g.chunk_ent[c].x, g.chunk_ent[c].y));
+  // first so the tail is short, a chunk item carrying its entry range; the grid pass takes the
+  // small chunks eight to an item {prob, kGridSmallItem, first of small_ids, count}, the fused
+  // de-grid + grid pass every chunk as an item of its own
   const Geometry* geo = &g;
+  const size_t first = S.p7.size(), first_f = S.p7f.size();
+  S.p7.push_back(make_int4(prob, kGridFactorItem, 0, 0));
+  S.p7f.push_back(make_int4(prob, kGridFactorItem, 0, 0));
+  for (size_t c = 0; c < g.chunks.size(); ++c) {
+    const int4 item = make_int4(prob, (int)c, g.chunk_ent[c].x, g.chunk_ent[c].y);
+    S.p7f.push_back(item);
+    if (item.w - item.z > kSmallChunk) S.p7.push_back(item);
+  }
+  const int ns = (int)g.small_ids.size(), per = kGridThreads / 64;
+  for (int i = 0; i < ns; i += per) S.p7.push_back(make_int4(prob, kGridSmallItem, i, std::min(per, ns - i)));
   order_grid_items(S.p7.begin() + first, S.p7.end(), [geo](int) { return geo; });
+  order_grid_items(S.p7f.begin() + first_f, S.p7f.end(), [geo](int) { return geo; });
   *n_p6 = part;
 }
 
@@ -342,7 +362,8 @@ template <typename R>
 template <typename T>
 T* Engine<R>::upload(const T* host, size_t count) {
   T* d = dalloc<T>(count);
-  copy_sync(d, host, count * sizeof(T), hipMemcpyHostToDevice, s0_, "hipMemcpy H2D");
+  if (host) copy_sync(d, host, count * sizeof(T), hipMemcpyHostToDevice, s0_, "hipMemcpy H2D");
+  else zero(d, std::max<size_t>(count, 1) * sizeof(T));   // an empty list's placeholder
   return d;
 }
 
@@ -388,7 +409,7 @@ void Engine<R>::upload_chunks() {
   const Geometry& g = geo_;
   dfree((void*)h_.run_beg); dfree((void*)h_.run_len); dfree((void*)h_.run_k0);
   dfree((void*)h_.chunk_ent); dfree((void*)h_.tile_slots); dfree((void*)h_.chunks); dfree((void*)h_.slot_box);
-  dfree((void*)h_.tile_box); dfree(h_.gpart);
+  dfree((void*)h_.tile_box); dfree((void*)h_.small_ids); dfree(h_.gpart);
   h_.run_beg = upload<int>(g.run_beg.data(), std::max<size_t>(1, g.run_beg.size()));
   h_.run_len = upload<int>(g.run_len.data(), std::max<size_t>(1, g.run_len.size()));
   h_.run_k0 = upload<int>(g.run_k0.data(), std::max<size_t>(1, g.run_k0.size()));
@@ -397,6 +418,7 @@ void Engine<R>::upload_chunks() {
   h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));
   h_.slot_box = upload<int>(g.slot_box.data(), std::max<size_t>(1, g.slot_box.size()));
   h_.tile_box = upload<int>(g.tile_box.data(), std::max<size_t>(1, g.tile_box.size()));
+  h_.small_ids = upload<int>(g.small_ids.data(), std::max<size_t>(1, g.small_ids.size()));
   // the gridding writes only the cells of a slot's box; the rest stay zero from here on
   const size_t cells = (size_t)std::max(g.n_slots, 1) * (kGridTile + g.T - 1) * (kGridTile + g.T - 1);
   h_.gpart = dalloc<Cell<R>>(cells);
@@ -407,6 +429,7 @@ void Engine<R>::upload_chunks() {
 template <typename R>
 void Engine<R>::build_operator_items() {
   items_.img.clear(); items_.rows.clear(); items_.cols.clear(); items_.p6.clear(); items_.p7.clear();
+  items_.p7f.clear();
   add_operator_items(items_, 0, geo_, cells_, rcells_, tuning_.degrid_item, &h_.n_p6);
 }
 
@@ -457,7 +480,7 @@ void Engine<R>::upload_items() {
     if (!v.empty()) d.ptr = upload<int4>(v.data(), v.size());
   };
   up(d_img_, items_.img); up(d_rows_, xcd_contiguous(items_.rows)); up(d_cols_, items_.cols);
-  up(d_p6_, items_.p6); up(d_p7_, items_.p7);
+  up(d_p6_, items_.p6); up(d_p7_, items_.p7); up(d_p7f_, items_.p7f);
   up(d_dirac_, items_.dirac); up(d_synfinal_, items_.synfinal); up(d_synsplit_, items_.synsplit);
   up(d_coarse_, items_.coarse);
   for (int l = 0; l <= kMaxLevels; ++l) {
@@ -467,7 +490,7 @@ void Engine<R>::upload_items() {
   if (!d_desc_) d_desc_ = dalloc<ProbDesc>(1);
   desc_dirty_ = true;
   pl_.descs = d_desc_;
-  pl_.img = d_img_; pl_.rows = d_rows_; pl_.cols = d_cols_; pl_.p6 = d_p6_; pl_.p7 = d_p7_;
+  pl_.img = d_img_; pl_.rows = d_rows_; pl_.cols = d_cols_; pl_.p6 = d_p6_; pl_.p7 = d_p7_; pl_.p7f = d_p7f_;
   pl_.synfinal = d_synsplit_; pl_.coarse = d_coarse_;
   for (int l = 0; l <= kMaxLevels; ++l) { pl_.ana_d[l] = d_ana_d_[l]; pl_.syn_d[l] = d_syn_d_[l]; }
   pl_.cells = cells_; pl_.rcells = rcells_;
@@ -667,8 +690,8 @@ template <typename R>
 void launch_p6_p8(const PassLists& L, int mode, hipStream_t s) {
   const bool tvm = pm_tv(mode);
   if (fused_p6_p7(L, mode)) {
-    if (tvm) launch_degrid_grid<R>(GR_STOKES, lists_la(L, L.p7, s), L.taps, VIS_Y, VIS_R);
-    else launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7, s), L.taps, VIS_BV, VIS_BV);
+    if (tvm) launch_degrid_grid<R>(GR_STOKES, lists_la(L, L.p7f, s), L.taps, VIS_Y, VIS_R);
+    else launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7f, s), L.taps, VIS_BV, VIS_BV);
     launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, tvm ? 2 : 1, 0);
   } else {
     launch_degrid<R>(DG_DUAL, lists_la(L, L.p6, s), L.max_ts, L.taps, VIS_BV, VIS_BV);
@@ -1255,7 +1278,7 @@ void profile_iterations(const PassLists& L, int mode, int iters, hipStream_t s, 
   auto p5_p8_run = [&]() {
     launch_fft<R>(1, lists_la(L, L.cols, s), L.cells, 0, 0);
     hip_check(hipEventRecord(ev[2], s), "event record");
-    if (fused) launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7, s), L.taps, VIS_BV, VIS_BV);
+    if (fused) launch_degrid_grid<R>(GR_DUAL, lists_la(L, L.p7f, s), L.taps, VIS_BV, VIS_BV);
     hip_check(hipEventRecord(ev[3], s), "event record");
     if (fused) launch_fft<R>(2, lists_la(L, L.cols, s), L.cells, 1, 0);
     else launch_p6_p8<R>(L, mode, s);
@@ -1348,8 +1371,9 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
                       std::is_same<R, double>::value, e->c_level(), e->tuning().ana_wide != 0, &nap);
     }
   }
-  // the gridding launch takes the heaviest chunks of all members first
+  // the gridding launches take the heaviest chunks of all members first
   order_grid_items(S.p7.begin(), S.p7.end(), [this](int prob) { return &members_[prob]->geometry(); });
+  order_grid_items(S.p7f.begin(), S.p7f.end(), [this](int prob) { return &members_[prob]->geometry(); });
   auto up = [&](DevItems& d, const std::vector<int4>& v) {
     d.count = (int)v.size();
     d.ptr = nullptr;
@@ -1364,7 +1388,7 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
     d.ptr = (int4*)p;
   };
   up(pl_.img, S.img); up(pl_.rows, xcd_contiguous(S.rows)); up(pl_.cols, S.cols);
-  up(pl_.p6, S.p6); up(pl_.p7, S.p7); up(pl_.synfinal, S.synsplit); up(pl_.coarse, S.coarse);
+  up(pl_.p6, S.p6); up(pl_.p7, S.p7); up(pl_.p7f, S.p7f); up(pl_.synfinal, S.synsplit); up(pl_.coarse, S.coarse);
   for (int l = 0; l <= kMaxLevels; ++l) { up(pl_.ana_d[l], S.ana_d[l]); up(pl_.syn_d[l], S.syn_d[l]); }
   void* p = nullptr;
   if (hipMalloc(&p, members_.size() * sizeof(ProbDesc)) != hipSuccess || !p) {

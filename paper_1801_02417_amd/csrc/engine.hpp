@@ -37,6 +37,7 @@ struct Geometry {
   std::vector<int2> tile_slots;          // per gridding tile {first partial slot, count}
   std::vector<int> slot_box;             // per slot: the region cells its chunk covers (pack_box)
   std::vector<int> tile_box;             // per gridding tile: the union of its slots' boxes
+  std::vector<int> small_ids;            // chunks of at most kSmallChunk entries, heaviest first
   int n_slots = 0;
   int chunk_entries = kChunkEntries;     // the chunk size the runs and chunks were cut for
 };
@@ -64,7 +65,7 @@ void check_tuning(const Tuning& t, int K);
 //   synsplit           the same with the bases of each tile split over two items {prob, tile, part,
 //                      mask} of about equal filter work (one item per tile below two bases)
 struct ItemSet {
-  std::vector<int4> img, rows, cols, p6, p7, dirac, synfinal, synsplit, coarse;
+  std::vector<int4> img, rows, cols, p6, p7, p7f, dirac, synfinal, synsplit, coarse;
   std::vector<int4> ana[kMaxLevels + 1], syn[kMaxLevels + 1];
   std::vector<int4> ana_d[kMaxLevels + 1], syn_d[kMaxLevels + 1];
 };
@@ -81,7 +82,7 @@ struct DevItems {
 // solves that share a precision and a tap count) that the iteration's pass sequence runs on.
 struct PassLists {
   const ProbDesc* descs = nullptr;
-  DevItems img, rows, cols, p6, p7, synfinal, coarse;
+  DevItems img, rows, cols, p6, p7, p7f, synfinal, coarse;
   DevItems ana_d[kMaxLevels + 1], syn_d[kMaxLevels + 1];
   int cells = 512, rcells = 512;   // FFT cells per workgroup of the column / row passes
   int max_ts = 16, taps = 8, max_levels = 0;
@@ -216,7 +217,7 @@ struct Engine {
   ProbDesc* d_desc_ = nullptr;
   bool desc_dirty_ = true;
   ItemSet items_;
-  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_dirac_, d_synfinal_, d_synsplit_, d_coarse_;
+  DevItems d_img_, d_rows_, d_cols_, d_p6_, d_p7_, d_p7f_, d_dirac_, d_synfinal_, d_synsplit_, d_coarse_;
   int c_level_ = 1 << 20;     // first level handled by the fused coarse kernel (> levels: none)
   DevItems d_ana_[kMaxLevels + 1], d_syn_[kMaxLevels + 1];
   DevItems d_ana_d_[kMaxLevels + 1], d_syn_d_[kMaxLevels + 1];

@@ -398,6 +398,94 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
   }
 }
 
+// A value of lane e (e the same in every lane), read into a scalar register.
+template <typename V>
+__device__ inline V lane_value(V v, int e) {
+  static_assert(sizeof(V) % 4 == 0, "32-bit words");
+  union { V v; int w[sizeof(V) / 4]; } a, b;
+  a.v = v;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(V) / 4); ++k) b.w[k] = __builtin_amdgcn_readlane(a.w[k], e);
+  return b.v;
+}
+
+// P7 of the small chunks (at most kSmallChunk entries): one wave per chunk, an item holding up
+// to eight of them (small_ids[it.z .. it.z + it.w)), no LDS and no atomics.  Lane e first loads
+// entry e (its index, offsets, window start, gridded channels); a lane owns the cells
+// q = lane + 64 k of the chunk's box and adds, entry by entry in list order, the entry's tap
+// product times its channels -- a fixed order, so the sums are deterministic like the
+// fixed-point sums of the larger chunks.  Lanes 0..T-1 evaluate the entry's k1 taps and lanes
+// 8..8+T-1 its k2 taps; a cell takes the two it needs by a lane shuffle.
+template <typename R, int MODE, int T>
+__device__ inline void grid_small(const ProbDesc& P, const int4 it, int src_slot) {
+  static_assert(T <= 8 && kSmallChunk <= 64, "eight taps and an entry per lane");
+  constexpr int RG = kGridTile + T - 1;
+  constexpr int DEG = KbDeg<R>::value;
+  constexpr int NCELL = (RG * RG + 63) / 64;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (wave >= it.w) return;
+  const int c = P.small_ids[it.z + wave];
+  const int4 ch = P.chunks[c];
+  const int2 ent = P.chunk_ent[c];
+  const int box = P.slot_box[ch.w];
+  const int ne = ent.y - ent.x;
+  const int m = lane < ne ? P.list_idx[ent.x + lane] : P.list_idx[ent.x];
+  R cr[DEG + 1];
+  {
+    const int tap = lane & 7;
+    const R* __restrict__ poly = (const R*)P.kbpoly + (tap < T ? tap : 0) * (DEG + 1);
+#pragma unroll
+    for (int k = 0; k <= DEG; ++k) cr[k] = poly[k];
+  }
+  const V2<R> fm = ((const V2<R>*)P.vis_frac)[m];
+  const int pkm = P.vis_k0[m];
+  V4<R> u0, u1;
+  (void)grid_channels<R, MODE>(P, m, ((const Cell<R>*)P.vis[src_slot])[m], u0, u1);
+
+  const int ntg = P.ntile_side_g;
+  const int t1 = ch.x / ntg, t2 = ch.x - t1 * ntg;
+  const int b1 = t1 * kGridTile, b2 = t2 * kGridTile;
+  const int lo1 = box & 255, lo2 = (box >> 16) & 255;
+  const int bw = ((box >> 8) & 255) - lo1 + 1, area = bw * (((box >> 24) & 255) - lo2 + 1);
+  int cell[NCELL];                                  // region offsets o1 | o2 << 8 of the lane's cells
+#pragma unroll
+  for (int k = 0; k < NCELL; ++k) {
+    const int q = lane + 64 * k, a = q / bw;
+    cell[k] = (lo1 + q - a * bw) | ((lo2 + a) << 8);
+  }
+  R acc[NCELL][8];
+#pragma unroll
+  for (int k = 0; k < NCELL; ++k)
+#pragma unroll
+    for (int h = 0; h < 8; ++h) acc[k][h] = R(0);
+  for (int e = 0; e < ne; ++e) {
+    const V2<R> f = lane_value(fm, e);
+    const int pk = lane_value(pkm, e);
+    const V4<R> v0 = lane_value(u0, e), v1 = lane_value(u1, e);
+    const R u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    const R w = kb_tap<R, T>(R(2) * (lane < 8 ? f.x : f.y) - R(T - 1), cr);
+    const int s1 = (pk >> 16) - b1, s2 = (pk & 0xffff) - b2;
+#pragma unroll
+    for (int k = 0; k < NCELL; ++k) {
+      const int i = (cell[k] & 255) - s1, j = (cell[k] >> 8) - s2;
+      const R wi = __shfl(w, i & 7), wj = __shfl(w, 8 + (j & 7));
+      const R ww = ((unsigned)i < (unsigned)T && (unsigned)j < (unsigned)T) ? wi * wj : R(0);
+#pragma unroll
+      for (int h = 0; h < 8; ++h) acc[k][h] += ww * u[h];
+    }
+  }
+  Cell<R>* __restrict__ dst = (Cell<R>*)P.gpart + (size_t)ch.w * RG * RG;
+#pragma unroll
+  for (int k = 0; k < NCELL; ++k) {
+    if (lane + 64 * k >= area) break;
+    Cell<R> o;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) o.s[h] = cmk(acc[k][2 * h], acc[k][2 * h + 1]);
+    dst[(cell[k] >> 8) * RG + (cell[k] & 255)] = o;
+  }
+}
+
 // (FP64: the LDS holds one workgroup per CU, so two waves per SIMD and 256 registers, which
 // keeps the FP64 accumulators out of scratch memory)
 // (ce: the largest chunk of the launch's problems; the staging arrays after the accumulator hold
@@ -413,8 +501,13 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
   __shared__ double red[2 * (kGridThreads / 64)];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
-  if (it.y < 0) {                  // the factor item: the factor the column inverse FFT applies
+  if (it.y == kGridSmallItem) {    // up to eight small chunks, one per wave
     if (halted(P)) return;         // stopped by an adaptive run
+    grid_small<R, MODE, T>(P, it, src_slot);
+    return;
+  }
+  if (it.y == kGridFactorItem) {   // the factor item: the factor the column inverse FFT applies
+    if (halted(P)) return;
     if (MODE == GR_DUAL) {
       const double v2 = block_sum_partials(P.partials, P.n_p6, red);
       if (threadIdx.x == 0) {

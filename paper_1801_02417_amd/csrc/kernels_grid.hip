@@ -77,13 +77,27 @@ __device__ inline Cell<R> brightness(const ProbDesc& P, int m, const cplx<R> v[4
   return phi;
 }
 
-// The de-grid pass's row m for MODE (not DG_FORWARD) from its de-gridded Stokes values, with
-// the squared moduli of its eight reals added to acc.  DG_DUAL: Bv = c/rho2 Bv_old + phi - Y
-// (src_slot holds Bv_old); DG_RESIDUAL: Y - phi; DG_STOKES: per Stokes map Phi S - Y L^{-1}
+// What the de-grid pass's row m reads besides its window: Y, and for DG_DUAL the previous Bv.
+template <typename R>
+struct RowIn {
+  Cell<R> y, bv;
+};
+template <typename R, int MODE>
+__device__ inline RowIn<R> row_inputs(const ProbDesc& P, long long m, int src_slot) {
+  RowIn<R> r{};
+  if (MODE != DG_FORWARD) r.y = ((const Cell<R>*)P.vis[VIS_Y])[m];
+  if (MODE == DG_DUAL) r.bv = ((const Cell<R>*)P.vis[src_slot])[m];
+  return r;
+}
+
+// The de-grid pass's row m for MODE (not DG_FORWARD) from its de-gridded Stokes values and its
+// inputs, with the squared moduli of its eight reals added to acc.  DG_DUAL: Bv = cb Bv_old +
+// phi - Y (cb = c/rho2); DG_RESIDUAL: Y - phi; DG_STOKES: per Stokes map Phi S - Y L^{-1}
 // (I = (Y1 + Y4) / 2, Q = (Y1 - Y4) / 2, U = (Y2 + Y3) / 2, V = -i (Y2 - Y3) / 2).
 template <typename R, int MODE>
-__device__ inline Cell<R> degrid_row(const ProbDesc& P, int m, const cplx<R> v[4], int src_slot, KSum& acc) {
-  const Cell<R> y = ((const Cell<R>*)P.vis[VIS_Y])[m];
+__device__ inline Cell<R> degrid_row_in(const ProbDesc& P, int m, const cplx<R> v[4], const RowIn<R>& in, R cb,
+                                        KSum& acc) {
+  const Cell<R>& y = in.y;
   Cell<R> o;
   if (MODE == DG_STOKES) {
     const R h = R(0.5);
@@ -95,12 +109,10 @@ __device__ inline Cell<R> degrid_row(const ProbDesc& P, int m, const cplx<R> v[4
   } else {
     const Cell<R> phi = brightness<R>(P, m, v);
     if (MODE == DG_DUAL) {
-      const Cell<R> bv = ((const Cell<R>*)P.vis[src_slot])[m];
-      const R cb = R(P.scal[SC_CFAC] / P.rho2);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        o.s[s].re = cb * bv.s[s].re + phi.s[s].re - y.s[s].re;
-        o.s[s].im = cb * bv.s[s].im + phi.s[s].im - y.s[s].im;
+        o.s[s].re = cb * in.bv.s[s].re + phi.s[s].re - y.s[s].re;
+        o.s[s].im = cb * in.bv.s[s].im + phi.s[s].im - y.s[s].im;
       }
     } else {
 #pragma unroll
@@ -114,6 +126,16 @@ __device__ inline Cell<R> degrid_row(const ProbDesc& P, int m, const cplx<R> v[4
     acc.add(im * im);
   }
   return o;
+}
+
+template <typename R, int MODE>
+__device__ inline R dual_factor(const ProbDesc& P) {
+  return MODE == DG_DUAL ? R(P.scal[SC_CFAC] / P.rho2) : R(0);
+}
+
+template <typename R, int MODE>
+__device__ inline Cell<R> degrid_row(const ProbDesc& P, int m, const cplx<R> v[4], int src_slot, KSum& acc) {
+  return degrid_row_in<R, MODE>(P, m, v, row_inputs<R, MODE>(P, m, src_slot), dual_factor<R, MODE>(P), acc);
 }
 
 // The gridded channels of row m with value b: B L^H (I = B1 + B4, Q = B1 - B4, U = B2 + B3,
@@ -149,45 +171,91 @@ __device__ inline R grid_channels(const ProbDesc& P, int m, const Cell<R>& b, V4
 // ---------------------------------------------------------------------------------------------
 // P6: de-grid + L mixing (+ dual B).  items: {prob, tile, first sorted vis, partial index}; an item
 // holds P.dg_item rows of the tile (fewer at its end), a thread takes every blockDim.x-th
+// One row of the de-grid pass: its window (starting at region offsets (pk >> 16) - c1,
+// (pk & 0xffff) - c2 of the staged band, ws cells wide) interpolated with its taps, then stored.
+template <typename R, int MODE, int T>
+__device__ __forceinline__ void degrid_one(const ProbDesc& P, const Cell<R>* win, int ws, int c1, int c2, int m, int pk,
+                                           V2<R> f, const RowIn<R>& in, R cb, Cell<R>* __restrict__ out, KSum& acc) {
+  R w1[T], w2[T];
+  kb_weights<R, T>(f.x, (const R*)P.kbpoly, w1);
+  kb_weights<R, T>(f.y, (const R*)P.kbpoly, w2);
+  cplx<R> v[4];
+  interpolate<R, T>(win, ws, (pk >> 16) - c1, (pk & 0xffff) - c2, w1, w2, v);
+  if (MODE == DG_FORWARD) out[m] = brightness<R>(P, m, v);
+  else out[m] = degrid_row_in<R, MODE>(P, m, v, in, cb, acc);
+}
+
 template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(256)
 degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cell<R>* win = (Cell<R>*)smem_raw;
   __shared__ double red[8];
+  __shared__ int band[2];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
-  if (halted(P)) return;                 // stopped by an adaptive run
   const int K = P.K, ts = P.ts, nts = P.ntile_side;
   const int tile = it.y;
   const int t1 = tile / nts, t2 = tile - t1 * nts;
   const int W = ts + T - 1;
   const Cell<R>* __restrict__ grid = (const Cell<R>*)P.grid;
   const int b1 = t1 * ts, b2 = t2 * ts;
-  // the item's visibilities are sorted by window start k1 within the tile, so they use only
-  // the k1 offsets [lo, hi + T - 1] of the tile window: stage that band, Wb wide
-  const int vend = min(it.z + P.dg_item, P.own_ptr[tile + 1]);
-  const int lo = (P.vis_k0[it.z] >> 16) - b1, hi = (P.vis_k0[vend - 1] >> 16) - b1;
-  const int Wb = hi - lo + T;
-  for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {
-    const int a = q / Wb, b = q - a * Wb;                    // a: k2 offset, b: k1 offset - lo
-    win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + lo + b) & (K - 1))];
-  }
-  __syncthreads();
-
+  Cell<R>* __restrict__ out = (Cell<R>*)P.vis[out_slot];
+  const R cb = dual_factor<R, MODE>(P);
+  const int mf = it.z + threadIdx.x;
   KSum acc;
-  for (int m = it.z + threadIdx.x; m < vend; m += blockDim.x) {
-    const int pk = P.vis_k0[m];
-    const int r1 = (pk >> 16) - b1 - lo, r2 = (pk & 0xffff) - b2;
-    const V2<R> f = ((const V2<R>*)P.vis_frac)[m];
-    R w1[T], w2[T];
-    kb_weights<R, T>(f.x, (const R*)P.kbpoly, w1);
-    kb_weights<R, T>(f.y, (const R*)P.kbpoly, w2);
-    cplx<R> v[4];
-    interpolate<R, T>(win, Wb, r1, r2, w1, w2, v);
-    Cell<R>* __restrict__ out = (Cell<R>*)P.vis[out_slot];
-    if (MODE == DG_FORWARD) out[m] = brightness<R>(P, m, v);
-    else out[m] = degrid_row<R, MODE>(P, m, v, src_slot, acc);
+  // the item's visibilities are sorted by window start k1 within the tile, so they use only
+  // the k1 offsets [lo, hi + T - 1] of the tile window: that band, Wb wide, is staged
+  if constexpr (sizeof(R) == 4) {
+    // FP32: the thread's first row and what it reads are requested before the halt test and
+    // the window, so those loads are in flight together (the index is clamped into range; a
+    // row past the item's end is not used); lo and hi come from the threads holding the first
+    // and the last row
+    const long long mc = min((long long)mf, P.M - 1);
+    const int pk0 = P.vis_k0[mc];
+    const V2<R> f0 = ((const V2<R>*)P.vis_frac)[mc];
+    const RowIn<R> in0 = row_inputs<R, MODE>(P, mc, src_slot);
+    const int vend = min(it.z + P.dg_item, P.own_ptr[tile + 1]);
+    if (halted(P)) return;                 // stopped by an adaptive run
+    const int last = vend - 1 - it.z;
+    if (threadIdx.x == 0) band[0] = (pk0 >> 16) - b1;
+    if (threadIdx.x == (unsigned)(last % (int)blockDim.x))
+      band[1] = ((last < (int)blockDim.x ? pk0 : P.vis_k0[vend - 1]) >> 16) - b1;
+    __syncthreads();
+    const int lo = band[0], Wb = band[1] - lo + T;
+    for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {
+      const int a = q / Wb, b = q - a * Wb;                    // a: k2 offset, b: k1 offset - lo
+      win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + lo + b) & (K - 1))];
+    }
+    __syncthreads();
+    // the first row from the values loaded above, later rows (items longer than the
+    // workgroup) loaded as they come
+    if (mf < vend) degrid_one<R, MODE, T>(P, win, Wb, b1 + lo, b2, mf, pk0, f0, in0, cb, out, acc);
+    for (int m = mf + blockDim.x; m < vend; m += blockDim.x)
+      degrid_one<R, MODE, T>(P, win, Wb, b1 + lo, b2, m, P.vis_k0[m], ((const V2<R>*)P.vis_frac)[m],
+                             row_inputs<R, MODE>(P, m, src_slot), cb, out, acc);
+  } else {
+    // FP64 (the interpolation takes every register): rows are read as they are de-gridded
+    if (halted(P)) return;                 // stopped by an adaptive run
+    const int vend = min(it.z + P.dg_item, P.own_ptr[tile + 1]);
+    const int lo = (P.vis_k0[it.z] >> 16) - b1, hi = (P.vis_k0[vend - 1] >> 16) - b1;
+    const int Wb = hi - lo + T;
+    for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {
+      const int a = q / Wb, b = q - a * Wb;
+      win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + lo + b) & (K - 1))];
+    }
+    __syncthreads();
+    for (int m = mf; m < vend; m += blockDim.x) {
+      const int pk = P.vis_k0[m];
+      const V2<R> f = ((const V2<R>*)P.vis_frac)[m];
+      R w1[T], w2[T];
+      kb_weights<R, T>(f.x, (const R*)P.kbpoly, w1);
+      kb_weights<R, T>(f.y, (const R*)P.kbpoly, w2);
+      cplx<R> v[4];
+      interpolate<R, T>(win, Wb, (pk >> 16) - b1 - lo, (pk & 0xffff) - b2, w1, w2, v);
+      if (MODE == DG_FORWARD) out[m] = brightness<R>(P, m, v);
+      else out[m] = degrid_row<R, MODE>(P, m, v, src_slot, acc);
+    }
   }
   if (MODE != DG_FORWARD) {
     const KSum tot = block_reduce(acc, red);

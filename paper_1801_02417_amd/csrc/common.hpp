@@ -104,9 +104,7 @@ struct ProbDesc {
   double l1w[4];          // l1 weights per Stokes map (l1 + TV)
   const int* own_ptr;     // ntiles+1: sorted-vis range whose window starts in each tile
   const int* list_idx;    // per gridding tile: every vis whose window touches it
-  const int* run_beg;     // gridding runs: first list entry and length
-  const int* run_len;
-  const int* run_k0;      // packed window start of each run
+  const int* run_pack;    // gridding runs (pack_run): entry offset in the chunk, length, window start in the tile
   const int2* chunk_ent;  // list-entry range [lo, hi) of each gridding chunk
   void* gpart;            // gridding partial slots: n_slots x (kGridTile + T - 1)^2 cells, k2-major
   const int4* chunks;     // gridding chunks {tile, first run, end run, partial slot}
@@ -134,6 +132,13 @@ __host__ __device__ constexpr int pack_box(int lo1, int hi1, int lo2, int hi2) {
 __host__ __device__ inline bool in_box(int box, int o1, int o2) {
   return o1 >= (box & 255) && o1 <= ((box >> 8) & 255) && o2 >= ((box >> 16) & 255) && o2 <= ((box >> 24) & 255);
 }
+
+// A gridding run in one word: the offset of its first entry in its chunk (< 1024), its length
+// (1 .. 32) and its window start relative to its tile (o1, o2 < 16).
+__host__ __device__ constexpr int pack_run(int off, int len, int o1, int o2) {
+  return off | ((len - 1) << 10) | (o1 << 15) | (o2 << 19);
+}
+static_assert(kChunkEntries <= 1024 && kRunMax <= 32 && kGridTile <= 16, "run fields");
 
 // --------------------------------------------------------------------------------------------
 // small vector types

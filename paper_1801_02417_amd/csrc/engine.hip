@@ -96,7 +96,7 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
 
 void build_grid_chunks(Geometry& g, int chunk_entries) {
   const int ntg = g.ntsg * g.ntsg;
-  g.run_beg.clear(); g.run_len.clear(); g.run_k0.clear();
+  g.run_pack.clear();
   g.chunks.clear(); g.chunk_ent.clear(); g.tile_slots.clear(); g.slot_box.clear(); g.tile_box.clear(); g.small_ids.clear();
   g.n_slots = 0;
   g.chunk_entries = chunk_entries;
@@ -122,18 +122,18 @@ void build_grid_chunks(Geometry& g, int chunk_entries) {
       while (r < runs.size() && (entries + runs[r].second <= chunk_entries || r == r0)) entries += runs[r++].second;
       std::stable_sort(runs.begin() + r0, runs.begin() + r,
                        [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.second > y.second; });
-      const int base = (int)g.run_beg.size();
+      const int base = (int)g.run_pack.size();
       int lo = g.list_ptr[t + 1], hi = g.list_ptr[t];
+      for (size_t q = r0; q < r; ++q) {
+        lo = std::min(lo, runs[q].first);
+        hi = std::max(hi, runs[q].first + runs[q].second);
+      }
       // the cells the chunk's windows cover, as offsets in the tile's region
       const int b1 = (t / g.ntsg) * kGridTile, b2 = (t % g.ntsg) * kGridTile;
       int lo1 = kGridTile, hi1 = 0, lo2 = kGridTile, hi2 = 0;
       for (size_t q = r0; q < r; ++q) {
         const int pk = g.k0[g.list_idx[runs[q].first]];
-        g.run_beg.push_back(runs[q].first);
-        g.run_len.push_back(runs[q].second);
-        g.run_k0.push_back(pk);
-        lo = std::min(lo, runs[q].first);
-        hi = std::max(hi, runs[q].first + runs[q].second);
+        g.run_pack.push_back(pack_run(runs[q].first - lo, runs[q].second, (pk >> 16) - b1, (pk & 0xffff) - b2));
         lo1 = std::min(lo1, (pk >> 16) - b1);
         hi1 = std::max(hi1, (pk >> 16) - b1);
         lo2 = std::min(lo2, (pk & 0xffff) - b2);
@@ -407,12 +407,10 @@ static std::vector<int4> xcd_contiguous(const std::vector<int4>& v) {
 template <typename R>
 void Engine<R>::upload_chunks() {
   const Geometry& g = geo_;
-  dfree((void*)h_.run_beg); dfree((void*)h_.run_len); dfree((void*)h_.run_k0);
+  dfree((void*)h_.run_pack);
   dfree((void*)h_.chunk_ent); dfree((void*)h_.tile_slots); dfree((void*)h_.chunks); dfree((void*)h_.slot_box);
   dfree((void*)h_.tile_box); dfree((void*)h_.small_ids); dfree(h_.gpart);
-  h_.run_beg = upload<int>(g.run_beg.data(), std::max<size_t>(1, g.run_beg.size()));
-  h_.run_len = upload<int>(g.run_len.data(), std::max<size_t>(1, g.run_len.size()));
-  h_.run_k0 = upload<int>(g.run_k0.data(), std::max<size_t>(1, g.run_k0.size()));
+  h_.run_pack = upload<int>(g.run_pack.data(), std::max<size_t>(1, g.run_pack.size()));
   h_.chunk_ent = upload<int2>(g.chunk_ent.data(), std::max<size_t>(1, g.chunk_ent.size()));
   h_.tile_slots = upload<int2>(g.tile_slots.data(), std::max<size_t>(1, g.tile_slots.size()));
   h_.chunks = upload<int4>(g.chunks.data(), std::max<size_t>(1, g.chunks.size()));

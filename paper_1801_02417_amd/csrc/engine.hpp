@@ -31,7 +31,7 @@ struct Geometry {
   // gridding work: runs of list entries sharing one window start (at most kRunMax long),
   // grouped into chunks of at most kChunkEntries entries; every chunk writes its tile and
   // the tile's halo to its own partial slot, summed when the column inverse FFT loads them
-  std::vector<int> run_beg, run_len, run_k0;   // per run: first list entry, length, window start
+  std::vector<int> run_pack;             // per run: pack_run(entry offset in its chunk, length, window start in the tile)
   std::vector<int4> chunks;              // {tile, first run, end run, partial slot}
   std::vector<int2> chunk_ent;           // list-entry range [lo, hi) each chunk covers
   std::vector<int2> tile_slots;          // per gridding tile {first partial slot, count}

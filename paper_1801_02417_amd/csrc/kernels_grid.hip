@@ -207,16 +207,18 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   // the item's visibilities are sorted by window start k1 within the tile, so they use only
   // the k1 offsets [lo, hi + T - 1] of the tile window: that band, Wb wide, is staged
   if constexpr (sizeof(R) == 4) {
-    // FP32: the thread's first row and what it reads are requested before the halt test and
-    // the window, so those loads are in flight together (the index is clamped into range; a
-    // row past the item's end is not used); lo and hi come from the threads holding the first
+    // FP32: the thread's first row is requested before the halt test and the window (its
+    // window start and offsets with the item's end, the index clamped into range; a row past
+    // the item's end is not used), its Y and Bv once the end is known, so that those loads are
+    // in flight during the window staging; lo and hi come from the threads holding the first
     // and the last row
     const long long mc = min((long long)mf, P.M - 1);
     const int pk0 = P.vis_k0[mc];
     const V2<R> f0 = ((const V2<R>*)P.vis_frac)[mc];
-    const RowIn<R> in0 = row_inputs<R, MODE>(P, mc, src_slot);
     const int vend = min(it.z + P.dg_item, P.own_ptr[tile + 1]);
     if (halted(P)) return;                 // stopped by an adaptive run
+    RowIn<R> in0{};
+    if (mf < vend) in0 = row_inputs<R, MODE>(P, mf, src_slot);
     const int last = vend - 1 - it.z;
     if (threadIdx.x == 0) band[0] = (pk0 >> 16) - b1;
     if (threadIdx.x == (unsigned)(last % (int)blockDim.x))
@@ -352,59 +354,65 @@ __device__ inline int fixed_exponent(double total) {
 }
 
 // What a gridding workgroup loads before its entries are staged (so those loads overlap the
-// staging's): this lane's tap polynomial, its group's first run, and the chunk's box.
+// staging's): its group's first run, the chunk's box and, with POLY, this lane's tap polynomial
+// (the kernels with more registers live during the staging -- the FP64 one and the fused
+// de-grid + grid -- load it after the staging instead, which keeps them free of spills).
 template <typename R>
 struct ChunkPre {
   R cr[KbDeg<R>::value + 1];
-  int beg = 0, len = 0, k0 = 0;
+  int run = 0;                                     // the group's first run (pack_run), 0 if none
   int box = 0;
 };
 
 template <typename R, int T>
-__device__ inline void chunk_preload(const ProbDesc& P, const int4 ch, ChunkPre<R>& pre) {
+__device__ inline void load_poly(const ProbDesc& P, R* cr) {
   constexpr int DEG = KbDeg<R>::value;
   const int lane8 = threadIdx.x & 7;
   const R* __restrict__ poly = (const R*)P.kbpoly + (lane8 < T ? lane8 : 0) * (DEG + 1);
 #pragma unroll
-  for (int k = 0; k <= DEG; ++k) pre.cr[k] = lane8 < T ? poly[k] : R(0);
+  for (int k = 0; k <= DEG; ++k) cr[k] = lane8 < T ? poly[k] : R(0);
+}
+
+template <typename R, int T, bool POLY>
+__device__ inline void chunk_preload(const ProbDesc& P, const int4 ch, ChunkPre<R>& pre) {
+  if (POLY) load_poly<R, T>(P, pre.cr);
   const int rr = ch.y + (threadIdx.x >> 3);
-  if (rr < ch.z) {
-    pre.beg = P.run_beg[rr];
-    pre.len = P.run_len[rr];
-    pre.k0 = P.run_k0[rr];
-  }
+  if (rr < ch.z) pre.run = P.run_pack[rr];
   pre.box = P.slot_box[ch.w];
 }
 
 // Accumulates a chunk whose rows are staged in LDS (sf: fractional offsets, su: two V4 of
-// gridded channels per entry, entry q at list position ent.x + q) into acc, which must be zero,
+// gridded channels per entry, entry q the chunk's q-th list entry) into acc, which must be zero,
 // and writes the cells of the chunk's box to its partial slot (the slot's other cells are zero
 // from the allocation on and stay so).  Called by the whole workgroup.
-template <typename R, int T>
-__device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 ent, int b1, int b2,
+template <typename R, int T, bool POLY>
+__device__ inline void grid_chunk(const ProbDesc& P, const int4 ch,
                                   const V2<R>* sf, const V4<R>* su, unsigned long long* acc, int E,
                                   const ChunkPre<R>& pre) {
   constexpr int RG = kGridTile + T - 1;
   constexpr int DEG = KbDeg<R>::value;
+  R cr[DEG + 1];                                   // this lane's tap polynomial
+  if (POLY) {
+#pragma unroll
+    for (int k = 0; k <= DEG; ++k) cr[k] = pre.cr[k];
+  } else {
+    load_poly<R, T>(P, cr);
+  }
   const double fx = ldexp(1.0, E);
   const int lane8 = threadIdx.x & 7;               // tap row owned by this lane
   const int grp = threadIdx.x >> 3, ngrp = blockDim.x >> 3;
   // FP64 accumulates a run's eight channels in two passes of four (T x 8 doubles would not stay
   // in registers); each channel's sum is the same either way
   constexpr int NC = sizeof(R) == 8 ? 4 : 8;
-  int rbeg = pre.beg, rlen = pre.len, rk0 = pre.k0;
+  int run = pre.run;
   for (int rr = ch.y + grp; rr - grp < ch.z; rr += ngrp) {
     const bool active = rr < ch.z;
-    const int e0 = active ? rbeg - ent.x : 0;
-    const int len = active ? rlen : 0;
-    const int pk = active ? rk0 : 0;
+    const int e0 = run & 1023;
+    const int len = active ? ((run >> 10) & 31) + 1 : 0;
+    const int o1 = (run >> 15) & 15, o2 = (run >> 19) & 15;   // window start in the tile
     // the group's next run, loaded while this one accumulates
     const int nr = rr + ngrp;
-    if (nr < ch.z) {
-      rbeg = P.run_beg[nr];
-      rlen = P.run_len[nr];
-      rk0 = P.run_k0[nr];
-    }
+    if (nr < ch.z) run = P.run_pack[nr];
     // (one pass of eight channels, or in FP64 one pass per staged V4 of four)
 #pragma unroll 1
     for (int c0 = 0; c0 < 8; c0 += NC) {
@@ -416,8 +424,8 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
       for (int q = 0; q < len; ++q) {
         const V2<R> f = sf[e0 + q];
         // this lane's tap in each dimension: psi(f - lane8) from its polynomial
-        const R w1 = kb_tap<R, T>(R(2) * f.x - R(T - 1), pre.cr);
-        const R w2 = kb_tap<R, T>(R(2) * f.y - R(T - 1), pre.cr);
+        const R w1 = kb_tap<R, T>(R(2) * f.x - R(T - 1), cr);
+        const R w2 = kb_tap<R, T>(R(2) * f.y - R(T - 1), cr);
         R u[NC];
         const V4<R> v0 = su[2 * (e0 + q) + (NC == 8 ? 0 : c0 / 4)];
         u[0] = v0.x; u[1] = v0.y; u[2] = v0.z; u[3] = v0.w;
@@ -433,11 +441,10 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch, const int2 e
         }
       }
       if (len > 0 && lane8 < T) {
-        const int c1 = (pk >> 16) - b1 + lane8;              // the window start lies in the tile
-        unsigned long long* row = acc + c1;
+        unsigned long long* row = acc + o1 + lane8;
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-          unsigned long long* cell = row + ((pk & 0xffff) - b2 + j) * RG;
+          unsigned long long* cell = row + (o2 + j) * RG;
           // one tap column at a time: the empty asm (ordered with the atomics) keeps the
           // compiler from widening all the sums to 64 bits at once, which would spill
           if (NC == 8) {
@@ -602,12 +609,10 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     me[e] = q < ne ? P.list_idx[ent.x + q] : 0;
   }
   const int4 ch = P.chunks[it.y];
+  constexpr bool kPoly = sizeof(R) == 4;
   ChunkPre<R> pre;
-  chunk_preload<R, T>(P, ch, pre);
+  chunk_preload<R, T, kPoly>(P, ch, pre);
   if (halted(P)) return;                 // stopped by an adaptive run
-  const int ntg = P.ntile_side_g;
-  const int t1 = ch.x / ntg, t2 = ch.x - t1 * ntg;
-  const int b1 = t1 * kGridTile, b2 = t2 * kGridTile;
 
   // stage the chunk's entries: offsets and gridded channels; sum the largest channel magnitude
   // of each for the fixed point
@@ -634,7 +639,7 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
     bound.add((double)mx);
   }
   const double total = block_reduce(bound, red).value();      // includes a barrier
-  grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total), pre);
+  grid_chunk<R, T, kPoly>(P, ch, sf, su, acc, fixed_exponent<R>(total), pre);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -666,7 +671,7 @@ degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ 
   const int4 ch = P.chunks[it.y];
   const int2 ent = make_int2(it.z, it.w);       // the chunk's entry range, carried by the item
   ChunkPre<R> pre;
-  chunk_preload<R, T>(P, ch, pre);
+  chunk_preload<R, T, false>(P, ch, pre);
   const int K = P.K, ntg = P.ntile_side_g;
   const int t1 = ch.x / ntg, t2 = ch.x - t1 * ntg;
   const int b1 = t1 * kGridTile, b2 = t2 * kGridTile;
@@ -726,7 +731,7 @@ degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ 
   const double total = block_reduce(bound, red).value();
   for (int q = threadIdx.x; q < 8 * RG * RG; q += blockDim.x) acc[q] = 0ull;
   __syncthreads();
-  grid_chunk<R, T>(P, ch, ent, b1, b2, sf, su, acc, fixed_exponent<R>(total), pre);
+  grid_chunk<R, T, false>(P, ch, sf, su, acc, fixed_exponent<R>(total), pre);
 }
 
 // dynamic LDS of the gridding kernels: the staged offsets and mixed values of ce entries

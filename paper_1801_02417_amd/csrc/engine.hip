@@ -195,7 +195,12 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
   const int ntiles = g.nts * g.nts;
   int part = 0;
   for (int t = 0; t < ntiles; ++t) {
-    for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += dg_item) S.p6.push_back(make_int4(prob, t, v, part++));
+    // (a de-grid item packs its tile and row count in one int: tiles < 2^16, rows < 2^15)
+    if (ntiles > 0xffff || dg_item > 0x7fff) throw Error(PSARA_EINVAL, "de-grid tiling out of range");
+    for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += dg_item) {
+      const int rows = std::min(dg_item, g.own_ptr[t + 1] - v);
+      S.p6.push_back(make_int4(prob, t | (rows << 16), v, part++));
+    }
   }
   // gridding: first the item that stores the pass's scalar factor, then the chunks heaviest
   // first so the tail is short, a chunk item carrying its entry range; the grid pass takes the

@@ -169,8 +169,6 @@ __device__ inline R grid_channels(const ProbDesc& P, int m, const Cell<R>& b, V4
 }
 
 // ---------------------------------------------------------------------------------------------
-// P6: de-grid + L mixing (+ dual B).  items: {prob, tile, first sorted vis, partial index}; an item
-// holds P.dg_item rows of the tile (fewer at its end), a thread takes every blockDim.x-th
 // One row of the de-grid pass: its window (starting at region offsets (pk >> 16) - c1,
 // (pk & 0xffff) - c2 of the staged band, ws cells wide) interpolated with its taps, then stored.
 template <typename R, int MODE, int T>
@@ -185,6 +183,9 @@ __device__ __forceinline__ void degrid_one(const ProbDesc& P, const Cell<R>* win
   else out[m] = degrid_row_in<R, MODE>(P, m, v, in, cb, acc);
 }
 
+// P6: de-grid + L mixing (+ dual B).  items: {prob, tile | rows << 16, first sorted vis, partial
+// index}; an item holds P.dg_item rows of the tile (fewer at its end), a thread takes every
+// blockDim.x-th
 template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(256)
 degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot) {
@@ -195,7 +196,7 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
   const int K = P.K, ts = P.ts, nts = P.ntile_side;
-  const int tile = it.y;
+  const int tile = it.y & 0xffff, vend = it.z + (it.y >> 16);
   const int t1 = tile / nts, t2 = tile - t1 * nts;
   const int W = ts + T - 1;
   const Cell<R>* __restrict__ grid = (const Cell<R>*)P.grid;
@@ -207,18 +208,18 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   // the item's visibilities are sorted by window start k1 within the tile, so they use only
   // the k1 offsets [lo, hi + T - 1] of the tile window: that band, Wb wide, is staged
   if constexpr (sizeof(R) == 4) {
-    // FP32: the thread's first row is requested before the halt test and the window (its
-    // window start and offsets with the item's end, the index clamped into range; a row past
-    // the item's end is not used), its Y and Bv once the end is known, so that those loads are
-    // in flight during the window staging; lo and hi come from the threads holding the first
-    // and the last row
-    const long long mc = min((long long)mf, P.M - 1);
-    const int pk0 = P.vis_k0[mc];
-    const V2<R> f0 = ((const V2<R>*)P.vis_frac)[mc];
-    const int vend = min(it.z + P.dg_item, P.own_ptr[tile + 1]);
-    if (halted(P)) return;                 // stopped by an adaptive run
+    // FP32: the thread's first row and what it reads are requested before the halt test and
+    // the window, so those loads are in flight together; lo and hi come from the threads
+    // holding the first and the last row
+    int pk0 = 0;
+    V2<R> f0{};
     RowIn<R> in0{};
-    if (mf < vend) in0 = row_inputs<R, MODE>(P, mf, src_slot);
+    if (mf < vend) {
+      pk0 = P.vis_k0[mf];
+      f0 = ((const V2<R>*)P.vis_frac)[mf];
+      in0 = row_inputs<R, MODE>(P, mf, src_slot);
+    }
+    if (halted(P)) return;                 // stopped by an adaptive run
     const int last = vend - 1 - it.z;
     if (threadIdx.x == 0) band[0] = (pk0 >> 16) - b1;
     if (threadIdx.x == (unsigned)(last % (int)blockDim.x))
@@ -239,7 +240,6 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   } else {
     // FP64 (the interpolation takes every register): rows are read as they are de-gridded
     if (halted(P)) return;                 // stopped by an adaptive run
-    const int vend = min(it.z + P.dg_item, P.own_ptr[tile + 1]);
     const int lo = (P.vis_k0[it.z] >> 16) - b1, hi = (P.vis_k0[vend - 1] >> 16) - b1;
     const int Wb = hi - lo + T;
     for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {

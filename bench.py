@@ -425,6 +425,8 @@ def main() -> int:
     ap.add_argument("--no-np-study", action="store_true")
     ap.add_argument("--large-iters", type=int, default=400,
                     help="timed iterations of the 512x512 / 1e6-visibility solve (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (for profiler runs, whose timings would steer the tuner)")
     ap.add_argument("--profile-form", choices=["batch", "large"],
                     help="only run the iterations of that form (for rocprofv3), then exit")
     ap.add_argument("--profile-form-iters", type=int, default=40)
@@ -491,7 +493,10 @@ def main() -> int:
     t_up = time.perf_counter() - t_up
     s.set_steps()
     # launch shapes from the autotuner (the trials leave the zero state as it was)
-    chosen, tune_ms = s.autotune(P.PSARA_CONSTRAINED)
+    if args.no_autotune:
+        chosen, tune_ms = dict(P.DEFAULT_TUNING), None
+    else:
+        chosen, tune_ms = s.autotune(P.PSARA_CONSTRAINED)
     # initialisation stage and first reweighting, so the timed iterations run every term
     s.solve(P.PSARA_NNLS_INIT, 100, report=False)
     s.psara_delta = P.psara_coef_std(s.ctx)
@@ -542,8 +547,9 @@ def main() -> int:
                                "KB 8x8 on a 2x oversampled grid; SARA Dirac+Db1-Db8, 4 levels; "
                                "Polarized SARA iteration, all terms active",
                    "n": n, "M": M, "taps": wl.taps, "levels": wl.levels, "precision": "FP32 bulk, FP64 reductions"},
-        "tuning": {"chosen": chosen, "trial_ms_per_iter_default": round(tune_ms[0], 5),
-                   "trial_ms_per_iter_chosen": round(tune_ms[1], 5)},
+        "tuning": ({"chosen": chosen, "trial_ms_per_iter_default": round(tune_ms[0], 5),
+                    "trial_ms_per_iter_chosen": round(tune_ms[1], 5)} if tune_ms else
+                   {"chosen": chosen, "autotuned": False}),
         "roofline": roofline,
         "passes": passes,
         "sum_of_pass_ms": round(float(sum(ms[i] for i in ITERATION_PASSES)), 5),

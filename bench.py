@@ -147,6 +147,37 @@ def make_data(P, wl, s):
     return Y, eps
 
 
+def device_transfers(P, s, Y, eps, N):
+    """Seconds of psara_set_data_dev (the same Y, from a device buffer) and psara_get_image_dev
+    (into a device buffer), each the best of three; the buffers come from the HIP runtime the
+    library runs on."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so.7")
+    hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+    hip.hipFree.argtypes = [C.c_void_p]
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    y = np.ascontiguousarray(Y, dtype=np.complex128)
+    yb, sb = C.c_void_p(), C.c_void_p()
+    if hip.hipMalloc(C.byref(yb), y.nbytes) != 0 or hip.hipMalloc(C.byref(sb), N * 4 * 8) != 0:
+        raise RuntimeError("hipMalloc failed")
+    try:
+        if hip.hipMemcpy(yb, y.ctypes.data, y.nbytes, 1) != 0:
+            raise RuntimeError("hipMemcpy failed")
+        s.synchronize()
+        up, down = [], []
+        for _ in range(3):
+            t = time.perf_counter()
+            P.psara_set_data_dev(s.ctx, yb.value, eps)
+            up.append(time.perf_counter() - t)
+            t = time.perf_counter()
+            P.psara_get_image_dev(s.ctx, sb.value)
+            down.append(time.perf_counter() - t)
+        return min(up), min(down)
+    finally:
+        hip.hipFree(yb)
+        hip.hipFree(sb)
+
+
 def ready_solver(P, wl, norm_iters=200, norm_rtol=1e-6):
     """A FP32 solver of one workload with data, prior (gamma from the data), and step sizes."""
     s = P.Solver(wl.n, wl.uv, taps=wl.taps, precision=P.PSARA_FP32_MIXED)
@@ -514,6 +545,7 @@ def main() -> int:
     s.image()                            # device S -> host
     t_down = time.perf_counter() - t_down
     rep = s.report()
+    dev_up, dev_down = device_transfers(P, s, Y, eps, N)
 
     ms = s.profile_passes(P.PSARA_CONSTRAINED, args.profile_iters)
     nbytes = pass_bytes(N, M)
@@ -559,6 +591,10 @@ def main() -> int:
         # boundary counted in (host buffers in and out)
         "host_inclusive": {"iters_per_s": round(args.steps / (dt + t_up + t_down), 2),
                            "upload_ms": round(t_up * 1e3, 3), "download_ms": round(t_down * 1e3, 3)},
+        "device_inclusive": {"iters_per_s": round(args.steps / (dt + dev_up + dev_down), 2),
+                             "upload_ms": round(dev_up * 1e3, 3), "download_ms": round(dev_down * 1e3, 3),
+                             "note": "Y from and S to caller-owned device buffers (psara_set_data_dev, "
+                                     "psara_get_image_dev)"},
     }
     s.close()
     progress(f"256x256 / 2e5-visibility iteration rate {its:.1f} iters/s")

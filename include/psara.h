@@ -121,6 +121,14 @@ psara_status psara_set_operator(psara_ctx* ctx, int n, int64_t M, const double* 
  * data-fidelity ball B(Y, epsilon) (eq. f_diff).  ENAN if Y holds a non-finite value. */
 psara_status psara_set_data(psara_ctx* ctx, const double* Y, double epsilon);
 
+/* psara_set_data with Y in device memory of the context's device (borrowed for the call only:
+ * the call returns once the library no longer reads it; the caller must have finished writing
+ * it, since the call is not ordered after the caller's streams).  Same layout and checks
+ * (ENAN, Y unchanged, if a value is not finite); the row permutation and the conversion to the
+ * working precision run on the device.  EINVAL for NULL or a pointer that is not device or
+ * managed memory of the context's device. */
+psara_status psara_set_data_dev(psara_ctx* ctx, const double* Y, double epsilon);
+
 /* SARA prior (Sec. 3.1): basis_mask bit 0 = Dirac, bits 1..8 = Db1..Db8; `levels` >= 1 with
  * n divisible by 2^levels; weights W (J x 4, >= 0) or NULL for all ones; gamma > 0 (the free
  * scale of eq. min_gen2).  The soft-threshold sizes are gamma * W.  Psi is normalised by
@@ -330,6 +338,10 @@ psara_status psara_batch_reweighted_solve(psara_ctx* const* ctxs, int count, psa
 
 /* Current Stokes estimate S (N x 4 doubles). */
 psara_status psara_get_image(psara_ctx* ctx, double* S);
+/* psara_get_image into device memory of the context's device (N x 4 doubles, same layout;
+ * returns once written).  EINVAL for NULL or a pointer that is not device or managed memory of
+ * the context's device. */
+psara_status psara_get_image_dev(psara_ctx* ctx, double* S);
 
 /* Size in bytes of the serialised state: (N*4 + N*2 + J*4 + M*8 + N*4 + N*2) doubles holding
  * S, Z, A, B (complex, original uv order), C, D in that order. */

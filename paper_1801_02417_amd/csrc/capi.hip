@@ -329,6 +329,30 @@ psara_status psara_set_data(psara_ctx* c, const double* Y, double epsilon) {
   });
 }
 
+// Whether p is device (or managed) memory of this context's device.
+static bool device_buffer(const void* p, int device) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == device;
+}
+
+psara_status psara_set_data_dev(psara_ctx* c, const double* Y, double epsilon) {
+  return guard(c, [&] {
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(Y != nullptr, PSARA_EINVAL, "Y is NULL");
+    require(std::isfinite(epsilon) && epsilon > 0.0, PSARA_EINVAL, "epsilon must be finite and > 0");
+    require(device_buffer(Y, c->device), PSARA_EINVAL, "Y is not device memory of the context's device");
+    bool ok = false;
+    with_engine(c, [&](auto& e) { ok = e.set_data_dev(Y, epsilon); });
+    require(ok, PSARA_ENAN, "non-finite visibility");
+    c->eps = epsilon;
+    c->data_set = true;
+  });
+}
+
 psara_status psara_set_mueller(psara_ctx* c, const double* D) {
   return guard(c, [&] {
     require(c->op_set, PSARA_ESTATE, "operator not set");
@@ -729,6 +753,15 @@ psara_status psara_get_image(psara_ctx* c, double* S) {
   return guard(c, [&] {
     require(S != nullptr, PSARA_EINVAL, "S is NULL");
     with_engine(c, [&](auto& e) { e.get_img(psara::IMG_S, S, 4); });
+  });
+}
+
+psara_status psara_get_image_dev(psara_ctx* c, double* S) {
+  return guard(c, [&] {
+    require(S != nullptr, PSARA_EINVAL, "S is NULL");
+    require(c->op_set, PSARA_ESTATE, "operator not set");
+    require(device_buffer(S, c->device), PSARA_EINVAL, "S is not device memory of the context's device");
+    with_engine(c, [&](auto& e) { e.get_img_dev(psara::IMG_S, S, 4); });
   });
 }
 

@@ -537,6 +537,30 @@ void Engine<R>::set_data(const double* Y_sorted, double eps) {
 }
 
 template <typename R>
+bool Engine<R>::set_data_dev(const double* Y_dev, double eps) {
+  const int64_t M = geo_.M;
+  if (M > std::numeric_limits<int>::max()) throw Error(PSARA_EINVAL, "too many rows for the device upload");
+  if (!d_flag_) d_flag_ = dalloc<int>(1);
+  if (!d_perm_) {
+    std::vector<int> p((size_t)std::max<int64_t>(M, 1), 0);
+    for (int64_t i = 0; i < M; ++i) p[(size_t)i] = (int)geo_.perm[(size_t)i];
+    d_perm_ = upload<int>(p.data(), p.size());
+  }
+  zero(d_flag_, sizeof(int));
+  launch_nonfinite(Y_dev, (size_t)M * 8, d_flag_, s0_);
+  hip_check(hipGetLastError(), "finite check launch");
+  int bad = 0;
+  copy_sync(&bad, d_flag_, sizeof(int), hipMemcpyDeviceToHost, s0_, "finite check");
+  if (bad) return false;
+  launch_gather_rows<R>(Y_dev, d_perm_, h_.vis[VIS_Y], (long long)M, s0_);
+  hip_check(hipGetLastError(), "Y gather launch");
+  hip_check(hipStreamSynchronize(s0_), "Y gather");
+  h_.eps = eps;
+  desc_dirty_ = true;
+  return true;
+}
+
+template <typename R>
 void Engine<R>::set_mixing(const double* mix_sorted) {
   dfree((void*)h_.mix);
   h_.mix = nullptr;
@@ -1146,6 +1170,13 @@ void Engine<R>::get_img(int slot, double* dst, int comps) {
   std::vector<R> tmp(cnt);
   copy_sync(tmp.data(), h_.img[slot], cnt * sizeof(R), hipMemcpyDeviceToHost, s0_, "image download");
   for (size_t i = 0; i < cnt; ++i) dst[i] = (double)tmp[i];
+}
+template <typename R>
+void Engine<R>::get_img_dev(int slot, double* dst_dev, int comps) {
+  hip_check(hipStreamSynchronize(s0_), "sync");
+  launch_to_double<R>(h_.img[slot], dst_dev, (size_t)geo_.n * geo_.n * comps, s0_);
+  hip_check(hipGetLastError(), "image conversion launch");
+  hip_check(hipStreamSynchronize(s0_), "image conversion");
 }
 template <typename R>
 void Engine<R>::put_coef(int slot, const double* src) {

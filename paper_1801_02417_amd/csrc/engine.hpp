@@ -111,6 +111,9 @@ struct Engine {
   Engine& operator=(const Engine&) = delete;
 
   void set_data(const double* Y_sorted, double eps);
+  // Y in device memory in the caller's row order (M x 4 complex doubles): false (Y unchanged) if
+  // a value is not finite; returns when the caller's buffer is no longer read
+  bool set_data_dev(const double* Y_dev, double eps);
   // per sorted visibility the 4 x 4 complex row mixing L D_m^T (32 doubles, row-major [s][j],
   // interleaved re, im), or NULL for the fixed L; the iteration state is reset
   void set_mixing(const double* mix_sorted);
@@ -151,6 +154,7 @@ struct Engine {
   void get_state(double* buf);
   void set_state(const double* buf);
   void get_img(int slot, double* dst, int comps);
+  void get_img_dev(int slot, double* dst_dev, int comps);   // into device memory; returns when written
   void profile(int mode, int iters, double* ms);
   size_t coef_elems() const { return coef_elems_; }
   const Tuning& tuning() const { return tuning_; }
@@ -210,6 +214,8 @@ struct Engine {
   Geometry geo_;
   hipStream_t s0_ = nullptr, s1_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+  int* d_perm_ = nullptr;        // the row permutation on the device (set_data_dev), made on first use
+  int* d_flag_ = nullptr;        // set_data_dev's non-finite flag
   int* d_active_ = nullptr;      // adaptive runs: problems still running (device) ...
   int* h_active_ = nullptr;      // ... and its pinned host copies, one per chunk parity
   hipEvent_t ev_active_[2] = {nullptr, nullptr};

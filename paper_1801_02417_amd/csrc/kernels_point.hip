@@ -260,6 +260,37 @@ void launch_finalize_zeta(const ProbDesc* descs, int nprob, hipStream_t s) {
   hipLaunchKernelGGL(finalize_zeta_kernel, dim3(nprob), dim3(64), 0, s, descs);
 }
 
+// The device-pointer data upload: *bad = 1 if any of the n doubles at y is not finite (every
+// offending thread stores the same value).
+__global__ void nonfinite_kernel(const double* __restrict__ y, size_t n, int* bad) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(y[i])) *bad = 1;
+}
+// out row p (sorted order) = y row perm[p] (the caller's order), 8 reals per row, converted to R.
+template <typename R>
+__global__ void gather_rows_kernel(const double* __restrict__ y, const int* __restrict__ perm, R* __restrict__ out,
+                                   long long M) {
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < M * 8; q += (long long)gridDim.x * blockDim.x)
+    out[q] = (R)y[(long long)perm[q >> 3] * 8 + (q & 7)];
+}
+template <typename R>
+__global__ void to_double_kernel(const R* __restrict__ src, double* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+void launch_nonfinite(const double* y, size_t n, int* bad, hipStream_t s) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
+  if (n > 0) hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, y, n, bad);
+}
+template <typename R> void launch_gather_rows(const double* y, const int* perm, void* out, long long M, hipStream_t s) {
+  const long long blocks = std::min<long long>((M * 8 + 255) / 256, 16384);
+  if (M > 0) hipLaunchKernelGGL((gather_rows_kernel<R>), dim3((unsigned)blocks), dim3(256), 0, s, y, perm, (R*)out, M);
+}
+template <typename R> void launch_to_double(const void* src, double* dst, size_t n, hipStream_t s) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
+  if (n > 0) hipLaunchKernelGGL((to_double_kernel<R>), dim3((unsigned)blocks), dim3(256), 0, s, (const R*)src, dst, n);
+}
+
 #define PSARA_INST(R)                                                       \
   template void launch_primal<R>(int, const LaunchArgs&);                   \
   template void launch_relvar<R>(const LaunchArgs&);                        \
@@ -268,7 +299,9 @@ void launch_finalize_zeta(const ProbDesc* descs, int nprob, hipStream_t s) {
   template void launch_img_dot<R>(const LaunchArgs&, int, int);             \
   template void launch_img_scale<R>(const LaunchArgs&, int, int, int);      \
   template void launch_fill<R>(void*, size_t, hipStream_t);                 \
-  template void launch_scale<R>(void*, size_t, double, hipStream_t);
+  template void launch_scale<R>(void*, size_t, double, hipStream_t);       \
+  template void launch_gather_rows<R>(const double*, const int*, void*, long long, hipStream_t); \
+  template void launch_to_double<R>(const void*, double*, size_t, hipStream_t);
 PSARA_INST(float)
 PSARA_INST(double)
 #undef PSARA_INST

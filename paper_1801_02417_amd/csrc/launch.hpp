@@ -80,5 +80,9 @@ void launch_stop_decide(const ProbDesc* descs, int nprob, int chunk, int* active
 // scal[scalar] = max of the first entries of `count` pairs of generic region q
 void launch_finalize_max(const ProbDesc* descs, int nprob, int q, int count, int scalar, hipStream_t s);
 template <typename R> void launch_scale(void* p, size_t count, double factor, hipStream_t s);
+// device-pointer data and image transfers (psara_set_data_dev, psara_get_image_dev)
+void launch_nonfinite(const double* y, size_t n, int* bad, hipStream_t s);
+template <typename R> void launch_gather_rows(const double* y, const int* perm, void* out, long long M, hipStream_t s);
+template <typename R> void launch_to_double(const void* src, double* dst, size_t n, hipStream_t s);
 
 }  // namespace psara

@@ -26,7 +26,7 @@ ALL_BASES = 0x1FF      # Dirac + Db1..Db8
 
 EXPORTS = (
     "psara_create", "psara_destroy", "psara_last_error", "psara_status_string", "psara_set_operator",
-    "psara_set_data", "psara_set_prior", "psara_set_steps", "psara_opnorm", "psara_solve", "psara_reweight",
+    "psara_set_data", "psara_set_data_dev", "psara_get_image_dev", "psara_set_prior", "psara_set_steps", "psara_opnorm", "psara_solve", "psara_reweight",
     "psara_coef_std", "psara_reweighted_solve", "psara_report_now", "psara_synchronize", "psara_get_image",
     "psara_state_bytes",
     "psara_get_state", "psara_set_state", "psara_reset_state", "psara_footprint", "psara_apply_phi",
@@ -114,6 +114,8 @@ def lib() -> C.CDLL:
         "psara_status_string": (C.c_char_p, [I]),
         "psara_set_operator": (I, [P, I, I64, D, I, I, I]),
         "psara_set_data": (I, [P, D, C.c_double]),
+        "psara_set_data_dev": (I, [P, P, C.c_double]),
+        "psara_get_image_dev": (I, [P, P]),
         "psara_set_prior": (I, [P, U32, I, D, C.c_double]),
         "psara_set_steps": (I, [P, C.c_double, C.c_double, C.c_double, C.c_double]),
         "psara_runtime_check": (I, [C.POINTER(I), C.POINTER(I)]),
@@ -239,6 +241,11 @@ def psara_set_operator(ctx, n: int, uv: np.ndarray, oversample: int = 2, taps: i
 def psara_set_data(ctx, Y: np.ndarray, epsilon: float) -> None:
     y = _vis(Y)
     _check(ctx, lib().psara_set_data(ctx, _dptr(y), float(epsilon)))
+
+
+def psara_set_data_dev(ctx, Y_dev: int, epsilon: float) -> None:
+    """Y_dev: the device address (an integer, e.g. a tensor's data_ptr()) of M x 4 complex128."""
+    _check(ctx, lib().psara_set_data_dev(ctx, C.c_void_p(int(Y_dev)), float(epsilon)))
 
 
 def psara_set_prior(ctx, basis_mask: int, levels: int, weights: Optional[np.ndarray], gamma: float) -> None:
@@ -403,6 +410,11 @@ def psara_get_image(ctx, N: int) -> np.ndarray:
     out = np.empty((N, 4))
     _check(ctx, lib().psara_get_image(ctx, _dptr(out)))
     return out
+
+
+def psara_get_image_dev(ctx, S_dev: int) -> None:
+    """S_dev: the device address of N x 4 doubles."""
+    _check(ctx, lib().psara_get_image_dev(ctx, C.c_void_p(int(S_dev))))
 
 
 def psara_state_bytes(ctx) -> int:

@@ -142,11 +142,13 @@ __device__ inline void write_partials(const ProbDesc& P, int part, const KSum& k
 // items: {prob, wavelet index, tile, partial index}; tile side dwt_ana_tile(h) per band.
 // TOM is the largest tile side among the launch's items: the LDS buffers are sized for it, so a
 // launch whose problems all use 8-wide tiles holds 22 KB (FP32) instead of 57 KB per workgroup.
+// The row pass's results overwrite the staged input (rowt aliases in: the pass holds its
+// outputs in registers across a barrier), so a workgroup needs one buffer.
 template <typename R, int TOM> struct AnaSmem {
   static constexpr int TO = TOM;
   static constexpr int IN = 2 * TO + kMaxFilter - 2;
   V4<R> in[IN * IN];
-  V4<R> rowt[IN * 2 * TO];
+  __device__ V4<R>* rowt() { return in; }
 };
 
 template <typename R, int MODE, int F, int TOM>
@@ -160,8 +162,33 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
   const int in = 2 * to + F - 2;
   const size_t base = (size_t)(P.has_dirac + w) * n * n;
   const bool last = (level == P.levels);
-  // prefetch the duals and thresholds this thread updates (their latency overlaps the filtering)
   constexpr int NPF = (TOM * 2 * TOM + 255) / 256;
+  const V4<R>* __restrict__ src = (level == 1)
+      ? (const V4<R>*)P.img[src_slot]
+      : (const V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level - 1];
+  for (int q = threadIdx.x; q < in * in; q += blockDim.x) {
+    const int a = q / in, b = q - a * in;
+    sm.in[q] = src[(size_t)((2 * o1 + a) & (m - 1)) * m + ((2 * o2 + b) & (m - 1))];
+  }
+  __syncthreads();
+  // rows: along the column index, into registers, then over the staged input
+  constexpr int NQ = (AnaSmem<R, TOM>::IN * TOM + 255) / 256;
+  V4<R> ra[NQ], rd[NQ];
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    const int q = threadIdx.x + u * 256;
+    if (q < in * to) {
+      const int a = q / to, k = q - a * to;
+      V4<R> sa = v4_zero<R>(), sd = v4_zero<R>();
+      const V4<R>* row = sm.in + a * in + 2 * k;
+#pragma unroll
+      for (int j = 0; j < F; ++j) { const V4<R> x = row[j]; v4_fma(sa, t.h[j], x); v4_fma(sd, t.g[j], x); }
+      ra[u] = sa;
+      rd[u] = sd;
+    }
+  }
+  // the duals and thresholds this thread updates, requested now so their latency overlaps the
+  // column filtering
   V4<R> pa[NPF][2], pg[NPF][2];
   if (MODE == AM_DUAL) {
     const V4<R>* __restrict__ A = (const V4<R>*)P.coef[COEF_A];
@@ -178,23 +205,16 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
       }
     }
   }
-  const V4<R>* __restrict__ src = (level == 1)
-      ? (const V4<R>*)P.img[src_slot]
-      : (const V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level - 1];
-  for (int q = threadIdx.x; q < in * in; q += blockDim.x) {
-    const int a = q / in, b = q - a * in;
-    sm.in[q] = src[(size_t)((2 * o1 + a) & (m - 1)) * m + ((2 * o2 + b) & (m - 1))];
-  }
-  __syncthreads();
-  // rows: along the column index
-  for (int q = threadIdx.x; q < in * to; q += blockDim.x) {
-    const int a = q / to, k = q - a * to;
-    V4<R> sa = v4_zero<R>(), sd = v4_zero<R>();
-    const V4<R>* row = sm.in + a * in + 2 * k;
+  __syncthreads();                       // every thread is done reading the staged input
+  V4<R>* rowt = sm.rowt();
 #pragma unroll
-    for (int j = 0; j < F; ++j) { const V4<R> x = row[j]; v4_fma(sa, t.h[j], x); v4_fma(sd, t.g[j], x); }
-    sm.rowt[a * (2 * to) + k] = sa;
-    sm.rowt[a * (2 * to) + to + k] = sd;
+  for (int u = 0; u < NQ; ++u) {
+    const int q = threadIdx.x + u * 256;
+    if (q < in * to) {
+      const int a = q / to, k = q - a * to;
+      rowt[a * (2 * to) + k] = ra[u];
+      rowt[a * (2 * to) + to + k] = rd[u];
+    }
   }
   __syncthreads();
   // columns, then the per-coefficient operation
@@ -209,7 +229,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
       V4<R> ca = v4_zero<R>(), cd = v4_zero<R>();
 #pragma unroll
       for (int j = 0; j < F; ++j) {
-        const V4<R> x = sm.rowt[(2 * kr + j) * (2 * to) + c];
+        const V4<R> x = rowt[(2 * kr + j) * (2 * to) + c];
         v4_fma(ca, t.h[j], x);
         v4_fma(cd, t.g[j], x);
       }

@@ -416,8 +416,9 @@ synthesis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ it
 // Dirac block.  The next basis's windows are loaded into registers while the current one is
 // filtered.  items: {prob, tile, part, mask of bases}; part 0 writes dst_slot (with the Dirac
 // block), part 1 dst_slot2, so that a tile's bases can be split over two workgroups.
+// (FP32: at most 96 registers, so five workgroups fit a CU; the kernel needs no more)
 template <typename R>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, sizeof(R) == 4 ? 5 : 1)
 synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_coef, int dst_slot,
                        int add_dirac, int dst_slot2) {
   __shared__ SynSmem<R> sm;

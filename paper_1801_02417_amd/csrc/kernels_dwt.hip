@@ -492,11 +492,29 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
   // every coarse band lies in the top-left m0 x m0 block of the basis: its duals (into pyr,
   // where the updated ones are kept) and thresholds are staged with the low-low band, so the
   // dual updates below read LDS only
-  for (int q = threadIdx.x; q < m * m; q += nt) {
-    const size_t g = (size_t)(q / m0) * n + q % m0;
-    bufA[q] = ll[4 * (P.ll_off[c_level - 1] + q) + ch];
-    pyr[q] = A[4 * g + ch];
-    gw[q] = GW[4 * g + ch];
+  // (each thread's loads are all issued before its LDS stores, so they are in flight together)
+  {
+    constexpr int NS = (CoarseMax<R>::value * CoarseMax<R>::value + 511) / 512;
+    R va[NS], vp[NS], vg[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int q = threadIdx.x + u * nt;
+      if (q < m * m) {
+        const size_t g = (size_t)(q / m0) * n + q % m0;
+        va[u] = ll[4 * (P.ll_off[c_level - 1] + q) + ch];
+        vp[u] = A[4 * g + ch];
+        vg[u] = GW[4 * g + ch];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int q = threadIdx.x + u * nt;
+      if (q < m * m) {
+        bufA[q] = va[u];
+        pyr[q] = vp[u];
+        gw[q] = vg[u];
+      }
+    }
   }
   __syncthreads();
   // ---- analysis c..L (bufA holds the m x m low-low band) ----

@@ -294,7 +294,10 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 }
 
 // ---------------------------------------------------------------------------------------------
-// P7: grid (adjoint of G, after mixing by L^H).  items: {prob, chunk (-1: the factor item), -, -}
+// P7: grid (adjoint of G, after mixing by L^H).  items: {prob, chunk, first list entry, end}
+// for a chunk of more than kSmallChunk entries, {prob, kGridFactorItem, -, -} for the factor
+// item, {prob, kGridSmallItem, first of small_ids, count} for up to eight small chunks
+// (grid_small above: one wave each, summed in registers in a fixed order).
 //
 // The grid is cut into kGridTile x kGridTile tiles and every visibility belongs to the tile
 // holding its window start, so it is gridded exactly once; the workgroup accumulates the tile
@@ -309,15 +312,16 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 // The tile accumulates in 64-bit fixed point with integer LDS atomics: integer addition is
 // associative, so the result does not depend on the order in which lanes arrive (the
 // gridding is bitwise reproducible), and integer LDS atomics run far faster than floating
-// ones.  The scale is the power of two 2^E <= 2^49 (FP32) or 2^61 (FP64) divided by
+// ones.  The scale is the power of two 2^E <= 2^48 (FP32) or 2^61 (FP64) divided by
 // sum_v max_c |u_v,c| over the chunk, a bound on any partial sum of a cell (the kernel weights
 // are at most 1), so no sum leaves the range of the conversion; the absolute rounding per
-// addition is at most 2^-50 (2^-62) of that bound.
+// addition is at most 2^-49 (2^-62) of that bound.
 //
-// The finished region goes to the chunk's partial slot; the column inverse FFT sums, for each
-// cell, the slots of its own tile and of the up to three tiles whose halos cover it, in a fixed
-// order, and multiplies the sum by the scalar factor of B, which the gridding leaves out: one
-// item per problem (chunk index -1, first in the work list, so it runs beside the chunks)
+// The cells of the chunk's box (those its windows reach) go to the chunk's partial slot; the
+// column inverse FFT sums, for each cell, the slots of its own tile and of the up to three
+// tiles whose halos cover it, in a fixed order, and multiplies the sum by the scalar factor of
+// B, which the gridding leaves out: one item per problem (kGridFactorItem, first in the work
+// list, so it runs beside the chunks)
 // stores that factor -- GR_DUAL: c, reduced in a fixed order from the de-grid partials and
 // also kept for the next iteration; GR_PLAIN: 1, or the stored c when use_cfac is set;
 // GR_STOKES: 1.

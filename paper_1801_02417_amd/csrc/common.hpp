@@ -133,6 +133,9 @@ __host__ __device__ inline bool in_box(int box, int o1, int o2) {
   return o1 >= (box & 255) && o1 <= ((box >> 8) & 255) && o2 >= ((box >> 16) & 255) && o2 <= ((box >> 24) & 255);
 }
 
+// log2 of a power of two
+__host__ __device__ inline int lg2(int p) { return __builtin_ctz((unsigned)p); }
+
 // A gridding run in one word: the offset of its first entry in its chunk (< 1024), its length
 // (1 .. 32) and its window start relative to its tile (o1, o2 < 16).
 __host__ __device__ constexpr int pack_run(int off, int len, int o1, int o2) {

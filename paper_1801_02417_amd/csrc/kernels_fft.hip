@@ -70,14 +70,17 @@ template <typename R, int RAD>
 __device__ inline void stockham_pass(cplx<R>* x, int K, int Ns, int tl, int per_line, int ch, bool inv,
                                      const cplx<R>* __restrict__ tw) {
   constexpr int NB = 8 / RAD;
-  const int stride = K / RAD;
+  constexpr int LR = RAD == 8 ? 3 : RAD == 4 ? 2 : 1;   // log2 RAD
+  // K and Ns are powers of two: divisions by them are shifts and masks
+  const int lk = lg2(K), ls = lg2(Ns);
+  const int stride = K >> LR;
   cplx<R> v[8];
   // the pass's twiddles first, so that their loads are in flight across the barrier
-  const int twstep = K / (Ns * RAD);
+  const int twstep = K >> (ls + LR);
   cplx<R> wt[NB][RAD];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int k = (tl + b * per_line) % Ns;
+    const int k = (tl + b * per_line) & (Ns - 1);
 #pragma unroll
     for (int r = 1; r < RAD; ++r) wt[b][r] = tw[r * k * twstep];
   }
@@ -91,7 +94,7 @@ __device__ inline void stockham_pass(cplx<R>* x, int K, int Ns, int tl, int per_
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = tl + b * per_line;
-    const int k = j % Ns;
+    const int k = j & (Ns - 1);
 #pragma unroll
     for (int r = 1; r < RAD; ++r) {
       cplx<R> w = wt[b][r];
@@ -101,7 +104,7 @@ __device__ inline void stockham_pass(cplx<R>* x, int K, int Ns, int tl, int per_
     if (RAD == 8) dft8(v + b * 8, inv);
     else if (RAD == 4) dft4(v[b * 4], v[b * 4 + 1], v[b * 4 + 2], v[b * 4 + 3], inv);
     else dft2(v[b * 2], v[b * 2 + 1]);
-    const int base = (j / Ns) * Ns * RAD + k;
+    const int base = ((j >> ls) << (ls + LR)) + k;
 #pragma unroll
     for (int r = 0; r < RAD; ++r) x[4 * (base + r * Ns) + ch] = v[b * RAD + r];
   }
@@ -114,11 +117,11 @@ template <typename R, int CELLS>
 __device__ void fft_lines(Cell<R>* lds, int K, bool inv, const cplx<R>* __restrict__ tw) {
   const int per_line = K >> 3;
   const int ch = threadIdx.x & 3, grp = threadIdx.x >> 2;
-  const int l = grp / per_line, tl = grp - l * per_line;
+  const int l = grp >> lg2(per_line), tl = grp & (per_line - 1);
   cplx<R>* x = (cplx<R>*)(lds + l * K);
   int Ns = 1;
   while (Ns < K) {
-    const int rem = K / Ns;
+    const int rem = K >> lg2(Ns);
     if (rem % 8 == 0) { stockham_pass<R, 8>(x, K, Ns, tl, per_line, ch, inv, tw); Ns *= 8; }
     else if (rem % 4 == 0) { stockham_pass<R, 4>(x, K, Ns, tl, per_line, ch, inv, tw); Ns *= 4; }
     else { stockham_pass<R, 2>(x, K, Ns, tl, per_line, ch, inv, tw); Ns *= 2; }
@@ -158,6 +161,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   if (halted(P)) return;                 // stopped by an adaptive run
   const int n = P.n, K = P.K, h2 = n / 2;
   const int lines = CELLS / K;
+  const int lgK = lg2(K), lgL = lg2(lines), lgN = lg2(n);   // all powers of two
   const int line0 = it.y;
   const R* __restrict__ s = (const R*)P.deapod;
   Cell<R>* __restrict__ half = (Cell<R>*)P.half;
@@ -194,9 +198,9 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
     trow0 = line0 / kGridTile - 1;
     const int ntr = min(K - 1, line0 + lines - 1) / kGridTile - trow0 + 1;
     for (int i = threadIdx.x; i < ntr * ntg; i += nthr) {
-      const int rr = i / ntg, u1 = i - rr * ntg;
-      tsl[i] = P.tile_slots[u1 * ntg + (trow0 + rr + ntg) % ntg];
-      tbx[i] = P.tile_box[u1 * ntg + (trow0 + rr + ntg) % ntg];
+      const int rr = i >> lg2(ntg), u1 = i & (ntg - 1);
+      tsl[i] = P.tile_slots[u1 * ntg + ((trow0 + rr + ntg) & (ntg - 1))];
+      tbx[i] = P.tile_box[u1 * ntg + ((trow0 + rr + ntg) & (ntg - 1))];
     }
     __syncthreads();
   }
@@ -204,7 +208,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   for (int q = threadIdx.x; q < lines * K; q += nthr) {
     Cell<R> c = zero_cell<R>();
     if (PASS == 0) {
-      const int l = q / K, k = q - l * K, r = line0 + l;
+      const int l = q >> lgK, k = q & (K - 1), r = line0 + l;
       const int col = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
       if (r < n && col >= 0) {
         V4<R> v;
@@ -215,7 +219,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       }
       lds[q] = c;
     } else if (PASS == 1) {
-      const int l = q / K, k = q - l * K, k2 = line0 + l;
+      const int l = q >> lgK, k = q & (K - 1), k2 = line0 + l;
       const int r = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
       if (k2 < K && r >= 0) c = half[(size_t)k2 * n + r];
       lds[q] = c;
@@ -223,7 +227,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       // the gridded values: the partial slots of the cell's tile and of the tiles whose halos
       // reach it (the previous tile in k1, in k2, and in both), in that order, times the
       // factor the gridding pass left out
-      const int l = q / K, k = q - l * K, k2 = line0 + l;
+      const int l = q >> lgK, k = q & (K - 1), k2 = line0 + l;
       if (k2 < K) {
         const int ntg = P.ntile_side_g, RG = kGridTile + P.T - 1;
         const int t1 = k / kGridTile, t2 = k2 / kGridTile, a1 = k - t1 * kGridTile, a2 = k2 - t2 * kGridTile;
@@ -232,7 +236,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
           const int d1 = d & 1, d2 = d >> 1;
           const int o1 = a1 + d1 * kGridTile, o2 = a2 + d2 * kGridTile;
           if (o1 >= RG || o2 >= RG) continue;
-          const int s1 = (t1 - d1 + ntg) % ntg;
+          const int s1 = (t1 - d1 + ntg) & (ntg - 1);
           const int2 ts = tsl[(t2 - d2 - trow0) * ntg + s1];
           if (!in_box(tbx[(t2 - d2 - trow0) * ntg + s1], o1, o2)) continue;   // no slot of the tile reaches it
           const Cell<R>* part = (const Cell<R>*)P.gpart + (size_t)ts.x * RG * RG + o2 * RG + o1;
@@ -248,7 +252,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       }
       lds[q] = c;
     } else {
-      const int k2 = q / lines, l = q - k2 * lines, r = line0 + l;
+      const int k2 = q >> lgL, l = q & (lines - 1), r = line0 + l;
       if (r < n) c = half[(size_t)k2 * n + r];
       lds[l * K + k2] = c;
     }
@@ -262,7 +266,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
     // and its X, deapodised and zero-padded, replaces the row in place (a pixel's crop position
     // and its zero-padding position are the same cell)
     for (int q = threadIdx.x; q < lines * K; q += nthr) {
-      const int l = q / K, k = q - l * K, r = line0 + l;
+      const int l = q >> lgK, k = q & (K - 1), r = line0 + l;
       const int col = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
       Cell<R> c = zero_cell<R>();
       if (r < n && col >= 0) {
@@ -285,24 +289,24 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   // ---- store ----
   if (PASS == 0 || PASS == 4) {
     for (int q = threadIdx.x; q < lines * K; q += nthr) {
-      const int k2 = q / lines, l = q - k2 * lines, r = line0 + l;
+      const int k2 = q >> lgL, l = q & (lines - 1), r = line0 + l;
       if (r < n) half[(size_t)k2 * n + r] = lds[l * K + k2];
     }
   } else if (PASS == 1) {
     for (int q = threadIdx.x; q < lines * K; q += nthr) {
-      const int l = q / K, k1 = q - l * K, k2 = line0 + l;
+      const int l = q >> lgK, k1 = q & (K - 1), k2 = line0 + l;
       if (k2 < K) grid[(size_t)k2 * K + k1] = lds[q];
     }
   } else if (PASS == 2) {
     for (int q = threadIdx.x; q < lines * n; q += nthr) {
-      const int l = q / n, r = q - l * n, k2 = line0 + l;
+      const int l = q >> lgN, r = q & (n - 1), k2 = line0 + l;
       const int pos = r < h2 ? r + (K - h2) : r - h2;        // (r - n/2) mod K
       if (k2 < K) half[(size_t)k2 * n + r] = lds[l * K + pos];
     }
   } else {
     V4<R>* __restrict__ out = (V4<R>*)P.img[dst_slot];
     for (int q = threadIdx.x; q < lines * n; q += nthr) {
-      const int l = q / n, c = q - l * n, r = line0 + l;
+      const int l = q >> lgN, c = q & (n - 1), r = line0 + l;
       const int pos = c < h2 ? c + (K - h2) : c - h2;
       if (r < n) {
         const Cell<R> v = lds[l * K + pos];

@@ -27,6 +27,11 @@
 
 namespace psara {
 
+// q / d for 0 <= q < 2^14 and 1 <= d <= 128 by a float multiply: (q + 0.5) times the rounded
+// reciprocal of d (even one ulp off) stays inside (q / d rounded down, + 1), which holds for
+// every such q and d; rcp = 1 / d is computed once.
+__device__ inline int small_div(int q, float rcp) { return (int)(((float)q + 0.5f) * rcp); }
+
 template <typename R>
 __device__ inline void v4_fma(V4<R>& acc, R w, const V4<R>& x) {
   acc.x += w * x.x; acc.y += w * x.y; acc.z += w * x.z; acc.w += w * x.w;
@@ -158,8 +163,10 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
   const int n = P.n;
   const int m = n >> (level - 1), h = m >> 1;
   const int to = dwt_ana_tile<R>(h, P.ana_wide != 0), tps = h / to;
-  const int o1 = (tile / tps) * to, o2 = (tile % tps) * to;
+  const int lto = lg2(to);                         // to and tps are powers of two
+  const int o1 = (tile >> lg2(tps)) * to, o2 = (tile & (tps - 1)) * to;
   const int in = 2 * to + F - 2;
+  const float rin = 1.0f / (float)in;
   const size_t base = (size_t)(P.has_dirac + w) * n * n;
   const bool last = (level == P.levels);
   constexpr int NPF = (TOM * 2 * TOM + 255) / 256;
@@ -167,7 +174,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
       ? (const V4<R>*)P.img[src_slot]
       : (const V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level - 1];
   for (int q = threadIdx.x; q < in * in; q += blockDim.x) {
-    const int a = q / in, b = q - a * in;
+    const int a = small_div(q, rin), b = q - a * in;
     sm.in[q] = src[(size_t)((2 * o1 + a) & (m - 1)) * m + ((2 * o2 + b) & (m - 1))];
   }
   __syncthreads();
@@ -178,7 +185,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
   for (int u = 0; u < NQ; ++u) {
     const int q = threadIdx.x + u * 256;
     if (q < in * to) {
-      const int a = q / to, k = q - a * to;
+      const int a = q >> lto, k = q & (to - 1);
       V4<R> sa = v4_zero<R>(), sd = v4_zero<R>();
       const V4<R>* row = sm.in + a * in + 2 * k;
 #pragma unroll
@@ -197,7 +204,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
     for (int u = 0; u < NPF; ++u) {
       const int q = threadIdx.x + u * 256;
       if (q < to * 2 * to) {
-        const int kr = q / (2 * to), c = q - kr * (2 * to);
+        const int kr = q >> (lto + 1), c = q & (2 * to - 1);
         const int col = (c < to) ? o2 + c : h + o2 + (c - to);
         const size_t ia = base + (size_t)(o1 + kr) * n + col, id = base + (size_t)(h + o1 + kr) * n + col;
         if (!(c < to && !last)) { pa[u][0] = A[ia]; pg[u][0] = GW[ia]; }
@@ -211,7 +218,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
   for (int u = 0; u < NQ; ++u) {
     const int q = threadIdx.x + u * 256;
     if (q < in * to) {
-      const int a = q / to, k = q - a * to;
+      const int a = q >> lto, k = q & (to - 1);
       rowt[a * (2 * to) + k] = ra[u];
       rowt[a * (2 * to) + to + k] = rd[u];
     }
@@ -225,7 +232,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
   for (int u = 0; u < NPF; ++u) {
     const int q = threadIdx.x + u * 256;
     if (q < to * 2 * to) {
-      const int kr = q / (2 * to), c = q - kr * (2 * to);
+      const int kr = q >> (lto + 1), c = q & (2 * to - 1);
       V4<R> ca = v4_zero<R>(), cd = v4_zero<R>();
 #pragma unroll
       for (int j = 0; j < F; ++j) {
@@ -337,11 +344,13 @@ __device__ __forceinline__ void syn_filter(const ProbDesc& P, SynSmem<R>& sm, in
   const Taps<R, F> t((const R*)P.filters + w * kMaxFilter);
   const int off = kMaxFilter / 2 - F / 2;          // sub-window of this filter length
   const int kw = to / 2 + F / 2 - 1, th = to / 2;
+  const float rkw = 1.0f / (float)kw;
+  const int lth = lg2(th);
   const int ks1 = o1 / 2 - (kMaxFilter / 2 - 1), ks2 = o2 / 2 - (kMaxFilter / 2 - 1);
   __syncthreads();
   // inverse column transform (along the row index): row pairs at full resolution
   for (int q = threadIdx.x; q < th * kw; q += blockDim.x) {
-    const int rp = q / kw, b = q - rp * kw + off;
+    const int rp = small_div(q, rkw), b = q - rp * kw + off;
     const int a0 = (o1 >> 1) + rp - ks1;             // coefficient row of output rows 2rp, 2rp+1
     V4<R> sa0 = v4_zero<R>(), sd0 = v4_zero<R>(), sa1 = v4_zero<R>(), sd1 = v4_zero<R>();
 #pragma unroll
@@ -365,7 +374,7 @@ __device__ __forceinline__ void syn_filter(const ProbDesc& P, SynSmem<R>& sm, in
   for (int u = 0; u < NPAIR; ++u) {
     const int q = threadIdx.x + u * 256;
     if (q < to * th) {
-      const int ir = q / th, cp = q - ir * th;
+      const int ir = q >> lth, cp = q & (th - 1);
       const int b0 = (o2 >> 1) + cp - ks2;
       V4<R> s0 = acc[2 * u], s1 = acc[2 * u + 1];
 #pragma unroll
@@ -392,7 +401,8 @@ synthesis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ it
   const int w = it.y;
   const int m = P.n >> (level - 1);
   const int to = dwt_syn_tile<R>(m), tps = m / to, th = to / 2;
-  const int o1 = (it.z / tps) * to, o2 = (it.z % tps) * to;
+  const int lth = lg2(th);                         // powers of two
+  const int o1 = (it.z >> lg2(tps)) * to, o2 = (it.z & (tps - 1)) * to;
   V4<R> acc[2 * NPAIR], pre[4];
 #pragma unroll
   for (int u = 0; u < 2 * NPAIR; ++u) acc[u] = v4_zero<R>();
@@ -405,7 +415,7 @@ synthesis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ it
   for (int u = 0; u < NPAIR; ++u) {
     const int q = threadIdx.x + u * 256;
     if (q < to * th) {
-      V4<R>* o = out + (size_t)(o1 + q / th) * m + o2 + 2 * (q % th);
+      V4<R>* o = out + (size_t)(o1 + (q >> lth)) * m + o2 + 2 * (q & (th - 1));
       o[0] = acc[2 * u];
       o[1] = acc[2 * u + 1];
     }
@@ -428,7 +438,8 @@ synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restric
   if (halted(P)) return;                 // stopped by an adaptive run
   const int n = P.n;
   const int to = dwt_syn_tile<R>(n), tps = n / to, th = to / 2;
-  const int o1 = (it.y / tps) * to, o2 = (it.y % tps) * to;
+  const int lth = lg2(th);                         // powers of two
+  const int o1 = (it.y >> lg2(tps)) * to, o2 = (it.y & (tps - 1)) * to;
   V4<R> acc[2 * NPAIR], pre[4];
 #pragma unroll
   for (int u = 0; u < 2 * NPAIR; ++u) acc[u] = v4_zero<R>();
@@ -453,7 +464,7 @@ synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restric
   for (int u = 0; u < 2 * NPAIR; ++u) {
     const int q = threadIdx.x + (u >> 1) * 256;
     if (q < to * th) {
-      const size_t idx = (size_t)(o1 + q / th) * n + o2 + 2 * (q % th) + (u & 1);
+      const size_t idx = (size_t)(o1 + (q >> lth)) * n + o2 + 2 * (q & (th - 1)) + (u & 1);
       V4<R> s = acc[u];
       if (first && add_dirac && P.has_dirac) {
         const V4<R> d = dirac[idx];
@@ -500,7 +511,7 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
     for (int u = 0; u < NS; ++u) {
       const int q = threadIdx.x + u * nt;
       if (q < m * m) {
-        const size_t g = (size_t)(q / m0) * n + q % m0;
+        const size_t g = (size_t)(q >> lg2(m0)) * n + (q & (m0 - 1));
         va[u] = ll[4 * (P.ll_off[c_level - 1] + q) + ch];
         vp[u] = A[4 * g + ch];
         vg[u] = GW[4 * g + ch];
@@ -521,7 +532,7 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
   for (int l = c_level; l <= L; ++l) {
     const int h = m >> 1;
     for (int q = threadIdx.x; q < m * h; q += nt) {          // rows: bufB[r][k] = a, bufB[r][h+k] = d
-      const int r = q / h, k = q - r * h;
+      const int r = q >> lg2(h), k = q & (h - 1);
       R sa = R(0), sd = R(0);
 #pragma unroll
       for (int j = 0; j < F; ++j) {
@@ -534,7 +545,7 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
     }
     __syncthreads();
     for (int q = threadIdx.x; q < h * m; q += nt) {          // columns; q = (k, col)
-      const int k = q / m, col = q - k * m;
+      const int k = q >> lg2(m), col = q & (m - 1);
       R ca = R(0), cd = R(0);
 #pragma unroll
       for (int j = 0; j < F; ++j) {
@@ -562,7 +573,7 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
   // ---- synthesis L..c on the updated duals (bufA: the h x h low-low input) ----
   {
     const int h = n >> L;
-    for (int q = threadIdx.x; q < h * h; q += nt) bufA[q] = pyr[(q / h) * m0 + q % h];
+    for (int q = threadIdx.x; q < h * h; q += nt) bufA[q] = pyr[(q >> lg2(h)) * m0 + (q & (h - 1))];
   }
   __syncthreads();
   for (int l = L; l >= c_level; --l) {
@@ -570,7 +581,7 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
     // inverse column transform: bufB[ir][b] (b < h) from LL/LH, bufB[mo*h + ir*h + b] from HL/HH;
     // output rows 2r', 2r'+1 read the same coefficients through the even / odd taps
     for (int q = threadIdx.x; q < h * h; q += nt) {
-      const int rp = q / h, b = q - rp * h;
+      const int rp = q >> lg2(h), b = q & (h - 1);
       R sa0 = R(0), sd0 = R(0), sa1 = R(0), sd1 = R(0);
 #pragma unroll
       for (int jj = 0; jj < F / 2; ++jj) {
@@ -590,7 +601,7 @@ __device__ __forceinline__ void coarse_body(const ProbDesc& P, int w, int ch, in
     __syncthreads();
     // inverse row transform into bufA (mo x mo), column pairs
     for (int q = threadIdx.x; q < mo * h; q += nt) {
-      const int ir = q / h, cp = q - ir * h;
+      const int ir = q >> lg2(h), cp = q & (h - 1);
       R s0 = R(0), s1 = R(0);
 #pragma unroll
       for (int jj = 0; jj < F / 2; ++jj) {

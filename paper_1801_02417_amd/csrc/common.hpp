@@ -135,6 +135,10 @@ __host__ __device__ inline bool in_box(int box, int o1, int o2) {
 
 // log2 of a power of two
 __host__ __device__ inline int lg2(int p) { return __builtin_ctz((unsigned)p); }
+// q / d for 0 <= q < 2^14 and 1 <= d <= 128 by a float multiply: (q + 0.5) times the rounded
+// reciprocal of d (even one ulp off) stays inside [floor(q / d), floor(q / d) + 1), which holds
+// for every such q and d; rcp = 1 / d is computed once.
+__device__ inline int small_div(int q, float rcp) { return (int)(((float)q + 0.5f) * rcp); }
 
 // A gridding run in one word: the offset of its first entry in its chunk (< 1024), its length
 // (1 .. 32) and its window start relative to its tile (o1, o2 < 16).

@@ -27,11 +27,6 @@
 
 namespace psara {
 
-// q / d for 0 <= q < 2^14 and 1 <= d <= 128 by a float multiply: (q + 0.5) times the rounded
-// reciprocal of d (even one ulp off) stays inside (q / d rounded down, + 1), which holds for
-// every such q and d; rcp = 1 / d is computed once.
-__device__ inline int small_div(int q, float rcp) { return (int)(((float)q + 0.5f) * rcp); }
-
 template <typename R>
 __device__ inline void v4_fma(V4<R>& acc, R w, const V4<R>& x) {
   acc.x += w * x.x; acc.y += w * x.y; acc.z += w * x.z; acc.w += w * x.w;

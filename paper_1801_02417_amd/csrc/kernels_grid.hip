@@ -20,6 +20,7 @@
 // B~ - rho2 P_B(Y,eps)(B~/rho2) without a second pass over the visibilities.
 #include <mutex>
 #include <set>
+#include <type_traits>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -385,6 +386,50 @@ __device__ inline void chunk_preload(const ProbDesc& P, const int4 ch, ChunkPre<
   pre.box = P.slot_box[ch.w];
 }
 
+// Lane moves inside a lane group of eight with DPP (a VALU operand modifier, so no trip
+// through the LDS unit): quad_bcast<K> gives every lane the value of lane K of its quad,
+// half_mirror the value of lane 7 - i of its group of eight.  A double moves as two words.
+template <int CTRL, typename V>
+__device__ inline V dpp_move(V v) {
+  static_assert(sizeof(V) % 4 == 0, "32-bit words");
+  union { V v; int w[sizeof(V) / 4]; } a, b;
+  a.v = v;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(V) / 4); ++k) b.w[k] = __builtin_amdgcn_mov_dpp(a.w[k], CTRL, 0xf, 0xf, true);
+  return b.v;
+}
+template <int K, typename V> __device__ inline V quad_bcast(V v) { return dpp_move<K * 0x55>(v); }
+template <typename V> __device__ inline V half_mirror(V v) { return dpp_move<0x141>(v); }
+
+// The tap product w1 * w2[j] of the lane's tap row and the group's tap column held in
+// accumulator column jj.  For T = 8 the accumulator columns of the upper quad (lanes 4..7) are
+// the tap columns jj ^ 4 (tap_col below): a lane then takes columns 0..3 of its own quad by a
+// quad broadcast of w2 and the other four from the mirrored w2 (lane 7 - i), so every
+// broadcast index is the same in both quads.  T = 4 uses the lower quad alone; T = 6 moves
+// the values with a lane shuffle.
+template <typename R, int T, int JJ>
+__device__ inline R tap_product(R w1, R w2, R w2m) {
+  if constexpr (T == 8) {
+    if constexpr (JJ < 4) return w1 * quad_bcast<JJ>(w2);
+    else return w1 * quad_bcast<7 - JJ>(w2m);
+  } else if constexpr (T == 4) {
+    return w1 * quad_bcast<JJ>(w2);
+  } else {
+    return w1 * __shfl(w2, JJ, 8);
+  }
+}
+template <int T>
+__device__ inline int tap_col(int jj, int lane8) { return T == 8 ? (jj ^ (lane8 & 4)) : jj; }
+
+// f(std::integral_constant<int, J>) for J = B .. E-1, in order
+template <int B, int E, class F>
+__device__ inline void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 // Accumulates a chunk whose rows are staged in LDS (sf: fractional offsets, su: two V4 of
 // gridded channels per entry, entry q the chunk's q-th list entry) into acc, which must be zero,
 // and writes the cells of the chunk's box to its partial slot (the slot's other cells are zero
@@ -437,18 +482,19 @@ __device__ inline void grid_chunk(const ProbDesc& P, const int4 ch,
           const V4<R> v1 = su[2 * (e0 + q) + 1];
           u[4 % NC] = v1.x; u[5 % NC] = v1.y; u[6 % NC] = v1.z; u[7 % NC] = v1.w;
         }
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-          const R wj = w1 * __shfl(w2, j, 8);
+        const R w2m = half_mirror(w2);
+        static_for<0, T>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          const R wj = tap_product<R, T, j>(w1, w2, w2m);
 #pragma unroll
           for (int c = 0; c < NC; ++c) a[j][c] += wj * u[c];
-        }
+        });
       }
       if (len > 0 && lane8 < T) {
         unsigned long long* row = acc + o1 + lane8;
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-          unsigned long long* cell = row + (o2 + j) * RG;
+          unsigned long long* cell = row + (o2 + tap_col<T>(j, lane8)) * RG;
           // one tap column at a time: the empty asm (ordered with the atomics) keeps the
           // compiler from widening all the sums to 64 bits at once, which would spill
           if (NC == 8) {

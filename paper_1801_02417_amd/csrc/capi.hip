@@ -803,7 +803,7 @@ size_t psara_footprint(int n, int64_t M, int taps, int levels, uint32_t basis_ma
   if (!is_pow2(n) || M < 1 || levels < 1) return 0;
   const size_t R = precision == PSARA_FP64 ? 8 : 4;
   const size_t N = (size_t)n * n, K = 2 * (size_t)n;
-  const size_t ts = K >= 512 ? 32 : 16, ntiles = (K / ts) * (K / ts);
+  const size_t ts = psara::degrid_tile((int)K), ntiles = (K / ts) * (K / ts);
   int nb = 0, nwav = 0;
   for (int b = 0; b <= 8; ++b) nb += (basis_mask >> b) & 1u;
   nwav = nb - (int)(basis_mask & 1u);

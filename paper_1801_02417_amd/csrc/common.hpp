@@ -25,6 +25,9 @@ constexpr int kGridSmallItem = -2;   // gridding work item of up to eight small 
 constexpr int kBatchChunk = 8;       // iterations per captured graph of a batch
 constexpr int kChain = 32;           // iterations per captured chain of a single solve
 constexpr int kMaxDegridTile = 32;  // largest de-gridding tile side (the geometry picks 16 or 32)
+// de-gridding tile side for a grid of side K: 32 from K = 64 on (a 32-cell tile stages a 39-cell
+// window with T = 8, 1.49 reads per grid cell against 2.07 for 16-cell tiles), 16 below
+constexpr int degrid_tile(int K) { return K >= 64 ? kMaxDegridTile : kMaxDegridTile / 2; }
 constexpr int kDegridItem = 256;        // default visibilities per de-gridding work item
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
 

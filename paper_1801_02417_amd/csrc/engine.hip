@@ -41,7 +41,7 @@ static void copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind ki
 Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
   Geometry g;
   g.n = n; g.K = alpha * n; g.T = T; g.M = M;
-  g.ts = (g.K >= 512) ? kMaxDegridTile : kMaxDegridTile / 2;
+  g.ts = degrid_tile(g.K);
   g.nts = g.K / g.ts;
   g.ntsg = g.K / kGridTile;
   g.beta = kb_beta(T, alpha);

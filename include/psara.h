@@ -273,8 +273,11 @@ typedef struct {
     int grid_chunk;      /* gridding entries per workgroup: 256, 512 or 1024 (default 1024) */
     int degrid_item;     /* visibilities per de-gridding workgroup: a power of two in [64, 1024]
                             (default 256) */
-    int analysis_wide;   /* 1: 16-wide output tiles for the analysis bands of side >= 128 of FP32
-                            solves (default); 0: 8-wide (more workgroups) */
+    int analysis_wide;   /* bit 0: 16-wide output tiles for the analysis bands of side >= 128 of
+                            FP32 solves (else 8-wide: more workgroups); bit 1: each level-1
+                            workgroup of the iterations filters one staged image region with every
+                            wavelet basis (the image is read once, not once per basis); 0 .. 3,
+                            default 1 */
     int fft_cells;       /* grid cells per FFT workgroup: 0 for max(512, 2n) (default), or 512, 1024,
                             2048 with at least 2n (several grid lines per workgroup) */
 } psara_tuning;
@@ -292,7 +295,7 @@ enum {
 
 /* The autotuner: times the iteration of `mode` (chains of 8 captured iterations, best of three)
  * under candidate shapes, one parameter at a time from the current ones (grid_chunk 1024 / 512 /
- * 256, degrid_item 256 / 128 / 512, analysis_wide 1 / 0, fft_cells default / 1024 / 2048), keeps
+ * 256, degrid_item 256 / 128 / 512, analysis_wide 1 / 0 / 3 / 2, fft_cells default / 1024 / 2048), keeps
  * a candidate that beats the incumbent by 1 %, and applies the fastest.  The iteration state is
  * saved and restored around the trials (the stored state exactly; the operator images the next
  * primal step reads are recomputed).  A shape class is the precision, taps, image side, levels,

@@ -30,6 +30,13 @@ constexpr int kMaxDegridTile = 32;  // largest de-gridding tile side (the geomet
 constexpr int degrid_tile(int K) { return K >= 64 ? kMaxDegridTile : kMaxDegridTile / 2; }
 constexpr int kDegridItem = 256;        // default visibilities per de-gridding work item
 constexpr int kGridTile = 16;       // side of the gridding tiles (the de-gridding tiles are P.ts)
+// analysis tiling (the analysis_wide tuning, a problem's ana_wide), two bits: kAnaWide, 16-wide
+// output tiles for FP32 bands of side >= 128 (else 8-wide); kAnaAllBases, level-1 items of the
+// iterations that run every basis over one staged image region (kAllBases in the item's basis
+// field) instead of one item per basis
+constexpr int kAnaWide = 1;
+constexpr int kAnaAllBases = 2;
+constexpr int kAllBases = -1;
 
 // Chebyshev degree of the per-tap Kaiser-Bessel expansions (max error ~1e-10 / ~1e-15)
 // SARA tile sides: analysis output tile per band for an input of side 2h, and synthesis
@@ -88,7 +95,7 @@ struct ProbDesc {
   int ntile_side_g;       // gridding tiles per side (side kGridTile)
   int n_slots;            // gridding chunks (= partial slots) of the problem
   int dg_item;            // visibilities per de-gridding work item
-  int ana_wide;           // 16-wide output tiles for analysis bands of side >= 128 (FP32)
+  int ana_wide;           // analysis tiling: kAnaWide | kAnaAllBases bits
   long long M;
   double tau, rho1, rho2, rho3, eps, gamma, norm;   // norm = 1/sqrt(nbases)
   double delta;                                     // reweighting delta in use

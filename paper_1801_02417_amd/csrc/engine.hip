@@ -161,7 +161,8 @@ void check_tuning(const Tuning& t, int K) {
     throw Error(PSARA_EINVAL, "grid_chunk must be 256, 512 or 1024");
   if (t.degrid_item < 64 || t.degrid_item > 1024 || (t.degrid_item & (t.degrid_item - 1)))
     throw Error(PSARA_EINVAL, "degrid_item must be a power of two in [64, 1024]");
-  if (t.ana_wide != 0 && t.ana_wide != 1) throw Error(PSARA_EINVAL, "analysis_wide must be 0 or 1");
+  if (t.ana_wide < 0 || t.ana_wide > (kAnaWide | kAnaAllBases))
+    throw Error(PSARA_EINVAL, "analysis_wide must be 0, 1, 2 or 3");
   if (t.fft_cells != 0 && ((t.fft_cells != 512 && t.fft_cells != 1024 && t.fft_cells != 2048) || t.fft_cells < K))
     throw Error(PSARA_EINVAL, "fft_cells must be 0 or 512, 1024 or 2048, and at least the grid side 2n");
 }
@@ -223,18 +224,23 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
 }
 
 void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const int* wav_len, bool fp64, int c_level,
-                     bool ana_wide, int* n_ana_parts) {
+                     int ana_wide, int* n_ana_parts) {
   const int N = n * n;
+  const bool wide = (ana_wide & kAnaWide) != 0;
+  // kAnaAllBases: the iterations' level-1 dual items take every basis of a tile at once
+  const bool all_bases = (ana_wide & kAnaAllBases) != 0 && nwav > 0 && 1 < c_level;
   int part = 0;
   for (int b = 0; b < (N + 255) / 256; ++b) S.dirac.push_back(make_int4(prob, b, 0, part++));
   for (int l = 1; l <= levels; ++l) {
     const int h = n >> l;
-    const int to = fp64 ? dwt_ana_tile<double>(h, ana_wide) : dwt_ana_tile<float>(h, ana_wide), tps = h / to;
+    const int to = fp64 ? dwt_ana_tile<double>(h, wide) : dwt_ana_tile<float>(h, wide), tps = h / to;
     for (int w = 0; w < nwav; ++w)
       for (int t = 0; t < tps * tps; ++t) {
         S.ana[l].push_back(make_int4(prob, w, t, part++));
-        if (l < c_level) S.ana_d[l].push_back(S.ana[l].back());
+        if (l < c_level && !(l == 1 && all_bases)) S.ana_d[l].push_back(S.ana[l].back());
       }
+    if (l == 1 && all_bases)
+      for (int t = 0; t < tps * tps; ++t) S.ana_d[1].push_back(make_int4(prob, kAllBases, t, 0));
   }
   for (int l = 2; l <= levels; ++l) {
     const int m = n >> (l - 1);
@@ -447,7 +453,7 @@ void Engine<R>::build_prior_items() {
   int nap = 0;
   if (h_.tv_kind == 0 && h_.coef[COEF_A] && h_.levels > 0)
     add_prior_items(items_, 0, geo_.n, h_.levels, h_.nwav, h_.wav_len, std::is_same<R, double>::value, c_level_,
-                    tuning_.ana_wide != 0, &nap);
+                    tuning_.ana_wide, &nap);
   ana_parts_ = nap;
   gen_parts_ = std::max((N + 255) / 256, nap);
 }
@@ -1402,7 +1408,7 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
     if (e->has_prior()) {
       int nap = 0;
       add_prior_items(S, (int)i, g.n, e->desc().levels, e->desc().nwav, e->desc().wav_len,
-                      std::is_same<R, double>::value, e->c_level(), e->tuning().ana_wide != 0, &nap);
+                      std::is_same<R, double>::value, e->c_level(), e->tuning().ana_wide, &nap);
     }
   }
   // the gridding launches take the heaviest chunks of all members first

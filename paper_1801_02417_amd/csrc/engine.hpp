@@ -51,7 +51,7 @@ void build_grid_chunks(Geometry& g, int chunk_entries);
 struct Tuning {
   int grid_chunk = kChunkEntries;   // gridding entries per workgroup: 256, 512 or 1024
   int degrid_item = kDegridItem;    // visibilities per de-gridding workgroup: 64 .. 1024
-  int ana_wide = 1;                 // 16-wide analysis tiles for bands of side >= 128 (FP32)
+  int ana_wide = 1;                 // analysis tiling: kAnaWide | kAnaAllBases bits (0 .. 3)
   int fft_cells = 0;                // grid cells per FFT workgroup (0: max(512, K)); 512, 1024, 2048
 };
 // Throws Error(PSARA_EINVAL) for a tuning outside those ranges or with fft_cells below the side K.
@@ -71,7 +71,7 @@ struct ItemSet {
 };
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int dg_item, int* n_p6);
 void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const int* wav_len, bool fp64, int c_level,
-                     bool ana_wide, int* n_ana_parts);
+                     int ana_wide, int* n_ana_parts);
 
 struct DevItems {
   int4* ptr = nullptr;
@@ -87,7 +87,7 @@ struct PassLists {
   int cells = 512, rcells = 512;   // FFT cells per workgroup of the column / row passes
   int max_ts = 16, taps = 8, max_levels = 0;
   int max_n = 0;                   // largest image side among the problems
-  int ana_wide = 1;                // any problem takes 16-wide analysis tiles
+  int ana_wide = 1;                // the problems' analysis tilings (kAnaWide | kAnaAllBases bits)
   int grid_ce = kChunkEntries;     // largest gridding chunk among the problems
   bool sparse = false;             // every problem has a wavelet prior (P2/P3 run)
   bool tv = false;                 // the problems carry a TV prior (Algorithm 3)

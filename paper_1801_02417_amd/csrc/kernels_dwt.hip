@@ -143,38 +143,69 @@ __device__ inline void write_partials(const ProbDesc& P, int part, const KSum& k
 // TOM is the largest tile side among the launch's items: the LDS buffers are sized for it, so a
 // launch whose problems all use 8-wide tiles holds 22 KB (FP32) instead of 57 KB per workgroup.
 // The row pass's results overwrite the staged input (rowt aliases in: the pass holds its
-// outputs in registers across a barrier), so a workgroup needs one buffer.
-template <typename R, int TOM> struct AnaSmem {
+// outputs in registers across a barrier), so a workgroup needs one buffer; with SEP the row
+// results have a buffer of their own, and the staged input outlives the pass (the level-1 items
+// that run every basis over one staged region).
+template <typename R, int TOM, bool SEP = false> struct AnaSmem {
   static constexpr int TO = TOM;
   static constexpr int IN = 2 * TO + kMaxFilter - 2;
   V4<R> in[IN * IN];
-  __device__ V4<R>* rowt() { return in; }
+  V4<R> rt[SEP ? IN * 2 * TO : 1];
+  __device__ V4<R>* rowt() { return SEP ? rt : in; }
 };
 
-template <typename R, int MODE, int F, int TOM>
-__device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>& sm, int w, int level, int tile, int src_slot,
-                              int out_coef, KSum& k1, KSum& k2) {
+// Where an analysis output tile lies: the level's band side m (input) and h (output), the tile
+// side to (a power of two) and the tile's first output row o1 and column o2.
+struct AnaTile {
+  int m, h, to, lto, o1, o2;
+};
+template <typename R>
+__device__ inline AnaTile ana_tile(const ProbDesc& P, int level, int tile) {
+  AnaTile t;
+  t.m = P.n >> (level - 1);
+  t.h = t.m >> 1;
+  t.to = dwt_ana_tile<R>(t.h, (P.ana_wide & kAnaWide) != 0);
+  t.lto = lg2(t.to);
+  const int tps = t.h >> t.lto;
+  t.o1 = (tile >> lg2(tps)) * t.to;
+  t.o2 = (tile & (tps - 1)) * t.to;
+  return t;
+}
+
+// Stages the in x in input elements of a tile (from row 2 o1, column 2 o2 of the m x m band src,
+// wrapped periodically) into sm.in as rows of in elements.
+template <typename R, class Smem>
+__device__ inline void ana_stage(Smem& sm, const V4<R>* __restrict__ src, const AnaTile& g, int in) {
+  const float rin = 1.0f / (float)in;
+  for (int q = threadIdx.x; q < in * in; q += blockDim.x) {
+    const int a = small_div(q, rin), b = q - a * in;
+    sm.in[q] = src[(size_t)((2 * g.o1 + a) & (g.m - 1)) * g.m + ((2 * g.o2 + b) & (g.m - 1))];
+  }
+}
+
+// One basis w over one output tile.  ins = 0: stages the tile's input for this filter first;
+// otherwise the input is staged already, as rows of ins elements (ins >= 2 to + F - 2).
+template <typename R, int MODE, int F, int TOM, bool SEP>
+__device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM, SEP>& sm, int w, int level, int tile,
+                                              int src_slot, int out_coef, KSum& k1, KSum& k2, int ins) {
   const Taps<R, F> t((const R*)P.filters + w * kMaxFilter);
   const int n = P.n;
-  const int m = n >> (level - 1), h = m >> 1;
-  const int to = dwt_ana_tile<R>(h, P.ana_wide != 0), tps = h / to;
-  const int lto = lg2(to);                         // to and tps are powers of two
-  const int o1 = (tile >> lg2(tps)) * to, o2 = (tile & (tps - 1)) * to;
-  const int in = 2 * to + F - 2;
-  const float rin = 1.0f / (float)in;
+  const AnaTile g = ana_tile<R>(P, level, tile);
+  const int h = g.h, to = g.to, lto = g.lto, o1 = g.o1, o2 = g.o2;
+  const int in = 2 * to + F - 2;                   // input rows and columns this filter reads
   const size_t base = (size_t)(P.has_dirac + w) * n * n;
   const bool last = (level == P.levels);
   constexpr int NPF = (TOM * 2 * TOM + 255) / 256;
-  const V4<R>* __restrict__ src = (level == 1)
-      ? (const V4<R>*)P.img[src_slot]
-      : (const V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level - 1];
-  for (int q = threadIdx.x; q < in * in; q += blockDim.x) {
-    const int a = small_div(q, rin), b = q - a * in;
-    sm.in[q] = src[(size_t)((2 * o1 + a) & (m - 1)) * m + ((2 * o2 + b) & (m - 1))];
+  if (ins == 0) {
+    const V4<R>* __restrict__ src = (level == 1)
+        ? (const V4<R>*)P.img[src_slot]
+        : (const V4<R>*)P.ll + (size_t)w * P.ll_stride + P.ll_off[level - 1];
+    ana_stage<R>(sm, src, g, in);
+    ins = in;
+    __syncthreads();
   }
-  __syncthreads();
   // rows: along the column index, into registers, then over the staged input
-  constexpr int NQ = (AnaSmem<R, TOM>::IN * TOM + 255) / 256;
+  constexpr int NQ = (AnaSmem<R, TOM, SEP>::IN * TOM + 255) / 256;
   V4<R> ra[NQ], rd[NQ];
 #pragma unroll
   for (int u = 0; u < NQ; ++u) {
@@ -182,7 +213,7 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
     if (q < in * to) {
       const int a = q >> lto, k = q & (to - 1);
       V4<R> sa = v4_zero<R>(), sd = v4_zero<R>();
-      const V4<R>* row = sm.in + a * in + 2 * k;
+      const V4<R>* row = sm.in + a * ins + 2 * k;
 #pragma unroll
       for (int j = 0; j < F; ++j) { const V4<R> x = row[j]; v4_fma(sa, t.h[j], x); v4_fma(sd, t.g[j], x); }
       ra[u] = sa;
@@ -251,17 +282,33 @@ __device__ __forceinline__ void analysis_body(const ProbDesc& P, AnaSmem<R, TOM>
   }
 }
 
-template <typename R, int MODE, int TOM>
+// items: {prob, basis, tile, partial index}; with SEP also {prob, kAllBases, tile, -} at level 1:
+// every basis over the tile, the image region staged once with the halo of the longest filter
+// (the bases of a level-1 tile all read the same image region; deeper levels read each basis's
+// own low-low band).
+template <typename R, int MODE, int TOM, bool SEP>
 __global__ void __launch_bounds__(256)
 analysis_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int level, int src_slot, int out_coef) {
-  __shared__ AnaSmem<R, TOM> sm;
+  __shared__ AnaSmem<R, TOM, SEP> sm;
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
   if (halted(P)) return;                 // stopped by an adaptive run
-  const int w = it.y;
   KSum k1, k2;
-#define PSARA_ANA(FF) analysis_body<R, MODE, FF, TOM>(P, sm, w, level, it.z, src_slot, out_coef, k1, k2)
+  if (SEP && it.y == kAllBases) {
+    const AnaTile g = ana_tile<R>(P, 1, it.z);
+    const int ins = 2 * g.to + kMaxFilter - 2;
+    ana_stage<R>(sm, (const V4<R>*)P.img[src_slot], g, ins);
+    __syncthreads();
+    for (int w = 0; w < P.nwav; ++w) {
+#define PSARA_ANA(FF) analysis_body<R, MODE, FF, TOM, SEP>(P, sm, w, 1, it.z, src_slot, out_coef, k1, k2, ins)
+      PSARA_FILTER_SWITCH(P.wav_len[w], PSARA_ANA)
+#undef PSARA_ANA
+    }
+    return;
+  }
+  const int w = it.y;
+#define PSARA_ANA(FF) analysis_body<R, MODE, FF, TOM, SEP>(P, sm, w, level, it.z, src_slot, out_coef, k1, k2, 0)
   PSARA_FILTER_SWITCH(P.wav_len[w], PSARA_ANA)
 #undef PSARA_ANA
   if (MODE == AM_OBJECTIVE || MODE == AM_MOMENTS || MODE == AM_MAXABS)
@@ -644,9 +691,18 @@ template <typename R, int TOM>
 void launch_analysis_t(int mode, int level, const LaunchArgs& a, int src_slot, int out_coef) {
   const dim3 g(a.nitems), b(256);
 #define PSARA_ANAL(M) \
-  hipLaunchKernelGGL((analysis_kernel<R, M, TOM>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef)
+  hipLaunchKernelGGL((analysis_kernel<R, M, TOM, false>), g, b, 0, a.stream, a.descs, a.items, level, src_slot, out_coef)
+  // (only the iterations' dual lists hold all-bases items, so only AM_DUAL needs the SEP kernel)
+  const bool all_bases = (a.ana_wide & kAnaAllBases) != 0;
   switch (mode) {
-    case AM_DUAL: PSARA_ANAL(AM_DUAL); break;
+    case AM_DUAL:
+      if (all_bases) {
+        hipLaunchKernelGGL((analysis_kernel<R, AM_DUAL, TOM, true>), g, b, 0, a.stream, a.descs, a.items, level, src_slot,
+                           out_coef);
+      } else {
+        PSARA_ANAL(AM_DUAL);
+      }
+      break;
     case AM_STORE: PSARA_ANAL(AM_STORE); break;
     case AM_REWEIGHT: PSARA_ANAL(AM_REWEIGHT); break;
     case AM_OBJECTIVE: PSARA_ANAL(AM_OBJECTIVE); break;
@@ -661,7 +717,7 @@ void launch_analysis(int mode, int level, const LaunchArgs& a, int src_slot, int
   if (a.nitems <= 0) return;
   // the largest tile side among the launch's problems (an unknown largest side takes the widest)
   constexpr int kWide = dwt_ana_tile<R>(1 << 30);
-  const int tom = a.max_n > 0 ? dwt_ana_tile<R>(a.max_n >> level, a.ana_wide != 0) : kWide;
+  const int tom = a.max_n > 0 ? dwt_ana_tile<R>(a.max_n >> level, (a.ana_wide & kAnaWide) != 0) : kWide;
   if constexpr (kWide > 8) {
     if (tom > 8) { launch_analysis_t<R, kWide>(mode, level, a, src_slot, out_coef); return; }
   }

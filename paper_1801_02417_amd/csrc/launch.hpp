@@ -14,7 +14,7 @@ struct LaunchArgs {
   int nitems;
   hipStream_t stream;
   int max_n = 0;           // largest image side among the launch's problems (0: not known)
-  int ana_wide = 1;        // whether any of them takes 16-wide analysis tiles
+  int ana_wide = 1;        // the analysis tilings among them: kAnaWide | kAnaAllBases bits
   int grid_ce = kChunkEntries;   // largest gridding chunk among them (entries staged per workgroup)
 };
 

@@ -151,9 +151,13 @@ Tuning search(const Tuning& start, int K, bool fp32, M&& measure, double* t_star
     if (v != best.grid_chunk) { Tuning c = best; c.grid_chunk = v; consider(c); }
   for (int v : {256, 128, 512})
     if (v != best.degrid_item) { Tuning c = best; c.degrid_item = v; consider(c); }
-  if (fp32)
-    for (int v : {1, 0})
-      if (v != best.ana_wide) { Tuning c = best; c.ana_wide = v; consider(c); }
+  // (FP64 analysis tiles are 8 wide either way, so there only the all-bases bit is a candidate)
+  for (int v : {1, 0, 3, 2})
+    if (v != best.ana_wide && (fp32 || v == (best.ana_wide ^ psara::kAnaAllBases))) {
+      Tuning c = best;
+      c.ana_wide = v;
+      consider(c);
+    }
   for (int v : {0, 1024, 2048})
     if (v != best.fft_cells && (v == 0 || v > std::max(512, K))) { Tuning c = best; c.fft_cells = v; consider(c); }
   measure(best);        // leaves the choice applied

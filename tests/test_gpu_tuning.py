@@ -22,6 +22,8 @@ TUNINGS = [
     {"degrid_item": 1024},
     {"degrid_item": 128, "fft_cells": 2048},
     {"fft_cells": 1024, "analysis_wide": 0},
+    {"analysis_wide": 2},
+    {"analysis_wide": 3, "fft_cells": 1024},
 ]
 
 
@@ -61,6 +63,52 @@ def test_iterations_under_tuning(tuning, prec, tol):
         s.close()
 
 
+@pytest.mark.parametrize("prec,n,per_basis", [("fp64", 64, 0), ("fp32", 64, 0), ("fp32", 256, 1)])
+def test_all_bases_analysis_bitwise_equals_per_basis(prec, n, per_basis):
+    """The all-bases bit (analysis_wide 2, 3) runs every basis of a level-1 tile in one workgroup
+    over one staged image region; the tiles and every coefficient's arithmetic are those of the
+    per-basis items of the same width (0: 8-wide; 1: 16-wide, which FP32 takes for the level-1
+    bands of a 256-pixel image), so the iterations end bitwise equal."""
+    out = {}
+    for aw in (per_basis, per_basis | 2):
+        wl, b, s, gW = _dense(prec, n=n)
+        try:
+            s.set_tuning({"analysis_wide": aw})
+            rng = np.random.default_rng(8)
+            st = _random_state(rng, wl.n * wl.n, b.sara.J, wl.M, gW)
+            s.set_state(st.S, st.Z, st.A, st.B, st.C, st.D)
+            s.solve(P.PSARA_CONSTRAINED, 6, report=False)
+            out[aw] = s.state()
+        finally:
+            s.close()
+    a, c = out[per_basis], out[per_basis | 2]
+    for k in a:
+        assert np.array_equal(a[k], c[k]), k
+    say(f"[tuning] analysis_wide {per_basis | 2} vs {per_basis} ({prec}, n={n}): bitwise equal after 6 iterations")
+
+
+def test_batch_all_bases_analysis_equals_alone():
+    stages = [12, 10, 10]
+    shapes = {"analysis_wide": 2}
+    members = [_batch_member(i, "fp32") for i in range(4)]
+    try:
+        for s in members:
+            s.set_tuning(shapes)
+        P.batch_reweighted_solve(members, P.PSARA_CONSTRAINED, stages)
+        batched = [s.image() for s in members]
+    finally:
+        for s in members:
+            s.close()
+    for i, img in enumerate(batched):
+        s = _batch_member(i, "fp32")
+        try:
+            s.set_tuning(shapes)
+            s.reweighted_solve(P.PSARA_CONSTRAINED, stages)
+            assert np.array_equal(s.image(), img), i
+        finally:
+            s.close()
+
+
 def test_set_tuning_keeps_state_and_checks_ranges():
     wl, b, s, gW = _dense("fp32")
     try:
@@ -70,7 +118,7 @@ def test_set_tuning_keeps_state_and_checks_ranges():
         after = s.state()
         for k in before:
             assert np.array_equal(before[k], after[k]), k
-        for bad in ({"grid_chunk": 300}, {"degrid_item": 32}, {"degrid_item": 96}, {"analysis_wide": 2},
+        for bad in ({"grid_chunk": 300}, {"degrid_item": 32}, {"degrid_item": 96}, {"analysis_wide": 4},
                     {"fft_cells": 4096}, {"fft_cells": 100}):
             with pytest.raises(P.PsaraError) as e:
                 s.set_tuning(bad)

@@ -391,21 +391,27 @@ def tv_form(P, wk, iters: int) -> dict:
     return out
 
 
-def profile_run(P, wk, form: str, iters: int) -> dict:
+def profile_run(P, wk, form: str, iters: int, shapes: dict | None = None) -> dict:
     """Only the timed passes of one form, for a profiler run: each pass launched on one stream with
     the two branches serialised (psara_profile_passes / psara_batch_profile_passes, constrained
     mode, every term active), so that kernel durations do not include time shared with the other
     branch.  `batch` = the 64-solve batched form (every pass one launch over all solves),
-    `large` = the 512 x 512, 1e6-visibility solve."""
+    `large` = the 512 x 512, 1e6-visibility solve.  `shapes`: launch shapes applied to every solve
+    (the default shapes if None)."""
     if form == "large":
         wl = wk.batch_request(0, sides=(512,))
         s = ready_solver(P, wl, norm_iters=50, norm_rtol=1e-4)[0]
+        if shapes:
+            s.set_tuning(shapes)
         ms = s.profile_passes(P.PSARA_CONSTRAINED, iters)
         s.close()
         return {"profile_form": "large", "n": wl.n, "M": wl.M, "iters": 2 * iters,
                 "passes_ms": {P.PASS_NAMES[i]: round(float(ms[i]), 4) for i in range(P.N_PASSES) if ms[i] > 0}}
     wls = [wk.batch_request(i) for i in range(64)]
     solvers = [ready_solver(P, wl, norm_iters=50, norm_rtol=1e-4)[0] for wl in wls]
+    if shapes:
+        for s in solvers:
+            s.set_tuning(shapes)
     ms = P.psara_batch_profile_passes([s.ctx for s in solvers], P.PSARA_CONSTRAINED, iters)
     for s in solvers:
         s.close()
@@ -461,6 +467,8 @@ def main() -> int:
     ap.add_argument("--profile-form", choices=["batch", "large"],
                     help="only run the iterations of that form (for rocprofv3), then exit")
     ap.add_argument("--profile-form-iters", type=int, default=40)
+    ap.add_argument("--profile-shapes", type=json.loads, default=None,
+                    help='launch shapes for --profile-form, as JSON (e.g. {"analysis_wide": 3})')
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 10 times (to scale HBM counters)")
     ap.add_argument("--served-only", action="store_true",
@@ -496,7 +504,7 @@ def main() -> int:
         print(f"bench.py needs a GPU and the built library: {e}", file=sys.stderr)
         return 2
     if args.profile_form:
-        print(json.dumps(profile_run(P, wk, args.profile_form, args.profile_form_iters)), flush=True)
+        print(json.dumps(profile_run(P, wk, args.profile_form, args.profile_form_iters, args.profile_shapes)), flush=True)
         return 0
     if args.served_only:
         print(json.dumps(served_form(P, wk, args.serve_requests, 20.0, [100, 100, 100], args.serve_budget_gb)),

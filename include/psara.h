@@ -276,8 +276,8 @@ typedef struct {
     int analysis_wide;   /* bit 0: 16-wide output tiles for the analysis bands of side >= 128 of
                             FP32 solves (else 8-wide: more workgroups); bit 1: each level-1
                             workgroup of the iterations filters one staged image region with every
-                            wavelet basis (the image is read once, not once per basis); 0 .. 3,
-                            default 1 */
+                            wavelet basis (the region is staged once, not once per basis);
+                            0 .. 3, default 1 */
     int fft_cells;       /* grid cells per FFT workgroup: 0 for max(512, 2n) (default), or 512, 1024,
                             2048 with at least 2n (several grid lines per workgroup) */
 } psara_tuning;

@@ -204,6 +204,20 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
     }
     __syncthreads();
   }
+  // P9 + P1 + P4: the primal step's inputs of this thread's pixels (its cells q and q + nthr in
+  // the crop) are requested now, so their loads overlap the loads and the inverse FFT below
+  // (not with 1024 threads, whose 128 registers would spill them)
+  constexpr bool kPrefetch = PASS == 4 && PM >= 0 && CELLS <= 1024;
+  PrimalIn<R> pin[kPrefetch ? 2 : 1];
+  if constexpr (kPrefetch) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = threadIdx.x + u * nthr;
+      const int l = q >> lgK, k = q & (K - 1), r = line0 + l;
+      const int col = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
+      if (r < n && col >= 0) pin[u] = primal_load<R, (PM < 0 ? 0 : PM)>(P, r * n + col);
+    }
+  }
   // ---- load ----
   for (int q = threadIdx.x; q < lines * K; q += nthr) {
     Cell<R> c = zero_cell<R>();
@@ -261,11 +275,14 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
   // lines * K == CELLS (K divides CELLS), so every thread owns one channel of 8 cells
   fft_lines<R, CELLS>(lds, K, PASS >= 2, (const cplx<R>*)P.twiddle);
 
-  if (PASS == 4) {
+  if constexpr (PASS == 4) {
     // crop, Z^dagger and Re give Re phi^dagger B at the row's pixels; the primal step takes it
     // and its X, deapodised and zero-padded, replaces the row in place (a pixel's crop position
     // and its zero-padding position are the same cell)
-    for (int q = threadIdx.x; q < lines * K; q += nthr) {
+    static_assert(CELLS == 2 * (CELLS / 2), "two cells per thread");
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = threadIdx.x + u * nthr;
       const int l = q >> lgK, k = q & (K - 1), r = line0 + l;
       const int col = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
       Cell<R> c = zero_cell<R>();
@@ -277,7 +294,9 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
         V4<R> g;
         g.x = mul_rn(v.s[0].re, sc); g.y = mul_rn(v.s[1].re, sc);
         g.z = mul_rn(v.s[2].re, sc); g.w = mul_rn(v.s[3].re, sc);
-        const V4<R> x = primal_pixel_g<R, (PM < 0 ? 0 : PM)>(P, r * n + col, g);
+        constexpr int PMM = PM < 0 ? 0 : PM;
+        const V4<R> x = kPrefetch ? primal_pixel_in<R, PMM>(P, r * n + col, g, pin[kPrefetch ? u : 0])
+                                  : primal_pixel_g<R, PMM>(P, r * n + col, g);
         c.s[0].re = x.x * sc; c.s[1].re = x.y * sc; c.s[2].re = x.z * sc; c.s[3].re = x.w * sc;
       }
       lds[q] = c;

@@ -32,31 +32,59 @@ __device__ inline void proj_E2(R r0, R r1, R r2, R d, R& p0, R& p1, R& p2, R& pd
   }
 }
 
-// Updates every per-pixel variable of pixel p in place and returns X (S_new in the TV modes);
-// g is Re phi^dagger B at p (the data term's gradient in the TV modes).
+// What the primal step of pixel p reads besides the data term's gradient, requested by
+// primal_load (so a caller can issue the loads early and use them later).
+template <typename R>
+struct PrimalIn {
+  V4<R> s, pa, pb, ad, gw, c;
+  V2<R> z, d;
+};
+
 template <typename R, int MODE>
-__device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
+__device__ inline PrimalIn<R> primal_load(const ProbDesc& P, int p) {
+  PrimalIn<R> in{};
+  in.s = ((const V4<R>*)P.img[IMG_S])[p];
+  if (MODE != PM_INIT) {
+    in.pa = ((const V4<R>*)P.img[IMG_PSIA])[p];
+    if (!pm_tv(MODE)) in.pb = ((const V4<R>*)P.img[IMG_PSIA2])[p];
+    if (P.has_dirac) {
+      in.ad = ((const V4<R>*)P.coef[COEF_A])[p];
+      in.gw = ((const V4<R>*)P.coef[COEF_GW])[p];
+    }
+  }
+  if (pm_constrained(MODE)) {
+    in.c = ((const V4<R>*)P.img[IMG_C])[p];
+    in.z = ((const V2<R>*)P.img[IMG_Z])[p];
+    in.d = ((const V2<R>*)P.img[IMG_D])[p];
+  }
+  return in;
+}
+
+// Updates every per-pixel variable of pixel p in place from its inputs `in` and returns X
+// (S_new in the TV modes); g is Re phi^dagger B at p (the data term's gradient in the TV modes).
+template <typename R, int MODE>
+__device__ inline V4<R> primal_pixel_in(const ProbDesc& P, int p, V4<R> g, const PrimalIn<R>& in) {
   const R tau = R(P.tau), nm = R(P.norm);
   V4<R>* S = (V4<R>*)P.img[IMG_S];
   V4<R>* X = (V4<R>*)P.img[IMG_X];
-  const V4<R> s = S[p];
+  const V4<R> s = in.s;
   V4<R> ad;
   const bool dirac = (MODE != PM_INIT) && P.has_dirac;
   if (MODE != PM_INIT) {
-    const V4<R> pa = ((const V4<R>*)P.img[IMG_PSIA])[p];
+    const V4<R> pa = in.pa;
     g.x += pa.x; g.y += pa.y; g.z += pa.z; g.w += pa.w;
     if (!pm_tv(MODE)) {
-      const V4<R> pb = ((const V4<R>*)P.img[IMG_PSIA2])[p];
+      const V4<R> pb = in.pb;
       g.x += pb.x; g.y += pb.y; g.z += pb.z; g.w += pb.w;
     }
     if (dirac) {
-      ad = ((const V4<R>*)P.coef[COEF_A])[p];
+      ad = in.ad;
       g.x += nm * ad.x; g.y += nm * ad.y; g.z += nm * ad.z; g.w += nm * ad.w;
     }
   }
   V4<R> c;
   if (pm_constrained(MODE)) {
-    c = ((const V4<R>*)P.img[IMG_C])[p];
+    c = in.c;
     g.x += c.x; g.y += c.y; g.z += c.z; g.w += c.w;
   }
   V4<R> sn;
@@ -67,7 +95,7 @@ __device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
   S[p] = sn;
   X[p] = x;
   if (dirac) {
-    const V4<R> gw = ((const V4<R>*)P.coef[COEF_GW])[p];
+    const V4<R> gw = in.gw;
     const R r1 = R(P.rho1) * nm;
     ad.x = fmin(fmax(ad.x + r1 * x.x, -gw.x), gw.x);
     ad.y = fmin(fmax(ad.y + r1 * x.y, -gw.y), gw.y);
@@ -78,7 +106,7 @@ __device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
   if (pm_constrained(MODE)) {
     V2<R>* Z = (V2<R>*)P.img[IMG_Z];
     V2<R>* D = (V2<R>*)P.img[IMG_D];
-    const V2<R> z = Z[p], d = D[p];
+    const V2<R> z = in.z, d = in.d;
     // Z = P_V(Z - tau D)
     V2<R> zt, zn;
     zt.x = z.x - tau * d.x; zt.y = z.y - tau * d.y;
@@ -105,6 +133,11 @@ __device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
     D[p] = dn;
   }
   return pm_tv(MODE) ? sn : x;    // Algorithm 3 transforms S_new for its next gradient
+}
+
+template <typename R, int MODE>
+__device__ inline V4<R> primal_pixel_g(const ProbDesc& P, int p, V4<R> g) {
+  return primal_pixel_in<R, MODE>(P, p, g, primal_load<R, MODE>(P, p));
 }
 
 // The same with Re phi^dagger B read from its image.

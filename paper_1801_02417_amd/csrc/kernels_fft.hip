@@ -219,6 +219,65 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
     }
   }
   // ---- load ----
+  // (the FP64 kernel with 1024 threads, 128 registers, keeps the gather one pair at a time: the
+  // eight pairs' cells in flight would spill)
+  constexpr bool kRounds = PASS == 2 && !(sizeof(R) == 8 && CELLS > 1024);
+  if constexpr (kRounds) {
+    // the gridded values of the thread's cells q and q + nthr: the partial slots of each cell's
+    // tile and of the tiles whose halos reach it (the previous tile in k1, in k2, and in both),
+    // times the factor the gridding pass left out.  Each (cell, tile) pair's first slot cell and
+    // slot count come from the staged tables; the slots are then added round by round (slot
+    // index sl of every pair, pairs in a fixed order), and a round loads all eight pairs' cells
+    // before adding any (a pair with fewer slots, or none, loads a cell of an existing slot that
+    // it does not add), so those loads are in flight together
+    const int ntg = P.ntile_side_g, RG = kGridTile + P.T - 1;
+    const Cell<R>* __restrict__ gp = (const Cell<R>*)P.gpart;
+    const Cell<R>* src[2][4];
+    int cnt[2][4];
+    int rounds = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = threadIdx.x + u * nthr;
+      const int l = q >> lgK, k = q & (K - 1), k2 = line0 + l;
+      const int t1 = k / kGridTile, t2 = k2 / kGridTile, a1 = k - t1 * kGridTile, a2 = k2 - t2 * kGridTile;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int d1 = d & 1, d2 = d >> 1;
+        const int o1 = a1 + d1 * kGridTile, o2 = a2 + d2 * kGridTile;
+        src[u][d] = gp;
+        cnt[u][d] = 0;
+        if (k2 >= K || o1 >= RG || o2 >= RG) continue;
+        const int ti = (t2 - d2 - trow0) * ntg + ((t1 - d1 + ntg) & (ntg - 1));
+        if (!in_box(tbx[ti], o1, o2)) continue;          // no slot of the tile reaches it
+        const int2 ts = tsl[ti];
+        src[u][d] = gp + (size_t)ts.x * RG * RG + o2 * RG + o1;
+        cnt[u][d] = ts.y;
+        rounds = max(rounds, ts.y);
+      }
+    }
+    Cell<R> c[2] = {zero_cell<R>(), zero_cell<R>()};
+    for (int sl = 0; sl < rounds; ++sl) {
+      Cell<R> o[2][4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) o[u][d] = src[u][d][sl < cnt[u][d] ? (size_t)sl * RG * RG : 0];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          if (sl < cnt[u][d]) {
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) c[u].s[ch] = cadd(c[u].s[ch], o[u][d].s[ch]);
+          }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) { c[u].s[ch].re *= gfac; c[u].s[ch].im *= gfac; }
+      lds[threadIdx.x + u * nthr] = c[u];
+    }
+  }
   for (int q = threadIdx.x; q < lines * K; q += nthr) {
     Cell<R> c = zero_cell<R>();
     if (PASS == 0) {
@@ -238,29 +297,36 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       if (k2 < K && r >= 0) c = half[(size_t)k2 * n + r];
       lds[q] = c;
     } else if (PASS == 2) {
-      // the gridded values: the partial slots of the cell's tile and of the tiles whose halos
-      // reach it (the previous tile in k1, in k2, and in both), in that order, times the
-      // factor the gridding pass left out
+      if (kRounds) continue;                           // gathered above
+      // the gathers one (cell, tile) pair at a time, in the order of the rounds above
       const int l = q >> lgK, k = q & (K - 1), k2 = line0 + l;
       if (k2 < K) {
         const int ntg = P.ntile_side_g, RG = kGridTile + P.T - 1;
         const int t1 = k / kGridTile, t2 = k2 / kGridTile, a1 = k - t1 * kGridTile, a2 = k2 - t2 * kGridTile;
+        const Cell<R>* src[4];
+        int cnt[4], rounds = 0;
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
           const int d1 = d & 1, d2 = d >> 1;
           const int o1 = a1 + d1 * kGridTile, o2 = a2 + d2 * kGridTile;
+          src[d] = (const Cell<R>*)P.gpart;
+          cnt[d] = 0;
           if (o1 >= RG || o2 >= RG) continue;
-          const int s1 = (t1 - d1 + ntg) & (ntg - 1);
-          const int2 ts = tsl[(t2 - d2 - trow0) * ntg + s1];
-          if (!in_box(tbx[(t2 - d2 - trow0) * ntg + s1], o1, o2)) continue;   // no slot of the tile reaches it
-          const Cell<R>* part = (const Cell<R>*)P.gpart + (size_t)ts.x * RG * RG + o2 * RG + o1;
-#pragma unroll 4
-          for (int sl = 0; sl < ts.y; ++sl) {
-            const Cell<R> o = part[(size_t)sl * RG * RG];
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) c.s[ch] = cadd(c.s[ch], o.s[ch]);
-          }
+          const int ti = (t2 - d2 - trow0) * ntg + ((t1 - d1 + ntg) & (ntg - 1));
+          if (!in_box(tbx[ti], o1, o2)) continue;
+          const int2 ts = tsl[ti];
+          src[d] = (const Cell<R>*)P.gpart + (size_t)ts.x * RG * RG + o2 * RG + o1;
+          cnt[d] = ts.y;
+          rounds = max(rounds, ts.y);
         }
+        for (int sl = 0; sl < rounds; ++sl)
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            if (sl < cnt[d]) {
+              const Cell<R> o = src[d][(size_t)sl * RG * RG];
+#pragma unroll
+              for (int ch = 0; ch < 4; ++ch) c.s[ch] = cadd(c.s[ch], o.s[ch]);
+            }
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) { c.s[ch].re *= gfac; c.s[ch].im *= gfac; }
       }

@@ -150,6 +150,24 @@ __host__ __device__ inline int lg2(int p) { return __builtin_ctz((unsigned)p); }
 // for every such q and d; rcp = 1 / d is computed once.
 __device__ inline int small_div(int q, float rcp) { return (int)(((float)q + 0.5f) * rcp); }
 
+// dst[q] = load(q) for q < n <= U * blockDim.x, each thread taking q = threadIdx.x + u * blockDim.x:
+// every load of the thread is issued before its first LDS store, so the loads are in flight
+// together (a loop that stores each element as it arrives waits for one load at a time).
+template <int U, class T, class Load>
+__device__ inline void stage_lds(T* dst, int n, Load&& load) {
+  T v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = threadIdx.x + u * blockDim.x;
+    if (q < n) v[u] = load(q);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = threadIdx.x + u * blockDim.x;
+    if (q < n) dst[q] = v[u];
+  }
+}
+
 // A gridding run in one word: the offset of its first entry in its chunk (< 1024), its length
 // (1 .. 32) and its window start relative to its tile (o1, o2 < 16).
 __host__ __device__ constexpr int pack_run(int off, int len, int o1, int o2) {

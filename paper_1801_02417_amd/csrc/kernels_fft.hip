@@ -199,8 +199,11 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
     const int ntr = min(K - 1, line0 + lines - 1) / kGridTile - trow0 + 1;
     for (int i = threadIdx.x; i < ntr * ntg; i += nthr) {
       const int rr = i >> lg2(ntg), u1 = i & (ntg - 1);
-      tsl[i] = P.tile_slots[u1 * ntg + ((trow0 + rr + ntg) & (ntg - 1))];
-      tbx[i] = P.tile_box[u1 * ntg + ((trow0 + rr + ntg) & (ntg - 1))];
+      const int t = u1 * ntg + ((trow0 + rr + ntg) & (ntg - 1));
+      const int2 sl = P.tile_slots[t];
+      const int bx = P.tile_box[t];
+      tsl[i] = sl;
+      tbx[i] = bx;
     }
     __syncthreads();
   }
@@ -278,7 +281,32 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       lds[threadIdx.x + u * nthr] = c[u];
     }
   }
+  if constexpr (PASS == 1 || PASS >= 3) {
+    // both of the thread's cells are loaded before either is stored, so the two loads are in
+    // flight together (P5 reads half[k2][r] into line order; P9 and the fused row pass read it
+    // transposed into their rows)
+    Cell<R> cv[2];
+    int dst[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = threadIdx.x + u * nthr;
+      cv[u] = zero_cell<R>();
+      if constexpr (PASS == 1) {
+        const int l = q >> lgK, k = q & (K - 1), k2 = line0 + l;
+        const int r = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
+        if (k2 < K && r >= 0) cv[u] = half[(size_t)k2 * n + r];
+        dst[u] = q;
+      } else {
+        const int k2 = q >> lgL, l = q & (lines - 1), r = line0 + l;
+        if (r < n) cv[u] = half[(size_t)k2 * n + r];
+        dst[u] = l * K + k2;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) lds[dst[u]] = cv[u];
+  }
   for (int q = threadIdx.x; q < lines * K; q += nthr) {
+    if (PASS == 1 || PASS >= 3) break;                 // loaded above
     Cell<R> c = zero_cell<R>();
     if (PASS == 0) {
       const int l = q >> lgK, k = q & (K - 1), r = line0 + l;
@@ -290,11 +318,6 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
         const R sc = s[r] * s[col];
         c.s[0].re = v.x * sc; c.s[1].re = v.y * sc; c.s[2].re = v.z * sc; c.s[3].re = v.w * sc;
       }
-      lds[q] = c;
-    } else if (PASS == 1) {
-      const int l = q >> lgK, k = q & (K - 1), k2 = line0 + l;
-      const int r = (k < h2) ? k + h2 : ((k >= K - h2) ? k - (K - h2) : -1);
-      if (k2 < K && r >= 0) c = half[(size_t)k2 * n + r];
       lds[q] = c;
     } else if (PASS == 2) {
       if (kRounds) continue;                           // gathered above
@@ -331,10 +354,6 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
         for (int ch = 0; ch < 4; ++ch) { c.s[ch].re *= gfac; c.s[ch].im *= gfac; }
       }
       lds[q] = c;
-    } else {
-      const int k2 = q >> lgL, l = q & (lines - 1), r = line0 + l;
-      if (r < n) c = half[(size_t)k2 * n + r];
-      lds[l * K + k2] = c;
     }
   }
   __syncthreads();

@@ -184,6 +184,10 @@ __device__ __forceinline__ void degrid_one(const ProbDesc& P, const Cell<R>* win
   else out[m] = degrid_row_in<R, MODE>(P, m, v, in, cb, acc);
 }
 
+// window elements a de-grid thread stages: the largest window ((ts + T - 1)^2 cells, ts <= 32)
+// over the 256 threads of a workgroup
+template <int T> constexpr int kDegridWin = ((kMaxDegridTile + T - 1) * (kMaxDegridTile + T - 1) + 255) / 256;
+
 // P6: de-grid + L mixing (+ dual B).  items: {prob, tile | rows << 16, first sorted vis, partial
 // index}; an item holds P.dg_item rows of the tile (fewer at its end), a thread takes every
 // blockDim.x-th
@@ -227,10 +231,11 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
       band[1] = ((last < (int)blockDim.x ? pk0 : P.vis_k0[vend - 1]) >> 16) - b1;
     __syncthreads();
     const int lo = band[0], Wb = band[1] - lo + T;
-    for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {
-      const int a = q / Wb, b = q - a * Wb;                    // a: k2 offset, b: k1 offset - lo
-      win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + lo + b) & (K - 1))];
-    }
+    const float rwb = 1.0f / (float)Wb;
+    stage_lds<kDegridWin<T>>(win, W * Wb, [&](int q) {
+      const int a = small_div(q, rwb), b = q - a * Wb;          // a: k2 offset, b: k1 offset - lo
+      return grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + lo + b) & (K - 1))];
+    });
     __syncthreads();
     // the first row from the values loaded above, later rows (items longer than the
     // workgroup) loaded as they come
@@ -243,10 +248,11 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
     if (halted(P)) return;                 // stopped by an adaptive run
     const int lo = (P.vis_k0[it.z] >> 16) - b1, hi = (P.vis_k0[vend - 1] >> 16) - b1;
     const int Wb = hi - lo + T;
-    for (int q = threadIdx.x; q < W * Wb; q += blockDim.x) {
-      const int a = q / Wb, b = q - a * Wb;
-      win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + lo + b) & (K - 1))];
-    }
+    const float rwb = 1.0f / (float)Wb;
+    stage_lds<kDegridWin<T>>(win, W * Wb, [&](int q) {
+      const int a = small_div(q, rwb), b = q - a * Wb;
+      return grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + lo + b) & (K - 1))];
+    });
     __syncthreads();
     for (int m = mf; m < vend; m += blockDim.x) {
       const int pk = P.vis_k0[m];
@@ -744,10 +750,10 @@ degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ 
   }
   Cell<R>* win = (Cell<R>*)acc;
   const Cell<R>* __restrict__ grid = (const Cell<R>*)P.grid;
-  for (int q = threadIdx.x; q < RG * RG; q += blockDim.x) {
+  stage_lds<(RG * RG + kGridThreads - 1) / kGridThreads>(win, RG * RG, [&](int q) {
     const int a = q / RG, b = q - a * RG;                     // a: k2 offset, b: k1 offset
-    win[q] = grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + b) & (K - 1))];
-  }
+    return grid[(size_t)((b2 + a) & (K - 1)) * K + ((b1 + b) & (K - 1))];
+  });
   __syncthreads();
 
   Cell<R>* __restrict__ out = (Cell<R>*)P.vis[out_slot];

@@ -187,6 +187,13 @@ void order_grid_items(It begin, It end, GeoOf geo_of) {
   };
   std::stable_sort(begin, end, [&](const int4& a, const int4& b) { return cost(a) > cost(b); });
 }
+// Orders de-grid items by decreasing row count, so the fullest start first and the tail of the
+// launch is made of the short ones (an item keeps its partial index, so the norm's reduction
+// order does not change).
+template <typename It>
+void order_degrid_items(It begin, It end) {
+  std::stable_sort(begin, end, [](const int4& a, const int4& b) { return (a.y >> 16) > (b.y >> 16); });
+}
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int dg_item, int* n_p6) {
   const int n = g.n, K = g.K, N = n * n;
   const int lines = cells / K, rlines = rcells / K;
@@ -194,6 +201,7 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
   for (int l = 0; l < n; l += rlines) S.rows.push_back(make_int4(prob, l, 0, 0));
   for (int l = 0; l < K; l += lines) S.cols.push_back(make_int4(prob, l, 0, 0));
   const int ntiles = g.nts * g.nts;
+  const size_t first_p6 = S.p6.size();
   int part = 0;
   for (int t = 0; t < ntiles; ++t) {
     // (a de-grid item packs its tile and row count in one int: tiles < 2^16, rows < 2^15)
@@ -203,6 +211,7 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
       S.p6.push_back(make_int4(prob, t | (rows << 16), v, part++));
     }
   }
+  order_degrid_items(S.p6.begin() + first_p6, S.p6.end());
   // gridding: first the item that stores the pass's scalar factor, then the chunks heaviest
   // first so the tail is short, a chunk item carrying its entry range; the grid pass takes the
   // small chunks eight to an item {prob, kGridSmallItem, first of small_ids, count}, the fused
@@ -1412,6 +1421,7 @@ Batch<R>::Batch(const std::vector<Engine<R>*>& members, hipStream_t stream) : me
     }
   }
   // the gridding launches take the heaviest chunks of all members first
+  order_degrid_items(S.p6.begin(), S.p6.end());
   order_grid_items(S.p7.begin(), S.p7.end(), [this](int prob) { return &members_[prob]->geometry(); });
   order_grid_items(S.p7f.begin(), S.p7f.end(), [this](int prob) { return &members_[prob]->geometry(); });
   auto up = [&](DevItems& d, const std::vector<int4>& v) {

@@ -208,7 +208,12 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
     if (ntiles > 0xffff || dg_item > 0x7fff) throw Error(PSARA_EINVAL, "de-grid tiling out of range");
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += dg_item) {
       const int rows = std::min(dg_item, g.own_ptr[t + 1] - v);
-      S.p6.push_back(make_int4(prob, t | (rows << 16), v, part++));
+      // the k1 band of the tile window the item's rows use: their first and last window
+      // starts, relative to the tile (the rows are in k1 order)
+      const int b1 = (t / g.nts) * g.ts;
+      const int lo = (g.k0[v] >> 16) - b1, hi = (g.k0[v + rows - 1] >> 16) - b1;
+      if (part >= (1 << 20) || g.ts > 32) throw Error(PSARA_EINVAL, "de-grid item fields out of range");
+      S.p6.push_back(make_int4(prob, t | (rows << 16), v, part++ | (lo << 20) | (hi << 25)));
     }
   }
   order_degrid_items(S.p6.begin() + first_p6, S.p6.end());

@@ -189,15 +189,16 @@ __device__ __forceinline__ void degrid_one(const ProbDesc& P, const Cell<R>* win
 template <int T> constexpr int kDegridWin = ((kMaxDegridTile + T - 1) * (kMaxDegridTile + T - 1) + 255) / 256;
 
 // P6: de-grid + L mixing (+ dual B).  items: {prob, tile | rows << 16, first sorted vis, partial
-// index}; an item holds P.dg_item rows of the tile (fewer at its end), a thread takes every
-// blockDim.x-th
+// index | lo << 20 | hi << 25}; an item holds P.dg_item rows of the tile (fewer at its end), a
+// thread takes every blockDim.x-th; lo and hi are the first and last window start k1 of its
+// rows relative to the tile (the rows are in k1 order), so the k1 band [lo, hi + T - 1] of the
+// tile window is all the item stages
 template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(256)
 degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cell<R>* win = (Cell<R>*)smem_raw;
   __shared__ double red[8];
-  __shared__ int band[2];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
   const int K = P.K, ts = P.ts, nts = P.ntile_side;
@@ -209,9 +210,8 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   Cell<R>* __restrict__ out = (Cell<R>*)P.vis[out_slot];
   const R cb = dual_factor<R, MODE>(P);
   const int mf = it.z + threadIdx.x;
+  const int part = it.w & 0xfffff, lo = (it.w >> 20) & 31, Wb = ((it.w >> 25) & 31) - lo + T;
   KSum acc;
-  // the item's visibilities are sorted by window start k1 within the tile, so they use only
-  // the k1 offsets [lo, hi + T - 1] of the tile window: that band, Wb wide, is staged
   if constexpr (sizeof(R) == 4) {
     // FP32: the thread's first row and what it reads are requested before the halt test and
     // the window, so those loads are in flight together; lo and hi come from the threads
@@ -225,12 +225,6 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
       in0 = row_inputs<R, MODE>(P, mf, src_slot);
     }
     if (halted(P)) return;                 // stopped by an adaptive run
-    const int last = vend - 1 - it.z;
-    if (threadIdx.x == 0) band[0] = (pk0 >> 16) - b1;
-    if (threadIdx.x == (unsigned)(last % (int)blockDim.x))
-      band[1] = ((last < (int)blockDim.x ? pk0 : P.vis_k0[vend - 1]) >> 16) - b1;
-    __syncthreads();
-    const int lo = band[0], Wb = band[1] - lo + T;
     const float rwb = 1.0f / (float)Wb;
     stage_lds<kDegridWin<T>>(win, W * Wb, [&](int q) {
       const int a = small_div(q, rwb), b = q - a * Wb;          // a: k2 offset, b: k1 offset - lo
@@ -246,8 +240,6 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   } else {
     // FP64 (the interpolation takes every register): rows are read as they are de-gridded
     if (halted(P)) return;                 // stopped by an adaptive run
-    const int lo = (P.vis_k0[it.z] >> 16) - b1, hi = (P.vis_k0[vend - 1] >> 16) - b1;
-    const int Wb = hi - lo + T;
     const float rwb = 1.0f / (float)Wb;
     stage_lds<kDegridWin<T>>(win, W * Wb, [&](int q) {
       const int a = small_div(q, rwb), b = q - a * Wb;
@@ -269,8 +261,8 @@ degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   if (MODE != DG_FORWARD) {
     const KSum tot = block_reduce(acc, red);
     if (threadIdx.x == 0) {
-      P.partials[2 * it.w] = tot.s;
-      P.partials[2 * it.w + 1] = tot.c;
+      P.partials[2 * part] = tot.s;
+      P.partials[2 * part + 1] = tot.c;
     }
   }
 }

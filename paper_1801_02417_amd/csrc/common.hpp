@@ -113,7 +113,6 @@ struct ProbDesc {
   double tvw[4];          // TV weights per Stokes map
   double l1w[4];          // l1 weights per Stokes map (l1 + TV)
   const int* own_ptr;     // ntiles+1: sorted-vis range whose window starts in each tile
-  const int* list_idx;    // per gridding tile: every vis whose window touches it
   const int* run_pack;    // gridding runs (pack_run): entry offset in the chunk, length, window start in the tile
   const int2* chunk_ent;  // list-entry range [lo, hi) of each gridding chunk
   void* gpart;            // gridding partial slots: n_slots x (kGridTile + T - 1)^2 cells, k2-major

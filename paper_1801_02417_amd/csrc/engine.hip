@@ -60,10 +60,17 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
     k2[m] = ((int)c2) & (K - 1);
     tile[m] = (k1[m] / ts) * nts + k2[m] / ts;
   }
+  // rows sorted by de-gridding tile, then by the gridding tile (kGridTile-sided, inside it) that
+  // holds their window start, then by window start: each gridding tile's rows are then one
+  // contiguous range, so the gridding reads its rows without an index list
+  const int tg0 = kGridTile, ntsg0 = K / kGridTile;
+  std::vector<int> gtile(M);
+  for (int64_t m = 0; m < M; ++m) gtile[m] = (k1[m] / tg0) * ntsg0 + k2[m] / tg0;
   std::vector<int64_t> order(M);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
     if (tile[a] != tile[b]) return tile[a] < tile[b];
+    if (gtile[a] != gtile[b]) return gtile[a] < gtile[b];
     if (k1[a] != k1[b]) return k1[a] < k1[b];
     return k2[a] < k2[b];
   });
@@ -80,16 +87,20 @@ Geometry build_geometry(int n, int64_t M, const double* uv, int alpha, int T) {
   }
   for (int t = 0; t < ntiles; ++t) g.own_ptr[t + 1] += g.own_ptr[t];
   // gridding: every visibility belongs to the kGridTile x kGridTile tile that holds its window
-  // start (a gridding tile lies inside one de-gridding tile, so its list, taken in sorted
-  // order, runs through the window starts in (k1, k2) order)
+  // start; a gridding tile lies inside one de-gridding tile, so by the sort its rows are one
+  // contiguous range, in (k1, k2) order
   const int tg = kGridTile, ntsg = g.ntsg, ntg = ntsg * ntsg;
   auto owner = [&](int64_t p) { return ((g.k0[p] >> 16) / tg) * ntsg + (g.k0[p] & 0xffff) / tg; };
-  g.list_ptr.assign(ntg + 1, 0);
-  for (int64_t p = 0; p < M; ++p) g.list_ptr[owner(p) + 1]++;
-  for (int t = 0; t < ntg; ++t) g.list_ptr[t + 1] += g.list_ptr[t];
-  g.list_idx.resize(g.list_ptr[ntg]);
-  std::vector<int> fillp(g.list_ptr.begin(), g.list_ptr.end() - 1);
-  for (int64_t p = 0; p < M; ++p) g.list_idx[fillp[owner(p)]++] = (int)p;
+  g.row_beg.assign(ntg, 0);
+  g.row_end.assign(ntg, 0);
+  std::vector<int> count(ntg, 0);
+  for (int64_t p = 0; p < M; ++p) {
+    const int t = owner(p);
+    if (count[t]++ == 0) g.row_beg[t] = (int)p;
+    g.row_end[t] = (int)p + 1;
+  }
+  for (int t = 0; t < ntg; ++t)
+    if (g.row_end[t] - g.row_beg[t] != count[t]) throw Error(PSARA_EINVAL, "internal: a gridding tile's rows are not contiguous");
   build_grid_chunks(g, kChunkEntries);
   return g;
 }
@@ -100,16 +111,16 @@ void build_grid_chunks(Geometry& g, int chunk_entries) {
   g.chunks.clear(); g.chunk_ent.clear(); g.tile_slots.clear(); g.slot_box.clear(); g.tile_box.clear(); g.small_ids.clear();
   g.n_slots = 0;
   g.chunk_entries = chunk_entries;
-  // runs: consecutive list entries of a tile with the same window start (their taps hit the
+  // runs: consecutive rows of a tile with the same window start (their taps hit the
   // same cells), split at kRunMax; chunks of whole runs with <= chunk_entries entries, runs
   // ordered longest first inside a chunk so the lanes of a wave loop for similar lengths.
   // Every chunk accumulates its tile plus the T-1 halo in its own slot; the column inverse
   // FFT sums the slots of a cell's tile and of the three tiles whose halos reach it.
   for (int t = 0; t < ntg; ++t) {
     std::vector<std::pair<int, int>> runs;
-    for (int e = g.list_ptr[t]; e < g.list_ptr[t + 1];) {
+    for (int e = g.row_beg[t]; e < g.row_end[t];) {
       int f = e + 1;
-      while (f < g.list_ptr[t + 1] && f - e < kRunMax && g.k0[g.list_idx[f]] == g.k0[g.list_idx[e]]) ++f;
+      while (f < g.row_end[t] && f - e < kRunMax && g.k0[f] == g.k0[e]) ++f;
       runs.push_back({e, f - e});
       e = f;
     }
@@ -123,7 +134,7 @@ void build_grid_chunks(Geometry& g, int chunk_entries) {
       std::stable_sort(runs.begin() + r0, runs.begin() + r,
                        [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.second > y.second; });
       const int base = (int)g.run_pack.size();
-      int lo = g.list_ptr[t + 1], hi = g.list_ptr[t];
+      int lo = g.row_end[t], hi = g.row_beg[t];
       for (size_t q = r0; q < r; ++q) {
         lo = std::min(lo, runs[q].first);
         hi = std::max(hi, runs[q].first + runs[q].second);
@@ -132,7 +143,7 @@ void build_grid_chunks(Geometry& g, int chunk_entries) {
       const int b1 = (t / g.ntsg) * kGridTile, b2 = (t % g.ntsg) * kGridTile;
       int lo1 = kGridTile, hi1 = 0, lo2 = kGridTile, hi2 = 0;
       for (size_t q = r0; q < r; ++q) {
-        const int pk = g.k0[g.list_idx[runs[q].first]];
+        const int pk = g.k0[runs[q].first];
         g.run_pack.push_back(pack_run(runs[q].first - lo, runs[q].second, (pk >> 16) - b1, (pk & 0xffff) - b2));
         lo1 = std::min(lo1, (pk >> 16) - b1);
         hi1 = std::max(hi1, (pk >> 16) - b1);
@@ -208,10 +219,14 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
     if (ntiles > 0xffff || dg_item > 0x7fff) throw Error(PSARA_EINVAL, "de-grid tiling out of range");
     for (int v = g.own_ptr[t]; v < g.own_ptr[t + 1]; v += dg_item) {
       const int rows = std::min(dg_item, g.own_ptr[t + 1] - v);
-      // the k1 band of the tile window the item's rows use: their first and last window
-      // starts, relative to the tile (the rows are in k1 order)
+      // the k1 band of the tile window the item's rows use: their smallest and largest window
+      // starts k1, relative to the tile
       const int b1 = (t / g.nts) * g.ts;
-      const int lo = (g.k0[v] >> 16) - b1, hi = (g.k0[v + rows - 1] >> 16) - b1;
+      int lo = g.ts, hi = 0;
+      for (int p = v; p < v + rows; ++p) {
+        lo = std::min(lo, (g.k0[p] >> 16) - b1);
+        hi = std::max(hi, (g.k0[p] >> 16) - b1);
+      }
       if (part >= (1 << 20) || g.ts > 32) throw Error(PSARA_EINVAL, "de-grid item fields out of range");
       S.p6.push_back(make_int4(prob, t | (rows << 16), v, part++ | (lo << 20) | (hi << 25)));
     }
@@ -320,7 +335,6 @@ Engine<R>::Engine(const Geometry& g, hipStream_t stream) : geo_(g), s0_(stream) 
   h_.vis_k0 = upload<int>(g.k0.data(), M);
   h_.vis_frac = upload_conv(g.frac.data(), 2 * M);
   h_.own_ptr = upload<int>(g.own_ptr.data(), g.own_ptr.size());
-  h_.list_idx = upload<int>(g.list_idx.data(), std::max<size_t>(1, g.list_idx.size()));
   upload_chunks();
   // tables
   std::vector<double> poly = kb_poly(g.T, g.beta, h_.deg);

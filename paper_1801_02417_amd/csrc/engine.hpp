@@ -27,13 +27,13 @@ struct Geometry {
   std::vector<int> k0;            // packed window starts (k1 << 16 | k2), sorted order
   std::vector<double> frac;       // (f1, f2) per sorted visibility
   std::vector<int> own_ptr;       // per tile: range of visibilities whose window starts there
-  std::vector<int> list_ptr, list_idx;   // per gridding tile: the visibilities whose window starts in it
-  // gridding work: runs of list entries sharing one window start (at most kRunMax long),
+  std::vector<int> row_beg, row_end;     // per gridding tile: its rows (window start in it), [beg, end)
+  // gridding work: runs of a tile's rows sharing one window start (at most kRunMax long),
   // grouped into chunks of at most kChunkEntries entries; every chunk writes its tile and
   // the tile's halo to its own partial slot, summed when the column inverse FFT loads them
   std::vector<int> run_pack;             // per run: pack_run(entry offset in its chunk, length, window start in the tile)
   std::vector<int4> chunks;              // {tile, first run, end run, partial slot}
-  std::vector<int2> chunk_ent;           // list-entry range [lo, hi) each chunk covers
+  std::vector<int2> chunk_ent;           // row range [lo, hi) each chunk covers
   std::vector<int2> tile_slots;          // per gridding tile {first partial slot, count}
   std::vector<int> slot_box;             // per slot: the region cells its chunk covers (pack_box)
   std::vector<int> tile_box;             // per gridding tile: the union of its slots' boxes

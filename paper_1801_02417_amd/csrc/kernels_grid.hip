@@ -190,9 +190,9 @@ template <int T> constexpr int kDegridWin = ((kMaxDegridTile + T - 1) * (kMaxDeg
 
 // P6: de-grid + L mixing (+ dual B).  items: {prob, tile | rows << 16, first sorted vis, partial
 // index | lo << 20 | hi << 25}; an item holds P.dg_item rows of the tile (fewer at its end), a
-// thread takes every blockDim.x-th; lo and hi are the first and last window start k1 of its
-// rows relative to the tile (the rows are in k1 order), so the k1 band [lo, hi + T - 1] of the
-// tile window is all the item stages
+// thread takes every blockDim.x-th; lo and hi are the smallest and largest window start k1 of
+// its rows relative to the tile, so the k1 band [lo, hi + T - 1] of the tile window is all the
+// item stages
 template <typename R, int MODE, int T>
 __global__ void __launch_bounds__(256)
 degrid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, int src_slot, int out_slot) {
@@ -293,7 +293,7 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 }
 
 // ---------------------------------------------------------------------------------------------
-// P7: grid (adjoint of G, after mixing by L^H).  items: {prob, chunk, first list entry, end}
+// P7: grid (adjoint of G, after mixing by L^H).  items: {prob, chunk, first row, end row}
 // for a chunk of more than kSmallChunk entries, {prob, kGridFactorItem, -, -} for the factor
 // item, {prob, kGridSmallItem, first of small_ids, count} for up to eight small chunks
 // (grid_small above: one wave each, summed in registers in a fixed order).
@@ -301,12 +301,13 @@ void launch_degrid(int mode, const LaunchArgs& a, int max_ts, int taps, int src_
 // The grid is cut into kGridTile x kGridTile tiles and every visibility belongs to the tile
 // holding its window start, so it is gridded exactly once; the workgroup accumulates the tile
 // plus its (T-1)-wide halo on the high sides, (kGridTile + T - 1)^2 cells, which every window
-// starting in the tile stays inside.  A chunk is a set of runs of one tile's list, a run being
-// visibilities with the same window start, so all their T x T taps land on the same cells.
-// The chunk's entries (offsets and L^H-mixed values) are first staged in LDS by the whole
-// workgroup.  A group of 8 lanes then takes one run: lane i owns tap row i and
+// starting in the tile stays inside.  A tile's rows are contiguous (rows are sorted by
+// de-gridding tile, then gridding tile, then window start); a chunk is a set of runs of them,
+// a run being visibilities with the same window start, so all their T x T taps land on the
+// same cells.  The chunk's entries (offsets and L^H-mixed values) are first staged in LDS by
+// the whole workgroup.  A group of 8 lanes then takes one run: lane i owns tap row i and
 // accumulates, over the run, the 8 cells of that row for the 8 real channels in registers
-// (the column weights are shared through lane shuffles), and adds the row to the tile once.
+// (the column weights are shared through DPP lane moves), and adds the row to the tile once.
 //
 // The tile accumulates in 64-bit fixed point with integer LDS atomics: integer addition is
 // associative, so the result does not depend on the order in which lanes arrive (the
@@ -429,7 +430,7 @@ __device__ inline void static_for(F&& f) {
 }
 
 // Accumulates a chunk whose rows are staged in LDS (sf: fractional offsets, su: two V4 of
-// gridded channels per entry, entry q the chunk's q-th list entry) into acc, which must be zero,
+// gridded channels per entry, entry q the chunk's q-th row) into acc, which must be zero,
 // and writes the cells of the chunk's box to its partial slot (the slot's other cells are zero
 // from the allocation on and stay so).  Called by the whole workgroup.
 template <typename R, int T, bool POLY>
@@ -553,7 +554,7 @@ __device__ inline void grid_small(const ProbDesc& P, const int4 it, int src_slot
   const int2 ent = P.chunk_ent[c];
   const int box = P.slot_box[ch.w];
   const int ne = ent.y - ent.x;
-  const int m = lane < ne ? P.list_idx[ent.x + lane] : P.list_idx[ent.x];
+  const int m = ent.x + (lane < ne ? lane : 0);             // the chunk's rows are contiguous
   R cr[DEG + 1];
   {
     const int tap = lane & 7;
@@ -654,7 +655,7 @@ grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items, 
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int q = threadIdx.x + e * blockDim.x;
-    me[e] = q < ne ? P.list_idx[ent.x + q] : 0;
+    me[e] = ent.x + (q < ne ? q : 0);                      // the chunk's rows are contiguous
   }
   const int4 ch = P.chunks[it.y];
   constexpr bool kPoly = sizeof(R) == 4;
@@ -733,7 +734,7 @@ degrid_grid_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ 
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int q = threadIdx.x + e * blockDim.x;
-    me[e] = q < ne ? P.list_idx[ent.x + q] : 0;
+    me[e] = ent.x + (q < ne ? q : 0);                      // the chunk's rows are contiguous
   }
 #pragma unroll
   for (int e = 0; e < 2; ++e) {

@@ -305,8 +305,10 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
 #pragma unroll
     for (int u = 0; u < 2; ++u) lds[dst[u]] = cv[u];
   }
+  // P4 (the rows of X, or with PM the primal step's X, staged as they are computed), and P8's
+  // gathers one (cell, tile) pair at a time where the rounds above would spill
+  if constexpr (PASS == 0 || (PASS == 2 && !kRounds)) {
   for (int q = threadIdx.x; q < lines * K; q += nthr) {
-    if (PASS == 1 || PASS >= 3) break;                 // loaded above
     Cell<R> c = zero_cell<R>();
     if (PASS == 0) {
       const int l = q >> lgK, k = q & (K - 1), r = line0 + l;
@@ -319,8 +321,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
         c.s[0].re = v.x * sc; c.s[1].re = v.y * sc; c.s[2].re = v.z * sc; c.s[3].re = v.w * sc;
       }
       lds[q] = c;
-    } else if (PASS == 2) {
-      if (kRounds) continue;                           // gathered above
+    } else {
       // the gathers one (cell, tile) pair at a time, in the order of the rounds above
       const int l = q >> lgK, k = q & (K - 1), k2 = line0 + l;
       if (k2 < K) {
@@ -355,6 +356,7 @@ fft_pass_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ ite
       }
       lds[q] = c;
     }
+  }
   }
   __syncthreads();
   // lines * K == CELLS (K divides CELLS), so every thread owns one channel of 8 cells

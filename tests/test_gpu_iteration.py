@@ -262,3 +262,36 @@ def test_max_image_side():
             say(f"   n={n} {prec}: worst rel err {w:.2e}")
         finally:
             s.close()
+
+
+def test_served_large_request_one_iteration():
+    """The served mix's large request at its full size (512^2 per Stokes map, 1e6 visibility rows,
+    8x8 taps, all nine bases at four levels, the launch shapes the large-solve benchmark runs):
+    one constrained iteration from a random state against the oracle, in FP64 and FP32.  The
+    oracle's step sizes come from its own five-step power iteration, inflated by 1.5 so that
+    they bound ||phi||^2 from above; its share is about 40 s."""
+    wl = wk.batch_request(0, sides=(512,))
+    n, M, T, L = wl.n, wl.M, wl.taps, wl.levels
+    assert (n, M, T, L) == (512, 1_000_000, 8, 4)
+    say(f"[iter] n={n} M={M}: oracle set-up")
+    est, _ = pd.phi_norm_sq(MeasurementOp(NUFFT(wl.uv, n, 2, T)), n * n, max_iter=5, rtol=0.0)
+    b = problem.build(wl, phi_norm=1.5 * est)
+    rng = np.random.default_rng(93)
+    W = rng.uniform(0.2, 1.0, size=(b.sara.J, 4))
+    gW = b.gamma * W
+    st = _random_state(rng, n * n, b.sara.J, M, gW)
+    scale = {}
+    ref = _oracle_steps(st.copy(), b.pb, gW, "polsara", 1, scale)
+    for prec, tol in (("fp64", 1e-9), ("fp32", 5e-6)):
+        say(f"[iter] n={n} M={M} {prec}")
+        s = solver_for(wl, n, T, prec, levels=L, gamma=b.gamma, weights=W)
+        try:
+            s.set_data(b.pb.Y, b.pb.eps)
+            s.opnorm(100, 1e-6)
+            s.set_steps(b.pb.tau, b.pb.rho1, b.pb.rho2, b.pb.rho3)
+            s.set_state(st.S, st.Z, st.A, st.B, st.C, st.D)
+            s.solve(P.PSARA_CONSTRAINED, 1, report=False)
+            w = _compare(s.state(), ref, tol, f"n={n} M={M} {prec}", scale if prec == "fp32" else None)
+            say(f"   n={n} M={M} {prec}: worst rel err {w:.2e}")
+        finally:
+            s.close()

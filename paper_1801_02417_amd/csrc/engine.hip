@@ -198,12 +198,45 @@ void order_grid_items(It begin, It end, GeoOf geo_of) {
   };
   std::stable_sort(begin, end, [&](const int4& a, const int4& b) { return cost(a) > cost(b); });
 }
-// Orders de-grid items by decreasing row count, so the fullest start first and the tail of the
-// launch is made of the short ones (an item keeps its partial index, so the norm's reduction
-// order does not change).
+// Orders de-grid items for the eight XCDs that workgroups are dealt to in turn: the items of
+// one tile (which stage overlapping k1 bands of the same window) all take positions of one XCD,
+// where they share its L2 lines; tiles go to the XCD with the fewest rows so far, largest
+// first, and each XCD's items run fullest first, so the tail of the launch is made of the short
+// ones.  (An item keeps its partial index, so the norm's reduction order does not change.)
 template <typename It>
 void order_degrid_items(It begin, It end) {
-  std::stable_sort(begin, end, [](const int4& a, const int4& b) { return (a.y >> 16) > (b.y >> 16); });
+  std::vector<int4> v(begin, end);
+  if (v.size() < 2) return;
+  auto rows = [](const int4& a) { return a.y >> 16; };
+  auto key = [](const int4& a) { return std::make_pair(a.x, a.y & 0xffff); };   // (problem, tile)
+  std::stable_sort(v.begin(), v.end(), [&](const int4& a, const int4& b) { return key(a) < key(b); });
+  struct Group { size_t beg, end; long long rows; };
+  std::vector<Group> groups;
+  for (size_t i = 0; i < v.size();) {
+    size_t j = i;
+    long long r = 0;
+    while (j < v.size() && key(v[j]) == key(v[i])) r += rows(v[j++]);
+    groups.push_back({i, j, r});
+    i = j;
+  }
+  std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) { return a.rows > b.rows; });
+  constexpr int kXcds = 8;
+  std::vector<int4> q[kXcds];
+  long long load[kXcds] = {};
+  for (const Group& g : groups) {
+    const int x = (int)(std::min_element(load, load + kXcds) - load);
+    q[x].insert(q[x].end(), v.begin() + g.beg, v.begin() + g.end);
+    load[x] += g.rows;
+  }
+  size_t longest = 0;
+  for (auto& qx : q) {
+    std::stable_sort(qx.begin(), qx.end(), [&](const int4& a, const int4& b) { return rows(a) > rows(b); });
+    longest = std::max(longest, qx.size());
+  }
+  It out = begin;
+  for (size_t j = 0; j < longest; ++j)
+    for (int x = 0; x < kXcds; ++x)
+      if (j < q[x].size()) *out++ = q[x][j];
 }
 void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int rcells, int dg_item, int* n_p6) {
   const int n = g.n, K = g.K, N = n * n;
@@ -252,6 +285,22 @@ void add_operator_items(ItemSet& S, int prob, const Geometry& g, int cells, int 
   *n_p6 = part;
 }
 
+// Tile order of the SARA work lists.  Workgroups are dealt to the eight XCDs in turn, so a
+// list whose j-th item takes tile xcd_tiles(tps)[j] runs every tile of one horizontal band
+// (an eighth of the tile rows) on the same XCD, where neighbouring tiles share the L2 lines of
+// their overlapping halos; the per-basis lists (a multiple of eight items each) keep every
+// basis of a tile on its band's XCD.  The identity where the tile rows do not split into
+// eight bands.
+static std::vector<int> xcd_tiles(int tps) {
+  std::vector<int> ord(tps * tps);
+  std::iota(ord.begin(), ord.end(), 0);
+  if (tps % 8 != 0) return ord;
+  const int per = tps * tps / 8;                   // tiles per band, row-major
+  for (int j = 0; j < per; ++j)
+    for (int b = 0; b < 8; ++b) ord[j * 8 + b] = b * per + j;
+  return ord;
+}
+
 void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const int* wav_len, bool fp64, int c_level,
                      int ana_wide, int* n_ana_parts) {
   const int N = n * n;
@@ -263,26 +312,35 @@ void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const in
   for (int l = 1; l <= levels; ++l) {
     const int h = n >> l;
     const int to = fp64 ? dwt_ana_tile<double>(h, wide) : dwt_ana_tile<float>(h, wide), tps = h / to;
+    const std::vector<int> ord = xcd_tiles(tps);
     for (int w = 0; w < nwav; ++w)
-      for (int t = 0; t < tps * tps; ++t) {
-        S.ana[l].push_back(make_int4(prob, w, t, part++));
+      for (int t : ord) {
+        S.ana[l].push_back(make_int4(prob, w, t, part + w * tps * tps + t));   // partials in tile order
         if (l < c_level && !(l == 1 && all_bases)) S.ana_d[l].push_back(S.ana[l].back());
       }
+    part += nwav * tps * tps;
     if (l == 1 && all_bases)
-      for (int t = 0; t < tps * tps; ++t) S.ana_d[1].push_back(make_int4(prob, kAllBases, t, 0));
+      for (int t : ord) S.ana_d[1].push_back(make_int4(prob, kAllBases, t, 0));
   }
   for (int l = 2; l <= levels; ++l) {
     const int m = n >> (l - 1);
     const int to = fp64 ? dwt_syn_tile<double>(m) : dwt_syn_tile<float>(m), tps = m / to;
+    const std::vector<int> ord = xcd_tiles(tps);
     for (int w = 0; w < nwav; ++w)
-      for (int t = 0; t < tps * tps; ++t) {
+      for (int t : ord) {
         S.syn[l].push_back(make_int4(prob, w, t, 0));
         if (l < c_level) S.syn_d[l].push_back(S.syn[l].back());
       }
   }
+  // the coarse items channel-major over eight basis places (an empty place is an item with
+  // basis -1, which does nothing): workgroups are dealt to the eight XCDs in turn, so the four
+  // channel workgroups of a basis run on one XCD and share its L2 lines (each reads and writes
+  // one component of the same four-component elements); a problem's 32 items keep the
+  // alignment when a batch concatenates the lists
+  static_assert(kMaxBases - 1 <= 8, "eight basis places");
   if (c_level <= levels)
-    for (int w = 0; w < nwav; ++w)
-      for (int ch = 0; ch < 4; ++ch) S.coarse.push_back(make_int4(prob, w, ch, c_level));
+    for (int ch = 0; ch < 4; ++ch)
+      for (int w = 0; w < 8; ++w) S.coarse.push_back(make_int4(prob, w < nwav ? w : -1, ch, c_level));
   {
     const int to = fp64 ? dwt_syn_tile<double>(n) : dwt_syn_tile<float>(n), tps = n / to;
     // the split: longest filters first, each to the lighter part (work ~ filter length plus the
@@ -297,14 +355,13 @@ void add_prior_items(ItemSet& S, int prob, int n, int levels, int nwav, const in
       work[p] += wav_len[w] + 8;
     }
     const int all = (1 << nwav) - 1;
-    for (int t = 0; t < tps * tps; ++t) {
-      S.synfinal.push_back(make_int4(prob, t, 0, all));
-      if (nwav < 2) {
-        S.synsplit.push_back(make_int4(prob, t, 0, all));
-      } else {
-        S.synsplit.push_back(make_int4(prob, t, 0, mask[0]));
-        S.synsplit.push_back(make_int4(prob, t, 1, mask[1]));
-      }
+    const std::vector<int> ord = xcd_tiles(tps);
+    for (int t : ord) S.synfinal.push_back(make_int4(prob, t, 0, all));
+    if (nwav < 2) {
+      for (int t : ord) S.synsplit.push_back(make_int4(prob, t, 0, all));
+    } else {
+      for (int p = 0; p < 2; ++p)
+        for (int t : ord) S.synsplit.push_back(make_int4(prob, t, p, mask[p]));
     }
   }
   *n_ana_parts = part;

@@ -60,7 +60,7 @@ void check_tuning(const Tuning& t, int K);
 // Work lists of the passes; every item names its problem (index into the descriptor array).
 //   ana[l], syn[l]     SARA analysis / synthesis of level l for every level (non-dual uses)
 //   ana_d[l], syn_d[l] the same restricted to the levels below each problem's fused coarse level
-//   coarse             {prob, wavelet, Stokes channel, first coarse level}
+//   coarse             {prob, wavelet (-1: an empty place), Stokes channel, first coarse level}
 //   synfinal           {prob, tile, 0, mask of every basis}
 //   synsplit           the same with the bases of each tile split over two items {prob, tile, part,
 //                      mask} of about equal filter work (one item per tile below two bases)

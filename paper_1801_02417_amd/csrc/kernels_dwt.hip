@@ -525,7 +525,7 @@ synthesis_final_kernel(const ProbDesc* __restrict__ descs, const int4* __restric
 // Mallat pyramid of the coarse levels; synthesis then runs back from level L to level c on
 // the updated duals and leaves the low-low band of level c-1 in the level scratch, where the
 // next synthesis launch reads it.  Replaces 2 (L - c + 1) small launches by one.
-// items: {prob, wavelet index, Stokes channel, first coarse level c}
+// items: {prob, wavelet index (-1: none), Stokes channel, first coarse level c}
 template <typename R> struct CoarseMax { static constexpr int value = sizeof(R) == 4 ? 64 : 32; };
 
 template <typename R>
@@ -667,7 +667,7 @@ coarse_kernel(const ProbDesc* __restrict__ descs, const int4* __restrict__ items
   __shared__ R bufA[MM * MM], bufB[MM * MM], pyr[MM * MM], gw[MM * MM];
   const int4 it = items[blockIdx.x];
   const ProbDesc& P = descs[it.x];
-  if (halted(P)) return;                 // stopped by an adaptive run
+  if (halted(P) || it.y < 0) return;    // stopped by an adaptive run, or an empty basis place
 #define PSARA_COARSE(FF) coarse_body<FF, R>(P, it.y, it.z, it.w, bufA, bufB, pyr, gw)
   PSARA_FILTER_SWITCH(P.wav_len[it.y], PSARA_COARSE)
 #undef PSARA_COARSE
